@@ -1,0 +1,171 @@
+"""Sector-blocked exact diagonalisation of the Hubbard model (oracle).
+
+Paper: Eq. (3), H = -t sum_<ij>,s (c+_is c_js + h.c.) + U sum_i n_iu n_id
+- mu sum_i n_i, on the lattices of ``oracle.lattice``; the density operator
+rho = exp(-beta H) and the bilayer identity rho(beta) = rho(beta/2)
+rho(beta/2)^dagger of SM Sec. II.A.
+
+Fock basis: 2N fermion modes ordered (site 0 up, site 0 down, site 1 up, ...)
+along the snake; a basis state is prod_m (c+_m)^{n_m} |vac> with the
+creation operators applied in increasing mode order (leftmost first).  The
+dense index of a state is sum_i sigma_i 4^(N-1-i), sigma_i = n_iu + 2 n_id,
+i.e. the local basis {0, up, down, updown} with |updown> = c+_u c+_d |0>.
+
+H commutes with N_up and N_down, so it is built and diagonalised block by
+block over (N_up, N_down).
+"""
+from itertools import product
+
+import numpy as np
+
+from . import lattice
+
+
+def _mode(site, spin):
+    return 2 * site + spin
+
+
+def _index(occ, N):
+    """Dense index of an occupation tuple (length 2N)."""
+    idx = 0
+    for i in range(N):
+        idx = idx * 4 + occ[2 * i] + 2 * occ[2 * i + 1]
+    return idx
+
+
+def _hop(occ, m, n):
+    """Apply c+_m c_n to a basis state.  Returns (sign, new_occ) or None."""
+    if occ[n] == 0:
+        return None
+    occ = list(occ)
+    sign = (-1) ** sum(occ[:n])          # c_n passes the occupied modes left of n
+    occ[n] = 0
+    if occ[m] == 1:
+        return None
+    sign *= (-1) ** sum(occ[:m])         # c+_m passes the occupied modes left of m
+    occ[m] = 1
+    return sign, tuple(occ)
+
+
+class Hubbard:
+    """Eq. (3) on a snake-ordered lattice; sector-blocked Hamiltonian."""
+
+    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0):
+        self.W, self.L, self.geometry = W, L, geometry
+        self.t, self.U, self.mu = float(t), float(U), float(mu)
+        self.N = W * L
+        self.bonds = lattice.nn_bonds(W, L, geometry)
+
+    def _diag(self, occ):
+        e = 0.0
+        for i in range(self.N):
+            nu, nd = occ[2 * i], occ[2 * i + 1]
+            e += self.U * nu * nd - self.mu * (nu + nd)
+        return e
+
+    def sector_states(self, nup, ndn):
+        N = self.N
+        states = []
+        for occ in product((0, 1), repeat=2 * N):
+            if sum(occ[0::2]) == nup and sum(occ[1::2]) == ndn:
+                states.append(occ)
+        return states
+
+    def sector_hamiltonian(self, nup, ndn):
+        """Dense H restricted to the (N_up, N_down) block, and the dense indices."""
+        states = self.sector_states(nup, ndn)
+        pos = {s: k for k, s in enumerate(states)}
+        H = np.zeros((len(states), len(states)))
+        for k, occ in enumerate(states):
+            H[k, k] += self._diag(occ)
+            for (i, j) in self.bonds:
+                for spin in (0, 1):
+                    mi, mj = _mode(i, spin), _mode(j, spin)
+                    for (m, n) in ((mi, mj), (mj, mi)):
+                        r = _hop(occ, m, n)
+                        if r is not None:
+                            sgn, new = r
+                            H[pos[new], k] += -self.t * sgn
+        idx = np.array([_index(s, self.N) for s in states], dtype=np.int64)
+        return H, idx
+
+    def dense_hamiltonian(self):
+        """Full 4^N x 4^N H in the dense basis (small N only)."""
+        N = self.N
+        H = np.zeros((4 ** N, 4 ** N))
+        for nup in range(N + 1):
+            for ndn in range(N + 1):
+                h, idx = self.sector_hamiltonian(nup, ndn)
+                H[np.ix_(idx, idx)] = h
+        return H
+
+    def spectrum(self):
+        """All eigenvalues with their (N_up, N_down) labels."""
+        N = self.N
+        evals, nups, ndns = [], [], []
+        for nup in range(N + 1):
+            for ndn in range(N + 1):
+                h, _ = self.sector_hamiltonian(nup, ndn)
+                e = np.linalg.eigvalsh(h)
+                evals.append(e)
+                nups.append(np.full(e.size, nup))
+                ndns.append(np.full(e.size, ndn))
+        return np.concatenate(evals), np.concatenate(nups), np.concatenate(ndns)
+
+    def hopping_matrix(self):
+        """Single-particle matrix h with H(U=0) = sum_s c+_s h c_s."""
+        h = -self.mu * np.eye(self.N)
+        for (i, j) in self.bonds:
+            h[i, j] -= self.t
+            h[j, i] -= self.t
+        return h
+
+
+def _logsumexp(x):
+    m = np.max(x)
+    return m + np.log(np.sum(np.exp(x - m)))
+
+
+def thermal_physical(E, beta):
+    """Exact ln Z(beta) and energy <H> for rho = exp(-beta H)."""
+    x = -beta * E
+    lnZ = _logsumexp(x)
+    w = np.exp(x - lnZ)
+    return lnZ, float(np.sum(w * E))
+
+
+def same_ode_bilayer(E, beta0, beta):
+    """Exact values reached by the flow d rho/d beta = -H rho from the linear
+    start rho(beta0) = 1 - beta0 H (main text, noninteracting-benchmark
+    paragraph): rho(beta) = exp(-(beta-beta0) H) (1 - beta0 H).
+
+    Bilayer (SM Sec. II.A): Z_bl = ||rho(beta)||_F^2 is the partition function
+    at the physical inverse temperature 2*beta, and
+    E_bl = <<rho|H (x) 1|rho>> / <<rho|rho>>.
+    Returns (ln Z_bl, E_bl).
+    """
+    a = 1.0 - beta0 * E
+    x = 2.0 * np.log(np.abs(a)) - 2.0 * (beta - beta0) * E
+    lnZ = _logsumexp(x)
+    w = np.exp(x - lnZ)
+    return lnZ, float(np.sum(w * E))
+
+
+def same_ode_single(E, beta0, beta):
+    """ln Tr rho(beta) for rho(beta) = exp(-(beta-beta0) H) (1 - beta0 H)."""
+    a = 1.0 - beta0 * E
+    x = -(beta - beta0) * E
+    m = np.max(x)
+    return m + np.log(np.sum(a * np.exp(x - m)))
+
+
+def free_fermion_lnZ(h, beta):
+    """U = 0 closed form: ln Z = 2 sum_k ln(1 + exp(-beta eps_k)), eps = eig(h)."""
+    eps = np.linalg.eigvalsh(h)
+    return 2.0 * float(np.sum(np.logaddexp(0.0, -beta * eps)))
+
+
+def free_fermion_energy(h, beta):
+    """U = 0 closed form: <H> = 2 sum_k eps_k f(eps_k)."""
+    eps = np.linalg.eigvalsh(h)
+    return 2.0 * float(np.sum(eps / (np.exp(beta * eps) + 1.0)))

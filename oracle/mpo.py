@@ -1,0 +1,171 @@
+"""Finite-state-machine MPO of the Hubbard Hamiltonian and the super-MPS of
+rho0 = 1 - beta0*H (oracle; test infrastructure only).
+
+Paper: Eq. (3); the MPO of H with a small bond D_H is only cited (main text,
+noninteracting-benchmark paragraph); the Choi map of SM Sec. II.A turns an MPO
+tensor W[a, sigma, sigma', b] into a super-MPS tensor with the combined index
+s = (sigma, sigma').
+
+Fermion signs (Jordan-Wigner along the snake, mode order up before down):
+c_{i,s} = (prod_{j<i} P_j) c^loc_{i,s} with the site parity P = (-1)^{n}, so
+for i < j
+    c+_{i s} c_{j s} = (c+_s P)_i  (prod_{i<k<j} P_k)  (c_s)_j
+    c+_{j s} c_{i s} = (P c_s)_i   (prod_{i<k<j} P_k)  (c+_s)_j .
+
+Bond states (a convention shared by every builder of this MPO, so that a
+padded rho0 is the same tensor everywhere).  With ks = N // 2:
+    bond 0: [start];  bond N: [start, done];
+    bond k, 0 < k <= ks (source-indexed):
+        [start] + [src(i, type) for i in pending_src(k) ascending, type] + [done]
+    bond k, ks < k < N (destination-indexed):
+        [start] + [dst(j, type) for j in pending_dst(k) ascending, type] + [done]
+type runs over (c+_up P, c+_dn P, P c_up, P c_dn); pending_src(k) = sites
+i < k with a neighbour j >= k, pending_dst(k) = sites j >= k with a
+neighbour i < k.  A source channel carries the left operator of site i and
+propagates with P; a destination channel carries the sum over sources i of
+-t times their left operators and is closed at j by the right operator.  The
+switch site ks maps src(i) to dst(j) with -t P for each neighbour j > ks of
+i.  Indexing by source on the left half and by destination on the right half
+keeps every bond inside the maximal charge sectors near both chain ends (a
+source-indexed right edge is not minimal on 2D lattices).
+W[a, so, si, b] acts as the operator sum_{so,si} |so><si| on the ket.
+"""
+import numpy as np
+
+from . import lattice
+
+# local basis {0, up, down, updown}, |updown> = c+_up c+_dn |0>
+CDAG_UP = np.zeros((4, 4)); CDAG_UP[1, 0] = 1.0; CDAG_UP[3, 2] = 1.0
+CDAG_DN = np.zeros((4, 4)); CDAG_DN[2, 0] = 1.0; CDAG_DN[3, 1] = -1.0
+C_UP = CDAG_UP.T.copy()
+C_DN = CDAG_DN.T.copy()
+PAR = np.diag([1.0, -1.0, -1.0, 1.0])
+N_UP = np.diag([0.0, 1.0, 0.0, 1.0])
+N_DN = np.diag([0.0, 0.0, 1.0, 1.0])
+ID4 = np.eye(4)
+
+# channel types: (left operator at the source site, right operator at the partner)
+CHANNELS = (
+    (CDAG_UP @ PAR, C_UP),
+    (CDAG_DN @ PAR, C_DN),
+    (PAR @ C_UP, CDAG_UP),
+    (PAR @ C_DN, CDAG_DN),
+)
+# U(1)xU(1) charge carried by a channel: q(b) = q(a) + q(so) - q(si)
+CHANNEL_CHARGE = ((1, 0), (0, 1), (-1, 0), (0, -1))
+
+
+def local_charge(sigma):
+    """(n_up, n_dn) of a local basis state."""
+    return (sigma & 1, sigma >> 1)
+
+
+class HubbardMPO:
+    """W tensors of Eq. (3) with the bond-state convention above."""
+
+    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0):
+        self.N = N = W * L
+        self.t, self.U, self.mu = float(t), float(U), float(mu)
+        bonds = lattice.nn_bonds(W, L, geometry)
+        self.partners = [set() for _ in range(N)]
+        for (i, j) in bonds:
+            self.partners[i].add(j)
+        # bond states: list of labels per bond k = 0..N
+        self.ks = ks = N // 2
+        self.states = []
+        for k in range(N + 1):
+            if k == 0:
+                self.states.append(["start"])
+                continue
+            if k == N:
+                self.states.append(["start", "done"])
+                continue
+            lab = ["start"]
+            if k <= ks:
+                pend = [i for i in range(k) if any(j >= k for j in self.partners[i])]
+                lab += [("src", i, ty) for i in pend for ty in range(4)]
+            else:
+                pend = [j for j in range(k, N) if any(i < k for i in self.neighbours(j))]
+                lab += [("dst", j, ty) for j in pend for ty in range(4)]
+            lab.append("done")
+            self.states.append(lab)
+        self.W = [self._site(k) for k in range(N)]
+
+    def neighbours(self, j):
+        return [i for i in range(self.N) if j in self.partners[i] or i in self.partners[j]]
+
+    def charge(self, label):
+        if label in ("start", "done"):
+            return (0, 0)
+        return CHANNEL_CHARGE[label[2]]
+
+    def bond_charges(self, k):
+        return [self.charge(lab) for lab in self.states[k]]
+
+    def _site(self, k):
+        left, right = self.states[k], self.states[k + 1]
+        ri = {lab: n for n, lab in enumerate(right)}
+        Wk = np.zeros((len(left), 4, 4, len(right)))
+        t = self.t
+        onsite = self.U * (N_UP @ N_DN) - self.mu * (N_UP + N_DN)
+        later = sorted(j for j in self.partners[k])          # neighbours j > k
+        for a, lab in enumerate(left):
+            if lab == "start":
+                Wk[a, :, :, ri["start"]] += ID4
+                if "done" in ri:
+                    Wk[a, :, :, ri["done"]] += onsite
+                for ty in range(4):
+                    if ("src", k, ty) in ri:
+                        Wk[a, :, :, ri[("src", k, ty)]] += CHANNELS[ty][0]
+                    for j in later:
+                        if ("dst", j, ty) in ri:
+                            Wk[a, :, :, ri[("dst", j, ty)]] += -t * CHANNELS[ty][0]
+            elif lab == "done":
+                Wk[a, :, :, ri["done"]] += ID4
+            elif lab[0] == "src":
+                _, i, ty = lab
+                if lab in ri:
+                    Wk[a, :, :, ri[lab]] += PAR
+                for j in sorted(self.partners[i]):
+                    if j > k and ("dst", j, ty) in ri:
+                        Wk[a, :, :, ri[("dst", j, ty)]] += -t * PAR
+                if k in self.partners[i]:
+                    Wk[a, :, :, ri["done"]] += -t * CHANNELS[ty][1]
+            else:
+                _, j, ty = lab
+                if j == k:
+                    Wk[a, :, :, ri["done"]] += CHANNELS[ty][1]
+                else:
+                    Wk[a, :, :, ri[lab]] += PAR
+        return Wk
+
+    def h_boundary_right(self):
+        """Right boundary vector selecting 'done' (the MPO of H)."""
+        return np.array([0.0, 1.0])
+
+    def mpo_for_env(self):
+        """W tensors with both boundary bonds of dimension 1 (for environments)."""
+        Ws = [w.copy() for w in self.W]
+        Ws[-1] = np.tensordot(Ws[-1], self.h_boundary_right(), axes=([3], [0]))[..., None]
+        return Ws
+
+    def rho0_tensors(self, beta0):
+        """Super-MPS tensors A[a, so, si, b] of rho0 = 1 - beta0 H (Choi map)."""
+        As = [w.copy() for w in self.W]
+        r = np.array([1.0, -beta0])
+        As[-1] = np.tensordot(As[-1], r, axes=([3], [0]))[..., None]
+        return As
+
+
+def mpo_to_dense(Ws):
+    """Contract an MPO (boundary bonds of dimension 1) to a 4^N x 4^N matrix."""
+    M = Ws[0][0]                      # (so, si, b)
+    M = M.transpose(2, 0, 1)          # (b, so, si)
+    for Wk in Ws[1:]:
+        # M[b, O, I], Wk[b, so, si, c] -> M[c, (O so), (I si)]
+        T = np.tensordot(M, Wk, axes=([0], [0]))       # (O, I, so, si, c)
+        T = T.transpose(4, 0, 2, 1, 3)                  # (c, O, so, I, si)
+        c, O, so, I, si = T.shape
+        M = T.reshape(c, O * so, I * si)
+    assert M.shape[0] == 1
+    return M[0]
