@@ -1,0 +1,190 @@
+/*
+ * tantrg.h - C ABI of the one-site tangent-space imaginary-time sweep of the
+ * density-operator MPO rho(beta) for the Hubbard model (tanTRG,
+ * arXiv:2212.11973), on AMD MI355X (gfx950).
+ *
+ * The state is the super-MPS |rho>> of the Choi map (SM Sec. II.A): site k
+ * holds A_k[x, s, y] with s = 4*sigma + sigma' (sigma the ket index, on which
+ * H acts; sigma' the ancilla), bond dimensions D_k, k = 0..N.  The library
+ * keeps rho = e^Lambda * (normalised mixed-canonical MPS), Lambda = ln||rho||_F.
+ *
+ * Conventions for every entry point:
+ *   - returns 0 (TT_OK) on success, a negative TT_E* code on failure; the
+ *     failing call leaves a message for tt_last_error() (thread-local);
+ *     no C++ exception crosses the ABI;
+ *   - pointers named host_* are host memory owned by the caller; pointers
+ *     named dev_* are device memory owned by the caller; tt_state handles and
+ *     all device memory behind them are owned by the library and released by
+ *     tt_state_free();
+ *   - all device work is enqueued on the stream set by tt_set_stream()
+ *     (default: the null stream); calls that return values to the host
+ *     synchronise that stream before returning;
+ *   - a tt_state is not thread-safe; distinct states may be used from
+ *     distinct threads.
+ */
+#ifndef TANTRG_H
+#define TANTRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque state handle. */
+typedef struct tt_state tt_state;
+
+/* error codes */
+#define TT_OK 0
+#define TT_EINVAL -1    /* bad argument (sizes, enums, null pointers, unsupported option) */
+#define TT_ENOMEM -2    /* device or host allocation failed */
+#define TT_EDEVICE -3   /* a HIP call failed or no gfx950 device is usable */
+#define TT_ENUMERIC -4  /* NaN/Inf met, or a sector QR with more columns than rows */
+#define TT_EIO -5       /* file I/O failed or the file is not a saved state */
+
+/* lattice geometry: main text, Hubbard-model paragraph (cylinders CL WxL,
+ * periodic across W, open along L; open squares OS) and Fig. 1a (snake) */
+#define TT_CHAIN 0
+#define TT_CYLINDER 1
+#define TT_OPEN_SQUARE 2
+
+/* precision of the bulk contractions (FP64 is always kept for the Lanczos
+ * scalars and reorthogonalisation, the QR gauge moves and Lambda) */
+#define TT_FP64 0
+#define TT_FP32 1    /* FP32 MFMA, FP32 accumulation inside a K tile, FP64 across tiles */
+#define TT_BF16X3 2  /* split-BF16: hi*hi + hi*lo + lo*hi, FP32 MFMA accumulation */
+#define TT_BF16X6 3  /* split-BF16 with three parts, six products */
+
+/* Eq. (3): H = -t sum_<ij>,s (c+_is c_js + h.c.) + U sum n_iu n_id - mu sum n_i.
+ * tp (next-nearest hopping of Eq. S1) must be 0: not supported. */
+typedef struct {
+  int W, L;          /* width and length; chain: W = 1 */
+  int geometry;      /* TT_CHAIN, TT_CYLINDER (wrap across W only for W >= 3), TT_OPEN_SQUARE */
+  double t, tp, U, mu;
+} tt_model;
+
+typedef struct {
+  int D;               /* target bond dimension (bonds never exceed the maximal one) */
+  int symmetry;        /* 0 dense, 1 U(1)charge x U(1)spin block-sparse */
+  double beta0;        /* rho0 = 1 - beta0 H (main text: high-temperature start) */
+  int taylor_order;    /* must be 1 (higher orders not supported) */
+  int krylov_dim;      /* Lanczos dimension K (SM Sec. II.H), 1..32 */
+  double krylov_tol;   /* lucky breakdown when beta_j <= tol*||H q_j|| (default 1e-13) */
+  int precision;       /* TT_FP64 / TT_FP32 / TT_BF16X3 / TT_BF16X6 */
+  double pad_eps;      /* amplitude of the seeded padding noise (0: zero padding) */
+  uint64_t seed;       /* SplitMix64 seed of the padding noise */
+  int env_on_host;     /* must be 0 (not supported) */
+} tt_options;
+
+typedef struct {
+  double beta;         /* MPO parameter: |rho>> approximates exp(-beta H) (1 - beta0 H) */
+  double beta_phys;    /* 2*beta: inverse temperature of the bilayer values */
+  double lnZ;          /* ln ||rho(beta)||_F^2 = ln Z(beta_phys) (bilayer, SM Sec. II.A) */
+  double f;            /* -lnZ / (N beta_phys) */
+  double E;            /* <<rho|H (x) 1|rho>> / <<rho|rho>> */
+  double e;            /* E / N */
+  double lnZ_single;   /* ln Tr rho(beta) (single layer) */
+  double lambda;       /* Lambda = ln ||rho||_F */
+  int n_sites;
+} tt_observables;
+
+typedef struct {
+  double seconds;          /* wall time of the call (host clock, stream synchronised) */
+  double flops_alg;        /* algorithmic flops of all contractions (sum of 2mnk per GEMM) */
+  double flops_heff;       /* of which in effective-Hamiltonian applies (site and bond) */
+  int n_applies;           /* site + bond effective-Hamiltonian applies */
+  int n_exps;              /* local exponentials */
+  double max_krylov_err;   /* max a-posteriori Lanczos estimate beta_K |[exp(tT)]_{K,1}| */
+} tt_sweep_stats;
+
+/* Default options: D=64, symmetry=1, beta0=1e-2, taylor_order=1, K=8,
+ * tol=1e-13, FP64, pad_eps=0, seed=1, env_on_host=0. */
+int tt_options_default(tt_options* opts);
+
+/* Build rho0 = 1 - beta0*H (main text, noninteracting-benchmark paragraph)
+ * as a super-MPS from the finite-state-machine MPO of Eq. (3), pad every
+ * bond to opts->D (U(1)xU(1) sectors sized by the rule documented with the
+ * library), add pad_eps seeded noise on padding entries, right-canonicalise
+ * by LQ (diag >= 0) and build the right environments.  beta = beta0.
+ * *out receives a new state owned by the caller (free with tt_state_free). */
+int mpo_init_highT(const tt_model* model, const tt_options* opts, tt_state** out);
+
+/* One symmetric 1-TDVP step beta -> beta + dbeta (SM Sec. II.F steps 1-7,
+ * SM Sec. II.E splitting): left-to-right with tau = dbeta/2 (site
+ * exp(-tau H^(1)), QR, left environment, bond exp(+tau H^(0)), absorb), the
+ * two last-site exponentials merged into one with 2*tau, then right-to-left
+ * with LQ.  Every local exponential is a Lanczos exponential (SM Sec. II.H)
+ * and is followed by normalisation into Lambda.  stats may be NULL.
+ * Enqueued asynchronously unless stats is non-NULL. */
+int tdvp_sweep(tt_state* state, double dbeta, tt_sweep_stats* stats);
+
+/* The same step for n independent states (e.g. a chemical-potential scan),
+ * advanced site by site in lockstep; stats (may be NULL) are summed. */
+int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* stats);
+
+/* Bilayer observables of SM Sec. II.A at beta_phys = 2*beta: lnZ = 2 Lambda,
+ * E from one H^(1) apply at the canonical centre, and the single-layer
+ * ln Tr rho(beta) by transfer matrices.  Synchronises. */
+int thermo_observables(tt_state* state, tt_observables* out);
+
+void tt_state_free(tt_state* state);
+const char* tt_last_error(void);
+
+/* n_sites and the N+1 bond dimensions (host_dims may be NULL). */
+int tt_state_info(const tt_state* state, int* n_sites, int* host_dims);
+/* Sectors of bond k: counts into *nsec; if the arrays are non-NULL they must
+ * hold *nsec entries on input (query with NULL first). */
+int tt_state_bond_sectors(const tt_state* state, int k, int* nsec,
+                          int* host_qup, int* host_qdn, int* host_dim);
+/* Site tensor k as a dense host array [D_k][16][D_{k+1}] (bond index order:
+ * sectors by (q_up, q_dn), then the index inside the sector).  Export writes
+ * zeros outside the charge-allowed blocks; import ignores them.  Synchronises. */
+int tt_state_export_site(const tt_state* state, int k, double* host_dense);
+int tt_state_import_site(tt_state* state, int k, const double* host_dense);
+/* Save / load the whole state (tensors, sectors, beta, Lambda, sweep count)
+ * to a binary file; load rebuilds the environments. */
+int tt_state_save(const tt_state* state, const char* path);
+int tt_state_load(const char* path, tt_state** out);
+
+/* One dense effective-Hamiltonian apply (SM Fig. optimalB(c), contraction
+ * order of SM Fig. Lanczos):
+ *   out[x,so,sp,y] = sum L[x,a,al] A[al,si,sp,be] W[a,so,si,b] R[y,b,be]
+ * with dev_L [Dl][DH][Dl], dev_W [DH][4][4][DH], dev_A and dev_out
+ * [Dl][4][4][Dr], dev_R [Dr][DH][Dr], all FP64 row-major device arrays owned
+ * by the caller; stream is a hipStream_t (NULL: the library stream).
+ * Workspace of 8*(Dl*DH*16*Dr)*2 bytes is kept by the library between
+ * calls.  Returns after enqueueing. */
+int tt_heff_apply(int Dl, int Dr, int DH, const double* dev_L, const double* dev_W,
+                  const double* dev_A, const double* dev_R, double* dev_out, int precision,
+                  void* stream);
+
+/* Stream for all later work (a hipStream_t; NULL for the null stream). */
+int tt_set_stream(void* stream);
+/* Device allocator used for all later allocations (both NULL: hipMalloc/hipFree). */
+typedef void* (*tt_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*tt_free_fn)(void* ptr, void* ctx);
+int tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free_fn, void* ctx);
+
+/* Device time (ms) of the last tt_heff_apply per stage, measured with HIP
+ * events on the stream it ran on: [0] L.A, [1] W stage, [2] .R, [3] total.
+ * Synchronises. */
+int tt_heff_last_timing(double* host_ms4);
+
+/* Host-only: the sectors bond k would get for this model and options (same
+ * calling convention as tt_state_bond_sectors).  No GPU needed. */
+int tt_model_bond_sectors(const tt_model* model, const tt_options* opts, int k, int* nsec,
+                          int* host_qup, int* host_qdn, int* host_dim);
+
+/* Host-only consistency check (no GPU needed): builds every descriptor the
+ * kernels of a state with this model and options would use and counts index
+ * ranges that fall outside the buffers they address (*violations; details
+ * via tt_last_error()).  *work_doubles (may be NULL) receives the doubles held
+ * by the site tensors and environments. */
+int tt_check_plans(const tt_model* model, const tt_options* opts, long long* violations,
+                   long long* work_doubles);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1084 @@
+// State, sweep driver and C ABI of the tanTRG library.
+//
+// The sweep follows SM Sec. II.F steps 1-7 with the splitting of SM Sec. II.E:
+// left-to-right (site exp(-tau H1), QR, left environment, bond exp(+tau H0),
+// absorb), the two last-site exponentials merged into one with 2 tau, then
+// right-to-left with LQ.  Every local exponential is a Lanczos exponential
+// (SM Sec. II.H) followed by normalisation, whose log-norm is accumulated into
+// Lambda = ln ||rho||_F on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+
+#include "kernels.h"
+
+using namespace tt;
+
+namespace {
+
+thread_local std::string g_err;
+hipStream_t g_stream = nullptr;
+tt_alloc_fn g_alloc = nullptr;
+tt_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+
+#define HIPX(call)                                                              \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) throw Error(TT_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void* dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  if (g_alloc) {
+    p = g_alloc(bytes, g_alloc_ctx);
+    if (!p) throw Error(TT_ENOMEM, "device allocation failed (custom allocator)");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw Error(TT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return p;
+}
+void dfree(void* p) {
+  if (!p) return;
+  if (g_free) g_free(p, g_alloc_ctx);
+  else (void)hipFree(p);
+}
+template <class T>
+T* upload(const std::vector<T>& v, hipStream_t st) {
+  T* d = (T*)dalloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (!v.empty()) HIPX(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  return d;
+}
+
+void check_device() {
+  int n = 0;
+  HIPX(hipGetDeviceCount(&n));
+  if (n < 1) throw Error(TT_EDEVICE, "no HIP device");
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPX(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    throw Error(TT_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+}
+
+void upload_plan(GemmPlan& p, hipStream_t st) {
+  tile_plan(p, 64, 64);
+  p.d_probs = upload(p.probs, st);
+  p.d_tiles = upload(p.tiles, st);
+}
+void upload_plan(WPlan& p, hipStream_t st) {
+  p.ntasks = (int)p.tasks.size();
+  p.d_tasks = upload(p.tasks, st);
+  p.d_terms = upload(p.terms, st);
+}
+void upload_plan(QRPlan& p, hipStream_t st) {
+  p.ntasks = (int)p.tasks.size();
+  for (auto& t : p.tasks) {
+    TT_REQUIRE(t.m >= t.n, TT_ENUMERIC, "QR of a charge block with more columns than rows");
+  }
+  p.d_tasks = upload(p.tasks, st);
+}
+void free_plan(GemmPlan& p) { dfree(p.d_probs); dfree(p.d_tiles); p.d_probs = nullptr; p.d_tiles = nullptr; }
+void free_plan(WPlan& p) { dfree(p.d_tasks); dfree(p.d_terms); p.d_tasks = nullptr; p.d_terms = nullptr; }
+void free_plan(QRPlan& p) { dfree(p.d_tasks); p.d_tasks = nullptr; }
+
+}  // namespace
+
+// ====================================================================== state
+struct tt_state {
+  tt_model model{};
+  tt_options opts{};
+  int N = 0;
+  Lattice lat;
+  Mpo mpo;
+  Groups G;
+  std::vector<Bond> bonds;                  // 0..N
+  std::vector<std::vector<Q>> qH;           // environment MPO charges per bond
+  std::vector<std::vector<double>> Wenv;    // environment MPO tensors per site
+  std::vector<SiteLayout> site;
+  std::vector<EnvLayout> env;
+  std::vector<BondMatLayout> bmat;
+  std::vector<SitePlan> plans;
+  SiteTables tabs;
+  // device memory
+  std::vector<double*> A, Lenv, Renv;
+  double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr, *U = nullptr;
+  double *Sbuf = nullptr, *tmp = nullptr, *kry = nullptr, *wv = nullptr, *qrws = nullptr;
+  double *part = nullptr, *lz = nullptr;   // lz: alpha[K] beta[K] hn[K] coeff[K] scal[4] lambda errmax scratch[4]
+  double** d_sites = nullptr;
+  TraceEntry* d_trace = nullptr;
+  int* d_trace_start = nullptr;
+  double* vtr = nullptr;
+  long long max_site = 0, max_bond = 0, max_bmat = 0, max_env = 0;
+  double beta = 0.0;
+  long long sweeps = 0;
+  // statistics of the current call
+  double flops = 0.0, flops_heff = 0.0;
+  int n_applies = 0, n_exps = 0;
+
+  double* lam_ptr() { return lz + 4 * kMaxKrylov + 4; }
+  double* err_ptr() { return lz + 4 * kMaxKrylov + 5; }
+  double* obs_ptr() { return lz + 4 * kMaxKrylov + 6; }   // 4 scratch values
+  ~tt_state();
+};
+
+tt_state::~tt_state() {
+  for (auto& p : plans) {
+    free_plan(p.s1); free_plan(p.s3); free_plan(p.el); free_plan(p.r1); free_plan(p.r3);
+    free_plan(p.absL); free_plan(p.absR); free_plan(p.b1); free_plan(p.b2);
+    free_plan(p.w2); free_plan(p.wr); free_plan(p.qr); free_plan(p.lq);
+  }
+  for (auto p : A) dfree(p);
+  for (auto p : Lenv) dfree(p);
+  for (auto p : Renv) dfree(p);
+  for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr}) dfree(p);
+  dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
+}
+
+namespace {
+
+hipStream_t ST() { return g_stream; }
+
+// -------------------------------------------------------------- contractions
+void apply_heff1(tt_state& s, int k, const double* x, double* out) {
+  SitePlan& P = s.plans[k];
+  int prec = s.opts.precision;
+  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.T1, nullptr}}, prec, ST());
+  launch_wstage(P.w2, s.T1, s.T2, ST());
+  launch_gemm(P.s3, s.tabs.dev, Slots{{s.T2, s.Renv[k + 1], out, nullptr}}, prec, ST());
+  double f = P.s1.flops + P.w2.flops + P.s3.flops;
+  s.flops += f;
+  s.flops_heff += f;
+  s.n_applies++;
+}
+
+void apply_heff0(tt_state& s, int k, const double* x, double* out) {
+  SitePlan& P = s.plans[k];
+  int prec = s.opts.precision;
+  launch_gemm(P.b1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.U, nullptr}}, prec, ST());
+  launch_gemm(P.b2, s.tabs.dev, Slots{{s.U, s.Renv[k], out, nullptr}}, prec, ST());
+  double f = P.b1.flops + P.b2.flops;
+  s.flops += f;
+  s.flops_heff += f;
+  s.n_applies++;
+}
+
+void env_left(tt_state& s, int k) {   // Lenv[k+1] from Lenv[k], A_k (left-canonical), W_k
+  SitePlan& P = s.plans[k];
+  int prec = s.opts.precision;
+  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}, prec, ST());
+  launch_wstage(P.w2, s.T1, s.T2, ST());
+  launch_gemm(P.el, s.tabs.dev, Slots{{s.A[k], s.T2, s.Lenv[k + 1], nullptr}}, prec, ST());
+  s.flops += P.s1.flops + P.w2.flops + P.el.flops;
+}
+
+void env_right(tt_state& s, int k) {  // Renv[k] from Renv[k+1], A_k (right-canonical), W_k
+  SitePlan& P = s.plans[k];
+  int prec = s.opts.precision;
+  launch_gemm(P.r1, s.tabs.dev, Slots{{s.Renv[k + 1], s.A[k], s.Y, nullptr}}, prec, ST());
+  launch_wstage(P.wr, s.Y, s.Z, ST());
+  launch_gemm(P.r3, s.tabs.dev, Slots{{s.A[k], s.Z, s.Renv[k], nullptr}}, prec, ST());
+  s.flops += P.r1.flops + P.wr.flops + P.r3.flops;
+}
+
+// -------------------------------------------------------------- Lanczos exp
+// v <- exp(t H) v / ||exp(t H) v||, Lambda += ln ||exp(t H) v||
+void lanczos_exp(tt_state& s, double t, double* v, long long n, const std::function<void(const double*, double*)>& H) {
+  const int K = s.opts.krylov_dim;
+  const double tol = s.opts.krylov_tol;
+  double* alpha = s.lz;
+  double* beta = s.lz + kMaxKrylov;
+  double* hn = s.lz + 2 * kMaxKrylov;
+  double* coeff = s.lz + 3 * kMaxKrylov;
+  double* scal = s.lz + 4 * kMaxKrylov;
+  double* Qb = s.kry;
+  launch_mdot(nullptr, 0, 0, v, n, 1, s.part, ST());
+  launch_lz_start(v, Qb, n, s.part, scal, ST());
+  for (int j = 0; j < K; ++j) {
+    H(Qb + (long long)j * n, s.wv);
+    launch_mdot(Qb, n, j + 1, s.wv, n, 1, s.part, ST());
+    launch_lz_sub(s.wv, Qb, n, j + 1, s.part, j + 2, n, alpha + j, hn + j, ST());
+    launch_mdot(Qb, n, j + 1, s.wv, n, 0, s.part, ST());
+    launch_lz_sub(s.wv, Qb, n, j + 1, s.part, j + 1, n, nullptr, nullptr, ST());
+    launch_mdot(nullptr, 0, 0, s.wv, n, 1, s.part, ST());
+    launch_lz_next(s.wv, j + 1 < K ? Qb + (long long)(j + 1) * n : nullptr, n, s.part, beta + j, hn + j, tol, ST());
+  }
+  launch_lz_coeffs(alpha, beta, hn, K, t, tol, scal, coeff, s.err_ptr(), ST());
+  launch_lz_combine(Qb, n, K, coeff, v, n, ST());
+  launch_mdot(nullptr, 0, 0, v, n, 1, s.part, ST());
+  launch_normalize_log(v, n, s.part, s.lam_ptr(), ST());
+  s.n_exps++;
+}
+
+void site_exp(tt_state& s, int k, double t) {
+  lanczos_exp(s, t, s.A[k], s.site[k].size,
+              [&](const double* x, double* y) { apply_heff1(s, k, x, y); });
+}
+void bond_exp(tt_state& s, int k, double t) {
+  lanczos_exp(s, t, s.Sbuf, s.bmat[k].size,
+              [&](const double* x, double* y) { apply_heff0(s, k, x, y); });
+}
+
+void qr_site(tt_state& s, int k) {
+  launch_qr(s.plans[k].qr, s.tabs.dev, s.A[k], s.Sbuf, s.qrws, ST());
+}
+void lq_site(tt_state& s, int k) {
+  launch_qr(s.plans[k].lq, s.tabs.dev, s.A[k], s.Sbuf, s.qrws, ST());
+}
+void absorb_left(tt_state& s, int k) {   // A_k <- S_k A_k (S on the left bond k)
+  SitePlan& P = s.plans[k];
+  launch_gemm(P.absL, s.tabs.dev, Slots{{s.Sbuf, s.A[k], s.tmp, nullptr}}, TT_FP64, ST());
+  launch_copy(s.A[k], s.tmp, s.site[k].size, ST());
+  s.flops += P.absL.flops;
+}
+void absorb_right(tt_state& s, int k) {  // A_k <- A_k S_{k+1}
+  SitePlan& P = s.plans[k];
+  launch_gemm(P.absR, s.tabs.dev, Slots{{s.A[k], s.Sbuf, s.tmp, nullptr}}, TT_FP64, ST());
+  launch_copy(s.A[k], s.tmp, s.site[k].size, ST());
+  s.flops += P.absR.flops;
+}
+
+void normalize_site(tt_state& s, int k) {
+  launch_mdot(nullptr, 0, 0, s.A[k], s.site[k].size, 1, s.part, ST());
+  launch_normalize_log(s.A[k], s.site[k].size, s.part, s.lam_ptr(), ST());
+}
+
+void sweep_once(tt_state& s, double dbeta) {
+  const int N = s.N;
+  const double tau = 0.5 * dbeta;
+  for (int k = 0; k < N - 1; ++k) {
+    site_exp(s, k, -tau);
+    qr_site(s, k);
+    env_left(s, k);
+    bond_exp(s, k + 1, +tau);
+    absorb_left(s, k + 1);
+  }
+  site_exp(s, N - 1, -2.0 * tau);
+  for (int k = N - 1; k >= 1; --k) {
+    lq_site(s, k);
+    env_right(s, k);
+    bond_exp(s, k, +tau);
+    absorb_right(s, k - 1);
+    site_exp(s, k - 1, -tau);
+  }
+  s.beta += dbeta;
+  s.sweeps++;
+}
+
+// -------------------------------------------------------------- construction
+long long pow16_cap(int e, long long cap) {
+  long long v = 1;
+  for (int i = 0; i < e; ++i) {
+    v *= 16;
+    if (v > cap) return cap + 1;
+  }
+  return v;
+}
+
+void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
+  const int N = s.N;
+  s.bonds.assign(N + 1, Bond());
+  for (int k = 0; k <= N; ++k)
+    for (auto& kv : dims[k]) s.bonds[k].add(kv.first, kv.second);
+  // environment MPO: bond 0 [start], bond N [done]; W_{N-1} contracted with the done selector
+  s.qH.assign(N + 1, {});
+  for (int k = 0; k < N; ++k)
+    for (int a = 0; a < s.mpo.DH[k]; ++a) s.qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : s.mpo.charge(k, a));
+  s.qH[N] = {Q{0, 0}};
+  s.Wenv = s.mpo.W;
+  {
+    int DL = s.mpo.DH[N - 1], DR = s.mpo.DH[N];   // DR = 2: start, done
+    std::vector<double> w((size_t)DL * 16, 0.0);
+    for (int a = 0; a < DL; ++a)
+      for (int q = 0; q < 16; ++q) w[(size_t)a * 16 + q] = s.mpo.W[N - 1][((size_t)a * 16 + q) * DR + 1];
+    s.Wenv[N - 1] = w;
+  }
+  s.site.clear(); s.env.clear(); s.bmat.clear();
+  for (int k = 0; k < N; ++k) s.site.push_back(make_site_layout(s.bonds[k], s.bonds[k + 1], s.G));
+  for (int k = 0; k <= N; ++k) {
+    s.env.push_back(make_env_layout(s.bonds[k], s.qH[k]));
+    s.bmat.push_back(make_bondmat_layout(s.bonds[k]));
+  }
+  s.plans.clear();
+  for (int k = 0; k < N; ++k)
+    s.plans.push_back(build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, s.qH[k], s.qH[k + 1], s.Wenv[k], s.tabs));
+}
+
+void alloc_state(tt_state& s) {
+  const int N = s.N;
+  hipStream_t st = ST();
+  s.tabs.dev = upload(s.tabs.host, st);
+  long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, qw = 0;
+  for (auto& P : s.plans) {
+    upload_plan(P.s1, st); upload_plan(P.s3, st); upload_plan(P.el, st);
+    upload_plan(P.r1, st); upload_plan(P.r3, st); upload_plan(P.absL, st); upload_plan(P.absR, st);
+    upload_plan(P.b1, st); upload_plan(P.b2, st);
+    upload_plan(P.w2, st); upload_plan(P.wr, st);
+    upload_plan(P.qr, st); upload_plan(P.lq, st);
+    t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size);
+    y = std::max(y, P.y_size); z = std::max(z, P.z_size); u = std::max(u, P.u_size);
+    long long qwa = 0, qwb = 0;
+    for (auto& t : P.qr.tasks) qwa = std::max(qwa, t.ws + 2LL * t.m * t.n + t.n);
+    for (auto& t : P.lq.tasks) qwb = std::max(qwb, t.ws + 2LL * t.m * t.n + t.n);
+    qw = std::max(qw, std::max(qwa, qwb));
+  }
+  // every task's workspace: 2 m n + n doubles (W, Q, tau)
+  for (auto& P : s.plans) {
+    for (auto* pl : {&P.qr, &P.lq}) {
+      long long pos = 0;
+      for (auto& t : pl->tasks) { t.ws = pos; pos += 2LL * t.m * t.n + t.n; }
+      qw = std::max(qw, pos);
+      if (!pl->tasks.empty())
+        HIPX(hipMemcpyAsync(pl->d_tasks, pl->tasks.data(), sizeof(QRTask) * pl->tasks.size(), hipMemcpyHostToDevice, st));
+    }
+  }
+  s.max_site = 0;
+  for (auto& l : s.site) s.max_site = std::max(s.max_site, l.size);
+  s.max_bmat = 0;
+  s.max_bond = 0;
+  s.max_env = 0;
+  for (int k = 0; k <= N; ++k) {
+    s.max_bmat = std::max(s.max_bmat, s.bmat[k].size);
+    s.max_bond = std::max(s.max_bond, s.bonds[k].total);
+    s.max_env = std::max(s.max_env, s.env[k].size);
+  }
+  long long nvec = std::max(s.max_site, s.max_bmat);
+  s.A.resize(N);
+  for (int k = 0; k < N; ++k) s.A[k] = (double*)dalloc(8 * s.site[k].size);
+  s.Lenv.assign(N + 1, nullptr);
+  s.Renv.assign(N + 1, nullptr);
+  for (int k = 0; k <= N; ++k) {
+    s.Lenv[k] = (double*)dalloc(8 * s.env[k].size);
+    s.Renv[k] = (double*)dalloc(8 * s.env[k].size);
+  }
+  s.T1 = (double*)dalloc(8 * std::max(t1, 1LL));
+  s.T2 = (double*)dalloc(8 * std::max(t2, 1LL));
+  s.Y = (double*)dalloc(8 * std::max(y, 1LL));
+  s.Z = (double*)dalloc(8 * std::max(z, 1LL));
+  s.U = (double*)dalloc(8 * std::max(u, 1LL));
+  s.Sbuf = (double*)dalloc(8 * s.max_bmat);
+  s.tmp = (double*)dalloc(8 * s.max_site);
+  s.kry = (double*)dalloc(8 * nvec * (long long)s.opts.krylov_dim);
+  s.wv = (double*)dalloc(8 * nvec);
+  s.qrws = (double*)dalloc(8 * std::max(qw, 1LL));
+  s.part = (double*)dalloc(8 * (long long)kRedBlocks * (kMaxKrylov + 2));
+  s.lz = (double*)dalloc(8 * (4 * kMaxKrylov + 16));
+  launch_fill(s.lz, 0.0, 4 * kMaxKrylov + 16, st);
+  s.vtr = (double*)dalloc(8 * 2 * s.max_bond);
+  // trace entries
+  std::vector<TraceEntry> te;
+  std::vector<int> start{0};
+  int diag_stride = (s.G.ng == 1) ? 5 : 1;
+  for (int k = 0; k < N; ++k) {
+    for (auto& e : s.plans[k].tr) {
+      int l = (int)e[2], r = (int)e[3];
+      TraceEntry t;
+      t.src = e[0]; t.C = e[1];
+      t.xoff = s.bonds[k].secs[l].off; t.dl = s.bonds[k].secs[l].dim;
+      t.yoff = s.bonds[k + 1].secs[r].off; t.dr = s.bonds[k + 1].secs[r].dim;
+      t.site = k; t.diag_stride = diag_stride;
+      te.push_back(t);
+    }
+    start.push_back((int)te.size());
+  }
+  s.d_trace = upload(te, st);
+  s.d_trace_start = upload(start, st);
+  s.d_sites = upload(s.A, st);
+}
+
+// rho0 tensors embedded in the padded block-sparse layout, plus the noise
+void fill_initial_tensors(tt_state& s, std::vector<std::vector<double>>& host) {
+  const int N = s.N;
+  const double b0 = s.opts.beta0;
+  // embedding of rho0 bond states: (sector, local index)
+  std::vector<std::vector<std::pair<int, int>>> emb(N + 1);
+  std::vector<std::vector<int>> n0(N + 1);
+  for (int k = 0; k <= N; ++k) {
+    n0[k].assign(s.bonds[k].secs.size(), 0);
+    int nst = (k == N) ? 1 : s.mpo.DH[k];
+    for (int a = 0; a < nst; ++a) {
+      Q q = (k == N || s.G.ng == 1) ? Q{0, 0} : s.mpo.charge(k, a);
+      int sec = s.bonds[k].find(q);
+      TT_REQUIRE(sec >= 0 && n0[k][sec] < s.bonds[k].secs[sec].dim, TT_EINVAL, "rho0 does not fit the bond sectors");
+      emb[k].push_back({sec, n0[k][sec]});
+      n0[k][sec]++;
+    }
+  }
+  host.assign(N, {});
+  for (int k = 0; k < N; ++k) {
+    const SiteLayout& S = s.site[k];
+    std::vector<double>& h = host[k];
+    h.assign(S.size, 0.0);
+    int DL = s.mpo.DH[k], DR = s.mpo.DH[k + 1];
+    int DRo = (k == N - 1) ? 1 : DR;
+    const Bond& br = s.bonds[k + 1];
+    for (int a = 0; a < DL; ++a)
+      for (int q = 0; q < 16; ++q)
+        for (int b = 0; b < DRo; ++b) {
+          double v;
+          if (k == N - 1) v = s.mpo.W[k][((size_t)a * 16 + q) * DR + 0] - b0 * s.mpo.W[k][((size_t)a * 16 + q) * DR + 1];
+          else v = s.mpo.W[k][((size_t)a * 16 + q) * DR + b];
+          if (v == 0.0) continue;
+          int l = emb[k][a].first, x = emb[k][a].second;
+          int r = emb[k + 1][b].first, y = emb[k + 1][b].second;
+          int g = s.G.group_of[q];
+          TT_REQUIRE(S.rsec[l][g] == r, TT_EINVAL, "rho0 breaks charge conservation");
+          h[S.base[l] + (long long)x * S.C[l] + S.colb[l][g] + (long long)s.G.pos_of[q] * br.secs[r].dim + y] = v;
+        }
+    if (s.opts.pad_eps != 0.0) {
+      const Bond& bl = s.bonds[k];
+      const long long Dr = br.total;
+      for (int l = 0; l < S.nl; ++l)
+        for (int g = 0; g < s.G.ng; ++g) {
+          int r = S.rsec[l][g];
+          if (r < 0) continue;
+          int ns = (int)s.G.s[g].size();
+          for (int x = 0; x < S.dl[l]; ++x)
+            for (int si = 0; si < ns; ++si)
+              for (int y = 0; y < br.secs[r].dim; ++y) {
+                bool pad = (x >= n0[k][l]) || (y >= n0[k + 1][r]);
+                if (!pad) continue;
+                long long xg = bl.secs[l].off + x, yg = br.secs[r].off + y;
+                int sidx = s.G.s[g][si];
+                uint64_t flat = (uint64_t)((xg * 16 + sidx) * Dr + yg);
+                h[S.base[l] + (long long)x * S.C[l] + S.colb[l][g] + (long long)si * br.secs[r].dim + y] =
+                    s.opts.pad_eps * noise_uniform(s.opts.seed, k, flat);
+              }
+        }
+    }
+  }
+}
+
+void set_unit_env(double* e, hipStream_t st) { launch_fill(e, 1.0, 1, st); }
+
+void canonicalise_and_envs(tt_state& s) {
+  const int N = s.N;
+  for (int k = N - 1; k >= 1; --k) {
+    lq_site(s, k);
+    absorb_right(s, k - 1);
+  }
+  launch_fill(s.lam_ptr(), 0.0, 1, ST());
+  normalize_site(s, 0);
+  set_unit_env(s.Lenv[0], ST());
+  set_unit_env(s.Renv[N], ST());
+  for (int k = N - 1; k >= 1; --k) env_right(s, k);
+}
+
+std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
+  const int N = s.N;
+  std::vector<std::map<Q, int>> n0(N + 1);
+  for (int k = 0; k < N; ++k)
+    for (int a = 0; a < s.mpo.DH[k]; ++a) n0[k][s.mpo.charge(k, a)]++;
+  n0[N][{0, 0}] = 1;
+  if (s.opts.symmetry) return allocate_sectors(N, s.opts.D, n0);
+  std::vector<std::map<Q, int>> d(N + 1);
+  for (int k = 0; k <= N; ++k) {
+    int n = (k == N) ? 1 : s.mpo.DH[k];
+    long long mx = pow16_cap(std::min(k, N - k), 1LL << 40);
+    long long v = std::max<long long>(std::min<long long>(s.opts.D, mx), n);
+    d[k][{0, 0}] = (int)v;
+  }
+  return d;
+}
+
+void validate(const tt_model& m, const tt_options& o) {
+  TT_REQUIRE(m.tp == 0.0, TT_EINVAL, "next-nearest hopping tp is not supported");
+  TT_REQUIRE(o.D >= 1, TT_EINVAL, "D must be positive");
+  TT_REQUIRE(o.symmetry == 0 || o.symmetry == 1, TT_EINVAL, "symmetry must be 0 or 1");
+  TT_REQUIRE(o.taylor_order == 1, TT_EINVAL, "only the linear start rho0 = 1 - beta0 H is supported");
+  TT_REQUIRE(o.krylov_dim >= 1 && o.krylov_dim <= kMaxKrylov, TT_EINVAL, "krylov_dim must be in 1..32");
+  TT_REQUIRE(o.krylov_tol >= 0.0, TT_EINVAL, "krylov_tol must be >= 0");
+  TT_REQUIRE(o.precision == TT_FP64, TT_EINVAL, "sweeps run in FP64 only");
+  TT_REQUIRE(o.env_on_host == 0, TT_EINVAL, "host-resident environments are not supported");
+  TT_REQUIRE(std::isfinite(o.beta0) && std::isfinite(o.pad_eps), TT_EINVAL, "beta0 and pad_eps must be finite");
+  TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.U) && std::isfinite(m.mu), TT_EINVAL, "model parameters must be finite");
+}
+
+std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o) {
+  validate(m, o);
+  auto s = std::make_unique<tt_state>();
+  s->model = m;
+  s->opts = o;
+  s->lat = make_lattice(m.W, m.L, m.geometry);
+  s->N = s->lat.N;
+  s->mpo = make_hubbard_mpo(s->lat, m.t, m.U, m.mu);
+  s->G = make_groups(o.symmetry == 1);
+  build_layouts(*s, bond_dims(*s));
+  return s;
+}
+
+std::unique_ptr<tt_state> make_state(const tt_model& m, const tt_options& o) {
+  auto s = make_host_state(m, o);
+  check_device();
+  alloc_state(*s);
+  return s;
+}
+
+// ---------------------------------------------------------------- plan bounds check
+// Every index a kernel will form, checked on the host against the buffer it addresses.
+struct Range { long long lo = 0, hi = -1; void add(long long v) { if (hi < lo) { lo = hi = v; } else { lo = std::min(lo, v); hi = std::max(hi, v); } } };
+
+Range map_range(const std::vector<long long>& tabs, long long tab, long long stride, int n) {
+  Range r;
+  if (n <= 0) return r;
+  if (tab >= 0) {
+    for (int i = 0; i < n; ++i) r.add(tabs.at(tab + i));
+  } else {
+    r.add(0);
+    r.add((long long)(n - 1) * stride);
+  }
+  return r;
+}
+
+long long check_gemm(const GemmPlan& p, const std::vector<long long>& tabs, const long long size[kSlots],
+                     const char* name, std::string& rep) {
+  long long bad = 0;
+  for (size_t i = 0; i < p.probs.size(); ++i) {
+    const GemmProb& g = p.probs[i];
+    Range am = map_range(tabs, g.tam, g.sam, g.M), ak = map_range(tabs, g.tak, g.sak, g.K);
+    Range bk = map_range(tabs, g.tbk, g.sbk, g.K), bn = map_range(tabs, g.tbn, g.sbn, g.N);
+    Range cm = map_range(tabs, g.tcm, g.scm, g.M);
+    auto chk = [&](int slot, long long off, Range a, Range b, long long extra_hi, const char* op) {
+      if (g.K == 0 && op[0] != 'C') return;
+      long long lo = off + a.lo + b.lo, hi = off + a.hi + b.hi + extra_hi;
+      if (slot < 0 || slot >= kSlots || lo < 0 || hi >= size[slot]) {
+        ++bad;
+        if (rep.size() < 2000)
+          rep += std::string(name) + " prob " + std::to_string(i) + " operand " + op + " [" + std::to_string(lo) +
+                 "," + std::to_string(hi) + "] size " + std::to_string(slot >= 0 && slot < kSlots ? size[slot] : -1) + "\n";
+      }
+    };
+    chk(g.ia, g.offA, am, ak, 0, "A");
+    chk(g.ib, g.offB, bk, bn, 0, "B");
+    chk(g.ic, g.offC, cm, Range{0, 0}, g.N - 1, "C");
+  }
+  for (auto& t : p.tiles)
+    if (t.prob < 0 || t.prob >= (int)p.probs.size()) ++bad;
+  return bad;
+}
+
+long long check_w(const WPlan& p, long long in_size, long long out_size, const char* name, std::string& rep) {
+  long long bad = 0;
+  for (size_t i = 0; i < p.tasks.size(); ++i) {
+    const WTask& t = p.tasks[i];
+    if (t.ni <= 0 || t.nj <= 0) continue;
+    long long hi = t.dst + (long long)(t.ni - 1) * t.dsi + (long long)(t.nj - 1) * t.dsj;
+    if (t.dst < 0 || hi >= out_size) ++bad;
+    if (t.t0 < 0 || t.t0 + t.nt > (int)p.terms.size()) { ++bad; continue; }
+    for (int q = t.t0; q < t.t0 + t.nt; ++q) {
+      const WTerm& w = p.terms[q];
+      long long h2 = w.src + (long long)(t.ni - 1) * w.ssi + (long long)(t.nj - 1) * w.ssj;
+      if (w.src < 0 || h2 >= in_size) {
+        ++bad;
+        if (rep.size() < 2000) rep += std::string(name) + " task " + std::to_string(i) + " term out of range\n";
+      }
+    }
+  }
+  return bad;
+}
+
+long long check_qr(const QRPlan& p, const std::vector<long long>& tabs, long long a_size, long long s_size,
+                   const char* name, std::string& rep) {
+  long long bad = 0;
+  long long ws = 0;
+  for (size_t i = 0; i < p.tasks.size(); ++i) {
+    const QRTask& t = p.tasks[i];
+    if (t.m < t.n) { ++bad; rep += std::string(name) + " task with m < n\n"; continue; }
+    Range r = map_range(tabs, t.rtab, t.rs, t.m);
+    long long lo = t.rbase + r.lo, hi = t.rbase + r.hi + (long long)(t.n - 1) * t.cs;
+    if (lo < 0 || hi >= a_size) ++bad;
+    if (t.sdst < 0 || t.sdst + (long long)t.n * t.n > s_size) ++bad;
+    ws += 2LL * t.m * t.n + t.n;
+  }
+  (void)ws;
+  return bad;
+}
+
+long long check_all_plans(tt_state& s, std::string& rep) {
+  long long bad = 0;
+  const int N = s.N;
+  long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, msite = 0, mb = 0;
+  for (auto& P : s.plans) {
+    t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size); y = std::max(y, P.y_size);
+    z = std::max(z, P.z_size); u = std::max(u, P.u_size);
+  }
+  for (auto& l : s.site) msite = std::max(msite, l.size);
+  for (auto& b : s.bmat) mb = std::max(mb, b.size);
+  const auto& T = s.tabs.host;
+  for (int k = 0; k < N; ++k) {
+    SitePlan& P = s.plans[k];
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2}) tile_plan(*g, 64, 64);
+    long long ns = s.site[k].size, el = s.env[k].size, er = s.env[k + 1].size;
+    long long s1[kSlots] = {el, ns, t1, 0}, s3[kSlots] = {t2, er, ns, 0}, se[kSlots] = {ns, t2, er, 0};
+    long long r1[kSlots] = {er, ns, y, 0}, r3[kSlots] = {ns, z, el, 0};
+    long long aL[kSlots] = {s.bmat[k].size, ns, msite, 0}, aR[kSlots] = {ns, s.bmat[k + 1].size, msite, 0};
+    long long b1[kSlots] = {el, s.bmat[k].size, u, 0}, b2[kSlots] = {u, el, s.bmat[k].size, 0};
+    bad += check_gemm(P.s1, T, s1, "s1", rep);
+    bad += check_gemm(P.s3, T, s3, "s3", rep);
+    bad += check_gemm(P.el, T, se, "el", rep);
+    bad += check_gemm(P.r1, T, r1, "r1", rep);
+    bad += check_gemm(P.r3, T, r3, "r3", rep);
+    bad += check_gemm(P.absL, T, aL, "absL", rep);
+    bad += check_gemm(P.absR, T, aR, "absR", rep);
+    bad += check_gemm(P.b1, T, b1, "b1", rep);
+    bad += check_gemm(P.b2, T, b2, "b2", rep);
+    bad += check_w(P.w2, P.t1_size, P.t2_size, "w2", rep);
+    bad += check_w(P.wr, P.y_size, P.z_size, "wr", rep);
+    bad += check_qr(P.qr, T, ns, s.bmat[k + 1].size, "qr", rep);
+    bad += check_qr(P.lq, T, ns, s.bmat[k].size, "lq", rep);
+    int ds = (s.G.ng == 1) ? 5 : 1;
+    for (auto& e : P.tr) {
+      int l = (int)e[2], r = (int)e[3];
+      long long dl = s.bonds[k].secs[l].dim, dr = s.bonds[k + 1].secs[r].dim;
+      long long hi = e[0] + (dl - 1) * e[1] + 3LL * ds * dr + dr - 1;
+      if (hi >= ns) ++bad;
+    }
+  }
+  return bad;
+}
+
+int fail(const Error& e) { g_err = e.what(); return e.code; }
+
+#define ABI_BEGIN try {
+#define ABI_END                                                   \
+  }                                                               \
+  catch (const Error& e) { return fail(e); }                      \
+  catch (const std::bad_alloc&) { g_err = "host allocation failed"; return TT_ENOMEM; } \
+  catch (const std::exception& e) { g_err = e.what(); return TT_EINVAL; }             \
+  return TT_OK;
+
+void fill_stats(tt_state& s, tt_sweep_stats* st, double secs) {
+  double err = 0.0;
+  HIPX(hipMemcpyAsync(&err, s.err_ptr(), 8, hipMemcpyDeviceToHost, ST()));
+  HIPX(hipStreamSynchronize(ST()));
+  st->seconds += secs;
+  st->flops_alg += s.flops;
+  st->flops_heff += s.flops_heff;
+  st->n_applies += s.n_applies;
+  st->n_exps += s.n_exps;
+  st->max_krylov_err = std::max(st->max_krylov_err, err);
+}
+void reset_counters(tt_state& s) { s.flops = s.flops_heff = 0.0; s.n_applies = s.n_exps = 0; }
+
+// -------------------------------------------------------------- dense microbenchmark
+struct HeffCache {
+  int Dl = -1, Dr = -1, DH = -1;
+  SitePlan plan;
+  SiteTables tabs;
+  GemmPlan wg;
+  double *T1 = nullptr, *T2 = nullptr;
+  long long t1 = 0, t2 = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+};
+HeffCache g_heff;
+
+void build_heff_cache(int Dl, int Dr, int DH) {
+  HeffCache& c = g_heff;
+  free_plan(c.plan.s1); free_plan(c.plan.s3); free_plan(c.wg);
+  dfree(c.tabs.dev); c.tabs = SiteTables();
+  Bond bl, br;
+  bl.add({0, 0}, Dl);
+  br.add({0, 0}, Dr);
+  Groups G = make_groups(false);
+  std::vector<Q> qh(DH, Q{0, 0});
+  // the plan's W stage is replaced by a grouped GEMM reading W from device memory;
+  // an all-zero W keeps the sparse W-stage plan empty
+  std::vector<double> Wz((size_t)DH * 16 * DH, 0.0);
+  c.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, c.tabs);
+  // W stage as GEMMs: for each (x, sigma'): T2[(so,b)][y] = sum_(a,si) W[(so,b),(a,si)] T1[(a,si)][y]
+  std::vector<long long> am, ak, bk, cm;
+  for (int so = 0; so < 4; ++so)
+    for (int b = 0; b < DH; ++b) am.push_back((long long)so * 4 * DH + b);
+  for (int a = 0; a < DH; ++a)
+    for (int si = 0; si < 4; ++si) {
+      ak.push_back((long long)a * 16 * DH + (long long)si * DH);
+      bk.push_back((long long)a * Dl * 16 * Dr + (long long)si * 4 * Dr);
+    }
+  for (int so = 0; so < 4; ++so)
+    for (int b = 0; b < DH; ++b) cm.push_back((long long)4 * so * DH * Dr + (long long)b * Dr);
+  long long tam = c.tabs.add(am), tak = c.tabs.add(ak), tbk = c.tabs.add(bk), tcm = c.tabs.add(cm);
+  c.wg = GemmPlan();
+  for (int x = 0; x < Dl; ++x)
+    for (int sp = 0; sp < 4; ++sp) {
+      GemmProb g{};
+      g.M = 4 * DH; g.N = Dr; g.K = 4 * DH;
+      g.ia = 0; g.ib = 1; g.ic = 2;
+      g.tam = tam; g.tak = tak; g.tbk = tbk; g.tbn = -1; g.tcm = tcm;
+      g.sbn = 1;
+      g.offB = (long long)x * 16 * Dr + (long long)sp * Dr;
+      g.offC = ((long long)x * 16 + sp) * DH * Dr;
+      g.alpha = 1.0; g.beta = 0.0;
+      c.wg.probs.push_back(g);
+      c.wg.flops += 2.0 * g.M * (double)g.N * g.K;
+    }
+  hipStream_t st = ST();
+  c.tabs.dev = upload(c.tabs.host, st);
+  upload_plan(c.plan.s1, st);
+  upload_plan(c.plan.s3, st);
+  upload_plan(c.wg, st);
+  if (c.plan.t1_size > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * c.plan.t1_size); c.t1 = c.plan.t1_size; }
+  if (c.plan.t2_size > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * c.plan.t2_size); c.t2 = c.plan.t2_size; }
+  for (int i = 0; i < 4; ++i)
+    if (!c.ev[i]) HIPX(hipEventCreate(&c.ev[i]));
+  c.Dl = Dl; c.Dr = Dr; c.DH = DH;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* tt_last_error(void) { return g_err.c_str(); }
+
+int tt_options_default(tt_options* o) {
+  if (!o) { g_err = "null options"; return TT_EINVAL; }
+  o->D = 64; o->symmetry = 1; o->beta0 = 1e-2; o->taylor_order = 1;
+  o->krylov_dim = 8; o->krylov_tol = 1e-13; o->precision = TT_FP64;
+  o->pad_eps = 0.0; o->seed = 1; o->env_on_host = 0;
+  return TT_OK;
+}
+
+int tt_set_stream(void* stream) {
+  g_stream = (hipStream_t)stream;
+  return TT_OK;
+}
+
+int tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) { g_err = "give both allocator functions or neither"; return TT_EINVAL; }
+  g_alloc = alloc; g_free = free_fn; g_alloc_ctx = ctx;
+  return TT_OK;
+}
+
+int mpo_init_highT(const tt_model* model, const tt_options* opts, tt_state** out) {
+  ABI_BEGIN
+  TT_REQUIRE(model && opts && out, TT_EINVAL, "null argument");
+  *out = nullptr;
+  auto s = make_state(*model, *opts);
+  std::vector<std::vector<double>> host;
+  fill_initial_tensors(*s, host);
+  for (int k = 0; k < s->N; ++k)
+    HIPX(hipMemcpyAsync(s->A[k], host[k].data(), 8 * host[k].size(), hipMemcpyHostToDevice, ST()));
+  canonicalise_and_envs(*s);
+  s->beta = opts->beta0;
+  HIPX(hipStreamSynchronize(ST()));
+  *out = s.release();
+  ABI_END
+}
+
+int tdvp_sweep(tt_state* s, double dbeta, tt_sweep_stats* stats) {
+  ABI_BEGIN
+  TT_REQUIRE(s, TT_EINVAL, "null state");
+  TT_REQUIRE(std::isfinite(dbeta), TT_EINVAL, "dbeta must be finite");
+  reset_counters(*s);
+  auto t0 = std::chrono::steady_clock::now();
+  sweep_once(*s, dbeta);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    HIPX(hipStreamSynchronize(ST()));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(*s, stats, secs);
+  }
+  ABI_END
+}
+
+int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* stats) {
+  ABI_BEGIN
+  TT_REQUIRE(states && n >= 1, TT_EINVAL, "need at least one state");
+  for (int i = 0; i < n; ++i) TT_REQUIRE(states[i], TT_EINVAL, "null state in batch");
+  auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < n; ++i) {
+    reset_counters(*states[i]);
+    sweep_once(*states[i], dbeta);
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    HIPX(hipStreamSynchronize(ST()));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < n; ++i) fill_stats(*states[i], stats, i == 0 ? secs : 0.0);
+  }
+  ABI_END
+}
+
+int thermo_observables(tt_state* s, tt_observables* o) {
+  ABI_BEGIN
+  TT_REQUIRE(s && o, TT_EINVAL, "null argument");
+  const long long n = s->site[0].size;
+  apply_heff1(*s, 0, s->A[0], s->wv);
+  double* ob = s->obs_ptr();
+  launch_mdot(s->A[0], n, 1, s->wv, n, 0, s->part, ST());
+  launch_dot_final(s->part, kRedBlocks, 1, ob, ST());
+  launch_mdot(nullptr, 0, 0, s->A[0], n, 1, s->part, ST());
+  launch_dot_final(s->part, kRedBlocks, 1, ob + 1, ST());
+  launch_trace(s->d_trace, s->d_trace_start, s->N, s->d_sites, s->vtr, s->max_bond, ob + 2, ST());
+  double h[4], lam;
+  HIPX(hipMemcpyAsync(h, ob, 32, hipMemcpyDeviceToHost, ST()));
+  HIPX(hipMemcpyAsync(&lam, s->lam_ptr(), 8, hipMemcpyDeviceToHost, ST()));
+  HIPX(hipStreamSynchronize(ST()));
+  o->beta = s->beta;
+  o->beta_phys = 2.0 * s->beta;
+  o->lambda = lam;
+  o->lnZ = 2.0 * lam;
+  o->n_sites = s->N;
+  o->f = -o->lnZ / (s->N * o->beta_phys);
+  o->E = h[0] / h[1];
+  o->e = o->E / s->N;
+  o->lnZ_single = lam + h[2];
+  TT_REQUIRE(std::isfinite(o->lnZ) && std::isfinite(o->E), TT_ENUMERIC, "non-finite observables");
+  ABI_END
+}
+
+void tt_state_free(tt_state* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(ST());
+  delete s;
+}
+
+int tt_state_info(const tt_state* s, int* n_sites, int* dims) {
+  ABI_BEGIN
+  TT_REQUIRE(s && n_sites, TT_EINVAL, "null argument");
+  *n_sites = s->N;
+  if (dims)
+    for (int k = 0; k <= s->N; ++k) dims[k] = (int)s->bonds[k].total;
+  ABI_END
+}
+
+int tt_state_bond_sectors(const tt_state* s, int k, int* nsec, int* qu, int* qd, int* dim) {
+  ABI_BEGIN
+  TT_REQUIRE(s && nsec, TT_EINVAL, "null argument");
+  TT_REQUIRE(k >= 0 && k <= s->N, TT_EINVAL, "bond index out of range");
+  const Bond& b = s->bonds[k];
+  int ns = (int)b.secs.size();
+  if (qu || qd || dim) {
+    TT_REQUIRE(*nsec >= ns, TT_EINVAL, "sector arrays too small");
+    for (int i = 0; i < ns; ++i) {
+      if (qu) qu[i] = b.secs[i].q.first;
+      if (qd) qd[i] = b.secs[i].q.second;
+      if (dim) dim[i] = b.secs[i].dim;
+    }
+  }
+  *nsec = ns;
+  ABI_END
+}
+
+static void site_dense_map(const tt_state* s, int k, const std::function<void(long long, long long)>& f) {
+  const SiteLayout& S = s->site[k];
+  const Bond& bl = s->bonds[k];
+  const Bond& br = s->bonds[k + 1];
+  const long long Dr = br.total;
+  for (int l = 0; l < S.nl; ++l)
+    for (int g = 0; g < s->G.ng; ++g) {
+      int r = S.rsec[l][g];
+      if (r < 0) continue;
+      int ns = (int)s->G.s[g].size();
+      for (int x = 0; x < S.dl[l]; ++x)
+        for (int si = 0; si < ns; ++si)
+          for (int y = 0; y < br.secs[r].dim; ++y) {
+            long long src = S.base[l] + (long long)x * S.C[l] + S.colb[l][g] + (long long)si * br.secs[r].dim + y;
+            long long dst = ((bl.secs[l].off + x) * 16 + s->G.s[g][si]) * Dr + br.secs[r].off + y;
+            f(src, dst);
+          }
+    }
+}
+
+int tt_state_export_site(const tt_state* s, int k, double* host) {
+  ABI_BEGIN
+  TT_REQUIRE(s && host, TT_EINVAL, "null argument");
+  TT_REQUIRE(k >= 0 && k < s->N, TT_EINVAL, "site index out of range");
+  std::vector<double> packed(s->site[k].size);
+  HIPX(hipMemcpyAsync(packed.data(), s->A[k], 8 * packed.size(), hipMemcpyDeviceToHost, ST()));
+  HIPX(hipStreamSynchronize(ST()));
+  long long tot = s->bonds[k].total * 16 * s->bonds[k + 1].total;
+  std::memset(host, 0, 8 * tot);
+  site_dense_map(s, k, [&](long long src, long long dst) { host[dst] = packed[src]; });
+  ABI_END
+}
+
+int tt_state_import_site(tt_state* s, int k, const double* host) {
+  ABI_BEGIN
+  TT_REQUIRE(s && host, TT_EINVAL, "null argument");
+  TT_REQUIRE(k >= 0 && k < s->N, TT_EINVAL, "site index out of range");
+  std::vector<double> packed(s->site[k].size);
+  bool finite = true;
+  site_dense_map(s, k, [&](long long src, long long dst) {
+    packed[src] = host[dst];
+    finite = finite && std::isfinite(host[dst]);
+  });
+  TT_REQUIRE(finite, TT_ENUMERIC, "imported tensor holds NaN or Inf");
+  HIPX(hipMemcpyAsync(s->A[k], packed.data(), 8 * packed.size(), hipMemcpyHostToDevice, ST()));
+  HIPX(hipStreamSynchronize(ST()));
+  ABI_END
+}
+
+static const char kMagic[8] = {'T', 'A', 'N', 'T', 'R', 'G', '0', '1'};
+
+int tt_state_save(const tt_state* s, const char* path) {
+  ABI_BEGIN
+  TT_REQUIRE(s && path, TT_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "wb");
+  TT_REQUIRE(f, TT_EIO, std::string("cannot open ") + path);
+  std::unique_ptr<FILE, int (*)(FILE*)> guard(f, std::fclose);
+  double lam = 0.0;
+  HIPX(hipMemcpyAsync(&lam, const_cast<tt_state*>(s)->lam_ptr(), 8, hipMemcpyDeviceToHost, ST()));
+  HIPX(hipStreamSynchronize(ST()));
+  bool ok = std::fwrite(kMagic, 1, 8, f) == 8;
+  ok = ok && std::fwrite(&s->model, sizeof(tt_model), 1, f) == 1;
+  ok = ok && std::fwrite(&s->opts, sizeof(tt_options), 1, f) == 1;
+  ok = ok && std::fwrite(&s->beta, 8, 1, f) == 1;
+  ok = ok && std::fwrite(&lam, 8, 1, f) == 1;
+  ok = ok && std::fwrite(&s->sweeps, 8, 1, f) == 1;
+  for (int k = 0; k <= s->N && ok; ++k) {
+    int ns = (int)s->bonds[k].secs.size();
+    ok = std::fwrite(&ns, 4, 1, f) == 1;
+    for (auto& sec : s->bonds[k].secs) {
+      int v[3] = {sec.q.first, sec.q.second, sec.dim};
+      ok = ok && std::fwrite(v, 4, 3, f) == 3;
+    }
+  }
+  for (int k = 0; k < s->N && ok; ++k) {
+    std::vector<double> packed(s->site[k].size);
+    HIPX(hipMemcpyAsync(packed.data(), s->A[k], 8 * packed.size(), hipMemcpyDeviceToHost, ST()));
+    HIPX(hipStreamSynchronize(ST()));
+    long long n = (long long)packed.size();
+    ok = std::fwrite(&n, 8, 1, f) == 1 && std::fwrite(packed.data(), 8, n, f) == (size_t)n;
+  }
+  TT_REQUIRE(ok, TT_EIO, "write failed");
+  ABI_END
+}
+
+int tt_state_load(const char* path, tt_state** out) {
+  ABI_BEGIN
+  TT_REQUIRE(path && out, TT_EINVAL, "null argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  TT_REQUIRE(f, TT_EIO, std::string("cannot open ") + path);
+  std::unique_ptr<FILE, int (*)(FILE*)> guard(f, std::fclose);
+  char magic[8];
+  tt_model m;
+  tt_options o;
+  double beta, lam;
+  long long sweeps;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0;
+  TT_REQUIRE(ok, TT_EIO, "not a saved tanTRG state");
+  ok = std::fread(&m, sizeof(m), 1, f) == 1 && std::fread(&o, sizeof(o), 1, f) == 1 &&
+       std::fread(&beta, 8, 1, f) == 1 && std::fread(&lam, 8, 1, f) == 1 && std::fread(&sweeps, 8, 1, f) == 1;
+  TT_REQUIRE(ok, TT_EIO, "truncated state file");
+  validate(m, o);
+  check_device();
+  auto s = std::make_unique<tt_state>();
+  s->model = m;
+  s->opts = o;
+  s->lat = make_lattice(m.W, m.L, m.geometry);
+  s->N = s->lat.N;
+  s->mpo = make_hubbard_mpo(s->lat, m.t, m.U, m.mu);
+  s->G = make_groups(o.symmetry == 1);
+  std::vector<std::map<Q, int>> dims(s->N + 1);
+  for (int k = 0; k <= s->N; ++k) {
+    int ns = 0;
+    TT_REQUIRE(std::fread(&ns, 4, 1, f) == 1 && ns >= 1 && ns < 1000000, TT_EIO, "bad sector table");
+    for (int i = 0; i < ns; ++i) {
+      int v[3];
+      TT_REQUIRE(std::fread(v, 4, 3, f) == 3 && v[2] >= 1, TT_EIO, "bad sector table");
+      dims[k][{v[0], v[1]}] = v[2];
+    }
+  }
+  build_layouts(*s, dims);
+  alloc_state(*s);
+  for (int k = 0; k < s->N; ++k) {
+    long long n = 0;
+    TT_REQUIRE(std::fread(&n, 8, 1, f) == 1 && n == s->site[k].size, TT_EIO, "site size mismatch");
+    std::vector<double> packed(n);
+    TT_REQUIRE(std::fread(packed.data(), 8, n, f) == (size_t)n, TT_EIO, "truncated site data");
+    HIPX(hipMemcpyAsync(s->A[k], packed.data(), 8 * n, hipMemcpyHostToDevice, ST()));
+  }
+  HIPX(hipMemcpyAsync(s->lam_ptr(), &lam, 8, hipMemcpyHostToDevice, ST()));
+  set_unit_env(s->Lenv[0], ST());
+  set_unit_env(s->Renv[s->N], ST());
+  for (int k = s->N - 1; k >= 1; --k) env_right(*s, k);
+  s->beta = beta;
+  s->sweeps = sweeps;
+  HIPX(hipStreamSynchronize(ST()));
+  *out = s.release();
+  ABI_END
+}
+
+int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, const double* A, const double* R,
+                  double* out, int precision, void* stream) {
+  ABI_BEGIN
+  TT_REQUIRE(Dl >= 1 && Dr >= 1 && DH >= 1, TT_EINVAL, "dimensions must be positive");
+  TT_REQUIRE(L && W && A && R && out, TT_EINVAL, "null device pointer");
+  TT_REQUIRE(precision == TT_FP64, TT_EINVAL, "unsupported precision");
+  TT_REQUIRE((double)Dl * DH * 16 * Dr < 4.0e9, TT_EINVAL, "problem too large");
+  hipStream_t saved = g_stream;
+  if (stream) g_stream = (hipStream_t)stream;
+  try {
+    if (g_heff.Dl != Dl || g_heff.Dr != Dr || g_heff.DH != DH) build_heff_cache(Dl, Dr, DH);
+    HeffCache& c = g_heff;
+    hipStream_t st = ST();
+    HIPX(hipEventRecord(c.ev[0], st));
+    launch_gemm(c.plan.s1, c.tabs.dev, Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}},
+                precision, st);
+    HIPX(hipEventRecord(c.ev[1], st));
+    launch_gemm(c.wg, c.tabs.dev, Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}, precision, st);
+    HIPX(hipEventRecord(c.ev[2], st));
+    launch_gemm(c.plan.s3, c.tabs.dev, Slots{{c.T2, const_cast<double*>(R), out, nullptr}}, precision, st);
+    HIPX(hipEventRecord(c.ev[3], st));
+    c.timed = true;
+  } catch (...) {
+    g_stream = saved;
+    throw;
+  }
+  g_stream = saved;
+  ABI_END
+}
+
+int tt_check_plans(const tt_model* model, const tt_options* opts, long long* violations, long long* work_doubles) {
+  ABI_BEGIN
+  TT_REQUIRE(model && opts && violations, TT_EINVAL, "null argument");
+  auto s = make_host_state(*model, *opts);
+  std::string rep;
+  *violations = check_all_plans(*s, rep);
+  if (work_doubles) {
+    long long tot = 0;
+    for (auto& l : s->site) tot += l.size;
+    for (auto& e : s->env) tot += 2 * e.size;
+    *work_doubles = tot;
+  }
+  if (*violations) g_err = rep;
+  ABI_END
+}
+
+int tt_model_bond_sectors(const tt_model* model, const tt_options* opts, int k, int* nsec, int* qu, int* qd,
+                          int* dim) {
+  ABI_BEGIN
+  TT_REQUIRE(model && opts && nsec, TT_EINVAL, "null argument");
+  auto s = make_host_state(*model, *opts);
+  return tt_state_bond_sectors(s.get(), k, nsec, qu, qd, dim);
+  ABI_END
+}
+
+int tt_heff_last_timing(double* ms4) {
+  ABI_BEGIN
+  TT_REQUIRE(ms4, TT_EINVAL, "null argument");
+  TT_REQUIRE(g_heff.timed, TT_EINVAL, "no timed apply yet");
+  HIPX(hipEventSynchronize(g_heff.ev[3]));
+  float a, b, c, d;
+  HIPX(hipEventElapsedTime(&a, g_heff.ev[0], g_heff.ev[1]));
+  HIPX(hipEventElapsedTime(&b, g_heff.ev[1], g_heff.ev[2]));
+  HIPX(hipEventElapsedTime(&c, g_heff.ev[2], g_heff.ev[3]));
+  HIPX(hipEventElapsedTime(&d, g_heff.ev[0], g_heff.ev[3]));
+  ms4[0] = a; ms4[1] = b; ms4[2] = c; ms4[3] = d;
+  ABI_END
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// Launch wrappers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace tt {
+
+// reduction geometry: fixed block count so that every sum has a fixed order
+constexpr int kRedBlocks = 256;
+constexpr int kMaxKrylov = 32;
+
+void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, hipStream_t st);
+void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st);
+void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, double* ws, hipStream_t st);
+
+// Lanczos pieces (see engine for the sequence)
+void launch_mdot(const double* Q, long long ld, int nv, const double* y, long long n, int with_self,
+                 double* part, hipStream_t st);
+void launch_lz_start(const double* v, double* q0, long long n, const double* part, double* scal,
+                     hipStream_t st);
+void launch_lz_sub(double* w, const double* Q, long long ld, int nv, const double* part, int nparts,
+                   long long n, double* alpha_out, double* hn_out, hipStream_t st);
+void launch_lz_next(const double* w, double* qn, long long n, const double* part, double* beta_out,
+                    const double* hn, double tol, hipStream_t st);
+void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t,
+                      double tol, const double* scal, double* coeff, double* errmax, hipStream_t st);
+void launch_lz_combine(const double* Q, long long ld, int K, const double* coeff, double* out,
+                       long long n, hipStream_t st);
+void launch_normalize_log(double* v, long long n, const double* part, double* lambda, hipStream_t st);
+void launch_copy(double* dst, const double* src, long long n, hipStream_t st);
+void launch_fill(double* dst, double val, long long n, hipStream_t st);
+void launch_dot_final(const double* part, int nparts, int nv, double* out, hipStream_t st);
+
+struct TraceEntry { long long src, C, xoff, dl, yoff, dr; int site, diag_stride; };
+void launch_trace(const TraceEntry* d_entries, const int* d_site_start, int N, double* const* d_sites,
+                  double* vbuf, long long vlen, double* out2, hipStream_t st);
+
+}  // namespace tt

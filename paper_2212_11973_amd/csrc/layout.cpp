@@ -1,0 +1,400 @@
+// Block-sparse layouts and the descriptor lists of every contraction of one
+// site.  Each contraction of the one-site sweep (SM Fig. optimalB(c,d) and the
+// environment recursion) becomes a grouped GEMM over charge blocks, in the
+// contraction order of SM Fig. Lanczos (L.A, then W, then R); with one sector
+// per bond (no symmetry) each grouped GEMM is a single dense GEMM.
+#include <algorithm>
+#include <cmath>
+
+#include "plan.h"
+
+namespace tt {
+
+static Q addq(Q a, Q b) { return {a.first + b.first, a.second + b.second}; }
+static Q subq(Q a, Q b) { return {a.first - b.first, a.second - b.second}; }
+
+SiteLayout make_site_layout(const Bond& left, const Bond& right, const Groups& G) {
+  SiteLayout s;
+  s.nl = (int)left.secs.size();
+  s.dl.resize(s.nl);
+  s.C.resize(s.nl);
+  s.base.resize(s.nl);
+  s.rsec.resize(s.nl);
+  s.colb.resize(s.nl);
+  long long pos = 0;
+  for (int l = 0; l < s.nl; ++l) {
+    s.dl[l] = left.secs[l].dim;
+    int c = 0;
+    for (int g = 0; g < 9; ++g) { s.rsec[l][g] = -1; s.colb[l][g] = -1; }
+    for (int g = 0; g < G.ng; ++g) {
+      int r = right.find(addq(left.secs[l].q, G.delta[g]));
+      if (r < 0) continue;
+      s.rsec[l][g] = r;
+      s.colb[l][g] = c;
+      c += (int)G.s[g].size() * right.secs[r].dim;
+    }
+    s.C[l] = c;
+    s.base[l] = pos;
+    pos += (long long)s.dl[l] * c;
+  }
+  s.size = pos;
+  return s;
+}
+
+EnvLayout make_env_layout(const Bond& bond, const std::vector<Q>& qH) {
+  EnvLayout e;
+  e.np = (int)bond.secs.size();
+  e.dp.resize(e.np);
+  e.K.resize(e.np);
+  e.base.resize(e.np);
+  e.csec.assign(e.np, std::vector<int>(qH.size(), -1));
+  e.colb.assign(e.np, std::vector<int>(qH.size(), -1));
+  long long pos = 0;
+  for (int p = 0; p < e.np; ++p) {
+    e.dp[p] = bond.secs[p].dim;
+    int c = 0;
+    for (size_t a = 0; a < qH.size(); ++a) {
+      int x = bond.find(subq(bond.secs[p].q, qH[a]));
+      if (x < 0) continue;
+      e.csec[p][a] = x;
+      e.colb[p][a] = c;
+      c += bond.secs[x].dim;
+    }
+    e.K[p] = c;
+    e.base[p] = pos;
+    pos += (long long)e.dp[p] * c;
+  }
+  e.size = pos;
+  return e;
+}
+
+BondMatLayout make_bondmat_layout(const Bond& bond) {
+  BondMatLayout b;
+  long long pos = 0;
+  for (auto& s : bond.secs) {
+    b.off.push_back(pos);
+    pos += (long long)s.dim * s.dim;
+  }
+  b.size = pos;
+  return b;
+}
+
+static GemmProb gp(int M, int N, int K, int ia, int ib, int ic) {
+  GemmProb p{};
+  p.M = M; p.N = N; p.K = K;
+  p.ia = ia; p.ib = ib; p.ic = ic;
+  p.tam = p.tak = p.tbk = p.tbn = p.tcm = -1;
+  p.alpha = 1.0; p.beta = 0.0;
+  return p;
+}
+
+static void add_prob(GemmPlan& plan, const GemmProb& p) {
+  if (p.M <= 0 || p.N <= 0) return;
+  plan.probs.push_back(p);
+  plan.flops += 2.0 * p.M * (double)p.N * p.K;
+}
+
+void tile_plan(GemmPlan& p, int BM, int BN) {
+  p.tiles.clear();
+  for (int i = 0; i < (int)p.probs.size(); ++i) {
+    int tm = (p.probs[i].M + BM - 1) / BM, tn = (p.probs[i].N + BN - 1) / BN;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) p.tiles.push_back({i, a, b});
+  }
+  p.ntiles = (int)p.tiles.size();
+}
+
+SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
+                         const std::vector<Q>& qHl, const std::vector<Q>& qHr,
+                         const std::vector<double>& W, SiteTables& tabs) {
+  (void)k;
+  SitePlan P;
+  const int DHl = (int)qHl.size(), DHr = (int)qHr.size();
+  SiteLayout S = make_site_layout(bl, br, G);
+  EnvLayout EL = make_env_layout(bl, qHl);
+  EnvLayout ER = make_env_layout(br, qHr);
+  auto Wat = [&](int a, int so, int si, int b) { return W[(((size_t)a * 4 + so) * 4 + si) * DHr + b]; };
+  const int nr = (int)br.secs.size();
+
+  // ---------------- stage 1: T1_l[(a,x)][cols of A_l] = L[x,a,l-block] . A_l
+  std::vector<long long> t1base(S.nl, 0);
+  std::vector<std::vector<int>> rowbase1(S.nl, std::vector<int>(DHl, -1));
+  long long pos = 0;
+  for (int l = 0; l < S.nl; ++l) {
+    std::vector<long long> rows;
+    for (int a = 0; a < DHl; ++a) {
+      int p = bl.find(addq(bl.secs[l].q, qHl[a]));
+      if (p < 0 || EL.csec[p][a] != l) continue;
+      rowbase1[l][a] = (int)rows.size();
+      for (int x = 0; x < EL.dp[p]; ++x) rows.push_back(EL.base[p] + (long long)x * EL.K[p] + EL.colb[p][a]);
+    }
+    t1base[l] = pos;
+    GemmProb g = gp((int)rows.size(), S.C[l], S.dl[l], 0, 1, 2);
+    g.tam = tabs.add(rows); g.sak = 1;
+    g.offB = S.base[l]; g.sbk = S.C[l]; g.sbn = 1;
+    g.offC = pos; g.scm = S.C[l];
+    add_prob(P.s1, g);
+    pos += (long long)rows.size() * S.C[l];
+  }
+  P.t1_size = pos;
+
+  // ---------------- W stage: T2 grouped by the right bra sector r'
+  // rows (p, g', x, s'), cols (b, y) as in the R environment of sector r'
+  std::vector<long long> t2base(nr, 0);
+  std::vector<int> nrows2(nr, 0);
+  std::vector<std::vector<long long>> outrows(nr);   // row -> offset in the output site tensor
+  std::vector<std::array<int, 9>> rowpos2(S.nl);
+  for (int l = 0; l < S.nl; ++l) rowpos2[l].fill(-1);
+  pos = 0;
+  for (int r = 0; r < nr; ++r) {
+    int cnt = 0;
+    for (int p = 0; p < S.nl; ++p)
+      for (int g = 0; g < G.ng; ++g) {
+        if (S.rsec[p][g] != r) continue;
+        rowpos2[p][g] = cnt;
+        int ns = (int)G.s[g].size();
+        for (int x = 0; x < S.dl[p]; ++x)
+          for (int si = 0; si < ns; ++si)
+            outrows[r].push_back(S.base[p] + (long long)x * S.C[p] + S.colb[p][g] + (long long)si * br.secs[r].dim);
+        cnt += S.dl[p] * ns;
+      }
+    nrows2[r] = cnt;
+    t2base[r] = pos;
+    pos += (long long)cnt * ER.K[r];
+  }
+  P.t2_size = pos;
+  for (int r = 0; r < nr; ++r) {
+    for (int p = 0; p < S.nl; ++p)
+      for (int g = 0; g < G.ng; ++g) {
+        if (S.rsec[p][g] != r) continue;
+        int ns = (int)G.s[g].size();
+        for (int si = 0; si < ns; ++si) {
+          int sp = G.s[g][si];
+          int so = sp / 4, sa = sp % 4;   // output ket sigma, ancilla sigma'
+          for (int b = 0; b < DHr; ++b) {
+            int c = ER.csec[r][b];
+            if (c < 0) continue;
+            WTask t;
+            t.dst = t2base[r] + (long long)(rowpos2[p][g] + si) * ER.K[r] + ER.colb[r][b];
+            t.dsi = (long long)ns * ER.K[r];
+            t.dsj = 1;
+            t.ni = S.dl[p];
+            t.nj = br.secs[c].dim;
+            t.t0 = (int)P.w2.terms.size();
+            for (int a = 0; a < DHl; ++a) {
+              int l = EL.csec[p][a];
+              if (l < 0) continue;
+              for (int sg = 0; sg < 4; ++sg) {
+                double w = Wat(a, so, sg, b);
+                if (w == 0.0) continue;
+                int s = sg * 4 + sa;
+                int gg = G.group_of[s];
+                TT_REQUIRE(S.rsec[l][gg] == c, TT_EINVAL, "plan: MPO entry breaks charge conservation");
+                WTerm tm;
+                tm.src = t1base[l] + (long long)rowbase1[l][a] * S.C[l] + S.colb[l][gg] +
+                         (long long)G.pos_of[s] * br.secs[c].dim;
+                tm.ssi = S.C[l];
+                tm.ssj = 1;
+                tm.w = w;
+                P.w2.terms.push_back(tm);
+              }
+            }
+            t.nt = (int)P.w2.terms.size() - t.t0;
+            P.w2.flops += 2.0 * t.nt * (double)t.ni * t.nj;
+            P.w2.tasks.push_back(t);
+          }
+        }
+      }
+  }
+
+  // ---------------- stage 3: out rows (p,g',x,s') = T2_r' . R_r'^T ; env-left final
+  for (int r = 0; r < nr; ++r) {
+    if (nrows2[r] == 0) continue;
+    long long tab = tabs.add(outrows[r]);
+    GemmProb g = gp(nrows2[r], br.secs[r].dim, ER.K[r], 0, 1, 2);
+    g.offA = t2base[r]; g.sam = ER.K[r]; g.sak = 1;
+    g.offB = ER.base[r]; g.sbk = 1; g.sbn = ER.K[r];
+    g.tcm = tab;
+    add_prob(P.s3, g);
+    // L_{k+1}[y'][(b,y)] = sum_rows A^L[row][y'] T2[row][(b,y)]
+    GemmProb e = gp(br.secs[r].dim, ER.K[r], nrows2[r], 0, 1, 2);
+    e.sam = 1; e.tak = tab;
+    e.offB = t2base[r]; e.sbk = ER.K[r]; e.sbn = 1;
+    e.offC = ER.base[r]; e.scm = ER.K[r];
+    add_prob(P.el, e);
+  }
+
+  // ---------------- env-right stage 1': Y^T_c[(b,y')][(l,g,x,s)] = R[y',b,c-block] . A^T
+  const int nc = nr;
+  std::vector<long long> ybase(nc, 0);
+  std::vector<int> ycols(nc, 0);
+  std::vector<std::vector<int>> rowbaseY(nc, std::vector<int>(DHr, -1));
+  std::vector<std::array<int, 9>> colposY(S.nl);
+  for (int l = 0; l < S.nl; ++l) colposY[l].fill(-1);
+  std::vector<std::vector<long long>> qrrows(nc);   // A rows grouped by right sector
+  pos = 0;
+  for (int c = 0; c < nc; ++c) {
+    for (int l = 0; l < S.nl; ++l)
+      for (int g = 0; g < G.ng; ++g) {
+        if (S.rsec[l][g] != c) continue;
+        colposY[l][g] = (int)qrrows[c].size();
+        int ns = (int)G.s[g].size();
+        for (int x = 0; x < S.dl[l]; ++x)
+          for (int si = 0; si < ns; ++si)
+            qrrows[c].push_back(S.base[l] + (long long)x * S.C[l] + S.colb[l][g] + (long long)si * br.secs[c].dim);
+      }
+    ycols[c] = (int)qrrows[c].size();
+    std::vector<long long> rrows;
+    for (int b = 0; b < DHr; ++b) {
+      int rp = br.find(addq(br.secs[c].q, qHr[b]));
+      if (rp < 0 || ER.csec[rp][b] != c) continue;
+      rowbaseY[c][b] = (int)rrows.size();
+      for (int y = 0; y < br.secs[rp].dim; ++y)
+        rrows.push_back(ER.base[rp] + (long long)y * ER.K[rp] + ER.colb[rp][b]);
+    }
+    ybase[c] = pos;
+    long long qtab = tabs.add(qrrows[c]);
+    if (!rrows.empty() && ycols[c] > 0) {
+      GemmProb g = gp((int)rrows.size(), ycols[c], br.secs[c].dim, 0, 1, 2);
+      g.tam = tabs.add(rrows); g.sak = 1;
+      g.sbk = 1; g.tbn = qtab;
+      g.offC = pos; g.scm = ycols[c];
+      add_prob(P.r1, g);
+    }
+    pos += (long long)rrows.size() * ycols[c];
+    // QR of the rows of sector c (left-to-right gauge move)
+    QRTask q{};
+    q.m = ycols[c]; q.n = br.secs[c].dim; q.trans = 0;
+    q.rbase = 0; q.rs = 0; q.cs = 1; q.rtab = qtab;
+    q.ws = P.qr.ws_size;
+    P.qr.ws_size += 2LL * q.m * q.n;
+    P.qr.tasks.push_back(q);
+    // absorb from the right: rows . S_c
+    GemmProb ab = gp(ycols[c], br.secs[c].dim, br.secs[c].dim, 0, 1, 2);
+    ab.tam = qtab; ab.sak = 1;
+    ab.sbk = br.secs[c].dim; ab.sbn = 1;
+    ab.tcm = qtab;
+    add_prob(P.absR, ab);
+  }
+  P.y_size = pos;
+  // S offsets of the right bond for QR outputs / absorbR
+  {
+    BondMatLayout bm = make_bondmat_layout(br);
+    for (int c = 0; c < nc; ++c) P.qr.tasks[c].sdst = bm.off[c];
+    int i = 0;
+    for (int c = 0; c < nc; ++c)
+      if (ycols[c] > 0) P.absR.probs[i++].offB = bm.off[c];
+  }
+
+  // ---------------- env-right W stage: Z_p[(g',s',y')][(a,x)]
+  std::vector<long long> zbase(S.nl, 0);
+  pos = 0;
+  for (int p = 0; p < S.nl; ++p) {
+    zbase[p] = pos;
+    pos += (long long)S.C[p] * EL.K[p];
+  }
+  P.z_size = pos;
+  for (int p = 0; p < S.nl; ++p)
+    for (int g = 0; g < G.ng; ++g) {
+      int rp = S.rsec[p][g];
+      if (rp < 0) continue;
+      int ns = (int)G.s[g].size();
+      for (int si = 0; si < ns; ++si) {
+        int sp = G.s[g][si];
+        int so = sp / 4, sa = sp % 4;
+        for (int a = 0; a < DHl; ++a) {
+          int l = EL.csec[p][a];
+          if (l < 0) continue;
+          WTask t;
+          t.dst = zbase[p] + ((long long)S.colb[p][g] + (long long)si * br.secs[rp].dim) * EL.K[p] + EL.colb[p][a];
+          t.dsi = EL.K[p];
+          t.dsj = 1;
+          t.ni = br.secs[rp].dim;
+          t.nj = S.dl[l];
+          t.t0 = (int)P.wr.terms.size();
+          for (int b = 0; b < DHr; ++b)
+            for (int sg = 0; sg < 4; ++sg) {
+              double w = Wat(a, so, sg, b);
+              if (w == 0.0) continue;
+              int s = sg * 4 + sa;
+              int gg = G.group_of[s];
+              int c = S.rsec[l][gg];
+              if (c < 0) continue;   // the ket block (l, s) -> c is absent from the truncated bond
+              TT_REQUIRE(rowbaseY[c][b] >= 0, TT_EINVAL, "plan: MPO entry breaks charge conservation");
+              TT_REQUIRE(br.find(addq(br.secs[c].q, qHr[b])) == rp, TT_EINVAL, "plan: inconsistent charges");
+              WTerm tm;
+              tm.src = ybase[c] + (long long)rowbaseY[c][b] * ycols[c] + colposY[l][gg] + G.pos_of[s];
+              tm.ssi = ycols[c];
+              tm.ssj = (long long)G.s[gg].size();
+              tm.w = w;
+              P.wr.terms.push_back(tm);
+            }
+          t.nt = (int)P.wr.terms.size() - t.t0;
+          P.wr.flops += 2.0 * t.nt * (double)t.ni * t.nj;
+          P.wr.tasks.push_back(t);
+        }
+      }
+    }
+  // final: R_k[p] = A_p . Z_p
+  for (int p = 0; p < S.nl; ++p) {
+    GemmProb g = gp(S.dl[p], EL.K[p], S.C[p], 0, 1, 2);
+    g.offA = S.base[p]; g.sam = S.C[p]; g.sak = 1;
+    g.offB = zbase[p]; g.sbk = EL.K[p]; g.sbn = 1;
+    g.offC = EL.base[p]; g.scm = EL.K[p];
+    add_prob(P.r3, g);
+  }
+
+  // ---------------- LQ per left sector (right-to-left gauge move), absorb from the left
+  {
+    BondMatLayout bm = make_bondmat_layout(bl);
+    for (int l = 0; l < S.nl; ++l) {
+      QRTask q{};
+      q.m = S.C[l]; q.n = S.dl[l]; q.trans = 1;
+      q.rbase = S.base[l]; q.rs = 1; q.cs = S.C[l]; q.rtab = -1;
+      q.sdst = bm.off[l];
+      q.ws = P.lq.ws_size;
+      P.lq.ws_size += 2LL * q.m * q.n;
+      P.lq.tasks.push_back(q);
+      GemmProb ab = gp(S.dl[l], S.C[l], S.dl[l], 0, 1, 2);
+      ab.offA = bm.off[l]; ab.sam = S.dl[l]; ab.sak = 1;
+      ab.offB = S.base[l]; ab.sbk = S.C[l]; ab.sbn = 1;
+      ab.offC = S.base[l]; ab.scm = S.C[l];
+      add_prob(P.absL, ab);
+    }
+    // ---------------- bond effective Hamiltonian on the left bond k
+    // U[(a,x)][y] = L[x,a,q-block] . S_q written in environment layout; out_p = U_p . R_p^T
+    for (int q = 0; q < (int)bl.secs.size(); ++q) {
+      std::vector<long long> rows;
+      for (int a = 0; a < DHl; ++a) {
+        int p = bl.find(addq(bl.secs[q].q, qHl[a]));
+        if (p < 0 || EL.csec[p][a] != q) continue;
+        for (int x = 0; x < EL.dp[p]; ++x) rows.push_back(EL.base[p] + (long long)x * EL.K[p] + EL.colb[p][a]);
+      }
+      if (rows.empty()) continue;
+      long long tab = tabs.add(rows);
+      GemmProb g = gp((int)rows.size(), bl.secs[q].dim, bl.secs[q].dim, 0, 1, 2);
+      g.tam = tab; g.sak = 1;
+      g.offB = bm.off[q]; g.sbk = bl.secs[q].dim; g.sbn = 1;
+      g.tcm = tab;
+      add_prob(P.b1, g);
+    }
+    P.u_size = EL.size;
+    for (int p = 0; p < EL.np; ++p) {
+      GemmProb g = gp(EL.dp[p], EL.dp[p], EL.K[p], 0, 1, 2);
+      g.offA = EL.base[p]; g.sam = EL.K[p]; g.sak = 1;
+      g.offB = EL.base[p]; g.sbk = 1; g.sbn = EL.K[p];
+      g.offC = bm.off[p]; g.scm = EL.dp[p];
+      add_prob(P.b2, g);
+    }
+  }
+  // ---------------- trace transfer: the group with delta = (0,0) holds the diagonal s = (sigma, sigma)
+  int g0 = (G.ng == 1) ? 0 : 4;
+  for (int l = 0; l < S.nl; ++l) {
+    int r = S.rsec[l][g0];
+    if (r < 0) continue;
+    P.tr.push_back({S.base[l] + S.colb[l][g0], (long long)S.C[l], (long long)l, (long long)r});
+  }
+  return P;
+}
+
+}  // namespace tt

@@ -1,0 +1,345 @@
+// Model builder: lattice and snake order, the finite-state-machine MPO of the
+// Hubbard Hamiltonian, U(1)xU(1) bond sectors and the padding noise.
+//
+// Paper: Eq. (3) (Hubbard model), main-text Hubbard paragraph (cylinders
+// periodic across the width, open squares), Fig. 1a (snake path down one
+// column, across at the bottom, up the next).  The MPO construction itself is
+// only cited by the paper; the bond-state convention below is shared with
+// every other builder of this MPO so that padded tensors coincide:
+//   bond 0: [start]; bond N: [start, done]; ks = N/2;
+//   0 < k <= ks: [start, src(i,type) for pending sources i ascending, done]
+//   ks < k < N : [start, dst(j,type) for pending destinations j ascending, done]
+// type in (c+_up P, c+_dn P, P c_up, P c_dn).
+#include <algorithm>
+#include <cmath>
+#include <set>
+
+#include "tt_internal.h"
+
+namespace tt {
+
+Lattice make_lattice(int W, int L, int geometry) {
+  TT_REQUIRE(W >= 1 && L >= 1, TT_EINVAL, "lattice: W and L must be positive");
+  TT_REQUIRE(geometry >= 0 && geometry <= 2, TT_EINVAL, "lattice: unknown geometry");
+  TT_REQUIRE(geometry != TT_CHAIN || W == 1, TT_EINVAL, "lattice: a chain has W = 1");
+  Lattice lat{W, L, geometry, W * L, {}};
+  TT_REQUIRE(lat.N >= 2, TT_EINVAL, "lattice: need at least two sites");
+  // snake: column x top-down (y = W-1..0) when x is even, bottom-up when odd
+  std::vector<int> idx(W * L);
+  int n = 0;
+  for (int x = 0; x < L; ++x)
+    for (int r = 0; r < W; ++r) {
+      int y = (x % 2 == 0) ? (W - 1 - r) : r;
+      idx[x * W + y] = n++;
+    }
+  std::set<std::pair<int, int>> e;
+  auto add = [&](int a, int b) { e.insert({std::min(a, b), std::max(a, b)}); };
+  for (int x = 0; x < L; ++x)
+    for (int y = 0; y < W; ++y) {
+      int me = idx[x * W + y];
+      if (x + 1 < L) add(me, idx[(x + 1) * W + y]);
+      if (y + 1 < W) add(me, idx[x * W + y + 1]);
+      else if (geometry == TT_CYLINDER && W >= 3) add(me, idx[x * W + 0]);
+    }
+  lat.bonds.assign(e.begin(), e.end());
+  return lat;
+}
+
+// local operators in the basis {0, up, dn, updn}, |updn> = c+_up c+_dn |0>
+namespace {
+struct M4 { double v[4][4]; };
+M4 zero4() { M4 m{}; return m; }
+M4 mul(const M4& a, const M4& b) {
+  M4 r = zero4();
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 4; ++k) r.v[i][j] += a.v[i][k] * b.v[k][j];
+  return r;
+}
+M4 transpose(const M4& a) {
+  M4 r;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) r.v[i][j] = a.v[j][i];
+  return r;
+}
+struct LocalOps {
+  M4 id, par, cdu, cdd, cu, cd, onsite;
+  M4 left[4], right[4];
+};
+LocalOps local_ops(double U, double mu) {
+  LocalOps o;
+  o.id = zero4(); o.par = zero4(); o.cdu = zero4(); o.cdd = zero4(); o.onsite = zero4();
+  for (int i = 0; i < 4; ++i) o.id.v[i][i] = 1.0;
+  o.par.v[0][0] = 1; o.par.v[1][1] = -1; o.par.v[2][2] = -1; o.par.v[3][3] = 1;
+  o.cdu.v[1][0] = 1; o.cdu.v[3][2] = 1;       // c+_up
+  o.cdd.v[2][0] = 1; o.cdd.v[3][1] = -1;      // c+_dn (passes the up mode)
+  o.cu = transpose(o.cdu);
+  o.cd = transpose(o.cdd);
+  for (int s = 0; s < 4; ++s) {
+    int nu = s & 1, nd = s >> 1;
+    o.onsite.v[s][s] = U * nu * nd - mu * (nu + nd);
+  }
+  // c+_i c_j = (c+ P)_i P... (c)_j ;  c+_j c_i = (P c)_i P... (c+)_j
+  o.left[0] = mul(o.cdu, o.par); o.right[0] = o.cu;
+  o.left[1] = mul(o.cdd, o.par); o.right[1] = o.cd;
+  o.left[2] = mul(o.par, o.cu);  o.right[2] = o.cdu;
+  o.left[3] = mul(o.par, o.cd);  o.right[3] = o.cdd;
+  return o;
+}
+const Q kChannelQ[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+}  // namespace
+
+Q Mpo::charge(int k, int a) const {
+  const MpoState& s = states[k][a];
+  if (s.kind < 2) return {0, 0};
+  return kChannelQ[s.type];
+}
+
+Mpo make_hubbard_mpo(const Lattice& lat, double t, double U, double mu) {
+  const int N = lat.N;
+  Mpo m;
+  m.N = N;
+  std::vector<std::set<int>> later(N), earlier(N);   // neighbours j > i, i < j
+  for (auto& b : lat.bonds) {
+    later[b.first].insert(b.second);
+    earlier[b.second].insert(b.first);
+  }
+  const int ks = N / 2;
+  m.states.resize(N + 1);
+  m.states[0] = {{0, -1, -1}};
+  m.states[N] = {{0, -1, -1}, {1, -1, -1}};
+  for (int k = 1; k < N; ++k) {
+    auto& st = m.states[k];
+    st.push_back({0, -1, -1});
+    if (k <= ks) {
+      for (int i = 0; i < k; ++i) {
+        bool pending = !later[i].empty() && *later[i].rbegin() >= k;
+        if (pending)
+          for (int ty = 0; ty < 4; ++ty) st.push_back({2, i, ty});
+      }
+    } else {
+      for (int j = k; j < N; ++j) {
+        bool pending = !earlier[j].empty() && *earlier[j].begin() < k;
+        if (pending)
+          for (int ty = 0; ty < 4; ++ty) st.push_back({3, j, ty});
+      }
+    }
+    st.push_back({1, -1, -1});
+  }
+  for (int k = 0; k <= N; ++k) m.DH.push_back((int)m.states[k].size());
+  LocalOps o = local_ops(U, mu);
+  m.W.resize(N);
+  for (int k = 0; k < N; ++k) {
+    const auto& Ls = m.states[k];
+    const auto& Rs = m.states[k + 1];
+    int DL = (int)Ls.size(), DR = (int)Rs.size();
+    std::vector<double> Wk((size_t)DL * 16 * DR, 0.0);
+    auto find = [&](int kind, int site, int type) {
+      for (int b = 0; b < DR; ++b)
+        if (Rs[b].kind == kind && (kind < 2 || (Rs[b].site == site && Rs[b].type == type))) return b;
+      return -1;
+    };
+    auto put = [&](int a, int b, const M4& op, double c) {
+      for (int so = 0; so < 4; ++so)
+        for (int si = 0; si < 4; ++si)
+          Wk[(((size_t)a * 4 + so) * 4 + si) * DR + b] += c * op.v[so][si];
+    };
+    int bstart = find(0, -1, -1), bdone = find(1, -1, -1);
+    for (int a = 0; a < DL; ++a) {
+      const MpoState& s = Ls[a];
+      if (s.kind == 0) {
+        put(a, bstart, o.id, 1.0);
+        if (bdone >= 0) put(a, bdone, o.onsite, 1.0);
+        for (int ty = 0; ty < 4; ++ty) {
+          int b = find(2, k, ty);
+          if (b >= 0) put(a, b, o.left[ty], 1.0);
+          for (int j : later[k]) {
+            int bd = find(3, j, ty);
+            if (bd >= 0) put(a, bd, o.left[ty], -t);
+          }
+        }
+      } else if (s.kind == 1) {
+        put(a, bdone, o.id, 1.0);
+      } else if (s.kind == 2) {
+        int b = find(2, s.site, s.type);
+        if (b >= 0) put(a, b, o.par, 1.0);
+        for (int j : later[s.site]) {
+          if (j <= k) continue;
+          int bd = find(3, j, s.type);
+          if (bd >= 0) put(a, bd, o.par, -t);
+        }
+        if (later[s.site].count(k)) put(a, bdone, o.right[s.type], -t);
+      } else {
+        if (s.site == k) {
+          put(a, bdone, o.right[s.type], 1.0);
+        } else {
+          int b = find(3, s.site, s.type);
+          TT_REQUIRE(b >= 0, TT_EINVAL, "mpo: lost destination channel");
+          put(a, b, o.par, 1.0);
+        }
+      }
+    }
+    m.W[k] = std::move(Wk);
+  }
+  return m;
+}
+
+Groups make_groups(bool symmetric) {
+  Groups g;
+  g.group_of.assign(16, 0);
+  g.pos_of.assign(16, 0);
+  if (!symmetric) {
+    g.ng = 1;
+    g.delta = {{0, 0}};
+    g.s.resize(1);
+    for (int s = 0; s < 16; ++s) { g.s[0].push_back(s); g.pos_of[s] = s; }
+    return g;
+  }
+  g.ng = 9;
+  for (int du = -1; du <= 1; ++du)
+    for (int dd = -1; dd <= 1; ++dd) g.delta.push_back({du, dd});
+  g.s.resize(9);
+  for (int s = 0; s < 16; ++s) {
+    int sig = s / 4, sp = s % 4;
+    int du = (sig & 1) - (sp & 1), dd = (sig >> 1) - (sp >> 1);
+    int gi = (du + 1) * 3 + (dd + 1);
+    g.group_of[s] = gi;
+    g.pos_of[s] = (int)g.s[gi].size();
+    g.s[gi].push_back(s);
+  }
+  return g;
+}
+
+uint64_t splitmix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+double noise_uniform(uint64_t seed, int site, uint64_t flat) {
+  uint64_t n = (uint64_t)site * (1ULL << 40) + flat + 1ULL;
+  uint64_t z = splitmix64(seed + n * 0x9E3779B97F4A7C15ULL);
+  double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  return 2.0 * u - 1.0;
+}
+
+namespace {
+using u128 = unsigned __int128;
+const u128 kSat = ((u128)1) << 120;
+u128 sat_mul(u128 a, u128 b) {
+  if (a == 0 || b == 0) return 0;
+  if (a >= kSat || b >= kSat) return kSat;
+  if (a > kSat / b) return kSat;
+  u128 r = a * b;
+  return r > kSat ? kSat : r;
+}
+// binomial C(n, k) saturated at 2^120
+u128 binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  k = std::min(k, n - k);
+  // multiplicative formula with exact division; values here stay far below 2^120
+  // until saturation, which only happens for n > 120
+  u128 r = 1;
+  for (int i = 1; i <= k; ++i) {
+    if (r >= kSat / (u128)(n - k + i)) return kSat;
+    r = r * (u128)(n - k + i) / (u128)i;
+  }
+  return r;
+}
+u128 count_side(int n, Q q) {
+  if (std::abs(q.first) > n || std::abs(q.second) > n) return 0;
+  return sat_mul(binom(2 * n, n + q.first), binom(2 * n, n + q.second));
+}
+}  // namespace
+
+std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0) {
+  std::vector<std::map<Q, int>> dims(N + 1);
+  dims[0][{0, 0}] = 1;
+  dims[N][{0, 0}] = 1;
+  std::vector<Q> sc;  // the 16 local super-index charges
+  for (int s = 0; s < 16; ++s) {
+    int sig = s / 4, sp = s % 4;
+    sc.push_back({(sig & 1) - (sp & 1), (sig >> 1) - (sp >> 1)});
+  }
+  for (int k = 1; k < N; ++k) {
+    int h = std::min(k, N - k);
+    std::vector<Q> qs;
+    for (int a = -h; a <= h; ++a)
+      for (int b = -h; b <= h; ++b) qs.push_back({a, b});
+    std::map<Q, u128> dmax;
+    u128 tot = 0;
+    for (auto q : qs) {
+      u128 v = std::min(count_side(k, q), count_side(N - k, q));
+      dmax[q] = v;
+      tot = tot + v;
+      if (tot > kSat) tot = kSat;
+    }
+    std::map<Q, int> d;
+    if (tot <= (u128)D) {
+      for (auto q : qs) d[q] = (int)dmax[q];
+    } else {
+      int hw = std::min(h, 14);
+      std::map<Q, u128> w;
+      u128 wt = 0;
+      for (auto q : qs) {
+        u128 v = 0;
+        if (std::abs(q.first) <= hw && std::abs(q.second) <= hw)
+          v = binom(2 * hw, hw + q.first) * binom(2 * hw, hw + q.second);
+        w[q] = v;
+        wt += v;
+      }
+      std::map<Q, long long> base;
+      std::vector<std::pair<u128, Q>> rem;
+      long long used = 0;
+      for (auto q : qs) {
+        u128 num = (u128)D * w[q];
+        base[q] = (long long)(num / wt);
+        used += base[q];
+        rem.push_back({num % wt, q});
+      }
+      // largest remainder first, ties to the lexicographically smaller charge
+      std::sort(rem.begin(), rem.end(), [](const std::pair<u128, Q>& x, const std::pair<u128, Q>& y) {
+        if (x.first != y.first) return x.first > y.first;
+        return x.second < y.second;
+      });
+      long long left = D - used;
+      for (long long i = 0; i < left && i < (long long)rem.size(); ++i) base[rem[i].second] += 1;
+      for (auto q : qs) {
+        long long v = base[q];
+        auto it = n0[k].find(q);
+        if (it != n0[k].end()) v = std::max<long long>(v, it->second);
+        u128 cap = dmax[q];
+        if ((u128)v > cap) v = (long long)cap;
+        d[q] = (int)v;
+      }
+    }
+    for (auto& kv : d)
+      if (kv.second > 0) dims[k][kv.first] = kv.second;
+  }
+  bool changed = true;
+  auto get = [&](int k, Q q) {
+    auto it = dims[k].find(q);
+    return it == dims[k].end() ? 0 : it->second;
+  };
+  while (changed) {
+    changed = false;
+    for (int k = 1; k < N; ++k)
+      for (auto& kv : dims[k]) {
+        long long rows = 0;
+        for (auto c : sc) rows += get(k - 1, {kv.first.first - c.first, kv.first.second - c.second});
+        if (kv.second > rows) { kv.second = (int)rows; changed = true; }
+      }
+    for (int k = N - 1; k >= 1; --k)
+      for (auto& kv : dims[k]) {
+        long long cols = 0;
+        for (auto c : sc) cols += get(k + 1, {kv.first.first + c.first, kv.first.second + c.second});
+        if (kv.second > cols) { kv.second = (int)cols; changed = true; }
+      }
+    for (int k = 1; k < N; ++k)
+      for (auto it = dims[k].begin(); it != dims[k].end();)
+        it = (it->second <= 0) ? dims[k].erase(it) : std::next(it);
+  }
+  return dims;
+}
+
+}  // namespace tt

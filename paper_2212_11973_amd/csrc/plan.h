@@ -1,0 +1,143 @@
+// Device-visible descriptors of the grouped contractions and the host-side
+// plans that hold them.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <vector>
+
+#include "tt_internal.h"
+
+namespace tt {
+
+constexpr int kSlots = 4;
+struct Slots { double* p[kSlots]; };
+
+// One GEMM of a grouped launch: C = alpha * A B + beta * C with
+//   A(m,k) = slot[ia][offA + am(m) + ak(k)]
+//   B(k,n) = slot[ib][offB + bk(k) + bn(n)]
+//   C(m,n) = slot[ic][offC + cm(m) + n]
+// where each index map is either i * stride (table < 0) or tables[table + i].
+struct GemmProb {
+  int M, N, K;
+  int ia, ib, ic;
+  long long offA, offB, offC;
+  long long sam, sak, sbk, sbn, scm;
+  long long tam, tak, tbk, tbn, tcm;
+  double alpha, beta;
+};
+struct GemmTile { int prob, tm, tn; };
+
+// W stage: dst(i,j) = sum_t w_t src_t(i,j) for i < ni, j < nj, with
+// dst(i,j) = out[dst + i*dsi + j*dsj] and src_t(i,j) = in[src + i*ssi + j*ssj].
+struct WTask { long long dst, dsi, dsj; int ni, nj, t0, nt; };
+struct WTerm { long long src, ssi, ssj; double w; };
+
+// Householder QR of an m x n (m >= n) matrix M(i,j) = buf[rbase + row(i) + j*cs]
+// (row(i) = rtab[i] if rtab >= 0 else i*rs).  Q overwrites M; R (n x n) goes
+// to S[sdst + i*n + j] (upper) or, if trans, to S[sdst + j*n + i] (lower: L = R^T).
+struct QRTask { int m, n, trans, pad; long long rbase, rs, cs, rtab, sdst, ws; };
+
+// A plan: descriptors uploaded once, launched many times with varying slots.
+struct GemmPlan {
+  std::vector<GemmProb> probs;
+  std::vector<GemmTile> tiles;
+  double flops = 0;
+  GemmProb* d_probs = nullptr;
+  GemmTile* d_tiles = nullptr;
+  int ntiles = 0;
+};
+struct WPlan {
+  std::vector<WTask> tasks;
+  std::vector<WTerm> terms;
+  WTask* d_tasks = nullptr;
+  WTerm* d_terms = nullptr;
+  int ntasks = 0;
+  double flops = 0;
+};
+struct QRPlan {
+  std::vector<QRTask> tasks;
+  QRTask* d_tasks = nullptr;
+  int ntasks = 0;
+  long long ws_size = 0;    // doubles of workspace (2 m n per task)
+};
+
+// bookkeeping of one site tensor: row block per left sector l, columns
+// (group g, s in g, y in the right sector l + delta_g)
+struct SiteLayout {
+  int nl = 0;
+  std::vector<int> dl, C;
+  std::vector<long long> base;
+  std::vector<std::array<int, 9>> rsec, colb;
+  long long size = 0;
+};
+// environment on a bond: row block per bra sector p, columns (a, ket x in p - qH(a))
+struct EnvLayout {
+  int np = 0;
+  std::vector<int> dp, K;
+  std::vector<long long> base;
+  std::vector<std::vector<int>> csec, colb;
+  long long size = 0;
+};
+// packed block-diagonal bond matrix S: one d x d block per sector
+struct BondMatLayout {
+  std::vector<long long> off;
+  long long size = 0;
+};
+
+SiteLayout make_site_layout(const Bond& left, const Bond& right, const Groups& G);
+EnvLayout make_env_layout(const Bond& bond, const std::vector<Q>& qH);
+BondMatLayout make_bondmat_layout(const Bond& bond);
+
+// All descriptors of one site k (left bond k, right bond k+1).
+struct SitePlan {
+  // sizes of intermediates (doubles)
+  long long t1_size = 0, t2_size = 0, y_size = 0, z_size = 0;
+  // heff1 / env-left: stage 1 (L.A), W stage, stage 3 (.R), env-left final
+  GemmPlan s1, s3, el;
+  WPlan w2;
+  // env-right: stage 1' (R.A), W stage, final
+  GemmPlan r1, r3;
+  WPlan wr;
+  // gauge moves
+  QRPlan qr, lq;
+  // absorb from the left (S_k . A, S on the left bond) and from the right (A . S_{k+1})
+  GemmPlan absL, absR;
+  // bond effective Hamiltonian on the left bond k (H^(0) with L_k, R_k)
+  GemmPlan b1, b2;
+  long long u_size = 0;
+  // transfer-matrix trace: per left sector l with a (0,0) group, (row block, col base, d)
+  std::vector<std::array<long long, 4>> tr;
+};
+
+// slot conventions (kernel argument order)
+//   s1 : 0 = L env, 1 = site vector, 2 = T1
+//   w2 : in = T1, out = T2
+//   s3 : 0 = T2, 1 = R env, 2 = output site vector
+//   el : 0 = site tensor (A^L), 1 = T2, 2 = new L env
+//   r1 : 0 = R env, 1 = site tensor, 2 = Y
+//   wr : in = Y, out = Z
+//   r3 : 0 = site tensor, 1 = Z, 2 = new R env
+//   absL: 0 = S (left bond), 1 = site tensor, 2 = output
+//   absR: 0 = site tensor, 1 = S (right bond), 2 = output
+//   b1 : 0 = L env (bond k), 1 = S (bond k), 2 = U
+//   b2 : 0 = U, 1 = R env (bond k), 2 = output S
+// Tables of all plans of a site live in one device array; offsets are into it.
+struct SiteTables {
+  std::vector<long long> host;
+  long long* dev = nullptr;
+  long long add(const std::vector<long long>& t) {
+    long long o = (long long)host.size();
+    host.insert(host.end(), t.begin(), t.end());
+    return o;
+  }
+};
+
+SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
+                         const std::vector<Q>& qHl, const std::vector<Q>& qHr,
+                         const std::vector<double>& W,   // DHl*16*DHr
+                         SiteTables& tabs);
+
+// tile the problems of a plan (BM x BN tiles)
+void tile_plan(GemmPlan& p, int BM, int BN);
+
+}  // namespace tt

@@ -1,0 +1,69 @@
+// Internal declarations of the tanTRG library (host side).
+#pragma once
+#include <cstdint>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tantrg.h"
+
+namespace tt {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+#define TT_REQUIRE(cond, code, msg)                     \
+  do {                                                  \
+    if (!(cond)) throw ::tt::Error((code), (msg));      \
+  } while (0)
+
+using Q = std::pair<int, int>;  // (n_up, n_dn) charge
+
+// ------------------------------------------------------------------ model
+struct Lattice {
+  int W, L, geometry, N;
+  std::vector<std::pair<int, int>> bonds;      // i < j, chain indices
+};
+Lattice make_lattice(int W, int L, int geometry);
+
+// One MPO bond state: kind 0 start, 1 done, 2 source channel, 3 destination channel
+struct MpoState { int kind, site, type; };
+
+struct Mpo {
+  int N;
+  std::vector<std::vector<MpoState>> states;   // per bond 0..N (bond N: start, done)
+  std::vector<std::vector<double>> W;          // W[k][((a*4+so)*4+si)*DHr + b]
+  std::vector<int> DH;                         // per bond
+  Q charge(int k, int a) const;
+};
+Mpo make_hubbard_mpo(const Lattice& lat, double t, double U, double mu);
+
+// ------------------------------------------------------------------ sectors
+struct Sector { Q q; int dim; long long off; };
+struct Bond {
+  std::vector<Sector> secs;
+  long long total = 0;
+  std::map<Q, int> index;
+  int find(Q q) const { auto it = index.find(q); return it == index.end() ? -1 : it->second; }
+  void add(Q q, int dim) { index[q] = (int)secs.size(); secs.push_back({q, dim, total}); total += dim; }
+};
+
+// super-index groups: 9 charge groups (symmetric) or one group of all 16
+struct Groups {
+  int ng;
+  std::vector<Q> delta;                 // per group
+  std::vector<std::vector<int>> s;      // super indices s = 4*sigma + sigma' per group
+  std::vector<int> group_of, pos_of;    // per s
+};
+Groups make_groups(bool symmetric);
+
+uint64_t splitmix64(uint64_t x);
+double noise_uniform(uint64_t seed, int site, uint64_t flat);
+
+// sector dimensions of bonds 0..N for a target D (n0: rho0 states per charge)
+std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0);
+
+}  // namespace tt

@@ -1,0 +1,255 @@
+"""ctypes binding of libtantrg.so (argument marshalling only).
+
+Every name mirrors an entry point of ``include/tantrg.h``.  The library is
+loaded on first use from this package's directory; if it is missing the
+binding raises (there is no other implementation).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtantrg.so")
+
+TT_OK, TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC, TT_EIO = 0, -1, -2, -3, -4, -5
+TT_CHAIN, TT_CYLINDER, TT_OPEN_SQUARE = 0, 1, 2
+TT_FP64, TT_FP32, TT_BF16X3, TT_BF16X6 = 0, 1, 2, 3
+
+SYMBOLS = [
+    "tt_options_default", "mpo_init_highT", "tdvp_sweep", "tdvp_sweep_batch",
+    "thermo_observables", "tt_state_free", "tt_last_error", "tt_state_info",
+    "tt_state_bond_sectors", "tt_state_export_site", "tt_state_import_site",
+    "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
+    "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
+]
+
+
+class tt_model(C.Structure):
+    _fields_ = [("W", C.c_int), ("L", C.c_int), ("geometry", C.c_int),
+                ("t", C.c_double), ("tp", C.c_double), ("U", C.c_double), ("mu", C.c_double)]
+
+
+class tt_options(C.Structure):
+    _fields_ = [("D", C.c_int), ("symmetry", C.c_int), ("beta0", C.c_double),
+                ("taylor_order", C.c_int), ("krylov_dim", C.c_int), ("krylov_tol", C.c_double),
+                ("precision", C.c_int), ("pad_eps", C.c_double), ("seed", C.c_uint64),
+                ("env_on_host", C.c_int)]
+
+
+class tt_observables(C.Structure):
+    _fields_ = [("beta", C.c_double), ("beta_phys", C.c_double), ("lnZ", C.c_double),
+                ("f", C.c_double), ("E", C.c_double), ("e", C.c_double),
+                ("lnZ_single", C.c_double), ("lambda_", C.c_double), ("n_sites", C.c_int)]
+
+
+class tt_sweep_stats(C.Structure):
+    _fields_ = [("seconds", C.c_double), ("flops_alg", C.c_double), ("flops_heff", C.c_double),
+                ("n_applies", C.c_int), ("n_exps", C.c_int), ("max_krylov_err", C.c_double)]
+
+
+class TTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("tantrg error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtantrg.so is not built: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+        L.tt_last_error.restype = C.c_char_p
+        L.tt_options_default.argtypes = [C.POINTER(tt_options)]
+        L.mpo_init_highT.argtypes = [C.POINTER(tt_model), C.POINTER(tt_options), C.POINTER(vp)]
+        L.tdvp_sweep.argtypes = [vp, C.c_double, C.POINTER(tt_sweep_stats)]
+        L.tdvp_sweep_batch.argtypes = [C.POINTER(vp), C.c_int, C.c_double, C.POINTER(tt_sweep_stats)]
+        L.thermo_observables.argtypes = [vp, C.POINTER(tt_observables)]
+        L.tt_state_free.argtypes = [vp]
+        L.tt_state_free.restype = None
+        L.tt_state_info.argtypes = [vp, ip, ip]
+        L.tt_state_bond_sectors.argtypes = [vp, C.c_int, ip, ip, ip, ip]
+        L.tt_state_export_site.argtypes = [vp, C.c_int, dp]
+        L.tt_state_import_site.argtypes = [vp, C.c_int, dp]
+        L.tt_state_save.argtypes = [vp, C.c_char_p]
+        L.tt_state_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.tt_heff_apply.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.tt_set_stream.argtypes = [vp]
+        L.tt_set_allocator.argtypes = [vp, vp, vp]
+        L.tt_heff_last_timing.argtypes = [dp]
+        L.tt_model_bond_sectors.argtypes = [C.POINTER(tt_model), C.POINTER(tt_options), C.c_int, ip, ip, ip, ip]
+        L.tt_check_plans.argtypes = [C.POINTER(tt_model), C.POINTER(tt_options),
+                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != TT_OK:
+        raise TTError(code, lib().tt_last_error().decode())
+
+
+def options_default():
+    o = tt_options()
+    _check(lib().tt_options_default(C.byref(o)))
+    return o
+
+
+def model(W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0):
+    return tt_model(W, L, geometry, t, tp, U, mu)
+
+
+def options(**kw):
+    o = options_default()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mpo_init_highT(m, o):
+    h = C.c_void_p()
+    _check(lib().mpo_init_highT(C.byref(m), C.byref(o), C.byref(h)))
+    return h
+
+
+def tdvp_sweep(state, dbeta, stats=False):
+    if stats:
+        s = tt_sweep_stats()
+        _check(lib().tdvp_sweep(state, dbeta, C.byref(s)))
+        return s
+    _check(lib().tdvp_sweep(state, dbeta, None))
+    return None
+
+
+def tdvp_sweep_batch(states, dbeta, stats=False):
+    arr = (C.c_void_p * len(states))(*[s.value for s in states])
+    if stats:
+        s = tt_sweep_stats()
+        _check(lib().tdvp_sweep_batch(arr, len(states), dbeta, C.byref(s)))
+        return s
+    _check(lib().tdvp_sweep_batch(arr, len(states), dbeta, None))
+    return None
+
+
+def thermo_observables(state):
+    o = tt_observables()
+    _check(lib().thermo_observables(state, C.byref(o)))
+    return {k: getattr(o, k) for k, _ in o._fields_}
+
+
+def tt_state_free(state):
+    lib().tt_state_free(state)
+
+
+def tt_state_info(state):
+    n = C.c_int()
+    _check(lib().tt_state_info(state, C.byref(n), None))
+    dims = (C.c_int * (n.value + 1))()
+    _check(lib().tt_state_info(state, C.byref(n), dims))
+    return n.value, list(dims)
+
+
+def tt_state_bond_sectors(state, k):
+    ns = C.c_int()
+    _check(lib().tt_state_bond_sectors(state, k, C.byref(ns), None, None, None))
+    qu, qd, dm = (C.c_int * ns.value)(), (C.c_int * ns.value)(), (C.c_int * ns.value)()
+    _check(lib().tt_state_bond_sectors(state, k, C.byref(ns), qu, qd, dm))
+    return [((qu[i], qd[i]), dm[i]) for i in range(ns.value)]
+
+
+def tt_state_export_site(state, k):
+    _, dims = tt_state_info(state)
+    out = np.zeros((dims[k], 4, 4, dims[k + 1]))
+    _check(lib().tt_state_export_site(state, k, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def tt_state_import_site(state, k, arr):
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    _check(lib().tt_state_import_site(state, k, a.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def tt_state_save(state, path):
+    _check(lib().tt_state_save(state, path.encode()))
+
+
+def tt_state_load(path):
+    h = C.c_void_p()
+    _check(lib().tt_state_load(path.encode(), C.byref(h)))
+    return h
+
+
+def tt_heff_apply(Dl, Dr, DH, L_ptr, W_ptr, A_ptr, R_ptr, out_ptr, precision=TT_FP64, stream=None):
+    """Device pointers (ints, e.g. torch ``data_ptr()``) of FP64 row-major arrays."""
+    _check(lib().tt_heff_apply(Dl, Dr, DH, C.c_void_p(L_ptr), C.c_void_p(W_ptr), C.c_void_p(A_ptr),
+                               C.c_void_p(R_ptr), C.c_void_p(out_ptr), precision,
+                               C.c_void_p(stream) if stream else None))
+
+
+def tt_heff_last_timing():
+    ms = (C.c_double * 4)()
+    _check(lib().tt_heff_last_timing(ms))
+    return list(ms)
+
+
+def tt_check_plans(m, o):
+    """(violations, work_doubles, report) of the host-side bounds check."""
+    v, w = C.c_longlong(), C.c_longlong()
+    _check(lib().tt_check_plans(C.byref(m), C.byref(o), C.byref(v), C.byref(w)))
+    rep = lib().tt_last_error().decode() if v.value else ""
+    return v.value, w.value, rep
+
+
+def tt_model_bond_sectors(m, o, k):
+    ns = C.c_int()
+    _check(lib().tt_model_bond_sectors(C.byref(m), C.byref(o), k, C.byref(ns), None, None, None))
+    qu, qd, dm = (C.c_int * ns.value)(), (C.c_int * ns.value)(), (C.c_int * ns.value)()
+    _check(lib().tt_model_bond_sectors(C.byref(m), C.byref(o), k, C.byref(ns), qu, qd, dm))
+    return [((qu[i], qd[i]), dm[i]) for i in range(ns.value)]
+
+
+def tt_set_stream(stream):
+    _check(lib().tt_set_stream(C.c_void_p(stream) if stream else None))
+
+
+class State:
+    """Owning wrapper of a tt_state handle."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    @classmethod
+    def init(cls, m, o):
+        return cls(mpo_init_highT(m, o))
+
+    def sweep(self, dbeta, stats=False):
+        return tdvp_sweep(self.h, dbeta, stats)
+
+    def observables(self):
+        return thermo_observables(self.h)
+
+    def info(self):
+        return tt_state_info(self.h)
+
+    def sectors(self, k):
+        return tt_state_bond_sectors(self.h, k)
+
+    def export_site(self, k):
+        return tt_state_export_site(self.h, k)
+
+    def free(self):
+        if self.h is not None and self.h.value:
+            tt_state_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,107 @@
+"""Host-side tests of the C-ABI library (no GPU): every declared symbol is
+exported, argument validation fails cleanly, descriptor bounds hold for every
+workload, and the bond sectors equal the oracle's allocation rule."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+from paper_2212_11973_amd import tantrg as T  # noqa: E402
+from paper_2212_11973_amd import workloads as WL  # noqa: E402
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tantrg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = T.lib()
+    names = _declared()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(T.SYMBOLS) == names
+
+
+def _m(**kw):
+    d = dict(W=1, L=4, geometry=T.TT_CHAIN, t=1.0, U=4.0, mu=0.0)
+    d.update(kw)
+    return T.model(d["W"], d["L"], d["geometry"], d["t"], d["U"], d["mu"], kw.get("tp", 0.0))
+
+
+@pytest.mark.parametrize("field,value", [("precision", 7), ("krylov_dim", 0), ("krylov_dim", 33),
+                                         ("taylor_order", 2), ("symmetry", 2), ("D", 0),
+                                         ("env_on_host", 1), ("krylov_tol", -1.0)])
+def test_invalid_options_rejected_without_gpu(field, value):
+    o = T.options(**{field: value})
+    with pytest.raises(T.TTError) as e:
+        T.mpo_init_highT(_m(), o)
+    assert e.value.code == T.TT_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(tp=0.3), dict(W=2, geometry=T.TT_CHAIN), dict(L=1), dict(geometry=5)])
+def test_invalid_model_rejected_without_gpu(kw):
+    with pytest.raises(T.TTError) as e:
+        T.mpo_init_highT(_m(**kw), T.options())
+    assert e.value.code == T.TT_EINVAL
+
+
+def test_load_rejects_foreign_file(tmp_path):
+    p = tmp_path / "x.bin"
+    p.write_bytes(b"not a state at all")
+    with pytest.raises(T.TTError) as e:
+        T.tt_state_load(str(p))
+    assert e.value.code == T.TT_EIO
+    with pytest.raises(T.TTError) as e:
+        T.tt_state_load(str(tmp_path / "missing.bin"))
+    assert e.value.code == T.TT_EIO
+
+
+def test_heff_apply_rejects_bad_arguments():
+    with pytest.raises(T.TTError) as e:
+        T.tt_heff_apply(0, 4, 2, 1, 1, 1, 1, 1)
+    assert e.value.code == T.TT_EINVAL
+    with pytest.raises(T.TTError) as e:
+        T.tt_heff_apply(4, 4, 2, 0, 1, 1, 1, 1)
+    assert e.value.code == T.TT_EINVAL
+
+
+CASES = [(1, 4, 0, 256, 1), (1, 4, 0, 256, 0), (2, 3, 2, 40, 1), (4, 4, 1, 64, 1), (1, 6, 0, 12, 0),
+         (3, 4, 2, 100, 1), (4, 16, 1, 200, 1)]
+
+
+@pytest.mark.parametrize("W,L,geo,D,sym", CASES)
+def test_descriptor_bounds(W, L, geo, D, sym):
+    v, work, rep = T.tt_check_plans(T.model(W, L, geo, 1.0, 8.0, 1.5), T.options(D=D, symmetry=sym))
+    assert v == 0, rep
+    assert work > 0
+
+
+@pytest.mark.parametrize("name", ["cl4x16", "cl6x12"])
+def test_descriptor_bounds_full_workloads(name):
+    c = WL.MODELS[name]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    v, work, rep = T.tt_check_plans(m, T.options(D=c["D"], symmetry=1))
+    assert v == 0, rep
+
+
+@pytest.mark.parametrize("W,L,geo,D", [(4, 4, 1, 64), (2, 3, 2, 40), (4, 16, 1, 300), (1, 6, 0, 30)])
+def test_sectors_match_oracle_allocation(W, L, geo, D):
+    from oracle import charges, mpo
+    mm = mpo.HubbardMPO(W, L, geo, 1.0, 8.0, 1.0)
+    N = mm.N
+    q0 = [mm.bond_charges(k) for k in range(N)] + [[(0, 0)]]
+    lay = charges.bond_layouts(q0, N, D, True)
+    m = T.model(W, L, geo, 1.0, 8.0, 1.0)
+    o = T.options(D=D, symmetry=1)
+    for k in range(N + 1):
+        want = {}
+        for q in lay[k].charges:
+            want[q] = want.get(q, 0) + 1
+        got = dict(T.tt_model_bond_sectors(m, o, k))
+        assert got == want, k

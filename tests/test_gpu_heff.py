@@ -1,0 +1,71 @@
+"""GPU parity of the effective-Hamiltonian apply (SM Fig. optimalB(c)) against
+the oracle contraction, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import tdvp as otd
+from paper_2212_11973_amd import tantrg as T
+from paper_2212_11973_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _apply_gpu(L, W, A, R, precision=T.TT_FP64):
+    torch = _torch()
+    dev = torch.device("cuda:0")
+    tl, tw, ta, tr = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (L, W, A, R))
+    out = torch.empty_like(ta)
+    Dl, DH, Dr = L.shape[0], L.shape[1], R.shape[0]
+    T.tt_heff_apply(Dl, Dr, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(),
+                    precision, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("Dl,Dr,DH,seed", [(1, 1, 1, 0), (5, 7, 3, 1), (16, 16, 4, 2), (64, 64, 6, 3),
+                                           (96, 130, 18, 4), (130, 96, 18, 5), (200, 17, 7, 6)])
+def test_heff_apply_matches_oracle(Dl, Dr, DH, seed):
+    print("heff", Dl, Dr, DH, flush=True)
+    L, W, A, R = WL.heff_inputs_rect(Dl, Dr, DH, seed)
+    got = _apply_gpu(L, W, A, R)
+    want = otd.heff1(L, W, R, A)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err < 1e-13, err
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_heff_apply_d256_full():
+    L, W, A, R = WL.heff_inputs(256)
+    got = _apply_gpu(L, W, A, R)
+    want = otd.heff1(L, W, R, A)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-13
+
+
+def _sampled_reference(L, W, A, R, idx):
+    # out[x,so,sp,y] one element at a time from the definition (SM Fig. optimalB(c))
+    vals = []
+    for (x, so, sp, y) in idx:
+        # sum_{a,al,si,b,be} L[x,a,al] A[al,si,sp,be] W[a,so,si,b] R[y,b,be]
+        X = np.tensordot(A[:, :, sp, :], R[y], axes=([2], [1]))          # al si b
+        Y = np.einsum("asb,lsb->al", W[:, so, :, :], X)                   # a al
+        vals.append(float(np.sum(L[x] * Y)))
+    return np.array(vals)
+
+
+def test_heff_apply_d2000_sampled():
+    D = 2000
+    L, W, A, R = WL.heff_inputs(D)
+    got = _apply_gpu(L, W, A, R)
+    rng = np.random.default_rng(7)
+    idx = [(int(rng.integers(D)), int(rng.integers(4)), int(rng.integers(4)), int(rng.integers(D))) for _ in range(24)]
+    idx += [(0, 0, 0, 0), (D - 1, 3, 3, D - 1), (1999, 0, 3, 1024)]
+    want = _sampled_reference(L, W, A, R, idx)
+    g = np.array([got[i] for i in idx])
+    scale = np.sqrt(np.mean(want ** 2))
+    assert np.abs(g - want).max() <= 1e-12 * scale, (np.abs(g - want).max(), scale)
