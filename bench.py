@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the tanTRG hot path on one MI355X.
+
+Metric: seconds per symmetric 1-TDVP beta step (one tdvp_sweep) on the 4x16
+cylinder Hubbard model (t=1, U=8, mu=1.5, U(1)xU(1) block-sparse, D=2000), and
+the dense effective-Hamiltonian apply throughput (TFLOP/s) at D=2000, D_H=18.
+Every input is synthetic: the state is rho0 = 1 - beta0 H padded with seeded
+noise; the dense apply uses i.i.d. N(0,1) tensors.
+
+Prints one JSON line.  --gpus N with N > 1 exits: the build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s (MI355X)
+PEAK_FP64_VALU = 78.6                                   # 256 CU x 2.4 GHz x 128 flop/clk
+PEAK_HBM_GBS = 8000.0
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+KERNEL_NAME = {"gemm": "k_gemm_f64", "wstage": "k_wstage", "qr": "k_qr"}
+
+
+def dense_sweep_flops(dims, DH, K):
+    """Dense-equivalent flops of one sweep (what a dense contraction of the same
+    bond dimensions costs): site applies, bond applies, environments, QR."""
+    N = len(dims) - 1
+    def h1(Dl, Dr):
+        return 32.0 * DH * Dl * Dr * (Dl + Dr) + 128.0 * DH * DH * Dl * Dr
+    f = 0.0
+    for k in range(N):                       # 2N-1 site exponentials
+        f += (2 if k < N - 1 else 1) * K * h1(dims[k], dims[k + 1])
+    for k in range(1, N):                    # 2N-2 bond exponentials, 2N-2 environments, QR
+        D = dims[k]
+        f += 2 * K * 4.0 * D ** 3 * DH
+        f += h1(dims[k - 1], dims[k]) + h1(dims[k], dims[k + 1])
+        f += 2 * (4.0 * 16 * D * D * D)
+    return f
+
+
+def cpu_baseline(D, DH):
+    """The oracle's dense apply at D on the host (bounded sample)."""
+    import numpy as np
+    from oracle import tdvp as otd
+    from paper_2212_11973_amd import workloads as WL
+    L, W, A, R = WL.heff_inputs(D, DH)
+    t0 = time.perf_counter()
+    otd.heff1(L, W, R, A)
+    t = time.perf_counter() - t0
+    flops = 32.0 * DH * D * D * (2 * D) + 128.0 * DH * DH * D * D
+    return t, flops
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cl4x16")
+    ap.add_argument("--D", type=int, default=0, help="override the bond dimension")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
+    ap.add_argument("--heff-D", type=int, default=2000)
+    ap.add_argument("--heff-reps", type=int, default=5)
+    ap.add_argument("--heff-precisions", default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-D", type=int, default=1500, help="bond dimension of the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU (--gpus 1); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2212_11973_amd import tantrg as T
+    from paper_2212_11973_amd import workloads as WL
+
+    torch.cuda.set_device(0)
+    T.lib()
+    c = WL.MODELS[args.workload]
+    D = args.D or c["D"]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
+                  precision=PREC[args.precision])
+    print("init %s D=%d" % (args.workload, D), file=sys.stderr, flush=True)
+    st = T.State.init(m, o)
+    n_sites, dims = st.info()
+    for i in range(args.warmup):
+        st.sweep(c["dbeta"])
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T.tt_profile_enable(True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stats.append(st.sweep(c["dbeta"], stats=True))
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T.tt_profile_enable(False)
+    prof = T.tt_profile_read()
+    obs = st.observables()
+    st.free()
+    s_per_step = (t1 - t0) / args.steps
+    flops_step = statistics.mean(s.flops_alg for s in stats)
+    applies_step = statistics.mean(s.n_applies for s in stats)
+
+    # dominant kernel of the timed region and its roofline
+    kind = max(prof, key=lambda k: prof[k]["ms"])
+    pk = prof[kind]
+    avg_ms = pk["ms"] / max(pk["launches"], 1)
+    if kind == "gemm":
+        pname = "fp64" if args.precision == "fp64" else ("fp32" if args.precision == "fp32" else "bf16")
+        roof = dict(bound="mfma", unit="TFLOP/s", peak=PEAK[pname],
+                    achieved=pk["flops"] / (pk["ms"] * 1e-3) / 1e12)
+    elif kind == "wstage":
+        roof = dict(bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS, achieved=pk["bytes"] / (pk["ms"] * 1e-3) / 1e9)
+    else:
+        roof = dict(bound="alu", unit="TFLOP/s", peak=PEAK_FP64_VALU,
+                    achieved=pk["flops"] / (pk["ms"] * 1e-3) / 1e12)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = KERNEL_NAME[kind]
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = pk["launches"]
+    kernels = {k: dict(ms_per_step=v["ms"] / args.steps, launches_per_step=v["launches"] / args.steps,
+                       tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
+                       gbs=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0)
+               for k, v in prof.items()}
+
+    # dense effective-Hamiltonian apply at D (microbenchmark)
+    heff = {}
+    Dh, DH = args.heff_D, 18
+    if Dh > 0:
+        L, W, A, R = WL.heff_inputs(Dh, DH)
+        dev = torch.device("cuda:0")
+        tl, tw, ta, tr = (torch.from_numpy(x).to(dev) for x in (L, W, A, R))
+        out = torch.empty_like(ta)
+        fl = 32.0 * DH * Dh * Dh * (2 * Dh) + 128.0 * DH * DH * Dh * Dh
+        sm = torch.cuda.current_stream().cuda_stream
+        for pname in args.heff_precisions.split(","):
+            p = PREC[pname]
+            T.tt_heff_apply(Dh, Dh, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(), p, sm)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(args.heff_reps):
+                T.tt_heff_apply(Dh, Dh, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(),
+                                p, sm)
+                ms.append(T.tt_heff_last_timing())
+            med = statistics.median(x[3] for x in ms)
+            heff[pname] = dict(ms=med, tflops=fl / (med * 1e-3) / 1e12, applies_per_s=1e3 / med,
+                               stage_ms=[statistics.median(x[i] for x in ms) for i in range(3)])
+        print("heff done", file=sys.stderr, flush=True)
+        del tl, tw, ta, tr, out
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t_apply, fl_apply = cpu_baseline(args.cpu_D, DH)
+        rate = fl_apply / t_apply
+        est = dense_sweep_flops(dims, DH, c["krylov"]) / rate
+        cpu = dict(value=est, unit="s/step", cores=nthreads, kind="oracle",
+                   sample="one dense oracle H_eff apply at D=%d (%.3g flop, %.2f s, %.3g flop/s) scaled by the "
+                          "dense-equivalent flops of one sweep of the same bond dimensions (%.3g flop)"
+                          % (args.cpu_D, fl_apply, t_apply, rate, dense_sweep_flops(dims, DH, c["krylov"])))
+
+    line = {
+        "metric": "TDVP beta-sweep s/step & H_eff TFLOP/s (FP64 vs split-BF16) at D=2000",
+        "value": s_per_step,
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": s_per_step * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16x6": "bf16x6+f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "Hubbard %dx%d %s, U=%g, mu=%g, U(1)xU(1) D=%d, d_beta=%g, Krylov %d"
+                   % (c["W"], c["L"], "cylinder" if c["geometry"] == 1 else "open square", c["U"], c["mu"], D,
+                      c["dbeta"], c["krylov"]),
+                   "n_sites": n_sites, "max_bond": max(dims), "parallelism": "single GPU"},
+        "sweep": {"flops_alg_per_step": flops_step, "tflops_alg": flops_step / s_per_step / 1e12,
+                  "applies_per_step": applies_step, "applies_per_s": applies_step / s_per_step,
+                  "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"]},
+        "heff": {"D": Dh, "D_H": DH, **heff},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,6 +75,7 @@ typedef struct {
   double pad_eps;      /* amplitude of the seeded padding noise (0: zero padding) */
   uint64_t seed;       /* SplitMix64 seed of the padding noise */
   int env_on_host;     /* must be 0 (not supported) */
+  int sector_cap;      /* largest U(1)xU(1) sector of a padded bond (0: no cap) */
 } tt_options;
 
 typedef struct {
@@ -99,7 +100,7 @@ typedef struct {
 } tt_sweep_stats;
 
 /* Default options: D=64, symmetry=1, beta0=1e-2, taylor_order=1, K=8,
- * tol=1e-13, FP64, pad_eps=0, seed=1, env_on_host=0. */
+ * tol=1e-13, FP64, pad_eps=0, seed=1, env_on_host=0, sector_cap=64. */
 int tt_options_default(tt_options* opts);
 
 /* Build rho0 = 1 - beta0*H (main text, noninteracting-benchmark paragraph)
@@ -170,6 +171,15 @@ int tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free_fn, void* ctx);
  * events on the stream it ran on: [0] L.A, [1] W stage, [2] .R, [3] total.
  * Synchronises. */
 int tt_heff_last_timing(double* host_ms4);
+
+/* Opt-in kernel timing: when on, every launch of the grouped GEMM, the MPO
+ * (W) stage and the QR kernel is bracketed by HIP events on its stream.
+ * tt_profile_read synchronises those events and fills host_out12 with
+ * {ms, flops, bytes, launches} for [GEMM, W stage, QR] accumulated since the
+ * previous read (flops and bytes are algorithmic: sum of 2mnk, operands read
+ * once), then resets. */
+int tt_profile_enable(int on);
+int tt_profile_read(double* host_out12);
 
 /* Host-only: the sectors bond k would get for this model and options (same
  * calling convention as tt_state_bond_sectors).  No GPU needed. */

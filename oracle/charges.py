@@ -21,8 +21,11 @@ Sector dimensions at bond k (0 < k < N) for a target D:
 * if sum_q Dmax_k(q) <= D every sector is maximal;
 * else sizes proportional to w(q) = C(2h, h+q_up) C(2h, h+q_dn),
   h = min(k, N-k, 14), by the largest-remainder rule in exact integers (ties
-  to the lexicographically smaller q), then raised to the number of rho0
-  states of charge q and capped at Dmax_k(q);
+  to the lexicographically smaller q), with every sector capped at
+  c(q) = min(Dmax_k(q), sector_cap) (sector_cap = 0: no cap): sectors whose
+  share exceeds their cap are fixed at the cap and the rest of D is shared
+  again among the others, until no share exceeds its cap; then every sector
+  is raised to the number of rho0 states of charge q;
 * then capped, until nothing changes, by the rows a left-to-right QR can
   supply (sum_Delta n(Delta) d_{k-1}(q - Delta)) and by the columns a
   right-to-left LQ can supply (sum_Delta n(Delta) d_{k+1}(q + Delta)).
@@ -37,9 +40,15 @@ symmetry, charge-allowed): pad_eps * (2u - 1), u in [0, 1) from SplitMix64
 with n = site*2^40 + flat + 1, flat = (x*16 + s)*D_{k+1} + y, and u the top
 53 bits times 2^-53.
 """
-from math import comb
+from functools import lru_cache
+from math import comb as _comb
 
 import numpy as np
+
+
+@lru_cache(maxsize=None)
+def comb(n, k):
+    return _comb(n, k)
 
 MASK = (1 << 64) - 1
 GAMMA = 0x9E3779B97F4A7C15
@@ -83,7 +92,20 @@ def _dmax(N, k, q):
     return min(cnt(k), cnt(m))
 
 
-def allocate_sectors(N, D, n0):
+def _share(D, qs, w):
+    """Largest-remainder split of D proportional to w (exact integers)."""
+    tot = sum(w[q] for q in qs)
+    if tot == 0 or D <= 0:
+        return {q: 0 for q in qs}
+    base = {q: (D * w[q]) // tot for q in qs}
+    rem = {q: (D * w[q]) % tot for q in qs}
+    left = D - sum(base.values())
+    for q in sorted(qs, key=lambda q: (-rem[q], q))[:left]:
+        base[q] += 1
+    return base
+
+
+def allocate_sectors(N, D, n0, sector_cap=0):
     """Sector dimensions per bond.  n0[k] maps charge -> number of rho0
     states.  Returns a list over bonds 0..N of dicts {q: dim} (nonzero)."""
     dims = [{(0, 0): 1}]
@@ -100,13 +122,17 @@ def allocate_sectors(N, D, n0):
                 a, b = q
                 w[q] = (comb(2 * hw, hw + a) * comb(2 * hw, hw + b)
                         if abs(a) <= hw and abs(b) <= hw else 0)
-            tot = sum(w.values())
-            base = {q: (D * w[q]) // tot for q in qs}
-            rem = {q: (D * w[q]) % tot for q in qs}
-            left = D - sum(base.values())
-            order = sorted(qs, key=lambda q: (-rem[q], q))
-            for q in order[:left]:
-                base[q] += 1
+            cap = {q: dmax[q] if sector_cap <= 0 else min(dmax[q], sector_cap) for q in qs}
+            fixed = {}
+            while True:
+                free = [q for q in qs if q not in fixed]
+                base = _share(D - sum(fixed.values()), free, w)
+                over = [q for q in free if base[q] > cap[q]]
+                if not over:
+                    break
+                for q in over:
+                    fixed[q] = cap[q]
+            base.update(fixed)
             d = {q: min(max(base[q], n0[k].get(q, 0)), dmax[q]) for q in qs}
         dims.append({q: v for q, v in d.items() if v > 0})
     dims.append({(0, 0): 1})
@@ -146,7 +172,7 @@ class BondLayout:
         return len(self.charges)
 
 
-def bond_layouts(rho0_charges, N, D, symmetric):
+def bond_layouts(rho0_charges, N, D, symmetric, sector_cap=0):
     """Layouts of bonds 0..N.  rho0_charges[k] = charge per rho0 bond state."""
     layouts = []
     if symmetric:
@@ -156,7 +182,7 @@ def bond_layouts(rho0_charges, N, D, symmetric):
             for q in rho0_charges[k]:
                 cnt[q] = cnt.get(q, 0) + 1
             n0.append(cnt)
-        dims = allocate_sectors(N, D, n0)
+        dims = allocate_sectors(N, D, n0, sector_cap)
         for k in range(N + 1):
             secs = sorted(dims[k])
             off, p = {}, 0

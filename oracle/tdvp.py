@@ -269,7 +269,7 @@ class State:
 
 
 # ---------------------------------------------------------------- start state
-def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0):
+def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0, sector_cap=0):
     """rho0 = 1 - beta0 H (main text, noninteracting-benchmark paragraph)
     padded to bond D as described in ``oracle.charges``, right-canonicalised,
     centre normalised into Lambda; beta = beta0."""
@@ -278,7 +278,7 @@ def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0):
     A0 = mpo_model.rho0_tensors(beta0)
     rho0_q = [mpo_model.bond_charges(k) for k in range(N)]
     rho0_q.append([(0, 0)])            # bond N of rho0 after the boundary vector
-    layouts = charges.bond_layouts(rho0_q, N, D, symmetric)
+    layouts = charges.bond_layouts(rho0_q, N, D, symmetric, sector_cap)
     A = charges.padded_rho0(A0, layouts, symmetric, pad_eps, seed)
     st = State(A, mpo_model.mpo_for_env(), beta0)
     if symmetric:

@@ -81,16 +81,29 @@ void upload_plan(WPlan& p, hipStream_t st) {
   p.d_tasks = upload(p.tasks, st);
   p.d_terms = upload(p.terms, st);
 }
+// assign workspace (global fallback area first, then the LDS path's chunk
+// factors) and upload every descriptor of a QR plan
 void upload_plan(QRPlan& p, hipStream_t st) {
   p.ntasks = (int)p.tasks.size();
+  long long pos = 0;
   for (auto& t : p.tasks) {
     TT_REQUIRE(t.m >= t.n, TT_ENUMERIC, "QR of a charge block with more columns than rows");
+    t.ws = pos;
+    pos += 2LL * t.m * t.n + t.n;
   }
+  p.ws_size = pos;
+  qr_plan_chunks(p);
   p.d_tasks = upload(p.tasks, st);
+  p.d_chunks = upload(p.chunks, st);
+  p.d_stacks = upload(p.stacks, st);
+  p.d_wide = upload(p.wide, st);
 }
 void free_plan(GemmPlan& p) { dfree(p.d_probs); dfree(p.d_tiles); p.d_probs = nullptr; p.d_tiles = nullptr; }
 void free_plan(WPlan& p) { dfree(p.d_tasks); dfree(p.d_terms); p.d_tasks = nullptr; p.d_terms = nullptr; }
-void free_plan(QRPlan& p) { dfree(p.d_tasks); p.d_tasks = nullptr; }
+void free_plan(QRPlan& p) {
+  dfree(p.d_tasks); dfree(p.d_chunks); dfree(p.d_stacks); dfree(p.d_wide);
+  p.d_tasks = nullptr; p.d_chunks = nullptr; p.d_stacks = nullptr; p.d_wide = nullptr;
+}
 
 }  // namespace
 
@@ -327,20 +340,7 @@ void alloc_state(tt_state& s) {
     upload_plan(P.qr, st); upload_plan(P.lq, st);
     t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size);
     y = std::max(y, P.y_size); z = std::max(z, P.z_size); u = std::max(u, P.u_size);
-    long long qwa = 0, qwb = 0;
-    for (auto& t : P.qr.tasks) qwa = std::max(qwa, t.ws + 2LL * t.m * t.n + t.n);
-    for (auto& t : P.lq.tasks) qwb = std::max(qwb, t.ws + 2LL * t.m * t.n + t.n);
-    qw = std::max(qw, std::max(qwa, qwb));
-  }
-  // every task's workspace: 2 m n + n doubles (W, Q, tau)
-  for (auto& P : s.plans) {
-    for (auto* pl : {&P.qr, &P.lq}) {
-      long long pos = 0;
-      for (auto& t : pl->tasks) { t.ws = pos; pos += 2LL * t.m * t.n + t.n; }
-      qw = std::max(qw, pos);
-      if (!pl->tasks.empty())
-        HIPX(hipMemcpyAsync(pl->d_tasks, pl->tasks.data(), sizeof(QRTask) * pl->tasks.size(), hipMemcpyHostToDevice, st));
-    }
+    qw = std::max(qw, std::max(P.qr.ws_size + P.qr.lds_ws, P.lq.ws_size + P.lq.lds_ws));
   }
   s.max_site = 0;
   for (auto& l : s.site) s.max_site = std::max(s.max_site, l.size);
@@ -480,7 +480,7 @@ std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
   for (int k = 0; k < N; ++k)
     for (int a = 0; a < s.mpo.DH[k]; ++a) n0[k][s.mpo.charge(k, a)]++;
   n0[N][{0, 0}] = 1;
-  if (s.opts.symmetry) return allocate_sectors(N, s.opts.D, n0);
+  if (s.opts.symmetry) return allocate_sectors(N, s.opts.D, n0, s.opts.sector_cap);
   std::vector<std::map<Q, int>> d(N + 1);
   for (int k = 0; k <= N; ++k) {
     int n = (k == N) ? 1 : s.mpo.DH[k];
@@ -500,11 +500,12 @@ void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(o.krylov_tol >= 0.0, TT_EINVAL, "krylov_tol must be >= 0");
   TT_REQUIRE(o.precision == TT_FP64, TT_EINVAL, "sweeps run in FP64 only");
   TT_REQUIRE(o.env_on_host == 0, TT_EINVAL, "host-resident environments are not supported");
+  TT_REQUIRE(o.sector_cap >= 0, TT_EINVAL, "sector_cap must be >= 0");
   TT_REQUIRE(std::isfinite(o.beta0) && std::isfinite(o.pad_eps), TT_EINVAL, "beta0 and pad_eps must be finite");
   TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.U) && std::isfinite(m.mu), TT_EINVAL, "model parameters must be finite");
 }
 
-std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o) {
+std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o, bool with_plans = true) {
   validate(m, o);
   auto s = std::make_unique<tt_state>();
   s->model = m;
@@ -513,7 +514,14 @@ std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o
   s->N = s->lat.N;
   s->mpo = make_hubbard_mpo(s->lat, m.t, m.U, m.mu);
   s->G = make_groups(o.symmetry == 1);
-  build_layouts(*s, bond_dims(*s));
+  auto dims = bond_dims(*s);
+  if (with_plans) {
+    build_layouts(*s, dims);
+  } else {
+    s->bonds.assign(s->N + 1, Bond());
+    for (int k = 0; k <= s->N; ++k)
+      for (auto& kv : dims[k]) s->bonds[k].add(kv.first, kv.second);
+  }
   return s;
 }
 
@@ -601,6 +609,23 @@ long long check_qr(const QRPlan& p, const std::vector<long long>& tabs, long lon
     ws += 2LL * t.m * t.n + t.n;
   }
   (void)ws;
+  QRPlan q = p;
+  qr_plan_chunks(q);
+  std::vector<int> covered(q.tasks.size(), 0);
+  for (auto& c : q.chunks) {
+    const QRTask& t = q.tasks.at(c.task);
+    if (c.row0 < 0 || c.rows < t.n || c.row0 + c.rows > t.m) ++bad;
+    if ((long long)c.rows * t.n > kQrLdsDoubles || t.n > kQrLdsMaxN) ++bad;
+    if (c.nchunks > 1) {
+      if (c.qw < 0 || c.qw + (long long)c.rows * t.n > q.lds_ws) ++bad;
+      if (c.rw < 0 || c.rw + (long long)c.nchunks * t.n * t.n > q.lds_ws) ++bad;
+      if ((long long)c.nchunks * t.n * t.n > kQrLdsDoubles) ++bad;
+    }
+    covered[c.task] += c.rows;
+  }
+  for (int w : q.wide) covered.at(w) += q.tasks[w].m;
+  for (size_t i = 0; i < q.tasks.size(); ++i)
+    if (covered[i] != q.tasks[i].m) { ++bad; rep += std::string(name) + " QR rows not covered exactly once\n"; }
   return bad;
 }
 
@@ -745,7 +770,7 @@ int tt_options_default(tt_options* o) {
   if (!o) { g_err = "null options"; return TT_EINVAL; }
   o->D = 64; o->symmetry = 1; o->beta0 = 1e-2; o->taylor_order = 1;
   o->krylov_dim = 8; o->krylov_tol = 1e-13; o->precision = TT_FP64;
-  o->pad_eps = 0.0; o->seed = 1; o->env_on_host = 0;
+  o->pad_eps = 0.0; o->seed = 1; o->env_on_host = 0; o->sector_cap = 64;
   return TT_OK;
 }
 
@@ -1062,8 +1087,24 @@ int tt_model_bond_sectors(const tt_model* model, const tt_options* opts, int k, 
                           int* dim) {
   ABI_BEGIN
   TT_REQUIRE(model && opts && nsec, TT_EINVAL, "null argument");
-  auto s = make_host_state(*model, *opts);
+  auto s = make_host_state(*model, *opts, false);
   return tt_state_bond_sectors(s.get(), k, nsec, qu, qd, dim);
+  ABI_END
+}
+
+int tt_profile_enable(int on) {
+  ABI_BEGIN
+  prof_enable(on != 0);
+  ABI_END
+}
+
+int tt_profile_read(double* host_out12) {
+  ABI_BEGIN
+  TT_REQUIRE(host_out12, TT_EINVAL, "null argument");
+  double out[PROF_KINDS][4];
+  prof_read(out);
+  for (int k = 0; k < PROF_KINDS; ++k)
+    for (int j = 0; j < 4; ++j) host_out12[k * 4 + j] = out[k][j];
   ABI_END
 }
 

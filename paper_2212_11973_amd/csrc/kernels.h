@@ -10,9 +10,22 @@ namespace tt {
 constexpr int kRedBlocks = 256;
 constexpr int kMaxKrylov = 32;
 
+// Optional timing of the grouped kernels: HIP events around every launch on its stream.
+enum ProfKind { PROF_GEMM = 0, PROF_WSTAGE = 1, PROF_QR = 2, PROF_KINDS = 3 };
+void prof_enable(bool on);
+bool prof_enabled();
+void prof_begin(hipStream_t st);
+void prof_end(hipStream_t st, int kind, double flops, double bytes);
+// (ms, flops, bytes, launches) per kind since the last read; synchronises the events
+void prof_read(double out[PROF_KINDS][4]);
+
 void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, hipStream_t st);
 void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st);
+// QR of every task of the plan: LDS chunk/stack/combine kernels for n <= 64,
+// the global-memory kernel for wider tasks.  ws holds p.ws_size + p.lds_ws doubles.
 void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, double* ws, hipStream_t st);
+// split the tasks of a plan into LDS chunks and stacks (host)
+void qr_plan_chunks(QRPlan& p);
 
 // Lanczos pieces (see engine for the sequence)
 void launch_mdot(const double* Q, long long ld, int nv, const double* y, long long n, int with_self,

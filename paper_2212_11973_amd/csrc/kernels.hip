@@ -9,14 +9,17 @@
 //  * k_wstage    : the contraction with the Hamiltonian MPO tensor W, which is
 //                  sparse (a few nonzero 4x4 operators per bond pair); a
 //                  bandwidth-bound weighted sum of strided blocks.
-//  * k_qr        : Householder QR of one charge block per workgroup with
-//                  non-negative diagonal (SM Sec. II.F step 3).
+//  * k_qr_*      : Householder QR of the charge blocks with non-negative
+//                  diagonal (SM Sec. II.F step 3): in LDS, tall blocks as a
+//                  two-level tall-skinny QR; blocks wider than 64 columns in
+//                  global memory, one workgroup each.
 //  * Lanczos     : deterministic fixed-order reductions, Gram-Schmidt
 //                  updates and the small tridiagonal exponential on the device
 //                  (SM Sec. II.H), so a local exponential needs no host sync.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 
 #include "kernels.h"
 
@@ -29,6 +32,52 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
     hipError_t e_ = hipGetLastError();                                           \
     if (e_ != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e_));        \
   } while (0)
+
+// ------------------------------------------------------------------ profiling
+namespace {
+struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; };
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+hipEvent_t g_open = nullptr;
+hipEvent_t take_event() {
+  if (!g_pool.empty()) { hipEvent_t e = g_pool.back(); g_pool.pop_back(); return e; }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) throw Error(TT_EDEVICE, "hipEventCreate failed");
+  return e;
+}
+}  // namespace
+
+void prof_enable(bool on) { g_prof = on; }
+bool prof_enabled() { return g_prof; }
+void prof_begin(hipStream_t st) {
+  if (!g_prof) return;
+  g_open = take_event();
+  if (hipEventRecord(g_open, st) != hipSuccess) throw Error(TT_EDEVICE, "hipEventRecord failed");
+}
+void prof_end(hipStream_t st, int kind, double flops, double bytes) {
+  if (!g_prof || !g_open) return;
+  hipEvent_t b = take_event();
+  if (hipEventRecord(b, st) != hipSuccess) throw Error(TT_EDEVICE, "hipEventRecord failed");
+  g_recs.push_back({g_open, b, kind, flops, bytes});
+  g_open = nullptr;
+}
+void prof_read(double out[PROF_KINDS][4]) {
+  for (int k = 0; k < PROF_KINDS; ++k)
+    for (int j = 0; j < 4; ++j) out[k][j] = 0.0;
+  for (auto& r : g_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) throw Error(TT_EDEVICE, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw Error(TT_EDEVICE, "hipEventElapsedTime failed");
+    out[r.kind][0] += ms;
+    out[r.kind][1] += r.flops;
+    out[r.kind][2] += r.bytes;
+    out[r.kind][3] += 1;
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+}
 
 // ------------------------------------------------------------------ GEMM
 constexpr int BM = 64, BN = 64, BK = 16;
@@ -129,8 +178,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
 void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, hipStream_t st) {
   (void)precision;
   if (p.ntiles == 0) return;
+  prof_begin(st);
   hipLaunchKernelGGL(k_gemm_f64, dim3(p.ntiles), dim3(256), 0, st, p.d_probs, p.d_tiles, d_tabs, s);
   HIP_CHECK_LAUNCH();
+  prof_end(st, PROF_GEMM, p.flops, p.bytes);
 }
 
 // ------------------------------------------------------------------ W stage
@@ -151,8 +202,10 @@ __global__ __launch_bounds__(256) void k_wstage(const WTask* __restrict__ tasks,
 
 void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st) {
   if (p.ntasks == 0) return;
+  prof_begin(st);
   hipLaunchKernelGGL(k_wstage, dim3(p.ntasks), dim3(256), 0, st, p.d_tasks, p.d_terms, in, out);
   HIP_CHECK_LAUNCH();
+  prof_end(st, PROF_WSTAGE, p.flops, p.bytes);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -176,11 +229,11 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ------------------------------------------------------------------ QR
-__global__ __launch_bounds__(256) void k_qr(const QRTask* __restrict__ tasks, const long long* __restrict__ tabs,
-                                            double* A, double* S, double* ws) {
+__global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
+                                                 const long long* __restrict__ tabs, double* A, double* S, double* ws) {
   __shared__ double red[8];
   __shared__ double s_tau[1];
-  const QRTask T = tasks[blockIdx.x];
+  const QRTask T = tasks[wide[blockIdx.x]];
   const int m = T.m, n = T.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* Wm = ws + T.ws;                 // m x n column-major
   double* Qm = Wm + (long long)m * n;     // m x n column-major
@@ -262,10 +315,234 @@ __global__ __launch_bounds__(256) void k_qr(const QRTask* __restrict__ tasks, co
   }
 }
 
+// ---- LDS-resident Householder QR (column-major W[i + j*m] in LDS)
+// On return the upper triangle holds R (diagonal of either sign) and the
+// reflector vectors sit below the diagonal; tau[j] are their factors.
+__device__ void lds_householder(double* W, int m, int n, double* tau, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j < n; ++j) {
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+      double x = W[i + j * m];
+      part += x * x;
+    }
+    double xn2 = block_sum(part, red);
+    double alpha = W[j + j * m];
+    double tj = 0.0;
+    if (xn2 > 0.0) {
+      double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tj = (beta - alpha) / beta;
+      double scal = 1.0 / (alpha - beta);
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) W[i + j * m] *= scal;
+      __syncthreads();   // every wave has read alpha before the diagonal is replaced
+      if (tid == 0) W[j + j * m] = beta;
+    }
+    if (tid == 0) tau[j] = tj;
+    __syncthreads();
+    if (tj != 0.0) {
+      const double* v = W + j * m;
+      for (int c = j + 1 + wave; c < n; c += nw) {
+        double* col = W + c * m;
+        double d = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
+        d = wave_sum(d);
+        d = __shfl(d, 0, 64) + col[j];
+        const double f = tj * d;
+        if (lane == 0) col[j] -= f;
+        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Overwrite the reflectors with the explicit m x n Q (backward accumulation,
+// column j starts as e_j).  R must have been saved before.
+__device__ void lds_form_q(double* W, int m, int n, const double* tau) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = n - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      const double* v = W + j * m;
+      for (int c = j + 1 + wave; c < n; c += nw) {
+        double* col = W + c * m;
+        double d = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
+        d = wave_sum(d);
+        d = __shfl(d, 0, 64) + col[j];
+        const double f = tj * d;
+        if (lane == 0) col[j] -= f;
+        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += blockDim.x) {
+      double v = (i > j) ? W[i + j * m] : 0.0;
+      W[i + j * m] = (i == j) ? 1.0 - tj : (i > j ? -tj * v : 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ long long qr_row(const QRTask& T, const long long* tabs, int i) {
+  return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs;
+}
+
+// kernel 1: QR of one row chunk in LDS.  Single-chunk tasks are finished here
+// (sign fix, Q to the matrix, R to S); otherwise Q_c goes to ws[qw] and R_c
+// (upper n x n) to the stacked R at ws[rw] (column-major, leading dim nchunks*n).
+__global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ tasks, const QRChunk* __restrict__ chunks,
+                                                   const long long* __restrict__ tabs, double* A, double* S,
+                                                   double* ws) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
+  const QRChunk C = chunks[blockIdx.x];
+  const QRTask T = tasks[C.task];
+  const int m = C.rows, n = T.n, tid = threadIdx.x;
+  double* W = lds;
+  for (int e = tid; e < m * n; e += blockDim.x) {
+    int i = e % m, j = e / m;
+    W[e] = A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs];
+  }
+  __syncthreads();
+  lds_householder(W, m, n, tau, red);
+  if (C.nchunks == 1) {
+    for (int j = tid; j < n; j += blockDim.x) sgn[j] = W[j + j * m] < 0.0 ? -1.0 : 1.0;
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      int i = e / n, j = e % n;
+      double val = (i <= j) ? sgn[i] * W[i + j * m] : 0.0;
+      S[T.sdst + (T.trans ? (long long)j * n + i : (long long)i * n + j)] = val;
+    }
+    __syncthreads();
+    lds_form_q(W, m, n, tau);
+    for (int e = tid; e < m * n; e += blockDim.x) {
+      int i = e % m, j = e / m;
+      A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs] = sgn[j] * W[e];
+    }
+    return;
+  }
+  const long long ldr = (long long)C.nchunks * n;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    int i = e % n, j = e / n;
+    ws[C.rw + (long long)j * ldr + (long long)C.chunk * n + i] = (i <= j) ? W[i + j * m] : 0.0;
+  }
+  __syncthreads();
+  lds_form_q(W, m, n, tau);
+  for (int e = tid; e < m * n; e += blockDim.x) ws[C.qw + e] = W[e];
+}
+
+// kernel 2: QR of the stacked chunk R factors; final R (non-negative
+// diagonal) to S, second-level Q (sign-fixed) back over the stack.
+__global__ __launch_bounds__(1024) void k_qr_stack(const QRTask* __restrict__ tasks, const QRStack* __restrict__ stacks,
+                                                   double* S, double* ws) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
+  const QRStack K = stacks[blockIdx.x];
+  const QRTask T = tasks[K.task];
+  const int n = T.n, m = K.nchunks * n, tid = threadIdx.x;
+  double* W = lds;
+  for (int e = tid; e < m * n; e += blockDim.x) W[e] = ws[K.rw + e];
+  __syncthreads();
+  lds_householder(W, m, n, tau, red);
+  for (int j = tid; j < n; j += blockDim.x) sgn[j] = W[j + j * m] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    int i = e / n, j = e % n;
+    double val = (i <= j) ? sgn[i] * W[i + j * m] : 0.0;
+    S[T.sdst + (T.trans ? (long long)j * n + i : (long long)i * n + j)] = val;
+  }
+  __syncthreads();
+  lds_form_q(W, m, n, tau);
+  for (int e = tid; e < m * n; e += blockDim.x) {
+    int j = e / m;
+    ws[K.rw + e] = sgn[j] * W[e];
+  }
+}
+
+// kernel 3: final Q rows of a chunk = Q_c (rows x n) . Q2_c (n x n)
+__global__ __launch_bounds__(256) void k_qr_combine(const QRTask* __restrict__ tasks, const QRChunk* __restrict__ chunks,
+                                                    const long long* __restrict__ tabs, double* A,
+                                                    const double* __restrict__ ws) {
+  __shared__ double Q2[kQrLdsMaxN * kQrLdsMaxN];
+  const QRChunk C = chunks[blockIdx.x];
+  if (C.nchunks == 1) return;
+  const QRTask T = tasks[C.task];
+  const int m = C.rows, n = T.n, tid = threadIdx.x;
+  const long long ldr = (long long)C.nchunks * n;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    int k = e % n, j = e / n;
+    Q2[k + j * n] = ws[C.rw + (long long)j * ldr + (long long)C.chunk * n + k];
+  }
+  __syncthreads();
+  for (int e = tid; e < m * n; e += blockDim.x) {
+    int i = e % m, j = e / m;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += ws[C.qw + i + (long long)k * m] * Q2[k + j * n];
+    A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs] = acc;
+  }
+}
+
+void qr_plan_chunks(QRPlan& p) {
+  p.chunks.clear();
+  p.stacks.clear();
+  p.wide.clear();
+  long long pos = 0;
+  for (int t = 0; t < (int)p.tasks.size(); ++t) {
+    const QRTask& T = p.tasks[t];
+    const int m = T.m, n = T.n;
+    if (n > kQrLdsMaxN) { p.wide.push_back(t); continue; }
+    int nc = 1;
+    if ((long long)m * n > kQrLdsDoubles) {
+      int mc = kQrLdsDoubles / n;
+      nc = (m + mc - 1) / mc;
+      if ((long long)nc * n * n > kQrLdsDoubles || m / nc < n) { p.wide.push_back(t); continue; }
+    }
+    long long rw = pos;
+    if (nc > 1) pos += (long long)nc * n * n;
+    for (int c = 0; c < nc; ++c) {
+      int r0 = (int)((long long)m * c / nc), r1 = (int)((long long)m * (c + 1) / nc);
+      QRChunk ch{t, r0, r1 - r0, c, nc, 0, 0, rw};
+      if (nc > 1) { ch.qw = pos; pos += (long long)(r1 - r0) * n; }
+      p.chunks.push_back(ch);
+    }
+    if (nc > 1) p.stacks.push_back({t, nc, rw});
+  }
+  p.lds_ws = pos;
+}
+
 void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, double* ws, hipStream_t st) {
   if (p.ntasks == 0) return;
-  hipLaunchKernelGGL(k_qr, dim3(p.ntasks), dim3(256), 0, st, p.d_tasks, d_tabs, A, S, ws);
-  HIP_CHECK_LAUNCH();
+  static bool attr = false;
+  const size_t shm = sizeof(double) * kQrLdsDoubles;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_qr_chunk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_qr_stack, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess)
+      throw Error(TT_EDEVICE, "cannot raise the LDS limit of the QR kernels");
+    attr = true;
+  }
+  prof_begin(st);
+  double* lws = ws + p.ws_size;
+  if (!p.chunks.empty()) {
+    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size()), dim3(1024), shm, st, p.d_tasks, p.d_chunks,
+                       d_tabs, A, S, lws);
+    HIP_CHECK_LAUNCH();
+  }
+  if (!p.stacks.empty()) {
+    hipLaunchKernelGGL(k_qr_stack, dim3((unsigned)p.stacks.size()), dim3(1024), shm, st, p.d_tasks, p.d_stacks, S, lws);
+    HIP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_qr_combine, dim3((unsigned)p.chunks.size()), dim3(256), 0, st, p.d_tasks, p.d_chunks, d_tabs,
+                       A, lws);
+    HIP_CHECK_LAUNCH();
+  }
+  if (!p.wide.empty()) {
+    hipLaunchKernelGGL(k_qr_wide, dim3((unsigned)p.wide.size()), dim3(256), 0, st, p.d_tasks, p.d_wide, d_tabs, A, S,
+                       ws);
+    HIP_CHECK_LAUNCH();
+  }
+  prof_end(st, PROF_QR, p.flops, p.bytes);
 }
 
 // ------------------------------------------------------------------ Lanczos
@@ -340,60 +617,76 @@ __global__ void k_lz_next(const double* __restrict__ w, double* __restrict__ qn,
     qn[i] = w[i] * inv;
 }
 
-// coefficients of exp(t T) e_1 * ||v|| for the Krylov tridiagonal T (cyclic Jacobi eigensolver)
-__global__ void k_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t,
-                            double tol, const double* scal, double* coeff, double* errmax) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double a[kMaxKrylov][kMaxKrylov], V[kMaxKrylov][kMaxKrylov];
-  int k = K;
-  for (int j = 0; j < K - 1; ++j)
-    if (!(beta[j] > tol * hn[j]) || beta[j] == 0.0) { k = j + 1; break; }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      a[i][j] = 0.0;
-      V[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-  for (int i = 0; i < k; ++i) a[i][i] = alpha[i];
-  for (int i = 0; i + 1 < k; ++i) a[i][i + 1] = a[i + 1][i] = beta[i];
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, dia = 0.0;
+// coefficients of exp(t T) e_1 * ||v|| for the Krylov tridiagonal T: Taylor
+// series of (tT)/2^s with 2^s >= 2 ||tT||_inf, then s squarings; one thread per
+// matrix element, everything in LDS.
+__global__ __launch_bounds__(256) void k_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K,
+                                                   double t, double tol, const double* scal, double* coeff,
+                                                   double* errmax) {
+  __shared__ double A[kMaxKrylov * kMaxKrylov], E[kMaxKrylov * kMaxKrylov], P[kMaxKrylov * kMaxKrylov],
+      X[kMaxKrylov * kMaxKrylov];
+  __shared__ int s_k, s_sq;
+  __shared__ double s_done;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int k = K;
+    for (int j = 0; j < K - 1; ++j)
+      if (!(beta[j] > tol * hn[j]) || beta[j] == 0.0) { k = j + 1; break; }
+    double nrm = 0.0;
     for (int i = 0; i < k; ++i) {
-      dia += a[i][i] * a[i][i];
-      for (int j = i + 1; j < k; ++j) off += a[i][j] * a[i][j];
+      double r = fabs(alpha[i]) + (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i + 1 < k ? fabs(beta[i]) : 0.0);
+      nrm = fmax(nrm, fabs(t) * r);
     }
-    if (off <= 1e-32 * dia || off == 0.0) break;
-    for (int p = 0; p < k; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        if (a[p][q] == 0.0) continue;
-        double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
-        double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
-        for (int r = 0; r < k; ++r) {
-          double arp = a[r][p], arq = a[r][q];
-          a[r][p] = c * arp - s * arq;
-          a[r][q] = s * arp + c * arq;
-        }
-        for (int r = 0; r < k; ++r) {
-          double apr = a[p][r], aqr = a[q][r];
-          a[p][r] = c * apr - s * aqr;
-          a[q][r] = s * apr + c * aqr;
-        }
-        for (int r = 0; r < k; ++r) {
-          double vrp = V[r][p], vrq = V[r][q];
-          V[r][p] = c * vrp - s * vrq;
-          V[r][q] = s * vrp + c * vrq;
-        }
-      }
+    int sq = 0;
+    while (nrm > 0.5 && sq < 60) { nrm *= 0.5; ++sq; }
+    s_k = k;
+    s_sq = sq;
   }
+  __syncthreads();
+  const int k = s_k, kk = k * k;
+  const double sc = ldexp(t, -s_sq);
+  for (int e = tid; e < kk; e += blockDim.x) {
+    int i = e / k, j = e % k;
+    double v = 0.0;
+    if (i == j) v = alpha[i];
+    else if (j == i + 1) v = beta[i];
+    else if (i == j + 1) v = beta[j];
+    A[e] = sc * v;
+    E[e] = (i == j) ? 1.0 : 0.0;
+    P[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // E = sum_{d<=24} A^d / d!  (||A|| <= 1/2: the tail is below 1e-25)
+  for (int d = 1; d <= 24; ++d) {
+    for (int e = tid; e < kk; e += blockDim.x) {
+      int i = e / k, j = e % k;
+      double acc = 0.0;
+      for (int q = 0; q < k; ++q) acc += P[i * k + q] * A[q * k + j];
+      X[e] = acc / d;
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += blockDim.x) {
+      P[e] = X[e];
+      E[e] += X[e];
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < s_sq; ++r) {
+    for (int e = tid; e < kk; e += blockDim.x) {
+      int i = e / k, j = e % k;
+      double acc = 0.0;
+      for (int q = 0; q < k; ++q) acc += E[i * k + q] * E[q * k + j];
+      X[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += blockDim.x) E[e] = X[e];
+    __syncthreads();
+  }
+  (void)s_done;
   const double nv = scal[0];
-  for (int i = 0; i < K; ++i) coeff[i] = 0.0;
-  for (int i = 0; i < k; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < k; ++j) s += V[i][j] * exp(t * a[j][j]) * V[0][j];
-    coeff[i] = nv * s;
-  }
-  if (k == K) {
-    double err = beta[K - 1] * fabs(coeff[K - 1]) / (nv > 0 ? nv : 1.0);
+  for (int i = tid; i < K; i += blockDim.x) coeff[i] = (i < k) ? nv * E[i * k + 0] : 0.0;
+  if (tid == 0 && k == K) {
+    double err = beta[K - 1] * fabs(E[(K - 1) * k + 0]);
     if (err > *errmax) *errmax = err;
   }
 }
@@ -462,7 +755,7 @@ void launch_lz_next(const double* w, double* qn, long long n, const double* part
 }
 void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t, double tol,
                       const double* scal, double* coeff, double* errmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_coeffs, dim3(1), dim3(64), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
+  hipLaunchKernelGGL(k_lz_coeffs, dim3(1), dim3(256), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_combine(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,

@@ -92,6 +92,30 @@ static void add_prob(GemmPlan& plan, const GemmProb& p) {
   if (p.M <= 0 || p.N <= 0) return;
   plan.probs.push_back(p);
   plan.flops += 2.0 * p.M * (double)p.N * p.K;
+  plan.bytes += 8.0 * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N);
+}
+
+// algorithmic traffic of a W stage: distinct source blocks read once, outputs written once
+static void finish_wplan(WPlan& w) {
+  std::vector<std::pair<long long, long long>> src;
+  double out = 0.0;
+  for (auto& t : w.tasks) {
+    out += (double)t.ni * t.nj;
+    for (int q = t.t0; q < t.t0 + t.nt; ++q) src.push_back({w.terms[q].src, (long long)t.ni * t.nj});
+  }
+  std::sort(src.begin(), src.end());
+  src.erase(std::unique(src.begin(), src.end()), src.end());
+  double in = 0.0;
+  for (auto& s : src) in += (double)s.second;
+  w.bytes = 8.0 * (in + out);
+}
+
+static void finish_qrplan(QRPlan& q) {
+  for (auto& t : q.tasks) {
+    double m = t.m, n = t.n;
+    q.flops += 4.0 * m * n * n - 4.0 / 3.0 * n * n * n;
+    q.bytes += 8.0 * (2.0 * m * n + n * n);
+  }
 }
 
 void tile_plan(GemmPlan& p, int BM, int BN) {
@@ -387,6 +411,10 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
       add_prob(P.b2, g);
     }
   }
+  finish_wplan(P.w2);
+  finish_wplan(P.wr);
+  finish_qrplan(P.qr);
+  finish_qrplan(P.lq);
   // ---------------- trace transfer: the group with delta = (0,0) holds the diagonal s = (sigma, sigma)
   int g0 = (G.ng == 1) ? 0 : 4;
   for (int l = 0; l < S.nl; ++l) {

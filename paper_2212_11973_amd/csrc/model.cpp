@@ -233,18 +233,20 @@ u128 sat_mul(u128 a, u128 b) {
   u128 r = a * b;
   return r > kSat ? kSat : r;
 }
-// binomial C(n, k) saturated at 2^120
+// binomial C(n, k) saturated at 2^120 (Pascal's triangle, cached)
 u128 binom(int n, int k) {
   if (k < 0 || k > n) return 0;
-  k = std::min(k, n - k);
-  // multiplicative formula with exact division; values here stay far below 2^120
-  // until saturation, which only happens for n > 120
-  u128 r = 1;
-  for (int i = 1; i <= k; ++i) {
-    if (r >= kSat / (u128)(n - k + i)) return kSat;
-    r = r * (u128)(n - k + i) / (u128)i;
+  static std::vector<std::vector<u128>> tri;
+  while ((int)tri.size() <= n) {
+    int r = (int)tri.size();
+    std::vector<u128> row(r + 1, 1);
+    for (int i = 1; i < r; ++i) {
+      u128 v = tri[r - 1][i - 1] + tri[r - 1][i];
+      row[i] = v > kSat ? kSat : v;
+    }
+    tri.push_back(std::move(row));
   }
-  return r;
+  return tri[n][k];
 }
 u128 count_side(int n, Q q) {
   if (std::abs(q.first) > n || std::abs(q.second) > n) return 0;
@@ -252,7 +254,8 @@ u128 count_side(int n, Q q) {
 }
 }  // namespace
 
-std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0) {
+std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0,
+                                               int sector_cap) {
   std::vector<std::map<Q, int>> dims(N + 1);
   dims[0][{0, 0}] = 1;
   dims[N][{0, 0}] = 1;
@@ -279,37 +282,54 @@ std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<s
       for (auto q : qs) d[q] = (int)dmax[q];
     } else {
       int hw = std::min(h, 14);
-      std::map<Q, u128> w;
-      u128 wt = 0;
+      std::map<Q, u128> w, cap;
       for (auto q : qs) {
         u128 v = 0;
         if (std::abs(q.first) <= hw && std::abs(q.second) <= hw)
           v = binom(2 * hw, hw + q.first) * binom(2 * hw, hw + q.second);
         w[q] = v;
-        wt += v;
+        cap[q] = (sector_cap <= 0) ? dmax[q] : std::min(dmax[q], (u128)sector_cap);
       }
-      std::map<Q, long long> base;
-      std::vector<std::pair<u128, Q>> rem;
-      long long used = 0;
-      for (auto q : qs) {
-        u128 num = (u128)D * w[q];
-        base[q] = (long long)(num / wt);
-        used += base[q];
-        rem.push_back({num % wt, q});
+      // largest-remainder split of D over the free sectors; sectors above their
+      // cap are fixed at the cap and the remainder is split again
+      std::map<Q, long long> fixed, base;
+      while (true) {
+        long long Dfree = D;
+        for (auto& kv : fixed) Dfree -= kv.second;
+        std::vector<Q> freeq;
+        u128 wt = 0;
+        for (auto q : qs)
+          if (!fixed.count(q)) { freeq.push_back(q); wt += w[q]; }
+        base.clear();
+        if (wt == 0 || Dfree <= 0) {
+          for (auto q : freeq) base[q] = 0;
+        } else {
+          std::vector<std::pair<u128, Q>> rem;
+          long long used = 0;
+          for (auto q : freeq) {
+            u128 num = (u128)Dfree * w[q];
+            base[q] = (long long)(num / wt);
+            used += base[q];
+            rem.push_back({num % wt, q});
+          }
+          std::sort(rem.begin(), rem.end(), [](const std::pair<u128, Q>& x, const std::pair<u128, Q>& y) {
+            if (x.first != y.first) return x.first > y.first;
+            return x.second < y.second;
+          });
+          long long left = Dfree - used;
+          for (long long i = 0; i < left && i < (long long)rem.size(); ++i) base[rem[i].second] += 1;
+        }
+        bool over = false;
+        for (auto q : freeq)
+          if ((u128)base[q] > cap[q]) { fixed[q] = (long long)cap[q]; over = true; }
+        if (!over) break;
       }
-      // largest remainder first, ties to the lexicographically smaller charge
-      std::sort(rem.begin(), rem.end(), [](const std::pair<u128, Q>& x, const std::pair<u128, Q>& y) {
-        if (x.first != y.first) return x.first > y.first;
-        return x.second < y.second;
-      });
-      long long left = D - used;
-      for (long long i = 0; i < left && i < (long long)rem.size(); ++i) base[rem[i].second] += 1;
+      for (auto& kv : fixed) base[kv.first] = kv.second;
       for (auto q : qs) {
         long long v = base[q];
         auto it = n0[k].find(q);
         if (it != n0[k].end()) v = std::max<long long>(v, it->second);
-        u128 cap = dmax[q];
-        if ((u128)v > cap) v = (long long)cap;
+        if ((u128)v > dmax[q]) v = (long long)dmax[q];
         d[q] = (int)v;
       }
     }

@@ -37,11 +37,21 @@ struct WTerm { long long src, ssi, ssj; double w; };
 // to S[sdst + i*n + j] (upper) or, if trans, to S[sdst + j*n + i] (lower: L = R^T).
 struct QRTask { int m, n, trans, pad; long long rbase, rs, cs, rtab, sdst, ws; };
 
+// LDS-resident QR (n <= kQrLdsMaxN): a task is split into row chunks that each
+// fit the LDS; chunk QRs, then one QR of the stacked chunk R factors, then the
+// product of the two Q levels (tall-skinny QR in two levels).  A task with one
+// chunk is finished by the chunk kernel.
+constexpr int kQrLdsMaxN = 64;
+constexpr int kQrLdsDoubles = 16384;
+struct QRChunk { int task, row0, rows, chunk, nchunks, pad; long long qw, rw; };
+struct QRStack { int task, nchunks; long long rw; };
+
 // A plan: descriptors uploaded once, launched many times with varying slots.
 struct GemmPlan {
   std::vector<GemmProb> probs;
   std::vector<GemmTile> tiles;
   double flops = 0;
+  double bytes = 0;        // algorithmic: every operand element read once, C written once
   GemmProb* d_probs = nullptr;
   GemmTile* d_tiles = nullptr;
   int ntiles = 0;
@@ -53,12 +63,24 @@ struct WPlan {
   WTerm* d_terms = nullptr;
   int ntasks = 0;
   double flops = 0;
+  double bytes = 0;        // algorithmic: every source block read once, every output written once
 };
 struct QRPlan {
   std::vector<QRTask> tasks;
   QRTask* d_tasks = nullptr;
   int ntasks = 0;
+  // LDS path: chunks of every task (n <= kQrLdsMaxN), stacks of multi-chunk tasks,
+  // and the global-memory fallback for wider tasks (indices into tasks)
+  std::vector<QRChunk> chunks;
+  std::vector<QRStack> stacks;
+  std::vector<int> wide;
+  QRChunk* d_chunks = nullptr;
+  QRStack* d_stacks = nullptr;
+  int* d_wide = nullptr;
+  long long lds_ws = 0;     // doubles: chunk Q factors and stacked R / Q2
   long long ws_size = 0;    // doubles of workspace (2 m n per task)
+  double flops = 0;         // Householder QR + explicit Q: 4 m n^2 - 4/3 n^3 per task
+  double bytes = 0;         // matrix read and written once, R written once
 };
 
 // bookkeeping of one site tensor: row block per left sector l, columns

@@ -64,6 +64,7 @@ uint64_t splitmix64(uint64_t x);
 double noise_uniform(uint64_t seed, int site, uint64_t flat);
 
 // sector dimensions of bonds 0..N for a target D (n0: rho0 states per charge)
-std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0);
+std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0,
+                                               int sector_cap);
 
 }  // namespace tt

@@ -22,6 +22,7 @@ SYMBOLS = [
     "tt_state_bond_sectors", "tt_state_export_site", "tt_state_import_site",
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
+    "tt_profile_enable", "tt_profile_read",
 ]
 
 
@@ -34,7 +35,7 @@ class tt_options(C.Structure):
     _fields_ = [("D", C.c_int), ("symmetry", C.c_int), ("beta0", C.c_double),
                 ("taylor_order", C.c_int), ("krylov_dim", C.c_int), ("krylov_tol", C.c_double),
                 ("precision", C.c_int), ("pad_eps", C.c_double), ("seed", C.c_uint64),
-                ("env_on_host", C.c_int)]
+                ("env_on_host", C.c_int), ("sector_cap", C.c_int)]
 
 
 class tt_observables(C.Structure):
@@ -84,6 +85,8 @@ def lib():
         L.tt_set_allocator.argtypes = [vp, vp, vp]
         L.tt_heff_last_timing.argtypes = [dp]
         L.tt_model_bond_sectors.argtypes = [C.POINTER(tt_model), C.POINTER(tt_options), C.c_int, ip, ip, ip, ip]
+        L.tt_profile_enable.argtypes = [C.c_int]
+        L.tt_profile_read.argtypes = [dp]
         L.tt_check_plans.argtypes = [C.POINTER(tt_model), C.POINTER(tt_options),
                                      C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         _lib = L
@@ -212,6 +215,20 @@ def tt_model_bond_sectors(m, o, k):
     qu, qd, dm = (C.c_int * ns.value)(), (C.c_int * ns.value)(), (C.c_int * ns.value)()
     _check(lib().tt_model_bond_sectors(C.byref(m), C.byref(o), k, C.byref(ns), qu, qd, dm))
     return [((qu[i], qd[i]), dm[i]) for i in range(ns.value)]
+
+
+def tt_profile_enable(on):
+    _check(lib().tt_profile_enable(1 if on else 0))
+
+
+def tt_profile_read():
+    """{kind: dict(ms, flops, bytes, launches)} for gemm, wstage, qr since the last read."""
+    buf = (C.c_double * 12)()
+    _check(lib().tt_profile_read(buf))
+    out = {}
+    for i, k in enumerate(("gemm", "wstage", "qr")):
+        out[k] = dict(ms=buf[4 * i], flops=buf[4 * i + 1], bytes=buf[4 * i + 2], launches=int(buf[4 * i + 3]))
+    return out
 
 
 def tt_set_stream(stream):

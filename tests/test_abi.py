@@ -90,16 +90,19 @@ def test_descriptor_bounds_full_workloads(name):
     assert v == 0, rep
 
 
-@pytest.mark.parametrize("W,L,geo,D", [(4, 4, 1, 64), (2, 3, 2, 40), (4, 16, 1, 300), (1, 6, 0, 30)])
-def test_sectors_match_oracle_allocation(W, L, geo, D):
+@pytest.mark.parametrize("W,L,geo,D,cap", [(4, 4, 1, 64, 0), (2, 3, 2, 40, 0), (4, 16, 1, 300, 0), (1, 6, 0, 30, 0),
+                                           (4, 4, 1, 64, 6), (4, 16, 1, 300, 12), (4, 16, 1, 2000, 64),
+                                           (3, 4, 2, 100, 5)])
+def test_sectors_match_oracle_allocation(W, L, geo, D, cap):
     from oracle import charges, mpo
     mm = mpo.HubbardMPO(W, L, geo, 1.0, 8.0, 1.0)
     N = mm.N
     q0 = [mm.bond_charges(k) for k in range(N)] + [[(0, 0)]]
-    lay = charges.bond_layouts(q0, N, D, True)
+    lay = charges.bond_layouts(q0, N, D, True, cap)
     m = T.model(W, L, geo, 1.0, 8.0, 1.0)
-    o = T.options(D=D, symmetry=1)
-    for k in range(N + 1):
+    o = T.options(D=D, symmetry=1, sector_cap=cap)
+    bonds = range(N + 1) if N <= 16 else sorted({0, 1, 2, 3, 4, 6, 9, 13, N // 2, N - 5, N - 2, N - 1, N})
+    for k in bonds:
         want = {}
         for q in lay[k].charges:
             want[q] = want.get(q, 0) + 1

@@ -74,7 +74,7 @@ def test_truncated_sweeps_match_oracle(W, L, geo, U, mu, D, sym, pad, ns, db):
     print("trunc", W, L, geo, D, sym, pad, flush=True)
     b0 = 0.01
     mm = ompo.HubbardMPO(W, L, geo, 1.0, U, mu)
-    ost = otd.initial_state(mm, b0, D, bool(sym), pad_eps=pad, seed=11)
+    ost = otd.initial_state(mm, b0, D, bool(sym), pad_eps=pad, seed=11, sector_cap=64)
     st = T.State.init(T.model(W, L, geo, 1.0, U, mu),
                       T.options(D=D, symmetry=sym, beta0=b0, pad_eps=pad, seed=11))
     assert st.info()[1] == ost.dims()
