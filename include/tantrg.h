@@ -173,13 +173,15 @@ int tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free_fn, void* ctx);
 int tt_heff_last_timing(double* host_ms4);
 
 /* Opt-in kernel timing: when on, every launch of the grouped GEMM, the MPO
- * (W) stage and the QR kernel is bracketed by HIP events on its stream.
- * tt_profile_read synchronises those events and fills host_out12 with
- * {ms, flops, bytes, launches} for [GEMM, W stage, QR] accumulated since the
- * previous read (flops and bytes are algorithmic: sum of 2mnk, operands read
- * once), then resets. */
+ * (W) stage and the QR kernels is bracketed by HIP events on its stream.
+ * tt_profile_read synchronises those events and fills host_out40 with
+ * {ms, flops, bytes, launches} for ten kinds accumulated since the previous
+ * read, then resets: the grouped GEMM by contraction [L.A, .R, left
+ * environment, right environment (R.A), right environment (A.Z), bond apply,
+ * absorb, dense W stage], then the sparse W stage and the QR.  Flops and bytes
+ * are algorithmic (sum of 2mnk; every operand element read once). */
 int tt_profile_enable(int on);
-int tt_profile_read(double* host_out12);
+int tt_profile_read(double* host_out40);
 
 /* Host-only: the sectors bond k would get for this model and options (same
  * calling convention as tt_state_bond_sectors).  No GPU needed. */

@@ -72,9 +72,10 @@ void check_device() {
 }
 
 void upload_plan(GemmPlan& p, hipStream_t st) {
-  tile_plan(p, 64, 64);
+  tile_plan(p);
   p.d_probs = upload(p.probs, st);
   p.d_tiles = upload(p.tiles, st);
+  p.d_splits = upload(p.splits, st);
 }
 void upload_plan(WPlan& p, hipStream_t st) {
   p.ntasks = (int)p.tasks.size();
@@ -98,7 +99,10 @@ void upload_plan(QRPlan& p, hipStream_t st) {
   p.d_stacks = upload(p.stacks, st);
   p.d_wide = upload(p.wide, st);
 }
-void free_plan(GemmPlan& p) { dfree(p.d_probs); dfree(p.d_tiles); p.d_probs = nullptr; p.d_tiles = nullptr; }
+void free_plan(GemmPlan& p) {
+  dfree(p.d_probs); dfree(p.d_tiles); dfree(p.d_splits);
+  p.d_probs = nullptr; p.d_tiles = nullptr; p.d_splits = nullptr;
+}
 void free_plan(WPlan& p) { dfree(p.d_tasks); dfree(p.d_terms); p.d_tasks = nullptr; p.d_terms = nullptr; }
 void free_plan(QRPlan& p) {
   dfree(p.d_tasks); dfree(p.d_chunks); dfree(p.d_stacks); dfree(p.d_wide);
@@ -127,6 +131,7 @@ struct tt_state {
   std::vector<double*> A, Lenv, Renv;
   double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr, *U = nullptr;
   double *Sbuf = nullptr, *tmp = nullptr, *kry = nullptr, *wv = nullptr, *qrws = nullptr;
+  double* pws = nullptr;                   // partial tiles of K-split GEMMs
   double *part = nullptr, *lz = nullptr;   // lz: alpha[K] beta[K] hn[K] coeff[K] scal[4] lambda errmax scratch[4]
   double** d_sites = nullptr;
   TraceEntry* d_trace = nullptr;
@@ -154,7 +159,7 @@ tt_state::~tt_state() {
   for (auto p : A) dfree(p);
   for (auto p : Lenv) dfree(p);
   for (auto p : Renv) dfree(p);
-  for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr}) dfree(p);
+  for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws}) dfree(p);
   dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
 }
 
@@ -166,9 +171,9 @@ hipStream_t ST() { return g_stream; }
 void apply_heff1(tt_state& s, int k, const double* x, double* out) {
   SitePlan& P = s.plans[k];
   int prec = s.opts.precision;
-  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.T1, nullptr}}, prec, ST());
+  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.T1, nullptr}}, prec, s.pws, ST());
   launch_wstage(P.w2, s.T1, s.T2, ST());
-  launch_gemm(P.s3, s.tabs.dev, Slots{{s.T2, s.Renv[k + 1], out, nullptr}}, prec, ST());
+  launch_gemm(P.s3, s.tabs.dev, Slots{{s.T2, s.Renv[k + 1], out, nullptr}}, prec, s.pws, ST());
   double f = P.s1.flops + P.w2.flops + P.s3.flops;
   s.flops += f;
   s.flops_heff += f;
@@ -178,8 +183,8 @@ void apply_heff1(tt_state& s, int k, const double* x, double* out) {
 void apply_heff0(tt_state& s, int k, const double* x, double* out) {
   SitePlan& P = s.plans[k];
   int prec = s.opts.precision;
-  launch_gemm(P.b1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.U, nullptr}}, prec, ST());
-  launch_gemm(P.b2, s.tabs.dev, Slots{{s.U, s.Renv[k], out, nullptr}}, prec, ST());
+  launch_gemm(P.b1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.U, nullptr}}, prec, s.pws, ST());
+  launch_gemm(P.b2, s.tabs.dev, Slots{{s.U, s.Renv[k], out, nullptr}}, prec, s.pws, ST());
   double f = P.b1.flops + P.b2.flops;
   s.flops += f;
   s.flops_heff += f;
@@ -189,18 +194,18 @@ void apply_heff0(tt_state& s, int k, const double* x, double* out) {
 void env_left(tt_state& s, int k) {   // Lenv[k+1] from Lenv[k], A_k (left-canonical), W_k
   SitePlan& P = s.plans[k];
   int prec = s.opts.precision;
-  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}, prec, ST());
+  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}, prec, s.pws, ST());
   launch_wstage(P.w2, s.T1, s.T2, ST());
-  launch_gemm(P.el, s.tabs.dev, Slots{{s.A[k], s.T2, s.Lenv[k + 1], nullptr}}, prec, ST());
+  launch_gemm(P.el, s.tabs.dev, Slots{{s.A[k], s.T2, s.Lenv[k + 1], nullptr}}, prec, s.pws, ST());
   s.flops += P.s1.flops + P.w2.flops + P.el.flops;
 }
 
 void env_right(tt_state& s, int k) {  // Renv[k] from Renv[k+1], A_k (right-canonical), W_k
   SitePlan& P = s.plans[k];
   int prec = s.opts.precision;
-  launch_gemm(P.r1, s.tabs.dev, Slots{{s.Renv[k + 1], s.A[k], s.Y, nullptr}}, prec, ST());
+  launch_gemm(P.r1, s.tabs.dev, Slots{{s.Renv[k + 1], s.A[k], s.Y, nullptr}}, prec, s.pws, ST());
   launch_wstage(P.wr, s.Y, s.Z, ST());
-  launch_gemm(P.r3, s.tabs.dev, Slots{{s.A[k], s.Z, s.Renv[k], nullptr}}, prec, ST());
+  launch_gemm(P.r3, s.tabs.dev, Slots{{s.A[k], s.Z, s.Renv[k], nullptr}}, prec, s.pws, ST());
   s.flops += P.r1.flops + P.wr.flops + P.r3.flops;
 }
 
@@ -215,21 +220,21 @@ void lanczos_exp(tt_state& s, double t, double* v, long long n, const std::funct
   double* coeff = s.lz + 3 * kMaxKrylov;
   double* scal = s.lz + 4 * kMaxKrylov;
   double* Qb = s.kry;
-  launch_mdot(nullptr, 0, 0, v, n, 1, s.part, ST());
-  launch_lz_start(v, Qb, n, s.part, scal, ST());
+  double* p1 = s.part;
+  double* p2 = s.part + (long long)kRedBlocks * (kMaxKrylov + 2);
+  launch_mdot(nullptr, 0, 0, v, n, 1, p1, ST());
+  launch_lz_start(v, Qb, n, p1, scal, ST());
   for (int j = 0; j < K; ++j) {
     H(Qb + (long long)j * n, s.wv);
-    launch_mdot(Qb, n, j + 1, s.wv, n, 1, s.part, ST());
-    launch_lz_sub(s.wv, Qb, n, j + 1, s.part, j + 2, n, alpha + j, hn + j, ST());
-    launch_mdot(Qb, n, j + 1, s.wv, n, 0, s.part, ST());
-    launch_lz_sub(s.wv, Qb, n, j + 1, s.part, j + 1, n, nullptr, nullptr, ST());
-    launch_mdot(nullptr, 0, 0, s.wv, n, 1, s.part, ST());
-    launch_lz_next(s.wv, j + 1 < K ? Qb + (long long)(j + 1) * n : nullptr, n, s.part, beta + j, hn + j, tol, ST());
+    // pass 1: c = Q^T w (and ||w||), w -= Q c, dots of the result; pass 2: w -= Q c', ||w||
+    launch_mdot(Qb, n, j + 1, s.wv, n, 1, p1, ST());
+    launch_lz_sub_dot(s.wv, Qb, n, j + 1, p1, j + 2, n, alpha + j, hn + j, p2, ST());
+    launch_lz_sub_norm(s.wv, Qb, n, j + 1, p2, n, p1, ST());
+    launch_lz_next(s.wv, j + 1 < K ? Qb + (long long)(j + 1) * n : nullptr, n, p1, beta + j, hn + j, tol, ST());
   }
   launch_lz_coeffs(alpha, beta, hn, K, t, tol, scal, coeff, s.err_ptr(), ST());
-  launch_lz_combine(Qb, n, K, coeff, v, n, ST());
-  launch_mdot(nullptr, 0, 0, v, n, 1, s.part, ST());
-  launch_normalize_log(v, n, s.part, s.lam_ptr(), ST());
+  launch_lz_combine_norm(Qb, n, K, coeff, v, n, p1, ST());
+  launch_normalize_log(v, n, p1, s.lam_ptr(), ST());
   s.n_exps++;
 }
 
@@ -250,13 +255,13 @@ void lq_site(tt_state& s, int k) {
 }
 void absorb_left(tt_state& s, int k) {   // A_k <- S_k A_k (S on the left bond k)
   SitePlan& P = s.plans[k];
-  launch_gemm(P.absL, s.tabs.dev, Slots{{s.Sbuf, s.A[k], s.tmp, nullptr}}, TT_FP64, ST());
+  launch_gemm(P.absL, s.tabs.dev, Slots{{s.Sbuf, s.A[k], s.tmp, nullptr}}, TT_FP64, s.pws, ST());
   launch_copy(s.A[k], s.tmp, s.site[k].size, ST());
   s.flops += P.absL.flops;
 }
 void absorb_right(tt_state& s, int k) {  // A_k <- A_k S_{k+1}
   SitePlan& P = s.plans[k];
-  launch_gemm(P.absR, s.tabs.dev, Slots{{s.A[k], s.Sbuf, s.tmp, nullptr}}, TT_FP64, ST());
+  launch_gemm(P.absR, s.tabs.dev, Slots{{s.A[k], s.Sbuf, s.tmp, nullptr}}, TT_FP64, s.pws, ST());
   launch_copy(s.A[k], s.tmp, s.site[k].size, ST());
   s.flops += P.absR.flops;
 }
@@ -342,6 +347,11 @@ void alloc_state(tt_state& s) {
     y = std::max(y, P.y_size); z = std::max(z, P.z_size); u = std::max(u, P.u_size);
     qw = std::max(qw, std::max(P.qr.ws_size + P.qr.lds_ws, P.lq.ws_size + P.lq.lds_ws));
   }
+  long long pw = 1;
+  for (auto& P : s.plans)
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2})
+      pw = std::max(pw, g->pws_size);
+  s.pws = (double*)dalloc(8 * pw);
   s.max_site = 0;
   for (auto& l : s.site) s.max_site = std::max(s.max_site, l.size);
   s.max_bmat = 0;
@@ -371,7 +381,7 @@ void alloc_state(tt_state& s) {
   s.kry = (double*)dalloc(8 * nvec * (long long)s.opts.krylov_dim);
   s.wv = (double*)dalloc(8 * nvec);
   s.qrws = (double*)dalloc(8 * std::max(qw, 1LL));
-  s.part = (double*)dalloc(8 * (long long)kRedBlocks * (kMaxKrylov + 2));
+  s.part = (double*)dalloc(8 * 2 * (long long)kRedBlocks * (kMaxKrylov + 2));
   s.lz = (double*)dalloc(8 * (4 * kMaxKrylov + 16));
   launch_fill(s.lz, 0.0, 4 * kMaxKrylov + 16, st);
   s.vtr = (double*)dalloc(8 * 2 * s.max_bond);
@@ -498,7 +508,7 @@ void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(o.taylor_order == 1, TT_EINVAL, "only the linear start rho0 = 1 - beta0 H is supported");
   TT_REQUIRE(o.krylov_dim >= 1 && o.krylov_dim <= kMaxKrylov, TT_EINVAL, "krylov_dim must be in 1..32");
   TT_REQUIRE(o.krylov_tol >= 0.0, TT_EINVAL, "krylov_tol must be >= 0");
-  TT_REQUIRE(o.precision == TT_FP64, TT_EINVAL, "sweeps run in FP64 only");
+  TT_REQUIRE(o.precision >= TT_FP64 && o.precision <= TT_BF16X6, TT_EINVAL, "unknown precision");
   TT_REQUIRE(o.env_on_host == 0, TT_EINVAL, "host-resident environments are not supported");
   TT_REQUIRE(o.sector_cap >= 0, TT_EINVAL, "sector_cap must be >= 0");
   TT_REQUIRE(std::isfinite(o.beta0) && std::isfinite(o.pad_eps), TT_EINVAL, "beta0 and pad_eps must be finite");
@@ -570,8 +580,16 @@ long long check_gemm(const GemmPlan& p, const std::vector<long long>& tabs, cons
     chk(g.ib, g.offB, bk, bn, 0, "B");
     chk(g.ic, g.offC, cm, Range{0, 0}, g.N - 1, "C");
   }
-  for (auto& t : p.tiles)
-    if (t.prob < 0 || t.prob >= (int)p.probs.size()) ++bad;
+  for (auto& t : p.tiles) {
+    if (t.prob < 0 || t.prob >= (int)p.probs.size() || t.cfg < 0 || t.cfg >= kGemmCfgs) { ++bad; continue; }
+    const GemmProb& g = p.probs[t.prob];
+    if (t.tm < 0 || t.tn < 0 || t.tm * kGemmBM[t.cfg] >= g.M || t.tn * kGemmBN[t.cfg] >= g.N) ++bad;
+    if (t.nk < 1 || t.ks < 0 || t.ks >= t.nk) ++bad;
+    if (t.nk > 1 && (t.pw < 0 || t.pw + (long long)t.nk * kGemmBM[t.cfg] * kGemmBN[t.cfg] > p.pws_size)) ++bad;
+  }
+  for (auto& sp : p.splits)
+    if (sp.prob < 0 || sp.prob >= (int)p.probs.size() || sp.pw < 0 ||
+        sp.pw + (long long)sp.nk * kGemmBM[sp.cfg] * kGemmBN[sp.cfg] > p.pws_size) ++bad;
   return bad;
 }
 
@@ -642,7 +660,7 @@ long long check_all_plans(tt_state& s, std::string& rep) {
   const auto& T = s.tabs.host;
   for (int k = 0; k < N; ++k) {
     SitePlan& P = s.plans[k];
-    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2}) tile_plan(*g, 64, 64);
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2}) tile_plan(*g);
     long long ns = s.site[k].size, el = s.env[k].size, er = s.env[k + 1].size;
     long long s1[kSlots] = {el, ns, t1, 0}, s3[kSlots] = {t2, er, ns, 0}, se[kSlots] = {ns, t2, er, 0};
     long long r1[kSlots] = {er, ns, y, 0}, r3[kSlots] = {ns, z, el, 0};
@@ -701,8 +719,8 @@ struct HeffCache {
   SitePlan plan;
   SiteTables tabs;
   GemmPlan wg;
-  double *T1 = nullptr, *T2 = nullptr;
-  long long t1 = 0, t2 = 0;
+  double *T1 = nullptr, *T2 = nullptr, *pws = nullptr;
+  long long t1 = 0, t2 = 0, pw = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
 };
@@ -734,6 +752,7 @@ void build_heff_cache(int Dl, int Dr, int DH) {
     for (int b = 0; b < DH; ++b) cm.push_back((long long)4 * so * DH * Dr + (long long)b * Dr);
   long long tam = c.tabs.add(am), tak = c.tabs.add(ak), tbk = c.tabs.add(bk), tcm = c.tabs.add(cm);
   c.wg = GemmPlan();
+  c.wg.tag = TAG_WGEMM;
   for (int x = 0; x < Dl; ++x)
     for (int sp = 0; sp < 4; ++sp) {
       GemmProb g{};
@@ -754,6 +773,8 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   upload_plan(c.wg, st);
   if (c.plan.t1_size > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * c.plan.t1_size); c.t1 = c.plan.t1_size; }
   if (c.plan.t2_size > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * c.plan.t2_size); c.t2 = c.plan.t2_size; }
+  long long pw = std::max(std::max(c.plan.s1.pws_size, c.plan.s3.pws_size), std::max(c.wg.pws_size, 1LL));
+  if (pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * pw); c.pw = pw; }
   for (int i = 0; i < 4; ++i)
     if (!c.ev[i]) HIPX(hipEventCreate(&c.ev[i]));
   c.Dl = Dl; c.Dr = Dr; c.DH = DH;
@@ -1042,7 +1063,7 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
   ABI_BEGIN
   TT_REQUIRE(Dl >= 1 && Dr >= 1 && DH >= 1, TT_EINVAL, "dimensions must be positive");
   TT_REQUIRE(L && W && A && R && out, TT_EINVAL, "null device pointer");
-  TT_REQUIRE(precision == TT_FP64, TT_EINVAL, "unsupported precision");
+  TT_REQUIRE(precision >= TT_FP64 && precision <= TT_BF16X6, TT_EINVAL, "unknown precision");
   TT_REQUIRE((double)Dl * DH * 16 * Dr < 4.0e9, TT_EINVAL, "problem too large");
   hipStream_t saved = g_stream;
   if (stream) g_stream = (hipStream_t)stream;
@@ -1052,11 +1073,11 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
     hipStream_t st = ST();
     HIPX(hipEventRecord(c.ev[0], st));
     launch_gemm(c.plan.s1, c.tabs.dev, Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}},
-                precision, st);
+                precision, c.pws, st);
     HIPX(hipEventRecord(c.ev[1], st));
-    launch_gemm(c.wg, c.tabs.dev, Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}, precision, st);
+    launch_gemm(c.wg, c.tabs.dev, Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}, precision, c.pws, st);
     HIPX(hipEventRecord(c.ev[2], st));
-    launch_gemm(c.plan.s3, c.tabs.dev, Slots{{c.T2, const_cast<double*>(R), out, nullptr}}, precision, st);
+    launch_gemm(c.plan.s3, c.tabs.dev, Slots{{c.T2, const_cast<double*>(R), out, nullptr}}, precision, c.pws, st);
     HIPX(hipEventRecord(c.ev[3], st));
     c.timed = true;
   } catch (...) {
@@ -1098,13 +1119,13 @@ int tt_profile_enable(int on) {
   ABI_END
 }
 
-int tt_profile_read(double* host_out12) {
+int tt_profile_read(double* host_out40) {
   ABI_BEGIN
-  TT_REQUIRE(host_out12, TT_EINVAL, "null argument");
+  TT_REQUIRE(host_out40, TT_EINVAL, "null argument");
   double out[PROF_KINDS][4];
   prof_read(out);
   for (int k = 0; k < PROF_KINDS; ++k)
-    for (int j = 0; j < 4; ++j) host_out12[k * 4 + j] = out[k][j];
+    for (int j = 0; j < 4; ++j) host_out40[k * 4 + j] = out[k][j];
   ABI_END
 }
 

@@ -11,7 +11,8 @@ constexpr int kRedBlocks = 256;
 constexpr int kMaxKrylov = 32;
 
 // Optional timing of the grouped kernels: HIP events around every launch on its stream.
-enum ProfKind { PROF_GEMM = 0, PROF_WSTAGE = 1, PROF_QR = 2, PROF_KINDS = 3 };
+// kinds 0..TAG_COUNT-1 are the GEMM tags, then the W stage and the QR
+enum ProfKind { PROF_WSTAGE = TAG_COUNT, PROF_QR = TAG_COUNT + 1, PROF_KINDS = TAG_COUNT + 2 };
 void prof_enable(bool on);
 bool prof_enabled();
 void prof_begin(hipStream_t st);
@@ -19,7 +20,8 @@ void prof_end(hipStream_t st, int kind, double flops, double bytes);
 // (ms, flops, bytes, launches) per kind since the last read; synchronises the events
 void prof_read(double out[PROF_KINDS][4]);
 
-void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, hipStream_t st);
+// pws: partial-tile workspace of at least p.pws_size doubles (split problems)
+void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, double* pws, hipStream_t st);
 void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st);
 // QR of every task of the plan: LDS chunk/stack/combine kernels for n <= 64,
 // the global-memory kernel for wider tasks.  ws holds p.ws_size + p.lds_ws doubles.
@@ -34,6 +36,12 @@ void launch_lz_start(const double* v, double* q0, long long n, const double* par
                      hipStream_t st);
 void launch_lz_sub(double* w, const double* Q, long long ld, int nv, const double* part, int nparts,
                    long long n, double* alpha_out, double* hn_out, hipStream_t st);
+void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
+                       long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st);
+void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
+                        double* part_out, hipStream_t st);
+void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
+                            double* part_out, hipStream_t st);
 void launch_lz_next(const double* w, double* qn, long long n, const double* part, double* beta_out,
                     const double* hn, double tol, hipStream_t st);
 void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t,

@@ -18,6 +18,7 @@
 //                  (SM Sec. II.H), so a local exponential needs no host sync.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -80,108 +81,379 @@ void prof_read(double out[PROF_KINDS][4]) {
 }
 
 // ------------------------------------------------------------------ GEMM
-constexpr int BM = 64, BN = 64, BK = 16;
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ long long idx_map(const long long* __restrict__ tabs, long long tab, long long stride,
                                              long long i) {
   return tab >= 0 ? tabs[tab + i] : i * stride;
 }
 
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ probs,
-                                                  const GemmTile* __restrict__ tiles,
-                                                  const long long* __restrict__ tabs, Slots slots) {
-  __shared__ double sA[BK][BM + 1];
-  __shared__ double sB[BK][BN + 1];
-  __shared__ long long rA[BM], cB[BN], rC[BM], kA[BK], kB[BK];
-  const GemmTile t = tiles[blockIdx.x];
-  const GemmProb P = probs[t.prob];
+// K depth of one LDS tile per precision (the BF16 MFMA consumes 32 K per instruction)
+template <int PREC> struct PrecTraits;
+template <> struct PrecTraits<TT_FP64> { static constexpr int BK = 16, PARTS = 1; };
+template <> struct PrecTraits<TT_FP32> { static constexpr int BK = 16, PARTS = 1; };
+template <> struct PrecTraits<TT_BF16X3> { static constexpr int BK = 32, PARTS = 2; };
+template <> struct PrecTraits<TT_BF16X6> { static constexpr int BK = 32, PARTS = 3; };
+constexpr int kBfPad = 8;   // keeps the 8-element BF16 rows 16-byte aligned
+
+template <int WGM, int WGN, int FM, int FN, bool SPLITK, int PREC>
+constexpr int gemm_smem_bytes_t() {
+  constexpr int BK = PrecTraits<PREC>::BK, P = PrecTraits<PREC>::PARTS;
+  constexpr int BM = WGM * 16 * FM, BN = WGN * 16 * FN;
+  constexpr int tiles = (PREC == TT_FP64) ? 8 * (BK * (BM + 1) + BK * (BN + 1))
+                        : (PREC == TT_FP32) ? 4 * (BK * (BM + 1) + BK * (BN + 1))
+                                            : 2 * P * (BM + BN) * (BK + kBfPad);
+  constexpr int tabs = 8 * (2 * BM + BN + 2 * BK);
+  constexpr int red = SPLITK ? 8 * 4 * BM * BN : 0;
+  return tiles + tabs + red;
+}
+
+// split a double into BF16 parts x ~ p0 + p1 (+ p2), each rounded to nearest
+template <int P>
+__device__ __forceinline__ void bf16_split(double x, __bf16* out) {
+  __bf16 h = (__bf16)(float)x;
+  out[0] = h;
+  double r = x - (double)(float)h;
+  __bf16 m = (__bf16)(float)r;
+  out[1] = m;
+  if (P == 3) out[2] = (__bf16)(float)(r - (double)(float)m);
+}
+
+// One BM x BN output tile of one problem.  Four 64-wide waves in a WGM x WGN
+// grid, each owning FM x FN MFMA 16x16 blocks; with SPLITK all waves own the
+// whole tile and take alternate 4-deep K sub-steps, reduced through LDS.  A
+// K-split problem covers only the K slice of this tile and writes a partial.
+// FP64: f64 MFMA.  FP32 / BF16: f32-accumulating MFMA inside each K tile,
+// added into FP64 accumulators after every K tile.
+template <int WGM, int WGN, int FM, int FN, bool SPLITK, int PREC>
+__device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, const long long* __restrict__ tabs,
+                                          const Slots& slots, char* smem, double* __restrict__ pws) {
+  constexpr int BK = PrecTraits<PREC>::BK, NP = PrecTraits<PREC>::PARTS;
+  constexpr int WM = 16 * FM, WN = 16 * FN;
+  constexpr int BM = WGM * WM, BN = WGN * WN;
+  constexpr bool F64 = (PREC == TT_FP64), F32 = (PREC == TT_FP32);
+  constexpr int tile_bytes = F64 ? 8 * (BK * (BM + 1) + BK * (BN + 1))
+                             : F32 ? 4 * (BK * (BM + 1) + BK * (BN + 1))
+                                   : 2 * NP * (BM + BN) * (BK + kBfPad);
+  // LDS carve-up
+  double(*dA)[BM + 1] = reinterpret_cast<double(*)[BM + 1]>(smem);
+  double(*dB)[BN + 1] = reinterpret_cast<double(*)[BN + 1]>(smem + 8 * BK * (BM + 1));
+  float(*fA)[BM + 1] = reinterpret_cast<float(*)[BM + 1]>(smem);
+  float(*fB)[BN + 1] = reinterpret_cast<float(*)[BN + 1]>(smem + 4 * BK * (BM + 1));
+  __bf16* bA = reinterpret_cast<__bf16*>(smem);                          // [NP][BM][BK+pad]
+  __bf16* bB = bA + NP * BM * (BK + kBfPad);                              // [NP][BN][BK+pad]
+  long long* rA = reinterpret_cast<long long*>(smem + tile_bytes);
+  long long* rC = rA + BM;
+  long long* cB = rC + BM;
+  long long* kA = cB + BN;
+  long long* kB = kA + BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = t.tm * BM, n0 = t.tn * BN;
+  const int tm = T.tm, tn = T.tn;
+  const int m0 = tm * BM, n0 = tn * BN;
   const double* __restrict__ A = slots.p[P.ia] + P.offA;
   const double* __restrict__ B = slots.p[P.ib] + P.offB;
   double* C = slots.p[P.ic] + P.offC;
-  if (tid < BM) {
-    int m = m0 + tid;
-    rA[tid] = m < P.M ? idx_map(tabs, P.tam, P.sam, m) : 0;
-    rC[tid] = m < P.M ? idx_map(tabs, P.tcm, P.scm, m) : 0;
-  } else if (tid < BM + BN) {
-    int n = n0 + tid - BM;
-    cB[tid - BM] = n < P.N ? idx_map(tabs, P.tbn, P.sbn, n) : 0;
+  for (int i = tid; i < BM; i += 256) {
+    int m = m0 + i;
+    rA[i] = m < P.M ? idx_map(tabs, P.tam, P.sam, m) : 0;
+    rC[i] = m < P.M ? idx_map(tabs, P.tcm, P.scm, m) : 0;
+  }
+  for (int j = tid; j < BN; j += 256) {
+    int n = n0 + j;
+    cB[j] = n < P.N ? idx_map(tabs, P.tbn, P.sbn, n) : 0;
   }
   const bool a_kfast = (P.tak < 0 && P.sak == 1);
   const bool b_nfast = (P.tbn < 0 && P.sbn == 1);
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  double4_t acc[2][2];
+  const int wm = SPLITK ? 0 : (wave / WGN) * WM, wn = SPLITK ? 0 : (wave % WGN) * WN;
+  double4_t acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < P.K; k0 += BK) {
+  int kbeg = 0, kstop = P.K;
+  if (T.nk > 1) {
+    const int per = ((P.K + T.nk - 1) / T.nk + BK - 1) / BK * BK;
+    kbeg = T.ks * per;
+    kstop = kbeg + per < P.K ? kbeg + per : P.K;
+  }
+  for (int k0 = kbeg; k0 < kstop; k0 += BK) {
     __syncthreads();
-    if (tid < BK) {
-      int k = k0 + tid;
-      kA[tid] = k < P.K ? idx_map(tabs, P.tak, P.sak, k) : 0;
-    } else if (tid >= 64 && tid < 64 + BK) {
-      int k = k0 + tid - 64;
-      kB[tid - 64] = k < P.K ? idx_map(tabs, P.tbk, P.sbk, k) : 0;
+    for (int q = tid; q < 2 * BK; q += 256) {
+      int k = k0 + (q % BK);
+      if (q < BK) kA[q] = k < kstop ? idx_map(tabs, P.tak, P.sak, k) : 0;
+      else kB[q - BK] = k < kstop ? idx_map(tabs, P.tbk, P.sbk, k) : 0;
     }
     __syncthreads();
 #pragma unroll
-    for (int e0 = 0; e0 < (BM * BK) / 256; ++e0) {
+    for (int e0 = 0; e0 < (BM * BK + 255) / 256; ++e0) {
       int e = tid + e0 * 256;
-      int i, kk;
-      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % BM; kk = e / BM; }
-      bool ok = (m0 + i < P.M) && (k0 + kk < P.K);
-      sA[kk][i] = ok ? A[rA[i] + kA[kk]] : 0.0;
+      if (e < BM * BK) {
+        int i, kk;
+        if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % BM; kk = e / BM; }
+        bool ok = (m0 + i < P.M) && (k0 + kk < kstop);
+        double x = ok ? A[rA[i] + kA[kk]] : 0.0;
+        if (F64) dA[kk][i] = x;
+        else if (F32) fA[kk][i] = (float)x;
+        else {
+          __bf16 parts[3];
+          bf16_split<NP>(x, parts);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) bA[(p * BM + i) * (BK + kBfPad) + kk] = parts[p];
+        }
+      }
     }
 #pragma unroll
-    for (int e0 = 0; e0 < (BN * BK) / 256; ++e0) {
+    for (int e0 = 0; e0 < (BN * BK + 255) / 256; ++e0) {
       int e = tid + e0 * 256;
-      int j, kk;
-      if (b_nfast) { j = e % BN; kk = e / BN; } else { j = e / BK; kk = e % BK; }
-      bool ok = (n0 + j < P.N) && (k0 + kk < P.K);
-      sB[kk][j] = ok ? B[kB[kk] + cB[j]] : 0.0;
+      if (e < BN * BK) {
+        int j, kk;
+        if (b_nfast) { j = e % BN; kk = e / BN; } else { j = e / BK; kk = e % BK; }
+        bool ok = (n0 + j < P.N) && (k0 + kk < kstop);
+        double x = ok ? B[kB[kk] + cB[j]] : 0.0;
+        if (F64) dB[kk][j] = x;
+        else if (F32) fB[kk][j] = (float)x;
+        else {
+          __bf16 parts[3];
+          bf16_split<NP>(x, parts);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) bB[(p * BN + j) * (BK + kBfPad) + kk] = parts[p];
+        }
+      }
     }
     __syncthreads();
+    const int kend = (kstop - k0 < BK) ? kstop - k0 : BK;
+    if (F64) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4), c = lane & 15;
-      double a0 = sA[kr][wm + c], a1 = sA[kr][wm + 16 + c];
-      double b0 = sB[kr][wn + c], b1 = sB[kr][wn + 16 + c];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      for (int kk = 0; kk < BK; kk += 4) {
+        if (kk >= kend) break;
+        if (SPLITK && (kk >> 2) != wave) continue;
+        const int kr = kk + (lane >> 4), c = lane & 15;
+        double a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = dA[kr][wm + i * 16 + c];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j] = dB[kr][wn + j * 16 + c];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else if (F32) {
+      float4_t a32[FM][FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) a32[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        if (kk >= kend) break;
+        if (SPLITK && (kk >> 2) != wave) continue;
+        const int kr = kk + (lane >> 4), c = lane & 15;
+        float a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = fA[kr][wm + i * 16 + c];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j] = fB[kr][wn + j * 16 + c];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], a32[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)a32[i][j][v];
+    } else {
+      // one 32-deep MFMA step per K tile; lane (r, g) reads k = 8g..8g+7 of row r
+      const int r = lane & 15, g = lane >> 4;
+      bf16x8_t a[NP][FM], b[NP][FN];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          a[p][i] = *reinterpret_cast<const bf16x8_t*>(bA + (p * BM + wm + i * 16 + r) * (BK + kBfPad) + 8 * g);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          b[p][j] = *reinterpret_cast<const bf16x8_t*>(bB + (p * BN + wn + j * 16 + r) * (BK + kBfPad) + 8 * g);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          float4_t t = (float4_t){0.f, 0.f, 0.f, 0.f};
+          if (NP == 3) {
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2 % NP][i], b[0][j], t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2 % NP][j], t, 0, 0, 0);
+          }
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], t, 0, 0, 0);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)t[v];
+        }
     }
   }
-  // D[i][j] of a 16x16 f64 MFMA block sits in lane j + 16*(i%4), element i/4
-  // (measured on gfx950; A[i][k] in lane i + 16k, B[k][j] in lane j + 16k)
+  // row of accumulator element v inside a 16x16 block (measured on gfx950):
+  // f64 MFMA: lane/16 + 4v; f32-accumulating MFMA: 4*(lane/16) + v
+  auto brow = [&](int v) { return F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v; };
+  if (SPLITK) {
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem + tile_bytes + 8 * (2 * BM + BN + 2 * BK));
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int row = i * 16 + brow(v), col = j * 16 + (lane & 15);
+          red[(wave * BM + row) * BN + col] = acc[i][j][v];
+        }
+    __syncthreads();
+    for (int e = tid; e < BM * BN; e += 256) {
+      int row = e / BN, col = e % BN;
+      int m = m0 + row, n = n0 + col;
+      double v = red[e] + red[BM * BN + e] + red[2 * BM * BN + e] + red[3 * BM * BN + e];
+      if (T.nk > 1) {
+        pws[T.pw + (long long)T.ks * BM * BN + e] = v;
+      } else if (m < P.M && n < P.N) {
+        double* cp = C + rC[row] + n;
+        double val = P.alpha * v;
+        if (P.beta != 0.0) val += P.beta * (*cp);
+        *cp = val;
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = wm + bi * 16 + (lane >> 4) + 4 * v;
-        int col = wn + bj * 16 + (lane & 15);
+        int row = wm + i * 16 + brow(v);
+        int col = wn + j * 16 + (lane & 15);
         int m = m0 + row, n = n0 + col;
-        if (m < P.M && n < P.N) {
+        if (T.nk > 1) {
+          pws[T.pw + (long long)T.ks * BM * BN + row * BN + col] = acc[i][j][v];
+        } else if (m < P.M && n < P.N) {
           double* cp = C + rC[row] + n;
-          double val = P.alpha * acc[bi][bj][v];
+          double val = P.alpha * acc[i][j][v];
           if (P.beta != 0.0) val += P.beta * (*cp);
           *cp = val;
         }
       }
 }
 
-void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, hipStream_t st) {
-  (void)precision;
+// tile shapes: 0 64x64, 1 128x32, 2 256x16, 3 32x128, 4 32x32 (split K over the
+// waves; with BF16 the four waves take one 16x16 block each instead)
+template <int CFG, int PREC> struct CfgT;
+template <int PREC> struct CfgT<0, PREC> { static constexpr int WGM = 2, WGN = 2, FM = 2, FN = 2; static constexpr bool SK = false; };
+template <int PREC> struct CfgT<1, PREC> { static constexpr int WGM = 4, WGN = 1, FM = 2, FN = 2; static constexpr bool SK = false; };
+template <int PREC> struct CfgT<2, PREC> { static constexpr int WGM = 4, WGN = 1, FM = 4, FN = 1; static constexpr bool SK = false; };
+template <int PREC> struct CfgT<3, PREC> { static constexpr int WGM = 1, WGN = 4, FM = 2, FN = 2; static constexpr bool SK = false; };
+template <int PREC> struct CfgT<4, PREC> {
+  static constexpr bool BFP = PREC >= TT_BF16X3;
+  static constexpr int WGM = BFP ? 2 : 1, WGN = BFP ? 2 : 1, FM = BFP ? 1 : 2, FN = BFP ? 1 : 2;
+  static constexpr bool SK = !BFP;
+};
+
+template <int CFG, int PREC>
+__global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs, const GemmTile* __restrict__ tiles,
+                                              int tile0, const long long* __restrict__ tabs, Slots slots,
+                                              double* __restrict__ pws) {
+  extern __shared__ __attribute__((aligned(16))) char smem_gemm[];
+  using C = CfgT<CFG, PREC>;
+  const GemmTile t = tiles[tile0 + blockIdx.x];
+  const GemmProb P = probs[t.prob];
+  gemm_tile<C::WGM, C::WGN, C::FM, C::FN, C::SK, PREC>(P, t, tabs, slots, smem_gemm, pws);
+}
+
+template <int CFG, int PREC>
+int cfg_smem() {
+  using C = CfgT<CFG, PREC>;
+  return gemm_smem_bytes_t<C::WGM, C::WGN, C::FM, C::FN, C::SK, PREC>();
+}
+
+int gemm_smem_bytes(int cfg) {   // FP64 tiles (the largest LDS of the precisions)
+  switch (cfg) {
+    case 0: return cfg_smem<0, TT_FP64>();
+    case 1: return cfg_smem<1, TT_FP64>();
+    case 2: return cfg_smem<2, TT_FP64>();
+    case 3: return cfg_smem<3, TT_FP64>();
+    default: return cfg_smem<4, TT_FP64>();
+  }
+}
+
+template <int CFG, int PREC>
+void launch_cfg(const GemmPlan& p, const long long* d_tabs, Slots s, double* pws, hipStream_t st) {
+  const int n = p.cfg_off[CFG + 1] - p.cfg_off[CFG];
+  if (n == 0) return;
+  static bool attr = false;
+  const int smem = cfg_smem<CFG, PREC>();
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_gemm<CFG, PREC>, hipFuncAttributeMaxDynamicSharedMemorySize, smem) !=
+        hipSuccess)
+      throw Error(TT_EDEVICE, "cannot set the LDS limit of the GEMM kernel");
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gemm<CFG, PREC>), dim3(n), dim3(256), smem, st, p.d_probs, p.d_tiles, p.cfg_off[CFG], d_tabs, s,
+                     pws);
+  HIP_CHECK_LAUNCH();
+}
+
+template <int PREC>
+void launch_prec(const GemmPlan& p, const long long* d_tabs, Slots s, double* pws, hipStream_t st) {
+  launch_cfg<0, PREC>(p, d_tabs, s, pws, st);
+  launch_cfg<1, PREC>(p, d_tabs, s, pws, st);
+  launch_cfg<2, PREC>(p, d_tabs, s, pws, st);
+  launch_cfg<3, PREC>(p, d_tabs, s, pws, st);
+  launch_cfg<4, PREC>(p, d_tabs, s, pws, st);
+}
+
+// C = alpha * (sum of the K-slice partials in slice order) + beta * C
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict__ probs,
+                                                     const GemmSplit* __restrict__ splits,
+                                                     const long long* __restrict__ tabs, Slots slots,
+                                                     const double* __restrict__ pws) {
+  const GemmSplit S = splits[blockIdx.x];
+  const GemmProb P = probs[S.prob];
+  const int BM = kGemmBM[S.cfg], BN = kGemmBN[S.cfg];
+  double* C = slots.p[P.ic] + P.offC;
+  const int m0 = S.tm * BM, n0 = S.tn * BN;
+  for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
+    int row = e / BN, col = e % BN;
+    int m = m0 + row, n = n0 + col;
+    if (m >= P.M || n >= P.N) continue;
+    double v = 0.0;
+    for (int ks = 0; ks < S.nk; ++ks) v += pws[S.pw + (long long)ks * BM * BN + e];
+    double* cp = C + idx_map(tabs, P.tcm, P.scm, m) + n;
+    double val = P.alpha * v;
+    if (P.beta != 0.0) val += P.beta * (*cp);
+    *cp = val;
+  }
+}
+
+void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, double* pws, hipStream_t st) {
   if (p.ntiles == 0) return;
   prof_begin(st);
-  hipLaunchKernelGGL(k_gemm_f64, dim3(p.ntiles), dim3(256), 0, st, p.d_probs, p.d_tiles, d_tabs, s);
-  HIP_CHECK_LAUNCH();
-  prof_end(st, PROF_GEMM, p.flops, p.bytes);
+  switch (precision) {
+    case TT_FP64: launch_prec<TT_FP64>(p, d_tabs, s, pws, st); break;
+    case TT_FP32: launch_prec<TT_FP32>(p, d_tabs, s, pws, st); break;
+    case TT_BF16X3: launch_prec<TT_BF16X3>(p, d_tabs, s, pws, st); break;
+    case TT_BF16X6: launch_prec<TT_BF16X6>(p, d_tabs, s, pws, st); break;
+    default: throw Error(TT_EINVAL, "unknown precision");
+  }
+  if (!p.splits.empty()) {
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)p.splits.size()), dim3(256), 0, st, p.d_probs, p.d_splits,
+                       d_tabs, s, pws);
+    HIP_CHECK_LAUNCH();
+  }
+  prof_end(st, p.tag, p.flops, p.bytes);
 }
 
 // ------------------------------------------------------------------ W stage
@@ -602,6 +874,85 @@ __global__ void k_lz_sub(double* __restrict__ w, const double* __restrict__ Q, l
   }
 }
 
+// Fused Gram-Schmidt passes.  Both kernels run on kRedBlocks blocks with the
+// same contiguous chunks as k_mdot, so every partial sum has a fixed order.
+// k_lz_sub_dot: w -= sum_v c_v Q_v with c from the partials of the previous
+// pass (alpha, ||H q|| stored by block 0), then partial dots Q_v . w of the
+// updated chunk (next pass).
+__global__ __launch_bounds__(256) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q, long long ld,
+                                                    int nv, const double* __restrict__ part_in, int stride_in, long long n,
+                                                    double* alpha_out, double* hn_out, double* __restrict__ part_out) {
+  __shared__ double c[kMaxKrylov + 1];
+  __shared__ double red[8];
+  if (threadIdx.x < nv) c[threadIdx.x] = sum_parts(part_in, kRedBlocks, stride_in, threadIdx.x);
+  if (threadIdx.x == 0 && stride_in > nv) c[nv] = sum_parts(part_in, kRedBlocks, stride_in, nv);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (alpha_out) *alpha_out = c[nv - 1];
+    if (hn_out) *hn_out = sqrt(c[nv]);
+  }
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long i0 = (long long)blockIdx.x * chunk;
+  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double s = w[i];
+    for (int v = 0; v < nv; ++v) s -= c[v] * Q[(long long)v * ld + i];
+    w[i] = s;
+  }
+  __syncthreads();
+  for (int v = 0; v < nv; ++v) {
+    const double* x = Q + (long long)v * ld;
+    double s = 0.0;
+    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += x[i] * w[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part_out[(long long)blockIdx.x * nv + v] = s;
+  }
+}
+
+// k_lz_sub_norm: second pass w -= sum_v c_v Q_v, then partial w . w
+__global__ __launch_bounds__(256) void k_lz_sub_norm(double* __restrict__ w, const double* __restrict__ Q, long long ld,
+                                                     int nv, const double* __restrict__ part_in, long long n,
+                                                     double* __restrict__ part_out) {
+  __shared__ double c[kMaxKrylov + 1];
+  __shared__ double red[8];
+  if (threadIdx.x < nv) c[threadIdx.x] = sum_parts(part_in, kRedBlocks, nv, threadIdx.x);
+  __syncthreads();
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long i0 = (long long)blockIdx.x * chunk;
+  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
+  double ss = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double s = w[i];
+    for (int v = 0; v < nv; ++v) s -= c[v] * Q[(long long)v * ld + i];
+    w[i] = s;
+    ss += s * s;
+  }
+  ss = block_sum(ss, red);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
+}
+
+// out = sum_v coeff_v Q_v and the partial out . out of each chunk
+__global__ __launch_bounds__(256) void k_lz_combine_norm(const double* __restrict__ Q, long long ld, int K,
+                                                         const double* __restrict__ coeff, double* __restrict__ out,
+                                                         long long n, double* __restrict__ part_out) {
+  __shared__ double c[kMaxKrylov];
+  __shared__ double red[8];
+  if (threadIdx.x < K) c[threadIdx.x] = coeff[threadIdx.x];
+  __syncthreads();
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long i0 = (long long)blockIdx.x * chunk;
+  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
+  double ss = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double s = 0.0;
+    for (int v = 0; v < K; ++v) s += c[v] * Q[(long long)v * ld + i];
+    out[i] = s;
+    ss += s * s;
+  }
+  ss = block_sum(ss, red);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
+}
+
 // beta = ||w||; qn = w / beta unless beta <= tol * ||H q|| (lucky breakdown: qn = 0)
 __global__ void k_lz_next(const double* __restrict__ w, double* __restrict__ qn, long long n,
                           const double* __restrict__ part, double* beta_out, const double* hn, double tol) {
@@ -746,6 +1097,22 @@ void launch_lz_start(const double* v, double* q0, long long n, const double* par
 void launch_lz_sub(double* w, const double* Q, long long ld, int nv, const double* part, int nparts, long long n,
                    double* alpha_out, double* hn_out, hipStream_t st) {
   hipLaunchKernelGGL(k_lz_sub, dim3(grid_for(n)), dim3(256), 0, st, w, Q, ld, nv, part, nparts, n, alpha_out, hn_out);
+  HIP_CHECK_LAUNCH();
+}
+void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
+                       long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_sub_dot, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, stride_in, n, alpha_out,
+                     hn_out, part_out);
+  HIP_CHECK_LAUNCH();
+}
+void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
+                        double* part_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_sub_norm, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, n, part_out);
+  HIP_CHECK_LAUNCH();
+}
+void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
+                            double* part_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_combine_norm, dim3(kRedBlocks), dim3(256), 0, st, Q, ld, K, coeff, out, n, part_out);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_next(const double* w, double* qn, long long n, const double* part, double* beta_out, const double* hn,

@@ -118,13 +118,50 @@ static void finish_qrplan(QRPlan& q) {
   }
 }
 
-void tile_plan(GemmPlan& p, int BM, int BN) {
+int gemm_cfg_for(int M, int N) {
+  if (M <= 32 && N <= 32) return 4;
+  if (M <= 32) return 3;
+  if (N <= 16) return 2;
+  if (N <= 32) return 1;
+  return 0;
+}
+
+void tile_plan(GemmPlan& p) {
   p.tiles.clear();
-  for (int i = 0; i < (int)p.probs.size(); ++i) {
-    int tm = (p.probs[i].M + BM - 1) / BM, tn = (p.probs[i].N + BN - 1) / BN;
-    for (int a = 0; a < tm; ++a)
-      for (int b = 0; b < tn; ++b) p.tiles.push_back({i, a, b});
+  p.splits.clear();
+  p.pws_size = 0;
+  p.smem_bytes = 0;
+  // K splitting only pays when the launch has too few tiles to fill the GPU
+  long long tiles0 = 0;
+  for (auto& g : p.probs) {
+    int cfg = gemm_cfg_for(g.M, g.N);
+    tiles0 += (long long)((g.M + kGemmBM[cfg] - 1) / kGemmBM[cfg]) * ((g.N + kGemmBN[cfg] - 1) / kGemmBN[cfg]);
   }
+  const bool may_split = tiles0 < kSplitBelowTiles;
+  for (int i = 0; i < (int)p.probs.size(); ++i) {
+    const GemmProb& g = p.probs[i];
+    int cfg = gemm_cfg_for(g.M, g.N);
+    int BM = kGemmBM[cfg], BN = kGemmBN[cfg];
+    int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    int nk = may_split ? (g.K + kKSlice - 1) / kKSlice : 1;
+    if (nk < 1) nk = 1;
+    if (nk > kMaxKSplit) nk = kMaxKSplit;
+    p.smem_bytes = std::max(p.smem_bytes, gemm_smem_bytes(cfg));
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) {
+        long long pw = -1;
+        if (nk > 1) {
+          pw = p.pws_size;
+          p.pws_size += (long long)nk * BM * BN;
+          p.splits.push_back({i, a, b, cfg, nk, 0, pw});
+        }
+        for (int ks = 0; ks < nk; ++ks) p.tiles.push_back({i, a, b, cfg, ks, nk, pw});
+      }
+  }
+  std::stable_sort(p.tiles.begin(), p.tiles.end(), [](const GemmTile& x, const GemmTile& y) { return x.cfg < y.cfg; });
+  for (int c = 0; c <= kGemmCfgs; ++c) p.cfg_off[c] = 0;
+  for (auto& t : p.tiles) p.cfg_off[t.cfg + 1]++;
+  for (int c = 0; c < kGemmCfgs; ++c) p.cfg_off[c + 1] += p.cfg_off[c];
   p.ntiles = (int)p.tiles.size();
 }
 
@@ -161,6 +198,8 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
     pos += (long long)rows.size() * S.C[l];
   }
   P.t1_size = pos;
+  P.s1.tag = TAG_LA; P.s3.tag = TAG_R; P.el.tag = TAG_ENVL; P.r1.tag = TAG_ENVR1; P.r3.tag = TAG_ENVR3;
+  P.b1.tag = TAG_BOND; P.b2.tag = TAG_BOND; P.absL.tag = TAG_ABSORB; P.absR.tag = TAG_ABSORB;
 
   // ---------------- W stage: T2 grouped by the right bra sector r'
   // rows (p, g', x, s'), cols (b, y) as in the R environment of sector r'

@@ -25,7 +25,19 @@ struct GemmProb {
   long long tam, tak, tbk, tbn, tcm;
   double alpha, beta;
 };
-struct GemmTile { int prob, tm, tn; };
+// tile shapes of the grouped GEMM, chosen per problem from its M and N:
+//   0: 64x64   1: 128x32   2: 256x16   3: 32x128   4: 32x32 with the K sub-steps split over the four waves
+// A problem with a long K is split into nk K-slices over separate workgroups:
+// each writes its partial BM x BN tile to the plan's partial buffer at
+// pw + ks*BM*BN, and a reduce pass adds the slices in order (deterministic).
+struct GemmTile { int prob, tm, tn, cfg, ks, nk; long long pw; };
+struct GemmSplit { int prob, tm, tn, cfg, nk, pad; long long pw; };
+constexpr int kKSlice = 128;      // K per slice when a problem is split
+constexpr int kMaxKSplit = 8;
+constexpr long long kSplitBelowTiles = 2048;   // split only launches with fewer tiles
+constexpr int kGemmCfgs = 5;
+constexpr int kGemmBM[kGemmCfgs] = {64, 128, 256, 32, 32};
+constexpr int kGemmBN[kGemmCfgs] = {64, 32, 16, 128, 32};
 
 // W stage: dst(i,j) = sum_t w_t src_t(i,j) for i < ni, j < nj, with
 // dst(i,j) = out[dst + i*dsi + j*dsj] and src_t(i,j) = in[src + i*ssi + j*ssj].
@@ -47,7 +59,11 @@ struct QRChunk { int task, row0, rows, chunk, nchunks, pad; long long qw, rw; };
 struct QRStack { int task, nchunks; long long rw; };
 
 // A plan: descriptors uploaded once, launched many times with varying slots.
+// profiler tags of the grouped GEMMs (which contraction a launch belongs to)
+enum GemmTag { TAG_LA = 0, TAG_R = 1, TAG_ENVL = 2, TAG_ENVR1 = 3, TAG_ENVR3 = 4, TAG_BOND = 5, TAG_ABSORB = 6,
+               TAG_WGEMM = 7, TAG_COUNT = 8 };
 struct GemmPlan {
+  int tag = TAG_LA;
   std::vector<GemmProb> probs;
   std::vector<GemmTile> tiles;
   double flops = 0;
@@ -55,6 +71,11 @@ struct GemmPlan {
   GemmProb* d_probs = nullptr;
   GemmTile* d_tiles = nullptr;
   int ntiles = 0;
+  std::vector<GemmSplit> splits;
+  GemmSplit* d_splits = nullptr;
+  int cfg_off[kGemmCfgs + 1] = {0, 0, 0, 0, 0, 0};   // tiles are sorted by shape
+  long long pws_size = 0;   // doubles of partial tiles
+  int smem_bytes = 0;       // LDS of the largest tile shape in the plan
 };
 struct WPlan {
   std::vector<WTask> tasks;
@@ -159,7 +180,9 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<double>& W,   // DHl*16*DHr
                          SiteTables& tabs);
 
-// tile the problems of a plan (BM x BN tiles)
-void tile_plan(GemmPlan& p, int BM, int BN);
+// tile the problems of a plan (shape per problem)
+int gemm_cfg_for(int M, int N);
+int gemm_smem_bytes(int cfg);     // LDS bytes of one tile of shape cfg
+void tile_plan(GemmPlan& p);
 
 }  // namespace tt

@@ -221,13 +221,23 @@ def tt_profile_enable(on):
     _check(lib().tt_profile_enable(1 if on else 0))
 
 
+PROFILE_KINDS = ("gemm_LA", "gemm_R", "gemm_envL", "gemm_envR1", "gemm_envR3", "gemm_bond", "gemm_absorb",
+                 "gemm_Wdense", "wstage", "qr")
+
+
 def tt_profile_read():
-    """{kind: dict(ms, flops, bytes, launches)} for gemm, wstage, qr since the last read."""
-    buf = (C.c_double * 12)()
+    """{kind: dict(ms, flops, bytes, launches)} since the last read; 'gemm' sums the GEMM kinds."""
+    buf = (C.c_double * 40)()
     _check(lib().tt_profile_read(buf))
     out = {}
-    for i, k in enumerate(("gemm", "wstage", "qr")):
+    for i, k in enumerate(PROFILE_KINDS):
         out[k] = dict(ms=buf[4 * i], flops=buf[4 * i + 1], bytes=buf[4 * i + 2], launches=int(buf[4 * i + 3]))
+    g = dict(ms=0.0, flops=0.0, bytes=0.0, launches=0)
+    for k in PROFILE_KINDS:
+        if k.startswith("gemm_"):
+            for f in g:
+                g[f] += out[k][f]
+    out["gemm"] = g
     return out
 
 

@@ -69,3 +69,30 @@ def test_heff_apply_d2000_sampled():
     g = np.array([got[i] for i in idx])
     scale = np.sqrt(np.mean(want ** 2))
     assert np.abs(g - want).max() <= 1e-12 * scale, (np.abs(g - want).max(), scale)
+
+
+# relative Frobenius error bounds of the mixed paths (one apply, N(0,1) inputs):
+# FP32 MFMA rounds operands to 24 bits; split-BF16 x3 keeps ~16 bits per
+# operand, x6 ~24 bits; accumulation is FP32 inside a K tile, FP64 across.
+MIXED_TOL = {T.TT_FP32: 2e-6, T.TT_BF16X3: 2e-4, T.TT_BF16X6: 2e-6}
+
+
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X3, T.TT_BF16X6])
+@pytest.mark.parametrize("Dl,Dr,DH,seed", [(5, 7, 3, 1), (96, 130, 18, 4), (200, 17, 7, 6), (40, 40, 2, 9)])
+def test_heff_apply_mixed_precision(prec, Dl, Dr, DH, seed):
+    L, W, A, R = WL.heff_inputs_rect(Dl, Dr, DH, seed)
+    got = _apply_gpu(L, W, A, R, prec)
+    want = otd.heff1(L, W, R, A)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err < MIXED_TOL[prec], err
+    # and it is not accidentally the FP64 path
+    if prec != T.TT_BF16X6:
+        assert err > 1e-12
+
+
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X3, T.TT_BF16X6])
+def test_heff_apply_mixed_d256(prec):
+    L, W, A, R = WL.heff_inputs(256)
+    got = _apply_gpu(L, W, A, R, prec)
+    want = otd.heff1(L, W, R, A)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < MIXED_TOL[prec]

@@ -170,3 +170,46 @@ def test_import_export_roundtrip():
         T.tt_state_import_site(st.h, 2, bad)
     assert e.value.code == T.TT_ENUMERIC
     st.free()
+
+
+# mixed-precision sweeps against the FP64 references: the bulk contractions in
+# FP32 / split-BF16, Lanczos scalars, QR and Lambda in FP64
+TOL_MIXED = 1e-6
+
+
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X6, T.TT_BF16X3])
+def test_mixed_precision_chain4_vs_ed(prec):
+    c = WL.MODELS["chain4"]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    st = T.State.init(m, T.options(D=c["D"], symmetry=1, beta0=c["beta0"], krylov_dim=c["krylov"], precision=prec))
+    E, _, _ = ed.Hubbard(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"]).spectrum()
+    errs = []
+    for step in range(100):
+        st.sweep(c["dbeta"])
+    o = st.observables()
+    lnZ, Ebl = ed.same_ode_bilayer(E, c["beta0"], o["beta"])
+    f_ref = -lnZ / (4 * 2 * o["beta"])
+    errs = (_rel(o["f"], f_ref), _rel(o["e"], Ebl / 4))
+    print("precision", prec, "rel err f, e", errs)
+    if prec != T.TT_BF16X3:
+        assert errs[0] <= TOL_MIXED and errs[1] <= TOL_MIXED, errs
+    else:
+        assert errs[0] <= 1e-4 and errs[1] <= 1e-4, errs
+    st.free()
+
+
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X6])
+def test_mixed_precision_truncated_vs_oracle(prec):
+    W, L, geo, U, mu, D, pad = 3, 3, T.TT_CYLINDER, 8.0, 2.0, 24, 0.3
+    b0 = 0.01
+    mm = ompo.HubbardMPO(W, L, geo, 1.0, U, mu)
+    ost = otd.initial_state(mm, b0, D, True, pad_eps=pad, seed=11, sector_cap=64)
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu),
+                      T.options(D=D, symmetry=1, beta0=b0, pad_eps=pad, seed=11, precision=prec))
+    for _ in range(2):
+        st.sweep(0.1)
+        ost.sweep(0.1)
+    o, r = st.observables(), ost.observables()
+    assert _rel(o["f"], r["f"]) <= TOL_MIXED, (o["f"], r["f"])
+    assert _rel(o["e"], r["e"]) <= TOL_MIXED, (o["e"], r["e"])
+    st.free()
