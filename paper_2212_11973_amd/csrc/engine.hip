@@ -585,6 +585,7 @@ long long check_gemm(const GemmPlan& p, const std::vector<long long>& tabs, cons
     const GemmProb& g = p.probs[t.prob];
     if (t.tm < 0 || t.tn < 0 || t.tm * kGemmBM[t.cfg] >= g.M || t.tn * kGemmBN[t.cfg] >= g.N) ++bad;
     if (t.nk < 1 || t.ks < 0 || t.ks >= t.nk) ++bad;
+    if (t.nk > 1 && (t.sidx < 0 || t.sidx >= (int)p.splits.size())) ++bad;
     if (t.nk > 1 && (t.pw < 0 || t.pw + (long long)t.nk * kGemmBM[t.cfg] * kGemmBN[t.cfg] > p.pws_size)) ++bad;
   }
   for (auto& sp : p.splits)

@@ -123,9 +123,12 @@ __device__ __forceinline__ void bf16_split(double x, __bf16* out) {
 // One BM x BN output tile of one problem.  Four 64-wide waves in a WGM x WGN
 // grid, each owning FM x FN MFMA 16x16 blocks; with SPLITK all waves own the
 // whole tile and take alternate 4-deep K sub-steps, reduced through LDS.  A
-// K-split problem covers only the K slice of this tile and writes a partial.
+// K-split problem covers only the K slice of this tile and writes a partial
+// that k_gemm_reduce adds up in slice order.
 // FP64: f64 MFMA.  FP32 / BF16: f32-accumulating MFMA inside each K tile,
 // added into FP64 accumulators after every K tile.
+// Global loads of the next K tile are issued before the MFMAs of the current
+// one (register double buffering), so their latency overlaps the compute.
 template <int WGM, int WGN, int FM, int FN, bool SPLITK, int PREC>
 __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, const long long* __restrict__ tabs,
                                           const Slots& slots, char* smem, double* __restrict__ pws) {
@@ -136,6 +139,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
   constexpr int tile_bytes = F64 ? 8 * (BK * (BM + 1) + BK * (BN + 1))
                              : F32 ? 4 * (BK * (BM + 1) + BK * (BN + 1))
                                    : 2 * NP * (BM + BN) * (BK + kBfPad);
+  constexpr int EA = (BM * BK + 255) / 256, EB = (BN * BK + 255) / 256;
   // LDS carve-up
   double(*dA)[BM + 1] = reinterpret_cast<double(*)[BM + 1]>(smem);
   double(*dB)[BN + 1] = reinterpret_cast<double(*)[BN + 1]>(smem + 8 * BK * (BM + 1));
@@ -146,8 +150,6 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
   long long* rA = reinterpret_cast<long long*>(smem + tile_bytes);
   long long* rC = rA + BM;
   long long* cB = rC + BM;
-  long long* kA = cB + BN;
-  long long* kB = kA + BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tm = T.tm, tn = T.tn;
   const int m0 = tm * BM, n0 = tn * BN;
@@ -178,51 +180,69 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
     kbeg = T.ks * per;
     kstop = kbeg + per < P.K ? kbeg + per : P.K;
   }
+  // element e = tid + 256 q of a tile -> (row/col, k) inside the tile
+  auto a_ik = [&](int e, int& i, int& kk) {
+    if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % BM; kk = e / BM; }
+  };
+  auto b_jk = [&](int e, int& j, int& kk) {
+    if (b_nfast) { j = e % BN; kk = e / BN; } else { j = e / BK; kk = e % BK; }
+  };
+  double ra[EA], rb[EB];
+  __syncthreads();   // row / column offsets ready
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      int e = tid + q * 256, i, kk;
+      a_ik(e, i, kk);
+      const int k = k0 + kk;
+      const bool ok = (e < BM * BK) && (m0 + i < P.M) && (k < kstop);
+      ra[q] = ok ? A[rA[i] + idx_map(tabs, P.tak, P.sak, k)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      int e = tid + q * 256, j, kk;
+      b_jk(e, j, kk);
+      const int k = k0 + kk;
+      const bool ok = (e < BN * BK) && (n0 + j < P.N) && (k < kstop);
+      rb[q] = ok ? B[idx_map(tabs, P.tbk, P.sbk, k) + cB[j]] : 0.0;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      int e = tid + q * 256, i, kk;
+      if (e >= BM * BK) break;
+      a_ik(e, i, kk);
+      if (F64) dA[kk][i] = ra[q];
+      else if (F32) fA[kk][i] = (float)ra[q];
+      else {
+        __bf16 parts[3];
+        bf16_split<NP>(ra[q], parts);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bA[(p * BM + i) * (BK + kBfPad) + kk] = parts[p];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      int e = tid + q * 256, j, kk;
+      if (e >= BN * BK) break;
+      b_jk(e, j, kk);
+      if (F64) dB[kk][j] = rb[q];
+      else if (F32) fB[kk][j] = (float)rb[q];
+      else {
+        __bf16 parts[3];
+        bf16_split<NP>(rb[q], parts);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bB[(p * BN + j) * (BK + kBfPad) + kk] = parts[p];
+      }
+    }
+  };
+  if (kbeg < kstop) fetch(kbeg);
   for (int k0 = kbeg; k0 < kstop; k0 += BK) {
+    __syncthreads();   // the previous K tile is consumed
+    stash();
     __syncthreads();
-    for (int q = tid; q < 2 * BK; q += 256) {
-      int k = k0 + (q % BK);
-      if (q < BK) kA[q] = k < kstop ? idx_map(tabs, P.tak, P.sak, k) : 0;
-      else kB[q - BK] = k < kstop ? idx_map(tabs, P.tbk, P.sbk, k) : 0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e0 = 0; e0 < (BM * BK + 255) / 256; ++e0) {
-      int e = tid + e0 * 256;
-      if (e < BM * BK) {
-        int i, kk;
-        if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % BM; kk = e / BM; }
-        bool ok = (m0 + i < P.M) && (k0 + kk < kstop);
-        double x = ok ? A[rA[i] + kA[kk]] : 0.0;
-        if (F64) dA[kk][i] = x;
-        else if (F32) fA[kk][i] = (float)x;
-        else {
-          __bf16 parts[3];
-          bf16_split<NP>(x, parts);
-#pragma unroll
-          for (int p = 0; p < NP; ++p) bA[(p * BM + i) * (BK + kBfPad) + kk] = parts[p];
-        }
-      }
-    }
-#pragma unroll
-    for (int e0 = 0; e0 < (BN * BK + 255) / 256; ++e0) {
-      int e = tid + e0 * 256;
-      if (e < BN * BK) {
-        int j, kk;
-        if (b_nfast) { j = e % BN; kk = e / BN; } else { j = e / BK; kk = e % BK; }
-        bool ok = (n0 + j < P.N) && (k0 + kk < kstop);
-        double x = ok ? B[kB[kk] + cB[j]] : 0.0;
-        if (F64) dB[kk][j] = x;
-        else if (F32) fB[kk][j] = (float)x;
-        else {
-          __bf16 parts[3];
-          bf16_split<NP>(x, parts);
-#pragma unroll
-          for (int p = 0; p < NP; ++p) bB[(p * BN + j) * (BK + kBfPad) + kk] = parts[p];
-        }
-      }
-    }
-    __syncthreads();
+    if (k0 + BK < kstop) fetch(k0 + BK);
     const int kend = (kstop - k0 < BK) ? kstop - k0 : BK;
     if (F64) {
 #pragma unroll
@@ -301,6 +321,15 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
   // row of accumulator element v inside a 16x16 block (measured on gfx950):
   // f64 MFMA: lane/16 + 4v; f32-accumulating MFMA: 4*(lane/16) + v
   auto brow = [&](int v) { return F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v; };
+  auto store = [&](int row, int col, double v) {
+    const int m = m0 + row, n = n0 + col;
+    if (m < P.M && n < P.N) {
+      double* cp = C + rC[row] + n;
+      double val = P.alpha * v;
+      if (P.beta != 0.0) val += P.beta * (*cp);
+      *cp = val;
+    }
+  };
   if (SPLITK) {
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem + tile_bytes + 8 * (2 * BM + BN + 2 * BK));
@@ -315,38 +344,49 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
         }
     __syncthreads();
     for (int e = tid; e < BM * BN; e += 256) {
-      int row = e / BN, col = e % BN;
-      int m = m0 + row, n = n0 + col;
       double v = red[e] + red[BM * BN + e] + red[2 * BM * BN + e] + red[3 * BM * BN + e];
-      if (T.nk > 1) {
-        pws[T.pw + (long long)T.ks * BM * BN + e] = v;
-      } else if (m < P.M && n < P.N) {
-        double* cp = C + rC[row] + n;
-        double val = P.alpha * v;
-        if (P.beta != 0.0) val += P.beta * (*cp);
-        *cp = val;
-      }
+      if (T.nk > 1) pws[T.pw + (long long)T.ks * BM * BN + e] = v;
+      else store(e / BN, e % BN, v);
     }
-    return;
-  }
+  } else {
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int row = wm + i * 16 + brow(v);
-        int col = wn + j * 16 + (lane & 15);
-        int m = m0 + row, n = n0 + col;
-        if (T.nk > 1) {
-          pws[T.pw + (long long)T.ks * BM * BN + row * BN + col] = acc[i][j][v];
-        } else if (m < P.M && n < P.N) {
-          double* cp = C + rC[row] + n;
-          double val = P.alpha * acc[i][j][v];
-          if (P.beta != 0.0) val += P.beta * (*cp);
-          *cp = val;
+        for (int v = 0; v < 4; ++v) {
+          int row = wm + i * 16 + brow(v);
+          int col = wn + j * 16 + (lane & 15);
+          if (T.nk > 1) pws[T.pw + (long long)T.ks * BM * BN + row * BN + col] = acc[i][j][v];
+          else store(row, col, acc[i][j][v]);
         }
-      }
+  }
+}
+
+// C = alpha * (sum of the K-slice partials in slice order) + beta * C
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict__ probs,
+                                                     const GemmSplit* __restrict__ splits,
+                                                     const long long* __restrict__ tabs, Slots slots,
+                                                     const double* __restrict__ pws) {
+  __shared__ long long rC[256];
+  const GemmSplit S = splits[blockIdx.x];
+  const GemmProb P = probs[S.prob];
+  const int BM = kGemmBM[S.cfg], BN = kGemmBN[S.cfg];
+  double* C = slots.p[P.ic] + P.offC;
+  const int m0 = S.tm * BM, n0 = S.tn * BN;
+  for (int i = threadIdx.x; i < BM; i += blockDim.x) rC[i] = (m0 + i < P.M) ? idx_map(tabs, P.tcm, P.scm, m0 + i) : 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
+    int row = e / BN, col = e % BN;
+    int m = m0 + row, n = n0 + col;
+    if (m >= P.M || n >= P.N) continue;
+    double v = 0.0;
+    for (int ks = 0; ks < S.nk; ++ks) v += pws[S.pw + (long long)ks * BM * BN + e];
+    double* cp = C + rC[row] + n;
+    double val = P.alpha * v;
+    if (P.beta != 0.0) val += P.beta * (*cp);
+    *cp = val;
+  }
 }
 
 // tile shapes: 0 64x64, 1 128x32, 2 256x16, 3 32x128, 4 32x32 (split K over the
@@ -413,29 +453,6 @@ void launch_prec(const GemmPlan& p, const long long* d_tabs, Slots s, double* pw
   launch_cfg<2, PREC>(p, d_tabs, s, pws, st);
   launch_cfg<3, PREC>(p, d_tabs, s, pws, st);
   launch_cfg<4, PREC>(p, d_tabs, s, pws, st);
-}
-
-// C = alpha * (sum of the K-slice partials in slice order) + beta * C
-__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict__ probs,
-                                                     const GemmSplit* __restrict__ splits,
-                                                     const long long* __restrict__ tabs, Slots slots,
-                                                     const double* __restrict__ pws) {
-  const GemmSplit S = splits[blockIdx.x];
-  const GemmProb P = probs[S.prob];
-  const int BM = kGemmBM[S.cfg], BN = kGemmBN[S.cfg];
-  double* C = slots.p[P.ic] + P.offC;
-  const int m0 = S.tm * BM, n0 = S.tn * BN;
-  for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
-    int row = e / BN, col = e % BN;
-    int m = m0 + row, n = n0 + col;
-    if (m >= P.M || n >= P.N) continue;
-    double v = 0.0;
-    for (int ks = 0; ks < S.nk; ++ks) v += pws[S.pw + (long long)ks * BM * BN + e];
-    double* cp = C + idx_map(tabs, P.tcm, P.scm, m) + n;
-    double val = P.alpha * v;
-    if (P.beta != 0.0) val += P.beta * (*cp);
-    *cp = val;
-  }
 }
 
 void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, double* pws, hipStream_t st) {

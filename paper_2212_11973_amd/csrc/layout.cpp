@@ -150,12 +150,14 @@ void tile_plan(GemmPlan& p) {
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
         long long pw = -1;
+        int sidx = -1;
         if (nk > 1) {
           pw = p.pws_size;
           p.pws_size += (long long)nk * BM * BN;
+          sidx = (int)p.splits.size();
           p.splits.push_back({i, a, b, cfg, nk, 0, pw});
         }
-        for (int ks = 0; ks < nk; ++ks) p.tiles.push_back({i, a, b, cfg, ks, nk, pw});
+        for (int ks = 0; ks < nk; ++ks) p.tiles.push_back({i, a, b, cfg, ks, nk, sidx, 0, pw});
       }
   }
   std::stable_sort(p.tiles.begin(), p.tiles.end(), [](const GemmTile& x, const GemmTile& y) { return x.cfg < y.cfg; });

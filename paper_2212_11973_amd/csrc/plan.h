@@ -30,7 +30,7 @@ struct GemmProb {
 // A problem with a long K is split into nk K-slices over separate workgroups:
 // each writes its partial BM x BN tile to the plan's partial buffer at
 // pw + ks*BM*BN, and a reduce pass adds the slices in order (deterministic).
-struct GemmTile { int prob, tm, tn, cfg, ks, nk; long long pw; };
+struct GemmTile { int prob, tm, tn, cfg, ks, nk, sidx, pad; long long pw; };
 struct GemmSplit { int prob, tm, tn, cfg, nk, pad; long long pw; };
 constexpr int kKSlice = 128;      // K per slice when a problem is split
 constexpr int kMaxKSplit = 8;
