@@ -23,7 +23,15 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s (MI3
 PEAK_FP64_VALU = 78.6                                   # 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_HBM_GBS = 8000.0
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
-KERNEL_NAME = {"gemm": "k_gemm_f64", "wstage": "k_wstage", "qr": "k_qr"}
+# single kernels that can be the dominant one, with the name rocprofv3 reports
+SHAPES = ("64x64", "128x32", "256x16", "32x128", "32x32")
+
+
+def kernel_name(kind, prec):
+    if kind.startswith("k_gemm_") and kind != "k_gemm_reduce":
+        return "tt::k_gemm<%d, %d>" % (SHAPES.index(kind[len("k_gemm_"):]), prec)
+    return {"k_gemm_reduce": "tt::k_gemm_reduce", "wstage": "tt::k_wstage",
+            "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
 
 
 def dense_sweep_flops(dims, DH, K):
@@ -63,10 +71,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl4x16")
     ap.add_argument("--D", type=int, default=0, help="override the bond dimension")
-    ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
+    ap.add_argument("--precision", default="fp64", choices=sorted(PREC),
+                    help="precision of the timed sweep that gives 'value'")
+    ap.add_argument("--mixed-precisions", default="bf16x6,fp32",
+                    help="further sweep precisions timed after the main one ('' for none)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy this many MiB once (a known-size kernel for counter calibration)")
     ap.add_argument("--heff-D", type=int, default=2000)
     ap.add_argument("--heff-reps", type=int, default=5)
-    ap.add_argument("--heff-precisions", default="fp64")
+    ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-D", type=int, default=1500, help="bond dimension of the oracle sample")
     args = ap.parse_args()
@@ -82,54 +95,82 @@ def main():
 
     torch.cuda.set_device(0)
     T.lib()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     c = WL.MODELS[args.workload]
     D = args.D or c["D"]
     m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
-    o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
-                  precision=PREC[args.precision])
-    print("init %s D=%d" % (args.workload, D), file=sys.stderr, flush=True)
-    st = T.State.init(m, o)
-    n_sites, dims = st.info()
-    for i in range(args.warmup):
-        st.sweep(c["dbeta"])
-        print("warmup %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    T.tt_profile_enable(True)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        stats.append(st.sweep(c["dbeta"], stats=True))
-        print("step %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    T.tt_profile_enable(False)
-    prof = T.tt_profile_read()
-    obs = st.observables()
-    st.free()
-    s_per_step = (t1 - t0) / args.steps
+
+    def timed_sweeps(prec, steps, warmup, profile):
+        o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
+                      precision=PREC[prec])
+        print("init %s D=%d %s" % (args.workload, D, prec), file=sys.stderr, flush=True)
+        st = T.State.init(m, o)
+        info = st.info()
+        for i in range(warmup):
+            st.sweep(c["dbeta"])
+            print("warmup %d done" % i, file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        if profile:
+            T.tt_profile_enable(True)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            stats.append(st.sweep(c["dbeta"], stats=True))
+            print("step %d done" % i, file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = None
+        if profile:
+            T.tt_profile_enable(False)
+            prof = T.tt_profile_read()
+        obs = st.observables()
+        st.free()
+        return (t1 - t0) / steps, stats, prof, obs, info
+
+    s_per_step, stats, prof, obs, (n_sites, dims) = timed_sweeps(args.precision, args.steps, args.warmup, True)
     flops_step = statistics.mean(s.flops_alg for s in stats)
     applies_step = statistics.mean(s.n_applies for s in stats)
+    mixed = {}
+    for pname in [x for x in args.mixed_precisions.split(",") if x and x != args.precision]:
+        sp, st2, _, ob2, _ = timed_sweeps(pname, args.steps, args.warmup, False)
+        mixed[pname] = dict(s_per_step=sp, f=ob2["f"], e=ob2["e"],
+                            rel_df_vs_main=abs(ob2["f"] - obs["f"]) / max(abs(obs["f"]), 1e-2),
+                            rel_de_vs_main=abs(ob2["e"] - obs["e"]) / max(abs(obs["e"]), 1e-2))
 
-    # dominant kernel of the timed region and its roofline
-    top = {k: v for k, v in prof.items() if k in ("gemm", "wstage", "qr")}
-    kind = max(top, key=lambda k: top[k]["ms"])
+    # dominant single kernel of the timed region and its roofline: the binding
+    # roof is the lower of the compute peak and arithmetic intensity x HBM peak
+    singles = [k for k in prof if k.startswith("k_gemm_") or k in ("wstage", "qr")]
+    kind = max(singles, key=lambda k: prof[k]["ms"])
     pk = prof[kind]
-    avg_ms = pk["ms"] / max(pk["launches"], 1)
-    if kind == "gemm":
+    sec = pk["ms"] * 1e-3
+    if kind.startswith("k_gemm_") and kind != "k_gemm_reduce":
         pname = "fp64" if args.precision == "fp64" else ("fp32" if args.precision == "fp32" else "bf16")
-        roof = dict(bound="mfma", unit="TFLOP/s", peak=PEAK[pname],
-                    achieved=pk["flops"] / (pk["ms"] * 1e-3) / 1e12)
-    elif kind == "wstage":
-        roof = dict(bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS, achieved=pk["bytes"] / (pk["ms"] * 1e-3) / 1e9)
+        peak_f = PEAK[pname]
     else:
-        roof = dict(bound="alu", unit="TFLOP/s", peak=PEAK_FP64_VALU,
-                    achieved=pk["flops"] / (pk["ms"] * 1e-3) / 1e12)
+        peak_f = PEAK_FP64_VALU
+    ai = pk["flops"] / max(pk["bytes"], 1.0)
+    if pk["flops"] > 0 and peak_f <= ai * PEAK_HBM_GBS / 1e3:
+        roof = dict(bound="mfma" if kind.startswith("k_gemm_") else "alu", unit="TFLOP/s", peak=peak_f,
+                    achieved=pk["flops"] / sec / 1e12)
+    else:
+        roof = dict(bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS, achieved=pk["bytes"] / sec / 1e9)
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = KERNEL_NAME[kind]
-    roof["avg_launch_ms"] = avg_ms
+    roof["kernel"] = kernel_name(kind, PREC[args.precision])
+    roof["avg_launch_ms"] = pk["ms"] / max(pk["launches"], 1)
     roof["launches"] = pk["launches"]
+    roof["alg_flops_per_launch"] = pk["flops"] / max(pk["launches"], 1)
+    roof["alg_bytes_per_launch"] = pk["bytes"] / max(pk["launches"], 1)
+    roof["intensity_flop_per_byte"] = ai
+    roof["share_of_step"] = pk["ms"] / (s_per_step * 1e3 * args.steps)
     kernels = {k: dict(ms_per_step=v["ms"] / args.steps, launches_per_step=v["launches"] / args.steps,
                        tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
                        gbs=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0)
@@ -188,9 +229,11 @@ def main():
                    % (c["W"], c["L"], "cylinder" if c["geometry"] == 1 else "open square", c["U"], c["mu"], D,
                       c["dbeta"], c["krylov"]),
                    "n_sites": n_sites, "max_bond": max(dims), "parallelism": "single GPU"},
-        "sweep": {"flops_alg_per_step": flops_step, "tflops_alg": flops_step / s_per_step / 1e12,
+        "sweep": {"precision": args.precision, "flops_alg_per_step": flops_step,
+                  "tflops_alg": flops_step / s_per_step / 1e12,
                   "applies_per_step": applies_step, "applies_per_s": applies_step / s_per_step,
-                  "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"]},
+                  "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
+                  "other_precisions": mixed},
         "heff": {"D": Dh, "D_H": DH, **heff},
         "roofline": roof,
         "cpu_baseline": cpu,

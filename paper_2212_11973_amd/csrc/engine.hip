@@ -1120,13 +1120,14 @@ int tt_profile_enable(int on) {
   ABI_END
 }
 
-int tt_profile_read(double* host_out40) {
+int tt_profile_read(double* host_out64) {
   ABI_BEGIN
-  TT_REQUIRE(host_out40, TT_EINVAL, "null argument");
+  static_assert(PROF_KINDS == 16, "tt_profile_read fills 16 kinds");
+  TT_REQUIRE(host_out64, TT_EINVAL, "null argument");
   double out[PROF_KINDS][4];
   prof_read(out);
   for (int k = 0; k < PROF_KINDS; ++k)
-    for (int j = 0; j < 4; ++j) host_out40[k * 4 + j] = out[k][j];
+    for (int j = 0; j < 4; ++j) host_out64[k * 4 + j] = out[k][j];
   ABI_END
 }
 

@@ -10,12 +10,20 @@ namespace tt {
 constexpr int kRedBlocks = 256;
 constexpr int kMaxKrylov = 32;
 
-// Optional timing of the grouped kernels: HIP events around every launch on its stream.
-// kinds 0..TAG_COUNT-1 are the GEMM tags, then the W stage and the QR
-enum ProfKind { PROF_WSTAGE = TAG_COUNT, PROF_QR = TAG_COUNT + 1, PROF_KINDS = TAG_COUNT + 2 };
+// Optional timing of the grouped kernels: HIP events on the launch stream.
+// kinds 0..TAG_COUNT-1 are the grouped GEMM contractions by tag, then the W
+// stage and the QR, then the individual GEMM kernels (one kind per tile shape,
+// then the K-slice reduce), each timed per dispatch.
+enum ProfKind {
+  PROF_WSTAGE = TAG_COUNT, PROF_QR = TAG_COUNT + 1, PROF_GEMM_CFG0 = TAG_COUNT + 2,
+  PROF_GEMM_REDUCE = PROF_GEMM_CFG0 + kGemmCfgs, PROF_KINDS = PROF_GEMM_REDUCE + 1
+};
 void prof_enable(bool on);
 bool prof_enabled();
+// begin an operation; prof_mark closes the dispatch launched since the previous
+// event (kind = a single kernel); prof_end closes the whole operation
 void prof_begin(hipStream_t st);
+void prof_mark(hipStream_t st, int kind, double flops, double bytes);
 void prof_end(hipStream_t st, int kind, double flops, double bytes);
 // (ms, flops, bytes, launches) per kind since the last read; synchronises the events
 void prof_read(double out[PROF_KINDS][4]);

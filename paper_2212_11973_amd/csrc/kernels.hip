@@ -36,16 +36,24 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ profiling
 namespace {
-struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; };
+// events recorded since the last read; a record spans two of them
+struct ProfRec { int a, b; int kind; double flops, bytes; };
 bool g_prof = false;
 std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_ev;
 std::vector<hipEvent_t> g_pool;
-hipEvent_t g_open = nullptr;
-hipEvent_t take_event() {
-  if (!g_pool.empty()) { hipEvent_t e = g_pool.back(); g_pool.pop_back(); return e; }
+int g_open = -1, g_last = -1;
+int record_event(hipStream_t st) {
   hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) throw Error(TT_EDEVICE, "hipEventCreate failed");
-  return e;
+  if (!g_pool.empty()) {
+    e = g_pool.back();
+    g_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    throw Error(TT_EDEVICE, "hipEventCreate failed");
+  }
+  g_ev.push_back(e);
+  if (hipEventRecord(e, st) != hipSuccess) throw Error(TT_EDEVICE, "hipEventRecord failed");
+  return (int)g_ev.size() - 1;
 }
 }  // namespace
 
@@ -53,31 +61,38 @@ void prof_enable(bool on) { g_prof = on; }
 bool prof_enabled() { return g_prof; }
 void prof_begin(hipStream_t st) {
   if (!g_prof) return;
-  g_open = take_event();
-  if (hipEventRecord(g_open, st) != hipSuccess) throw Error(TT_EDEVICE, "hipEventRecord failed");
+  g_open = g_last = record_event(st);
+}
+void prof_mark(hipStream_t st, int kind, double flops, double bytes) {
+  if (!g_prof || g_open < 0) return;
+  int e = record_event(st);
+  g_recs.push_back({g_last, e, kind, flops, bytes});
+  g_last = e;
 }
 void prof_end(hipStream_t st, int kind, double flops, double bytes) {
-  if (!g_prof || !g_open) return;
-  hipEvent_t b = take_event();
-  if (hipEventRecord(b, st) != hipSuccess) throw Error(TT_EDEVICE, "hipEventRecord failed");
-  g_recs.push_back({g_open, b, kind, flops, bytes});
-  g_open = nullptr;
+  if (!g_prof || g_open < 0) return;
+  int e = (g_last != g_open) ? g_last : record_event(st);
+  g_recs.push_back({g_open, e, kind, flops, bytes});
+  g_open = g_last = -1;
 }
 void prof_read(double out[PROF_KINDS][4]) {
   for (int k = 0; k < PROF_KINDS; ++k)
     for (int j = 0; j < 4; ++j) out[k][j] = 0.0;
+  if (!g_ev.empty() && hipEventSynchronize(g_ev.back()) != hipSuccess)
+    throw Error(TT_EDEVICE, "hipEventSynchronize failed");
   for (auto& r : g_recs) {
-    if (hipEventSynchronize(r.b) != hipSuccess) throw Error(TT_EDEVICE, "hipEventSynchronize failed");
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw Error(TT_EDEVICE, "hipEventElapsedTime failed");
+    if (hipEventElapsedTime(&ms, g_ev[r.a], g_ev[r.b]) != hipSuccess)
+      throw Error(TT_EDEVICE, "hipEventElapsedTime failed");
     out[r.kind][0] += ms;
     out[r.kind][1] += r.flops;
     out[r.kind][2] += r.bytes;
     out[r.kind][3] += 1;
-    g_pool.push_back(r.a);
-    g_pool.push_back(r.b);
   }
   g_recs.clear();
+  g_pool.insert(g_pool.end(), g_ev.begin(), g_ev.end());
+  g_ev.clear();
+  g_open = g_last = -1;
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -444,6 +459,7 @@ void launch_cfg(const GemmPlan& p, const long long* d_tabs, Slots s, double* pws
   hipLaunchKernelGGL((k_gemm<CFG, PREC>), dim3(n), dim3(256), smem, st, p.d_probs, p.d_tiles, p.cfg_off[CFG], d_tabs, s,
                      pws);
   HIP_CHECK_LAUNCH();
+  prof_mark(st, PROF_GEMM_CFG0 + CFG, p.cfg_flops[CFG], p.cfg_bytes[CFG]);
 }
 
 template <int PREC>
@@ -469,6 +485,7 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precis
     hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)p.splits.size()), dim3(256), 0, st, p.d_probs, p.d_splits,
                        d_tabs, s, pws);
     HIP_CHECK_LAUNCH();
+    prof_mark(st, PROF_GEMM_REDUCE, 0.0, p.red_bytes);
   }
   prof_end(st, p.tag, p.flops, p.bytes);
 }

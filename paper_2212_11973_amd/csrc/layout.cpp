@@ -131,6 +131,8 @@ void tile_plan(GemmPlan& p) {
   p.splits.clear();
   p.pws_size = 0;
   p.smem_bytes = 0;
+  p.red_bytes = 0;
+  for (int c = 0; c < kGemmCfgs; ++c) p.cfg_flops[c] = p.cfg_bytes[c] = 0;
   // K splitting only pays when the launch has too few tiles to fill the GPU
   long long tiles0 = 0;
   for (auto& g : p.probs) {
@@ -147,6 +149,9 @@ void tile_plan(GemmPlan& p) {
     if (nk < 1) nk = 1;
     if (nk > kMaxKSplit) nk = kMaxKSplit;
     p.smem_bytes = std::max(p.smem_bytes, gemm_smem_bytes(cfg));
+    p.cfg_flops[cfg] += 2.0 * g.M * g.N * g.K;
+    p.cfg_bytes[cfg] += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+    if (nk > 1) p.red_bytes += 8.0 * ((double)nk * tm * tn * BM * BN + (double)g.M * g.N);
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
         long long pw = -1;

@@ -32,9 +32,18 @@ struct GemmProb {
 // pw + ks*BM*BN, and a reduce pass adds the slices in order (deterministic).
 struct GemmTile { int prob, tm, tn, cfg, ks, nk, sidx, pad; long long pw; };
 struct GemmSplit { int prob, tm, tn, cfg, nk, pad; long long pw; };
-constexpr int kKSlice = 128;      // K per slice when a problem is split
-constexpr int kMaxKSplit = 8;
-constexpr long long kSplitBelowTiles = 2048;   // split only launches with fewer tiles
+#ifndef TT_KSLICE
+#define TT_KSLICE 128
+#endif
+#ifndef TT_MAX_KSPLIT
+#define TT_MAX_KSPLIT 8
+#endif
+#ifndef TT_SPLIT_BELOW_TILES
+#define TT_SPLIT_BELOW_TILES 2048
+#endif
+constexpr int kKSlice = TT_KSLICE;          // K per slice when a problem is split
+constexpr int kMaxKSplit = TT_MAX_KSPLIT;
+constexpr long long kSplitBelowTiles = TT_SPLIT_BELOW_TILES;   // split only launches with fewer tiles
 constexpr int kGemmCfgs = 5;
 constexpr int kGemmBM[kGemmCfgs] = {64, 128, 256, 32, 32};
 constexpr int kGemmBN[kGemmCfgs] = {64, 32, 16, 128, 32};
@@ -76,6 +85,10 @@ struct GemmPlan {
   int cfg_off[kGemmCfgs + 1] = {0, 0, 0, 0, 0, 0};   // tiles are sorted by shape
   long long pws_size = 0;   // doubles of partial tiles
   int smem_bytes = 0;       // LDS of the largest tile shape in the plan
+  // per tile shape: algorithmic flops and bytes of the problems given that shape
+  double cfg_flops[kGemmCfgs] = {0, 0, 0, 0, 0};
+  double cfg_bytes[kGemmCfgs] = {0, 0, 0, 0, 0};
+  double red_bytes = 0;     // the K-slice reduce: partials read once, C written once
 };
 struct WPlan {
   std::vector<WTask> tasks;
