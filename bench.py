@@ -30,7 +30,7 @@ SHAPES = ("64x64", "128x32", "256x16", "32x128", "32x32")
 def kernel_name(kind, prec):
     if kind.startswith("k_gemm_") and kind != "k_gemm_reduce":
         return "tt::k_gemm<%d, %d>" % (SHAPES.index(kind[len("k_gemm_"):]), prec)
-    return {"k_gemm_reduce": "tt::k_gemm_reduce", "wstage": "tt::k_wstage",
+    return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm<%d>" % prec, "wstage": "tt::k_wstage",
             "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
 
 
@@ -147,18 +147,19 @@ def main():
 
     # dominant single kernel of the timed region and its roofline: the binding
     # roof is the lower of the compute peak and arithmetic intensity x HBM peak
-    singles = [k for k in prof if k.startswith("k_gemm_") or k in ("wstage", "qr")]
+    singles = [k for k in prof if k.startswith("k_gemm_") or k in ("k_wgemm", "wstage", "qr")]
     kind = max(singles, key=lambda k: prof[k]["ms"])
     pk = prof[kind]
     sec = pk["ms"] * 1e-3
-    if kind.startswith("k_gemm_") and kind != "k_gemm_reduce":
+    is_mfma = (kind.startswith("k_gemm_") and kind != "k_gemm_reduce") or kind == "k_wgemm"
+    if is_mfma:
         pname = "fp64" if args.precision == "fp64" else ("fp32" if args.precision == "fp32" else "bf16")
         peak_f = PEAK[pname]
     else:
         peak_f = PEAK_FP64_VALU
     ai = pk["flops"] / max(pk["bytes"], 1.0)
     if pk["flops"] > 0 and peak_f <= ai * PEAK_HBM_GBS / 1e3:
-        roof = dict(bound="mfma" if kind.startswith("k_gemm_") else "alu", unit="TFLOP/s", peak=peak_f,
+        roof = dict(bound="mfma" if is_mfma else "alu", unit="TFLOP/s", peak=peak_f,
                     achieved=pk["flops"] / sec / 1e12)
     else:
         roof = dict(bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS, achieved=pk["bytes"] / sec / 1e9)

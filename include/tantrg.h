@@ -175,8 +175,8 @@ int tt_heff_last_timing(double* host_ms4);
 /* Opt-in kernel timing: when on, every launch of the grouped GEMM, the MPO
  * (W) stage and the QR kernels is bracketed by HIP events on its stream, and
  * inside a grouped GEMM every kernel dispatch is timed on its own.
- * tt_profile_read synchronises those events and fills host_out64 with
- * {ms, flops, bytes, launches} for sixteen kinds accumulated since the
+ * tt_profile_read synchronises those events and fills host_out68 with
+ * {ms, flops, bytes, launches} for seventeen kinds accumulated since the
  * previous read, then resets:
  *   0-7   the grouped GEMM by contraction (all its dispatches together):
  *         L.A, .R, left environment, right environment (R.A), right
@@ -184,12 +184,14 @@ int tt_heff_last_timing(double* host_ms4);
  *   8, 9  the sparse W stage and the QR;
  *   10-14 the GEMM kernel of each tile shape (64x64, 128x32, 256x16, 32x128,
  *         32x32), one record per dispatch;
- *   15    the K-slice reduce kernel, one record per dispatch.
+ *   15    the K-slice reduce kernel, one record per dispatch;
+ *   16    the wave GEMM kernel (small and skinny problems), one record per
+ *         dispatch.
  * Flops and bytes are algorithmic (sum of 2mnk; every operand element read
  * once, every output written once); for the reduce, the partial tiles read
  * and the outputs written. */
 int tt_profile_enable(int on);
-int tt_profile_read(double* host_out64);
+int tt_profile_read(double* host_out68);
 
 /* Host-only: the sectors bond k would get for this model and options (same
  * calling convention as tt_state_bond_sectors).  No GPU needed. */

@@ -71,11 +71,12 @@ void check_device() {
     throw Error(TT_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
 }
 
-void upload_plan(GemmPlan& p, hipStream_t st) {
-  tile_plan(p);
+void upload_plan(GemmPlan& p, const std::vector<long long>* tabs, hipStream_t st) {
+  tile_plan(p, tabs);
   p.d_probs = upload(p.probs, st);
   p.d_tiles = upload(p.tiles, st);
   p.d_splits = upload(p.splits, st);
+  p.d_jobs = upload(p.jobs, st);
 }
 void upload_plan(WPlan& p, hipStream_t st) {
   p.ntasks = (int)p.tasks.size();
@@ -100,8 +101,8 @@ void upload_plan(QRPlan& p, hipStream_t st) {
   p.d_wide = upload(p.wide, st);
 }
 void free_plan(GemmPlan& p) {
-  dfree(p.d_probs); dfree(p.d_tiles); dfree(p.d_splits);
-  p.d_probs = nullptr; p.d_tiles = nullptr; p.d_splits = nullptr;
+  dfree(p.d_probs); dfree(p.d_tiles); dfree(p.d_splits); dfree(p.d_jobs);
+  p.d_probs = nullptr; p.d_tiles = nullptr; p.d_splits = nullptr; p.d_jobs = nullptr;
 }
 void free_plan(WPlan& p) { dfree(p.d_tasks); dfree(p.d_terms); p.d_tasks = nullptr; p.d_terms = nullptr; }
 void free_plan(QRPlan& p) {
@@ -330,6 +331,12 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   s.plans.clear();
   for (int k = 0; k < N; ++k)
     s.plans.push_back(build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, s.qH[k], s.qH[k + 1], s.Wenv[k], s.tabs));
+  // the wave GEMM serves FP64 and FP32 launches; the absorb step always runs in FP64
+  const bool wave = s.opts.precision == TT_FP64 || s.opts.precision == TT_FP32;
+  for (auto& P : s.plans) {
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = wave;
+    P.absL.wave_ok = P.absR.wave_ok = true;
+  }
 }
 
 void alloc_state(tt_state& s) {
@@ -338,9 +345,10 @@ void alloc_state(tt_state& s) {
   s.tabs.dev = upload(s.tabs.host, st);
   long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, qw = 0;
   for (auto& P : s.plans) {
-    upload_plan(P.s1, st); upload_plan(P.s3, st); upload_plan(P.el, st);
-    upload_plan(P.r1, st); upload_plan(P.r3, st); upload_plan(P.absL, st); upload_plan(P.absR, st);
-    upload_plan(P.b1, st); upload_plan(P.b2, st);
+    const std::vector<long long>* T = &s.tabs.host;
+    upload_plan(P.s1, T, st); upload_plan(P.s3, T, st); upload_plan(P.el, T, st);
+    upload_plan(P.r1, T, st); upload_plan(P.r3, T, st); upload_plan(P.absL, T, st); upload_plan(P.absR, T, st);
+    upload_plan(P.b1, T, st); upload_plan(P.b2, T, st);
     upload_plan(P.w2, st); upload_plan(P.wr, st);
     upload_plan(P.qr, st); upload_plan(P.lq, st);
     t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size);
@@ -591,6 +599,24 @@ long long check_gemm(const GemmPlan& p, const std::vector<long long>& tabs, cons
   for (auto& sp : p.splits)
     if (sp.prob < 0 || sp.prob >= (int)p.probs.size() || sp.pw < 0 ||
         sp.pw + (long long)sp.nk * kGemmBM[sp.cfg] * kGemmBN[sp.cfg] > p.pws_size) ++bad;
+  // wave jobs: four per workgroup; a split block fills its workgroup with parts 0..3
+  if (p.jobs.size() % 4 != 0 || (long long)p.jobs.size() != 4LL * p.wave_blocks) ++bad;
+  for (size_t w = 0; w + 3 < p.jobs.size(); w += 4) {
+    const GemmJob& j0 = p.jobs[w];
+    for (int q = 0; q < 4; ++q) {
+      const GemmJob& j = p.jobs[w + q];
+      if (j.nparts != j0.nparts) ++bad;
+      if (j.prob < 0) { if (j.nparts != 1) ++bad; continue; }
+      if (j.prob >= (int)p.probs.size() || j.shape < 0 || j.shape >= kWaveShapes) { ++bad; continue; }
+      const GemmProb& g = p.probs[j.prob];
+      if (j.tm < 0 || j.tn < 0 || j.tm * kWaveBM[j.shape] >= g.M || j.tn * kWaveBN[j.shape] >= g.N) ++bad;
+      if (j.nparts == 4) {
+        if (j.part != q || j.prob != j0.prob || j.tm != j0.tm || j.tn != j0.tn || j.shape != j0.shape) ++bad;
+      } else if (j.nparts != 1 || j.part != 0) {
+        ++bad;
+      }
+    }
+  }
   return bad;
 }
 
@@ -661,7 +687,7 @@ long long check_all_plans(tt_state& s, std::string& rep) {
   const auto& T = s.tabs.host;
   for (int k = 0; k < N; ++k) {
     SitePlan& P = s.plans[k];
-    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2}) tile_plan(*g);
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2}) tile_plan(*g, &T);
     long long ns = s.site[k].size, el = s.env[k].size, er = s.env[k + 1].size;
     long long s1[kSlots] = {el, ns, t1, 0}, s3[kSlots] = {t2, er, ns, 0}, se[kSlots] = {ns, t2, er, 0};
     long long r1[kSlots] = {er, ns, y, 0}, r3[kSlots] = {ns, z, el, 0};
@@ -769,9 +795,9 @@ void build_heff_cache(int Dl, int Dr, int DH) {
     }
   hipStream_t st = ST();
   c.tabs.dev = upload(c.tabs.host, st);
-  upload_plan(c.plan.s1, st);
-  upload_plan(c.plan.s3, st);
-  upload_plan(c.wg, st);
+  upload_plan(c.plan.s1, &c.tabs.host, st);
+  upload_plan(c.plan.s3, &c.tabs.host, st);
+  upload_plan(c.wg, &c.tabs.host, st);
   if (c.plan.t1_size > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * c.plan.t1_size); c.t1 = c.plan.t1_size; }
   if (c.plan.t2_size > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * c.plan.t2_size); c.t2 = c.plan.t2_size; }
   long long pw = std::max(std::max(c.plan.s1.pws_size, c.plan.s3.pws_size), std::max(c.wg.pws_size, 1LL));
@@ -1120,14 +1146,14 @@ int tt_profile_enable(int on) {
   ABI_END
 }
 
-int tt_profile_read(double* host_out64) {
+int tt_profile_read(double* host_out68) {
   ABI_BEGIN
-  static_assert(PROF_KINDS == 16, "tt_profile_read fills 16 kinds");
-  TT_REQUIRE(host_out64, TT_EINVAL, "null argument");
+  static_assert(PROF_KINDS == 17, "tt_profile_read fills 17 kinds");
+  TT_REQUIRE(host_out68, TT_EINVAL, "null argument");
   double out[PROF_KINDS][4];
   prof_read(out);
   for (int k = 0; k < PROF_KINDS; ++k)
-    for (int j = 0; j < 4; ++j) host_out64[k * 4 + j] = out[k][j];
+    for (int j = 0; j < 4; ++j) host_out68[k * 4 + j] = out[k][j];
   ABI_END
 }
 

@@ -13,10 +13,11 @@ constexpr int kMaxKrylov = 32;
 // Optional timing of the grouped kernels: HIP events on the launch stream.
 // kinds 0..TAG_COUNT-1 are the grouped GEMM contractions by tag, then the W
 // stage and the QR, then the individual GEMM kernels (one kind per tile shape,
-// then the K-slice reduce), each timed per dispatch.
+// then the K-slice reduce, then the wave GEMM), each timed per dispatch.
 enum ProfKind {
   PROF_WSTAGE = TAG_COUNT, PROF_QR = TAG_COUNT + 1, PROF_GEMM_CFG0 = TAG_COUNT + 2,
-  PROF_GEMM_REDUCE = PROF_GEMM_CFG0 + kGemmCfgs, PROF_KINDS = PROF_GEMM_REDUCE + 1
+  PROF_GEMM_REDUCE = PROF_GEMM_CFG0 + kGemmCfgs, PROF_GEMM_WAVE = PROF_GEMM_REDUCE + 1,
+  PROF_KINDS = PROF_GEMM_WAVE + 1
 };
 void prof_enable(bool on);
 bool prof_enabled();

@@ -5,7 +5,13 @@
 //                  MFMA 16x16x4 tiles, one 64x64 output tile per workgroup of
 //                  four 64-wide waves.  Used for every dense contraction of the
 //                  sweep: L.A, .R, the environment updates, the bond apply
-//                  and the absorb step (SM Fig. Lanczos, Fig. optimalB).
+//                  and the absorb step (SM Fig. Lanczos, Fig. optimalB), for
+//                  problems large in all three dimensions.
+//  * k_wgemm     : the same grouped contractions for small, short-K or
+//                  skinny charge blocks (most blocks of a U(1)xU(1) sweep):
+//                  one wave per 64x16 / 32x32 / 16x64 output block, operands
+//                  straight from global memory, optional four-way K split
+//                  inside the workgroup; one launch per contraction.
 //  * k_wstage    : the contraction with the Hamiltonian MPO tensor W, which is
 //                  sparse (a few nonzero 4x4 operators per bond pair); a
 //                  bandwidth-bound weighted sum of strided blocks.
@@ -404,6 +410,166 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict_
   }
 }
 
+// ------------------------------------------------------------------ wave GEMM
+// Workgroup b of n: consecutive workgroups go round-robin to the eight XCDs, so
+// hand each XCD a contiguous range of work items (neighbouring blocks of one
+// problem then share that XCD's L2).  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, slot = b >> 3;
+  return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+// One wave's (16 FM) x (16 FN) output block from global memory, f64 MFMA
+// 16x16x4 (FP32 precision: f32 MFMA within each 16-deep K chunk, FP64 across
+// chunks).  In a chunk, lane (r, g) = (lane % 16, lane / 16) supplies row r /
+// column r at k = 4g + s on MFMA step s, so the chunk's 16 products are taken
+// in a fixed permuted order and every lane reads four consecutive k.  The
+// chunks of the job (part, part + nparts, ...) are loaded one chunk ahead of
+// the MFMAs.  With nparts = 4 the four waves of the workgroup hold the four
+// K parts of one block and wave 0 adds them in part order.
+template <int FM, int FN, int PREC>
+__device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
+                                          const Slots& slots, double* red) {
+  constexpr bool F64 = (PREC == TT_FP64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  // operand bases are wave-uniform (scalar registers); element offsets from
+  // them fit 32 bits (checked when the plan is built)
+  const double* __restrict__ A = slots.p[P.ia] + P.offA;
+  const double* __restrict__ B = slots.p[P.ib] + P.offB;
+  double* C = slots.p[P.ic] + P.offC;
+  const int m0 = J.tm * 16 * FM, n0 = J.tn * 16 * FN;
+  unsigned ra[FM], cb[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int m = m0 + 16 * i + r16;
+    ra[i] = m < P.M ? (unsigned)idx_map(tabs, P.tam, P.sam, m) : 0xffffffffu;
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int n = n0 + 16 * j + r16;
+    cb[j] = n < P.N ? (unsigned)idx_map(tabs, P.tbn, P.sbn, n) : 0xffffffffu;
+  }
+  const int nch = (P.K + 15) >> 4;
+  double4_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  double a[FM][4], b[FN][4];
+  auto load = [&](int c, double (&xa)[FM][4], double (&xb)[FN][4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = c * 16 + 4 * g + s;
+      const bool ok = k < P.K;
+      const unsigned ka = ok ? (unsigned)idx_map(tabs, P.tak, P.sak, k) : 0u;
+      const unsigned kb = ok ? (unsigned)idx_map(tabs, P.tbk, P.sbk, k) : 0u;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) xa[i][s] = (ok && ra[i] != 0xffffffffu) ? A[ra[i] + ka] : 0.0;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) xb[j][s] = (ok && cb[j] != 0xffffffffu) ? B[kb + cb[j]] : 0.0;
+    }
+  };
+  int c = J.part;
+  if (c < nch) load(c, a, b);
+  for (; c < nch; c += J.nparts) {
+    double an[FM][4], bn[FN][4];
+    const bool more = c + J.nparts < nch;
+    if (more) load(c + J.nparts, an, bn);
+    if (F64) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+    } else {
+      float4_t t[FM][FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) t[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            t[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i][s], (float)b[j][s], t[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)t[i][j][v];
+    }
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i][s] = an[i][s];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j][s] = bn[j][s];
+      }
+    }
+  }
+  if (J.nparts > 1) {   // uniform over the workgroup: its four jobs are the parts of one block
+    if (wave > 0) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[(wave - 1) * 1024 + ((i * FN + j) * 4 + v) * 64 + lane] = acc[i][j][v];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int e = ((i * FN + j) * 4 + v) * 64 + lane;
+          acc[i][j][v] = ((acc[i][j][v] + red[e]) + red[1024 + e]) + red[2048 + e];
+        }
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // accumulator row inside a 16x16 block: f64 MFMA lane/16 + 4v, f32 MFMA 4 (lane/16) + v
+      const int m = m0 + 16 * i + (F64 ? g + 4 * v : 4 * g + v);
+      if (m >= P.M) continue;
+      const unsigned rowc = (unsigned)idx_map(tabs, P.tcm, P.scm, m);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + 16 * j + r16;
+        if (n >= P.N) continue;
+        double val = P.alpha * acc[i][j][v];
+        if (P.beta != 0.0) val += P.beta * C[rowc + n];
+        C[rowc + n] = val;
+      }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
+                                               int nblocks, const long long* __restrict__ tabs, Slots slots) {
+  __shared__ double red[3 * 1024];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  // the job index is wave-uniform: job and problem descriptors load into scalar registers
+  const int jidx = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+  const GemmJob J = jobs[jidx];
+  if (J.prob < 0) return;   // an unused slot: only in workgroups of unsplit jobs, which never synchronise
+  const GemmProb P = probs[J.prob];
+  switch (J.shape) {
+    case 0: wave_tile<4, 1, PREC>(P, J, tabs, slots, red); break;
+    case 1: wave_tile<2, 2, PREC>(P, J, tabs, slots, red); break;
+    default: wave_tile<1, 4, PREC>(P, J, tabs, slots, red); break;
+  }
+}
+
 // tile shapes: 0 64x64, 1 128x32, 2 256x16, 3 32x128, 4 32x32 (split K over the
 // waves; with BF16 the four waves take one 16x16 block each instead)
 template <int CFG, int PREC> struct CfgT;
@@ -472,8 +638,20 @@ void launch_prec(const GemmPlan& p, const long long* d_tabs, Slots s, double* pw
 }
 
 void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, double* pws, hipStream_t st) {
-  if (p.ntiles == 0) return;
+  if (p.ntiles == 0 && p.wave_blocks == 0) return;
   prof_begin(st);
+  if (p.wave_blocks > 0) {
+    if (precision == TT_FP64)
+      hipLaunchKernelGGL(k_wgemm<TT_FP64>, dim3(p.wave_blocks), dim3(256), 0, st, p.d_probs, p.d_jobs, p.wave_blocks,
+                         d_tabs, s);
+    else if (precision == TT_FP32)
+      hipLaunchKernelGGL(k_wgemm<TT_FP32>, dim3(p.wave_blocks), dim3(256), 0, st, p.d_probs, p.d_jobs, p.wave_blocks,
+                         d_tabs, s);
+    else
+      throw Error(TT_EINVAL, "the wave GEMM runs FP64 or FP32 only: plan built for another precision");
+    HIP_CHECK_LAUNCH();
+    prof_mark(st, PROF_GEMM_WAVE, p.wave_flops, p.wave_bytes);
+  }
   switch (precision) {
     case TT_FP64: launch_prec<TT_FP64>(p, d_tabs, s, pws, st); break;
     case TT_FP32: launch_prec<TT_FP32>(p, d_tabs, s, pws, st); break;

@@ -126,22 +126,80 @@ int gemm_cfg_for(int M, int N) {
   return 0;
 }
 
-void tile_plan(GemmPlan& p) {
+static int wave_shape_for(int M, int N) {
+  if (N <= 16) return 0;
+  if (M <= 16) return 2;
+  return 1;
+}
+
+// largest element offset of an index map over [0, n) (tables hold non-negative offsets)
+static long long map_max(const std::vector<long long>* T, long long tab, long long stride, int n) {
+  if (n <= 0) return 0;
+  if (tab < 0) return (long long)(n - 1) * stride;
+  long long m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, (*T)[tab + i]);
+  return m;
+}
+
+void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
   p.tiles.clear();
   p.splits.clear();
+  p.jobs.clear();
   p.pws_size = 0;
   p.smem_bytes = 0;
   p.red_bytes = 0;
+  p.wave_blocks = 0;
+  p.wave_flops = p.wave_bytes = 0;
   for (int c = 0; c < kGemmCfgs; ++c) p.cfg_flops[c] = p.cfg_bytes[c] = 0;
-  // K splitting only pays when the launch has too few tiles to fill the GPU
+  // the wave kernel addresses operands with 32-bit byte offsets from each operand base
+  const long long lim = 1LL << 29;
+  std::vector<char> wave(p.probs.size(), 0);
+  for (size_t i = 0; i < p.probs.size(); ++i) {
+    const GemmProb& g = p.probs[i];
+    if (!p.wave_ok || (g.M >= kLdsMinMN && g.N >= kLdsMinMN && g.K >= kLdsMinK)) continue;
+    TT_REQUIRE(tabs != nullptr, TT_EINVAL, "plan: wave GEMM planning needs the index tables");
+    const long long a = map_max(tabs, g.tam, g.sam, g.M) + map_max(tabs, g.tak, g.sak, g.K);
+    const long long b = map_max(tabs, g.tbk, g.sbk, g.K) + map_max(tabs, g.tbn, g.sbn, g.N);
+    const long long c = map_max(tabs, g.tcm, g.scm, g.M) + g.N;
+    wave[i] = (a < lim && b < lim && c < lim) ? 1 : 0;
+  }
+  auto use_wave = [&](const GemmProb& g) { return wave[&g - p.probs.data()] != 0; };
+  // wave jobs: split blocks (four K parts in one workgroup) first, then
+  // unsplit blocks four to a workgroup
+  std::vector<GemmJob> single;
+  for (int i = 0; i < (int)p.probs.size(); ++i) {
+    const GemmProb& g = p.probs[i];
+    if (!use_wave(g) || g.M == 0 || g.N == 0) continue;
+    const int sh = wave_shape_for(g.M, g.N);
+    const int tm = (g.M + kWaveBM[sh] - 1) / kWaveBM[sh], tn = (g.N + kWaveBN[sh] - 1) / kWaveBN[sh];
+    const bool split = (g.K + 15) / 16 >= 8;   // every part then takes at least two 16-deep chunks
+    p.wave_flops += 2.0 * g.M * g.N * g.K;
+    p.wave_bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) {
+        if (split) {
+          for (int q = 0; q < 4; ++q) p.jobs.push_back({i, a, b, sh, q, 4});
+        } else {
+          single.push_back({i, a, b, sh, 0, 1});
+        }
+      }
+  }
+  for (auto& j : single) p.jobs.push_back(j);
+  while (p.jobs.size() % 4) p.jobs.push_back({-1, 0, 0, 0, 0, 1});
+  p.wave_blocks = (int)(p.jobs.size() / 4);
+
+  // LDS-staged tiles for the rest; K splitting only pays when the launch has
+  // too few tiles to fill the GPU
   long long tiles0 = 0;
   for (auto& g : p.probs) {
+    if (use_wave(g)) continue;
     int cfg = gemm_cfg_for(g.M, g.N);
     tiles0 += (long long)((g.M + kGemmBM[cfg] - 1) / kGemmBM[cfg]) * ((g.N + kGemmBN[cfg] - 1) / kGemmBN[cfg]);
   }
   const bool may_split = tiles0 < kSplitBelowTiles;
   for (int i = 0; i < (int)p.probs.size(); ++i) {
     const GemmProb& g = p.probs[i];
+    if (use_wave(g)) continue;
     int cfg = gemm_cfg_for(g.M, g.N);
     int BM = kGemmBM[cfg], BN = kGemmBN[cfg];
     int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;

@@ -48,6 +48,27 @@ constexpr int kGemmCfgs = 5;
 constexpr int kGemmBM[kGemmCfgs] = {64, 128, 256, 32, 32};
 constexpr int kGemmBN[kGemmCfgs] = {64, 32, 16, 128, 32};
 
+// Wave GEMM for small, short-K or skinny problems: one 64-wide wave computes a
+// 64x16, 32x32 or 16x64 output block (shape 0, 1, 2) straight from global
+// memory.  A job is one wave's share: a whole block (nparts = 1), or part
+// `part` of the nparts = 4 interleaved K parts of a block, whose partial sums
+// the four waves of one workgroup add in LDS.  Jobs are grouped four per
+// workgroup; the four jobs of a split block fill one workgroup, and unused
+// slots of a workgroup have prob = -1.
+struct GemmJob { int prob, tm, tn, shape, part, nparts; };
+constexpr int kWaveShapes = 3;
+constexpr int kWaveBM[kWaveShapes] = {64, 32, 16};
+constexpr int kWaveBN[kWaveShapes] = {16, 32, 64};
+// problems at least this large in M, N and K use the LDS-staged tile kernel
+#ifndef TT_LDS_MIN_MN
+#define TT_LDS_MIN_MN 128
+#endif
+#ifndef TT_LDS_MIN_K
+#define TT_LDS_MIN_K 48
+#endif
+constexpr int kLdsMinMN = TT_LDS_MIN_MN;
+constexpr int kLdsMinK = TT_LDS_MIN_K;
+
 // W stage: dst(i,j) = sum_t w_t src_t(i,j) for i < ni, j < nj, with
 // dst(i,j) = out[dst + i*dsi + j*dsj] and src_t(i,j) = in[src + i*ssi + j*ssj].
 struct WTask { long long dst, dsi, dsj; int ni, nj, t0, nt; };
@@ -89,6 +110,12 @@ struct GemmPlan {
   double cfg_flops[kGemmCfgs] = {0, 0, 0, 0, 0};
   double cfg_bytes[kGemmCfgs] = {0, 0, 0, 0, 0};
   double red_bytes = 0;     // the K-slice reduce: partials read once, C written once
+  // wave-GEMM jobs (only when wave_ok: FP64 / FP32 launches)
+  bool wave_ok = false;
+  std::vector<GemmJob> jobs;
+  GemmJob* d_jobs = nullptr;
+  int wave_blocks = 0;
+  double wave_flops = 0, wave_bytes = 0;
 };
 struct WPlan {
   std::vector<WTask> tasks;
@@ -196,6 +223,6 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
 // tile the problems of a plan (shape per problem)
 int gemm_cfg_for(int M, int N);
 int gemm_smem_bytes(int cfg);     // LDS bytes of one tile of shape cfg
-void tile_plan(GemmPlan& p);
+void tile_plan(GemmPlan& p, const std::vector<long long>* tabs);   // tabs: host copy of the index tables
 
 }  // namespace tt

@@ -224,13 +224,13 @@ def tt_profile_enable(on):
 PROFILE_KINDS = ("gemm_LA", "gemm_R", "gemm_envL", "gemm_envR1", "gemm_envR3", "gemm_bond", "gemm_absorb",
                  "gemm_Wdense", "wstage", "qr",
                  "k_gemm_64x64", "k_gemm_128x32", "k_gemm_256x16", "k_gemm_32x128", "k_gemm_32x32",
-                 "k_gemm_reduce")
+                 "k_gemm_reduce", "k_wgemm")
 
 
 def tt_profile_read():
     """{kind: dict(ms, flops, bytes, launches)} since the last read; 'gemm' sums the
     grouped-GEMM kinds (gemm_*), the k_gemm_* kinds time single kernel dispatches."""
-    buf = (C.c_double * 64)()
+    buf = (C.c_double * 68)()
     _check(lib().tt_profile_read(buf))
     out = {}
     for i, k in enumerate(PROFILE_KINDS):
