@@ -7,7 +7,7 @@
 namespace tt {
 
 // reduction geometry: fixed block count so that every sum has a fixed order
-constexpr int kRedBlocks = 256;
+constexpr int kRedBlocks = 1024;
 constexpr int kMaxKrylov = 32;
 
 // Optional timing of the grouped kernels: HIP events on the launch stream.
@@ -43,8 +43,6 @@ void launch_mdot(const double* Q, long long ld, int nv, const double* y, long lo
                  double* part, hipStream_t st);
 void launch_lz_start(const double* v, double* q0, long long n, const double* part, double* scal,
                      hipStream_t st);
-void launch_lz_sub(double* w, const double* Q, long long ld, int nv, const double* part, int nparts,
-                   long long n, double* alpha_out, double* hn_out, hipStream_t st);
 void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
                        long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st);
 void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
@@ -55,8 +53,6 @@ void launch_lz_next(const double* w, double* qn, long long n, const double* part
                     const double* hn, double tol, hipStream_t st);
 void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t,
                       double tol, const double* scal, double* coeff, double* errmax, hipStream_t st);
-void launch_lz_combine(const double* Q, long long ld, int K, const double* coeff, double* out,
-                       long long n, hipStream_t st);
 void launch_normalize_log(double* v, long long n, const double* part, double* lambda, hipStream_t st);
 void launch_copy(double* dst, const double* src, long long n, hipStream_t st);
 void launch_fill(double* dst, double val, long long n, hipStream_t st);

@@ -1030,22 +1030,54 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, d
 }
 
 // ------------------------------------------------------------------ Lanczos
-// part[b*(nv+self) + v] = sum over block b's chunk of Q_v[i] * y[i]; last entry y.y if with_self
+// Sums of the nv per-thread accumulators over the block in a fixed order:
+// wave sums, then the four waves in order; out[v] written by thread v.
+template <int MAXV>
+__device__ __forceinline__ void block_sums(const double (&acc)[MAXV], int nv, double* red, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    if (v >= nv) break;
+    const double s = wave_sum(acc[v]);
+    if (lane == 0) red[wave * MAXV + v] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    const int v = threadIdx.x;
+    out[v] = ((red[v] + red[MAXV + v]) + red[2 * MAXV + v]) + red[3 * MAXV + v];
+  }
+}
+
+// contiguous chunk of block b (the same in every Lanczos kernel, so each
+// partial sum covers the same elements in the same order)
+__device__ __forceinline__ void red_chunk(long long n, long long& i0, long long& i1) {
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  i0 = (long long)blockIdx.x * chunk;
+  i1 = i0 + chunk < n ? i0 + chunk : n;
+}
+
+// part[b*(nv+self) + v] = sum over block b's chunk of Q_v[i] * y[i]; last entry y.y if with_self.
+// One pass: y and every Q_v are read once.
+template <int MAXV>
 __global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ Q, long long ld, int nv,
                                               const double* __restrict__ y, long long n, int with_self,
                                               double* __restrict__ part) {
-  __shared__ double red[8];
-  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
-  const long long i0 = (long long)blockIdx.x * chunk;
-  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
-  const int nout = nv + with_self;
-  for (int v = 0; v < nout; ++v) {
-    const double* x = (v < nv) ? Q + (long long)v * ld : y;
-    double s = 0.0;
-    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += x[i] * y[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + v] = s;
+  __shared__ double red[4 * MAXV];
+  long long i0, i1;
+  red_chunk(n, i0, i1);
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double yi = y[i];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      if (v < nv) acc[v] += Q[(long long)v * ld + i] * yi;
+      else if (v == nv && with_self) acc[v] += yi * yi;
+    }
   }
+  const int nout = nv + with_self;
+  block_sums<MAXV>(acc, nout, red, part + (long long)blockIdx.x * nout);
 }
 
 __device__ double sum_parts(const double* part, int nparts, int stride, int v) {
@@ -1054,93 +1086,101 @@ __device__ double sum_parts(const double* part, int nparts, int stride, int v) {
   return s;
 }
 
+// c[v] = sum over the kRedBlocks partials part[b*stride + v], v < nv, in a fixed
+// order (lane-strided sums, then the wave sum); one wave per value, written to
+// LDS by its lane 0.  The caller synchronises before reading c.
+__device__ __forceinline__ void gather_parts(const double* __restrict__ part, int stride, int nv, double* c) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int v = wave; v < nv; v += nw) {
+    double s = 0.0;
+    for (int b = lane; b < kRedBlocks; b += 64) s += part[(long long)b * stride + v];
+    s = wave_sum(s);
+    if (lane == 0) c[v] = s;
+  }
+}
+
 // q0 = v / ||v||; scal[0] = ||v||
 __global__ void k_lz_start(const double* __restrict__ v, double* __restrict__ q0, long long n,
                            const double* __restrict__ part, double* scal) {
   __shared__ double s_nv;
-  if (threadIdx.x == 0) s_nv = sqrt(sum_parts(part, kRedBlocks, 1, 0));
+  gather_parts(part, 1, 1, &s_nv);
   __syncthreads();
-  const double nv = s_nv;
+  const double nv = sqrt(s_nv);
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[0] = nv;
   const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     q0[i] = v[i] * inv;
 }
 
-// w -= sum_v c_v Q_v with c_v = sum of partials; optionally store alpha = c_{nv-1}, hn = sqrt(self)
-__global__ void k_lz_sub(double* __restrict__ w, const double* __restrict__ Q, long long ld, int nv,
-                         const double* __restrict__ part, int stride, long long n, double* alpha_out,
-                         double* hn_out) {
-  __shared__ double c[kMaxKrylov + 1];
-  if (threadIdx.x < nv) c[threadIdx.x] = sum_parts(part, kRedBlocks, stride, threadIdx.x);
-  if (threadIdx.x == 0 && stride > nv) c[nv] = sum_parts(part, kRedBlocks, stride, nv);
-  __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (alpha_out) *alpha_out = c[nv - 1];
-    if (hn_out) *hn_out = sqrt(c[nv]);
-  }
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double s = w[i];
-    for (int v = 0; v < nv; ++v) s -= c[v] * Q[(long long)v * ld + i];
-    w[i] = s;
-  }
-}
-
-// Fused Gram-Schmidt passes.  Both kernels run on kRedBlocks blocks with the
-// same contiguous chunks as k_mdot, so every partial sum has a fixed order.
-// k_lz_sub_dot: w -= sum_v c_v Q_v with c from the partials of the previous
-// pass (alpha, ||H q|| stored by block 0), then partial dots Q_v . w of the
-// updated chunk (next pass).
+// Fused Gram-Schmidt passes on the same chunks as k_mdot, so every partial
+// sum has a fixed order.  k_lz_sub_dot: w -= sum_v c_v Q_v with c from the
+// partials of the previous pass (alpha, ||H q|| stored by block 0), and in the
+// same pass the partial dots Q_v . w of the updated chunk (next pass).
+template <int MAXV>
 __global__ __launch_bounds__(256) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q, long long ld,
                                                     int nv, const double* __restrict__ part_in, int stride_in, long long n,
                                                     double* alpha_out, double* hn_out, double* __restrict__ part_out) {
   __shared__ double c[kMaxKrylov + 1];
-  __shared__ double red[8];
-  if (threadIdx.x < nv) c[threadIdx.x] = sum_parts(part_in, kRedBlocks, stride_in, threadIdx.x);
-  if (threadIdx.x == 0 && stride_in > nv) c[nv] = sum_parts(part_in, kRedBlocks, stride_in, nv);
+  __shared__ double red[4 * MAXV];
+  gather_parts(part_in, stride_in, stride_in > nv ? nv + 1 : nv, c);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (alpha_out) *alpha_out = c[nv - 1];
     if (hn_out) *hn_out = sqrt(c[nv]);
   }
-  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
-  const long long i0 = (long long)blockIdx.x * chunk;
-  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
+  double cr[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) cr[v] = v < nv ? c[v] : 0.0;
+  long long i0, i1;
+  red_chunk(n, i0, i1);
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double q[MAXV];
     double s = w[i];
-    for (int v = 0; v < nv; ++v) s -= c[v] * Q[(long long)v * ld + i];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      if (v >= nv) break;
+      q[v] = Q[(long long)v * ld + i];
+      s -= cr[v] * q[v];
+    }
     w[i] = s;
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      if (v >= nv) break;
+      acc[v] += q[v] * s;
+    }
   }
-  __syncthreads();
-  for (int v = 0; v < nv; ++v) {
-    const double* x = Q + (long long)v * ld;
-    double s = 0.0;
-    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += x[i] * w[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part_out[(long long)blockIdx.x * nv + v] = s;
-  }
+  block_sums<MAXV>(acc, nv, red, part_out + (long long)blockIdx.x * nv);
 }
 
 // k_lz_sub_norm: second pass w -= sum_v c_v Q_v, then partial w . w
+template <int MAXV>
 __global__ __launch_bounds__(256) void k_lz_sub_norm(double* __restrict__ w, const double* __restrict__ Q, long long ld,
                                                      int nv, const double* __restrict__ part_in, long long n,
                                                      double* __restrict__ part_out) {
   __shared__ double c[kMaxKrylov + 1];
-  __shared__ double red[8];
-  if (threadIdx.x < nv) c[threadIdx.x] = sum_parts(part_in, kRedBlocks, nv, threadIdx.x);
+  __shared__ double red[4];
+  gather_parts(part_in, nv, nv, c);
   __syncthreads();
-  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
-  const long long i0 = (long long)blockIdx.x * chunk;
-  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
-  double ss = 0.0;
+  double cr[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) cr[v] = v < nv ? c[v] : 0.0;
+  long long i0, i1;
+  red_chunk(n, i0, i1);
+  double acc[1] = {0.0};
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     double s = w[i];
-    for (int v = 0; v < nv; ++v) s -= c[v] * Q[(long long)v * ld + i];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      if (v >= nv) break;
+      s -= cr[v] * Q[(long long)v * ld + i];
+    }
     w[i] = s;
-    ss += s * s;
+    acc[0] += s * s;
   }
-  ss = block_sum(ss, red);
-  if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
+  block_sums<1>(acc, 1, red, part_out + blockIdx.x);
 }
 
 // out = sum_v coeff_v Q_v and the partial out . out of each chunk
@@ -1169,9 +1209,9 @@ __global__ __launch_bounds__(256) void k_lz_combine_norm(const double* __restric
 __global__ void k_lz_next(const double* __restrict__ w, double* __restrict__ qn, long long n,
                           const double* __restrict__ part, double* beta_out, const double* hn, double tol) {
   __shared__ double s_b;
-  if (threadIdx.x == 0) s_b = sqrt(sum_parts(part, kRedBlocks, 1, 0));
+  gather_parts(part, 1, 1, &s_b);
   __syncthreads();
-  const double b = s_b;
+  const double b = sqrt(s_b);
   if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = b;
   if (!qn) return;
   const bool brk = !(b > tol * (*hn)) || b == 0.0;
@@ -1254,24 +1294,12 @@ __global__ __launch_bounds__(256) void k_lz_coeffs(const double* alpha, const do
   }
 }
 
-__global__ void k_lz_combine(const double* __restrict__ Q, long long ld, int K, const double* __restrict__ coeff,
-                             double* __restrict__ out, long long n) {
-  __shared__ double c[kMaxKrylov];
-  if (threadIdx.x < K) c[threadIdx.x] = coeff[threadIdx.x];
-  __syncthreads();
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int v = 0; v < K; ++v) s += c[v] * Q[(long long)v * ld + i];
-    out[i] = s;
-  }
-}
-
 // v /= ||v||; lambda += ln ||v||
 __global__ void k_normalize_log(double* __restrict__ v, long long n, const double* __restrict__ part, double* lambda) {
   __shared__ double s_n;
-  if (threadIdx.x == 0) s_n = sqrt(sum_parts(part, kRedBlocks, 1, 0));
+  gather_parts(part, 1, 1, &s_n);
   __syncthreads();
-  const double nv = s_n;
+  const double nv = sqrt(s_n);
   if (blockIdx.x == 0 && threadIdx.x == 0) *lambda += log(nv);
   const double inv = 1.0 / nv;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1297,29 +1325,33 @@ static int grid_for(long long n) {
   return (int)g;
 }
 
+// the Lanczos kernels keep one accumulator per vector in registers: instances
+// for up to 9, 17 and kMaxKrylov + 1 vectors
+#define TT_BY_MAXV(NV, KERNEL, ...)                                                              \
+  do {                                                                                           \
+    if ((NV) <= 9) hipLaunchKernelGGL(KERNEL<9>, __VA_ARGS__);                                   \
+    else if ((NV) <= 17) hipLaunchKernelGGL(KERNEL<17>, __VA_ARGS__);                            \
+    else hipLaunchKernelGGL(KERNEL<kMaxKrylov + 1>, __VA_ARGS__);                                \
+  } while (0)
+
 void launch_mdot(const double* Q, long long ld, int nv, const double* y, long long n, int with_self, double* part,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_mdot, dim3(kRedBlocks), dim3(256), 0, st, Q, ld, nv, y, n, with_self, part);
+  TT_BY_MAXV(nv + with_self, k_mdot, dim3(kRedBlocks), dim3(256), 0, st, Q, ld, nv, y, n, with_self, part);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_start(const double* v, double* q0, long long n, const double* part, double* scal, hipStream_t st) {
   hipLaunchKernelGGL(k_lz_start, dim3(grid_for(n)), dim3(256), 0, st, v, q0, n, part, scal);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_sub(double* w, const double* Q, long long ld, int nv, const double* part, int nparts, long long n,
-                   double* alpha_out, double* hn_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_sub, dim3(grid_for(n)), dim3(256), 0, st, w, Q, ld, nv, part, nparts, n, alpha_out, hn_out);
-  HIP_CHECK_LAUNCH();
-}
 void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
                        long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_sub_dot, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, stride_in, n, alpha_out,
-                     hn_out, part_out);
+  TT_BY_MAXV(nv, k_lz_sub_dot, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, stride_in, n, alpha_out,
+             hn_out, part_out);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
                         double* part_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_sub_norm, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, n, part_out);
+  TT_BY_MAXV(nv, k_lz_sub_norm, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, n, part_out);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
@@ -1335,11 +1367,6 @@ void launch_lz_next(const double* w, double* qn, long long n, const double* part
 void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t, double tol,
                       const double* scal, double* coeff, double* errmax, hipStream_t st) {
   hipLaunchKernelGGL(k_lz_coeffs, dim3(1), dim3(256), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
-  HIP_CHECK_LAUNCH();
-}
-void launch_lz_combine(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_combine, dim3(grid_for(n)), dim3(256), 0, st, Q, ld, K, coeff, out, n);
   HIP_CHECK_LAUNCH();
 }
 void launch_normalize_log(double* v, long long n, const double* part, double* lambda, hipStream_t st) {
