@@ -800,72 +800,100 @@ __global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ task
 }
 
 // ---- LDS-resident Householder QR (column-major W[i + j*m] in LDS)
+// Column c belongs to wave c % nw, which does every update of that column.
+// Rows i > j of a column are always handled by lane (i - j - 1) % 64 of its
+// wave, both when the column is updated and when its reflector is made, so a
+// lane only reads LDS words it wrote itself; values shared across lanes pass
+// through registers (shuffles).  One barrier per step: while applying
+// reflector j, the owner of column j+1 updates that column first and then
+// turns it into reflector j+1 (look-ahead).
+
+// Make the reflector of column j from its current entries (one wave).  alpha:
+// the current diagonal entry, valid in every lane.  On return rows i > j hold
+// v (v_j = 1 implicit), the diagonal holds beta, tau[j] the factor.
+__device__ __forceinline__ void make_reflector(double* W, int m, int j, double alpha, double* tau) {
+  const int lane = threadIdx.x & 63;
+  double* col = W + (long long)j * m;
+  double part = 0.0;
+  for (int i = j + 1 + lane; i < m; i += 64) part += col[i] * col[i];
+  const double xn2 = __shfl(wave_sum(part), 0, 64);
+  double tj = 0.0;
+  if (xn2 > 0.0) {
+    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    tj = (beta - alpha) / beta;
+    const double scal = 1.0 / (alpha - beta);
+    for (int i = j + 1 + lane; i < m; i += 64) col[i] *= scal;
+    if (lane == 0) col[j] = beta;
+  }
+  if (lane == 0) tau[j] = tj;
+}
+
+// Apply reflector j (tau tj, v below the diagonal of column j) to column c
+// (rows >= j); returns the new entry of row j+1 (valid in every lane).
+__device__ __forceinline__ double apply_reflector(double* W, int m, int j, double tj, int c) {
+  const int lane = threadIdx.x & 63;
+  const double* v = W + (long long)j * m;
+  double* col = W + (long long)c * m;
+  double d = 0.0;
+  for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
+  d = __shfl(wave_sum(d), 0, 64) + col[j];
+  const double f = tj * d;
+  double r1 = 0.0;
+  for (int i = j + 1 + lane; i < m; i += 64) {
+    const double x = col[i] - f * v[i];
+    col[i] = x;
+    if (i == j + 1) r1 = x;
+  }
+  if (lane == 0) col[j] -= f;
+  return __shfl(r1, 0, 64);
+}
+
 // On return the upper triangle holds R (diagonal of either sign) and the
 // reflector vectors sit below the diagonal; tau[j] are their factors.
-__device__ void lds_householder(double* W, int m, int n, double* tau, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+__device__ void lds_householder(double* W, int m, int n, double* tau) {
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (wave == 0) make_reflector(W, m, 0, W[0], tau);
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < m; i += blockDim.x) {
-      double x = W[i + j * m];
-      part += x * x;
-    }
-    double xn2 = block_sum(part, red);
-    double alpha = W[j + j * m];
-    double tj = 0.0;
-    if (xn2 > 0.0) {
-      double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tj = (beta - alpha) / beta;
-      double scal = 1.0 / (alpha - beta);
-      for (int i = j + 1 + tid; i < m; i += blockDim.x) W[i + j * m] *= scal;
-      __syncthreads();   // every wave has read alpha before the diagonal is replaced
-      if (tid == 0) W[j + j * m] = beta;
-    }
-    if (tid == 0) tau[j] = tj;
-    __syncthreads();
-    if (tj != 0.0) {
-      const double* v = W + j * m;
-      for (int c = j + 1 + wave; c < n; c += nw) {
-        double* col = W + c * m;
-        double d = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-        d = wave_sum(d);
-        d = __shfl(d, 0, 64) + col[j];
-        const double f = tj * d;
-        if (lane == 0) col[j] -= f;
-        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+    const double tj = tau[j];
+    // first owned column after j (the owner of j+1 starts with it)
+    int c = j + 1 + ((wave - (j + 1)) % nw + nw) % nw;
+    for (; c < n; c += nw) {
+      double diag_next = W[(long long)c * m + c];   // row c of column c (used when c == j+1)
+      if (tj != 0.0) {
+        const double r1 = apply_reflector(W, m, j, tj, c);
+        if (c == j + 1) diag_next = r1;
       }
+      if (c == j + 1) make_reflector(W, m, j + 1, diag_next, tau);
     }
     __syncthreads();
   }
 }
 
-// Overwrite the reflectors with the explicit m x n Q (backward accumulation,
-// column j starts as e_j).  R must have been saved before.
+// Overwrite the reflectors with the explicit m x n Q (backward accumulation:
+// column j starts as e_j).  R must have been saved before.  Column j is
+// rewritten by its owner at the start of step j-1 (after every wave has used
+// reflector j), so each step needs one barrier.
 __device__ void lds_form_q(double* W, int m, int n, const double* tau) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  auto rewrite = [&](int j) {   // column j := (I - tau_j v v^T) e_j, by its owner
+    const double tj = tau[j];
+    double* col = W + (long long)j * m;
+    for (int i = lane; i < j; i += 64) col[i] = 0.0;
+    for (int i = j + 1 + lane; i < m; i += 64) col[i] = -tj * col[i];
+    if (lane == 0) col[j] = 1.0 - tj;
+  };
   for (int j = n - 1; j >= 0; --j) {
+    if (j + 1 < n && (j + 1) % nw == wave) rewrite(j + 1);
     const double tj = tau[j];
     if (tj != 0.0) {
-      const double* v = W + j * m;
-      for (int c = j + 1 + wave; c < n; c += nw) {
-        double* col = W + c * m;
-        double d = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-        d = wave_sum(d);
-        d = __shfl(d, 0, 64) + col[j];
-        const double f = tj * d;
-        if (lane == 0) col[j] -= f;
-        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < m; i += blockDim.x) {
-      double v = (i > j) ? W[i + j * m] : 0.0;
-      W[i + j * m] = (i == j) ? 1.0 - tj : (i > j ? -tj * v : 0.0);
+      int c = j + 1 + ((wave - (j + 1)) % nw + nw) % nw;
+      for (; c < n; c += nw) apply_reflector(W, m, j, tj, c);
     }
     __syncthreads();
   }
+  if (wave == 0) rewrite(0);
+  __syncthreads();
 }
 
 __device__ __forceinline__ long long qr_row(const QRTask& T, const long long* tabs, int i) {
@@ -879,7 +907,6 @@ __global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ ta
                                                    const long long* __restrict__ tabs, double* A, double* S,
                                                    double* ws) {
   extern __shared__ double lds[];
-  __shared__ double red[16];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRChunk C = chunks[blockIdx.x];
   const QRTask T = tasks[C.task];
@@ -890,7 +917,7 @@ __global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ ta
     W[e] = A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs];
   }
   __syncthreads();
-  lds_householder(W, m, n, tau, red);
+  lds_householder(W, m, n, tau);
   if (C.nchunks == 1) {
     for (int j = tid; j < n; j += blockDim.x) sgn[j] = W[j + j * m] < 0.0 ? -1.0 : 1.0;
     __syncthreads();
@@ -922,7 +949,6 @@ __global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ ta
 __global__ __launch_bounds__(1024) void k_qr_stack(const QRTask* __restrict__ tasks, const QRStack* __restrict__ stacks,
                                                    double* S, double* ws) {
   extern __shared__ double lds[];
-  __shared__ double red[16];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRStack K = stacks[blockIdx.x];
   const QRTask T = tasks[K.task];
@@ -930,7 +956,7 @@ __global__ __launch_bounds__(1024) void k_qr_stack(const QRTask* __restrict__ ta
   double* W = lds;
   for (int e = tid; e < m * n; e += blockDim.x) W[e] = ws[K.rw + e];
   __syncthreads();
-  lds_householder(W, m, n, tau, red);
+  lds_householder(W, m, n, tau);
   for (int j = tid; j < n; j += blockDim.x) sgn[j] = W[j + j * m] < 0.0 ? -1.0 : 1.0;
   __syncthreads();
   for (int e = tid; e < n * n; e += blockDim.x) {
@@ -1010,8 +1036,8 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, d
   prof_begin(st);
   double* lws = ws + p.ws_size;
   if (!p.chunks.empty()) {
-    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size()), dim3(1024), shm, st, p.d_tasks, p.d_chunks,
-                       d_tabs, A, S, lws);
+    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size()), dim3(1024), shm, st, p.d_tasks, p.d_chunks, d_tabs,
+                       A, S, lws);
     HIP_CHECK_LAUNCH();
   }
   if (!p.stacks.empty()) {
