@@ -422,10 +422,9 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 // One wave's (16 FM) x (16 FN) output block from global memory, f64 MFMA
 // 16x16x4 (FP32 precision: f32 MFMA within each 16-deep K chunk, FP64 across
 // chunks).  In a chunk, lane (r, g) = (lane % 16, lane / 16) supplies row r /
-// column r at k = 4g + s on MFMA step s, so the chunk's 16 products are taken
-// in a fixed permuted order and every lane reads four consecutive k.  The
-// chunks of the job (part, part + nparts, ...) are loaded one chunk ahead of
-// the MFMAs.  With nparts = 4 the four waves of the workgroup hold the four
+// column r at k = 4g + s on MFMA step s = 0..3, so the chunk's 16 products are
+// taken in a fixed permuted order and every lane reads four consecutive k.  The job
+// takes chunks part, part + nparts, ...  With nparts = 4 the four waves of the workgroup hold the four
 // K parts of one block and wave 0 adds them in part order.
 template <int FM, int FN, int PREC>
 __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
@@ -456,61 +455,48 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
-  double a[FM][4], b[FN][4];
-  auto load = [&](int c, double (&xa)[FM][4], double (&xb)[FN][4]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = c * 16 + 4 * g + s;
-      const bool ok = k < P.K;
-      const unsigned ka = ok ? (unsigned)idx_map(tabs, P.tak, P.sak, k) : 0u;
-      const unsigned kb = ok ? (unsigned)idx_map(tabs, P.tbk, P.sbk, k) : 0u;
-#pragma unroll
-      for (int i = 0; i < FM; ++i) xa[i][s] = (ok && ra[i] != 0xffffffffu) ? A[ra[i] + ka] : 0.0;
-#pragma unroll
-      for (int j = 0; j < FN; ++j) xb[j][s] = (ok && cb[j] != 0xffffffffu) ? B[kb + cb[j]] : 0.0;
-    }
-  };
-  int c = J.part;
-  if (c < nch) load(c, a, b);
-  for (; c < nch; c += J.nparts) {
-    double an[FM][4], bn[FN][4];
-    const bool more = c + J.nparts < nch;
-    if (more) load(c + J.nparts, an, bn);
-    if (F64) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-    } else {
-      float4_t t[FM][FN];
+  // no register double buffering, and a chunk is loaded in two halves of two
+  // MFMA steps: few live registers, and the occupancy that buys hides the
+  // load latency better on these short loops
+  for (int c = J.part; c < nch; c += J.nparts) {
+    float4_t t[FM][FN];
+    if (!F64) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) t[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+    for (int h = 0; h < 2; ++h) {
+      double a[FM][2], b[FN][2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = c * 16 + 4 * g + 2 * h + q;
+        const bool ok = k < P.K;
+        const unsigned ka = ok ? (unsigned)idx_map(tabs, P.tak, P.sak, k) : 0u;
+        const unsigned kb = ok ? (unsigned)idx_map(tabs, P.tbk, P.sbk, k) : 0u;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i][q] = (ok && ra[i] != 0xffffffffu) ? A[ra[i] + ka] : 0.0;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j][q] = (ok && cb[j] != 0xffffffffu) ? B[kb + cb[j]] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            t[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i][s], (float)b[j][s], t[i][j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j) {
+            if (F64) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+            else t[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i][q], (float)b[j][q], t[i][j], 0, 0, 0);
+          }
+    }
+    if (!F64) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)t[i][j][v];
-    }
-    if (more) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i) a[i][s] = an[i][s];
-#pragma unroll
-        for (int j = 0; j < FN; ++j) b[j][s] = bn[j][s];
-      }
     }
   }
   if (J.nparts > 1) {   // uniform over the workgroup: its four jobs are the parts of one block
@@ -553,8 +539,10 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
     }
 }
 
+// six waves per SIMD: the register budget that fits six four-wave workgroups
+// (also the LDS limit of the split reduction buffer)
 template <int PREC>
-__global__ __launch_bounds__(256) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
                                                int nblocks, const long long* __restrict__ tabs, Slots slots) {
   __shared__ double red[3 * 1024];
   const int blk = xcd_block(blockIdx.x, nblocks);
