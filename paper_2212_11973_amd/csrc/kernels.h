@@ -7,7 +7,8 @@
 namespace tt {
 
 // reduction geometry: fixed block count so that every sum has a fixed order
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 256;
+constexpr int kRedThreads = 1024;   // threads per block of the reducing kernels
 constexpr int kMaxKrylov = 32;
 
 // Optional timing of the grouped kernels: HIP events on the launch stream.

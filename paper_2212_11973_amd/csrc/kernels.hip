@@ -657,12 +657,19 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precis
 }
 
 // ------------------------------------------------------------------ W stage
-__global__ __launch_bounds__(256) void k_wstage(const WTask* __restrict__ tasks, const WTerm* __restrict__ terms,
-                                                const double* __restrict__ in, double* __restrict__ out) {
+// One workgroup of TT_WSTAGE_THREADS threads per task; lanes run over the
+// task's elements, each summing its terms in order.  The task index is
+// uniform (descriptors in scalar registers).
+#ifndef TT_WSTAGE_THREADS
+#define TT_WSTAGE_THREADS 256
+#endif
+__global__ __launch_bounds__(TT_WSTAGE_THREADS) void k_wstage(const WTask* __restrict__ tasks,
+                                                              const WTerm* __restrict__ terms,
+                                                              const double* __restrict__ in, double* __restrict__ out) {
   const WTask t = tasks[blockIdx.x];
   const int n = t.ni * t.nj;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    int i = e / t.nj, j = e - i * t.nj;
+  for (int e = threadIdx.x; e < n; e += TT_WSTAGE_THREADS) {
+    const int i = e / t.nj, j = e - i * t.nj;
     double acc = 0.0;
     for (int q = 0; q < t.nt; ++q) {
       const WTerm w = terms[t.t0 + q];
@@ -675,7 +682,7 @@ __global__ __launch_bounds__(256) void k_wstage(const WTask* __restrict__ tasks,
 void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st) {
   if (p.ntasks == 0) return;
   prof_begin(st);
-  hipLaunchKernelGGL(k_wstage, dim3(p.ntasks), dim3(256), 0, st, p.d_tasks, p.d_terms, in, out);
+  hipLaunchKernelGGL(k_wstage, dim3(p.ntasks), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, p.d_terms, in, out);
   HIP_CHECK_LAUNCH();
   prof_end(st, PROF_WSTAGE, p.flops, p.bytes);
 }
@@ -1045,10 +1052,11 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, d
 
 // ------------------------------------------------------------------ Lanczos
 // Sums of the nv per-thread accumulators over the block in a fixed order:
-// wave sums, then the four waves in order; out[v] written by thread v.
+// wave sums, then the waves in order; out[v] written by thread v.  red holds
+// (blockDim / 64) * MAXV doubles.
 template <int MAXV>
 __device__ __forceinline__ void block_sums(const double (&acc)[MAXV], int nv, double* red, double* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int v = 0; v < MAXV; ++v) {
     if (v >= nv) break;
@@ -1058,7 +1066,9 @@ __device__ __forceinline__ void block_sums(const double (&acc)[MAXV], int nv, do
   __syncthreads();
   if ((int)threadIdx.x < nv) {
     const int v = threadIdx.x;
-    out[v] = ((red[v] + red[MAXV + v]) + red[2 * MAXV + v]) + red[3 * MAXV + v];
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * MAXV + v];
+    out[v] = s;
   }
 }
 
@@ -1073,10 +1083,10 @@ __device__ __forceinline__ void red_chunk(long long n, long long& i0, long long&
 // part[b*(nv+self) + v] = sum over block b's chunk of Q_v[i] * y[i]; last entry y.y if with_self.
 // One pass: y and every Q_v are read once.
 template <int MAXV>
-__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ Q, long long ld, int nv,
+__global__ __launch_bounds__(kRedThreads) void k_mdot(const double* __restrict__ Q, long long ld, int nv,
                                               const double* __restrict__ y, long long n, int with_self,
                                               double* __restrict__ part) {
-  __shared__ double red[4 * MAXV];
+  __shared__ double red[(kRedThreads / 64) * MAXV];
   long long i0, i1;
   red_chunk(n, i0, i1);
   double acc[MAXV];
@@ -1131,11 +1141,11 @@ __global__ void k_lz_start(const double* __restrict__ v, double* __restrict__ q0
 // partials of the previous pass (alpha, ||H q|| stored by block 0), and in the
 // same pass the partial dots Q_v . w of the updated chunk (next pass).
 template <int MAXV>
-__global__ __launch_bounds__(256) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q, long long ld,
+__global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q, long long ld,
                                                     int nv, const double* __restrict__ part_in, int stride_in, long long n,
                                                     double* alpha_out, double* hn_out, double* __restrict__ part_out) {
   __shared__ double c[kMaxKrylov + 1];
-  __shared__ double red[4 * MAXV];
+  __shared__ double red[(kRedThreads / 64) * MAXV];
   gather_parts(part_in, stride_in, stride_in > nv ? nv + 1 : nv, c);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1171,11 +1181,11 @@ __global__ __launch_bounds__(256) void k_lz_sub_dot(double* __restrict__ w, cons
 
 // k_lz_sub_norm: second pass w -= sum_v c_v Q_v, then partial w . w
 template <int MAXV>
-__global__ __launch_bounds__(256) void k_lz_sub_norm(double* __restrict__ w, const double* __restrict__ Q, long long ld,
+__global__ __launch_bounds__(kRedThreads) void k_lz_sub_norm(double* __restrict__ w, const double* __restrict__ Q, long long ld,
                                                      int nv, const double* __restrict__ part_in, long long n,
                                                      double* __restrict__ part_out) {
   __shared__ double c[kMaxKrylov + 1];
-  __shared__ double red[4];
+  __shared__ double red[kRedThreads / 64];
   gather_parts(part_in, nv, nv, c);
   __syncthreads();
   double cr[MAXV];
@@ -1198,11 +1208,11 @@ __global__ __launch_bounds__(256) void k_lz_sub_norm(double* __restrict__ w, con
 }
 
 // out = sum_v coeff_v Q_v and the partial out . out of each chunk
-__global__ __launch_bounds__(256) void k_lz_combine_norm(const double* __restrict__ Q, long long ld, int K,
+__global__ __launch_bounds__(kRedThreads) void k_lz_combine_norm(const double* __restrict__ Q, long long ld, int K,
                                                          const double* __restrict__ coeff, double* __restrict__ out,
                                                          long long n, double* __restrict__ part_out) {
   __shared__ double c[kMaxKrylov];
-  __shared__ double red[8];
+  __shared__ double red[kRedThreads / 64];
   if (threadIdx.x < K) c[threadIdx.x] = coeff[threadIdx.x];
   __syncthreads();
   const long long chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -1350,7 +1360,7 @@ static int grid_for(long long n) {
 
 void launch_mdot(const double* Q, long long ld, int nv, const double* y, long long n, int with_self, double* part,
                  hipStream_t st) {
-  TT_BY_MAXV(nv + with_self, k_mdot, dim3(kRedBlocks), dim3(256), 0, st, Q, ld, nv, y, n, with_self, part);
+  TT_BY_MAXV(nv + with_self, k_mdot, dim3(kRedBlocks), dim3(kRedThreads), 0, st, Q, ld, nv, y, n, with_self, part);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_start(const double* v, double* q0, long long n, const double* part, double* scal, hipStream_t st) {
@@ -1359,18 +1369,18 @@ void launch_lz_start(const double* v, double* q0, long long n, const double* par
 }
 void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
                        long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st) {
-  TT_BY_MAXV(nv, k_lz_sub_dot, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, stride_in, n, alpha_out,
+  TT_BY_MAXV(nv, k_lz_sub_dot, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, stride_in, n, alpha_out,
              hn_out, part_out);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
                         double* part_out, hipStream_t st) {
-  TT_BY_MAXV(nv, k_lz_sub_norm, dim3(kRedBlocks), dim3(256), 0, st, w, Q, ld, nv, part_in, n, part_out);
+  TT_BY_MAXV(nv, k_lz_sub_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, n, part_out);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
                             double* part_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_combine_norm, dim3(kRedBlocks), dim3(256), 0, st, Q, ld, K, coeff, out, n, part_out);
+  hipLaunchKernelGGL(k_lz_combine_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, Q, ld, K, coeff, out, n, part_out);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_next(const double* w, double* qn, long long n, const double* part, double* beta_out, const double* hn,
