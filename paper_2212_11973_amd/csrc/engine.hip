@@ -227,11 +227,12 @@ void lanczos_exp(tt_state& s, double t, double* v, long long n, const std::funct
   launch_lz_start(v, Qb, n, p1, scal, ST());
   for (int j = 0; j < K; ++j) {
     H(Qb + (long long)j * n, s.wv);
-    // pass 1: c = Q^T w (and ||w||), w -= Q c, dots of the result; pass 2: w -= Q c', ||w||
+    // pass 1: c = Q^T w (and ||w||), w -= Q c, dots and norm of the result;
+    // pass 2: q_{j+1} = (w - Q c') / beta
     launch_mdot(Qb, n, j + 1, s.wv, n, 1, p1, ST());
     launch_lz_sub_dot(s.wv, Qb, n, j + 1, p1, j + 2, n, alpha + j, hn + j, p2, ST());
-    launch_lz_sub_norm(s.wv, Qb, n, j + 1, p2, n, p1, ST());
-    launch_lz_next(s.wv, j + 1 < K ? Qb + (long long)(j + 1) * n : nullptr, n, p1, beta + j, hn + j, tol, ST());
+    launch_lz_sub_next(s.wv, Qb, n, j + 1, p2, n, j + 1 < K ? Qb + (long long)(j + 1) * n : nullptr, beta + j, hn + j,
+                       tol, ST());
   }
   launch_lz_coeffs(alpha, beta, hn, K, t, tol, scal, coeff, s.err_ptr(), ST());
   launch_lz_combine_norm(Qb, n, K, coeff, v, n, p1, ST());

@@ -46,12 +46,12 @@ void launch_lz_start(const double* v, double* q0, long long n, const double* par
                      hipStream_t st);
 void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
                        long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st);
-void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
-                        double* part_out, hipStream_t st);
+// second pass and normalisation in one: qn = (w - Q c') / beta, beta from
+// ||w||^2 - ||c'||^2 (part_in: stride nv + 1 partials of k_lz_sub_dot)
+void launch_lz_sub_next(const double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
+                        double* qn, double* beta_out, const double* hn, double tol, hipStream_t st);
 void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
                             double* part_out, hipStream_t st);
-void launch_lz_next(const double* w, double* qn, long long n, const double* part, double* beta_out,
-                    const double* hn, double tol, hipStream_t st);
 void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t,
                       double tol, const double* scal, double* coeff, double* errmax, hipStream_t st);
 void launch_normalize_log(double* v, long long n, const double* part, double* lambda, hipStream_t st);

@@ -1051,23 +1051,31 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, d
 }
 
 // ------------------------------------------------------------------ Lanczos
-// Sums of the nv per-thread accumulators over the block in a fixed order:
-// wave sums, then the waves in order; out[v] written by thread v.  red holds
-// (blockDim / 64) * MAXV doubles.
+// Sums of the nv per-thread accumulators (then `extra` at index nv when
+// with_extra) over the block in a fixed order: wave sums, then the waves in
+// order; out[v] written by thread v.  red holds (blockDim / 64) * (MAXV + 1)
+// doubles.
 template <int MAXV>
-__device__ __forceinline__ void block_sums(const double (&acc)[MAXV], int nv, double* red, double* out) {
+__device__ __forceinline__ void block_sums(const double (&acc)[MAXV], int nv, double* red, double* out,
+                                           bool with_extra = false, double extra = 0.0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  constexpr int S = MAXV + 1;
 #pragma unroll
   for (int v = 0; v < MAXV; ++v) {
     if (v >= nv) break;
     const double s = wave_sum(acc[v]);
-    if (lane == 0) red[wave * MAXV + v] = s;
+    if (lane == 0) red[wave * S + v] = s;
+  }
+  if (with_extra) {
+    const double s = wave_sum(extra);
+    if (lane == 0) red[wave * S + nv] = s;
   }
   __syncthreads();
-  if ((int)threadIdx.x < nv) {
+  const int nout = nv + (with_extra ? 1 : 0);
+  if ((int)threadIdx.x < nout) {
     const int v = threadIdx.x;
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[w * MAXV + v];
+    for (int w = 0; w < nw; ++w) s += red[w * S + v];
     out[v] = s;
   }
 }
@@ -1086,22 +1094,23 @@ template <int MAXV>
 __global__ __launch_bounds__(kRedThreads) void k_mdot(const double* __restrict__ Q, long long ld, int nv,
                                               const double* __restrict__ y, long long n, int with_self,
                                               double* __restrict__ part) {
-  __shared__ double red[(kRedThreads / 64) * MAXV];
+  __shared__ double red[(kRedThreads / 64) * (MAXV + 1)];
   long long i0, i1;
   red_chunk(n, i0, i1);
   double acc[MAXV];
 #pragma unroll
   for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  double self = 0.0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const double yi = y[i];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
-      if (v < nv) acc[v] += Q[(long long)v * ld + i] * yi;
-      else if (v == nv && with_self) acc[v] += yi * yi;
+      if (v >= nv) break;
+      acc[v] += Q[(long long)v * ld + i] * yi;
     }
+    self += yi * yi;
   }
-  const int nout = nv + with_self;
-  block_sums<MAXV>(acc, nout, red, part + (long long)blockIdx.x * nout);
+  block_sums<MAXV>(acc, nv, red, part + (long long)blockIdx.x * (nv + with_self), with_self != 0, self);
 }
 
 __device__ double sum_parts(const double* part, int nparts, int stride, int v) {
@@ -1139,13 +1148,15 @@ __global__ void k_lz_start(const double* __restrict__ v, double* __restrict__ q0
 // Fused Gram-Schmidt passes on the same chunks as k_mdot, so every partial
 // sum has a fixed order.  k_lz_sub_dot: w -= sum_v c_v Q_v with c from the
 // partials of the previous pass (alpha, ||H q|| stored by block 0), and in the
-// same pass the partial dots Q_v . w of the updated chunk (next pass).
+// same pass the partial dots Q_v . w of the updated chunk and its partial w . w
+// (part_out stride nv + 1).
 template <int MAXV>
-__global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q, long long ld,
-                                                    int nv, const double* __restrict__ part_in, int stride_in, long long n,
-                                                    double* alpha_out, double* hn_out, double* __restrict__ part_out) {
+__global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q,
+                                                            long long ld, int nv, const double* __restrict__ part_in,
+                                                            int stride_in, long long n, double* alpha_out,
+                                                            double* hn_out, double* __restrict__ part_out) {
   __shared__ double c[kMaxKrylov + 1];
-  __shared__ double red[(kRedThreads / 64) * MAXV];
+  __shared__ double red[(kRedThreads / 64) * (MAXV + 1)];
   gather_parts(part_in, stride_in, stride_in > nv ? nv + 1 : nv, c);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1160,40 +1171,55 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(double* __restrict__
   double acc[MAXV];
 #pragma unroll
   for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  double ss = 0.0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     double q[MAXV];
     double s = w[i];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
-      if (v >= nv) break;
-      q[v] = Q[(long long)v * ld + i];
+      q[v] = v < nv ? Q[(long long)v * ld + i] : 0.0;
       s -= cr[v] * q[v];
     }
     w[i] = s;
 #pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-      if (v >= nv) break;
-      acc[v] += q[v] * s;
-    }
+    for (int v = 0; v < MAXV; ++v) acc[v] += q[v] * s;
+    ss += s * s;
   }
-  block_sums<MAXV>(acc, nv, red, part_out + (long long)blockIdx.x * nv);
+  block_sums<MAXV>(acc, nv, red, part_out + (long long)blockIdx.x * (nv + 1), true, ss);
 }
 
-// k_lz_sub_norm: second pass w -= sum_v c_v Q_v, then partial w . w
+// Second Gram-Schmidt pass fused with the normalisation: with c' = Q^T w'
+// (the dots of the previous pass) the new vector is w'' = w' - Q c', and since
+// Q has orthonormal columns ||w''||^2 = ||w'||^2 - ||c'||^2, so beta and
+// q_next = w'' / beta come out of one pass.  (Near a lucky breakdown both terms
+// are O(eps ||H q||), and so is the computed beta: the test beta <= tol ||H q||
+// still holds.)  qn = null: only beta is stored.
 template <int MAXV>
-__global__ __launch_bounds__(kRedThreads) void k_lz_sub_norm(double* __restrict__ w, const double* __restrict__ Q, long long ld,
-                                                     int nv, const double* __restrict__ part_in, long long n,
-                                                     double* __restrict__ part_out) {
+__global__ __launch_bounds__(kRedThreads) void k_lz_sub_next(const double* __restrict__ w, const double* __restrict__ Q,
+                                                             long long ld, int nv, const double* __restrict__ part_in,
+                                                             long long n, double* __restrict__ qn, double* beta_out,
+                                                             const double* hn, double tol) {
   __shared__ double c[kMaxKrylov + 1];
-  __shared__ double red[kRedThreads / 64];
-  gather_parts(part_in, nv, nv, c);
+  __shared__ double s_inv;
+  gather_parts(part_in, nv + 1, nv + 1, c);
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double p = 0.0;
+    for (int v = 0; v < nv; ++v) p += c[v] * c[v];
+    const double b2 = c[nv] - p;
+    const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
+    if (blockIdx.x == 0) *beta_out = b;
+    const bool brk = !(b > tol * (*hn)) || b == 0.0;
+    s_inv = brk ? 0.0 : 1.0 / b;
+  }
+  __syncthreads();
+  if (!qn) return;
+  const double inv = s_inv;
   double cr[MAXV];
 #pragma unroll
   for (int v = 0; v < MAXV; ++v) cr[v] = v < nv ? c[v] : 0.0;
   long long i0, i1;
   red_chunk(n, i0, i1);
-  double acc[1] = {0.0};
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     double s = w[i];
 #pragma unroll
@@ -1201,10 +1227,8 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_sub_norm(double* __restrict_
       if (v >= nv) break;
       s -= cr[v] * Q[(long long)v * ld + i];
     }
-    w[i] = s;
-    acc[0] += s * s;
+    qn[i] = s * inv;
   }
-  block_sums<1>(acc, 1, red, part_out + blockIdx.x);
 }
 
 // out = sum_v coeff_v Q_v and the partial out . out of each chunk
@@ -1227,21 +1251,6 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_combine_norm(const double* _
   }
   ss = block_sum(ss, red);
   if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
-}
-
-// beta = ||w||; qn = w / beta unless beta <= tol * ||H q|| (lucky breakdown: qn = 0)
-__global__ void k_lz_next(const double* __restrict__ w, double* __restrict__ qn, long long n,
-                          const double* __restrict__ part, double* beta_out, const double* hn, double tol) {
-  __shared__ double s_b;
-  gather_parts(part, 1, 1, &s_b);
-  __syncthreads();
-  const double b = sqrt(s_b);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = b;
-  if (!qn) return;
-  const bool brk = !(b > tol * (*hn)) || b == 0.0;
-  const double inv = brk ? 0.0 : 1.0 / b;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    qn[i] = w[i] * inv;
 }
 
 // coefficients of exp(t T) e_1 * ||v|| for the Krylov tridiagonal T: Taylor
@@ -1373,19 +1382,15 @@ void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const d
              hn_out, part_out);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_sub_norm(double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
-                        double* part_out, hipStream_t st) {
-  TT_BY_MAXV(nv, k_lz_sub_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, n, part_out);
+void launch_lz_sub_next(const double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
+                        double* qn, double* beta_out, const double* hn, double tol, hipStream_t st) {
+  TT_BY_MAXV(nv, k_lz_sub_next, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, n, qn, beta_out, hn,
+             tol);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
                             double* part_out, hipStream_t st) {
   hipLaunchKernelGGL(k_lz_combine_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, Q, ld, K, coeff, out, n, part_out);
-  HIP_CHECK_LAUNCH();
-}
-void launch_lz_next(const double* w, double* qn, long long n, const double* part, double* beta_out, const double* hn,
-                    double tol, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_next, dim3(grid_for(n)), dim3(256), 0, st, w, qn, n, part, beta_out, hn, tol);
   HIP_CHECK_LAUNCH();
 }
 void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t, double tol,
