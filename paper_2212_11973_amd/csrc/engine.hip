@@ -168,131 +168,211 @@ namespace {
 
 hipStream_t ST() { return g_stream; }
 
+// -------------------------------------------------------------- batches
+// A batch: up to kMaxBatch states with identical plans (same lattice, bond
+// sectors and options; the couplings may differ), advanced by the same
+// launches.  Plan descriptors and tables come from the lead state; every
+// data pointer is per state.  A single state is a batch of one.
+struct Batch {
+  int n = 0;
+  tt_state* s[kMaxBatch] = {};
+  tt_state& lead() const { return *s[0]; }
+};
+Batch batch_of(tt_state& st) {
+  Batch b;
+  b.n = 1;
+  b.s[0] = &st;
+  return b;
+}
+template <typename F> BPtr<double> per_state(const Batch& b, F f) {
+  BPtr<double> r{};
+  for (int i = 0; i < b.n; ++i) r.p[i] = f(*b.s[i]);
+  return r;
+}
+BPtr<double> offset(BPtr<double> x, const Batch& b, long long off) {
+  for (int i = 0; i < b.n; ++i) x.p[i] = x.p[i] ? x.p[i] + off : nullptr;
+  return x;
+}
+BPtr<double> pws_of(const Batch& b) { return per_state(b, [](tt_state& s) { return s.pws; }); }
+// Slots of every state: slot j = f_j(state, index in batch)
+template <typename F> BSlots slots_of(const Batch& b, F f) {
+  BSlots r{};
+  for (int i = 0; i < b.n; ++i) r.s[i] = f(*b.s[i], i);
+  return r;
+}
+template <typename F> BPtr<const WTerm> terms_of(const Batch& b, F f) {
+  BPtr<const WTerm> r{};
+  for (int i = 0; i < b.n; ++i) r.p[i] = f(*b.s[i]).d_terms;
+  return r;
+}
+void add_flops(const Batch& b, double f, bool heff) {
+  for (int i = 0; i < b.n; ++i) {
+    b.s[i]->flops += f;
+    if (heff) {
+      b.s[i]->flops_heff += f;
+      b.s[i]->n_applies++;
+    }
+  }
+}
+
 // -------------------------------------------------------------- contractions
-void apply_heff1(tt_state& s, int k, const double* x, double* out) {
-  SitePlan& P = s.plans[k];
-  int prec = s.opts.precision;
-  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.T1, nullptr}}, prec, s.pws, ST());
-  launch_wstage(P.w2, s.T1, s.T2, ST());
-  launch_gemm(P.s3, s.tabs.dev, Slots{{s.T2, s.Renv[k + 1], out, nullptr}}, prec, s.pws, ST());
-  double f = P.s1.flops + P.w2.flops + P.s3.flops;
-  s.flops += f;
-  s.flops_heff += f;
-  s.n_applies++;
+void apply_heff1(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
+  SitePlan& P = b.lead().plans[k];
+  const int prec = b.lead().opts.precision;
+  const long long* tabs = b.lead().tabs.dev;
+  launch_gemm(P.s1, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.Lenv[k], x.p[i], s.T1, nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  launch_wstage(P.w2, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].w2; }),
+                cst(per_state(b, [](tt_state& s) { return s.T1; })), per_state(b, [](tt_state& s) { return s.T2; }),
+                b.n, ST());
+  launch_gemm(P.s3, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.T2, s.Renv[k + 1], out.p[i], nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  add_flops(b, P.s1.flops + P.w2.flops + P.s3.flops, true);
 }
 
-void apply_heff0(tt_state& s, int k, const double* x, double* out) {
-  SitePlan& P = s.plans[k];
-  int prec = s.opts.precision;
-  launch_gemm(P.b1, s.tabs.dev, Slots{{s.Lenv[k], const_cast<double*>(x), s.U, nullptr}}, prec, s.pws, ST());
-  launch_gemm(P.b2, s.tabs.dev, Slots{{s.U, s.Renv[k], out, nullptr}}, prec, s.pws, ST());
-  double f = P.b1.flops + P.b2.flops;
-  s.flops += f;
-  s.flops_heff += f;
-  s.n_applies++;
+void apply_heff0(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
+  SitePlan& P = b.lead().plans[k];
+  const int prec = b.lead().opts.precision;
+  const long long* tabs = b.lead().tabs.dev;
+  launch_gemm(P.b1, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.Lenv[k], x.p[i], s.U, nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  launch_gemm(P.b2, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.U, s.Renv[k], out.p[i], nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  add_flops(b, P.b1.flops + P.b2.flops, true);
 }
 
-void env_left(tt_state& s, int k) {   // Lenv[k+1] from Lenv[k], A_k (left-canonical), W_k
-  SitePlan& P = s.plans[k];
-  int prec = s.opts.precision;
-  launch_gemm(P.s1, s.tabs.dev, Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}, prec, s.pws, ST());
-  launch_wstage(P.w2, s.T1, s.T2, ST());
-  launch_gemm(P.el, s.tabs.dev, Slots{{s.A[k], s.T2, s.Lenv[k + 1], nullptr}}, prec, s.pws, ST());
-  s.flops += P.s1.flops + P.w2.flops + P.el.flops;
+void env_left(const Batch& b, int k) {   // Lenv[k+1] from Lenv[k], A_k (left-canonical), W_k
+  SitePlan& P = b.lead().plans[k];
+  const int prec = b.lead().opts.precision;
+  const long long* tabs = b.lead().tabs.dev;
+  launch_gemm(P.s1, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  launch_wstage(P.w2, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].w2; }),
+                cst(per_state(b, [](tt_state& s) { return s.T1; })), per_state(b, [](tt_state& s) { return s.T2; }),
+                b.n, ST());
+  launch_gemm(P.el, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.A[k], s.T2, s.Lenv[k + 1], nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  add_flops(b, P.s1.flops + P.w2.flops + P.el.flops, false);
 }
 
-void env_right(tt_state& s, int k) {  // Renv[k] from Renv[k+1], A_k (right-canonical), W_k
-  SitePlan& P = s.plans[k];
-  int prec = s.opts.precision;
-  launch_gemm(P.r1, s.tabs.dev, Slots{{s.Renv[k + 1], s.A[k], s.Y, nullptr}}, prec, s.pws, ST());
-  launch_wstage(P.wr, s.Y, s.Z, ST());
-  launch_gemm(P.r3, s.tabs.dev, Slots{{s.A[k], s.Z, s.Renv[k], nullptr}}, prec, s.pws, ST());
-  s.flops += P.r1.flops + P.wr.flops + P.r3.flops;
+void env_right(const Batch& b, int k) {  // Renv[k] from Renv[k+1], A_k (right-canonical), W_k
+  SitePlan& P = b.lead().plans[k];
+  const int prec = b.lead().opts.precision;
+  const long long* tabs = b.lead().tabs.dev;
+  launch_gemm(P.r1, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.Renv[k + 1], s.A[k], s.Y, nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  launch_wstage(P.wr, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].wr; }),
+                cst(per_state(b, [](tt_state& s) { return s.Y; })), per_state(b, [](tt_state& s) { return s.Z; }),
+                b.n, ST());
+  launch_gemm(P.r3, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.A[k], s.Z, s.Renv[k], nullptr}}; }),
+              b.n, prec, pws_of(b), ST());
+  add_flops(b, P.r1.flops + P.wr.flops + P.r3.flops, false);
 }
 
 // -------------------------------------------------------------- Lanczos exp
-// v <- exp(t H) v / ||exp(t H) v||, Lambda += ln ||exp(t H) v||
-void lanczos_exp(tt_state& s, double t, double* v, long long n, const std::function<void(const double*, double*)>& H) {
-  const int K = s.opts.krylov_dim;
-  const double tol = s.opts.krylov_tol;
-  double* alpha = s.lz;
-  double* beta = s.lz + kMaxKrylov;
-  double* hn = s.lz + 2 * kMaxKrylov;
-  double* coeff = s.lz + 3 * kMaxKrylov;
-  double* scal = s.lz + 4 * kMaxKrylov;
-  double* Qb = s.kry;
-  double* p1 = s.part;
-  double* p2 = s.part + (long long)kRedBlocks * (kMaxKrylov + 2);
-  launch_mdot(nullptr, 0, 0, v, n, 1, p1, ST());
-  launch_lz_start(v, Qb, n, p1, scal, ST());
+// v <- exp(t H) v / ||exp(t H) v||, Lambda += ln ||exp(t H) v||, for every state of the batch
+void lanczos_exp(const Batch& b, double t, BPtr<double> v, long long n,
+                 const std::function<void(BPtr<double>, BPtr<double>)>& H) {
+  const tt_state& L = b.lead();
+  const int K = L.opts.krylov_dim;
+  const double tol = L.opts.krylov_tol;
+  const int nb = b.n;
+  BPtr<double> lz = per_state(b, [](tt_state& s) { return s.lz; });
+  BPtr<double> alpha = lz, beta = offset(lz, b, kMaxKrylov), hn = offset(lz, b, 2 * kMaxKrylov);
+  BPtr<double> coeff = offset(lz, b, 3 * kMaxKrylov), scal = offset(lz, b, 4 * kMaxKrylov);
+  BPtr<double> err = per_state(b, [](tt_state& s) { return s.err_ptr(); });
+  BPtr<double> lam = per_state(b, [](tt_state& s) { return s.lam_ptr(); });
+  BPtr<double> Qb = per_state(b, [](tt_state& s) { return s.kry; });
+  BPtr<double> wv = per_state(b, [](tt_state& s) { return s.wv; });
+  BPtr<double> p1 = per_state(b, [](tt_state& s) { return s.part; });
+  BPtr<double> p2 = offset(p1, b, (long long)kRedBlocks * (kMaxKrylov + 2));
+  BPtr<double> none{};
+  launch_mdot(cst(none), 0, 0, cst(v), n, 1, p1, nb, ST());
+  launch_lz_start(cst(v), Qb, n, cst(p1), scal, nb, ST());
   for (int j = 0; j < K; ++j) {
-    H(Qb + (long long)j * n, s.wv);
+    H(offset(Qb, b, (long long)j * n), wv);
     // pass 1: c = Q^T w (and ||w||), w -= Q c, dots and norm of the result;
     // pass 2: q_{j+1} = (w - Q c') / beta
-    launch_mdot(Qb, n, j + 1, s.wv, n, 1, p1, ST());
-    launch_lz_sub_dot(s.wv, Qb, n, j + 1, p1, j + 2, n, alpha + j, hn + j, p2, ST());
-    launch_lz_sub_next(s.wv, Qb, n, j + 1, p2, n, j + 1 < K ? Qb + (long long)(j + 1) * n : nullptr, beta + j, hn + j,
-                       tol, ST());
+    launch_mdot(cst(Qb), n, j + 1, cst(wv), n, 1, p1, nb, ST());
+    launch_lz_sub_dot(wv, cst(Qb), n, j + 1, cst(p1), j + 2, n, offset(alpha, b, j), offset(hn, b, j), p2, nb, ST());
+    launch_lz_sub_next(cst(wv), cst(Qb), n, j + 1, cst(p2), n, j + 1 < K ? offset(Qb, b, (long long)(j + 1) * n) : none,
+                       offset(beta, b, j), cst(offset(hn, b, j)), tol, nb, ST());
   }
-  launch_lz_coeffs(alpha, beta, hn, K, t, tol, scal, coeff, s.err_ptr(), ST());
-  launch_lz_combine_norm(Qb, n, K, coeff, v, n, p1, ST());
-  launch_normalize_log(v, n, p1, s.lam_ptr(), ST());
-  s.n_exps++;
+  launch_lz_coeffs(cst(alpha), cst(beta), cst(hn), K, t, tol, cst(scal), coeff, err, nb, ST());
+  launch_lz_combine_norm(cst(Qb), n, K, cst(coeff), v, n, p1, nb, ST());
+  launch_normalize_log(v, n, cst(p1), lam, nb, ST());
+  for (int i = 0; i < nb; ++i) b.s[i]->n_exps++;
 }
 
-void site_exp(tt_state& s, int k, double t) {
-  lanczos_exp(s, t, s.A[k], s.site[k].size,
-              [&](const double* x, double* y) { apply_heff1(s, k, x, y); });
+void site_exp(const Batch& b, int k, double t) {
+  lanczos_exp(b, t, per_state(b, [&](tt_state& s) { return s.A[k]; }), b.lead().site[k].size,
+              [&](BPtr<double> x, BPtr<double> y) { apply_heff1(b, k, x, y); });
 }
-void bond_exp(tt_state& s, int k, double t) {
-  lanczos_exp(s, t, s.Sbuf, s.bmat[k].size,
-              [&](const double* x, double* y) { apply_heff0(s, k, x, y); });
-}
-
-void qr_site(tt_state& s, int k) {
-  launch_qr(s.plans[k].qr, s.tabs.dev, s.A[k], s.Sbuf, s.qrws, ST());
-}
-void lq_site(tt_state& s, int k) {
-  launch_qr(s.plans[k].lq, s.tabs.dev, s.A[k], s.Sbuf, s.qrws, ST());
-}
-void absorb_left(tt_state& s, int k) {   // A_k <- S_k A_k (S on the left bond k)
-  SitePlan& P = s.plans[k];
-  launch_gemm(P.absL, s.tabs.dev, Slots{{s.Sbuf, s.A[k], s.tmp, nullptr}}, TT_FP64, s.pws, ST());
-  launch_copy(s.A[k], s.tmp, s.site[k].size, ST());
-  s.flops += P.absL.flops;
-}
-void absorb_right(tt_state& s, int k) {  // A_k <- A_k S_{k+1}
-  SitePlan& P = s.plans[k];
-  launch_gemm(P.absR, s.tabs.dev, Slots{{s.A[k], s.Sbuf, s.tmp, nullptr}}, TT_FP64, s.pws, ST());
-  launch_copy(s.A[k], s.tmp, s.site[k].size, ST());
-  s.flops += P.absR.flops;
+void bond_exp(const Batch& b, int k, double t) {
+  lanczos_exp(b, t, per_state(b, [](tt_state& s) { return s.Sbuf; }), b.lead().bmat[k].size,
+              [&](BPtr<double> x, BPtr<double> y) { apply_heff0(b, k, x, y); });
 }
 
-void normalize_site(tt_state& s, int k) {
-  launch_mdot(nullptr, 0, 0, s.A[k], s.site[k].size, 1, s.part, ST());
-  launch_normalize_log(s.A[k], s.site[k].size, s.part, s.lam_ptr(), ST());
+void qr_site(const Batch& b, int k) {
+  launch_qr(b.lead().plans[k].qr, b.lead().tabs.dev, per_state(b, [&](tt_state& s) { return s.A[k]; }),
+            per_state(b, [](tt_state& s) { return s.Sbuf; }), per_state(b, [](tt_state& s) { return s.qrws; }), b.n,
+            ST());
+}
+void lq_site(const Batch& b, int k) {
+  launch_qr(b.lead().plans[k].lq, b.lead().tabs.dev, per_state(b, [&](tt_state& s) { return s.A[k]; }),
+            per_state(b, [](tt_state& s) { return s.Sbuf; }), per_state(b, [](tt_state& s) { return s.qrws; }), b.n,
+            ST());
+}
+void absorb_left(const Batch& b, int k) {   // A_k <- S_k A_k (S on the left bond k)
+  SitePlan& P = b.lead().plans[k];
+  launch_gemm(P.absL, b.lead().tabs.dev,
+              slots_of(b, [&](tt_state& s, int) { return Slots{{s.Sbuf, s.A[k], s.tmp, nullptr}}; }), b.n, TT_FP64,
+              pws_of(b), ST());
+  launch_copy(per_state(b, [&](tt_state& s) { return s.A[k]; }), cst(per_state(b, [](tt_state& s) { return s.tmp; })),
+              b.lead().site[k].size, b.n, ST());
+  add_flops(b, P.absL.flops, false);
+}
+void absorb_right(const Batch& b, int k) {  // A_k <- A_k S_{k+1}
+  SitePlan& P = b.lead().plans[k];
+  launch_gemm(P.absR, b.lead().tabs.dev,
+              slots_of(b, [&](tt_state& s, int) { return Slots{{s.A[k], s.Sbuf, s.tmp, nullptr}}; }), b.n, TT_FP64,
+              pws_of(b), ST());
+  launch_copy(per_state(b, [&](tt_state& s) { return s.A[k]; }), cst(per_state(b, [](tt_state& s) { return s.tmp; })),
+              b.lead().site[k].size, b.n, ST());
+  add_flops(b, P.absR.flops, false);
 }
 
-void sweep_once(tt_state& s, double dbeta) {
-  const int N = s.N;
+void normalize_site(const Batch& b, int k) {
+  BPtr<double> A = per_state(b, [&](tt_state& s) { return s.A[k]; });
+  BPtr<double> part = per_state(b, [](tt_state& s) { return s.part; });
+  BPtr<const double> none{};
+  launch_mdot(none, 0, 0, cst(A), b.lead().site[k].size, 1, part, b.n, ST());
+  launch_normalize_log(A, b.lead().site[k].size, cst(part), per_state(b, [](tt_state& s) { return s.lam_ptr(); }), b.n,
+                       ST());
+}
+
+void sweep_once(const Batch& b, double dbeta) {
+  const int N = b.lead().N;
   const double tau = 0.5 * dbeta;
   for (int k = 0; k < N - 1; ++k) {
-    site_exp(s, k, -tau);
-    qr_site(s, k);
-    env_left(s, k);
-    bond_exp(s, k + 1, +tau);
-    absorb_left(s, k + 1);
+    site_exp(b, k, -tau);
+    qr_site(b, k);
+    env_left(b, k);
+    bond_exp(b, k + 1, +tau);
+    absorb_left(b, k + 1);
   }
-  site_exp(s, N - 1, -2.0 * tau);
+  site_exp(b, N - 1, -2.0 * tau);
   for (int k = N - 1; k >= 1; --k) {
-    lq_site(s, k);
-    env_right(s, k);
-    bond_exp(s, k, +tau);
-    absorb_right(s, k - 1);
-    site_exp(s, k - 1, -tau);
+    lq_site(b, k);
+    env_right(b, k);
+    bond_exp(b, k, +tau);
+    absorb_right(b, k - 1);
+    site_exp(b, k - 1, -tau);
   }
-  s.beta += dbeta;
-  s.sweeps++;
+  for (int i = 0; i < b.n; ++i) {
+    b.s[i]->beta += dbeta;
+    b.s[i]->sweeps++;
+  }
 }
 
 // -------------------------------------------------------------- construction
@@ -482,15 +562,16 @@ void set_unit_env(double* e, hipStream_t st) { launch_fill(e, 1.0, 1, st); }
 
 void canonicalise_and_envs(tt_state& s) {
   const int N = s.N;
+  const Batch b = batch_of(s);
   for (int k = N - 1; k >= 1; --k) {
-    lq_site(s, k);
-    absorb_right(s, k - 1);
+    lq_site(b, k);
+    absorb_right(b, k - 1);
   }
   launch_fill(s.lam_ptr(), 0.0, 1, ST());
-  normalize_site(s, 0);
+  normalize_site(b, 0);
   set_unit_env(s.Lenv[0], ST());
   set_unit_env(s.Renv[N], ST());
-  for (int k = N - 1; k >= 1; --k) env_right(s, k);
+  for (int k = N - 1; k >= 1; --k) env_right(b, k);
 }
 
 std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
@@ -741,6 +822,50 @@ void fill_stats(tt_state& s, tt_sweep_stats* st, double secs) {
 }
 void reset_counters(tt_state& s) { s.flops = s.flops_heff = 0.0; s.n_applies = s.n_exps = 0; }
 
+template <typename T> bool same_bytes(const std::vector<T>& x, const std::vector<T>& y) {
+  return x.size() == y.size() && (x.empty() || std::memcmp(x.data(), y.data(), sizeof(T) * x.size()) == 0);
+}
+bool same_gemm(const GemmPlan& x, const GemmPlan& y) {
+  return same_bytes(x.probs, y.probs) && same_bytes(x.tiles, y.tiles) && same_bytes(x.jobs, y.jobs) &&
+         same_bytes(x.splits, y.splits) && x.pws_size == y.pws_size && x.wave_blocks == y.wave_blocks;
+}
+bool same_w(const WPlan& x, const WPlan& y) {   // the weights may differ
+  if (!same_bytes(x.tasks, y.tasks) || x.terms.size() != y.terms.size()) return false;
+  for (size_t i = 0; i < x.terms.size(); ++i)
+    if (x.terms[i].src != y.terms[i].src || x.terms[i].ssi != y.terms[i].ssi || x.terms[i].ssj != y.terms[i].ssj)
+      return false;
+  return true;
+}
+bool same_qr(const QRPlan& x, const QRPlan& y) {
+  return same_bytes(x.tasks, y.tasks) && same_bytes(x.chunks, y.chunks) && same_bytes(x.stacks, y.stacks) &&
+         same_bytes(x.wide, y.wide) && x.ws_size == y.ws_size && x.lds_ws == y.lds_ws;
+}
+// two states can share launches: same lattice size, options, bond sectors,
+// index tables and plans (only MPO weights, i.e. the couplings, may differ)
+bool same_plans(const tt_state& a, const tt_state& b) {
+  const tt_options &x = a.opts, &y = b.opts;
+  if (a.N != b.N || x.D != y.D || x.symmetry != y.symmetry || x.precision != y.precision ||
+      x.krylov_dim != y.krylov_dim || x.krylov_tol != y.krylov_tol || x.sector_cap != y.sector_cap)
+    return false;
+  if (!same_bytes(a.tabs.host, b.tabs.host)) return false;
+  for (int k = 0; k <= a.N; ++k) {
+    if (a.bonds[k].secs.size() != b.bonds[k].secs.size() || a.qH[k] != b.qH[k]) return false;
+    for (size_t i = 0; i < a.bonds[k].secs.size(); ++i)
+      if (!(a.bonds[k].secs[i].q == b.bonds[k].secs[i].q) || a.bonds[k].secs[i].dim != b.bonds[k].secs[i].dim)
+        return false;
+  }
+  for (int k = 0; k < a.N; ++k) {
+    const SitePlan &P = a.plans[k], &Q = b.plans[k];
+    if (a.site[k].size != b.site[k].size || a.bmat[k].size != b.bmat[k].size) return false;
+    for (auto pr : {std::make_pair(&P.s1, &Q.s1), std::make_pair(&P.s3, &Q.s3), std::make_pair(&P.el, &Q.el),
+                    std::make_pair(&P.r1, &Q.r1), std::make_pair(&P.r3, &Q.r3), std::make_pair(&P.absL, &Q.absL),
+                    std::make_pair(&P.absR, &Q.absR), std::make_pair(&P.b1, &Q.b1), std::make_pair(&P.b2, &Q.b2)})
+      if (!same_gemm(*pr.first, *pr.second)) return false;
+    if (!same_w(P.w2, Q.w2) || !same_w(P.wr, Q.wr) || !same_qr(P.qr, Q.qr) || !same_qr(P.lq, Q.lq)) return false;
+  }
+  return true;
+}
+
 // -------------------------------------------------------------- dense microbenchmark
 struct HeffCache {
   int Dl = -1, Dr = -1, DH = -1;
@@ -856,7 +981,7 @@ int tdvp_sweep(tt_state* s, double dbeta, tt_sweep_stats* stats) {
   TT_REQUIRE(std::isfinite(dbeta), TT_EINVAL, "dbeta must be finite");
   reset_counters(*s);
   auto t0 = std::chrono::steady_clock::now();
-  sweep_once(*s, dbeta);
+  sweep_once(batch_of(*s), dbeta);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     HIPX(hipStreamSynchronize(ST()));
@@ -870,10 +995,18 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
   ABI_BEGIN
   TT_REQUIRE(states && n >= 1, TT_EINVAL, "need at least one state");
   for (int i = 0; i < n; ++i) TT_REQUIRE(states[i], TT_EINVAL, "null state in batch");
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) TT_REQUIRE(states[i] != states[j], TT_EINVAL, "a state appears twice in the batch");
   auto t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < n; ++i) {
-    reset_counters(*states[i]);
-    sweep_once(*states[i], dbeta);
+  for (int i = 0; i < n; ++i) reset_counters(*states[i]);
+  // consecutive states with identical plans run together, up to kMaxBatch per launch
+  int i = 0;
+  while (i < n) {
+    Batch b = batch_of(*states[i]);
+    int j = i + 1;
+    while (j < n && b.n < kMaxBatch && same_plans(*states[i], *states[j])) b.s[b.n++] = states[j++];
+    sweep_once(b, dbeta);
+    i = j;
   }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
@@ -888,11 +1021,12 @@ int thermo_observables(tt_state* s, tt_observables* o) {
   ABI_BEGIN
   TT_REQUIRE(s && o, TT_EINVAL, "null argument");
   const long long n = s->site[0].size;
-  apply_heff1(*s, 0, s->A[0], s->wv);
+  const Batch b = batch_of(*s);
+  apply_heff1(b, 0, one(s->A[0]), one(s->wv));
   double* ob = s->obs_ptr();
-  launch_mdot(s->A[0], n, 1, s->wv, n, 0, s->part, ST());
+  launch_mdot(one<const double>(s->A[0]), n, 1, one<const double>(s->wv), n, 0, one(s->part), 1, ST());
   launch_dot_final(s->part, kRedBlocks, 1, ob, ST());
-  launch_mdot(nullptr, 0, 0, s->A[0], n, 1, s->part, ST());
+  launch_mdot(BPtr<const double>{}, 0, 0, one<const double>(s->A[0]), n, 1, one(s->part), 1, ST());
   launch_dot_final(s->part, kRedBlocks, 1, ob + 1, ST());
   launch_trace(s->d_trace, s->d_trace_start, s->N, s->d_sites, s->vtr, s->max_bond, ob + 2, ST());
   double h[4], lam;
@@ -1078,7 +1212,7 @@ int tt_state_load(const char* path, tt_state** out) {
   HIPX(hipMemcpyAsync(s->lam_ptr(), &lam, 8, hipMemcpyHostToDevice, ST()));
   set_unit_env(s->Lenv[0], ST());
   set_unit_env(s->Renv[s->N], ST());
-  for (int k = s->N - 1; k >= 1; --k) env_right(*s, k);
+  for (int k = s->N - 1; k >= 1; --k) env_right(batch_of(*s), k);
   s->beta = beta;
   s->sweeps = sweeps;
   HIPX(hipStreamSynchronize(ST()));
@@ -1100,12 +1234,14 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
     HeffCache& c = g_heff;
     hipStream_t st = ST();
     HIPX(hipEventRecord(c.ev[0], st));
-    launch_gemm(c.plan.s1, c.tabs.dev, Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}},
-                precision, c.pws, st);
+    launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}}), 1,
+                precision, one(c.pws), st);
     HIPX(hipEventRecord(c.ev[1], st));
-    launch_gemm(c.wg, c.tabs.dev, Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}, precision, c.pws, st);
+    launch_gemm(c.wg, c.tabs.dev, one(Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}), 1, precision, one(c.pws),
+                st);
     HIPX(hipEventRecord(c.ev[2], st));
-    launch_gemm(c.plan.s3, c.tabs.dev, Slots{{c.T2, const_cast<double*>(R), out, nullptr}}, precision, c.pws, st);
+    launch_gemm(c.plan.s3, c.tabs.dev, one(Slots{{c.T2, const_cast<double*>(R), out, nullptr}}), 1, precision,
+                one(c.pws), st);
     HIPX(hipEventRecord(c.ev[3], st));
     c.timed = true;
   } catch (...) {

@@ -30,32 +30,63 @@ void prof_end(hipStream_t st, int kind, double flops, double bytes);
 // (ms, flops, bytes, launches) per kind since the last read; synchronises the events
 void prof_read(double out[PROF_KINDS][4]);
 
+// Batched launches: every kernel of the sweep runs a batch of nb <= kMaxBatch
+// independent states with identical plans in one launch (blockIdx.y = state);
+// the plan descriptors and index tables are shared, data pointers are per
+// state.  A single state is a batch of one.
+constexpr int kMaxBatch = 16;
+template <typename T> struct BPtr { T* p[kMaxBatch]; };
+struct BSlots { Slots s[kMaxBatch]; };
+template <typename T> BPtr<const T> cst(BPtr<T> x) {
+  BPtr<const T> r;
+  for (int i = 0; i < kMaxBatch; ++i) r.p[i] = x.p[i];
+  return r;
+}
+template <typename T> BPtr<T> one(T* x) {
+  BPtr<T> r{};
+  r.p[0] = x;
+  return r;
+}
+inline BSlots one(Slots s) {
+  BSlots r{};
+  r.s[0] = s;
+  return r;
+}
+
 // pws: partial-tile workspace of at least p.pws_size doubles (split problems)
-void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, double* pws, hipStream_t st);
-void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st);
+void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, int nb, int precision,
+                 BPtr<double> pws, hipStream_t st);
+// terms: each state's copy of the plan's terms (the weights may differ)
+void launch_wstage(const WPlan& p, BPtr<const WTerm> terms, BPtr<const double> in, BPtr<double> out, int nb,
+                   hipStream_t st);
 // QR of every task of the plan: LDS chunk/stack/combine kernels for n <= 64,
 // the global-memory kernel for wider tasks.  ws holds p.ws_size + p.lds_ws doubles.
-void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, double* ws, hipStream_t st);
+void launch_qr(const QRPlan& p, const long long* d_tabs, BPtr<double> A, BPtr<double> S, BPtr<double> ws, int nb,
+               hipStream_t st);
 // split the tasks of a plan into LDS chunks and stacks (host)
 void qr_plan_chunks(QRPlan& p);
 
 // Lanczos pieces (see engine for the sequence)
-void launch_mdot(const double* Q, long long ld, int nv, const double* y, long long n, int with_self,
-                 double* part, hipStream_t st);
-void launch_lz_start(const double* v, double* q0, long long n, const double* part, double* scal,
-                     hipStream_t st);
-void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
-                       long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st);
+void launch_mdot(BPtr<const double> Q, long long ld, int nv, BPtr<const double> y, long long n, int with_self,
+                 BPtr<double> part, int nb, hipStream_t st);
+void launch_lz_start(BPtr<const double> v, BPtr<double> q0, long long n, BPtr<const double> part, BPtr<double> scal,
+                     int nb, hipStream_t st);
+void launch_lz_sub_dot(BPtr<double> w, BPtr<const double> Q, long long ld, int nv, BPtr<const double> part_in,
+                       int stride_in, long long n, BPtr<double> alpha_out, BPtr<double> hn_out, BPtr<double> part_out,
+                       int nb, hipStream_t st);
 // second pass and normalisation in one: qn = (w - Q c') / beta, beta from
-// ||w||^2 - ||c'||^2 (part_in: stride nv + 1 partials of k_lz_sub_dot)
-void launch_lz_sub_next(const double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
-                        double* qn, double* beta_out, const double* hn, double tol, hipStream_t st);
-void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
-                            double* part_out, hipStream_t st);
-void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t,
-                      double tol, const double* scal, double* coeff, double* errmax, hipStream_t st);
-void launch_normalize_log(double* v, long long n, const double* part, double* lambda, hipStream_t st);
-void launch_copy(double* dst, const double* src, long long n, hipStream_t st);
+// ||w||^2 - ||c'||^2 (part_in: stride nv + 1 partials of k_lz_sub_dot); qn null: beta only
+void launch_lz_sub_next(BPtr<const double> w, BPtr<const double> Q, long long ld, int nv, BPtr<const double> part_in,
+                        long long n, BPtr<double> qn, BPtr<double> beta_out, BPtr<const double> hn, double tol,
+                        int nb, hipStream_t st);
+void launch_lz_combine_norm(BPtr<const double> Q, long long ld, int K, BPtr<const double> coeff, BPtr<double> out,
+                            long long n, BPtr<double> part_out, int nb, hipStream_t st);
+void launch_lz_coeffs(BPtr<const double> alpha, BPtr<const double> beta, BPtr<const double> hn, int K, double t,
+                      double tol, BPtr<const double> scal, BPtr<double> coeff, BPtr<double> errmax, int nb,
+                      hipStream_t st);
+void launch_normalize_log(BPtr<double> v, long long n, BPtr<const double> part, BPtr<double> lambda, int nb,
+                          hipStream_t st);
+void launch_copy(BPtr<double> dst, BPtr<const double> src, long long n, int nb, hipStream_t st);
 void launch_fill(double* dst, double val, long long n, hipStream_t st);
 void launch_dot_final(const double* part, int nparts, int nv, double* out, hipStream_t st);
 

@@ -387,9 +387,11 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
 // C = alpha * (sum of the K-slice partials in slice order) + beta * C
 __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict__ probs,
                                                      const GemmSplit* __restrict__ splits,
-                                                     const long long* __restrict__ tabs, Slots slots,
-                                                     const double* __restrict__ pws) {
+                                                     const long long* __restrict__ tabs, BSlots bs,
+                                                     BPtr<double> b_pws) {
   __shared__ long long rC[256];
+  const Slots& slots = bs.s[blockIdx.y];
+  const double* __restrict__ pws = b_pws.p[blockIdx.y];
   const GemmSplit S = splits[blockIdx.x];
   const GemmProb P = probs[S.prob];
   const int BM = kGemmBM[S.cfg], BN = kGemmBN[S.cfg];
@@ -543,8 +545,9 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
 // (also the LDS limit of the split reduction buffer)
 template <int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
-                                               int nblocks, const long long* __restrict__ tabs, Slots slots) {
+                                               int nblocks, const long long* __restrict__ tabs, BSlots bs) {
   __shared__ double red[3 * 1024];
+  const Slots& slots = bs.s[blockIdx.y];
   const int blk = xcd_block(blockIdx.x, nblocks);
   // the job index is wave-uniform: job and problem descriptors load into scalar registers
   const int jidx = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
@@ -573,9 +576,11 @@ template <int PREC> struct CfgT<4, PREC> {
 
 template <int CFG, int PREC>
 __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs, const GemmTile* __restrict__ tiles,
-                                              int tile0, const long long* __restrict__ tabs, Slots slots,
-                                              double* __restrict__ pws) {
+                                              int tile0, const long long* __restrict__ tabs, BSlots bs,
+                                              BPtr<double> b_pws) {
   extern __shared__ __attribute__((aligned(16))) char smem_gemm[];
+  const Slots& slots = bs.s[blockIdx.y];
+  double* __restrict__ pws = b_pws.p[blockIdx.y];
   using C = CfgT<CFG, PREC>;
   const GemmTile t = tiles[tile0 + blockIdx.x];
   const GemmProb P = probs[t.prob];
@@ -599,7 +604,8 @@ int gemm_smem_bytes(int cfg) {   // FP64 tiles (the largest LDS of the precision
 }
 
 template <int CFG, int PREC>
-void launch_cfg(const GemmPlan& p, const long long* d_tabs, Slots s, double* pws, hipStream_t st) {
+void launch_cfg(const GemmPlan& p, const long long* d_tabs, const BSlots& s, int nb, BPtr<double> pws,
+                hipStream_t st) {
   const int n = p.cfg_off[CFG + 1] - p.cfg_off[CFG];
   if (n == 0) return;
   static bool attr = false;
@@ -610,50 +616,52 @@ void launch_cfg(const GemmPlan& p, const long long* d_tabs, Slots s, double* pws
       throw Error(TT_EDEVICE, "cannot set the LDS limit of the GEMM kernel");
     attr = true;
   }
-  hipLaunchKernelGGL((k_gemm<CFG, PREC>), dim3(n), dim3(256), smem, st, p.d_probs, p.d_tiles, p.cfg_off[CFG], d_tabs, s,
-                     pws);
+  hipLaunchKernelGGL((k_gemm<CFG, PREC>), dim3(n, nb), dim3(256), smem, st, p.d_probs, p.d_tiles, p.cfg_off[CFG], d_tabs,
+                     s, pws);
   HIP_CHECK_LAUNCH();
-  prof_mark(st, PROF_GEMM_CFG0 + CFG, p.cfg_flops[CFG], p.cfg_bytes[CFG]);
+  prof_mark(st, PROF_GEMM_CFG0 + CFG, nb * p.cfg_flops[CFG], nb * p.cfg_bytes[CFG]);
 }
 
 template <int PREC>
-void launch_prec(const GemmPlan& p, const long long* d_tabs, Slots s, double* pws, hipStream_t st) {
-  launch_cfg<0, PREC>(p, d_tabs, s, pws, st);
-  launch_cfg<1, PREC>(p, d_tabs, s, pws, st);
-  launch_cfg<2, PREC>(p, d_tabs, s, pws, st);
-  launch_cfg<3, PREC>(p, d_tabs, s, pws, st);
-  launch_cfg<4, PREC>(p, d_tabs, s, pws, st);
+void launch_prec(const GemmPlan& p, const long long* d_tabs, const BSlots& s, int nb, BPtr<double> pws, hipStream_t st) {
+  launch_cfg<0, PREC>(p, d_tabs, s, nb, pws, st);
+  launch_cfg<1, PREC>(p, d_tabs, s, nb, pws, st);
+  launch_cfg<2, PREC>(p, d_tabs, s, nb, pws, st);
+  launch_cfg<3, PREC>(p, d_tabs, s, nb, pws, st);
+  launch_cfg<4, PREC>(p, d_tabs, s, nb, pws, st);
 }
 
-void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precision, double* pws, hipStream_t st) {
+void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, int nb, int precision,
+                 BPtr<double> pws, hipStream_t st) {
   if (p.ntiles == 0 && p.wave_blocks == 0) return;
+  TT_REQUIRE(nb >= 1 && nb <= kMaxBatch, TT_EINVAL, "batch size out of range");
   prof_begin(st);
   if (p.wave_blocks > 0) {
     if (precision == TT_FP64)
-      hipLaunchKernelGGL(k_wgemm<TT_FP64>, dim3(p.wave_blocks), dim3(256), 0, st, p.d_probs, p.d_jobs, p.wave_blocks,
-                         d_tabs, s);
+      hipLaunchKernelGGL(k_wgemm<TT_FP64>, dim3(p.wave_blocks, nb), dim3(256), 0, st, p.d_probs, p.d_jobs,
+                         p.wave_blocks, d_tabs, s);
     else if (precision == TT_FP32)
-      hipLaunchKernelGGL(k_wgemm<TT_FP32>, dim3(p.wave_blocks), dim3(256), 0, st, p.d_probs, p.d_jobs, p.wave_blocks,
-                         d_tabs, s);
+      hipLaunchKernelGGL(k_wgemm<TT_FP32>, dim3(p.wave_blocks, nb), dim3(256), 0, st, p.d_probs, p.d_jobs,
+                         p.wave_blocks, d_tabs, s);
     else
       throw Error(TT_EINVAL, "the wave GEMM runs FP64 or FP32 only: plan built for another precision");
     HIP_CHECK_LAUNCH();
-    prof_mark(st, PROF_GEMM_WAVE, p.wave_flops, p.wave_bytes);
+    prof_mark(st, PROF_GEMM_WAVE, nb * p.wave_flops, nb * p.wave_bytes);
   }
   switch (precision) {
-    case TT_FP64: launch_prec<TT_FP64>(p, d_tabs, s, pws, st); break;
-    case TT_FP32: launch_prec<TT_FP32>(p, d_tabs, s, pws, st); break;
-    case TT_BF16X3: launch_prec<TT_BF16X3>(p, d_tabs, s, pws, st); break;
-    case TT_BF16X6: launch_prec<TT_BF16X6>(p, d_tabs, s, pws, st); break;
+    case TT_FP64: launch_prec<TT_FP64>(p, d_tabs, s, nb, pws, st); break;
+    case TT_FP32: launch_prec<TT_FP32>(p, d_tabs, s, nb, pws, st); break;
+    case TT_BF16X3: launch_prec<TT_BF16X3>(p, d_tabs, s, nb, pws, st); break;
+    case TT_BF16X6: launch_prec<TT_BF16X6>(p, d_tabs, s, nb, pws, st); break;
     default: throw Error(TT_EINVAL, "unknown precision");
   }
   if (!p.splits.empty()) {
-    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)p.splits.size()), dim3(256), 0, st, p.d_probs, p.d_splits,
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)p.splits.size(), nb), dim3(256), 0, st, p.d_probs, p.d_splits,
                        d_tabs, s, pws);
     HIP_CHECK_LAUNCH();
-    prof_mark(st, PROF_GEMM_REDUCE, 0.0, p.red_bytes);
+    prof_mark(st, PROF_GEMM_REDUCE, 0.0, nb * p.red_bytes);
   }
-  prof_end(st, p.tag, p.flops, p.bytes);
+  prof_end(st, p.tag, nb * p.flops, nb * p.bytes);
 }
 
 // ------------------------------------------------------------------ W stage
@@ -663,10 +671,8 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, Slots s, int precis
 #ifndef TT_WSTAGE_THREADS
 #define TT_WSTAGE_THREADS 256
 #endif
-__global__ __launch_bounds__(TT_WSTAGE_THREADS) void k_wstage(const WTask* __restrict__ tasks,
-                                                              const WTerm* __restrict__ terms,
-                                                              const double* __restrict__ in, double* __restrict__ out) {
-  const WTask t = tasks[blockIdx.x];
+__device__ __forceinline__ void wstage_task(const WTask& t, const WTerm* __restrict__ terms,
+                                            const double* __restrict__ in, double* __restrict__ out) {
   const int n = t.ni * t.nj;
   for (int e = threadIdx.x; e < n; e += TT_WSTAGE_THREADS) {
     const int i = e / t.nj, j = e - i * t.nj;
@@ -679,12 +685,20 @@ __global__ __launch_bounds__(TT_WSTAGE_THREADS) void k_wstage(const WTask* __res
   }
 }
 
-void launch_wstage(const WPlan& p, const double* in, double* out, hipStream_t st) {
+__global__ __launch_bounds__(TT_WSTAGE_THREADS) void k_wstage(const WTask* __restrict__ tasks,
+                                                              BPtr<const WTerm> b_terms, BPtr<const double> b_in,
+                                                              BPtr<double> b_out) {
+  const int ib = blockIdx.y;
+  wstage_task(tasks[blockIdx.x], b_terms.p[ib], b_in.p[ib], b_out.p[ib]);
+}
+
+void launch_wstage(const WPlan& p, BPtr<const WTerm> terms, BPtr<const double> in, BPtr<double> out, int nb,
+                   hipStream_t st) {
   if (p.ntasks == 0) return;
   prof_begin(st);
-  hipLaunchKernelGGL(k_wstage, dim3(p.ntasks), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, p.d_terms, in, out);
+  hipLaunchKernelGGL(k_wstage, dim3(p.ntasks, nb), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, terms, in, out);
   HIP_CHECK_LAUNCH();
-  prof_end(st, PROF_WSTAGE, p.flops, p.bytes);
+  prof_end(st, PROF_WSTAGE, nb * p.flops, nb * p.bytes);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -709,7 +723,11 @@ __device__ double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ QR
 __global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
-                                                 const long long* __restrict__ tabs, double* A, double* S, double* ws) {
+                                                 const long long* __restrict__ tabs, BPtr<double> b_A, BPtr<double> b_S,
+                                                 BPtr<double> b_ws) {
+  double* A = b_A.p[blockIdx.y];
+  double* S = b_S.p[blockIdx.y];
+  double* ws = b_ws.p[blockIdx.y];
   __shared__ double red[8];
   __shared__ double s_tau[1];
   const QRTask T = tasks[wide[blockIdx.x]];
@@ -899,8 +917,11 @@ __device__ __forceinline__ long long qr_row(const QRTask& T, const long long* ta
 // (sign fix, Q to the matrix, R to S); otherwise Q_c goes to ws[qw] and R_c
 // (upper n x n) to the stacked R at ws[rw] (column-major, leading dim nchunks*n).
 __global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ tasks, const QRChunk* __restrict__ chunks,
-                                                   const long long* __restrict__ tabs, double* A, double* S,
-                                                   double* ws) {
+                                                   const long long* __restrict__ tabs, BPtr<double> b_A,
+                                                   BPtr<double> b_S, BPtr<double> b_ws) {
+  double* A = b_A.p[blockIdx.y];
+  double* S = b_S.p[blockIdx.y];
+  double* ws = b_ws.p[blockIdx.y];
   extern __shared__ double lds[];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRChunk C = chunks[blockIdx.x];
@@ -942,7 +963,9 @@ __global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ ta
 // kernel 2: QR of the stacked chunk R factors; final R (non-negative
 // diagonal) to S, second-level Q (sign-fixed) back over the stack.
 __global__ __launch_bounds__(1024) void k_qr_stack(const QRTask* __restrict__ tasks, const QRStack* __restrict__ stacks,
-                                                   double* S, double* ws) {
+                                                   BPtr<double> b_S, BPtr<double> b_ws) {
+  double* S = b_S.p[blockIdx.y];
+  double* ws = b_ws.p[blockIdx.y];
   extern __shared__ double lds[];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRStack K = stacks[blockIdx.x];
@@ -969,8 +992,10 @@ __global__ __launch_bounds__(1024) void k_qr_stack(const QRTask* __restrict__ ta
 
 // kernel 3: final Q rows of a chunk = Q_c (rows x n) . Q2_c (n x n)
 __global__ __launch_bounds__(256) void k_qr_combine(const QRTask* __restrict__ tasks, const QRChunk* __restrict__ chunks,
-                                                    const long long* __restrict__ tabs, double* A,
-                                                    const double* __restrict__ ws) {
+                                                    const long long* __restrict__ tabs, BPtr<double> b_A,
+                                                    BPtr<double> b_ws) {
+  double* A = b_A.p[blockIdx.y];
+  const double* __restrict__ ws = b_ws.p[blockIdx.y];
   __shared__ double Q2[kQrLdsMaxN * kQrLdsMaxN];
   const QRChunk C = chunks[blockIdx.x];
   if (C.nchunks == 1) return;
@@ -1018,7 +1043,8 @@ void qr_plan_chunks(QRPlan& p) {
   p.lds_ws = pos;
 }
 
-void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, double* ws, hipStream_t st) {
+void launch_qr(const QRPlan& p, const long long* d_tabs, BPtr<double> A, BPtr<double> S, BPtr<double> ws, int nb,
+               hipStream_t st) {
   if (p.ntasks == 0) return;
   static bool attr = false;
   const size_t shm = sizeof(double) * kQrLdsDoubles;
@@ -1029,25 +1055,27 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, double* A, double* S, d
     attr = true;
   }
   prof_begin(st);
-  double* lws = ws + p.ws_size;
+  BPtr<double> lws = ws;   // the LDS path's workspace follows the global fallback's
+  for (int b = 0; b < nb; ++b) lws.p[b] = ws.p[b] + p.ws_size;
   if (!p.chunks.empty()) {
-    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size()), dim3(1024), shm, st, p.d_tasks, p.d_chunks, d_tabs,
-                       A, S, lws);
+    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size(), nb), dim3(1024), shm, st, p.d_tasks, p.d_chunks,
+                       d_tabs, A, S, lws);
     HIP_CHECK_LAUNCH();
   }
   if (!p.stacks.empty()) {
-    hipLaunchKernelGGL(k_qr_stack, dim3((unsigned)p.stacks.size()), dim3(1024), shm, st, p.d_tasks, p.d_stacks, S, lws);
+    hipLaunchKernelGGL(k_qr_stack, dim3((unsigned)p.stacks.size(), nb), dim3(1024), shm, st, p.d_tasks, p.d_stacks, S,
+                       lws);
     HIP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_qr_combine, dim3((unsigned)p.chunks.size()), dim3(256), 0, st, p.d_tasks, p.d_chunks, d_tabs,
-                       A, lws);
+    hipLaunchKernelGGL(k_qr_combine, dim3((unsigned)p.chunks.size(), nb), dim3(256), 0, st, p.d_tasks, p.d_chunks,
+                       d_tabs, A, lws);
     HIP_CHECK_LAUNCH();
   }
   if (!p.wide.empty()) {
-    hipLaunchKernelGGL(k_qr_wide, dim3((unsigned)p.wide.size()), dim3(256), 0, st, p.d_tasks, p.d_wide, d_tabs, A, S,
-                       ws);
+    hipLaunchKernelGGL(k_qr_wide, dim3((unsigned)p.wide.size(), nb), dim3(256), 0, st, p.d_tasks, p.d_wide, d_tabs, A,
+                       S, ws);
     HIP_CHECK_LAUNCH();
   }
-  prof_end(st, PROF_QR, p.flops, p.bytes);
+  prof_end(st, PROF_QR, nb * p.flops, nb * p.bytes);
 }
 
 // ------------------------------------------------------------------ Lanczos
@@ -1091,9 +1119,12 @@ __device__ __forceinline__ void red_chunk(long long n, long long& i0, long long&
 // part[b*(nv+self) + v] = sum over block b's chunk of Q_v[i] * y[i]; last entry y.y if with_self.
 // One pass: y and every Q_v are read once.
 template <int MAXV>
-__global__ __launch_bounds__(kRedThreads) void k_mdot(const double* __restrict__ Q, long long ld, int nv,
-                                              const double* __restrict__ y, long long n, int with_self,
-                                              double* __restrict__ part) {
+__global__ __launch_bounds__(kRedThreads) void k_mdot(BPtr<const double> b_Q, long long ld, int nv,
+                                                      BPtr<const double> b_y, long long n, int with_self,
+                                                      BPtr<double> b_part) {
+  const double* __restrict__ Q = b_Q.p[blockIdx.y];
+  const double* __restrict__ y = b_y.p[blockIdx.y];
+  double* __restrict__ part = b_part.p[blockIdx.y];
   __shared__ double red[(kRedThreads / 64) * (MAXV + 1)];
   long long i0, i1;
   red_chunk(n, i0, i1);
@@ -1133,8 +1164,12 @@ __device__ __forceinline__ void gather_parts(const double* __restrict__ part, in
 }
 
 // q0 = v / ||v||; scal[0] = ||v||
-__global__ void k_lz_start(const double* __restrict__ v, double* __restrict__ q0, long long n,
-                           const double* __restrict__ part, double* scal) {
+__global__ void k_lz_start(BPtr<const double> b_v, BPtr<double> b_q0, long long n, BPtr<const double> b_part,
+                           BPtr<double> b_scal) {
+  const double* __restrict__ v = b_v.p[blockIdx.y];
+  double* __restrict__ q0 = b_q0.p[blockIdx.y];
+  const double* __restrict__ part = b_part.p[blockIdx.y];
+  double* scal = b_scal.p[blockIdx.y];
   __shared__ double s_nv;
   gather_parts(part, 1, 1, &s_nv);
   __syncthreads();
@@ -1151,10 +1186,16 @@ __global__ void k_lz_start(const double* __restrict__ v, double* __restrict__ q0
 // same pass the partial dots Q_v . w of the updated chunk and its partial w . w
 // (part_out stride nv + 1).
 template <int MAXV>
-__global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(double* __restrict__ w, const double* __restrict__ Q,
-                                                            long long ld, int nv, const double* __restrict__ part_in,
-                                                            int stride_in, long long n, double* alpha_out,
-                                                            double* hn_out, double* __restrict__ part_out) {
+__global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(BPtr<double> b_w, BPtr<const double> b_Q, long long ld,
+                                                            int nv, BPtr<const double> b_part_in, int stride_in,
+                                                            long long n, BPtr<double> b_alpha, BPtr<double> b_hn,
+                                                            BPtr<double> b_part_out) {
+  double* __restrict__ w = b_w.p[blockIdx.y];
+  const double* __restrict__ Q = b_Q.p[blockIdx.y];
+  const double* __restrict__ part_in = b_part_in.p[blockIdx.y];
+  double* alpha_out = b_alpha.p[blockIdx.y];
+  double* hn_out = b_hn.p[blockIdx.y];
+  double* __restrict__ part_out = b_part_out.p[blockIdx.y];
   __shared__ double c[kMaxKrylov + 1];
   __shared__ double red[(kRedThreads / 64) * (MAXV + 1)];
   gather_parts(part_in, stride_in, stride_in > nv ? nv + 1 : nv, c);
@@ -1195,10 +1236,16 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_sub_dot(double* __restrict__
 // are O(eps ||H q||), and so is the computed beta: the test beta <= tol ||H q||
 // still holds.)  qn = null: only beta is stored.
 template <int MAXV>
-__global__ __launch_bounds__(kRedThreads) void k_lz_sub_next(const double* __restrict__ w, const double* __restrict__ Q,
-                                                             long long ld, int nv, const double* __restrict__ part_in,
-                                                             long long n, double* __restrict__ qn, double* beta_out,
-                                                             const double* hn, double tol) {
+__global__ __launch_bounds__(kRedThreads) void k_lz_sub_next(BPtr<const double> b_w, BPtr<const double> b_Q,
+                                                             long long ld, int nv, BPtr<const double> b_part_in,
+                                                             long long n, BPtr<double> b_qn, BPtr<double> b_beta,
+                                                             BPtr<const double> b_hn, double tol) {
+  const double* __restrict__ w = b_w.p[blockIdx.y];
+  const double* __restrict__ Q = b_Q.p[blockIdx.y];
+  const double* __restrict__ part_in = b_part_in.p[blockIdx.y];
+  double* __restrict__ qn = b_qn.p[blockIdx.y];
+  double* beta_out = b_beta.p[blockIdx.y];
+  const double* hn = b_hn.p[blockIdx.y];
   __shared__ double c[kMaxKrylov + 1];
   __shared__ double s_inv;
   gather_parts(part_in, nv + 1, nv + 1, c);
@@ -1232,9 +1279,13 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_sub_next(const double* __res
 }
 
 // out = sum_v coeff_v Q_v and the partial out . out of each chunk
-__global__ __launch_bounds__(kRedThreads) void k_lz_combine_norm(const double* __restrict__ Q, long long ld, int K,
-                                                         const double* __restrict__ coeff, double* __restrict__ out,
-                                                         long long n, double* __restrict__ part_out) {
+__global__ __launch_bounds__(kRedThreads) void k_lz_combine_norm(BPtr<const double> b_Q, long long ld, int K,
+                                                                 BPtr<const double> b_coeff, BPtr<double> b_out,
+                                                                 long long n, BPtr<double> b_part_out) {
+  const double* __restrict__ Q = b_Q.p[blockIdx.y];
+  const double* __restrict__ coeff = b_coeff.p[blockIdx.y];
+  double* __restrict__ out = b_out.p[blockIdx.y];
+  double* __restrict__ part_out = b_part_out.p[blockIdx.y];
   __shared__ double c[kMaxKrylov];
   __shared__ double red[kRedThreads / 64];
   if (threadIdx.x < K) c[threadIdx.x] = coeff[threadIdx.x];
@@ -1256,9 +1307,16 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_combine_norm(const double* _
 // coefficients of exp(t T) e_1 * ||v|| for the Krylov tridiagonal T: Taylor
 // series of (tT)/2^s with 2^s >= 2 ||tT||_inf, then s squarings; one thread per
 // matrix element, everything in LDS.
-__global__ __launch_bounds__(256) void k_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K,
-                                                   double t, double tol, const double* scal, double* coeff,
-                                                   double* errmax) {
+__global__ __launch_bounds__(256) void k_lz_coeffs(BPtr<const double> b_alpha, BPtr<const double> b_beta,
+                                                   BPtr<const double> b_hn, int K, double t, double tol,
+                                                   BPtr<const double> b_scal, BPtr<double> b_coeff,
+                                                   BPtr<double> b_err) {
+  const double* alpha = b_alpha.p[blockIdx.y];
+  const double* beta = b_beta.p[blockIdx.y];
+  const double* hn = b_hn.p[blockIdx.y];
+  const double* scal = b_scal.p[blockIdx.y];
+  double* coeff = b_coeff.p[blockIdx.y];
+  double* errmax = b_err.p[blockIdx.y];
   __shared__ double A[kMaxKrylov * kMaxKrylov], E[kMaxKrylov * kMaxKrylov], P[kMaxKrylov * kMaxKrylov],
       X[kMaxKrylov * kMaxKrylov];
   __shared__ int s_k, s_sq;
@@ -1328,7 +1386,10 @@ __global__ __launch_bounds__(256) void k_lz_coeffs(const double* alpha, const do
 }
 
 // v /= ||v||; lambda += ln ||v||
-__global__ void k_normalize_log(double* __restrict__ v, long long n, const double* __restrict__ part, double* lambda) {
+__global__ void k_normalize_log(BPtr<double> b_v, long long n, BPtr<const double> b_part, BPtr<double> b_lambda) {
+  double* __restrict__ v = b_v.p[blockIdx.y];
+  const double* __restrict__ part = b_part.p[blockIdx.y];
+  double* lambda = b_lambda.p[blockIdx.y];
   __shared__ double s_n;
   gather_parts(part, 1, 1, &s_n);
   __syncthreads();
@@ -1339,7 +1400,9 @@ __global__ void k_normalize_log(double* __restrict__ v, long long n, const doubl
     v[i] *= inv;
 }
 
-__global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long long n) {
+__global__ void k_copy(BPtr<double> b_d, BPtr<const double> b_s, long long n) {
+  double* __restrict__ d = b_d.p[blockIdx.y];
+  const double* __restrict__ s = b_s.p[blockIdx.y];
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     d[i] = s[i];
 }
@@ -1367,43 +1430,49 @@ static int grid_for(long long n) {
     else hipLaunchKernelGGL(KERNEL<kMaxKrylov + 1>, __VA_ARGS__);                                \
   } while (0)
 
-void launch_mdot(const double* Q, long long ld, int nv, const double* y, long long n, int with_self, double* part,
-                 hipStream_t st) {
-  TT_BY_MAXV(nv + with_self, k_mdot, dim3(kRedBlocks), dim3(kRedThreads), 0, st, Q, ld, nv, y, n, with_self, part);
+void launch_mdot(BPtr<const double> Q, long long ld, int nv, BPtr<const double> y, long long n, int with_self,
+                 BPtr<double> part, int nb, hipStream_t st) {
+  TT_BY_MAXV(nv + with_self, k_mdot, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, st, Q, ld, nv, y, n, with_self, part);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_start(const double* v, double* q0, long long n, const double* part, double* scal, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_start, dim3(grid_for(n)), dim3(256), 0, st, v, q0, n, part, scal);
+void launch_lz_start(BPtr<const double> v, BPtr<double> q0, long long n, BPtr<const double> part, BPtr<double> scal,
+                     int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_start, dim3(grid_for(n), nb), dim3(256), 0, st, v, q0, n, part, scal);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_sub_dot(double* w, const double* Q, long long ld, int nv, const double* part_in, int stride_in,
-                       long long n, double* alpha_out, double* hn_out, double* part_out, hipStream_t st) {
-  TT_BY_MAXV(nv, k_lz_sub_dot, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, stride_in, n, alpha_out,
-             hn_out, part_out);
+void launch_lz_sub_dot(BPtr<double> w, BPtr<const double> Q, long long ld, int nv, BPtr<const double> part_in,
+                       int stride_in, long long n, BPtr<double> alpha_out, BPtr<double> hn_out, BPtr<double> part_out,
+                       int nb, hipStream_t st) {
+  TT_BY_MAXV(nv, k_lz_sub_dot, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, stride_in, n,
+             alpha_out, hn_out, part_out);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_sub_next(const double* w, const double* Q, long long ld, int nv, const double* part_in, long long n,
-                        double* qn, double* beta_out, const double* hn, double tol, hipStream_t st) {
-  TT_BY_MAXV(nv, k_lz_sub_next, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, n, qn, beta_out, hn,
-             tol);
+void launch_lz_sub_next(BPtr<const double> w, BPtr<const double> Q, long long ld, int nv, BPtr<const double> part_in,
+                        long long n, BPtr<double> qn, BPtr<double> beta_out, BPtr<const double> hn, double tol,
+                        int nb, hipStream_t st) {
+  TT_BY_MAXV(nv, k_lz_sub_next, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, st, w, Q, ld, nv, part_in, n, qn, beta_out,
+             hn, tol);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_combine_norm(const double* Q, long long ld, int K, const double* coeff, double* out, long long n,
-                            double* part_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_combine_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, Q, ld, K, coeff, out, n, part_out);
+void launch_lz_combine_norm(BPtr<const double> Q, long long ld, int K, BPtr<const double> coeff, BPtr<double> out,
+                            long long n, BPtr<double> part_out, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_combine_norm, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, st, Q, ld, K, coeff, out, n,
+                     part_out);
   HIP_CHECK_LAUNCH();
 }
-void launch_lz_coeffs(const double* alpha, const double* beta, const double* hn, int K, double t, double tol,
-                      const double* scal, double* coeff, double* errmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_coeffs, dim3(1), dim3(256), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
+void launch_lz_coeffs(BPtr<const double> alpha, BPtr<const double> beta, BPtr<const double> hn, int K, double t,
+                      double tol, BPtr<const double> scal, BPtr<double> coeff, BPtr<double> errmax, int nb,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_coeffs, dim3(1, nb), dim3(256), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
   HIP_CHECK_LAUNCH();
 }
-void launch_normalize_log(double* v, long long n, const double* part, double* lambda, hipStream_t st) {
-  hipLaunchKernelGGL(k_normalize_log, dim3(grid_for(n)), dim3(256), 0, st, v, n, part, lambda);
+void launch_normalize_log(BPtr<double> v, long long n, BPtr<const double> part, BPtr<double> lambda, int nb,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize_log, dim3(grid_for(n), nb), dim3(256), 0, st, v, n, part, lambda);
   HIP_CHECK_LAUNCH();
 }
-void launch_copy(double* dst, const double* src, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
+void launch_copy(BPtr<double> dst, BPtr<const double> src, long long n, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n), nb), dim3(256), 0, st, dst, src, n);
   HIP_CHECK_LAUNCH();
 }
 void launch_fill(double* dst, double val, long long n, hipStream_t st) {

@@ -213,3 +213,55 @@ def test_mixed_precision_truncated_vs_oracle(prec):
     assert _rel(o["f"], r["f"]) <= TOL_MIXED, (o["f"], r["f"])
     assert _rel(o["e"], r["e"]) <= TOL_MIXED, (o["e"], r["e"])
     st.free()
+
+
+def _grouped_launches(fn):
+    T.tt_profile_enable(True)
+    fn()
+    T.tt_profile_enable(False)
+    return T.tt_profile_read()["gemm"]["launches"]
+
+
+def test_batch_shares_launches_and_matches_single_sweeps():
+    # a mu-scan: identical plans, different couplings -> one launch per contraction for the whole batch
+    mus = [0.7, 1.3, 2.1, 2.9, 3.6]
+    o = T.options(D=24, symmetry=1, beta0=0.01, pad_eps=0.3, seed=7)
+    batch = [T.State.init(T.model(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, mu), o) for mu in mus]
+    single = [T.State.init(T.model(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, mu), o) for mu in mus]
+    n_batch = _grouped_launches(lambda: T.tdvp_sweep_batch([s.h for s in batch], 0.05))
+    n_one = _grouped_launches(lambda: single[0].sweep(0.05))
+    assert n_batch == n_one
+    for s in single[1:]:
+        s.sweep(0.05)
+    T.tdvp_sweep_batch([s.h for s in batch], 0.05)
+    for s in single:
+        s.sweep(0.05)
+    for a, b in zip(batch, single):
+        assert a.observables() == b.observables()
+        for k in range(a.info()[0]):
+            assert np.array_equal(a.export_site(k), b.export_site(k))
+    for s in batch + single:
+        s.free()
+
+
+def test_batch_with_different_plans_falls_back_to_groups():
+    # mu = U/2 zeroes MPO entries and D differs: these states cannot share launches
+    m = [T.model(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, mu) for mu in (1.0, 4.0, 1.0)]
+    opts = [T.options(D=d, symmetry=1, beta0=0.01, pad_eps=0.3, seed=5) for d in (20, 20, 16)]
+    batch = [T.State.init(mm, oo) for mm, oo in zip(m, opts)]
+    single = [T.State.init(mm, oo) for mm, oo in zip(m, opts)]
+    T.tdvp_sweep_batch([s.h for s in batch], 0.1)
+    for s in single:
+        s.sweep(0.1)
+    for a, b in zip(batch, single):
+        assert a.observables() == b.observables()
+    for s in batch + single:
+        s.free()
+
+
+def test_batch_rejects_duplicates():
+    st = T.State.init(T.model(1, 4, T.TT_CHAIN, 1.0, 4.0, 0.0), T.options(D=16, symmetry=1, beta0=0.01))
+    with pytest.raises(T.TTError) as e:
+        T.tdvp_sweep_batch([st.h, st.h], 0.1)
+    assert e.value.code == T.TT_EINVAL
+    st.free()
