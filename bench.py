@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-D", type=int, default=1500, help="bond dimension of the oracle sample")
+    ap.add_argument("--mu-scan", type=int, default=8,
+                    help="instances of the batched mu-scan on the 6x12 cylinder (0: skip)")
+    ap.add_argument("--mu-scan-D", type=int, default=0, help="override the mu-scan bond dimension")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (--gpus 1); multi-GPU runs are not part of this build",
@@ -189,6 +192,41 @@ def main():
                        gbs=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0)
                for k, v in prof.items()}
 
+    # batched mu-scan: instances with identical plans advance in shared launches
+    mu_scan = None
+    if args.mu_scan > 0:
+        c4 = WL.MODELS["cl6x12"]
+        D4 = args.mu_scan_D or c4["D"]
+        mus = WL.MU_SCAN[:args.mu_scan]
+        o4 = T.options(D=D4, symmetry=1, beta0=c4["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c4["krylov"],
+                       precision=PREC[args.precision])
+        print("init mu-scan: %d x 6x12 cylinder D=%d" % (len(mus), D4), file=sys.stderr, flush=True)
+        sts = [T.State.init(T.model(c4["W"], c4["L"], c4["geometry"], c4["t"], c4["U"], mu), o4) for mu in mus]
+        hs = [st.h for st in sts]
+        T.tdvp_sweep_batch(hs, c4["dbeta"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fl = 0.0
+        for i in range(args.steps):
+            fl += T.tdvp_sweep_batch(hs, c4["dbeta"], stats=True).flops_alg
+        torch.cuda.synchronize()
+        s_batch = (time.perf_counter() - t0) / args.steps
+        print("mu-scan batch done", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            sts[0].sweep(c4["dbeta"])
+        torch.cuda.synchronize()
+        s_single = (time.perf_counter() - t0) / args.steps
+        dens = [st.observables() for st in sts]
+        for st in sts:
+            st.free()
+        mu_scan = dict(workload="Hubbard 6x12 cylinder, U=8, U(1)xU(1) D=%d, d_beta=%g, mu = %s"
+                       % (D4, c4["dbeta"], ", ".join("%.4g" % m for m in mus)),
+                       instances=len(mus), batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
+                       single_instance_s_per_step=s_single, speedup_vs_one_at_a_time=s_single * len(mus) / s_batch,
+                       tflops_alg=fl / args.steps / s_batch / 1e12,
+                       e_per_site=[d["e"] for d in dens])
+
     # dense effective-Hamiltonian apply at D (microbenchmark)
     heff = {}
     Dh, DH = args.heff_D, 18
@@ -248,6 +286,7 @@ def main():
                   "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
                   "other_precisions": mixed},
         "heff": {"D": Dh, "D_H": DH, **heff},
+        "mu_scan": mu_scan,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
