@@ -30,7 +30,7 @@ SHAPES = ("64x64", "128x32", "256x16", "32x128", "32x32")
 def kernel_name(kind, prec):
     if kind.startswith("k_gemm_") and kind != "k_gemm_reduce":
         return "tt::k_gemm<%d, %d>" % (SHAPES.index(kind[len("k_gemm_"):]), prec)
-    return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm<%d>" % prec, "wstage": "tt::k_wstage",
+    return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm", "wstage": "tt::k_wstage",
             "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
 
 
@@ -167,7 +167,9 @@ def main():
     sec = pk["ms"] * 1e-3
     is_mfma = (kind.startswith("k_gemm_") and kind != "k_gemm_reduce") or kind == "k_wgemm"
     if is_mfma:
-        pname = "fp64" if args.precision == "fp64" else ("fp32" if args.precision == "fp32" else "bf16")
+        # the wave GEMM multiplies in FP64 in every mode
+        pname = "fp64" if (args.precision == "fp64" or kind == "k_wgemm") else (
+            "fp32" if args.precision == "fp32" else "bf16")
         peak_f = PEAK[pname]
     else:
         peak_f = PEAK_FP64_VALU

@@ -123,6 +123,7 @@ struct tt_state {
   std::vector<Bond> bonds;                  // 0..N
   std::vector<std::vector<Q>> qH;           // environment MPO charges per bond
   std::vector<std::vector<double>> Wenv;    // environment MPO tensors per site
+  std::vector<std::vector<double>> Wpat;    // the same for generic couplings (nonzero pattern of the lattice)
   std::vector<SiteLayout> site;
   std::vector<EnvLayout> env;
   std::vector<BondMatLayout> bmat;
@@ -395,14 +396,21 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   for (int k = 0; k < N; ++k)
     for (int a = 0; a < s.mpo.DH[k]; ++a) s.qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : s.mpo.charge(k, a));
   s.qH[N] = {Q{0, 0}};
-  s.Wenv = s.mpo.W;
-  {
-    int DL = s.mpo.DH[N - 1], DR = s.mpo.DH[N];   // DR = 2: start, done
+  // W_{N-1} contracted with the done selector
+  auto env_tensors = [&](const Mpo& mpo) {
+    std::vector<std::vector<double>> W = mpo.W;
+    int DL = mpo.DH[N - 1], DR = mpo.DH[N];   // DR = 2: start, done
     std::vector<double> w((size_t)DL * 16, 0.0);
     for (int a = 0; a < DL; ++a)
-      for (int q = 0; q < 16; ++q) w[(size_t)a * 16 + q] = s.mpo.W[N - 1][((size_t)a * 16 + q) * DR + 1];
-    s.Wenv[N - 1] = w;
-  }
+      for (int q = 0; q < 16; ++q) w[(size_t)a * 16 + q] = mpo.W[N - 1][((size_t)a * 16 + q) * DR + 1];
+    W[N - 1] = w;
+    return W;
+  };
+  s.Wenv = env_tensors(s.mpo);
+  // the plans keep every MPO entry that is nonzero for generic couplings, so
+  // states that differ only in t, U, mu (an exact zero such as U - 2 mu at
+  // half filling included) get identical plans and can share launches
+  s.Wpat = env_tensors(make_hubbard_mpo(s.lat, 1.0, 1.0, 0.3));
   s.site.clear(); s.env.clear(); s.bmat.clear();
   for (int k = 0; k < N; ++k) s.site.push_back(make_site_layout(s.bonds[k], s.bonds[k + 1], s.G));
   for (int k = 0; k <= N; ++k) {
@@ -411,12 +419,21 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   }
   s.plans.clear();
   for (int k = 0; k < N; ++k)
-    s.plans.push_back(build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, s.qH[k], s.qH[k + 1], s.Wenv[k], s.tabs));
+    s.plans.push_back(
+        build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, s.qH[k], s.qH[k + 1], s.Wenv[k], s.Wpat[k], s.tabs));
   // the wave GEMM serves FP64 and FP32 launches; the absorb step always runs in FP64
   const bool wave = s.opts.precision == TT_FP64 || s.opts.precision == TT_FP32;
   for (auto& P : s.plans) {
     for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = wave;
     P.absL.wave_ok = P.absR.wave_ok = true;
+    if (s.opts.precision == TT_FP32) {
+      // FP32 mode keeps the intermediates of H_eff and of the environment
+      // updates (T1, T2, Y, Z) in float: half the memory traffic of those stages
+      P.s1.slot_f32[2] = P.r1.slot_f32[2] = true;   // T1, Y written
+      P.s3.slot_f32[0] = true;                      // T2 read
+      P.el.slot_f32[1] = P.r3.slot_f32[1] = true;   // T2, Z read
+      P.w2.f32 = P.wr.f32 = true;
+    }
   }
 }
 
@@ -891,7 +908,7 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   // the plan's W stage is replaced by a grouped GEMM reading W from device memory;
   // an all-zero W keeps the sparse W-stage plan empty
   std::vector<double> Wz((size_t)DH * 16 * DH, 0.0);
-  c.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, c.tabs);
+  c.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, Wz, c.tabs);
   // W stage as GEMMs: for each (x, sigma'): T2[(so,b)][y] = sum_(a,si) W[(so,b),(a,si)] T1[(a,si)][y]
   std::vector<long long> am, ak, bk, cm;
   for (int so = 0; so < 4; ++so)

@@ -422,23 +422,27 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 }
 
 // One wave's (16 FM) x (16 FN) output block from global memory, f64 MFMA
-// 16x16x4 (FP32 precision: f32 MFMA within each 16-deep K chunk, FP64 across
-// chunks).  In a chunk, lane (r, g) = (lane % 16, lane / 16) supplies row r /
-// column r at k = 4g + s on MFMA step s = 0..3, so the chunk's 16 products are
-// taken in a fixed permuted order and every lane reads four consecutive k.  The job
-// takes chunks part, part + nparts, ...  With nparts = 4 the four waves of the workgroup hold the four
+// 16x16x4 (in every precision mode: these blocks are bound by memory and
+// issue, so FP32 mode only keeps its float intermediates).  In a 16-deep chunk, lane (r, g) = (lane % 16, lane / 16) supplies
+// row r / column r at k = 4s + g on MFMA step s = 0..3 (the four lane groups
+// read four consecutive k).  The job takes chunks part, part + nparts, ...
+// With nparts = 4 the four waves of the workgroup hold the four
 // K parts of one block and wave 0 adds them in part order.
-template <int FM, int FN, int PREC>
+template <int FM, int FN>
 __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
                                           const Slots& slots, double* red) {
-  constexpr bool F64 = (PREC == TT_FP64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
   // operand bases are wave-uniform (scalar registers); element offsets from
-  // them fit 32 bits (checked when the plan is built)
+  // them fit 32 bits (checked when the plan is built).  Operands flagged in
+  // P.dt are float arrays (offsets count floats).
+  const bool fa = P.dt & kDtA, fb = P.dt & kDtB, fc = P.dt & kDtC;
   const double* __restrict__ A = slots.p[P.ia] + P.offA;
   const double* __restrict__ B = slots.p[P.ib] + P.offB;
   double* C = slots.p[P.ic] + P.offC;
+  const float* __restrict__ Af = reinterpret_cast<const float*>(slots.p[P.ia]) + P.offA;
+  const float* __restrict__ Bf = reinterpret_cast<const float*>(slots.p[P.ib]) + P.offB;
+  float* Cf = reinterpret_cast<float*>(slots.p[P.ic]) + P.offC;
   const int m0 = J.tm * 16 * FM, n0 = J.tn * 16 * FN;
   unsigned ra[FM], cb[FN];
 #pragma unroll
@@ -459,46 +463,36 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
     for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
   // no register double buffering, and a chunk is loaded in two halves of two
   // MFMA steps: few live registers, and the occupancy that buys hides the
-  // load latency better on these short loops
+  // load latency better on these short loops.  Steps past the end of K are
+  // skipped (most blocks of a sweep have K below 16).
   for (int c = J.part; c < nch; c += J.nparts) {
-    float4_t t[FM][FN];
-    if (!F64) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) t[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    }
+    const int ns = min(4, (P.K - 16 * c + 3) >> 2);   // steps holding a valid k (wave-uniform)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      if (2 * h >= ns) break;
       double a[FM][2], b[FN][2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int k = c * 16 + 4 * g + 2 * h + q;
+        const int k = c * 16 + 4 * (2 * h + q) + g;
         const bool ok = k < P.K;
         const unsigned ka = ok ? (unsigned)idx_map(tabs, P.tak, P.sak, k) : 0u;
         const unsigned kb = ok ? (unsigned)idx_map(tabs, P.tbk, P.sbk, k) : 0u;
 #pragma unroll
-        for (int i = 0; i < FM; ++i) a[i][q] = (ok && ra[i] != 0xffffffffu) ? A[ra[i] + ka] : 0.0;
+        for (int i = 0; i < FM; ++i)
+          a[i][q] = (ok && ra[i] != 0xffffffffu) ? (fa ? (double)Af[ra[i] + ka] : A[ra[i] + ka]) : 0.0;
 #pragma unroll
-        for (int j = 0; j < FN; ++j) b[j][q] = (ok && cb[j] != 0xffffffffu) ? B[kb + cb[j]] : 0.0;
+        for (int j = 0; j < FN; ++j)
+          b[j][q] = (ok && cb[j] != 0xffffffffu) ? (fb ? (double)Bf[kb + cb[j]] : B[kb + cb[j]]) : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < 2; ++q) {
+        if (2 * h + q >= ns) break;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) {
-            if (F64) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
-            else t[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i][q], (float)b[j][q], t[i][j], 0, 0, 0);
-          }
-    }
-    if (!F64) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)t[i][j][v];
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+      }
     }
   }
   if (J.nparts > 1) {   // uniform over the workgroup: its four jobs are the parts of one block
@@ -526,8 +520,8 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // accumulator row inside a 16x16 block: f64 MFMA lane/16 + 4v, f32 MFMA 4 (lane/16) + v
-      const int m = m0 + 16 * i + (F64 ? g + 4 * v : 4 * g + v);
+      // accumulator row inside a 16x16 block of the f64 MFMA: lane/16 + 4v
+      const int m = m0 + 16 * i + g + 4 * v;
       if (m >= P.M) continue;
       const unsigned rowc = (unsigned)idx_map(tabs, P.tcm, P.scm, m);
 #pragma unroll
@@ -535,15 +529,19 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
         const int n = n0 + 16 * j + r16;
         if (n >= P.N) continue;
         double val = P.alpha * acc[i][j][v];
-        if (P.beta != 0.0) val += P.beta * C[rowc + n];
-        C[rowc + n] = val;
+        if (fc) {
+          if (P.beta != 0.0) val += P.beta * (double)Cf[rowc + n];
+          Cf[rowc + n] = (float)val;
+        } else {
+          if (P.beta != 0.0) val += P.beta * C[rowc + n];
+          C[rowc + n] = val;
+        }
       }
     }
 }
 
 // six waves per SIMD: the register budget that fits six four-wave workgroups
 // (also the LDS limit of the split reduction buffer)
-template <int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
                                                int nblocks, const long long* __restrict__ tabs, BSlots bs) {
   __shared__ double red[3 * 1024];
@@ -555,9 +553,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   if (J.prob < 0) return;   // an unused slot: only in workgroups of unsplit jobs, which never synchronise
   const GemmProb P = probs[J.prob];
   switch (J.shape) {
-    case 0: wave_tile<4, 1, PREC>(P, J, tabs, slots, red); break;
-    case 1: wave_tile<2, 2, PREC>(P, J, tabs, slots, red); break;
-    default: wave_tile<1, 4, PREC>(P, J, tabs, slots, red); break;
+    case 0: wave_tile<4, 1>(P, J, tabs, slots, red); break;
+    case 1: wave_tile<2, 2>(P, J, tabs, slots, red); break;
+    default: wave_tile<1, 4>(P, J, tabs, slots, red); break;
   }
 }
 
@@ -637,12 +635,12 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
   TT_REQUIRE(nb >= 1 && nb <= kMaxBatch, TT_EINVAL, "batch size out of range");
   prof_begin(st);
   if (p.wave_blocks > 0) {
-    if (precision == TT_FP64)
-      hipLaunchKernelGGL(k_wgemm<TT_FP64>, dim3(p.wave_blocks, nb), dim3(256), 0, st, p.d_probs, p.d_jobs,
-                         p.wave_blocks, d_tabs, s);
-    else if (precision == TT_FP32)
-      hipLaunchKernelGGL(k_wgemm<TT_FP32>, dim3(p.wave_blocks, nb), dim3(256), 0, st, p.d_probs, p.d_jobs,
-                         p.wave_blocks, d_tabs, s);
+    // FP32 mode: the wave GEMM's blocks are bound by memory and issue, not by
+    // the MFMA rate, so it multiplies in FP64 and the precision reduction comes
+    // from the float intermediates (P.dt); the LDS-tile kernel uses FP32 MFMA
+    if (precision == TT_FP64 || precision == TT_FP32)
+      hipLaunchKernelGGL(k_wgemm, dim3(p.wave_blocks, nb), dim3(256), 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs,
+                         s);
     else
       throw Error(TT_EINVAL, "the wave GEMM runs FP64 or FP32 only: plan built for another precision");
     HIP_CHECK_LAUNCH();
@@ -671,34 +669,41 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
 #ifndef TT_WSTAGE_THREADS
 #define TT_WSTAGE_THREADS 256
 #endif
+template <typename TV>
 __device__ __forceinline__ void wstage_task(const WTask& t, const WTerm* __restrict__ terms,
-                                            const double* __restrict__ in, double* __restrict__ out) {
+                                            const TV* __restrict__ in, TV* __restrict__ out) {
   const int n = t.ni * t.nj;
   for (int e = threadIdx.x; e < n; e += TT_WSTAGE_THREADS) {
     const int i = e / t.nj, j = e - i * t.nj;
     double acc = 0.0;
     for (int q = 0; q < t.nt; ++q) {
       const WTerm w = terms[t.t0 + q];
-      acc += w.w * in[w.src + i * w.ssi + j * w.ssj];
+      acc += w.w * (double)in[w.src + i * w.ssi + j * w.ssj];
     }
-    out[t.dst + i * t.dsi + j * t.dsj] = acc;
+    out[t.dst + i * t.dsi + j * t.dsj] = (TV)acc;
   }
 }
 
+// TV: the stored type of the input and output intermediates (float in FP32 mode)
+template <typename TV>
 __global__ __launch_bounds__(TT_WSTAGE_THREADS) void k_wstage(const WTask* __restrict__ tasks,
                                                               BPtr<const WTerm> b_terms, BPtr<const double> b_in,
                                                               BPtr<double> b_out) {
   const int ib = blockIdx.y;
-  wstage_task(tasks[blockIdx.x], b_terms.p[ib], b_in.p[ib], b_out.p[ib]);
+  wstage_task<TV>(tasks[blockIdx.x], b_terms.p[ib], reinterpret_cast<const TV*>(b_in.p[ib]),
+                  reinterpret_cast<TV*>(b_out.p[ib]));
 }
 
 void launch_wstage(const WPlan& p, BPtr<const WTerm> terms, BPtr<const double> in, BPtr<double> out, int nb,
                    hipStream_t st) {
   if (p.ntasks == 0) return;
   prof_begin(st);
-  hipLaunchKernelGGL(k_wstage, dim3(p.ntasks, nb), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, terms, in, out);
+  if (p.f32)
+    hipLaunchKernelGGL(k_wstage<float>, dim3(p.ntasks, nb), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, terms, in, out);
+  else
+    hipLaunchKernelGGL(k_wstage<double>, dim3(p.ntasks, nb), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, terms, in, out);
   HIP_CHECK_LAUNCH();
-  prof_end(st, PROF_WSTAGE, nb * p.flops, nb * p.bytes);
+  prof_end(st, PROF_WSTAGE, nb * p.flops, nb * p.bytes * (p.f32 ? 0.5 : 1.0));
 }
 
 // ------------------------------------------------------------------ reductions

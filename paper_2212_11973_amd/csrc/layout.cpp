@@ -153,15 +153,23 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
   for (int c = 0; c < kGemmCfgs; ++c) p.cfg_flops[c] = p.cfg_bytes[c] = 0;
   // the wave kernel addresses operands with 32-bit byte offsets from each operand base
   const long long lim = 1LL << 29;
+  // float operands (dt) are read and written by the wave GEMM only
   std::vector<char> wave(p.probs.size(), 0);
   for (size_t i = 0; i < p.probs.size(); ++i) {
-    const GemmProb& g = p.probs[i];
-    if (!p.wave_ok || (g.M >= kLdsMinMN && g.N >= kLdsMinMN && g.K >= kLdsMinK)) continue;
+    GemmProb& g = p.probs[i];
+    g.dt = (p.slot_f32[g.ia] ? kDtA : 0) | (p.slot_f32[g.ib] ? kDtB : 0) | (p.slot_f32[g.ic] ? kDtC : 0);
+    if (!p.wave_ok) {
+      TT_REQUIRE(g.dt == 0, TT_EINVAL, "plan: float operands need the wave GEMM");
+      continue;
+    }
+    if (g.dt == 0 && g.M >= kLdsMinMN && g.N >= kLdsMinMN && g.K >= kLdsMinK) continue;
     TT_REQUIRE(tabs != nullptr, TT_EINVAL, "plan: wave GEMM planning needs the index tables");
     const long long a = map_max(tabs, g.tam, g.sam, g.M) + map_max(tabs, g.tak, g.sak, g.K);
     const long long b = map_max(tabs, g.tbk, g.sbk, g.K) + map_max(tabs, g.tbn, g.sbn, g.N);
     const long long c = map_max(tabs, g.tcm, g.scm, g.M) + g.N;
-    wave[i] = (a < lim && b < lim && c < lim) ? 1 : 0;
+    const bool fit = a < lim && b < lim && c < lim;
+    TT_REQUIRE(fit || g.dt == 0, TT_EINVAL, "plan: float operands beyond 32-bit offsets");
+    wave[i] = fit ? 1 : 0;
   }
   auto use_wave = [&](const GemmProb& g) { return wave[&g - p.probs.data()] != 0; };
   // wave jobs: split blocks (four K parts in one workgroup) first, then
@@ -174,7 +182,8 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
     const int tm = (g.M + kWaveBM[sh] - 1) / kWaveBM[sh], tn = (g.N + kWaveBN[sh] - 1) / kWaveBN[sh];
     const bool split = (g.K + 15) / 16 >= 8;   // every part then takes at least two 16-deep chunks
     p.wave_flops += 2.0 * g.M * g.N * g.K;
-    p.wave_bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+    p.wave_bytes += (g.dt & kDtA ? 4.0 : 8.0) * g.M * g.K + (g.dt & kDtB ? 4.0 : 8.0) * g.K * g.N +
+                    (g.dt & kDtC ? 4.0 : 8.0) * g.M * g.N;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
         if (split) {
@@ -232,7 +241,7 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
 
 SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<Q>& qHl, const std::vector<Q>& qHr,
-                         const std::vector<double>& W, SiteTables& tabs) {
+                         const std::vector<double>& W, const std::vector<double>& Wp, SiteTables& tabs) {
   (void)k;
   SitePlan P;
   const int DHl = (int)qHl.size(), DHr = (int)qHr.size();
@@ -240,6 +249,7 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
   EnvLayout EL = make_env_layout(bl, qHl);
   EnvLayout ER = make_env_layout(br, qHr);
   auto Wat = [&](int a, int so, int si, int b) { return W[(((size_t)a * 4 + so) * 4 + si) * DHr + b]; };
+  auto Wpat = [&](int a, int so, int si, int b) { return Wp[(((size_t)a * 4 + so) * 4 + si) * DHr + b]; };
   const int nr = (int)br.secs.size();
 
   // ---------------- stage 1: T1_l[(a,x)][cols of A_l] = L[x,a,l-block] . A_l
@@ -314,7 +324,7 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
               if (l < 0) continue;
               for (int sg = 0; sg < 4; ++sg) {
                 double w = Wat(a, so, sg, b);
-                if (w == 0.0) continue;
+                if (w == 0.0 && Wpat(a, so, sg, b) == 0.0) continue;
                 int s = sg * 4 + sa;
                 int gg = G.group_of[s];
                 TT_REQUIRE(S.rsec[l][gg] == c, TT_EINVAL, "plan: MPO entry breaks charge conservation");
@@ -443,7 +453,7 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
           for (int b = 0; b < DHr; ++b)
             for (int sg = 0; sg < 4; ++sg) {
               double w = Wat(a, so, sg, b);
-              if (w == 0.0) continue;
+              if (w == 0.0 && Wpat(a, so, sg, b) == 0.0) continue;
               int s = sg * 4 + sa;
               int gg = G.group_of[s];
               int c = S.rsec[l][gg];

@@ -17,9 +17,12 @@ struct Slots { double* p[kSlots]; };
 //   B(k,n) = slot[ib][offB + bk(k) + bn(n)]
 //   C(m,n) = slot[ic][offC + cm(m) + n]
 // where each index map is either i * stride (table < 0) or tables[table + i].
+// dt: operands stored as float instead of double (bit 0 A, bit 1 B, bit 2 C;
+// offsets then count floats); only the wave GEMM takes such problems.
+constexpr int kDtA = 1, kDtB = 2, kDtC = 4;
 struct GemmProb {
   int M, N, K;
-  int ia, ib, ic;
+  int ia, ib, ic, dt;
   long long offA, offB, offC;
   long long sam, sak, sbk, sbn, scm;
   long long tam, tak, tbk, tbn, tcm;
@@ -112,12 +115,15 @@ struct GemmPlan {
   double red_bytes = 0;     // the K-slice reduce: partials read once, C written once
   // wave-GEMM jobs (only when wave_ok: FP64 / FP32 launches)
   bool wave_ok = false;
+  // slots that hold float data (FP32 mode keeps the contraction intermediates in float)
+  bool slot_f32[kSlots] = {false, false, false, false};
   std::vector<GemmJob> jobs;
   GemmJob* d_jobs = nullptr;
   int wave_blocks = 0;
   double wave_flops = 0, wave_bytes = 0;
 };
 struct WPlan {
+  bool f32 = false;   // input and output stored as float
   std::vector<WTask> tasks;
   std::vector<WTerm> terms;
   WTask* d_tasks = nullptr;
@@ -217,7 +223,8 @@ struct SiteTables {
 
 SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<Q>& qHl, const std::vector<Q>& qHr,
-                         const std::vector<double>& W,   // DHl*16*DHr
+                         const std::vector<double>& W,    // DHl*16*DHr
+                         const std::vector<double>& Wp,   // pattern: entries kept when nonzero in W or Wp
                          SiteTables& tabs);
 
 // tile the problems of a plan (shape per problem)
