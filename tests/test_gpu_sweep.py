@@ -245,7 +245,7 @@ def test_batch_shares_launches_and_matches_single_sweeps():
 
 
 def test_batch_with_different_plans_falls_back_to_groups():
-    # mu = U/2 zeroes MPO entries and D differs: these states cannot share launches
+    # a different D gives different plans: that state runs in its own group
     m = [T.model(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, mu) for mu in (1.0, 4.0, 1.0)]
     opts = [T.options(D=d, symmetry=1, beta0=0.01, pad_eps=0.3, seed=5) for d in (20, 20, 16)]
     batch = [T.State.init(mm, oo) for mm, oo in zip(m, opts)]
@@ -265,3 +265,30 @@ def test_batch_rejects_duplicates():
         T.tdvp_sweep_batch([st.h, st.h], 0.1)
     assert e.value.code == T.TT_EINVAL
     st.free()
+
+
+def test_full_size_workload_properties():
+    # the benchmark's workload and launch configuration (4x16 cylinder, D=2000, FP64):
+    # properties that hold at any size, checked on sampled rows
+    c = WL.MODELS["cl4x16"]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    o = T.options(D=c["D"], symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"])
+    a, b = T.State.init(m, o), T.State.init(m, o)
+    for st in (a, b):
+        st.sweep(c["dbeta"])
+    oa, ob = a.observables(), b.observables()
+    assert oa == ob                                   # deterministic at full size
+    assert all(np.isfinite([oa["lnZ"], oa["E"], oa["f"], oa["lnZ_single"]]))
+    assert abs(oa["beta"] - (c["beta0"] + c["dbeta"])) < 1e-12
+    n, dims = a.info()
+    assert max(dims) == c["D"]
+    rng = np.random.default_rng(0)
+    A0 = a.export_site(0)
+    assert abs(np.linalg.norm(A0) - 1.0) < 1e-12      # the centre carries the norm
+    for k in (1, n // 2, n - 1):                      # right-canonical sites: orthonormal rows
+        A = a.export_site(k).reshape(dims[k], -1)
+        rows = rng.choice(dims[k], size=min(48, dims[k]), replace=False)
+        G = A[rows] @ A[rows].T
+        assert np.abs(G - np.eye(len(rows))).max() < 1e-11, k
+    a.free()
+    b.free()
