@@ -817,181 +817,253 @@ __global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ task
   }
 }
 
-// ---- LDS-resident Householder QR (column-major W[i + j*m] in LDS)
-// Column c belongs to wave c % nw, which does every update of that column.
-// Rows i > j of a column are always handled by lane (i - j - 1) % 64 of its
-// wave, both when the column is updated and when its reflector is made, so a
-// lane only reads LDS words it wrote itself; values shared across lanes pass
-// through registers (shuffles).  One barrier per step: while applying
-// reflector j, the owner of column j+1 updates that column first and then
-// turns it into reflector j+1 (look-ahead).
-
-// Make the reflector of column j from its current entries (one wave).  alpha:
-// the current diagonal entry, valid in every lane.  On return rows i > j hold
-// v (v_j = 1 implicit), the diagonal holds beta, tau[j] the factor.
-__device__ __forceinline__ void make_reflector(double* W, int m, int j, double alpha, double* tau) {
-  const int lane = threadIdx.x & 63;
-  double* col = W + (long long)j * m;
-  double part = 0.0;
-  for (int i = j + 1 + lane; i < m; i += 64) part += col[i] * col[i];
-  const double xn2 = __shfl(wave_sum(part), 0, 64);
-  double tj = 0.0;
-  if (xn2 > 0.0) {
-    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-    tj = (beta - alpha) / beta;
-    const double scal = 1.0 / (alpha - beta);
-    for (int i = j + 1 + lane; i < m; i += 64) col[i] *= scal;
-    if (lane == 0) col[j] = beta;
-  }
-  if (lane == 0) tau[j] = tj;
-}
-
-// Apply reflector j (tau tj, v below the diagonal of column j) to column c
-// (rows >= j); returns the new entry of row j+1 (valid in every lane).
-__device__ __forceinline__ double apply_reflector(double* W, int m, int j, double tj, int c) {
-  const int lane = threadIdx.x & 63;
-  const double* v = W + (long long)j * m;
-  double* col = W + (long long)c * m;
-  double d = 0.0;
-  for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-  d = __shfl(wave_sum(d), 0, 64) + col[j];
-  const double f = tj * d;
-  double r1 = 0.0;
-  for (int i = j + 1 + lane; i < m; i += 64) {
-    const double x = col[i] - f * v[i];
-    col[i] = x;
-    if (i == j + 1) r1 = x;
-  }
-  if (lane == 0) col[j] -= f;
-  return __shfl(r1, 0, 64);
-}
-
-// On return the upper triangle holds R (diagonal of either sign) and the
-// reflector vectors sit below the diagonal; tau[j] are their factors.
-__device__ void lds_householder(double* W, int m, int n, double* tau) {
-  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (wave == 0) make_reflector(W, m, 0, W[0], tau);
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double tj = tau[j];
-    // first owned column after j (the owner of j+1 starts with it)
-    int c = j + 1 + ((wave - (j + 1)) % nw + nw) % nw;
-    for (; c < n; c += nw) {
-      double diag_next = W[(long long)c * m + c];   // row c of column c (used when c == j+1)
-      if (tj != 0.0) {
-        const double r1 = apply_reflector(W, m, j, tj, c);
-        if (c == j + 1) diag_next = r1;
-      }
-      if (c == j + 1) make_reflector(W, m, j + 1, diag_next, tau);
-    }
-    __syncthreads();
-  }
-}
-
-// Overwrite the reflectors with the explicit m x n Q (backward accumulation:
-// column j starts as e_j).  R must have been saved before.  Column j is
-// rewritten by its owner at the start of step j-1 (after every wave has used
-// reflector j), so each step needs one barrier.
-__device__ void lds_form_q(double* W, int m, int n, const double* tau) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  auto rewrite = [&](int j) {   // column j := (I - tau_j v v^T) e_j, by its owner
-    const double tj = tau[j];
-    double* col = W + (long long)j * m;
-    for (int i = lane; i < j; i += 64) col[i] = 0.0;
-    for (int i = j + 1 + lane; i < m; i += 64) col[i] = -tj * col[i];
-    if (lane == 0) col[j] = 1.0 - tj;
-  };
-  for (int j = n - 1; j >= 0; --j) {
-    if (j + 1 < n && (j + 1) % nw == wave) rewrite(j + 1);
-    const double tj = tau[j];
-    if (tj != 0.0) {
-      int c = j + 1 + ((wave - (j + 1)) % nw + nw) % nw;
-      for (; c < n; c += nw) apply_reflector(W, m, j, tj, c);
-    }
-    __syncthreads();
-  }
-  if (wave == 0) rewrite(0);
-  __syncthreads();
-}
-
 __device__ __forceinline__ long long qr_row(const QRTask& T, const long long* tabs, int i) {
   return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs;
 }
 
-// kernel 1: QR of one row chunk in LDS.  Single-chunk tasks are finished here
-// (sign fix, Q to the matrix, R to S); otherwise Q_c goes to ws[qw] and R_c
-// (upper n x n) to the stacked R at ws[rw] (column-major, leading dim nchunks*n).
-__global__ __launch_bounds__(1024) void k_qr_chunk(const QRTask* __restrict__ tasks, const QRChunk* __restrict__ chunks,
-                                                   const long long* __restrict__ tabs, BPtr<double> b_A,
-                                                   BPtr<double> b_S, BPtr<double> b_ws) {
+// ---- register-resident Householder QR of an m x n block (m <= kQrRegRows,
+// n <= kQrLdsMaxN) by one workgroup of kQrWaves waves.  Column c belongs to
+// wave c % kQrWaves and lives in its registers: row i in lane i % 64, slot
+// i / 64.  The reflector of the step goes through LDS (two buffers,
+// alternating by step), so every step needs one barrier: while applying
+// reflector j, the owner of column j+1 updates that column first and then
+// turns it into reflector j+1.
+constexpr int kQrWaves = 16;
+constexpr int kQrCPW = kQrLdsMaxN / kQrWaves;   // columns per wave
+constexpr int kQrSlots = kQrRegRows / 64;       // rows per lane
+struct QrCols { double x[kQrCPW][kQrSlots]; };
+
+__device__ __forceinline__ double bcast_sum(double v) { return __shfl(wave_sum(v), 0, 64); }
+
+// entry of local column cc at row i (valid in every lane)
+__device__ __forceinline__ double reg_entry(const QrCols& R, int cc, int i) {
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q)
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t)
+      if (q == cc && t == (i >> 6)) v = R.x[q][t];
+  return __shfl(v, i & 63, 64);
+}
+
+// reflector of column j (local cc of this wave): v (v_j = 1, zero above) to
+// vout, the column keeps R in rows <= j (row j := beta) and v below; tau[j]
+__device__ void reg_reflector(QrCols& R, int cc, int j, int m, double* vout, double* tau) {
+  const int lane = threadIdx.x & 63;
+  const double alpha = reg_entry(R, cc, j);
+  double p = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    if (q != cc) continue;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      if (i > j && i < m) p += R.x[q][t] * R.x[q][t];
+    }
+  }
+  const double xn2 = bcast_sum(p);
+  double tj = 0.0, beta = alpha, scal = 1.0;
+  if (xn2 > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    tj = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    if (q != cc) continue;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      if (i >= m) continue;
+      if (i > j) R.x[q][t] *= scal;
+      vout[i] = (i < j) ? 0.0 : (i == j ? 1.0 : R.x[q][t]);
+      if (i == j) R.x[q][t] = beta;
+    }
+  }
+  if (lane == 0) tau[j] = tj;
+}
+
+// x -= tau (v . x) v on every owned column c with lo < c < n (v from LDS)
+__device__ __forceinline__ void reg_apply(QrCols& R, const double* v, double tj, int lo, int n, int m, int stop_after,
+                                          double* vnext, double* tau) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double vr[kQrSlots];
+#pragma unroll
+  for (int t = 0; t < kQrSlots; ++t) {
+    const int i = lane + 64 * t;
+    vr[t] = i < m ? v[i] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    const int c = wave + q * kQrWaves;
+    if (c <= lo || c >= n) continue;
+    if (tj != 0.0) {
+      double d = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) d += vr[t] * R.x[q][t];
+      const double f = tj * bcast_sum(d);
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) R.x[q][t] -= f * vr[t];
+    }
+    if (c == stop_after) reg_reflector(R, q, c, m, vnext, tau);   // look-ahead (factorisation only)
+  }
+}
+
+__device__ void reg_householder(QrCols& R, int m, int n, double* vbuf, double* tau) {
+  const int wave = threadIdx.x >> 6;
+  if (wave == 0) reg_reflector(R, 0, 0, m, vbuf, tau);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    reg_apply(R, vbuf + (j & 1) * kQrRegRows, tau[j], j, n, m, j + 1 < n ? j + 1 : -1,
+              vbuf + ((j + 1) & 1) * kQrRegRows, tau);
+    __syncthreads();
+  }
+}
+
+// signs of the diagonal of R to LDS (owners), then barrier
+__device__ void reg_signs(const QrCols& R, int n, double* sgn) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    const int c = wave + q * kQrWaves;
+    if (c >= n) continue;
+    const double d = reg_entry(R, q, c);
+    if (lane == 0) sgn[c] = d < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+}
+
+// explicit Q (backward accumulation); R must have been written out before
+__device__ void reg_form_q(QrCols& R, int m, int n, double* vbuf, const double* tau) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = n - 1; j >= 0; --j) {
+    double* v = vbuf + (j & 1) * kQrRegRows;
+    if (j % kQrWaves == wave) {   // publish v_j, then column j := (I - tau_j v v^T) e_j
+      const int cc = j / kQrWaves;
+      const double tj = tau[j];
+#pragma unroll
+      for (int q = 0; q < kQrCPW; ++q) {
+        if (q != cc) continue;
+#pragma unroll
+        for (int t = 0; t < kQrSlots; ++t) {
+          const int i = lane + 64 * t;
+          if (i >= m) continue;
+          const double vi = (i < j) ? 0.0 : (i == j ? 1.0 : R.x[q][t]);
+          v[i] = vi;
+          R.x[q][t] = (i == j) ? 1.0 - tj : -tj * vi;
+        }
+      }
+    }
+    __syncthreads();
+    reg_apply(R, v, tau[j], j, n, m, -1, nullptr, nullptr);
+  }
+  __syncthreads();
+}
+
+// kernel 1: QR of one row chunk (at most kQrRegRows rows).  Single-chunk tasks
+// are finished here (sign fix, Q to the matrix, R to S); otherwise Q_c goes to
+// ws[qw] and R_c (upper n x n) to the stacked R at ws[rw] (column-major,
+// leading dimension nchunks*n).
+__global__ __launch_bounds__(kQrWaves * 64) void k_qr_chunk(const QRTask* __restrict__ tasks,
+                                                            const QRChunk* __restrict__ chunks,
+                                                            const long long* __restrict__ tabs, BPtr<double> b_A,
+                                                            BPtr<double> b_S, BPtr<double> b_ws) {
   double* A = b_A.p[blockIdx.y];
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
-  extern __shared__ double lds[];
+  __shared__ double vbuf[2 * kQrRegRows];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRChunk C = chunks[blockIdx.x];
   const QRTask T = tasks[C.task];
-  const int m = C.rows, n = T.n, tid = threadIdx.x;
-  double* W = lds;
-  for (int e = tid; e < m * n; e += blockDim.x) {
-    int i = e % m, j = e / m;
-    W[e] = A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs];
-  }
-  __syncthreads();
-  lds_householder(W, m, n, tau);
-  if (C.nchunks == 1) {
-    for (int j = tid; j < n; j += blockDim.x) sgn[j] = W[j + j * m] < 0.0 ? -1.0 : 1.0;
-    __syncthreads();
-    for (int e = tid; e < n * n; e += blockDim.x) {
-      int i = e / n, j = e % n;
-      double val = (i <= j) ? sgn[i] * W[i + j * m] : 0.0;
-      S[T.sdst + (T.trans ? (long long)j * n + i : (long long)i * n + j)] = val;
+  const int m = C.rows, n = T.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  QrCols R;
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    const int c = wave + q * kQrWaves;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      R.x[q][t] = (c < n && i < m) ? A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] : 0.0;
     }
-    __syncthreads();
-    lds_form_q(W, m, n, tau);
-    for (int e = tid; e < m * n; e += blockDim.x) {
-      int i = e % m, j = e / m;
-      A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs] = sgn[j] * W[e];
-    }
-    return;
   }
+  reg_householder(R, m, n, vbuf, tau);
+  const bool last = C.nchunks == 1;
+  if (last) reg_signs(R, n, sgn);
   const long long ldr = (long long)C.nchunks * n;
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    int i = e % n, j = e / n;
-    ws[C.rw + (long long)j * ldr + (long long)C.chunk * n + i] = (i <= j) ? W[i + j * m] : 0.0;
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {   // R (rows <= c of column c)
+    const int c = wave + q * kQrWaves;
+    if (c >= n) continue;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      if (i >= n) continue;
+      const double r = (i <= c) ? R.x[q][t] : 0.0;
+      if (last) S[T.sdst + (T.trans ? (long long)c * n + i : (long long)i * n + c)] = sgn[i] * r;
+      else ws[C.rw + (long long)c * ldr + (long long)C.chunk * n + i] = r;
+    }
   }
-  __syncthreads();
-  lds_form_q(W, m, n, tau);
-  for (int e = tid; e < m * n; e += blockDim.x) ws[C.qw + e] = W[e];
+  reg_form_q(R, m, n, vbuf, tau);
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {   // Q
+    const int c = wave + q * kQrWaves;
+    if (c >= n) continue;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      if (i >= m) continue;
+      if (last) A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] = sgn[c] * R.x[q][t];
+      else ws[C.qw + i + (long long)c * m] = R.x[q][t];
+    }
+  }
 }
 
 // kernel 2: QR of the stacked chunk R factors; final R (non-negative
 // diagonal) to S, second-level Q (sign-fixed) back over the stack.
-__global__ __launch_bounds__(1024) void k_qr_stack(const QRTask* __restrict__ tasks, const QRStack* __restrict__ stacks,
-                                                   BPtr<double> b_S, BPtr<double> b_ws) {
+__global__ __launch_bounds__(kQrWaves * 64) void k_qr_stack(const QRTask* __restrict__ tasks,
+                                                            const QRStack* __restrict__ stacks, BPtr<double> b_S,
+                                                            BPtr<double> b_ws) {
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
-  extern __shared__ double lds[];
+  __shared__ double vbuf[2 * kQrRegRows];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRStack K = stacks[blockIdx.x];
   const QRTask T = tasks[K.task];
-  const int n = T.n, m = K.nchunks * n, tid = threadIdx.x;
-  double* W = lds;
-  for (int e = tid; e < m * n; e += blockDim.x) W[e] = ws[K.rw + e];
-  __syncthreads();
-  lds_householder(W, m, n, tau);
-  for (int j = tid; j < n; j += blockDim.x) sgn[j] = W[j + j * m] < 0.0 ? -1.0 : 1.0;
-  __syncthreads();
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    int i = e / n, j = e % n;
-    double val = (i <= j) ? sgn[i] * W[i + j * m] : 0.0;
-    S[T.sdst + (T.trans ? (long long)j * n + i : (long long)i * n + j)] = val;
+  const int n = T.n, m = K.nchunks * n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  QrCols R;
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    const int c = wave + q * kQrWaves;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      R.x[q][t] = (c < n && i < m) ? ws[K.rw + i + (long long)c * m] : 0.0;
+    }
   }
-  __syncthreads();
-  lds_form_q(W, m, n, tau);
-  for (int e = tid; e < m * n; e += blockDim.x) {
-    int j = e / m;
-    ws[K.rw + e] = sgn[j] * W[e];
+  reg_householder(R, m, n, vbuf, tau);
+  reg_signs(R, n, sgn);
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    const int c = wave + q * kQrWaves;
+    if (c >= n) continue;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      if (i >= n) continue;
+      const double r = (i <= c) ? R.x[q][t] : 0.0;
+      S[T.sdst + (T.trans ? (long long)c * n + i : (long long)i * n + c)] = sgn[i] * r;
+    }
+  }
+  reg_form_q(R, m, n, vbuf, tau);
+#pragma unroll
+  for (int q = 0; q < kQrCPW; ++q) {
+    const int c = wave + q * kQrWaves;
+    if (c >= n) continue;
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int i = lane + 64 * t;
+      if (i < m) ws[K.rw + i + (long long)c * m] = sgn[c] * R.x[q][t];
+    }
   }
 }
 
@@ -1030,10 +1102,9 @@ void qr_plan_chunks(QRPlan& p) {
     const int m = T.m, n = T.n;
     if (n > kQrLdsMaxN) { p.wide.push_back(t); continue; }
     int nc = 1;
-    if ((long long)m * n > kQrLdsDoubles) {
-      int mc = kQrLdsDoubles / n;
-      nc = (m + mc - 1) / mc;
-      if ((long long)nc * n * n > kQrLdsDoubles || m / nc < n) { p.wide.push_back(t); continue; }
+    if (m > kQrRegRows) {
+      nc = (m + kQrRegRows - 1) / kQrRegRows;
+      if ((long long)nc * n > kQrRegRows || m / nc < n) { p.wide.push_back(t); continue; }
     }
     long long rw = pos;
     if (nc > 1) pos += (long long)nc * n * n;
@@ -1051,25 +1122,17 @@ void qr_plan_chunks(QRPlan& p) {
 void launch_qr(const QRPlan& p, const long long* d_tabs, BPtr<double> A, BPtr<double> S, BPtr<double> ws, int nb,
                hipStream_t st) {
   if (p.ntasks == 0) return;
-  static bool attr = false;
-  const size_t shm = sizeof(double) * kQrLdsDoubles;
-  if (!attr) {
-    if (hipFuncSetAttribute((const void*)k_qr_chunk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess ||
-        hipFuncSetAttribute((const void*)k_qr_stack, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess)
-      throw Error(TT_EDEVICE, "cannot raise the LDS limit of the QR kernels");
-    attr = true;
-  }
   prof_begin(st);
-  BPtr<double> lws = ws;   // the LDS path's workspace follows the global fallback's
+  BPtr<double> lws = ws;   // the chunk path's workspace follows the global fallback's
   for (int b = 0; b < nb; ++b) lws.p[b] = ws.p[b] + p.ws_size;
   if (!p.chunks.empty()) {
-    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size(), nb), dim3(1024), shm, st, p.d_tasks, p.d_chunks,
-                       d_tabs, A, S, lws);
+    hipLaunchKernelGGL(k_qr_chunk, dim3((unsigned)p.chunks.size(), nb), dim3(kQrWaves * 64), 0, st, p.d_tasks,
+                       p.d_chunks, d_tabs, A, S, lws);
     HIP_CHECK_LAUNCH();
   }
   if (!p.stacks.empty()) {
-    hipLaunchKernelGGL(k_qr_stack, dim3((unsigned)p.stacks.size(), nb), dim3(1024), shm, st, p.d_tasks, p.d_stacks, S,
-                       lws);
+    hipLaunchKernelGGL(k_qr_stack, dim3((unsigned)p.stacks.size(), nb), dim3(kQrWaves * 64), 0, st, p.d_tasks,
+                       p.d_stacks, S, lws);
     HIP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_qr_combine, dim3((unsigned)p.chunks.size(), nb), dim3(256), 0, st, p.d_tasks, p.d_chunks,
                        d_tabs, A, lws);
