@@ -169,3 +169,27 @@ def free_fermion_energy(h, beta):
     """U = 0 closed form: <H> = 2 sum_k eps_k f(eps_k)."""
     eps = np.linalg.eigvalsh(h)
     return 2.0 * float(np.sum(eps / (np.exp(beta * eps) + 1.0)))
+
+
+def same_ode_bilayer_local(model, beta0, beta):
+    """Density and double occupancy per site, bilayer values at 2*beta:
+    <O> = Tr(O rho^2) / Tr(rho^2) for rho = exp(-(beta-beta0) H) (1 - beta0 H)
+    (SM Sec. II.A), O = sum_i n_i or sum_i n_iu n_id.  Both are diagonal in
+    the Fock basis, so <k|O|k> = sum_f |V_fk|^2 O_f over each eigenvector.
+    Returns (n, docc)."""
+    N = model.N
+    xs, ns, ds = [], [], []
+    for nup in range(N + 1):
+        for ndn in range(N + 1):
+            h, _ = model.sector_hamiltonian(nup, ndn)
+            states = model.sector_states(nup, ndn)
+            docc = np.array([sum(o[2 * i] * o[2 * i + 1] for i in range(N)) for o in states], dtype=float)
+            E, V = np.linalg.eigh(h)
+            a = 1.0 - beta0 * E
+            xs.append(2.0 * np.log(np.abs(a)) - 2.0 * (beta - beta0) * E)
+            ns.append(np.full(E.size, float(nup + ndn)))
+            ds.append((V ** 2).T @ docc)
+    x, n, d = np.concatenate(xs), np.concatenate(ns), np.concatenate(ds)
+    w = np.exp(x - _logsumexp(x))
+    return float(np.sum(w * n)) / N, float(np.sum(w * d)) / N
+

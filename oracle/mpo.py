@@ -157,6 +157,23 @@ class HubbardMPO:
         return As
 
 
+def local_sum_mpo(N, op_diag):
+    """MPO of sum_i op_i for a diagonal on-site operator (entries on the basis
+    {0, up, down, updown}): channels start (identity so far) and done (op
+    placed), boundary bonds of dimension 1 (start on the left, done on the
+    right)."""
+    op = np.diag(np.asarray(op_diag, dtype=float))
+    one = np.eye(4)
+    W = np.zeros((2, 4, 4, 2))
+    W[0, :, :, 0] = one
+    W[0, :, :, 1] = op
+    W[1, :, :, 1] = one
+    Ws = [W.copy() for _ in range(N)]
+    Ws[0] = Ws[0][:1]
+    Ws[-1] = Ws[-1][..., 1:]
+    return Ws
+
+
 def mpo_to_dense(Ws):
     """Contract an MPO (boundary bonds of dimension 1) to a 4^N x 4^N matrix."""
     M = Ws[0][0]                      # (so, si, b)

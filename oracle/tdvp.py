@@ -251,6 +251,18 @@ class State:
         HA = heff1(self.Lenv[k], self.W[k], self.Renv[k + 1], A)
         return float(np.vdot(A, HA)) / float(np.vdot(A, A))
 
+    def expectation(self, Ws):
+        """<<rho|O (x) 1|rho>> / <<rho|rho>> for an operator O given as an MPO
+        (boundary bonds of dimension 1), e.g. a sum of on-site operators:
+        right environments of O down to bond 1, then O^(1) at the centre."""
+        assert self.centre == 0
+        R = np.ones((1, 1, 1))
+        for k in range(self.N - 1, 0, -1):
+            R = env_right(R, self.A[k], Ws[k])
+        A = self.A[0]
+        OA = heff1(np.ones((1, 1, 1)), Ws[0], R, A)
+        return float(np.vdot(A, OA)) / float(np.vdot(A, A))
+
     def ln_trace(self):
         """ln Tr rho(beta): contract every site with delta(sigma, sigma')."""
         v = np.ones(1)
