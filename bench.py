@@ -220,14 +220,19 @@ def main():
         torch.cuda.synchronize()
         s_single = (time.perf_counter() - t0) / args.steps
         dens = [st.observables() for st in sts]
+        locs = [st.local_observables() for st in sts]
         for st in sts:
             st.free()
+        # compressibility chi = dn/dmu from neighbouring instances (centred differences)
+        ns = [lo["n"] for lo in locs]
+        chi = [(ns[i + 1] - ns[i - 1]) / (mus[i + 1] - mus[i - 1]) for i in range(1, len(mus) - 1)]
         mu_scan = dict(workload="Hubbard 6x12 cylinder, U=8, U(1)xU(1) D=%d, d_beta=%g, mu = %s"
                        % (D4, c4["dbeta"], ", ".join("%.4g" % m for m in mus)),
                        instances=len(mus), batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
                        single_instance_s_per_step=s_single, speedup_vs_one_at_a_time=s_single * len(mus) / s_batch,
                        tflops_alg=fl / args.steps / s_batch / 1e12,
-                       e_per_site=[d["e"] for d in dens])
+                       beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens], n_per_site=ns,
+                       docc_per_site=[lo["docc"] for lo in locs], chi_dn_dmu=chi)
 
     # dense effective-Hamiltonian apply at D (microbenchmark)
     heff = {}

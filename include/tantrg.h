@@ -129,6 +129,17 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
  * ln Tr rho(beta) by transfer matrices.  Synchronises. */
 int thermo_observables(tt_state* state, tt_observables* out);
 
+/* Local observables per site at beta_phys = 2 beta (same bilayer meaning as
+ * thermo_observables): host_out2[0] = particle density n = <N>/N_sites,
+ * host_out2[1] = double occupancy D_n = <sum_i n_up,i n_dn,i>/N_sites (the
+ * quantity of main text Fig. 2), each <<rho|O (x) 1|rho>> / <<rho|rho>> for a
+ * sum of on-site operators O (SM Sec. II.A, bilayer).  Evaluated with the
+ * two-channel MPO of O through right environments to the centre (site 0):
+ * valid for a state as left by mpo_init_highT or tdvp_sweep.  The first call
+ * on a state builds the needed plans; FP64 in every precision mode.
+ * Synchronises.  TT_ENUMERIC for non-finite results. */
+int thermo_local_observables(tt_state* s, double* host_out2);
+
 void tt_state_free(tt_state* state);
 const char* tt_last_error(void);
 

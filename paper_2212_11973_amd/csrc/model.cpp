@@ -362,4 +362,29 @@ std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<s
   return dims;
 }
 
+// Sum of one on-site operator over all sites, sum_i op_i (a diagonal 4x4 in
+// the local basis {0, up, dn, updn}), as an MPO with two channels per bond:
+// start (identity so far) and done (op placed).  Bond 0 has start only, bond N
+// start and done, like the Hamiltonian.
+Mpo make_local_sum_mpo(int N, const double op[4]) {
+  Mpo m;
+  m.N = N;
+  m.states.resize(N + 1);
+  m.states[0] = {{0, -1, -1}};
+  for (int k = 1; k <= N; ++k) m.states[k] = {{0, -1, -1}, {1, -1, -1}};
+  for (int k = 0; k <= N; ++k) m.DH.push_back((int)m.states[k].size());
+  m.W.resize(N);
+  for (int k = 0; k < N; ++k) {
+    const int DL = m.DH[k], DR = m.DH[k + 1];
+    std::vector<double> Wk((size_t)DL * 16 * DR, 0.0);
+    for (int s = 0; s < 4; ++s) {
+      Wk[(((size_t)0 * 4 + s) * 4 + s) * DR + 0] = 1.0;    // start -> start: identity
+      Wk[(((size_t)0 * 4 + s) * 4 + s) * DR + 1] = op[s];  // start -> done: the operator
+      if (DL == 2) Wk[(((size_t)1 * 4 + s) * 4 + s) * DR + 1] = 1.0;   // done -> done
+    }
+    m.W[k] = Wk;
+  }
+  return m;
+}
+
 }  // namespace tt

@@ -40,6 +40,7 @@ struct Mpo {
   Q charge(int k, int a) const;
 };
 Mpo make_hubbard_mpo(const Lattice& lat, double t, double U, double mu);
+Mpo make_local_sum_mpo(int N, const double op[4]);   // sum_i op_i, op diagonal
 
 // ------------------------------------------------------------------ sectors
 struct Sector { Q q; int dim; long long off; };

@@ -22,7 +22,7 @@ SYMBOLS = [
     "tt_state_bond_sectors", "tt_state_export_site", "tt_state_import_site",
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
-    "tt_profile_enable", "tt_profile_read",
+    "tt_profile_enable", "tt_profile_read", "thermo_local_observables",
 ]
 
 
@@ -72,6 +72,7 @@ def lib():
         L.tdvp_sweep.argtypes = [vp, C.c_double, C.POINTER(tt_sweep_stats)]
         L.tdvp_sweep_batch.argtypes = [C.POINTER(vp), C.c_int, C.c_double, C.POINTER(tt_sweep_stats)]
         L.thermo_observables.argtypes = [vp, C.POINTER(tt_observables)]
+        L.thermo_local_observables.argtypes = [vp, dp]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -144,6 +145,13 @@ def thermo_observables(state):
     o = tt_observables()
     _check(lib().thermo_observables(state, C.byref(o)))
     return {k: getattr(o, k) for k, _ in o._fields_}
+
+
+def thermo_local_observables(state):
+    """dict(n=density, docc=double occupancy) per site at beta_phys = 2 beta."""
+    out = (C.c_double * 2)()
+    _check(lib().thermo_local_observables(state, out))
+    return dict(n=out[0], docc=out[1])
 
 
 def tt_state_free(state):
@@ -263,6 +271,9 @@ class State:
 
     def observables(self):
         return thermo_observables(self.h)
+
+    def local_observables(self):
+        return thermo_local_observables(self.h)
 
     def info(self):
         return tt_state_info(self.h)
