@@ -120,8 +120,12 @@ int mpo_init_highT(const tt_model* model, const tt_options* opts, tt_state** out
  * Enqueued asynchronously unless stats is non-NULL. */
 int tdvp_sweep(tt_state* state, double dbeta, tt_sweep_stats* stats);
 
-/* The same step for n independent states (e.g. a chemical-potential scan),
- * advanced site by site in lockstep; stats (may be NULL) are summed. */
+/* The same step for n independent states (e.g. a chemical-potential scan).
+ * Consecutive states with identical plans (same lattice, options and bond
+ * sectors; the couplings may differ) advance together, up to 16 per kernel
+ * launch; others run in their own groups.  Results equal those of separate
+ * tdvp_sweep calls bit for bit.  A state may appear only once (TT_EINVAL).
+ * stats (may be NULL) are summed. */
 int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* stats);
 
 /* Bilayer observables of SM Sec. II.A at beta_phys = 2*beta: lnZ = 2 Lambda,
