@@ -775,11 +775,11 @@ long long check_qr(const QRPlan& p, const std::vector<long long>& tabs, long lon
   for (auto& c : q.chunks) {
     const QRTask& t = q.tasks.at(c.task);
     if (c.row0 < 0 || c.rows < t.n || c.row0 + c.rows > t.m) ++bad;
-    if (c.rows > kQrRegRows || t.n > kQrLdsMaxN) ++bad;
+    if (c.rows > kQrChunkRows || t.n > kQrLdsMaxN) ++bad;
     if (c.nchunks > 1) {
       if (c.qw < 0 || c.qw + (long long)c.rows * t.n > q.lds_ws) ++bad;
       if (c.rw < 0 || c.rw + (long long)c.nchunks * t.n * t.n > q.lds_ws) ++bad;
-      if ((long long)c.nchunks * t.n > kQrRegRows) ++bad;
+      if ((long long)c.nchunks * t.n > kQrStackRows) ++bad;
     }
     covered[c.task] += c.rows;
   }

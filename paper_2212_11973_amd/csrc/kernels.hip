@@ -821,7 +821,7 @@ __device__ __forceinline__ long long qr_row(const QRTask& T, const long long* ta
   return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs;
 }
 
-// ---- register-resident Householder QR of an m x n block (m <= kQrRegRows,
+// ---- register-resident Householder QR of an m x n block (m <= 64 SL,
 // n <= kQrLdsMaxN) by one workgroup of kQrWaves waves.  Column c belongs to
 // wave c % kQrWaves and lives in its registers: row i in lane i % 64, slot
 // i / 64.  The reflector of the step goes through LDS (two buffers,
@@ -830,25 +830,28 @@ __device__ __forceinline__ long long qr_row(const QRTask& T, const long long* ta
 // turns it into reflector j+1.
 constexpr int kQrWaves = 16;
 constexpr int kQrCPW = kQrLdsMaxN / kQrWaves;   // columns per wave
-constexpr int kQrSlots = kQrRegRows / 64;       // rows per lane
-struct QrCols { double x[kQrCPW][kQrSlots]; };
+// SL: rows per lane (a block has at most 64 SL rows); the chunk kernel uses
+// kQrChunkRows / 64, the stack kernel kQrStackRows / 64
+template <int SL> struct QrCols { double x[kQrCPW][SL]; };
 
 __device__ __forceinline__ double bcast_sum(double v) { return __shfl(wave_sum(v), 0, 64); }
 
 // entry of local column cc at row i (valid in every lane)
-__device__ __forceinline__ double reg_entry(const QrCols& R, int cc, int i) {
+template <int SL>
+__device__ __forceinline__ double reg_entry(const QrCols<SL>& R, int cc, int i) {
   double v = 0.0;
 #pragma unroll
   for (int q = 0; q < kQrCPW; ++q)
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t)
+    for (int t = 0; t < SL; ++t)
       if (q == cc && t == (i >> 6)) v = R.x[q][t];
   return __shfl(v, i & 63, 64);
 }
 
 // reflector of column j (local cc of this wave): v (v_j = 1, zero above) to
 // vout, the column keeps R in rows <= j (row j := beta) and v below; tau[j]
-__device__ void reg_reflector(QrCols& R, int cc, int j, int m, double* vout, double* tau) {
+template <int SL>
+__device__ void reg_reflector(QrCols<SL>& R, int cc, int j, int m, double* vout, double* tau) {
   const int lane = threadIdx.x & 63;
   const double alpha = reg_entry(R, cc, j);
   double p = 0.0;
@@ -856,7 +859,7 @@ __device__ void reg_reflector(QrCols& R, int cc, int j, int m, double* vout, dou
   for (int q = 0; q < kQrCPW; ++q) {
     if (q != cc) continue;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       if (i > j && i < m) p += R.x[q][t] * R.x[q][t];
     }
@@ -872,7 +875,7 @@ __device__ void reg_reflector(QrCols& R, int cc, int j, int m, double* vout, dou
   for (int q = 0; q < kQrCPW; ++q) {
     if (q != cc) continue;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       if (i >= m) continue;
       if (i > j) R.x[q][t] *= scal;
@@ -884,12 +887,13 @@ __device__ void reg_reflector(QrCols& R, int cc, int j, int m, double* vout, dou
 }
 
 // x -= tau (v . x) v on every owned column c with lo < c < n (v from LDS)
-__device__ __forceinline__ void reg_apply(QrCols& R, const double* v, double tj, int lo, int n, int m, int stop_after,
+template <int SL>
+__device__ __forceinline__ void reg_apply(QrCols<SL>& R, const double* v, double tj, int lo, int n, int m, int stop_after,
                                           double* vnext, double* tau) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double vr[kQrSlots];
+  double vr[SL];
 #pragma unroll
-  for (int t = 0; t < kQrSlots; ++t) {
+  for (int t = 0; t < SL; ++t) {
     const int i = lane + 64 * t;
     vr[t] = i < m ? v[i] : 0.0;
   }
@@ -900,28 +904,30 @@ __device__ __forceinline__ void reg_apply(QrCols& R, const double* v, double tj,
     if (tj != 0.0) {
       double d = 0.0;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) d += vr[t] * R.x[q][t];
+      for (int t = 0; t < SL; ++t) d += vr[t] * R.x[q][t];
       const double f = tj * bcast_sum(d);
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) R.x[q][t] -= f * vr[t];
+      for (int t = 0; t < SL; ++t) R.x[q][t] -= f * vr[t];
     }
     if (c == stop_after) reg_reflector(R, q, c, m, vnext, tau);   // look-ahead (factorisation only)
   }
 }
 
-__device__ void reg_householder(QrCols& R, int m, int n, double* vbuf, double* tau) {
+template <int SL>
+__device__ void reg_householder(QrCols<SL>& R, int m, int n, double* vbuf, double* tau) {
   const int wave = threadIdx.x >> 6;
   if (wave == 0) reg_reflector(R, 0, 0, m, vbuf, tau);
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    reg_apply(R, vbuf + (j & 1) * kQrRegRows, tau[j], j, n, m, j + 1 < n ? j + 1 : -1,
-              vbuf + ((j + 1) & 1) * kQrRegRows, tau);
+    reg_apply(R, vbuf + (j & 1) * 64 * SL, tau[j], j, n, m, j + 1 < n ? j + 1 : -1,
+              vbuf + ((j + 1) & 1) * 64 * SL, tau);
     __syncthreads();
   }
 }
 
 // signs of the diagonal of R to LDS (owners), then barrier
-__device__ void reg_signs(const QrCols& R, int n, double* sgn) {
+template <int SL>
+__device__ void reg_signs(const QrCols<SL>& R, int n, double* sgn) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < kQrCPW; ++q) {
@@ -934,10 +940,11 @@ __device__ void reg_signs(const QrCols& R, int n, double* sgn) {
 }
 
 // explicit Q (backward accumulation); R must have been written out before
-__device__ void reg_form_q(QrCols& R, int m, int n, double* vbuf, const double* tau) {
+template <int SL>
+__device__ void reg_form_q(QrCols<SL>& R, int m, int n, double* vbuf, const double* tau) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = n - 1; j >= 0; --j) {
-    double* v = vbuf + (j & 1) * kQrRegRows;
+    double* v = vbuf + (j & 1) * 64 * SL;
     if (j % kQrWaves == wave) {   // publish v_j, then column j := (I - tau_j v v^T) e_j
       const int cc = j / kQrWaves;
       const double tj = tau[j];
@@ -945,7 +952,7 @@ __device__ void reg_form_q(QrCols& R, int m, int n, double* vbuf, const double* 
       for (int q = 0; q < kQrCPW; ++q) {
         if (q != cc) continue;
 #pragma unroll
-        for (int t = 0; t < kQrSlots; ++t) {
+        for (int t = 0; t < SL; ++t) {
           const int i = lane + 64 * t;
           if (i >= m) continue;
           const double vi = (i < j) ? 0.0 : (i == j ? 1.0 : R.x[q][t]);
@@ -960,7 +967,7 @@ __device__ void reg_form_q(QrCols& R, int m, int n, double* vbuf, const double* 
   __syncthreads();
 }
 
-// kernel 1: QR of one row chunk (at most kQrRegRows rows).  Single-chunk tasks
+// kernel 1: QR of one row chunk (at most kQrChunkRows rows).  Single-chunk tasks
 // are finished here (sign fix, Q to the matrix, R to S); otherwise Q_c goes to
 // ws[qw] and R_c (upper n x n) to the stacked R at ws[rw] (column-major,
 // leading dimension nchunks*n).
@@ -971,17 +978,18 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_chunk(const QRTask* __rest
   double* A = b_A.p[blockIdx.y];
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
-  __shared__ double vbuf[2 * kQrRegRows];
+  constexpr int SL = kQrChunkRows / 64;
+  __shared__ double vbuf[2 * kQrChunkRows];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRChunk C = chunks[blockIdx.x];
   const QRTask T = tasks[C.task];
   const int m = C.rows, n = T.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  QrCols R;
+  QrCols<SL> R;
 #pragma unroll
   for (int q = 0; q < kQrCPW; ++q) {
     const int c = wave + q * kQrWaves;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       R.x[q][t] = (c < n && i < m) ? A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] : 0.0;
     }
@@ -995,7 +1003,7 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_chunk(const QRTask* __rest
     const int c = wave + q * kQrWaves;
     if (c >= n) continue;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       if (i >= n) continue;
       const double r = (i <= c) ? R.x[q][t] : 0.0;
@@ -1009,7 +1017,7 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_chunk(const QRTask* __rest
     const int c = wave + q * kQrWaves;
     if (c >= n) continue;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       if (i >= m) continue;
       if (last) A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] = sgn[c] * R.x[q][t];
@@ -1025,17 +1033,18 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_stack(const QRTask* __rest
                                                             BPtr<double> b_ws) {
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
-  __shared__ double vbuf[2 * kQrRegRows];
+  constexpr int SL = kQrStackRows / 64;
+  __shared__ double vbuf[2 * kQrStackRows];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRStack K = stacks[blockIdx.x];
   const QRTask T = tasks[K.task];
   const int n = T.n, m = K.nchunks * n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  QrCols R;
+  QrCols<SL> R;
 #pragma unroll
   for (int q = 0; q < kQrCPW; ++q) {
     const int c = wave + q * kQrWaves;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       R.x[q][t] = (c < n && i < m) ? ws[K.rw + i + (long long)c * m] : 0.0;
     }
@@ -1047,7 +1056,7 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_stack(const QRTask* __rest
     const int c = wave + q * kQrWaves;
     if (c >= n) continue;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       if (i >= n) continue;
       const double r = (i <= c) ? R.x[q][t] : 0.0;
@@ -1060,7 +1069,7 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_stack(const QRTask* __rest
     const int c = wave + q * kQrWaves;
     if (c >= n) continue;
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < SL; ++t) {
       const int i = lane + 64 * t;
       if (i < m) ws[K.rw + i + (long long)c * m] = sgn[c] * R.x[q][t];
     }
@@ -1102,9 +1111,9 @@ void qr_plan_chunks(QRPlan& p) {
     const int m = T.m, n = T.n;
     if (n > kQrLdsMaxN) { p.wide.push_back(t); continue; }
     int nc = 1;
-    if (m > kQrRegRows) {
-      nc = (m + kQrRegRows - 1) / kQrRegRows;
-      if ((long long)nc * n > kQrRegRows || m / nc < n) { p.wide.push_back(t); continue; }
+    if (m > kQrChunkRows) {
+      nc = (m + kQrChunkRows - 1) / kQrChunkRows;
+      if ((long long)nc * n > kQrStackRows || m / nc < n) { p.wide.push_back(t); continue; }
     }
     long long rw = pos;
     if (nc > 1) pos += (long long)nc * n * n;

@@ -83,12 +83,13 @@ struct WTerm { long long src, ssi, ssj; double w; };
 struct QRTask { int m, n, trans, pad; long long rbase, rs, cs, rtab, sdst, ws; };
 
 // Register-resident QR (n <= kQrLdsMaxN): a task is split into row chunks of
-// at most kQrRegRows rows; chunk QRs, then one QR of the stacked chunk R
-// factors (at most kQrRegRows rows), then the product of the two Q levels
+// at most kQrChunkRows rows; chunk QRs, then one QR of the stacked chunk R
+// factors (at most kQrStackRows rows), then the product of the two Q levels
 // (tall-skinny QR in two levels).  A task with one chunk is finished by the
 // chunk kernel; wider or taller tasks use the global-memory kernel.
 constexpr int kQrLdsMaxN = 64;
-constexpr int kQrRegRows = 512;
+constexpr int kQrChunkRows = 256;
+constexpr int kQrStackRows = 512;
 struct QRChunk { int task, row0, rows, chunk, nchunks, pad; long long qw, rw; };
 struct QRStack { int task, nchunks; long long rw; };
 
