@@ -421,6 +421,27 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
 }
 
+// k addressing of a wave GEMM problem: index tables or general strides; A
+// contiguous in k (B strided); both contiguous in k
+constexpr int kKGeneric = 0, kKAContig = 1, kKBothContig = 2;
+
+// Element i of a wave-uniform base.  The byte offset is formed in 32 bits (the
+// plans keep element offsets below 2^29), so the load takes the scalar-base
+// form with a single 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ double ld32(const T* __restrict__ base, unsigned i) {
+  return (double)*reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (i * (unsigned)sizeof(T)));
+}
+// Elements i and i + 1 of a wave-uniform base in one load (8-byte alignment
+// suffices: the device runs in unaligned-access mode).
+template <typename T>
+__device__ __forceinline__ void ld32x2(const T* __restrict__ base, unsigned i, double& x0, double& x1) {
+  typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  const v2 v = *reinterpret_cast<const v2*>(reinterpret_cast<const char*>(base) + (i * (unsigned)sizeof(T)));
+  x0 = (double)v.x;
+  x1 = (double)v.y;
+}
+
 // One wave's (16 FM) x (16 FN) output block from global memory, f64 MFMA
 // 16x16x4 (in every precision mode: these blocks are bound by memory and
 // issue, so FP32 mode only keeps its float intermediates).  In a 16-deep chunk, lane (r, g) = (lane % 16, lane / 16) supplies
@@ -428,7 +449,12 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 // read four consecutive k).  The job takes chunks part, part + nparts, ...
 // With nparts = 4 the four waves of the workgroup hold the four
 // K parts of one block and wave 0 adds them in part order.
-template <int FM, int FN>
+// TA / TB are the element types of the two operands (float where the plan
+// keeps that operand in single precision).  Loads are unconditional: rows,
+// columns and k past the ends are clamped to the last valid index (an
+// element of the same problem), so a half chunk issues all of its loads
+// before its first wait.
+template <int FM, int FN, typename TA, typename TB, int KM>
 __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
                                           const Slots& slots, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -436,25 +462,24 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
   // operand bases are wave-uniform (scalar registers); element offsets from
   // them fit 32 bits (checked when the plan is built).  Operands flagged in
   // P.dt are float arrays (offsets count floats).
-  const bool fa = P.dt & kDtA, fb = P.dt & kDtB, fc = P.dt & kDtC;
-  const double* __restrict__ A = slots.p[P.ia] + P.offA;
-  const double* __restrict__ B = slots.p[P.ib] + P.offB;
+  const bool fc = P.dt & kDtC;
+  const TA* __restrict__ A = reinterpret_cast<const TA*>(slots.p[P.ia]) + P.offA;
+  const TB* __restrict__ B = reinterpret_cast<const TB*>(slots.p[P.ib]) + P.offB;
   double* C = slots.p[P.ic] + P.offC;
-  const float* __restrict__ Af = reinterpret_cast<const float*>(slots.p[P.ia]) + P.offA;
-  const float* __restrict__ Bf = reinterpret_cast<const float*>(slots.p[P.ib]) + P.offB;
   float* Cf = reinterpret_cast<float*>(slots.p[P.ic]) + P.offC;
   const int m0 = J.tm * 16 * FM, n0 = J.tn * 16 * FN;
   unsigned ra[FM], cb[FN];
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
-    const int m = m0 + 16 * i + r16;
-    ra[i] = m < P.M ? (unsigned)idx_map(tabs, P.tam, P.sam, m) : 0xffffffffu;
-  }
+  for (int i = 0; i < FM; ++i) ra[i] = (unsigned)idx_map(tabs, P.tam, P.sam, min(m0 + 16 * i + r16, P.M - 1));
 #pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int n = n0 + 16 * j + r16;
-    cb[j] = n < P.N ? (unsigned)idx_map(tabs, P.tbn, P.sbn, n) : 0xffffffffu;
-  }
+  for (int j = 0; j < FN; ++j) cb[j] = (unsigned)idx_map(tabs, P.tbn, P.sbn, min(n0 + 16 * j + r16, P.N - 1));
+  // row / column offsets with this lane group's first k of a full chunk
+  // (4g for contiguous operands, g * 4 * stride for a strided B)
+  unsigned rg[FM], cg[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) rg[i] = ra[i] + 4u * g;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) cg[j] = cb[j] + (KM == kKBothContig ? 4u * g : 4u * g * (unsigned)P.sbk);
   const int nch = (P.K + 15) >> 4;
   double4_t acc[FM][FN];
 #pragma unroll
@@ -465,8 +490,59 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
   // MFMA steps: few live registers, and the occupancy that buys hides the
   // load latency better on these short loops.  Steps past the end of K are
   // skipped (most blocks of a sweep have K below 16).
-  for (int c = J.part; c < nch; c += J.nparts) {
-    const int ns = min(4, (P.K - 16 * c + 3) >> 2);   // steps holding a valid k (wave-uniform)
+  const int nfull = P.K >> 4;
+  for (int c = J.part; c < nfull; c += J.nparts) {
+    // full chunk: every k is valid and clamped rows / columns only feed
+    // outputs that are never stored, so the loads need no mask
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double a[FM][2], b[FN][2];
+      if (KM == kKGeneric) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int k = c * 16 + 4 * (2 * h + q) + g;
+          const unsigned ka = (unsigned)idx_map(tabs, P.tak, P.sak, k);
+          const unsigned kb = (unsigned)idx_map(tabs, P.tbk, P.sbk, k);
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a[i][q] = ld32(A, ra[i] + ka);
+#pragma unroll
+          for (int j = 0; j < FN; ++j) b[j][q] = ld32(B, kb + cb[j]);
+        }
+      } else {
+        // k-contiguous operands: lane group g takes k = 16c + 4g + s on
+        // step s, so steps 2h and 2h + 1 are one two-element load per row
+        // (the four lane groups together read each row's whole chunk)
+        const int k0 = c * 16 + 2 * h;   // wave-uniform part of the k of step 2h
+        const TA* As = A + k0;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) ld32x2(As, rg[i], a[i][0], a[i][1]);
+        if (KM == kKBothContig) {
+          const TB* Bs = B + k0;
+#pragma unroll
+          for (int j = 0; j < FN; ++j) ld32x2(Bs, cg[j], b[j][0], b[j][1]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const TB* Bs = B + (long long)(k0 + q) * P.sbk;
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j][q] = ld32(Bs, cg[j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+    }
+  }
+  if (nfull < nch && nfull % J.nparts == J.part) {
+    const int c = nfull;
+    // the last, partial chunk: k past the end is clamped to K - 1 and its B
+    // value replaced by zero (that alone cancels the product)
+    const int ns = (P.K - 16 * c + 3) >> 2;   // steps holding a valid k (wave-uniform)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (2 * h >= ns) break;
@@ -475,14 +551,20 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
       for (int q = 0; q < 2; ++q) {
         const int k = c * 16 + 4 * (2 * h + q) + g;
         const bool ok = k < P.K;
-        const unsigned ka = ok ? (unsigned)idx_map(tabs, P.tak, P.sak, k) : 0u;
-        const unsigned kb = ok ? (unsigned)idx_map(tabs, P.tbk, P.sbk, k) : 0u;
+        const int kc = ok ? k : P.K - 1;
+        const unsigned ka = KM == kKGeneric ? (unsigned)idx_map(tabs, P.tak, P.sak, kc) : (unsigned)kc;
+        const unsigned kb = KM == kKGeneric ? (unsigned)idx_map(tabs, P.tbk, P.sbk, kc)
+                            : KM == kKBothContig ? (unsigned)kc : (unsigned)kc * (unsigned)P.sbk;
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-          a[i][q] = (ok && ra[i] != 0xffffffffu) ? (fa ? (double)Af[ra[i] + ka] : A[ra[i] + ka]) : 0.0;
+        for (int i = 0; i < FM; ++i) a[i][q] = ld32(A, ra[i] + ka);
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          b[j][q] = (ok && cb[j] != 0xffffffffu) ? (fb ? (double)Bf[kb + cb[j]] : B[kb + cb[j]]) : 0.0;
+        for (int j = 0; j < FN; ++j) {
+          double v = ld32(B, kb + cb[j]);
+          // keeps the load unconditional (a select on a loaded value is
+          // otherwise turned into a branch around the load and a wait)
+          asm volatile("" : "+v"(v));
+          b[j][q] = ok ? v : 0.0;
+        }
       }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -540,9 +622,29 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
     }
 }
 
-// six waves per SIMD: the register budget that fits six four-wave workgroups
-// (also the LDS limit of the split reduction buffer)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
+// operand element types and the k addressing are wave-uniform (one problem
+// per wave)
+template <int FM, int FN, int KM>
+__device__ __forceinline__ void wave_tile_dt(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
+                                             const Slots& slots, double* red) {
+  switch (P.dt & (kDtA | kDtB)) {
+    case 0: wave_tile<FM, FN, double, double, KM>(P, J, tabs, slots, red); break;
+    case kDtA: wave_tile<FM, FN, float, double, KM>(P, J, tabs, slots, red); break;
+    case kDtB: wave_tile<FM, FN, double, float, KM>(P, J, tabs, slots, red); break;
+    default: wave_tile<FM, FN, float, float, KM>(P, J, tabs, slots, red); break;
+  }
+}
+template <int FM, int FN>
+__device__ __forceinline__ void wave_tile_k(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
+                                            const Slots& slots, double* red) {
+  if (P.tak >= 0 || P.tbk >= 0 || P.sak != 1) wave_tile_dt<FM, FN, kKGeneric>(P, J, tabs, slots, red);
+  else if (P.sbk == 1) wave_tile_dt<FM, FN, kKBothContig>(P, J, tabs, slots, red);
+  else wave_tile_dt<FM, FN, kKAContig>(P, J, tabs, slots, red);
+}
+
+// five waves per SIMD: the register budget (96) that keeps a half chunk's
+// loads of the next steps in flight without spilling
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
                                                int nblocks, const long long* __restrict__ tabs, BSlots bs) {
   __shared__ double red[3 * 1024];
   const Slots& slots = bs.s[blockIdx.y];
@@ -553,9 +655,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   if (J.prob < 0) return;   // an unused slot: only in workgroups of unsplit jobs, which never synchronise
   const GemmProb P = probs[J.prob];
   switch (J.shape) {
-    case 0: wave_tile<4, 1>(P, J, tabs, slots, red); break;
-    case 1: wave_tile<2, 2>(P, J, tabs, slots, red); break;
-    default: wave_tile<1, 4>(P, J, tabs, slots, red); break;
+    case 0: wave_tile_k<4, 1>(P, J, tabs, slots, red); break;
+    case 1: wave_tile_k<2, 2>(P, J, tabs, slots, red); break;
+    default: wave_tile_k<1, 4>(P, J, tabs, slots, red); break;
   }
 }
 
