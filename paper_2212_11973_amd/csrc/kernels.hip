@@ -767,43 +767,78 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
 // ------------------------------------------------------------------ W stage
 // One workgroup of TT_WSTAGE_THREADS threads per task; lanes run over the
 // task's elements, each summing its terms in order.  The task index is
-// uniform (descriptors in scalar registers).
+// uniform (descriptors in scalar registers).  A thread takes up to four
+// elements at a time (indices past the end clamped to the last element, the
+// result not stored) so that their loads are in flight together.  Offsets
+// inside a block are 32-bit unless the plan has a block spanning 2^29
+// elements or more (OFF = long long).
 #ifndef TT_WSTAGE_THREADS
 #define TT_WSTAGE_THREADS 256
 #endif
-template <typename TV>
+template <typename TV, typename OFF>
 __device__ __forceinline__ void wstage_task(const WTask& t, const WTerm* __restrict__ terms,
                                             const TV* __restrict__ in, TV* __restrict__ out) {
-  const int n = t.ni * t.nj;
-  for (int e = threadIdx.x; e < n; e += TT_WSTAGE_THREADS) {
-    const int i = e / t.nj, j = e - i * t.nj;
-    double acc = 0.0;
+  constexpr int U = 4, T = TT_WSTAGE_THREADS;
+  const int nj = t.nj, n = t.ni * nj;
+  const OFF dsi = (OFF)t.dsi, dsj = (OFF)t.dsj;
+  TV* __restrict__ dst = out + t.dst;
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * T) {
+    int ii[U], jj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min(e0 + u * T, n - 1);
+      ii[u] = e / nj;
+      jj[u] = e - ii[u] * nj;
+    }
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
     for (int q = 0; q < t.nt; ++q) {
       const WTerm w = terms[t.t0 + q];
-      acc += w.w * (double)in[w.src + i * w.ssi + j * w.ssj];
+      const TV* __restrict__ src = in + w.src;
+      const OFF ssi = (OFF)w.ssi, ssj = (OFF)w.ssj;
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const OFF o = (OFF)ii[u] * ssi + (OFF)jj[u] * ssj;
+        if constexpr (sizeof(OFF) == 4) v[u] = ld32(src, (unsigned)o);
+        else v[u] = (double)src[o];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] += w.w * v[u];
     }
-    out[t.dst + i * t.dsi + j * t.dsj] = (TV)acc;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * T < n) {
+        const OFF o = (OFF)ii[u] * dsi + (OFF)jj[u] * dsj;
+        if constexpr (sizeof(OFF) == 4) dst[(unsigned)o] = (TV)acc[u];
+        else dst[o] = (TV)acc[u];
+      }
   }
 }
 
 // TV: the stored type of the input and output intermediates (float in FP32 mode)
-template <typename TV>
+template <typename TV, typename OFF>
 __global__ __launch_bounds__(TT_WSTAGE_THREADS) void k_wstage(const WTask* __restrict__ tasks,
                                                               BPtr<const WTerm> b_terms, BPtr<const double> b_in,
                                                               BPtr<double> b_out) {
   const int ib = blockIdx.y;
-  wstage_task<TV>(tasks[blockIdx.x], b_terms.p[ib], reinterpret_cast<const TV*>(b_in.p[ib]),
-                  reinterpret_cast<TV*>(b_out.p[ib]));
+  wstage_task<TV, OFF>(tasks[blockIdx.x], b_terms.p[ib], reinterpret_cast<const TV*>(b_in.p[ib]),
+                       reinterpret_cast<TV*>(b_out.p[ib]));
 }
 
 void launch_wstage(const WPlan& p, BPtr<const WTerm> terms, BPtr<const double> in, BPtr<double> out, int nb,
                    hipStream_t st) {
   if (p.ntasks == 0) return;
   prof_begin(st);
-  if (p.f32)
-    hipLaunchKernelGGL(k_wstage<float>, dim3(p.ntasks, nb), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, terms, in, out);
-  else
-    hipLaunchKernelGGL(k_wstage<double>, dim3(p.ntasks, nb), dim3(TT_WSTAGE_THREADS), 0, st, p.d_tasks, terms, in, out);
+  const dim3 grid(p.ntasks, nb), block(TT_WSTAGE_THREADS);
+  if (p.f32) {
+    if (p.wide) hipLaunchKernelGGL((k_wstage<float, long long>), grid, block, 0, st, p.d_tasks, terms, in, out);
+    else hipLaunchKernelGGL((k_wstage<float, int>), grid, block, 0, st, p.d_tasks, terms, in, out);
+  } else {
+    if (p.wide) hipLaunchKernelGGL((k_wstage<double, long long>), grid, block, 0, st, p.d_tasks, terms, in, out);
+    else hipLaunchKernelGGL((k_wstage<double, int>), grid, block, 0, st, p.d_tasks, terms, in, out);
+  }
   HIP_CHECK_LAUNCH();
   prof_end(st, PROF_WSTAGE, nb * p.flops, nb * p.bytes * (p.f32 ? 0.5 : 1.0));
 }

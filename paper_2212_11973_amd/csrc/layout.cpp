@@ -99,7 +99,16 @@ static void add_prob(GemmPlan& plan, const GemmProb& p) {
 static void finish_wplan(WPlan& w) {
   std::vector<std::pair<long long, long long>> src;
   double out = 0.0;
+  // byte offsets inside a block fit 32 bits unless some block spans 2^29
+  // elements or more (then the kernel forms them in 64 bits)
+  auto fits = [](long long ni, long long nj, long long si, long long sj) {
+    return ni <= 0 || nj <= 0 || (ni - 1) * si + (nj - 1) * sj < (1LL << 29);
+  };
+  w.wide = false;
   for (auto& t : w.tasks) {
+    if (!fits(t.ni, t.nj, t.dsi, t.dsj)) w.wide = true;
+    for (int q = t.t0; q < t.t0 + t.nt; ++q)
+      if (!fits(t.ni, t.nj, w.terms[q].ssi, w.terms[q].ssj)) w.wide = true;
     out += (double)t.ni * t.nj;
     for (int q = t.t0; q < t.t0 + t.nt; ++q) src.push_back({w.terms[q].src, (long long)t.ni * t.nj});
   }

@@ -62,12 +62,15 @@ struct GemmJob { int prob, tm, tn, shape, part, nparts; };
 constexpr int kWaveShapes = 3;
 constexpr int kWaveBM[kWaveShapes] = {64, 32, 16};
 constexpr int kWaveBN[kWaveShapes] = {16, 32, 64};
-// problems at least this large in M, N and K use the LDS-staged tile kernel
+// problems at least this large in M, N and K use the LDS-staged tile kernel.
+// Below K = 128 the wave kernel (one pass over each operand row, paired
+// loads) is faster: that covers every block of a block-sparse sweep, whose K
+// is at most the sector cap; the dense apply (K = D) stays on LDS tiles.
 #ifndef TT_LDS_MIN_MN
 #define TT_LDS_MIN_MN 128
 #endif
 #ifndef TT_LDS_MIN_K
-#define TT_LDS_MIN_K 48
+#define TT_LDS_MIN_K 128
 #endif
 constexpr int kLdsMinMN = TT_LDS_MIN_MN;
 constexpr int kLdsMinK = TT_LDS_MIN_K;
@@ -125,7 +128,8 @@ struct GemmPlan {
   double wave_flops = 0, wave_bytes = 0;
 };
 struct WPlan {
-  bool f32 = false;   // input and output stored as float
+  bool f32 = false;    // input and output stored as float
+  bool wide = false;   // some block spans 2^29 elements or more (64-bit offsets)
   std::vector<WTask> tasks;
   std::vector<WTerm> terms;
   WTask* d_tasks = nullptr;
