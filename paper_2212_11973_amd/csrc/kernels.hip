@@ -958,148 +958,164 @@ __device__ __forceinline__ long long qr_row(const QRTask& T, const long long* ta
   return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs;
 }
 
-// ---- register-resident Householder QR of an m x n block (m <= 64 SL,
-// n <= kQrLdsMaxN) by one workgroup of kQrWaves waves.  Column c belongs to
-// wave c % kQrWaves and lives in its registers: row i in lane i % 64, slot
-// i / 64.  The reflector of the step goes through LDS (two buffers,
-// alternating by step), so every step needs one barrier: while applying
-// reflector j, the owner of column j+1 updates that column first and then
-// turns it into reflector j+1.
+// ---- register-resident Householder QR of an m x n block (m <= 16 SL,
+// n <= kQrLdsMaxN) by one workgroup of kQrWaves waves.  Column c lives in
+// DPP row c % 4 (lanes 16 (c % 4) .. 16 (c % 4) + 15) of wave c / 4, lane
+// 16 r + l holding rows l, l + 16, ..., l + 16 (SL - 1) (so that the 16 lanes
+// of a row read 16 consecutive reflector entries from LDS: no bank conflicts).  A column's dot product is a
+// sum over its 16 lanes by DPP row rotations, four columns of a wave at once,
+// and a wave whose columns are all finished skips the step.  The reflector of
+// the step goes through LDS (two buffers, alternating by step, written in
+// full: zero above the diagonal and past m), so every step needs one barrier:
+// while applying reflector j, the owner of column j + 1 updates that column
+// first and then turns it into reflector j + 1.
 constexpr int kQrWaves = 16;
-constexpr int kQrCPW = kQrLdsMaxN / kQrWaves;   // columns per wave
-// SL: rows per lane (a block has at most 64 SL rows); the chunk kernel uses
-// kQrChunkRows / 64, the stack kernel kQrStackRows / 64
-template <int SL> struct QrCols { double x[kQrCPW][SL]; };
+static_assert(kQrWaves * 4 == kQrLdsMaxN, "one column per DPP row");
+// SL: rows per lane; the chunk kernel uses kQrChunkRows / 16, the stack
+// kernel kQrStackRows / 16
+template <int SL> struct QrCol { double x[SL]; };
+// a column index is below kQrLdsMaxN = 64, so only a lane's first four slots
+// (rows below 64) can lie at or above the diagonal; later slots never do
+constexpr int kQrHead = kQrLdsMaxN / 16;
 
-__device__ __forceinline__ double bcast_sum(double v) { return __shfl(wave_sum(v), 0, 64); }
-
-// entry of local column cc at row i (valid in every lane)
-template <int SL>
-__device__ __forceinline__ double reg_entry(const QrCols<SL>& R, int cc, int i) {
-  double v = 0.0;
-#pragma unroll
-  for (int q = 0; q < kQrCPW; ++q)
-#pragma unroll
-    for (int t = 0; t < SL; ++t)
-      if (q == cc && t == (i >> 6)) v = R.x[q][t];
-  return __shfl(v, i & 63, 64);
+// DPP move of a double within rows of 16 lanes (lanes without a source get 0)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of each DPP row, in every lane of the row (rotations
+// by 8, 4, 2, 1; lanes of a row differ only in the order of the additions)
+__device__ __forceinline__ double row_allsum(double v) {
+  v += dpp_shift<0x128, 0xf>(v);
+  v += dpp_shift<0x124, 0xf>(v);
+  v += dpp_shift<0x122, 0xf>(v);
+  v += dpp_shift<0x121, 0xf>(v);
+  return v;
+}
+// the value of a wave-uniform lane, as a scalar
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// reflector of column j (local cc of this wave): v (v_j = 1, zero above) to
-// vout, the column keeps R in rows <= j (row j := beta) and v below; tau[j]
+// reflector of column c (held by this wave, c < m): row c := beta, rows
+// below := v (v_c = 1, kept for forming Q), rows above untouched; the whole
+// v to vout and tau[c].  alpha and |x below c|^2 are read from one lane, so
+// every lane uses the same scalars.
 template <int SL>
-__device__ void reg_reflector(QrCols<SL>& R, int cc, int j, int m, double* vout, double* tau) {
-  const int lane = threadIdx.x & 63;
-  const double alpha = reg_entry(R, cc, j);
-  double p = 0.0;
+__device__ void qr_reflector(QrCol<SL>& X, int c, int m, double* vout, double* tau) {
+  const int lane = threadIdx.x & 63, r = c & 3, l16 = lane & 15;
+  double a = 0.0, p[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: short dependency chains
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    if (q != cc) continue;
-#pragma unroll
-    for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
-      if (i > j && i < m) p += R.x[q][t] * R.x[q][t];
+  for (int t = 0; t < SL; ++t) {   // rows past m hold zero
+    const int i = l16 + 16 * t;
+    if (t < kQrHead) {
+      if (i == c) a = X.x[t];
+      if (i > c) p[t & 3] += X.x[t] * X.x[t];
+    } else {
+      p[t & 3] += X.x[t] * X.x[t];
     }
   }
-  const double xn2 = bcast_sum(p);
+  const double alpha = lane_value(a, 16 * r + (c & 15));
+  const double xn2 = lane_value(row_allsum((p[0] + p[1]) + (p[2] + p[3])), 16 * r);
   double tj = 0.0, beta = alpha, scal = 1.0;
   if (xn2 > 0.0) {
     beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
     tj = (beta - alpha) / beta;
     scal = 1.0 / (alpha - beta);
   }
-#pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    if (q != cc) continue;
+  if ((lane >> 4) == r) {
 #pragma unroll
     for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
-      if (i >= m) continue;
-      if (i > j) R.x[q][t] *= scal;
-      vout[i] = (i < j) ? 0.0 : (i == j ? 1.0 : R.x[q][t]);
-      if (i == j) R.x[q][t] = beta;
+      const int i = l16 + 16 * t;
+      if (t < kQrHead) {
+        if (i > c) X.x[t] *= scal;   // rows past m hold zero and stay zero
+        vout[i] = (i < c) ? 0.0 : (i == c ? 1.0 : X.x[t]);
+        if (i == c) X.x[t] = beta;
+      } else {
+        X.x[t] *= scal;
+        vout[i] = X.x[t];
+      }
     }
-  }
-  if (lane == 0) tau[j] = tj;
-}
-
-// x -= tau (v . x) v on every owned column c with lo < c < n (v from LDS)
-template <int SL>
-__device__ __forceinline__ void reg_apply(QrCols<SL>& R, const double* v, double tj, int lo, int n, int m, int stop_after,
-                                          double* vnext, double* tau) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double vr[SL];
-#pragma unroll
-  for (int t = 0; t < SL; ++t) {
-    const int i = lane + 64 * t;
-    vr[t] = i < m ? v[i] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    const int c = wave + q * kQrWaves;
-    if (c <= lo || c >= n) continue;
-    if (tj != 0.0) {
-      double d = 0.0;
-#pragma unroll
-      for (int t = 0; t < SL; ++t) d += vr[t] * R.x[q][t];
-      const double f = tj * bcast_sum(d);
-#pragma unroll
-      for (int t = 0; t < SL; ++t) R.x[q][t] -= f * vr[t];
-    }
-    if (c == stop_after) reg_reflector(R, q, c, m, vnext, tau);   // look-ahead (factorisation only)
+    if (l16 == 0) tau[c] = tj;
   }
 }
 
+// x -= tau (v . x) v on every column c of this wave with lo < c < n (v from
+// LDS), then the look-ahead reflector of column stop_after if this wave owns it
 template <int SL>
-__device__ void reg_householder(QrCols<SL>& R, int m, int n, double* vbuf, double* tau) {
+__device__ __forceinline__ void qr_apply(QrCol<SL>& X, const double* v, double tj, int lo, int n, int m, int stop_after,
+                                         double* vnext, double* tau) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15;
+  const int c0 = 4 * wave, c = c0 + (lane >> 4);
+  const double* vl = v + l16;
+  // the wave that builds the next reflector is on every step's critical path:
+  // it issues first on its SIMD
+  const bool owner = stop_after >= 0 && (stop_after >> 2) == wave;
+  if (owner) __builtin_amdgcn_s_setprio(3);
+  if (tj != 0.0 && c0 + 3 > lo && c0 < n) {   // wave-uniform: some column of the wave is still open
+    double d[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: short dependency chains
+#pragma unroll
+    for (int t = 0; t < SL; ++t) d[t & 3] += vl[16 * t] * X.x[t];
+    const double f = tj * row_allsum((d[0] + d[1]) + (d[2] + d[3]));
+    if (c > lo && c < n) {
+#pragma unroll
+      for (int t = 0; t < SL; ++t) X.x[t] -= f * vl[16 * t];
+    }
+  }
+  if (owner) {
+    qr_reflector(X, stop_after, m, vnext, tau);
+    __builtin_amdgcn_s_setprio(0);
+  }
+}
+
+template <int SL>
+__device__ void qr_factor(QrCol<SL>& X, int m, int n, double* vbuf, double* tau) {
   const int wave = threadIdx.x >> 6;
-  if (wave == 0) reg_reflector(R, 0, 0, m, vbuf, tau);
+  if (wave == 0) qr_reflector(X, 0, m, vbuf, tau);
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    reg_apply(R, vbuf + (j & 1) * 64 * SL, tau[j], j, n, m, j + 1 < n ? j + 1 : -1,
-              vbuf + ((j + 1) & 1) * 64 * SL, tau);
+    qr_apply(X, vbuf + (j & 1) * 16 * SL, tau[j], j, n, m, j + 1 < n ? j + 1 : -1,
+             vbuf + ((j + 1) & 1) * 16 * SL, tau);
     __syncthreads();
   }
 }
 
-// signs of the diagonal of R to LDS (owners), then barrier
+// signs of the diagonal of R to LDS (the lane holding each diagonal entry),
+// then barrier
 template <int SL>
-__device__ void reg_signs(const QrCols<SL>& R, int n, double* sgn) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ void qr_signs(const QrCol<SL>& X, int n, double* sgn) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15;
+  const int c = 4 * (threadIdx.x >> 6) + (lane >> 4);
+  if (c < n) {
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    const int c = wave + q * kQrWaves;
-    if (c >= n) continue;
-    const double d = reg_entry(R, q, c);
-    if (lane == 0) sgn[c] = d < 0.0 ? -1.0 : 1.0;
+    for (int t = 0; t < kQrHead; ++t)
+      if (l16 + 16 * t == c) sgn[c] = X.x[t] < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
 }
 
 // explicit Q (backward accumulation); R must have been written out before
 template <int SL>
-__device__ void reg_form_q(QrCols<SL>& R, int m, int n, double* vbuf, const double* tau) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ void qr_form_q(QrCol<SL>& X, int m, int n, double* vbuf, const double* tau) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15;
   for (int j = n - 1; j >= 0; --j) {
-    double* v = vbuf + (j & 1) * 64 * SL;
-    if (j % kQrWaves == wave) {   // publish v_j, then column j := (I - tau_j v v^T) e_j
-      const int cc = j / kQrWaves;
+    double* v = vbuf + (j & 1) * 16 * SL;
+    if ((j >> 2) == wave && (lane >> 4) == (j & 3)) {   // publish v_j, then column j := (I - tau_j v v^T) e_j
       const double tj = tau[j];
 #pragma unroll
-      for (int q = 0; q < kQrCPW; ++q) {
-        if (q != cc) continue;
-#pragma unroll
-        for (int t = 0; t < SL; ++t) {
-          const int i = lane + 64 * t;
-          if (i >= m) continue;
-          const double vi = (i < j) ? 0.0 : (i == j ? 1.0 : R.x[q][t]);
-          v[i] = vi;
-          R.x[q][t] = (i == j) ? 1.0 - tj : -tj * vi;
-        }
+      for (int t = 0; t < SL; ++t) {
+        const int i = l16 + 16 * t;
+        const double vi = t >= kQrHead ? X.x[t] : ((i < j) ? 0.0 : (i == j ? 1.0 : X.x[t]));
+        v[i] = vi;
+        X.x[t] = (t < kQrHead && i == j) ? 1.0 - tj : -tj * vi;
       }
     }
     __syncthreads();
-    reg_apply(R, v, tau[j], j, n, m, -1, nullptr, nullptr);
+    qr_apply(X, v, tau[j], j, n, m, -1, nullptr, nullptr);
   }
   __syncthreads();
 }
@@ -1115,50 +1131,41 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_chunk(const QRTask* __rest
   double* A = b_A.p[blockIdx.y];
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
-  constexpr int SL = kQrChunkRows / 64;
-  __shared__ double vbuf[2 * kQrChunkRows];
+  constexpr int SL = kQrChunkRows / 16;
+  __shared__ __attribute__((aligned(16))) double vbuf[2 * kQrChunkRows];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRChunk C = chunks[blockIdx.x];
   const QRTask T = tasks[C.task];
-  const int m = C.rows, n = T.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  QrCols<SL> R;
+  const int m = C.rows, n = T.n, l16 = threadIdx.x & 15;
+  const int c = 4 * (threadIdx.x >> 6) + ((threadIdx.x & 63) >> 4);
+  QrCol<SL> X;
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    const int c = wave + q * kQrWaves;
-#pragma unroll
-    for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
-      R.x[q][t] = (c < n && i < m) ? A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] : 0.0;
-    }
+  for (int t = 0; t < SL; ++t) {
+    const int i = l16 + 16 * t;
+    X.x[t] = (c < n && i < m) ? A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] : 0.0;
   }
-  reg_householder(R, m, n, vbuf, tau);
+  qr_factor(X, m, n, vbuf, tau);
   const bool last = C.nchunks == 1;
-  if (last) reg_signs(R, n, sgn);
+  if (last) qr_signs(X, n, sgn);
   const long long ldr = (long long)C.nchunks * n;
+  if (c < n) {
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {   // R (rows <= c of column c)
-    const int c = wave + q * kQrWaves;
-    if (c >= n) continue;
-#pragma unroll
-    for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
+    for (int t = 0; t < kQrHead; ++t) {   // R (rows <= c of column c; i < n <= 64)
+      const int i = l16 + 16 * t;
       if (i >= n) continue;
-      const double r = (i <= c) ? R.x[q][t] : 0.0;
+      const double r = (i <= c) ? X.x[t] : 0.0;
       if (last) S[T.sdst + (T.trans ? (long long)c * n + i : (long long)i * n + c)] = sgn[i] * r;
       else ws[C.rw + (long long)c * ldr + (long long)C.chunk * n + i] = r;
     }
   }
-  reg_form_q(R, m, n, vbuf, tau);
+  qr_form_q(X, m, n, vbuf, tau);
+  if (c < n) {
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {   // Q
-    const int c = wave + q * kQrWaves;
-    if (c >= n) continue;
-#pragma unroll
-    for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
+    for (int t = 0; t < SL; ++t) {   // Q
+      const int i = l16 + 16 * t;
       if (i >= m) continue;
-      if (last) A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] = sgn[c] * R.x[q][t];
-      else ws[C.qw + i + (long long)c * m] = R.x[q][t];
+      if (last) A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)c * T.cs] = sgn[c] * X.x[t];
+      else ws[C.qw + i + (long long)c * m] = X.x[t];
     }
   }
 }
@@ -1170,45 +1177,36 @@ __global__ __launch_bounds__(kQrWaves * 64) void k_qr_stack(const QRTask* __rest
                                                             BPtr<double> b_ws) {
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
-  constexpr int SL = kQrStackRows / 64;
-  __shared__ double vbuf[2 * kQrStackRows];
+  constexpr int SL = kQrStackRows / 16;
+  __shared__ __attribute__((aligned(16))) double vbuf[2 * kQrStackRows];
   __shared__ double tau[kQrLdsMaxN], sgn[kQrLdsMaxN];
   const QRStack K = stacks[blockIdx.x];
   const QRTask T = tasks[K.task];
-  const int n = T.n, m = K.nchunks * n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  QrCols<SL> R;
+  const int n = T.n, m = K.nchunks * n, l16 = threadIdx.x & 15;
+  const int c = 4 * (threadIdx.x >> 6) + ((threadIdx.x & 63) >> 4);
+  QrCol<SL> X;
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    const int c = wave + q * kQrWaves;
-#pragma unroll
-    for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
-      R.x[q][t] = (c < n && i < m) ? ws[K.rw + i + (long long)c * m] : 0.0;
-    }
+  for (int t = 0; t < SL; ++t) {
+    const int i = l16 + 16 * t;
+    X.x[t] = (c < n && i < m) ? ws[K.rw + i + (long long)c * m] : 0.0;
   }
-  reg_householder(R, m, n, vbuf, tau);
-  reg_signs(R, n, sgn);
+  qr_factor(X, m, n, vbuf, tau);
+  qr_signs(X, n, sgn);
+  if (c < n) {
 #pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    const int c = wave + q * kQrWaves;
-    if (c >= n) continue;
-#pragma unroll
-    for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
+    for (int t = 0; t < kQrHead; ++t) {   // R (i < n <= 64)
+      const int i = l16 + 16 * t;
       if (i >= n) continue;
-      const double r = (i <= c) ? R.x[q][t] : 0.0;
+      const double r = (i <= c) ? X.x[t] : 0.0;
       S[T.sdst + (T.trans ? (long long)c * n + i : (long long)i * n + c)] = sgn[i] * r;
     }
   }
-  reg_form_q(R, m, n, vbuf, tau);
-#pragma unroll
-  for (int q = 0; q < kQrCPW; ++q) {
-    const int c = wave + q * kQrWaves;
-    if (c >= n) continue;
+  qr_form_q(X, m, n, vbuf, tau);
+  if (c < n) {
 #pragma unroll
     for (int t = 0; t < SL; ++t) {
-      const int i = lane + 64 * t;
-      if (i < m) ws[K.rw + i + (long long)c * m] = sgn[c] * R.x[q][t];
+      const int i = l16 + 16 * t;
+      if (i < m) ws[K.rw + i + (long long)c * m] = sgn[c] * X.x[t];
     }
   }
 }

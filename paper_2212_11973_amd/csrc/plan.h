@@ -92,7 +92,7 @@ struct QRTask { int m, n, trans, pad; long long rbase, rs, cs, rtab, sdst, ws; }
 // chunk kernel; wider or taller tasks use the global-memory kernel.
 constexpr int kQrLdsMaxN = 64;
 constexpr int kQrChunkRows = 256;
-constexpr int kQrStackRows = 512;
+constexpr int kQrStackRows = 256;   // 16 rows per lane, as the chunks (larger stacks spill)
 struct QRChunk { int task, row0, rows, chunk, nchunks, pad; long long qw, rw; };
 struct QRStack { int task, nchunks; long long rw; };
 
