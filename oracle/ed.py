@@ -151,6 +151,36 @@ def same_ode_bilayer(E, beta0, beta):
     return lnZ, float(np.sum(w * E))
 
 
+def same_ode_bilayer_thermo(E, beta0, beta, N):
+    """Per-site thermodynamics of the bilayer values at beta_phys = 2*beta
+    for the same flow as ``same_ode_bilayer`` (weights w_n proportional to
+    (1 - beta0 E_n)^2 exp(-2 (beta - beta0) E_n)):
+    e = <E>_w / N, f = -ln Z_bl / (N beta_phys), the entropy s = beta_phys
+    (e - f) and the specific heat C_e = -beta_phys de/dln(beta_phys) (main
+    text, Fig. 2(b)).  d ln w_n / d beta = -2 E_n, so de/d beta_phys =
+    -Var_w(E) / N and C_e = beta_phys^2 Var_w(E) / N.
+    Returns a dict with beta_phys, e, f, s, c."""
+    lnZ, En = same_ode_bilayer(E, beta0, beta)
+    a = 1.0 - beta0 * E
+    x = 2.0 * np.log(np.abs(a)) - 2.0 * (beta - beta0) * E
+    w = np.exp(x - _logsumexp(x))
+    var = float(np.sum(w * (E - En) ** 2))
+    bp = 2.0 * beta
+    e = En / N
+    f = -lnZ / (N * bp)
+    return {"beta_phys": bp, "e": e, "f": f, "s": bp * (e - f), "c": bp * bp * var / N}
+
+
+def free_fermion_entropy_heat(h, beta):
+    """U = 0 closed forms per mode pair (both spins): with f_k the Fermi
+    function of eps_k = eig(h), S = 2 sum_k [-f ln f - (1-f) ln(1-f)] and
+    C = 2 beta^2 sum_k eps_k^2 f_k (1 - f_k).  Returns (S, C) (totals)."""
+    eps = np.linalg.eigvalsh(h)
+    fk = 1.0 / (np.exp(beta * eps) + 1.0)
+    ent = -(fk * np.log(fk) + (1.0 - fk) * np.log1p(-fk))
+    return 2.0 * float(np.sum(ent)), 2.0 * beta * beta * float(np.sum(eps * eps * fk * (1.0 - fk)))
+
+
 def same_ode_single(E, beta0, beta):
     """ln Tr rho(beta) for rho(beta) = exp(-(beta-beta0) H) (1 - beta0 H)."""
     a = 1.0 - beta0 * E
