@@ -145,16 +145,26 @@ def main():
             for i in range(steps):   # same final beta as the profiled run, for the observable comparison
                 st.sweep(c["dbeta"])
         obs = st.observables()
+        thermo = None
+        if profile:   # two more sweeps after the timed region: entropy and specific heat per site
+            series = [obs]
+            for _ in range(2):
+                st.sweep(c["dbeta"])
+                series.append(st.observables())
+            bp = [o_["beta_phys"] for o_ in series]
+            ce, se = T.tt_thermo_derived(bp, [o_["e"] for o_ in series], [o_["f"] for o_ in series])
+            thermo = dict(beta_phys=bp, e=[o_["e"] for o_ in series], f=[o_["f"] for o_ in series],
+                          c_e=ce, s_e=se)
         st.free()
-        return (t1 - t0) / steps, stats, (prof, prof_s), obs, info
+        return (t1 - t0) / steps, stats, (prof, prof_s), obs, info, thermo
 
-    s_per_step, stats, (prof, prof_s_per_step), obs, (n_sites, dims) = timed_sweeps(args.precision, args.steps,
-                                                                                   args.warmup, True)
+    s_per_step, stats, (prof, prof_s_per_step), obs, (n_sites, dims), thermo = timed_sweeps(
+        args.precision, args.steps, args.warmup, True)
     flops_step = statistics.mean(s.flops_alg for s in stats)
     applies_step = statistics.mean(s.n_applies for s in stats)
     mixed = {}
     for pname in [x for x in args.mixed_precisions.split(",") if x and x != args.precision]:
-        sp, st2, _, ob2, _ = timed_sweeps(pname, args.steps, args.warmup, False)
+        sp, st2, _, ob2, _, _ = timed_sweeps(pname, args.steps, args.warmup, False)
         mixed[pname] = dict(s_per_step=sp, f=ob2["f"], e=ob2["e"],
                             rel_df_vs_main=abs(ob2["f"] - obs["f"]) / max(abs(obs["f"]), 1e-2),
                             rel_de_vs_main=abs(ob2["e"] - obs["e"]) / max(abs(obs["e"]), 1e-2))
@@ -214,13 +224,14 @@ def main():
         torch.cuda.synchronize()
         s_batch = (time.perf_counter() - t0) / args.steps
         print("mu-scan batch done", file=sys.stderr, flush=True)
+        # observables of every instance at the same beta, before instance 0 is timed alone
+        dens = [st.observables() for st in sts]
+        locs = [st.local_observables() for st in sts]
         t0 = time.perf_counter()
         for i in range(args.steps):
             sts[0].sweep(c4["dbeta"])
         torch.cuda.synchronize()
         s_single = (time.perf_counter() - t0) / args.steps
-        dens = [st.observables() for st in sts]
-        locs = [st.local_observables() for st in sts]
         for st in sts:
             st.free()
         # compressibility chi = dn/dmu from neighbouring instances (centred differences)
@@ -231,7 +242,8 @@ def main():
                        instances=len(mus), batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
                        single_instance_s_per_step=s_single, speedup_vs_one_at_a_time=s_single * len(mus) / s_batch,
                        tflops_alg=fl / args.steps / s_batch / 1e12,
-                       beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens], n_per_site=ns,
+                       beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens],
+                       s_per_site=[d["beta_phys"] * (d["e"] - d["f"]) for d in dens], n_per_site=ns,
                        docc_per_site=[lo["docc"] for lo in locs], chi_dn_dmu=chi)
 
     # dense effective-Hamiltonian apply at D (microbenchmark)
@@ -291,7 +303,7 @@ def main():
                   "tflops_alg": flops_step / s_per_step / 1e12,
                   "applies_per_step": applies_step, "applies_per_s": applies_step / s_per_step,
                   "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
-                  "other_precisions": mixed},
+                  "thermo": thermo, "other_precisions": mixed},
         "heff": {"D": Dh, "D_H": DH, **heff},
         "mu_scan": mu_scan,
         "roofline": roof,

@@ -144,6 +144,15 @@ int thermo_observables(tt_state* state, tt_observables* out);
  * Synchronises.  TT_ENUMERIC for non-finite results. */
 int thermo_local_observables(tt_state* s, double* host_out2);
 
+/* Entropy and specific heat per site from n >= 3 bilayer observables taken
+ * along a sweep (host arrays of length n, beta = beta_phys strictly
+ * increasing, e and f per site as in tt_observables): s_out[i] = beta (e - f)
+ * and c_out[i] = C_e = -beta de/dln(beta) (main text, Fig. 2(b); SM Fig.
+ * S1(c)), the slope from the quadratic through three neighbouring points
+ * (centred, one-sided at the ends).  Host arithmetic only; TT_EINVAL for
+ * n < 3, null pointers, non-finite or non-increasing input. */
+int tt_thermo_derived(int n, const double* beta, const double* e, const double* f, double* c_out, double* s_out);
+
 void tt_state_free(tt_state* state);
 const char* tt_last_error(void);
 

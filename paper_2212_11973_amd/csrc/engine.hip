@@ -1423,6 +1423,32 @@ int tt_profile_read(double* host_out68) {
   ABI_END
 }
 
+// Entropy and specific heat per site from a series of bilayer observables
+// (main text, Fig. 2(b); SM Fig. S1(c)): s = beta (e - f), C_e = -beta^2 de/dbeta
+// with the slope of the quadratic through three neighbouring points (centred
+// inside, one-sided at the ends; exact for quadratics).  Host arithmetic only.
+int tt_thermo_derived(int n, const double* beta, const double* e, const double* f, double* c_out, double* s_out) {
+  ABI_BEGIN
+  TT_REQUIRE(n >= 3 && beta && e && f && c_out && s_out, TT_EINVAL, "tt_thermo_derived: need n >= 3 and non-null arrays");
+  for (int i = 0; i < n; ++i) {
+    TT_REQUIRE(std::isfinite(beta[i]) && std::isfinite(e[i]) && std::isfinite(f[i]), TT_EINVAL,
+               "tt_thermo_derived: non-finite input");
+    TT_REQUIRE(beta[i] > 0.0, TT_EINVAL, "tt_thermo_derived: beta must be positive");
+    TT_REQUIRE(i == 0 || beta[i] > beta[i - 1], TT_EINVAL, "tt_thermo_derived: beta must increase strictly");
+  }
+  for (int i = 0; i < n; ++i) {
+    const int a = i == 0 ? 0 : (i == n - 1 ? n - 3 : i - 1);   // nodes a, a+1, a+2
+    double slope = 0.0;
+    for (int p = 0; p < 3; ++p) {   // derivative of the Lagrange basis polynomial of node a+p at beta[i]
+      const int k = a + p, q = a + (p + 1) % 3, r = a + (p + 2) % 3;
+      slope += e[k] * ((beta[i] - beta[q]) + (beta[i] - beta[r])) / ((beta[k] - beta[q]) * (beta[k] - beta[r]));
+    }
+    c_out[i] = -beta[i] * beta[i] * slope;
+    s_out[i] = beta[i] * (e[i] - f[i]);
+  }
+  ABI_END
+}
+
 int tt_heff_last_timing(double* ms4) {
   ABI_BEGIN
   TT_REQUIRE(ms4, TT_EINVAL, "null argument");

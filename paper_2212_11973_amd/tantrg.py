@@ -22,7 +22,7 @@ SYMBOLS = [
     "tt_state_bond_sectors", "tt_state_export_site", "tt_state_import_site",
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
-    "tt_profile_enable", "tt_profile_read", "thermo_local_observables",
+    "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
 ]
 
 
@@ -73,6 +73,7 @@ def lib():
         L.tdvp_sweep_batch.argtypes = [C.POINTER(vp), C.c_int, C.c_double, C.POINTER(tt_sweep_stats)]
         L.thermo_observables.argtypes = [vp, C.POINTER(tt_observables)]
         L.thermo_local_observables.argtypes = [vp, dp]
+        L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -152,6 +153,18 @@ def thermo_local_observables(state):
     out = (C.c_double * 2)()
     _check(lib().thermo_local_observables(state, out))
     return dict(n=out[0], docc=out[1])
+
+
+def tt_thermo_derived(beta_phys, e, f):
+    """(C_e, s) per site for a series of bilayer observables (beta_phys
+    strictly increasing, at least three points)."""
+    n = len(beta_phys)
+    if len(e) != n or len(f) != n:
+        raise ValueError("beta_phys, e and f must have the same length")
+    arr = lambda x: (C.c_double * n)(*[float(v) for v in x])
+    c, s = (C.c_double * n)(), (C.c_double * n)()
+    _check(lib().tt_thermo_derived(n, arr(beta_phys), arr(e), arr(f), c, s))
+    return list(c), list(s)
 
 
 def tt_state_free(state):
