@@ -47,6 +47,20 @@ def _hop(occ, m, n):
     return sign, tuple(occ)
 
 
+def _spin_flip(occ, i, j):
+    """S+_i S-_j = (c+_{i up} c_{i dn}) (c+_{j dn} c_{j up}) on a basis state
+    (S-_j applied first).  Returns (sign, new_occ) or None."""
+    r = _hop(occ, _mode(j, 1), _mode(j, 0))
+    if r is None:
+        return None
+    s1, occ1 = r
+    r = _hop(occ1, _mode(i, 0), _mode(i, 1))
+    if r is None:
+        return None
+    s2, occ2 = r
+    return s1 * s2, occ2
+
+
 class Hubbard:
     """Eq. (3) on a snake-ordered lattice; sector-blocked Hamiltonian."""
 
@@ -88,6 +102,35 @@ class Hubbard:
                             H[pos[new], k] += -self.t * sgn
         idx = np.array([_index(s, self.N) for s in states], dtype=np.int64)
         return H, idx
+
+    def sector_spin_pairs(self, nup, ndn, pairs, zz_only=False):
+        """Dense sum over pairs of S_i . S_j = Sz_i Sz_j + (S+_i S-_j + S-_i S+_j)/2
+        on the (N_up, N_down) block (the operator conserves both), with
+        Sz = (n_up - n_dn)/2; zz_only keeps the Sz Sz part."""
+        states = self.sector_states(nup, ndn)
+        pos = {s: k for k, s in enumerate(states)}
+        O = np.zeros((len(states), len(states)))
+        for k, occ in enumerate(states):
+            for (i, j) in pairs:
+                O[k, k] += 0.25 * (occ[2 * i] - occ[2 * i + 1]) * (occ[2 * j] - occ[2 * j + 1])
+                if zz_only:
+                    continue
+                for (a, b) in ((i, j), (j, i)):
+                    r = _spin_flip(occ, a, b)
+                    if r is not None:
+                        sgn, new = r
+                        O[pos[new], k] += 0.5 * sgn
+        return O
+
+    def dense_spin_pairs(self, pairs):
+        """The full 4^N x 4^N matrix of sum over pairs of S_i . S_j (small N)."""
+        N = self.N
+        O = np.zeros((4 ** N, 4 ** N))
+        for nup in range(N + 1):
+            for ndn in range(N + 1):
+                _, idx = self.sector_hamiltonian(nup, ndn)
+                O[np.ix_(idx, idx)] = self.sector_spin_pairs(nup, ndn, pairs)
+        return O
 
     def dense_hamiltonian(self):
         """Full 4^N x 4^N H in the dense basis (small N only)."""
@@ -179,6 +222,34 @@ def free_fermion_entropy_heat(h, beta):
     fk = 1.0 / (np.exp(beta * eps) + 1.0)
     ent = -(fk * np.log(fk) + (1.0 - fk) * np.log1p(-fk))
     return 2.0 * float(np.sum(ent)), 2.0 * beta * beta * float(np.sum(eps * eps * fk * (1.0 - fk)))
+
+
+def same_ode_bilayer_spin_pairs(model, beta0, beta, pairs, zz_only=False):
+    """Bilayer value at 2*beta of the spin correlation averaged over pairs,
+    F = sum_pairs <S_i . S_j> / len(pairs) (main text, Fig. 2(c)), with
+    <O> = Tr(O rho^2) / Tr(rho^2) for rho = exp(-(beta-beta0) H)(1 - beta0 H):
+    sum_k w_k <k|O|k> over the eigenvectors of every (N_up, N_down) block."""
+    xs, os_ = [], []
+    for nup in range(model.N + 1):
+        for ndn in range(model.N + 1):
+            h, _ = model.sector_hamiltonian(nup, ndn)
+            E, V = np.linalg.eigh(h)
+            O = model.sector_spin_pairs(nup, ndn, pairs, zz_only)
+            a = 1.0 - beta0 * E
+            xs.append(2.0 * np.log(np.abs(a)) - 2.0 * (beta - beta0) * E)
+            os_.append(np.einsum("fk,fg,gk->k", V, O, V))
+    x, o = np.concatenate(xs), np.concatenate(os_)
+    w = np.exp(x - _logsumexp(x))
+    return float(np.sum(w * o)) / len(pairs)
+
+
+def free_fermion_spin_pairs(h, beta, pairs):
+    """U = 0 closed form (Wick): with the one-particle density matrix
+    G = (exp(beta h) + 1)^-1 per spin, <S_i . S_j> = -(3/2) G_ij^2 for i != j
+    (Sz Sz gives -G_ij^2/2, the spin-flip pair -G_ij^2).  Averaged over pairs."""
+    eps, U = np.linalg.eigh(h)
+    G = (U / (np.exp(beta * eps) + 1.0)) @ U.T
+    return float(np.mean([-1.5 * G[i, j] ** 2 for (i, j) in pairs]))
 
 
 def same_ode_single(E, beta0, beta):

@@ -43,3 +43,23 @@ def nn_bonds(W, L, geometry):
         elif geometry == CYLINDER and W >= 3:
             edges.add(tuple(sorted((index[(x, y)], index[(x, 0)]))))
     return sorted(edges)
+
+
+def pairs_at_distance(W, L, geometry, d2):
+    """Pairs (i, j), i < j, of chain indices whose squared lattice distance is
+    d2: dx^2 + dy^2 with dy taken the short way round a cylinder's width (W >=
+    3), as in the spin correlation F(d) of the main text (average over the
+    pairs at distance d)."""
+    if geometry == CHAIN and W != 1:
+        raise ValueError("a chain has W = 1")
+    order = snake_order(W, L)
+    out = []
+    for i, (xi, yi) in enumerate(order):
+        for j in range(i + 1, len(order)):
+            xj, yj = order[j]
+            dy = abs(yi - yj)
+            if geometry == CYLINDER and W >= 3:
+                dy = min(dy, W - dy)
+            if (xi - xj) ** 2 + dy ** 2 == d2:
+                out.append((i, j))
+    return out

@@ -186,3 +186,48 @@ def mpo_to_dense(Ws):
         M = T.reshape(c, O * so, I * si)
     assert M.shape[0] == 1
     return M[0]
+
+
+SZ = np.diag([0.0, 0.5, -0.5, 0.0])
+SP = CDAG_UP @ C_DN          # S+ = c+_up c_dn on one site: |up><dn|
+SM = SP.T.copy()
+# spin channels: (left operator, right operator, coefficient); all bosonic
+SPIN_CHANNELS = ((SZ, SZ, 1.0), (SP, SM, 0.5), (SM, SP, 0.5))
+
+
+def spin_pair_mpo(N, pairs):
+    """MPO of sum over pairs (i < j) of S_i . S_j (boundary bonds of dimension
+    1): channels start, src(i, type) for every site i < k that has a partner
+    j >= k (type over Sz, S+, S-), and done."""
+    later = [sorted(j for (i2, j) in pairs if i2 == i) for i in range(N)]
+    def states(k):
+        st = [("start",)]
+        for i in range(k):
+            if later[i] and later[i][-1] >= k:
+                st += [("src", i, ty) for ty in range(3)]
+        return st + [("done",)]
+    bonds = [states(k) for k in range(N + 1)]
+    Ws = []
+    for k in range(N):
+        L, R = bonds[k], bonds[k + 1]
+        col = {s: b for b, s in enumerate(R)}
+        W = np.zeros((len(L), 4, 4, len(R)))
+        for a, s in enumerate(L):
+            if s[0] == "start":
+                W[a, :, :, col[("start",)]] += ID4
+                for ty, (lop, _, _) in enumerate(SPIN_CHANNELS):
+                    if ("src", k, ty) in col:
+                        W[a, :, :, col[("src", k, ty)]] += lop
+            elif s[0] == "done":
+                W[a, :, :, col[("done",)]] += ID4
+            else:
+                _, i, ty = s
+                _, rop, cf = SPIN_CHANNELS[ty]
+                if ("src", i, ty) in col:
+                    W[a, :, :, col[("src", i, ty)]] += ID4
+                if k in later[i]:
+                    W[a, :, :, col[("done",)]] += cf * rop
+        Ws.append(W)
+    Ws[0] = Ws[0][:1]
+    Ws[-1] = Ws[-1][..., -1:]
+    return Ws
