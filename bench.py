@@ -153,8 +153,12 @@ def main():
                 series.append(st.observables())
             bp = [o_["beta_phys"] for o_ in series]
             ce, se = T.tt_thermo_derived(bp, [o_["e"] for o_ in series], [o_["f"] for o_ in series])
+            spin = {}
+            for d2 in (1, 2, 4):   # spin correlation F(d), d = 1, sqrt 2, 2, at the last beta
+                F_, npairs = st.spin_correlation(d2)
+                spin["d2=%d" % d2] = dict(F=F_, pairs=npairs)
             thermo = dict(beta_phys=bp, e=[o_["e"] for o_ in series], f=[o_["f"] for o_ in series],
-                          c_e=ce, s_e=se)
+                          c_e=ce, s_e=se, spin_correlation=spin)
         st.free()
         return (t1 - t0) / steps, stats, (prof, prof_s), obs, info, thermo
 
@@ -227,6 +231,7 @@ def main():
         # observables of every instance at the same beta, before instance 0 is timed alone
         dens = [st.observables() for st in sts]
         locs = [st.local_observables() for st in sts]
+        f_nn = [st.spin_correlation(1)[0] for st in sts]
         t0 = time.perf_counter()
         for i in range(args.steps):
             sts[0].sweep(c4["dbeta"])
@@ -244,7 +249,7 @@ def main():
                        tflops_alg=fl / args.steps / s_batch / 1e12,
                        beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens],
                        s_per_site=[d["beta_phys"] * (d["e"] - d["f"]) for d in dens], n_per_site=ns,
-                       docc_per_site=[lo["docc"] for lo in locs], chi_dn_dmu=chi)
+                       docc_per_site=[lo["docc"] for lo in locs], chi_dn_dmu=chi, spin_corr_nn=f_nn)
 
     # dense effective-Hamiltonian apply at D (microbenchmark)
     heff = {}

@@ -144,6 +144,18 @@ int thermo_observables(tt_state* state, tt_observables* out);
  * Synchronises.  TT_ENUMERIC for non-finite results. */
 int thermo_local_observables(tt_state* s, double* host_out2);
 
+/* Spin correlation F(d) = (1/N_d) sum over the N_d pairs (i, j) at squared
+ * lattice distance d2 of <S_i . S_j> (main text, Fig. 2(c)), S_i . S_j =
+ * Sz_i Sz_j + (S+_i S-_j + S-_i S+_j)/2, as the bilayer value at beta_phys =
+ * 2 beta (<<rho|O (x) 1|rho>> / <<rho|rho>>, SM Sec. II.A).  The distance is
+ * dx^2 + dy^2 on the lattice, dy the short way round a cylinder's width;
+ * *host_npairs (may be NULL) receives N_d.  Evaluated with a finite-state-
+ * machine MPO of the pair sum through right environments to the centre
+ * (site 0): valid for a state as left by mpo_init_highT or tdvp_sweep.  The
+ * first call for a d2 builds its plans; FP64 in every precision mode.
+ * Synchronises.  TT_EINVAL if no pair lies at that distance. */
+int thermo_spin_correlation(tt_state* s, int d2, double* host_F, int* host_npairs);
+
 /* Entropy and specific heat per site from n >= 3 bilayer observables taken
  * along a sweep (host arrays of length n, beta = beta_phys strictly
  * increasing, e and f per site as in tt_observables): s_out[i] = beta (e - f)

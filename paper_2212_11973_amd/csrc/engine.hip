@@ -146,15 +146,15 @@ struct tt_state {
   double flops = 0.0, flops_heff = 0.0;
   int n_applies = 0, n_exps = 0;
 
-  // sums of on-site operators (density, double occupancy): plans and buffers
-  // built on the first request
-  struct LocalObs {
-    bool built = false;
+  // observables given as MPOs (sums of on-site operators, sums of spin
+  // pairs), keyed by kind: plans and buffers built on the first request
+  struct ObsMpo {
     SiteTables tabs;
-    std::vector<SitePlan> plans[2];
+    std::vector<SitePlan> plans;
     double *ea = nullptr, *eb = nullptr, *unit = nullptr, *pws = nullptr;
     double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr;
-  } lobs;
+  };
+  std::map<int, ObsMpo> obs;
 
   double* lam_ptr() { return lz + 4 * kMaxKrylov + 4; }
   double* err_ptr() { return lz + 4 * kMaxKrylov + 5; }
@@ -173,12 +173,14 @@ tt_state::~tt_state() {
   for (auto p : Renv) dfree(p);
   for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws}) dfree(p);
   dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
-  for (auto& kind : lobs.plans)
-    for (auto& p : kind) {
+  for (auto& kv : obs) {
+    ObsMpo& O = kv.second;
+    for (auto& p : O.plans) {
       free_plan(p.s1); free_plan(p.s3); free_plan(p.r1); free_plan(p.r3); free_plan(p.w2); free_plan(p.wr);
     }
-  for (double* p : {lobs.ea, lobs.eb, lobs.unit, lobs.pws, lobs.T1, lobs.T2, lobs.Y, lobs.Z}) dfree(p);
-  dfree(lobs.tabs.dev);
+    for (double* p : {O.ea, O.eb, O.unit, O.pws, O.T1, O.T2, O.Y, O.Z}) dfree(p);
+    dfree(O.tabs.dev);
+  }
 }
 
 namespace {
@@ -834,74 +836,73 @@ long long check_all_plans(tt_state& s, std::string& rep) {
 
 int fail(const Error& e) { g_err = e.what(); return e.code; }
 
-// ------------------------------------------------------------ local observables
-// <<rho| O (x) 1 |rho>> / <<rho|rho>> for O = sum_i op_i (bilayer value at
-// beta_phys = 2 beta, as for the energy): right environments of the two-channel
-// MPO of O from the right end to bond 1, then one effective-operator apply at
-// the centre (site 0).  Always FP64.
+// ------------------------------------------------------------ MPO observables
+// <<rho| O (x) 1 |rho>> / <<rho|rho>> for an operator O given as an MPO
+// (bilayer value at beta_phys = 2 beta, as for the energy): right
+// environments of the MPO of O from the right end to bond 1, then one
+// effective-operator apply at the centre (site 0).  Always FP64.
 const double kLocalOps[2][4] = {{0.0, 1.0, 1.0, 2.0},    // n = n_up + n_dn
                                 {0.0, 0.0, 0.0, 1.0}};   // n_up n_dn
+constexpr int kObsSpinPairs = 1000;                      // + d2: spin pairs at squared distance d2
 
-void build_local_obs(tt_state& s) {
-  auto& O = s.lobs;
+// plans and buffers of one observable MPO (bond 0: start; bond N: start and
+// done, of which only done is kept)
+tt_state::ObsMpo& build_obs_mpo(tt_state& s, int key, const Mpo& m) {
+  auto& O = s.obs[key];
   const int N = s.N;
   hipStream_t st = ST();
   std::vector<std::vector<Q>> qH(N + 1);
-  qH[0] = {Q{0, 0}};
-  for (int k = 1; k < N; ++k) qH[k] = {Q{0, 0}, Q{0, 0}};
+  for (int k = 0; k < N; ++k)
+    for (int a = 0; a < m.DH[k]; ++a) qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : m.charge(k, a));
   qH[N] = {Q{0, 0}};
+  std::vector<std::vector<double>> W = m.W;
+  const int DRN = m.DH[N];
+  std::vector<double> w((size_t)m.DH[N - 1] * 16, 0.0);   // last site: the done selector
+  for (int a = 0; a < m.DH[N - 1]; ++a)
+    for (int q = 0; q < 16; ++q) w[(size_t)a * 16 + q] = m.W[N - 1][((size_t)a * 16 + q) * DRN + (DRN - 1)];
+  W[N - 1] = w;
   long long t1 = 1, t2 = 1, y = 1, z = 1, env = 1, pw = 1;
   for (int k = 0; k <= N; ++k) env = std::max(env, make_env_layout(s.bonds[k], qH[k]).size);
-  for (int kind = 0; kind < 2; ++kind) {
-    Mpo m = make_local_sum_mpo(N, kLocalOps[kind]);
-    std::vector<std::vector<double>> W = m.W;
-    std::vector<double> w((size_t)m.DH[N - 1] * 16, 0.0);   // last site: the done selector
-    for (int a = 0; a < m.DH[N - 1]; ++a)
-      for (int q = 0; q < 16; ++q) w[(size_t)a * 16 + q] = m.W[N - 1][((size_t)a * 16 + q) * 2 + 1];
-    W[N - 1] = w;
-    for (int k = 0; k < N; ++k) {
-      SitePlan P = build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, qH[k], qH[k + 1], W[k], W[k], O.tabs);
-      for (GemmPlan* g : {&P.s1, &P.s3, &P.r1, &P.r3}) g->wave_ok = true;
-      O.plans[kind].push_back(std::move(P));
-    }
+  for (int k = 0; k < N; ++k) {
+    SitePlan P = build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, qH[k], qH[k + 1], W[k], W[k], O.tabs);
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.r1, &P.r3}) g->wave_ok = true;
+    O.plans.push_back(std::move(P));
   }
   O.tabs.dev = upload(O.tabs.host, st);
   const std::vector<long long>* T = &O.tabs.host;
-  for (int kind = 0; kind < 2; ++kind)
-    for (int k = 0; k < N; ++k) {
-      SitePlan& P = O.plans[kind][k];
-      if (k == 0) {
-        upload_plan(P.s1, T, st); upload_plan(P.w2, st); upload_plan(P.s3, T, st);
-        t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size);
-        pw = std::max(pw, std::max(P.s1.pws_size, P.s3.pws_size));
-      } else {
-        upload_plan(P.r1, T, st); upload_plan(P.wr, st); upload_plan(P.r3, T, st);
-        y = std::max(y, P.y_size); z = std::max(z, P.z_size);
-        pw = std::max(pw, std::max(P.r1.pws_size, P.r3.pws_size));
-      }
+  for (int k = 0; k < N; ++k) {
+    SitePlan& P = O.plans[k];
+    if (k == 0) {
+      upload_plan(P.s1, T, st); upload_plan(P.w2, st); upload_plan(P.s3, T, st);
+      t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size);
+      pw = std::max(pw, std::max(P.s1.pws_size, P.s3.pws_size));
+    } else {
+      upload_plan(P.r1, T, st); upload_plan(P.wr, st); upload_plan(P.r3, T, st);
+      y = std::max(y, P.y_size); z = std::max(z, P.z_size);
+      pw = std::max(pw, std::max(P.r1.pws_size, P.r3.pws_size));
     }
+  }
   O.ea = (double*)dalloc(8 * env); O.eb = (double*)dalloc(8 * env); O.unit = (double*)dalloc(8);
   O.pws = (double*)dalloc(8 * pw);
   O.T1 = (double*)dalloc(8 * t1); O.T2 = (double*)dalloc(8 * t2);
   O.Y = (double*)dalloc(8 * y); O.Z = (double*)dalloc(8 * z);
-  O.built = true;
+  return O;
 }
 
-double local_expectation(tt_state& s, int kind) {
-  auto& O = s.lobs;
+double obs_expectation(tt_state& s, tt_state::ObsMpo& O) {
   const int N = s.N;
   hipStream_t st = ST();
   double* Rin = O.ea;
   double* Rout = O.eb;
   launch_fill(Rin, 1.0, 1, st);      // bond N: the done channel
   for (int k = N - 1; k >= 1; --k) {
-    SitePlan& P = O.plans[kind][k];
+    SitePlan& P = O.plans[k];
     launch_gemm(P.r1, O.tabs.dev, one(Slots{{Rin, s.A[k], O.Y, nullptr}}), 1, TT_FP64, one(O.pws), st);
     launch_wstage(P.wr, one<const WTerm>(P.wr.d_terms), one<const double>(O.Y), one(O.Z), 1, st);
     launch_gemm(P.r3, O.tabs.dev, one(Slots{{s.A[k], O.Z, Rout, nullptr}}), 1, TT_FP64, one(O.pws), st);
     std::swap(Rin, Rout);
   }
-  SitePlan& P = O.plans[kind][0];
+  SitePlan& P = O.plans[0];
   launch_fill(O.unit, 1.0, 1, st);   // bond 0: the start channel
   launch_gemm(P.s1, O.tabs.dev, one(Slots{{O.unit, s.A[0], O.T1, nullptr}}), 1, TT_FP64, one(O.pws), st);
   launch_wstage(P.w2, one<const WTerm>(P.w2.d_terms), one<const double>(O.T1), one(O.T2), 1, st);
@@ -916,6 +917,12 @@ double local_expectation(tt_state& s, int kind) {
   HIPX(hipMemcpyAsync(h, ob, 16, hipMemcpyDeviceToHost, st));
   HIPX(hipStreamSynchronize(st));
   return h[0] / h[1];
+}
+
+double local_expectation(tt_state& s, int kind) {
+  auto it = s.obs.find(kind);
+  tt_state::ObsMpo& O = it != s.obs.end() ? it->second : build_obs_mpo(s, kind, make_local_sum_mpo(s.N, kLocalOps[kind]));
+  return obs_expectation(s, O);
 }
 
 #define ABI_BEGIN try {
@@ -1166,12 +1173,27 @@ int thermo_observables(tt_state* s, tt_observables* o) {
 int thermo_local_observables(tt_state* s, double* host_out2) {
   ABI_BEGIN
   TT_REQUIRE(s && host_out2, TT_EINVAL, "null argument");
-  if (!s->lobs.built) build_local_obs(*s);
   const double n = local_expectation(*s, 0) / s->N;
   const double docc = local_expectation(*s, 1) / s->N;
   TT_REQUIRE(std::isfinite(n) && std::isfinite(docc), TT_ENUMERIC, "non-finite observables");
   host_out2[0] = n;
   host_out2[1] = docc;
+  ABI_END
+}
+
+int thermo_spin_correlation(tt_state* s, int d2, double* host_F, int* host_npairs) {
+  ABI_BEGIN
+  TT_REQUIRE(s && host_F, TT_EINVAL, "null argument");
+  TT_REQUIRE(d2 >= 1, TT_EINVAL, "thermo_spin_correlation: d2 must be positive");
+  const auto pairs = pairs_at_distance(s->lat, d2);
+  TT_REQUIRE(!pairs.empty(), TT_EINVAL, "thermo_spin_correlation: no pair of sites at that distance");
+  const int key = kObsSpinPairs + d2;
+  auto it = s->obs.find(key);
+  tt_state::ObsMpo& O = it != s->obs.end() ? it->second : build_obs_mpo(*s, key, make_spin_pair_mpo(s->N, pairs));
+  const double F = obs_expectation(*s, O) / (double)pairs.size();
+  TT_REQUIRE(std::isfinite(F), TT_ENUMERIC, "non-finite spin correlation");
+  *host_F = F;
+  if (host_npairs) *host_npairs = (int)pairs.size();
   ABI_END
 }
 

@@ -11,6 +11,7 @@
 //   ks < k < N : [start, dst(j,type) for pending destinations j ascending, done]
 // type in (c+_up P, c+_dn P, P c_up, P c_dn).
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <set>
 
@@ -86,7 +87,9 @@ LocalOps local_ops(double U, double mu) {
   o.left[3] = mul(o.par, o.cd);  o.right[3] = o.cdd;
   return o;
 }
-const Q kChannelQ[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+// channel charges: the hopping channels 0..3 (c+_up, c+_dn, c_up, c_dn at the
+// source), then the spin channels 4..6 (Sz, S+, S- at the source)
+const Q kChannelQ[7] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}, {0, 0}, {1, -1}, {-1, 1}};
 }  // namespace
 
 Q Mpo::charge(int k, int a) const {
@@ -360,6 +363,93 @@ std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<s
         it = (it->second <= 0) ? dims[k].erase(it) : std::next(it);
   }
   return dims;
+}
+
+// Pairs (i, j), i < j, of chain indices at squared lattice distance d2: dx^2 +
+// dy^2, dy the short way round a cylinder's width (W >= 3).  Coordinates
+// follow the snake: column x = n / W, top-down for even x, bottom-up for odd.
+std::vector<std::pair<int, int>> pairs_at_distance(const Lattice& lat, int d2) {
+  const int W = lat.W;
+  auto xy = [&](int n, int& x, int& y) {
+    x = n / W;
+    const int r = n % W;
+    y = (x % 2 == 0) ? W - 1 - r : r;
+  };
+  std::vector<std::pair<int, int>> out;
+  for (int i = 0; i < lat.N; ++i)
+    for (int j = i + 1; j < lat.N; ++j) {
+      int xi, yi, xj, yj;
+      xy(i, xi, yi);
+      xy(j, xj, yj);
+      int dy = std::abs(yi - yj);
+      if (lat.geometry == TT_CYLINDER && W >= 3) dy = std::min(dy, W - dy);
+      if ((xi - xj) * (xi - xj) + dy * dy == d2) out.push_back({i, j});
+    }
+  return out;
+}
+
+// Sum over pairs (i < j) of S_i . S_j = Sz_i Sz_j + (S+_i S-_j + S-_i S+_j)/2
+// (the spin correlation of main text Fig. 2(c)) as an MPO: channels start,
+// src(i, type) for every site i < k that has a partner j >= k (type Sz, S+,
+// S-: spin channels 4..6), and done.  Spin operators are bosonic (no string).
+Mpo make_spin_pair_mpo(int N, const std::vector<std::pair<int, int>>& pairs) {
+  std::vector<std::set<int>> later(N);
+  for (auto& p : pairs) later[p.first].insert(p.second);
+  Mpo m;
+  m.N = N;
+  m.states.resize(N + 1);
+  for (int k = 0; k <= N; ++k) {
+    auto& st = m.states[k];
+    st.push_back({0, -1, -1});
+    for (int i = 0; i < k && k < N; ++i)
+      if (!later[i].empty() && *later[i].rbegin() >= k)
+        for (int ty = 4; ty < 7; ++ty) st.push_back({2, i, ty});
+    if (k > 0) st.push_back({1, -1, -1});
+  }
+  for (int k = 0; k <= N; ++k) m.DH.push_back((int)m.states[k].size());
+  M4 id = zero4(), sz = zero4(), sp = zero4(), sm = zero4();
+  for (int i = 0; i < 4; ++i) id.v[i][i] = 1.0;
+  sz.v[1][1] = 0.5; sz.v[2][2] = -0.5;
+  sp.v[1][2] = 1.0;   // |up><dn|
+  sm.v[2][1] = 1.0;
+  const M4* left[3] = {&sz, &sp, &sm};
+  const M4* right[3] = {&sz, &sm, &sp};
+  const double coef[3] = {1.0, 0.5, 0.5};
+  m.W.resize(N);
+  for (int k = 0; k < N; ++k) {
+    const auto& Ls = m.states[k];
+    const auto& Rs = m.states[k + 1];
+    const int DL = (int)Ls.size(), DR = (int)Rs.size();
+    std::vector<double> Wk((size_t)DL * 16 * DR, 0.0);
+    auto find = [&](int kind, int site, int type) {
+      for (int b = 0; b < DR; ++b)
+        if (Rs[b].kind == kind && (kind < 2 || (Rs[b].site == site && Rs[b].type == type))) return b;
+      return -1;
+    };
+    auto put = [&](int a, int b, const M4& op, double c) {
+      for (int so = 0; so < 4; ++so)
+        for (int si = 0; si < 4; ++si) Wk[(((size_t)a * 4 + so) * 4 + si) * DR + b] += c * op.v[so][si];
+    };
+    const int bstart = find(0, -1, -1), bdone = find(1, -1, -1);
+    for (int a = 0; a < DL; ++a) {
+      const MpoState& s = Ls[a];
+      if (s.kind == 0) {
+        put(a, bstart, id, 1.0);
+        for (int ty = 4; ty < 7; ++ty) {
+          const int b = find(2, k, ty);
+          if (b >= 0) put(a, b, *left[ty - 4], 1.0);
+        }
+      } else if (s.kind == 1) {
+        put(a, bdone, id, 1.0);
+      } else {
+        const int b = find(2, s.site, s.type);
+        if (b >= 0) put(a, b, id, 1.0);
+        if (later[s.site].count(k)) put(a, bdone, *right[s.type - 4], coef[s.type - 4]);
+      }
+    }
+    m.W[k] = Wk;
+  }
+  return m;
 }
 
 // Sum of one on-site operator over all sites, sum_i op_i (a diagonal 4x4 in

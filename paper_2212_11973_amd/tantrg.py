@@ -23,6 +23,7 @@ SYMBOLS = [
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
+    "thermo_spin_correlation",
 ]
 
 
@@ -74,6 +75,7 @@ def lib():
         L.thermo_observables.argtypes = [vp, C.POINTER(tt_observables)]
         L.thermo_local_observables.argtypes = [vp, dp]
         L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
+        L.thermo_spin_correlation.argtypes = [vp, C.c_int, dp, ip]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -153,6 +155,13 @@ def thermo_local_observables(state):
     out = (C.c_double * 2)()
     _check(lib().thermo_local_observables(state, out))
     return dict(n=out[0], docc=out[1])
+
+
+def thermo_spin_correlation(state, d2):
+    """(F(d), number of pairs) for pairs at squared lattice distance d2."""
+    F, n = C.c_double(), C.c_int()
+    _check(lib().thermo_spin_correlation(state, d2, C.byref(F), C.byref(n)))
+    return F.value, n.value
 
 
 def tt_thermo_derived(beta_phys, e, f):
@@ -287,6 +296,9 @@ class State:
 
     def local_observables(self):
         return thermo_local_observables(self.h)
+
+    def spin_correlation(self, d2):
+        return thermo_spin_correlation(self.h, d2)
 
     def info(self):
         return tt_state_info(self.h)
