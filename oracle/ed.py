@@ -64,11 +64,15 @@ def _spin_flip(occ, i, j):
 class Hubbard:
     """Eq. (3) on a snake-ordered lattice; sector-blocked Hamiltonian."""
 
-    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0):
+    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0):
         self.W, self.L, self.geometry = W, L, geometry
-        self.t, self.U, self.mu = float(t), float(U), float(mu)
+        self.t, self.U, self.mu, self.tp = float(t), float(U), float(mu), float(tp)
         self.N = W * L
         self.bonds = lattice.nn_bonds(W, L, geometry)
+        # hopping amplitude per coupled pair: t on bonds, tp on diagonals (SM Eq. S1)
+        self.hops = [(i, j, self.t) for (i, j) in self.bonds]
+        if self.tp != 0.0:
+            self.hops += [(i, j, self.tp) for (i, j) in lattice.nnn_bonds(W, L, geometry)]
 
     def _diag(self, occ):
         e = 0.0
@@ -92,14 +96,14 @@ class Hubbard:
         H = np.zeros((len(states), len(states)))
         for k, occ in enumerate(states):
             H[k, k] += self._diag(occ)
-            for (i, j) in self.bonds:
+            for (i, j, amp) in self.hops:
                 for spin in (0, 1):
                     mi, mj = _mode(i, spin), _mode(j, spin)
                     for (m, n) in ((mi, mj), (mj, mi)):
                         r = _hop(occ, m, n)
                         if r is not None:
                             sgn, new = r
-                            H[pos[new], k] += -self.t * sgn
+                            H[pos[new], k] += -amp * sgn
         idx = np.array([_index(s, self.N) for s in states], dtype=np.int64)
         return H, idx
 
@@ -158,9 +162,9 @@ class Hubbard:
     def hopping_matrix(self):
         """Single-particle matrix h with H(U=0) = sum_s c+_s h c_s."""
         h = -self.mu * np.eye(self.N)
-        for (i, j) in self.bonds:
-            h[i, j] -= self.t
-            h[j, i] -= self.t
+        for (i, j, amp) in self.hops:
+            h[i, j] -= amp
+            h[j, i] -= amp
         return h
 
 

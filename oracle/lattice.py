@@ -63,3 +63,9 @@ def pairs_at_distance(W, L, geometry, d2):
             if (xi - xj) ** 2 + dy ** 2 == d2:
                 out.append((i, j))
     return out
+
+
+def nnn_bonds(W, L, geometry):
+    """Next-nearest-neighbour pairs of SM Eq. S1: the diagonal neighbours
+    (squared distance 2; a chain has none)."""
+    return pairs_at_distance(W, L, geometry, 2)

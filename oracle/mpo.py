@@ -63,12 +63,16 @@ def local_charge(sigma):
 class HubbardMPO:
     """W tensors of Eq. (3) with the bond-state convention above."""
 
-    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0):
+    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0):
         self.N = N = W * L
-        self.t, self.U, self.mu = float(t), float(U), float(mu)
-        bonds = lattice.nn_bonds(W, L, geometry)
+        self.t, self.U, self.mu, self.tp = float(t), float(U), float(mu), float(tp)
+        # hopping amplitude per coupled pair (i < j): t on bonds, tp on the
+        # diagonal neighbours of SM Eq. S1 when tp != 0
+        self.amp = {b: self.t for b in lattice.nn_bonds(W, L, geometry)}
+        if self.tp != 0.0:
+            self.amp.update({b: self.tp for b in lattice.nnn_bonds(W, L, geometry)})
         self.partners = [set() for _ in range(N)]
-        for (i, j) in bonds:
+        for (i, j) in self.amp:
             self.partners[i].add(j)
         # bond states: list of labels per bond k = 0..N
         self.ks = ks = N // 2
@@ -106,7 +110,6 @@ class HubbardMPO:
         left, right = self.states[k], self.states[k + 1]
         ri = {lab: n for n, lab in enumerate(right)}
         Wk = np.zeros((len(left), 4, 4, len(right)))
-        t = self.t
         onsite = self.U * (N_UP @ N_DN) - self.mu * (N_UP + N_DN)
         later = sorted(j for j in self.partners[k])          # neighbours j > k
         for a, lab in enumerate(left):
@@ -119,7 +122,7 @@ class HubbardMPO:
                         Wk[a, :, :, ri[("src", k, ty)]] += CHANNELS[ty][0]
                     for j in later:
                         if ("dst", j, ty) in ri:
-                            Wk[a, :, :, ri[("dst", j, ty)]] += -t * CHANNELS[ty][0]
+                            Wk[a, :, :, ri[("dst", j, ty)]] += -self.amp[(k, j)] * CHANNELS[ty][0]
             elif lab == "done":
                 Wk[a, :, :, ri["done"]] += ID4
             elif lab[0] == "src":
@@ -128,9 +131,9 @@ class HubbardMPO:
                     Wk[a, :, :, ri[lab]] += PAR
                 for j in sorted(self.partners[i]):
                     if j > k and ("dst", j, ty) in ri:
-                        Wk[a, :, :, ri[("dst", j, ty)]] += -t * PAR
+                        Wk[a, :, :, ri[("dst", j, ty)]] += -self.amp[(i, j)] * PAR
                 if k in self.partners[i]:
-                    Wk[a, :, :, ri["done"]] += -t * CHANNELS[ty][1]
+                    Wk[a, :, :, ri["done"]] += -self.amp[(i, k)] * CHANNELS[ty][1]
             else:
                 _, j, ty = lab
                 if j == k:
