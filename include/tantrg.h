@@ -56,8 +56,12 @@ typedef struct tt_state tt_state;
 #define TT_BF16X3 2  /* split-BF16: hi*hi + hi*lo + lo*hi, FP32 MFMA accumulation */
 #define TT_BF16X6 3  /* split-BF16 with three parts, six products */
 
-/* Eq. (3): H = -t sum_<ij>,s (c+_is c_js + h.c.) + U sum n_iu n_id - mu sum n_i.
- * tp (next-nearest hopping of Eq. S1) must be 0: not supported. */
+/* Eq. (3): H = -t sum_<ij>,s (c+_is c_js + h.c.) + U sum n_iu n_id - mu sum n_i,
+ * with the next-nearest hopping of SM Eq. S1, -tp sum_<<ij>>,s (c+_is c_js +
+ * h.c.), over diagonal neighbours (squared lattice distance 2, a cylinder's
+ * width taken the short way for W >= 3; a chain has none).  tp = 0 gives the
+ * MPO of Eq. (3) unchanged; tp != 0 adds the diagonal partners to its
+ * channels (larger D_H). */
 typedef struct {
   int W, L;          /* width and length; chain: W = 1 */
   int geometry;      /* TT_CHAIN, TT_CYLINDER (wrap across W only for W >= 3), TT_OPEN_SQUARE */

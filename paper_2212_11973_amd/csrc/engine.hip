@@ -428,7 +428,7 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   // the plans keep every MPO entry that is nonzero for generic couplings, so
   // states that differ only in t, U, mu (an exact zero such as U - 2 mu at
   // half filling included) get identical plans and can share launches
-  s.Wpat = env_tensors(make_hubbard_mpo(s.lat, 1.0, 1.0, 0.3));
+  s.Wpat = env_tensors(make_hubbard_mpo(s.lat, 1.0, s.model.tp != 0.0 ? 0.7 : 0.0, 1.0, 0.3));
   s.site.clear(); s.env.clear(); s.bmat.clear();
   for (int k = 0; k < N; ++k) s.site.push_back(make_site_layout(s.bonds[k], s.bonds[k + 1], s.G));
   for (int k = 0; k <= N; ++k) {
@@ -627,7 +627,6 @@ std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
 }
 
 void validate(const tt_model& m, const tt_options& o) {
-  TT_REQUIRE(m.tp == 0.0, TT_EINVAL, "next-nearest hopping tp is not supported");
   TT_REQUIRE(o.D >= 1, TT_EINVAL, "D must be positive");
   TT_REQUIRE(o.symmetry == 0 || o.symmetry == 1, TT_EINVAL, "symmetry must be 0 or 1");
   TT_REQUIRE(o.taylor_order == 1, TT_EINVAL, "only the linear start rho0 = 1 - beta0 H is supported");
@@ -637,7 +636,8 @@ void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(o.env_on_host == 0, TT_EINVAL, "host-resident environments are not supported");
   TT_REQUIRE(o.sector_cap >= 0, TT_EINVAL, "sector_cap must be >= 0");
   TT_REQUIRE(std::isfinite(o.beta0) && std::isfinite(o.pad_eps), TT_EINVAL, "beta0 and pad_eps must be finite");
-  TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.U) && std::isfinite(m.mu), TT_EINVAL, "model parameters must be finite");
+  TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.tp) && std::isfinite(m.U) && std::isfinite(m.mu), TT_EINVAL,
+             "model parameters must be finite");
 }
 
 std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o, bool with_plans = true) {
@@ -647,7 +647,7 @@ std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o
   s->opts = o;
   s->lat = make_lattice(m.W, m.L, m.geometry);
   s->N = s->lat.N;
-  s->mpo = make_hubbard_mpo(s->lat, m.t, m.U, m.mu);
+  s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu);
   s->G = make_groups(o.symmetry == 1);
   auto dims = bond_dims(*s);
   if (with_plans) {
@@ -1339,7 +1339,7 @@ int tt_state_load(const char* path, tt_state** out) {
   s->opts = o;
   s->lat = make_lattice(m.W, m.L, m.geometry);
   s->N = s->lat.N;
-  s->mpo = make_hubbard_mpo(s->lat, m.t, m.U, m.mu);
+  s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu);
   s->G = make_groups(o.symmetry == 1);
   std::vector<std::map<Q, int>> dims(s->N + 1);
   for (int k = 0; k <= s->N; ++k) {

@@ -98,14 +98,21 @@ Q Mpo::charge(int k, int a) const {
   return kChannelQ[s.type];
 }
 
-Mpo make_hubbard_mpo(const Lattice& lat, double t, double U, double mu) {
+Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double mu) {
   const int N = lat.N;
   Mpo m;
   m.N = N;
-  std::vector<std::set<int>> later(N), earlier(N);   // neighbours j > i, i < j
-  for (auto& b : lat.bonds) {
-    later[b.first].insert(b.second);
-    earlier[b.second].insert(b.first);
+  // hopping amplitude of every coupled pair (i < j): t on nearest neighbours,
+  // tp on next-nearest (diagonal) neighbours when tp != 0 (SM Eq. S1)
+  std::map<std::pair<int, int>, double> hop;
+  for (auto& b : lat.bonds) hop[b] = t;
+  if (tp != 0.0)
+    for (auto& b : pairs_at_distance(lat, 2)) hop[b] = tp;
+  auto amp = [&](int i, int j) { return hop.at({std::min(i, j), std::max(i, j)}); };
+  std::vector<std::set<int>> later(N), earlier(N);   // coupled sites j > i, i < j
+  for (auto& kv : hop) {
+    later[kv.first.first].insert(kv.first.second);
+    earlier[kv.first.second].insert(kv.first.first);
   }
   const int ks = N / 2;
   m.states.resize(N + 1);
@@ -158,7 +165,7 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double U, double mu) {
           if (b >= 0) put(a, b, o.left[ty], 1.0);
           for (int j : later[k]) {
             int bd = find(3, j, ty);
-            if (bd >= 0) put(a, bd, o.left[ty], -t);
+            if (bd >= 0) put(a, bd, o.left[ty], -amp(k, j));
           }
         }
       } else if (s.kind == 1) {
@@ -169,9 +176,9 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double U, double mu) {
         for (int j : later[s.site]) {
           if (j <= k) continue;
           int bd = find(3, j, s.type);
-          if (bd >= 0) put(a, bd, o.par, -t);
+          if (bd >= 0) put(a, bd, o.par, -amp(s.site, j));
         }
-        if (later[s.site].count(k)) put(a, bdone, o.right[s.type], -t);
+        if (later[s.site].count(k)) put(a, bdone, o.right[s.type], -amp(s.site, k));
       } else {
         if (s.site == k) {
           put(a, bdone, o.right[s.type], 1.0);

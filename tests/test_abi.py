@@ -44,7 +44,7 @@ def test_invalid_options_rejected_without_gpu(field, value):
     assert e.value.code == T.TT_EINVAL
 
 
-@pytest.mark.parametrize("kw", [dict(tp=0.3), dict(W=2, geometry=T.TT_CHAIN), dict(L=1), dict(geometry=5)])
+@pytest.mark.parametrize("kw", [dict(tp=float("nan")), dict(W=2, geometry=T.TT_CHAIN), dict(L=1), dict(geometry=5)])
 def test_invalid_model_rejected_without_gpu(kw):
     with pytest.raises(T.TTError) as e:
         T.mpo_init_highT(_m(**kw), T.options())
@@ -90,16 +90,17 @@ def test_descriptor_bounds_full_workloads(name):
     assert v == 0, rep
 
 
-@pytest.mark.parametrize("W,L,geo,D,cap", [(4, 4, 1, 64, 0), (2, 3, 2, 40, 0), (4, 16, 1, 300, 0), (1, 6, 0, 30, 0),
-                                           (4, 4, 1, 64, 6), (4, 16, 1, 300, 12), (4, 16, 1, 2000, 64),
-                                           (3, 4, 2, 100, 5)])
-def test_sectors_match_oracle_allocation(W, L, geo, D, cap):
+@pytest.mark.parametrize("W,L,geo,D,cap,tp", [(4, 4, 1, 64, 0, 0.0), (2, 3, 2, 40, 0, 0.0), (4, 16, 1, 300, 0, 0.0),
+                                              (1, 6, 0, 30, 0, 0.0), (4, 4, 1, 64, 6, 0.0), (4, 16, 1, 300, 12, 0.0),
+                                              (4, 16, 1, 2000, 64, 0.0), (3, 4, 2, 100, 5, 0.0),
+                                              (4, 4, 1, 64, 0, -0.25), (3, 4, 2, 100, 5, 0.3)])
+def test_sectors_match_oracle_allocation(W, L, geo, D, cap, tp):
     from oracle import charges, mpo
-    mm = mpo.HubbardMPO(W, L, geo, 1.0, 8.0, 1.0)
+    mm = mpo.HubbardMPO(W, L, geo, 1.0, 8.0, 1.0, tp=tp)
     N = mm.N
     q0 = [mm.bond_charges(k) for k in range(N)] + [[(0, 0)]]
     lay = charges.bond_layouts(q0, N, D, True, cap)
-    m = T.model(W, L, geo, 1.0, 8.0, 1.0)
+    m = T.model(W, L, geo, 1.0, 8.0, 1.0, tp)
     o = T.options(D=D, symmetry=1, sector_cap=cap)
     bonds = range(N + 1) if N <= 16 else sorted({0, 1, 2, 3, 4, 6, 9, 13, N // 2, N - 5, N - 2, N - 1, N})
     for k in bonds:
