@@ -1228,11 +1228,24 @@ __global__ __launch_bounds__(256) void k_qr_combine(const QRTask* __restrict__ t
     Q2[k + j * n] = ws[C.rw + (long long)j * ldr + (long long)C.chunk * n + k];
   }
   __syncthreads();
-  for (int e = tid; e < m * n; e += blockDim.x) {
-    int i = e % m, j = e / m;
-    double acc = 0.0;
-    for (int k = 0; k < n; ++k) acc += ws[C.qw + i + (long long)k * m] * Q2[k + j * n];
-    A[T.rbase + qr_row(T, tabs, C.row0 + i) + (long long)j * T.cs] = acc;
+  // a thread forms four outputs of one row (columns j0 .. j0 + 3), so each
+  // element of Q_c it loads serves four products; the column group of a
+  // lane's neighbours is the same (Q2 entries broadcast from LDS)
+  const int ng = (n + 3) >> 2;
+  const double* __restrict__ Qc = ws + C.qw;
+  for (int e = tid; e < m * ng; e += blockDim.x) {
+    const int i = e % m, j0 = 4 * (e / m);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) {
+      const double q = Qc[i + (long long)k * m];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += q * Q2[k + min(j0 + u, n - 1) * n];
+    }
+    const long long row = T.rbase + qr_row(T, tabs, C.row0 + i);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u < n) A[row + (long long)(j0 + u) * T.cs] = acc[u];
   }
 }
 
