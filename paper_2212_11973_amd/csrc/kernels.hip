@@ -1532,10 +1532,10 @@ __global__ __launch_bounds__(kRedThreads) void k_lz_combine_norm(BPtr<const doub
 // coefficients of exp(t T) e_1 * ||v|| for the Krylov tridiagonal T: Taylor
 // series of (tT)/2^s with 2^s >= 2 ||tT||_inf, then s squarings; one thread per
 // matrix element, everything in LDS.
-__global__ __launch_bounds__(256) void k_lz_coeffs(BPtr<const double> b_alpha, BPtr<const double> b_beta,
-                                                   BPtr<const double> b_hn, int K, double t, double tol,
-                                                   BPtr<const double> b_scal, BPtr<double> b_coeff,
-                                                   BPtr<double> b_err) {
+__global__ __launch_bounds__(64) void k_lz_coeffs(BPtr<const double> b_alpha, BPtr<const double> b_beta,
+                                                  BPtr<const double> b_hn, int K, double t, double tol,
+                                                  BPtr<const double> b_scal, BPtr<double> b_coeff,
+                                                  BPtr<double> b_err) {
   const double* alpha = b_alpha.p[blockIdx.y];
   const double* beta = b_beta.p[blockIdx.y];
   const double* hn = b_hn.p[blockIdx.y];
@@ -1545,20 +1545,26 @@ __global__ __launch_bounds__(256) void k_lz_coeffs(BPtr<const double> b_alpha, B
   __shared__ double A[kMaxKrylov * kMaxKrylov], E[kMaxKrylov * kMaxKrylov], P[kMaxKrylov * kMaxKrylov],
       X[kMaxKrylov * kMaxKrylov];
   __shared__ int s_k, s_sq;
-  __shared__ double s_done;
+  // one wave (K <= kMaxKrylov <= 64): lane j reads alpha_j, beta_j, ||H q_j||
   const int tid = threadIdx.x;
+  const double aj = tid < K ? alpha[tid] : 0.0;
+  const double bj = tid < K - 1 ? beta[tid] : 0.0;
+  const double hj = tid < K - 1 ? hn[tid] : 0.0;
+  // the basis ends at the first j < K - 1 with beta_j <= tol ||H q_j|| (or beta_j = 0): k = j + 1
+  const bool brk = tid < K - 1 && (!(bj > tol * hj) || bj == 0.0);
+  const unsigned long long mask = __ballot(brk);
+  const int kb = mask ? __ffsll((long long)mask) : K;
+  // infinity norm of t T_k (row i: |alpha_i| + |beta_{i-1}| + |beta_i| inside the k x k block)
+  const double bprev = __shfl(bj, tid > 0 ? tid - 1 : 0, 64);
+  double r = 0.0;
+  if (tid < kb) r = fabs(t) * (fabs(aj) + (tid > 0 ? fabs(bprev) : 0.0) + (tid + 1 < kb ? fabs(bj) : 0.0));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
   if (tid == 0) {
-    int k = K;
-    for (int j = 0; j < K - 1; ++j)
-      if (!(beta[j] > tol * hn[j]) || beta[j] == 0.0) { k = j + 1; break; }
-    double nrm = 0.0;
-    for (int i = 0; i < k; ++i) {
-      double r = fabs(alpha[i]) + (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i + 1 < k ? fabs(beta[i]) : 0.0);
-      nrm = fmax(nrm, fabs(t) * r);
-    }
+    double nrm = r;
     int sq = 0;
     while (nrm > 0.5 && sq < 60) { nrm *= 0.5; ++sq; }
-    s_k = k;
+    s_k = kb;
     s_sq = sq;
   }
   __syncthreads();
@@ -1601,7 +1607,6 @@ __global__ __launch_bounds__(256) void k_lz_coeffs(BPtr<const double> b_alpha, B
     for (int e = tid; e < kk; e += blockDim.x) E[e] = X[e];
     __syncthreads();
   }
-  (void)s_done;
   const double nv = scal[0];
   for (int i = tid; i < K; i += blockDim.x) coeff[i] = (i < k) ? nv * E[i * k + 0] : 0.0;
   if (tid == 0 && k == K) {
@@ -1688,7 +1693,7 @@ void launch_lz_combine_norm(BPtr<const double> Q, long long ld, int K, BPtr<cons
 void launch_lz_coeffs(BPtr<const double> alpha, BPtr<const double> beta, BPtr<const double> hn, int K, double t,
                       double tol, BPtr<const double> scal, BPtr<double> coeff, BPtr<double> errmax, int nb,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_lz_coeffs, dim3(1, nb), dim3(256), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
+  hipLaunchKernelGGL(k_lz_coeffs, dim3(1, nb), dim3(64), 0, st, alpha, beta, hn, K, t, tol, scal, coeff, errmax);
   HIP_CHECK_LAUNCH();
 }
 void launch_normalize_log(BPtr<double> v, long long n, BPtr<const double> part, BPtr<double> lambda, int nb,
