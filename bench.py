@@ -250,6 +250,28 @@ def main():
                        beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens],
                        s_per_site=[d["beta_phys"] * (d["e"] - d["f"]) for d in dens], n_per_site=ns,
                        docc_per_site=[lo["docc"] for lo in locs], chi_dn_dmu=chi, spin_corr_nn=f_nn)
+        if args.precision == "fp64":
+            # the mixed-precision batched form: the same scan with FP32 contractions
+            o32 = T.options(D=D4, symmetry=1, beta0=c4["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c4["krylov"],
+                            precision=PREC["fp32"])
+            print("init mu-scan fp32", file=sys.stderr, flush=True)
+            s32 = [T.State.init(T.model(c4["W"], c4["L"], c4["geometry"], c4["t"], c4["U"], mu), o32) for mu in mus]
+            h32 = [st.h for st in s32]
+            T.tdvp_sweep_batch(h32, c4["dbeta"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                T.tdvp_sweep_batch(h32, c4["dbeta"])
+            torch.cuda.synchronize()
+            s_b32 = (time.perf_counter() - t0) / args.steps
+            e32 = [st.observables()["e"] for st in s32]
+            for st in s32:
+                st.free()
+            print("mu-scan fp32 batch done", file=sys.stderr, flush=True)
+            mu_scan.update(fp32_batched_s_per_instance_step=s_b32 / len(mus),
+                           fp32_batched_speedup_vs_fp64_one_at_a_time=s_single * len(mus) / s_b32,
+                           fp32_max_rel_de_vs_fp64=max(abs(a - b) / max(abs(b), 1e-2)
+                                                       for a, b in zip(e32, [d_["e"] for d_ in dens])))
 
     # dense effective-Hamiltonian apply at D (microbenchmark)
     heff = {}
