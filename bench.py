@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--heff-reps", type=int, default=5)
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-observables", action="store_true",
+                    help="skip the entropy, specific heat and spin correlations after the timed sweeps")
     ap.add_argument("--cpu-D", type=int, default=1500, help="bond dimension of the oracle sample")
     ap.add_argument("--mu-scan", type=int, default=8,
                     help="instances of the batched mu-scan on the 6x12 cylinder (0: skip)")
@@ -146,7 +148,7 @@ def main():
                 st.sweep(c["dbeta"])
         obs = st.observables()
         thermo = None
-        if profile:   # two more sweeps after the timed region: entropy and specific heat per site
+        if profile and not args.no_observables:   # two more sweeps after the timed region: entropy and specific heat
             series = [obs]
             for _ in range(2):
                 st.sweep(c["dbeta"])
