@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--heff-reps", type=int, default=5)
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graphs", action="store_true", help="replay captured sweeps (hipGraph) in the timed loop")
     ap.add_argument("--no-observables", action="store_true",
                     help="skip the entropy, specific heat and spin correlations after the timed sweeps")
     ap.add_argument("--cpu-D", type=int, default=1500, help="bond dimension of the oracle sample")
@@ -121,6 +122,7 @@ def main():
         print("init %s D=%d %s" % (args.workload, D, prec), file=sys.stderr, flush=True)
         st = T.State.init(m, o)
         info = st.info()
+        T.tt_sweep_graphs(args.graphs)   # the first sweep of a step captures, later ones replay
         for i in range(warmup):
             st.sweep(c["dbeta"])
             print("warmup %d done" % i, file=sys.stderr, flush=True)
@@ -146,6 +148,7 @@ def main():
         else:
             for i in range(steps):   # same final beta as the profiled run, for the observable comparison
                 st.sweep(c["dbeta"])
+        T.tt_sweep_graphs(False)
         obs = st.observables()
         thermo = None
         if profile and not args.no_observables:   # two more sweeps after the timed region: entropy and specific heat

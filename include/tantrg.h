@@ -212,6 +212,15 @@ int tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free_fn, void* ctx);
  * Synchronises. */
 int tt_heff_last_timing(double* host_ms4);
 
+/* Sweeps as replayed hipGraphs (default off).  When on, the first
+ * tdvp_sweep of a state with a step dbeta captures the sweep's launches
+ * into a graph (on a private stream; the call's results are those of the
+ * graph's first launch), and later tdvp_sweep calls with the same dbeta
+ * launch that graph on the registered stream; a different dbeta captures
+ * anew.  Results equal those of uncaptured sweeps bit for bit.  Not used
+ * while profiling is enabled, nor by tdvp_sweep_batch. */
+int tt_sweep_graphs(int on);
+
 /* Opt-in kernel timing: when on, every launch of the grouped GEMM, the MPO
  * (W) stage and the QR kernels is bracketed by HIP events on its stream, and
  * inside a grouped GEMM every kernel dispatch is timed on its own.

@@ -25,6 +25,7 @@ namespace {
 
 thread_local std::string g_err;
 hipStream_t g_stream = nullptr;
+bool g_graphs = false;   // sweeps captured into hipGraphs and replayed (tt_sweep_graphs)
 tt_alloc_fn g_alloc = nullptr;
 tt_free_fn g_free = nullptr;
 void* g_alloc_ctx = nullptr;
@@ -156,6 +157,14 @@ struct tt_state {
   };
   std::map<int, ObsMpo> obs;
 
+  // a captured sweep (hipGraph) for one step dbeta, replayed by later sweeps
+  // with the same step; the host counters of one sweep are kept with it
+  struct SweepGraph {
+    hipGraphExec_t exec = nullptr;
+    double dbeta = 0.0, flops = 0.0, flops_heff = 0.0;
+    int n_applies = 0, n_exps = 0;
+  } sg;
+
   double* lam_ptr() { return lz + 4 * kMaxKrylov + 4; }
   double* err_ptr() { return lz + 4 * kMaxKrylov + 5; }
   double* obs_ptr() { return lz + 4 * kMaxKrylov + 6; }   // 4 scratch values
@@ -173,6 +182,7 @@ tt_state::~tt_state() {
   for (auto p : Renv) dfree(p);
   for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws}) dfree(p);
   dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
+  if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
   for (auto& kv : obs) {
     ObsMpo& O = kv.second;
     for (auto& p : O.plans) {
@@ -1099,13 +1109,57 @@ int mpo_init_highT(const tt_model* model, const tt_options* opts, tt_state** out
   ABI_END
 }
 
+// One sweep through a captured graph: the first sweep with a step dbeta is
+// captured on a private stream (the caller's stream may be the null stream,
+// which cannot be captured) and instantiated; every sweep launches the graph on
+// the caller's stream.  Kernel arguments are fixed by the state's buffers and
+// dbeta, and a sweep has no host round trip, so a replay repeats it exactly.
+void sweep_graph(tt_state& s, double dbeta) {
+  static hipStream_t cap = nullptr;
+  if (!cap) HIPX(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  auto& G = s.sg;
+  if (!G.exec || G.dbeta != dbeta) {
+    if (G.exec) { HIPX(hipGraphExecDestroy(G.exec)); G.exec = nullptr; }
+    hipStream_t saved = g_stream;
+    g_stream = cap;
+    hipGraph_t graph = nullptr;
+    HIPX(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    try {
+      sweep_once(batch_of(s), dbeta);   // records the launches; advances beta on the host
+    } catch (...) {
+      (void)hipStreamEndCapture(cap, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      g_stream = saved;
+      throw;
+    }
+    g_stream = saved;
+    HIPX(hipStreamEndCapture(cap, &graph));
+    const hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      G.exec = nullptr;
+      throw Error(TT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    G.dbeta = dbeta;
+    G.flops = s.flops; G.flops_heff = s.flops_heff; G.n_applies = s.n_applies; G.n_exps = s.n_exps;
+  } else {
+    s.beta += dbeta;
+    s.sweeps++;
+    s.flops = G.flops; s.flops_heff = G.flops_heff; s.n_applies = G.n_applies; s.n_exps = G.n_exps;
+  }
+  HIPX(hipGraphLaunch(G.exec, g_stream));
+}
+
 int tdvp_sweep(tt_state* s, double dbeta, tt_sweep_stats* stats) {
   ABI_BEGIN
   TT_REQUIRE(s, TT_EINVAL, "null state");
   TT_REQUIRE(std::isfinite(dbeta), TT_EINVAL, "dbeta must be finite");
   reset_counters(*s);
   auto t0 = std::chrono::steady_clock::now();
-  sweep_once(batch_of(*s), dbeta);
+  if (g_graphs && !prof_enabled())
+    sweep_graph(*s, dbeta);
+  else
+    sweep_once(batch_of(*s), dbeta);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     HIPX(hipStreamSynchronize(ST()));
@@ -1425,6 +1479,12 @@ int tt_model_bond_sectors(const tt_model* model, const tt_options* opts, int k, 
   TT_REQUIRE(model && opts && nsec, TT_EINVAL, "null argument");
   auto s = make_host_state(*model, *opts, false);
   return tt_state_bond_sectors(s.get(), k, nsec, qu, qd, dim);
+  ABI_END
+}
+
+int tt_sweep_graphs(int on) {
+  ABI_BEGIN
+  g_graphs = on != 0;
   ABI_END
 }
 

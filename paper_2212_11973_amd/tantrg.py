@@ -23,7 +23,7 @@ SYMBOLS = [
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
-    "thermo_spin_correlation",
+    "thermo_spin_correlation", "tt_sweep_graphs",
 ]
 
 
@@ -76,6 +76,7 @@ def lib():
         L.thermo_local_observables.argtypes = [vp, dp]
         L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         L.thermo_spin_correlation.argtypes = [vp, C.c_int, dp, ip]
+        L.tt_sweep_graphs.argtypes = [C.c_int]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -155,6 +156,11 @@ def thermo_local_observables(state):
     out = (C.c_double * 2)()
     _check(lib().thermo_local_observables(state, out))
     return dict(n=out[0], docc=out[1])
+
+
+def tt_sweep_graphs(on):
+    """Replay captured sweeps (hipGraph) for repeated steps of equal dbeta."""
+    _check(lib().tt_sweep_graphs(1 if on else 0))
 
 
 def thermo_spin_correlation(state, d2):
