@@ -61,6 +61,16 @@ def _spin_flip(occ, i, j):
     return s1 * s2, occ2
 
 
+def _annihilate(occ, m):
+    """Apply c_m to a basis state.  Returns (sign, new_occ) or None."""
+    if occ[m] == 0:
+        return None
+    sign = (-1) ** sum(occ[:m])
+    occ = list(occ)
+    occ[m] = 0
+    return sign, tuple(occ)
+
+
 class Hubbard:
     """Eq. (3) on a snake-ordered lattice; sector-blocked Hamiltonian."""
 
@@ -158,6 +168,28 @@ class Hubbard:
                 nups.append(np.full(e.size, nup))
                 ndns.append(np.full(e.size, ndn))
         return np.concatenate(evals), np.concatenate(nups), np.concatenate(ndns)
+
+    def dense_annihilator(self, site, spin):
+        """The full 4^N x 4^N matrix of c_{site, spin} (small N)."""
+        N = self.N
+        C = np.zeros((4 ** N, 4 ** N))
+        for occ in product((0, 1), repeat=2 * N):
+            r = _annihilate(occ, _mode(site, spin))
+            if r is not None:
+                C[_index(r[1], N), _index(occ, N)] = r[0]
+        return C
+
+    def dense_function(self, fn):
+        """The full 4^N x 4^N matrix fn(H), built block by block from the
+        eigen-decomposition of every (N_up, N_down) block (small N)."""
+        N = self.N
+        M = np.zeros((4 ** N, 4 ** N))
+        for nup in range(N + 1):
+            for ndn in range(N + 1):
+                h, idx = self.sector_hamiltonian(nup, ndn)
+                E, V = np.linalg.eigh(h)
+                M[np.ix_(idx, idx)] = (V * fn(E)) @ V.T
+        return M
 
     def hopping_matrix(self):
         """Single-particle matrix h with H(U=0) = sum_s c+_s h c_s."""
@@ -298,3 +330,61 @@ def same_ode_bilayer_local(model, beta0, beta):
     w = np.exp(x - _logsumexp(x))
     return float(np.sum(w * n)) / N, float(np.sum(w * d)) / N
 
+
+
+# ---------------------------------------------------------------- Matsubara G
+def momentum_phases(W, L, k):
+    """k . r for every chain index, r = (x, y) the lattice coordinates of the
+    snake order (x along the length L, y across the width W)."""
+    return np.array([k[0] * x + k[1] * y for (x, y) in lattice.snake_order(W, L)])
+
+
+def green_k(model, rho, k):
+    """Single-particle Matsubara Green's function at half the imaginary time
+    of a density operator (main text, Fermi-surface paragraph):
+    G(k, beta/2) = sum_s Tr[rho c+_ks rho c_ks] / Tr[rho rho], with
+    c_ks = N^-1/2 sum_r exp(-i k.r) c_rs.  For rho = exp(-beta H / 2) this is
+    sum_s <exp(beta H/2) c+_ks exp(-beta H/2) c_ks>_beta; for a bilayer state
+    rho(beta) it is the value at beta_phys = 2 beta.  Complex arithmetic as
+    written; the imaginary part vanishes for a real symmetric rho."""
+    N = model.N
+    ph = momentum_phases(model.W, model.L, k)
+    num = 0.0 + 0.0j
+    for spin in (0, 1):
+        ck = sum(np.exp(-1j * ph[r]) * model.dense_annihilator(r, spin) for r in range(N)) / np.sqrt(N)
+        num += np.trace(rho @ ck.conj().T @ rho @ ck)
+    den = np.trace(rho @ rho)
+    assert abs(num.imag) <= 1e-12 * max(1.0, abs(num.real))
+    return float(num.real / den)
+
+
+def thermal_green(model, beta, k):
+    """G(k, beta/2) of the thermal state exp(-beta H)."""
+    return green_k(model, model.dense_function(lambda E: np.exp(-0.5 * beta * E)), k)
+
+
+def same_ode_bilayer_green(model, beta0, beta, k):
+    """G(k, beta_phys/2) at beta_phys = 2 beta for the flow of
+    ``same_ode_bilayer``: rho(beta) = exp(-(beta-beta0) H) (1 - beta0 H)."""
+    return green_k(model, model.dense_function(lambda E: np.exp(-(beta - beta0) * E) * (1.0 - beta0 * E)), k)
+
+
+def free_fermion_green(h, W, L, beta, k):
+    """U = 0 closed form: with h = sum_m eps_m phi_m phi_m^T,
+    <c+_r(beta/2) c_r'> = sum_m phi_m(r) phi_m(r') exp(beta eps_m / 2) f(eps_m)
+    = sum_m phi_m(r) phi_m(r') / (2 cosh(beta eps_m / 2)), so
+    G(k, beta/2) = (2/N) sum_m |sum_r exp(i k.r) phi_m(r)|^2 / (2 cosh(beta eps_m / 2))
+    (both spins)."""
+    eps, phi = np.linalg.eigh(h)
+    ph = momentum_phases(W, L, k)
+    amp = np.abs(np.exp(1j * ph) @ phi) ** 2
+    return 2.0 * float(np.sum(amp / (2.0 * np.cosh(0.5 * beta * eps)))) / h.shape[0]
+
+
+def atomic_green(U, mu, beta):
+    """t = 0 closed form (every k): one site with energies 0, -mu (twice),
+    U - 2 mu; per spin Tr[exp(-beta H/2) c+ exp(-beta H/2) c] collects the
+    pairs (0 -> s) and (other spin -> both), so
+    G = 2 [exp(beta mu / 2) + exp(-beta (U - 3 mu) / 2)] / Z_site."""
+    z = 1.0 + 2.0 * np.exp(beta * mu) + np.exp(-beta * (U - 2.0 * mu))
+    return 2.0 * (np.exp(0.5 * beta * mu) + np.exp(-0.5 * beta * (U - 3.0 * mu))) / z

@@ -234,3 +234,57 @@ def spin_pair_mpo(N, pairs):
     Ws[0] = Ws[0][:1]
     Ws[-1] = Ws[-1][..., -1:]
     return Ws
+
+
+def green_mpo(W, L, k):
+    """Super-operator MPO (tensors W[a, s_out, s_in, b], s = 4 sigma + sigma',
+    16 x 16 local matrices, boundary bonds of dimension 1) of
+        X(k) = sum_s sum_{r, r'} cos(k.(r - r')) c+_{r s} (x) (c_{r' s})^T ,
+    so that <<rho|X|rho>> = sum_{r r'} cos(k.(r - r')) Tr[rho c+_r rho c_r']
+    = N Tr[rho c+_k rho c_k] (main text, Fermi-surface paragraph; the Choi map
+    of SM Sec. II.A sends A rho B to (A (x) B^T)|rho>>).
+
+    With the Jordan-Wigner strings, c+_r = (prod_{q<r} P_q) CDAG_r and
+    (c_r')^T = (prod_{q<r'} P_q) CDAG_r' (P diagonal, C^T = CDAG), so X is a
+    sum of products of local (ket op) (x) (ancilla op).  cos(k.(r - r')) =
+    cos(k.r) cos(k.r') + sin(k.r) sin(k.r') splits every pair into two
+    separable terms.  Bond states: start (nothing placed yet: P (x) P),
+    (ket, spin, cos|sin) (ket operator placed: 1 (x) P until the ancilla one),
+    (anc, spin, cos|sin) (ancilla operator placed: P (x) 1), done (1 (x) 1);
+    a site that holds both operators goes from start to done directly."""
+    N = W * L
+    ph = [k[0] * x + k[1] * y for (x, y) in lattice.snake_order(W, L)]
+    mid = [("ket", sp, f) for sp in (0, 1) for f in (0, 1)] + [("anc", sp, f) for sp in (0, 1) for f in (0, 1)]
+    bonds = [["start"]] + [["start"] + mid + ["done"] for _ in range(N - 1)] + [["done"]]
+    cdag = (CDAG_UP, CDAG_DN)
+    Ws = []
+    for q in range(N):
+        Lb, Rb = bonds[q], bonds[q + 1]
+        col = {s: b for b, s in enumerate(Rb)}
+        trig = (np.cos(ph[q]), np.sin(ph[q]))
+        Wq = np.zeros((len(Lb), 16, 16, len(Rb)))
+
+        def put(a, lab, ket, anc, c):
+            if lab in col:
+                Wq[a, :, :, col[lab]] += c * np.kron(ket, anc)
+
+        for a, s in enumerate(Lb):
+            if s == "start":
+                put(a, "start", PAR, PAR, 1.0)
+                for sp in (0, 1):
+                    for f in (0, 1):
+                        put(a, ("ket", sp, f), cdag[sp], PAR, trig[f])
+                        put(a, ("anc", sp, f), PAR, cdag[sp], trig[f])
+                    put(a, "done", cdag[sp], cdag[sp], 1.0)
+            elif s == "done":
+                put(a, "done", ID4, ID4, 1.0)
+            else:
+                side, sp, f = s
+                if side == "ket":
+                    put(a, s, ID4, PAR, 1.0)
+                    put(a, "done", ID4, cdag[sp], trig[f])
+                else:
+                    put(a, s, PAR, ID4, 1.0)
+                    put(a, "done", cdag[sp], ID4, trig[f])
+        Ws.append(Wq)
+    return Ws

@@ -263,6 +263,25 @@ class State:
         OA = heff1(np.ones((1, 1, 1)), Ws[0], R, A)
         return float(np.vdot(A, OA)) / float(np.vdot(A, A))
 
+    def super_expectation(self, Ws):
+        """<<rho|X|rho>> / <<rho|rho>> for a super-operator X given as an MPO
+        with 16 x 16 local matrices W[a, s_out, s_in, b] (s = 4 sigma +
+        sigma', boundary bonds of dimension 1) that may act on the ancilla
+        index too: the site tensors are read as A[x, s, y] and the same right
+        environments and centre apply are taken with s in place of sigma."""
+        assert self.centre == 0
+        R = np.ones((1, 1, 1))
+        for k in range(self.N - 1, 0, -1):
+            A = self.A[k].reshape(self.A[k].shape[0], 16, self.A[k].shape[3])
+            T1 = np.tensordot(A, R, axes=([2], [2]))                      # x si y' b
+            T2 = np.tensordot(T1, Ws[k], axes=([1, 3], [2, 3]))            # x y' a so
+            R = np.tensordot(A.conj(), T2, axes=([1, 2], [3, 1])).transpose(0, 2, 1)
+        A = self.A[0].reshape(self.A[0].shape[0], 16, self.A[0].shape[3])
+        T1 = np.tensordot(np.ones((1, 1, 1)), A, axes=([2], [0]))         # x a si be
+        T2 = np.tensordot(T1, Ws[0], axes=([1, 2], [0, 2]))                # x be so b
+        XA = np.tensordot(T2, R, axes=([1, 3], [2, 1]))                     # x so y
+        return float(np.vdot(A, XA)) / float(np.vdot(A, A))
+
     def ln_trace(self):
         """ln Tr rho(beta): contract every site with delta(sigma, sigma')."""
         v = np.ones(1)
