@@ -160,6 +160,19 @@ int thermo_local_observables(tt_state* s, double* host_out2);
  * Synchronises.  TT_EINVAL if no pair lies at that distance. */
 int thermo_spin_correlation(tt_state* s, int d2, double* host_F, int* host_npairs);
 
+/* Single-particle Matsubara Green's function at half the imaginary time
+ * (main text, Fermi-surface paragraph): *host_G = G(k, beta_phys/2) =
+ * sum_s <exp(beta_phys H/2) c+_ks exp(-beta_phys H/2) c_ks> at beta_phys = 2 beta,
+ * c_ks = N^-1/2 sum_r exp(-i k.r) c_rs, i.e. Tr[rho c+_k rho c_k] / Tr[rho rho]
+ * for the state's rho(beta): the bilayer expectation of a super-operator MPO
+ * that acts on both the ket and the ancilla index (Choi map, SM Sec. II.A).
+ * r = (x, y) lattice coordinates, x = 0..L-1 along the length, y = 0..W-1
+ * across the width; k = (kx, ky) in radians per lattice spacing.  The first
+ * call builds the plans (FP64 in every precision mode); a later call with
+ * another k rewrites their weights only.  Synchronises.  TT_EINVAL for a
+ * non-finite k. */
+int thermo_green_function(tt_state* s, double kx, double ky, double* host_G);
+
 /* Entropy and specific heat per site from n >= 3 bilayer observables taken
  * along a sweep (host arrays of length n, beta = beta_phys strictly
  * increasing, e and f per site as in tt_observables): s_out[i] = beta (e - f)

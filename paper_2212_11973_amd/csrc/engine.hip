@@ -152,6 +152,7 @@ struct tt_state {
   struct ObsMpo {
     SiteTables tabs;
     std::vector<SitePlan> plans;
+    double kx = 0.0, ky = 0.0;   // the momentum whose weights the plans hold (Green's function)
     double *ea = nullptr, *eb = nullptr, *unit = nullptr, *pws = nullptr;
     double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr;
   };
@@ -801,8 +802,18 @@ long long check_qr(const QRPlan& p, const std::vector<long long>& tabs, long lon
   return bad;
 }
 
+std::vector<SitePlan> make_obs_plans(const tt_state& s, const Mpo& m, const Mpo& pat, SiteTables& tabs);
+long long check_obs_plans(const tt_state& s, const Mpo& m, std::vector<SitePlan>& plans, const SiteTables& tabs,
+                          std::string& rep);
+
 long long check_all_plans(tt_state& s, std::string& rep) {
   long long bad = 0;
+  {   // the Green's-function observable (super-operator W stage), all momenta
+    const Mpo pat = make_green_mpo(s.lat, 0.0, 0.0, true);
+    SiteTables gt;
+    std::vector<SitePlan> gp = make_obs_plans(s, pat, pat, gt);
+    bad += check_obs_plans(s, pat, gp, gt, rep);
+  }
   const int N = s.N;
   long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, msite = 0, mb = 0;
   for (auto& P : s.plans) {
@@ -855,29 +866,87 @@ const double kLocalOps[2][4] = {{0.0, 1.0, 1.0, 2.0},    // n = n_up + n_dn
                                 {0.0, 0.0, 0.0, 1.0}};   // n_up n_dn
 constexpr int kObsSpinPairs = 1000;                      // + d2: spin pairs at squared distance d2
 
-// plans and buffers of one observable MPO (bond 0: start; bond N: start and
-// done, of which only done is kept)
-tt_state::ObsMpo& build_obs_mpo(tt_state& s, int key, const Mpo& m) {
-  auto& O = s.obs[key];
+template <typename T> bool same_bytes(const std::vector<T>& x, const std::vector<T>& y) {
+  return x.size() == y.size() && (x.empty() || std::memcmp(x.data(), y.data(), sizeof(T) * x.size()) == 0);
+}
+constexpr int kObsGreen = 2000;                          // the Green's function G(k, beta/2)
+
+// MPO charges per bond of an observable MPO (bond 0: start; bond N: done)
+std::vector<std::vector<Q>> obs_charges(const tt_state& s, const Mpo& m) {
+  std::vector<std::vector<Q>> qH(s.N + 1);
+  for (int k = 0; k < s.N; ++k)
+    for (int a = 0; a < m.DH[k]; ++a) qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : m.charge(k, a));
+  qH[s.N] = {Q{0, 0}};
+  return qH;
+}
+// site tensors with the last one contracted with the done selector (the last
+// state of bond N)
+std::vector<std::vector<double>> obs_tensors(const Mpo& m) {
+  const int N = m.N, LL = m.ld * m.ld, DRN = m.DH[N];
+  std::vector<std::vector<double>> W = m.W;
+  std::vector<double> w((size_t)m.DH[N - 1] * LL, 0.0);
+  for (int a = 0; a < m.DH[N - 1]; ++a)
+    for (int q = 0; q < LL; ++q) w[(size_t)a * LL + q] = m.W[N - 1][((size_t)a * LL + q) * DRN + (DRN - 1)];
+  W[N - 1] = w;
+  return W;
+}
+// host plans of an observable MPO m; pat gives the nonzero pattern kept in
+// the W stage (so that MPOs differing only in weights share descriptors)
+std::vector<SitePlan> make_obs_plans(const tt_state& s, const Mpo& m, const Mpo& pat, SiteTables& tabs) {
+  const auto qH = obs_charges(s, m);
+  const auto W = obs_tensors(m), Wp = obs_tensors(pat);
+  std::vector<SitePlan> plans;
+  for (int k = 0; k < s.N; ++k) {
+    SitePlan P = build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, qH[k], qH[k + 1], W[k], Wp[k], tabs, m.ld == 16);
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.r1, &P.r3}) g->wave_ok = true;
+    plans.push_back(std::move(P));
+  }
+  return plans;
+}
+// descriptor bounds of the launches of obs_expectation: centre apply at site
+// 0 (unit, A_0 -> T1 -> T2 -> with R_1 into a site-sized vector) and the
+// right environments of sites N-1 .. 1 (R_{k+1}, A_k -> Y -> Z -> R_k)
+long long check_obs_plans(const tt_state& s, const Mpo& m, std::vector<SitePlan>& plans, const SiteTables& tabs,
+                          std::string& rep) {
+  const auto qH = obs_charges(s, m);
+  const auto& T = tabs.host;
+  long long bad = 0;
+  for (int k = 0; k < s.N; ++k) {
+    SitePlan& P = plans[k];
+    const long long ns = s.site[k].size, el = make_env_layout(s.bonds[k], qH[k]).size,
+                    er = make_env_layout(s.bonds[k + 1], qH[k + 1]).size;
+    if (k == 0) {
+      for (GemmPlan* g : {&P.s1, &P.s3}) tile_plan(*g, &T);
+      long long s1[kSlots] = {el, ns, P.t1_size, 0}, s3[kSlots] = {P.t2_size, er, ns, 0};
+      bad += check_gemm(P.s1, T, s1, "obs s1", rep);
+      bad += check_w(P.w2, P.t1_size, P.t2_size, "obs w2", rep);
+      bad += check_gemm(P.s3, T, s3, "obs s3", rep);
+    } else {
+      for (GemmPlan* g : {&P.r1, &P.r3}) tile_plan(*g, &T);
+      long long r1[kSlots] = {er, ns, P.y_size, 0}, r3[kSlots] = {ns, P.z_size, el, 0};
+      bad += check_gemm(P.r1, T, r1, "obs r1", rep);
+      bad += check_w(P.wr, P.y_size, P.z_size, "obs wr", rep);
+      bad += check_gemm(P.r3, T, r3, "obs r3", rep);
+    }
+  }
+  return bad;
+}
+
+// plans and buffers of one observable MPO (bond 0: start; bond N: its last
+// state, done)
+tt_state::ObsMpo& build_obs_mpo(tt_state& s, int key, const Mpo& m, const Mpo* pat = nullptr) {
   const int N = s.N;
   hipStream_t st = ST();
-  std::vector<std::vector<Q>> qH(N + 1);
-  for (int k = 0; k < N; ++k)
-    for (int a = 0; a < m.DH[k]; ++a) qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : m.charge(k, a));
-  qH[N] = {Q{0, 0}};
-  std::vector<std::vector<double>> W = m.W;
-  const int DRN = m.DH[N];
-  std::vector<double> w((size_t)m.DH[N - 1] * 16, 0.0);   // last site: the done selector
-  for (int a = 0; a < m.DH[N - 1]; ++a)
-    for (int q = 0; q < 16; ++q) w[(size_t)a * 16 + q] = m.W[N - 1][((size_t)a * 16 + q) * DRN + (DRN - 1)];
-  W[N - 1] = w;
+  SiteTables tabs;
+  std::vector<SitePlan> plans = make_obs_plans(s, m, pat ? *pat : m, tabs);
+  std::string rep;
+  TT_REQUIRE(check_obs_plans(s, m, plans, tabs, rep) == 0, TT_EINVAL, "observable plans out of bounds: " + rep);
+  auto& O = s.obs[key];
+  O.tabs = std::move(tabs);
+  O.plans = std::move(plans);
+  const auto qH = obs_charges(s, m);
   long long t1 = 1, t2 = 1, y = 1, z = 1, env = 1, pw = 1;
   for (int k = 0; k <= N; ++k) env = std::max(env, make_env_layout(s.bonds[k], qH[k]).size);
-  for (int k = 0; k < N; ++k) {
-    SitePlan P = build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, qH[k], qH[k + 1], W[k], W[k], O.tabs);
-    for (GemmPlan* g : {&P.s1, &P.s3, &P.r1, &P.r3}) g->wave_ok = true;
-    O.plans.push_back(std::move(P));
-  }
   O.tabs.dev = upload(O.tabs.host, st);
   const std::vector<long long>* T = &O.tabs.host;
   for (int k = 0; k < N; ++k) {
@@ -929,6 +998,39 @@ double obs_expectation(tt_state& s, tt_state::ObsMpo& O) {
   return h[0] / h[1];
 }
 
+// G(k, beta_phys/2) of the bilayer state: <<rho|X(k)|rho>> / (N <<rho|rho>>).
+// The plans keep the nonzero pattern of every momentum, so a new k only
+// rewrites the W-stage weights of the cached plans.
+double green_expectation(tt_state& s, double kx, double ky) {
+  auto it = s.obs.find(kObsGreen);
+  const Mpo m = make_green_mpo(s.lat, kx, ky, false);
+  if (it == s.obs.end()) {
+    const Mpo pat = make_green_mpo(s.lat, kx, ky, true);
+    tt_state::ObsMpo& O = build_obs_mpo(s, kObsGreen, m, &pat);
+    O.kx = kx; O.ky = ky;
+    return obs_expectation(s, O) / s.N;
+  }
+  tt_state::ObsMpo& O = it->second;
+  if (O.kx != kx || O.ky != ky) {
+    const Mpo pat = make_green_mpo(s.lat, kx, ky, true);
+    SiteTables tabs;
+    std::vector<SitePlan> fresh = make_obs_plans(s, m, pat, tabs);
+    hipStream_t st = ST();
+    for (int k = 0; k < s.N; ++k) {
+      WPlan& dst = k == 0 ? O.plans[k].w2 : O.plans[k].wr;
+      const WPlan& src = k == 0 ? fresh[k].w2 : fresh[k].wr;
+      TT_REQUIRE(src.terms.size() == dst.terms.size() && same_bytes(src.tasks, dst.tasks), TT_EINVAL,
+                 "green function: plans of two momenta differ");
+      dst.terms = src.terms;
+      if (!dst.terms.empty())
+        HIPX(hipMemcpyAsync(dst.d_terms, dst.terms.data(), dst.terms.size() * sizeof(WTerm), hipMemcpyHostToDevice, st));
+    }
+    HIPX(hipStreamSynchronize(st));
+    O.kx = kx; O.ky = ky;
+  }
+  return obs_expectation(s, O) / s.N;
+}
+
 double local_expectation(tt_state& s, int kind) {
   auto it = s.obs.find(kind);
   tt_state::ObsMpo& O = it != s.obs.end() ? it->second : build_obs_mpo(s, kind, make_local_sum_mpo(s.N, kLocalOps[kind]));
@@ -956,9 +1058,6 @@ void fill_stats(tt_state& s, tt_sweep_stats* st, double secs) {
 }
 void reset_counters(tt_state& s) { s.flops = s.flops_heff = 0.0; s.n_applies = s.n_exps = 0; }
 
-template <typename T> bool same_bytes(const std::vector<T>& x, const std::vector<T>& y) {
-  return x.size() == y.size() && (x.empty() || std::memcmp(x.data(), y.data(), sizeof(T) * x.size()) == 0);
-}
 bool same_gemm(const GemmPlan& x, const GemmPlan& y) {
   return same_bytes(x.probs, y.probs) && same_bytes(x.tiles, y.tiles) && same_bytes(x.jobs, y.jobs) &&
          same_bytes(x.splits, y.splits) && x.pws_size == y.pws_size && x.wave_blocks == y.wave_blocks;
@@ -1248,6 +1347,16 @@ int thermo_spin_correlation(tt_state* s, int d2, double* host_F, int* host_npair
   TT_REQUIRE(std::isfinite(F), TT_ENUMERIC, "non-finite spin correlation");
   *host_F = F;
   if (host_npairs) *host_npairs = (int)pairs.size();
+  ABI_END
+}
+
+int thermo_green_function(tt_state* s, double kx, double ky, double* host_G) {
+  ABI_BEGIN
+  TT_REQUIRE(s && host_G, TT_EINVAL, "null argument");
+  TT_REQUIRE(std::isfinite(kx) && std::isfinite(ky), TT_EINVAL, "thermo_green_function: non-finite momentum");
+  const double G = green_expectation(*s, kx, ky);
+  TT_REQUIRE(std::isfinite(G), TT_ENUMERIC, "non-finite Green's function");
+  *host_G = G;
   ABI_END
 }
 

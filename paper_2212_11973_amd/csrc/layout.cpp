@@ -250,15 +250,22 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
 
 SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<Q>& qHl, const std::vector<Q>& qHr,
-                         const std::vector<double>& W, const std::vector<double>& Wp, SiteTables& tabs) {
+                         const std::vector<double>& W, const std::vector<double>& Wp, SiteTables& tabs,
+                         bool super_op) {
   (void)k;
   SitePlan P;
   const int DHl = (int)qHl.size(), DHr = (int)qHr.size();
   SiteLayout S = make_site_layout(bl, br, G);
   EnvLayout EL = make_env_layout(bl, qHl);
   EnvLayout ER = make_env_layout(br, qHr);
-  auto Wat = [&](int a, int so, int si, int b) { return W[(((size_t)a * 4 + so) * 4 + si) * DHr + b]; };
-  auto Wpat = [&](int a, int so, int si, int b) { return Wp[(((size_t)a * 4 + so) * 4 + si) * DHr + b]; };
+  // MPO entry for the super indices s_out, s_in (s = 4 sigma + sigma'): a
+  // ket-only tensor W[a, so, si, b] leaves the ancilla sigma' unchanged; a
+  // super-operator tensor holds all 16 x 16 entries
+  auto Wsup = [&](const std::vector<double>& T, int a, int sout, int sin, int b) -> double {
+    if (super_op) return T[(((size_t)a * 16 + sout) * 16 + sin) * DHr + b];
+    if ((sout & 3) != (sin & 3)) return 0.0;
+    return T[(((size_t)a * 4 + (sout >> 2)) * 4 + (sin >> 2)) * DHr + b];
+  };
   const int nr = (int)br.secs.size();
 
   // ---------------- stage 1: T1_l[(a,x)][cols of A_l] = L[x,a,l-block] . A_l
@@ -316,8 +323,7 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
         if (S.rsec[p][g] != r) continue;
         int ns = (int)G.s[g].size();
         for (int si = 0; si < ns; ++si) {
-          int sp = G.s[g][si];
-          int so = sp / 4, sa = sp % 4;   // output ket sigma, ancilla sigma'
+          int sp = G.s[g][si];   // output super index
           for (int b = 0; b < DHr; ++b) {
             int c = ER.csec[r][b];
             if (c < 0) continue;
@@ -331,10 +337,9 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
             for (int a = 0; a < DHl; ++a) {
               int l = EL.csec[p][a];
               if (l < 0) continue;
-              for (int sg = 0; sg < 4; ++sg) {
-                double w = Wat(a, so, sg, b);
-                if (w == 0.0 && Wpat(a, so, sg, b) == 0.0) continue;
-                int s = sg * 4 + sa;
+              for (int s = 0; s < 16; ++s) {
+                double w = Wsup(W, a, sp, s, b);
+                if (w == 0.0 && Wsup(Wp, a, sp, s, b) == 0.0) continue;
                 int gg = G.group_of[s];
                 TT_REQUIRE(S.rsec[l][gg] == c, TT_EINVAL, "plan: MPO entry breaks charge conservation");
                 WTerm tm;
@@ -448,7 +453,6 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
       int ns = (int)G.s[g].size();
       for (int si = 0; si < ns; ++si) {
         int sp = G.s[g][si];
-        int so = sp / 4, sa = sp % 4;
         for (int a = 0; a < DHl; ++a) {
           int l = EL.csec[p][a];
           if (l < 0) continue;
@@ -460,10 +464,9 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
           t.nj = S.dl[l];
           t.t0 = (int)P.wr.terms.size();
           for (int b = 0; b < DHr; ++b)
-            for (int sg = 0; sg < 4; ++sg) {
-              double w = Wat(a, so, sg, b);
-              if (w == 0.0 && Wpat(a, so, sg, b) == 0.0) continue;
-              int s = sg * 4 + sa;
+            for (int s = 0; s < 16; ++s) {
+              double w = Wsup(W, a, sp, s, b);
+              if (w == 0.0 && Wsup(Wp, a, sp, s, b) == 0.0) continue;
               int gg = G.group_of[s];
               int c = S.rsec[l][gg];
               if (c < 0) continue;   // the ket block (l, s) -> c is absent from the truncated bond

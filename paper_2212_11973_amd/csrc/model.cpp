@@ -484,4 +484,85 @@ Mpo make_local_sum_mpo(int N, const double op[4]) {
   return m;
 }
 
+// Matsubara Green's function at half the imaginary time (main text,
+// Fermi-surface paragraph), as a super-operator MPO on the super index
+// s = 4 sigma + sigma' (16 x 16 local matrices, ld = 16):
+//   X(k) = sum_s sum_{r,r'} cos(k.(r - r')) c+_{rs} (x) (c_{r's})^T ,
+// <<rho|X|rho>> = sum_{rr'} cos(k.(r - r')) Tr[rho c+_r rho c_r'] (the Choi map
+// sends A rho B to (A (x) B^T)|rho>>, SM Sec. II.A).  With the Jordan-Wigner
+// strings c+_r = P..P c+ at r and (c_r')^T = P..P c+ at r' (c^T = c+ for the
+// real local matrices, P diagonal), so every pair is a product of local
+// (ket op) (x) (ancilla op); cos(k.(r - r')) = cos cos + sin sin splits it into
+// separable terms.  Bond states: start (P (x) P), the placed-ket channels
+// (1 (x) P) and placed-ancilla channels (P (x) 1) per spin and per cos|sin
+// (site = 0|1, type 0..3: ket up, ket dn, ancilla up, ancilla dn, whose charge
+// is that of the channel table), done (1 (x) 1).  r = (x, y): x along the
+// length, y across the width, in the snake order.  pattern = true puts 1 in
+// place of every cos and sin (the nonzero pattern for any k).
+Mpo make_green_mpo(const Lattice& lat, double kx, double ky, bool pattern) {
+  const int N = lat.N, W = lat.W;
+  const LocalOps o = local_ops(0.0, 0.0);
+  Mpo m;
+  m.N = N;
+  m.ld = 16;
+  m.states.resize(N + 1);
+  m.states[0] = {{0, -1, -1}};
+  for (int k = 1; k <= N; ++k) {
+    m.states[k] = {{0, -1, -1}};
+    for (int ty = 0; ty < 4; ++ty)
+      for (int f = 0; f < 2; ++f) m.states[k].push_back({2, f, ty});
+    m.states[k].push_back({1, -1, -1});
+  }
+  for (int k = 0; k <= N; ++k) m.DH.push_back((int)m.states[k].size());
+  const M4* cdag[2] = {&o.cdu, &o.cdd};
+  m.W.resize(N);
+  for (int q = 0; q < N; ++q) {
+    const int x = q / W, rr = q % W, y = (x % 2 == 0) ? (W - 1 - rr) : rr;
+    const double th = kx * x + ky * y;
+    const double trig[2] = {pattern ? 1.0 : std::cos(th), pattern ? 1.0 : std::sin(th)};
+    const auto& Ls = m.states[q];
+    const auto& Rs = m.states[q + 1];
+    const int DL = (int)Ls.size(), DR = (int)Rs.size();
+    std::vector<double> Wk((size_t)DL * 256 * DR, 0.0);
+    auto find = [&](int kind, int f, int type) {
+      for (int b = 0; b < DR; ++b)
+        if (Rs[b].kind == kind && (kind < 2 || (Rs[b].site == f && Rs[b].type == type))) return b;
+      return -1;
+    };
+    // W[a, 4 so + ao, 4 si + ai, b] += c ket[so][si] anc[ao][ai]
+    auto put = [&](int a, int b, const M4& ket, const M4& anc, double c) {
+      if (b < 0) return;
+      for (int so = 0; so < 4; ++so)
+        for (int si = 0; si < 4; ++si)
+          for (int ao = 0; ao < 4; ++ao)
+            for (int ai = 0; ai < 4; ++ai)
+              Wk[(((size_t)a * 16 + 4 * so + ao) * 16 + 4 * si + ai) * DR + b] += c * ket.v[so][si] * anc.v[ao][ai];
+    };
+    const int bstart = find(0, -1, -1), bdone = find(1, -1, -1);
+    for (int a = 0; a < DL; ++a) {
+      const MpoState& s = Ls[a];
+      if (s.kind == 0) {
+        put(a, bstart, o.par, o.par, 1.0);
+        for (int sp = 0; sp < 2; ++sp) {
+          for (int f = 0; f < 2; ++f) {
+            put(a, find(2, f, sp), *cdag[sp], o.par, trig[f]);
+            put(a, find(2, f, 2 + sp), o.par, *cdag[sp], trig[f]);
+          }
+          put(a, bdone, *cdag[sp], *cdag[sp], 1.0);
+        }
+      } else if (s.kind == 1) {
+        put(a, bdone, o.id, o.id, 1.0);
+      } else if (s.type < 2) {   // ket operator placed
+        put(a, find(2, s.site, s.type), o.id, o.par, 1.0);
+        put(a, bdone, o.id, *cdag[s.type], trig[s.site]);
+      } else {                   // ancilla operator placed
+        put(a, find(2, s.site, s.type), o.par, o.id, 1.0);
+        put(a, bdone, *cdag[s.type - 2], o.id, trig[s.site]);
+      }
+    }
+    m.W[q] = Wk;
+  }
+  return m;
+}
+
 }  // namespace tt

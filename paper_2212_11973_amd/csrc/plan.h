@@ -229,9 +229,11 @@ struct SiteTables {
 
 SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<Q>& qHl, const std::vector<Q>& qHr,
-                         const std::vector<double>& W,    // DHl*16*DHr
+                         const std::vector<double>& W,    // DHl*16*DHr (super_op: DHl*256*DHr)
                          const std::vector<double>& Wp,   // pattern: entries kept when nonzero in W or Wp
-                         SiteTables& tabs);
+                         SiteTables& tabs,
+                         bool super_op = false);          // W acts on the super index s = 4 sigma + sigma'
+
 
 // tile the problems of a plan (shape per problem)
 int gemm_cfg_for(int M, int N);

@@ -35,7 +35,8 @@ struct MpoState { int kind, site, type; };
 struct Mpo {
   int N;
   std::vector<std::vector<MpoState>> states;   // per bond 0..N (bond N: start, done)
-  std::vector<std::vector<double>> W;          // W[k][((a*4+so)*4+si)*DHr + b]
+  int ld = 4;                                  // local operator size: 4 (ket only) or 16 (super index)
+  std::vector<std::vector<double>> W;          // W[k][((a*ld+so)*ld+si)*DHr + b]
   std::vector<int> DH;                         // per bond
   Q charge(int k, int a) const;
 };
@@ -43,6 +44,7 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double m
 Mpo make_local_sum_mpo(int N, const double op[4]);   // sum_i op_i, op diagonal
 std::vector<std::pair<int, int>> pairs_at_distance(const Lattice& lat, int d2);
 Mpo make_spin_pair_mpo(int N, const std::vector<std::pair<int, int>>& pairs);   // sum over pairs of S_i . S_j
+Mpo make_green_mpo(const Lattice& lat, double kx, double ky, bool pattern);      // super-operator of G(k, beta/2)
 
 // ------------------------------------------------------------------ sectors
 struct Sector { Q q; int dim; long long off; };

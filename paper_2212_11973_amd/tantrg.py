@@ -23,7 +23,7 @@ SYMBOLS = [
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
-    "thermo_spin_correlation", "tt_sweep_graphs",
+    "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function",
 ]
 
 
@@ -59,12 +59,26 @@ class TTError(RuntimeError):
 _lib = None
 
 
+def _init_torch_runtime():
+    """Initialise torch's HIP runtime before the library's own.  The library
+    links the system ROCm runtime and torch ships another; both live in one
+    process and share the GPU address space (device pointers pass freely),
+    but torch finds no device if the system runtime initialised first."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """The loaded library (raises if it was not built)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libtantrg.so is not built: run __graft_entry__.build()")
+        _init_torch_runtime()
         L = C.CDLL(LIB_PATH)
         vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
         L.tt_last_error.restype = C.c_char_p
@@ -77,6 +91,7 @@ def lib():
         L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         L.thermo_spin_correlation.argtypes = [vp, C.c_int, dp, ip]
         L.tt_sweep_graphs.argtypes = [C.c_int]
+        L.thermo_green_function.argtypes = [vp, C.c_double, C.c_double, dp]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -168,6 +183,13 @@ def thermo_spin_correlation(state, d2):
     F, n = C.c_double(), C.c_int()
     _check(lib().thermo_spin_correlation(state, d2, C.byref(F), C.byref(n)))
     return F.value, n.value
+
+
+def thermo_green_function(state, kx, ky):
+    """G(k, beta_phys/2) at k = (kx, ky) (x along the length, y across the width)."""
+    G = C.c_double()
+    _check(lib().thermo_green_function(state, float(kx), float(ky), C.byref(G)))
+    return G.value
 
 
 def tt_thermo_derived(beta_phys, e, f):
@@ -305,6 +327,9 @@ class State:
 
     def spin_correlation(self, d2):
         return thermo_spin_correlation(self.h, d2)
+
+    def green_function(self, kx, ky):
+        return thermo_green_function(self.h, kx, ky)
 
     def info(self):
         return tt_state_info(self.h)
