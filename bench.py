@@ -11,6 +11,7 @@ Prints one JSON line.  --gpus N with N > 1 exits: the build runs on one GPU.
 """
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -162,8 +163,15 @@ def main():
             for d2 in (1, 2, 4):   # spin correlation F(d), d = 1, sqrt 2, 2, at the last beta
                 F_, npairs = st.spin_correlation(d2)
                 spin["d2=%d" % d2] = dict(F=F_, pairs=npairs)
+            green = {}   # G(k, beta_phys/2) at a few momenta (x along the length, y around the cylinder)
+            tg = time.perf_counter()
+            for name, kx, ky in (("0,0", 0.0, 0.0), ("pi/2,pi/2", math.pi / 2, math.pi / 2),
+                                 ("pi,0", math.pi, 0.0), ("pi,pi/2", math.pi, math.pi / 2)):
+                G_ = st.green_function(kx, ky)
+                green[name] = dict(G=G_, beta_G=bp[-1] * G_)
+            green["seconds_per_k"] = (time.perf_counter() - tg) / 4
             thermo = dict(beta_phys=bp, e=[o_["e"] for o_ in series], f=[o_["f"] for o_ in series],
-                          c_e=ce, s_e=se, spin_correlation=spin)
+                          c_e=ce, s_e=se, spin_correlation=spin, green_k=green)
         st.free()
         return (t1 - t0) / steps, stats, (prof, prof_s), obs, info, thermo
 

@@ -1012,18 +1012,14 @@ double green_expectation(tt_state& s, double kx, double ky) {
   }
   tt_state::ObsMpo& O = it->second;
   if (O.kx != kx || O.ky != ky) {
-    const Mpo pat = make_green_mpo(s.lat, kx, ky, true);
-    SiteTables tabs;
-    std::vector<SitePlan> fresh = make_obs_plans(s, m, pat, tabs);
+    const auto W = obs_tensors(m);
     hipStream_t st = ST();
     for (int k = 0; k < s.N; ++k) {
-      WPlan& dst = k == 0 ? O.plans[k].w2 : O.plans[k].wr;
-      const WPlan& src = k == 0 ? fresh[k].w2 : fresh[k].wr;
-      TT_REQUIRE(src.terms.size() == dst.terms.size() && same_bytes(src.tasks, dst.tasks), TT_EINVAL,
-                 "green function: plans of two momenta differ");
-      dst.terms = src.terms;
-      if (!dst.terms.empty())
-        HIPX(hipMemcpyAsync(dst.d_terms, dst.terms.data(), dst.terms.size() * sizeof(WTerm), hipMemcpyHostToDevice, st));
+      WPlan& P = k == 0 ? O.plans[k].w2 : O.plans[k].wr;
+      TT_REQUIRE(P.widx.size() == P.terms.size(), TT_EINVAL, "green function: plan without weight indices");
+      for (size_t i = 0; i < P.terms.size(); ++i) P.terms[i].w = W[k].at((size_t)P.widx[i]);
+      if (!P.terms.empty())
+        HIPX(hipMemcpyAsync(P.d_terms, P.terms.data(), P.terms.size() * sizeof(WTerm), hipMemcpyHostToDevice, st));
     }
     HIPX(hipStreamSynchronize(st));
     O.kx = kx; O.ky = ky;

@@ -261,10 +261,15 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
   // MPO entry for the super indices s_out, s_in (s = 4 sigma + sigma'): a
   // ket-only tensor W[a, so, si, b] leaves the ancilla sigma' unchanged; a
   // super-operator tensor holds all 16 x 16 entries
+  // widx: the flat index of the entry in W, or -1 where it is zero by structure
+  auto widx = [&](int a, int sout, int sin, int b) -> long long {
+    if (super_op) return (((long long)a * 16 + sout) * 16 + sin) * DHr + b;
+    if ((sout & 3) != (sin & 3)) return -1;
+    return (((long long)a * 4 + (sout >> 2)) * 4 + (sin >> 2)) * DHr + b;
+  };
   auto Wsup = [&](const std::vector<double>& T, int a, int sout, int sin, int b) -> double {
-    if (super_op) return T[(((size_t)a * 16 + sout) * 16 + sin) * DHr + b];
-    if ((sout & 3) != (sin & 3)) return 0.0;
-    return T[(((size_t)a * 4 + (sout >> 2)) * 4 + (sin >> 2)) * DHr + b];
+    const long long i = widx(a, sout, sin, b);
+    return i < 0 ? 0.0 : T[(size_t)i];
   };
   const int nr = (int)br.secs.size();
 
@@ -349,6 +354,7 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                 tm.ssj = 1;
                 tm.w = w;
                 P.w2.terms.push_back(tm);
+                P.w2.widx.push_back(widx(a, sp, s, b));
               }
             }
             t.nt = (int)P.w2.terms.size() - t.t0;
@@ -478,6 +484,7 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
               tm.ssj = (long long)G.s[gg].size();
               tm.w = w;
               P.wr.terms.push_back(tm);
+              P.wr.widx.push_back(widx(a, sp, s, b));
             }
           t.nt = (int)P.wr.terms.size() - t.t0;
           P.wr.flops += 2.0 * t.nt * (double)t.ni * t.nj;

@@ -132,6 +132,7 @@ struct WPlan {
   bool wide = false;   // some block spans 2^29 elements or more (64-bit offsets)
   std::vector<WTask> tasks;
   std::vector<WTerm> terms;
+  std::vector<long long> widx;   // per term: the flat index of its weight in the site's MPO tensor
   WTask* d_tasks = nullptr;
   WTerm* d_terms = nullptr;
   int ntasks = 0;
