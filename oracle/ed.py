@@ -213,7 +213,19 @@ def thermal_physical(E, beta):
     return lnZ, float(np.sum(w * E))
 
 
-def same_ode_bilayer(E, beta0, beta):
+def start_poly(E, beta0, order=1):
+    """The start rho0 on the eigenvalues: sum_{n <= order} (-beta0 E)^n / n!
+    (order 1: the linear start 1 - beta0 E; higher orders: SETTN, SM I.E)."""
+    a = np.zeros_like(np.asarray(E, dtype=float))
+    term = np.ones_like(a)
+    for n in range(order + 1):
+        if n:
+            term = term * (-beta0 * np.asarray(E, dtype=float)) / n
+        a = a + term
+    return a
+
+
+def same_ode_bilayer(E, beta0, beta, order=1):
     """Exact values reached by the flow d rho/d beta = -H rho from the linear
     start rho(beta0) = 1 - beta0 H (main text, noninteracting-benchmark
     paragraph): rho(beta) = exp(-(beta-beta0) H) (1 - beta0 H).
@@ -221,9 +233,10 @@ def same_ode_bilayer(E, beta0, beta):
     Bilayer (SM Sec. II.A): Z_bl = ||rho(beta)||_F^2 is the partition function
     at the physical inverse temperature 2*beta, and
     E_bl = <<rho|H (x) 1|rho>> / <<rho|rho>>.
-    Returns (ln Z_bl, E_bl).
+    Returns (ln Z_bl, E_bl).  order > 1: the start is the Taylor polynomial
+    of ``start_poly``.
     """
-    a = 1.0 - beta0 * E
+    a = start_poly(E, beta0, order)
     x = 2.0 * np.log(np.abs(a)) - 2.0 * (beta - beta0) * E
     lnZ = _logsumexp(x)
     w = np.exp(x - lnZ)
@@ -288,9 +301,10 @@ def free_fermion_spin_pairs(h, beta, pairs):
     return float(np.mean([-1.5 * G[i, j] ** 2 for (i, j) in pairs]))
 
 
-def same_ode_single(E, beta0, beta):
-    """ln Tr rho(beta) for rho(beta) = exp(-(beta-beta0) H) (1 - beta0 H)."""
-    a = 1.0 - beta0 * E
+def same_ode_single(E, beta0, beta, order=1):
+    """ln Tr rho(beta) for rho(beta) = exp(-(beta-beta0) H) rho0, rho0 the
+    start of ``start_poly``."""
+    a = start_poly(E, beta0, order)
     x = -(beta - beta0) * E
     m = np.max(x)
     return m + np.log(np.sum(a * np.exp(x - m)))

@@ -288,3 +288,124 @@ def green_mpo(W, L, k):
                     put(a, "done", cdag[sp], ID4, trig[f])
         Ws.append(Wq)
     return Ws
+
+
+SETTN_TOL = 3e-12     # a column is dependent if its residual is <= SETTN_TOL x its norm
+
+
+def _mgs_keep(M, tol_rel):
+    """Ordered modified Gram-Schmidt (two passes) over the columns of M:
+    returns (Q, R) with M = Q R and Q's columns orthonormal.  A column whose
+    residual norm is <= tol_rel x its own norm is a linear dependency: it is
+    dropped and its coefficients go to R.  Columns are taken in their order,
+    so the result is deterministic.  A residual within a factor 10 of the
+    threshold raises (the decision would depend on rounding)."""
+    m, n = M.shape
+    Q = []
+    R = np.zeros((n, n))
+    for j in range(n):
+        v = M[:, j].copy()
+        n0 = np.linalg.norm(v)
+        coef = np.zeros(len(Q))
+        for _ in range(2):
+            for i, q in enumerate(Q):
+                c = q @ v
+                coef[i] += c
+                v -= c * q
+        nv = np.linalg.norm(v)
+        R[:len(Q), j] = coef
+        if n0 == 0.0:
+            continue
+        if 0.1 * tol_rel * n0 < nv <= 10.0 * tol_rel * n0:
+            raise ValueError("SETTN reduction: a residual is too close to the threshold")
+        if nv > tol_rel * n0:
+            Q.append(v / nv)
+            R[len(Q) - 1, j] = nv
+    r = len(Q)
+    Qm = np.array(Q).T if r else np.zeros((m, 0))
+    return Qm, R[:r, :]
+
+
+def settn_rho0(model, beta0, order, tol_rel=SETTN_TOL):
+    """SETTN start (SM I.E): super-MPS tensors of
+        rho0 = sum_{n <= order} (-beta0 H)^n / n!
+    and the charge of every bond state (bonds 0..N-1; bond N has one state of
+    charge 0 after the boundary vector).
+
+    H^order as the product MPO of ``order`` copies of H's MPO (bond states are
+    tuples of H's states, charge the sum); at the right end every factor is in
+    'start' (identity) or 'done' (H), so a tuple with k factors done stands for
+    H^k, and the boundary vector puts (-beta0)^k / k! / C(order, k) on it.
+    order = 1 is 1 - beta0 H.  The product bond is then reduced exactly (to
+    linearly independent states): left to right, the columns of each site's
+    left unfolding of one charge are orthonormalised by ordered modified
+    Gram-Schmidt (dependent columns, residual <= tol_rel x their own norm,
+    are dropped) and the coefficients move into the next site; then right to
+    left over the rows of the right unfoldings."""
+    from math import comb, factorial
+    N = model.N
+    W = model.W
+    charges = [model.bond_charges(k) for k in range(N + 1)]
+    A, Q = [], []
+    for k in range(N):
+        P, qL, qR = W[k], list(charges[k]), list(charges[k + 1])
+        for _ in range(order - 1):
+            a, _, _, b = P.shape
+            c, _, _, d = W[k].shape
+            P = np.einsum("AotB,atib->AaoiBb", P, W[k]).reshape(a * c, 4, 4, b * d)
+            qL = [(x[0] + y[0], x[1] + y[1]) for x in qL for y in charges[k]]
+            qR = [(x[0] + y[0], x[1] + y[1]) for x in qR for y in charges[k + 1]]
+        A.append(P)
+        Q.append(qL)
+        if k == N - 1:
+            Q.append(qR)
+    # boundary vector over the last bond's tuples of (start = 0, done = 1)
+    nR = len(charges[N])
+    r = np.zeros(nR ** order)
+    for idx in range(nR ** order):
+        digits = [(idx // nR ** (order - 1 - i)) % nR for i in range(order)]
+        kdone = sum(digits)
+        r[idx] = (-beta0) ** kdone / factorial(kdone) / comb(order, kdone)
+    A[-1] = np.tensordot(A[-1], r, axes=([3], [0]))[..., None]
+    Q[N] = [(0, 0)]
+    if order == 1:
+        return A, Q[:N]
+    # exact reduction, left to right
+    for k in range(N - 1):
+        a, _, _, b = A[k].shape
+        M = A[k].reshape(a * 16, b)
+        cols, coefs, newq = [], [], []
+        for q in sorted(set(Q[k + 1])):
+            J = [j for j in range(b) if Q[k + 1][j] == q]
+            Qm, R = _mgs_keep(M[:, J], tol_rel)
+            if Qm.shape[1] == 0:
+                continue
+            cols.append(Qm)
+            T = np.zeros((Qm.shape[1], b))
+            T[:, J] = R
+            coefs.append(T)
+            newq += [q] * Qm.shape[1]
+        A[k] = np.concatenate(cols, axis=1).reshape(a, 4, 4, -1)
+        C = np.concatenate(coefs, axis=0)
+        A[k + 1] = np.tensordot(C, A[k + 1], axes=([1], [0]))
+        Q[k + 1] = newq
+    # right to left over the rows
+    for k in range(N - 1, 0, -1):
+        a, _, _, b = A[k].shape
+        M = A[k].reshape(a, 16 * b).T
+        rows, coefs, newq = [], [], []
+        for q in sorted(set(Q[k])):
+            J = [j for j in range(a) if Q[k][j] == q]
+            Qm, R = _mgs_keep(M[:, J], tol_rel)
+            if Qm.shape[1] == 0:
+                continue
+            rows.append(Qm.T)
+            T = np.zeros((Qm.shape[1], a))
+            T[:, J] = R
+            coefs.append(T)
+            newq += [q] * Qm.shape[1]
+        A[k] = np.concatenate(rows, axis=0).reshape(-1, 4, 4, b)
+        C = np.concatenate(coefs, axis=0)           # A_old = C^T A_new
+        A[k - 1] = np.tensordot(A[k - 1], C.T, axes=([3], [0]))
+        Q[k] = newq
+    return A, Q[:N]

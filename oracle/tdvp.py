@@ -300,14 +300,21 @@ class State:
 
 
 # ---------------------------------------------------------------- start state
-def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0, sector_cap=0):
-    """rho0 = 1 - beta0 H (main text, noninteracting-benchmark paragraph)
-    padded to bond D as described in ``oracle.charges``, right-canonicalised,
-    centre normalised into Lambda; beta = beta0."""
+def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0, sector_cap=0, taylor_order=1):
+    """rho0 = 1 - beta0 H (main text, noninteracting-benchmark paragraph), or
+    for taylor_order > 1 the SETTN start sum_{n <= order} (-beta0 H)^n / n!
+    (SM I.E, ``oracle.mpo.settn_rho0``), padded to bond D as described in
+    ``oracle.charges``, right-canonicalised, centre normalised into Lambda;
+    beta = beta0."""
     from . import charges
+    from . import mpo as _mpo
     N = mpo_model.N
-    A0 = mpo_model.rho0_tensors(beta0)
-    rho0_q = [mpo_model.bond_charges(k) for k in range(N)]
+    if taylor_order == 1:
+        A0 = mpo_model.rho0_tensors(beta0)
+        rho0_q = [mpo_model.bond_charges(k) for k in range(N)]
+    else:
+        A0, rho0_q = _mpo.settn_rho0(mpo_model, beta0, taylor_order)
+        rho0_q = list(rho0_q)
     rho0_q.append([(0, 0)])            # bond N of rho0 after the boundary vector
     layouts = charges.bond_layouts(rho0_q, N, D, symmetric, sector_cap)
     A = charges.padded_rho0(A0, layouts, symmetric, pad_eps, seed)
