@@ -72,7 +72,12 @@ typedef struct {
   int D;               /* target bond dimension (bonds never exceed the maximal one) */
   int symmetry;        /* 0 dense, 1 U(1)charge x U(1)spin block-sparse */
   double beta0;        /* rho0 = 1 - beta0 H (main text: high-temperature start) */
-  int taylor_order;    /* must be 1 (higher orders not supported) */
+  int taylor_order;    /* 1: rho0 = 1 - beta0 H; 2..4: the SETTN start
+                          sum_{n <= order} (-beta0 H)^n / n! (SM I.E), the
+                          product MPO of H reduced exactly to independent bond
+                          states (ordered Gram-Schmidt); TT_EINVAL if the
+                          product is too large or a reduction decision would
+                          rest on rounding */
   int krylov_dim;      /* Lanczos dimension K (SM Sec. II.H), 1..32 */
   double krylov_tol;   /* lucky breakdown when beta_j <= tol*||H q_j|| (default 1e-13) */
   int precision;       /* TT_FP64 / TT_FP32 / TT_BF16X3 / TT_BF16X6 */

@@ -290,7 +290,7 @@ def green_mpo(W, L, k):
     return Ws
 
 
-SETTN_TOL = 3e-12     # a column is dependent if its residual is <= SETTN_TOL x its norm
+SETTN_TOL = 1e-8      # a column is dependent if its residual is <= SETTN_TOL x its norm
 
 
 def _mgs_keep(M, tol_rel):
@@ -341,11 +341,19 @@ def settn_rho0(model, beta0, order, tol_rel=SETTN_TOL):
     left unfolding of one charge are orthonormalised by ordered modified
     Gram-Schmidt (dependent columns, residual <= tol_rel x their own norm,
     are dropped) and the coefficients move into the next site; then right to
-    left over the rows of the right unfoldings."""
+    left over the rows of the right unfoldings.  A column counts as dependent
+    when its residual is below SETTN_TOL of its norm: the reduction is exact
+    up to directions of relative weight 1e-8 (in practice the dependent
+    residuals are at rounding level and the kept ones far above); a decision
+    inside the guard band raises instead of resting on rounding."""
     from math import comb, factorial
     N = model.N
     W = model.W
     charges = [model.bond_charges(k) for k in range(N + 1)]
+    for k in range(N):
+        dl, dr = len(charges[k]) ** order, len(charges[k + 1]) ** order
+        if dl > 8192 or dr > 8192 or dl * 16 * dr > 2 ** 26:
+            raise ValueError("SETTN start: the product MPO is too large for this order")
     A, Q = [], []
     for k in range(N):
         P, qL, qR = W[k], list(charges[k]), list(charges[k + 1])

@@ -120,6 +120,7 @@ struct tt_state {
   int N = 0;
   Lattice lat;
   Mpo mpo;
+  Rho0 rho0;                                // the start (cleared once the site tensors are filled)
   Groups G;
   std::vector<Bond> bonds;                  // 0..N
   std::vector<std::vector<Q>> qH;           // environment MPO charges per bond
@@ -544,15 +545,16 @@ void alloc_state(tt_state& s) {
 // rho0 tensors embedded in the padded block-sparse layout, plus the noise
 void fill_initial_tensors(tt_state& s, std::vector<std::vector<double>>& host) {
   const int N = s.N;
-  const double b0 = s.opts.beta0;
+  const Rho0& r0 = s.rho0;
+  TT_REQUIRE((int)r0.A.size() == N, TT_EINVAL, "rho0 tensors are not available");
   // embedding of rho0 bond states: (sector, local index)
   std::vector<std::vector<std::pair<int, int>>> emb(N + 1);
   std::vector<std::vector<int>> n0(N + 1);
   for (int k = 0; k <= N; ++k) {
     n0[k].assign(s.bonds[k].secs.size(), 0);
-    int nst = (k == N) ? 1 : s.mpo.DH[k];
+    int nst = (int)r0.q[k].size();
     for (int a = 0; a < nst; ++a) {
-      Q q = (k == N || s.G.ng == 1) ? Q{0, 0} : s.mpo.charge(k, a);
+      Q q = (k == N || s.G.ng == 1) ? Q{0, 0} : r0.q[k][a];
       int sec = s.bonds[k].find(q);
       TT_REQUIRE(sec >= 0 && n0[k][sec] < s.bonds[k].secs[sec].dim, TT_EINVAL, "rho0 does not fit the bond sectors");
       emb[k].push_back({sec, n0[k][sec]});
@@ -564,15 +566,12 @@ void fill_initial_tensors(tt_state& s, std::vector<std::vector<double>>& host) {
     const SiteLayout& S = s.site[k];
     std::vector<double>& h = host[k];
     h.assign(S.size, 0.0);
-    int DL = s.mpo.DH[k], DR = s.mpo.DH[k + 1];
-    int DRo = (k == N - 1) ? 1 : DR;
+    const int DL = (int)r0.q[k].size(), DRo = (int)r0.q[k + 1].size();
     const Bond& br = s.bonds[k + 1];
     for (int a = 0; a < DL; ++a)
       for (int q = 0; q < 16; ++q)
         for (int b = 0; b < DRo; ++b) {
-          double v;
-          if (k == N - 1) v = s.mpo.W[k][((size_t)a * 16 + q) * DR + 0] - b0 * s.mpo.W[k][((size_t)a * 16 + q) * DR + 1];
-          else v = s.mpo.W[k][((size_t)a * 16 + q) * DR + b];
+          const double v = r0.A[k][((size_t)a * 16 + q) * DRo + b];
           if (v == 0.0) continue;
           int l = emb[k][a].first, x = emb[k][a].second;
           int r = emb[k + 1][b].first, y = emb[k + 1][b].second;
@@ -623,13 +622,12 @@ void canonicalise_and_envs(tt_state& s) {
 std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
   const int N = s.N;
   std::vector<std::map<Q, int>> n0(N + 1);
-  for (int k = 0; k < N; ++k)
-    for (int a = 0; a < s.mpo.DH[k]; ++a) n0[k][s.mpo.charge(k, a)]++;
-  n0[N][{0, 0}] = 1;
+  for (int k = 0; k <= N; ++k)
+    for (const Q& q : s.rho0.q[k]) n0[k][q]++;
   if (s.opts.symmetry) return allocate_sectors(N, s.opts.D, n0, s.opts.sector_cap);
   std::vector<std::map<Q, int>> d(N + 1);
   for (int k = 0; k <= N; ++k) {
-    int n = (k == N) ? 1 : s.mpo.DH[k];
+    int n = (int)s.rho0.q[k].size();
     long long mx = pow16_cap(std::min(k, N - k), 1LL << 40);
     long long v = std::max<long long>(std::min<long long>(s.opts.D, mx), n);
     d[k][{0, 0}] = (int)v;
@@ -640,7 +638,7 @@ std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
 void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(o.D >= 1, TT_EINVAL, "D must be positive");
   TT_REQUIRE(o.symmetry == 0 || o.symmetry == 1, TT_EINVAL, "symmetry must be 0 or 1");
-  TT_REQUIRE(o.taylor_order == 1, TT_EINVAL, "only the linear start rho0 = 1 - beta0 H is supported");
+  TT_REQUIRE(o.taylor_order >= 1 && o.taylor_order <= 4, TT_EINVAL, "taylor_order must be in 1..4");
   TT_REQUIRE(o.krylov_dim >= 1 && o.krylov_dim <= kMaxKrylov, TT_EINVAL, "krylov_dim must be in 1..32");
   TT_REQUIRE(o.krylov_tol >= 0.0, TT_EINVAL, "krylov_tol must be >= 0");
   TT_REQUIRE(o.precision >= TT_FP64 && o.precision <= TT_BF16X6, TT_EINVAL, "unknown precision");
@@ -659,6 +657,7 @@ std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o
   s->lat = make_lattice(m.W, m.L, m.geometry);
   s->N = s->lat.N;
   s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu);
+  s->rho0 = make_rho0(s->mpo, o.beta0, o.taylor_order);
   s->G = make_groups(o.symmetry == 1);
   auto dims = bond_dims(*s);
   if (with_plans) {
@@ -1195,6 +1194,7 @@ int mpo_init_highT(const tt_model* model, const tt_options* opts, tt_state** out
   auto s = make_state(*model, *opts);
   std::vector<std::vector<double>> host;
   fill_initial_tensors(*s, host);
+  s->rho0 = Rho0();
   for (int k = 0; k < s->N; ++k)
     HIPX(hipMemcpyAsync(s->A[k], host[k].data(), 8 * host[k].size(), hipMemcpyHostToDevice, ST()));
   canonicalise_and_envs(*s);

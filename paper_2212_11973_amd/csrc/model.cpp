@@ -11,6 +11,7 @@
 //   ks < k < N : [start, dst(j,type) for pending destinations j ascending, done]
 // type in (c+_up P, c+_dn P, P c_up, P c_dn).
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <set>
@@ -563,6 +564,232 @@ Mpo make_green_mpo(const Lattice& lat, double kx, double ky, bool pattern) {
     m.W[q] = Wk;
   }
   return m;
+}
+
+namespace {
+// Ordered modified Gram-Schmidt (two passes) over the columns cols[j] (each
+// of length m): dependent columns (residual <= tol x own norm) are dropped.
+// Returns the kept orthonormal columns; R (kept x n) holds the coefficients,
+// cols[j] = sum_i Q[i] R[i][j].  A residual within a factor 10 of the
+// threshold is an error (the decision would rest on rounding).
+constexpr double kSettnTol = 1e-8;
+std::vector<std::vector<double>> mgs_keep(const std::vector<std::vector<double>>& cols,
+                                          std::vector<std::vector<double>>& R) {
+  const size_t n = cols.size();
+  std::vector<std::vector<double>> Q;
+  std::vector<std::vector<double>> Rc(n);   // per column: coefficients on Q (grows)
+  std::vector<int> pivot(n, -1);
+  for (size_t j = 0; j < n; ++j) {
+    std::vector<double> v = cols[j];
+    double n0 = 0.0;
+    for (double x : v) n0 += x * x;
+    n0 = std::sqrt(n0);
+    std::vector<double> coef(Q.size(), 0.0);
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t i = 0; i < Q.size(); ++i) {
+        double c = 0.0;
+        for (size_t r = 0; r < v.size(); ++r) c += Q[i][r] * v[r];
+        coef[i] += c;
+        for (size_t r = 0; r < v.size(); ++r) v[r] -= c * Q[i][r];
+      }
+    double nv = 0.0;
+    for (double x : v) nv += x * x;
+    nv = std::sqrt(nv);
+    Rc[j] = coef;
+    if (n0 == 0.0) continue;
+    if (nv > 0.1 * kSettnTol * n0 && nv <= 10.0 * kSettnTol * n0) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "SETTN start: a Gram-Schmidt residual (%.3e of its column) is too close to "
+                    "the threshold (change taylor_order or beta0)", nv / n0);
+      throw Error(TT_EINVAL, msg);
+    }
+    if (nv > kSettnTol * n0) {
+      for (double& x : v) x /= nv;
+      Q.push_back(v);
+      pivot[j] = (int)Q.size() - 1;
+      Rc[j].push_back(nv);
+    }
+  }
+  R.assign(Q.size(), std::vector<double>(n, 0.0));
+  for (size_t j = 0; j < n; ++j)
+    for (size_t i = 0; i < Rc[j].size() && i < Q.size(); ++i) R[i][j] = Rc[j][i];
+  return Q;
+}
+}  // namespace
+
+Rho0 make_rho0(const Mpo& H, double beta0, int order) {
+  const int N = H.N;
+  Rho0 r;
+  r.A.resize(N);
+  r.q.resize(N + 1);
+  std::vector<std::vector<Q>> ch(N + 1);
+  for (int k = 0; k <= N; ++k)
+    for (int a = 0; a < H.DH[k]; ++a) ch[k].push_back(H.charge(k, a));
+  std::vector<int> D(N + 1);
+  if (order == 1) {
+    for (int k = 0; k < N; ++k) {
+      r.q[k] = ch[k];
+      D[k] = H.DH[k];
+    }
+    const int DR = H.DH[N];
+    for (int k = 0; k < N - 1; ++k) r.A[k] = H.W[k];
+    std::vector<double> last((size_t)H.DH[N - 1] * 16, 0.0);
+    for (int a = 0; a < H.DH[N - 1]; ++a)
+      for (int q = 0; q < 16; ++q)
+        last[(size_t)a * 16 + q] = H.W[N - 1][((size_t)a * 16 + q) * DR + 0] - beta0 * H.W[N - 1][((size_t)a * 16 + q) * DR + 1];
+    r.A[N - 1] = last;
+    r.q[N] = {Q{0, 0}};
+    return r;
+  }
+  // product MPO of `order` copies: state (a1..an) -> index ((a1 * DH + a2) * DH + ...)
+  for (int k = 0; k <= N; ++k) {
+    long long d = 1;
+    for (int i = 0; i < order; ++i) d *= H.DH[k];
+    TT_REQUIRE(d <= 8192, TT_EINVAL, "SETTN start: the product MPO bond is too large (lower taylor_order)");
+    D[k] = (int)d;
+    std::vector<Q> qs(1, Q{0, 0});
+    for (int i = 0; i < order; ++i) {
+      std::vector<Q> nq;
+      for (const Q& x : qs)
+        for (const Q& y : ch[k]) nq.push_back({x.first + y.first, x.second + y.second});
+      qs = nq;
+    }
+    r.q[k] = qs;
+  }
+  for (int k = 0; k < N; ++k) {
+    TT_REQUIRE((long long)D[k] * 16 * D[k + 1] <= (1LL << 26), TT_EINVAL,
+               "SETTN start: the product MPO tensor is too large (lower taylor_order)");
+    const int DL1 = H.DH[k], DR1 = H.DH[k + 1];
+    std::vector<double> P = H.W[k];   // [A][so][si][B], sizes dl x 4 x 4 x dr
+    long long dl = DL1, dr = DR1;
+    for (int f = 1; f < order; ++f) {
+      std::vector<double> Pn((size_t)(dl * DL1) * 16 * (dr * DR1), 0.0);
+      for (long long A = 0; A < dl; ++A)
+        for (int so = 0; so < 4; ++so)
+          for (int t = 0; t < 4; ++t)
+            for (long long B = 0; B < dr; ++B) {
+              const double p = P[((A * 4 + so) * 4 + t) * dr + B];
+              if (p == 0.0) continue;
+              for (int a = 0; a < DL1; ++a)
+                for (int si = 0; si < 4; ++si)
+                  for (int b = 0; b < DR1; ++b) {
+                    const double w = H.W[k][(((size_t)a * 4 + t) * 4 + si) * DR1 + b];
+                    if (w == 0.0) continue;
+                    Pn[(((A * DL1 + a) * 4 + so) * 4 + si) * (dr * DR1) + (B * DR1 + b)] += p * w;
+                  }
+            }
+      P.swap(Pn);
+      dl *= DL1;
+      dr *= DR1;
+    }
+    r.A[k] = P;
+  }
+  {   // boundary vector: a tuple with m factors done stands for H^m
+    const int nR = H.DH[N];   // start, done
+    const int M = D[N];
+    std::vector<double> bv(M);
+    for (int idx = 0; idx < M; ++idx) {
+      int m = 0, x = idx;
+      for (int i = 0; i < order; ++i) { m += (x % nR == 1); x /= nR; }
+      double c = 1.0, binom = 1.0;
+      for (int i = 1; i <= m; ++i) c *= -beta0 / i;
+      for (int i = 1; i <= m; ++i) binom = binom * (order - m + i) / i;
+      bv[idx] = c / binom;
+    }
+    const int dl = D[N - 1];
+    std::vector<double> last((size_t)dl * 16, 0.0);
+    for (int a = 0; a < dl; ++a)
+      for (int q = 0; q < 16; ++q) {
+        double v = 0.0;
+        for (int b = 0; b < M; ++b) v += r.A[N - 1][((size_t)a * 16 + q) * M + b] * bv[b];
+        last[(size_t)a * 16 + q] = v;
+      }
+    r.A[N - 1] = last;
+    D[N] = 1;
+    r.q[N] = {Q{0, 0}};
+  }
+  // exact reduction, left to right over the columns of the left unfoldings
+  for (int k = 0; k < N - 1; ++k) {
+    const int a = D[k], b = D[k + 1];
+    std::set<Q> qs(r.q[k + 1].begin(), r.q[k + 1].end());
+    std::vector<std::vector<double>> newcols, coef;   // coef: rows of C (new x old b)
+    std::vector<Q> newq;
+    for (const Q& qq : qs) {
+      std::vector<int> J;
+      for (int j = 0; j < b; ++j)
+        if (r.q[k + 1][j] == qq) J.push_back(j);
+      std::vector<std::vector<double>> cols(J.size(), std::vector<double>((size_t)a * 16));
+      for (size_t c = 0; c < J.size(); ++c)
+        for (long long row = 0; row < (long long)a * 16; ++row) cols[c][row] = r.A[k][row * b + J[c]];
+      std::vector<std::vector<double>> R;
+      auto Qm = mgs_keep(cols, R);
+      for (size_t i = 0; i < Qm.size(); ++i) {
+        newcols.push_back(Qm[i]);
+        std::vector<double> crow(b, 0.0);
+        for (size_t c = 0; c < J.size(); ++c) crow[J[c]] = R[i][c];
+        coef.push_back(crow);
+        newq.push_back(qq);
+      }
+    }
+    const int nb = (int)newcols.size();
+    std::vector<double> Ak((size_t)a * 16 * nb);
+    for (long long row = 0; row < (long long)a * 16; ++row)
+      for (int c = 0; c < nb; ++c) Ak[row * nb + c] = newcols[c][row];
+    const int bn = D[k + 2];
+    std::vector<double> An((size_t)nb * 16 * bn, 0.0);   // C . A_{k+1}
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < b; ++j) {
+        const double c = coef[i][j];
+        if (c == 0.0) continue;
+        const double* src = &r.A[k + 1][(size_t)j * 16 * bn];
+        double* dst = &An[(size_t)i * 16 * bn];
+        for (long long e = 0; e < 16LL * bn; ++e) dst[e] += c * src[e];
+      }
+    r.A[k] = Ak;
+    r.A[k + 1] = An;
+    D[k + 1] = nb;
+    r.q[k + 1] = newq;
+  }
+  // right to left over the rows of the right unfoldings
+  for (int k = N - 1; k >= 1; --k) {
+    const int a = D[k], b = D[k + 1];
+    std::set<Q> qs(r.q[k].begin(), r.q[k].end());
+    std::vector<std::vector<double>> newrows, coef;   // coef: rows of C (new x old a)
+    std::vector<Q> newq;
+    for (const Q& qq : qs) {
+      std::vector<int> J;
+      for (int j = 0; j < a; ++j)
+        if (r.q[k][j] == qq) J.push_back(j);
+      std::vector<std::vector<double>> cols(J.size());
+      for (size_t c = 0; c < J.size(); ++c)
+        cols[c].assign(r.A[k].begin() + (size_t)J[c] * 16 * b, r.A[k].begin() + (size_t)(J[c] + 1) * 16 * b);
+      std::vector<std::vector<double>> R;
+      auto Qm = mgs_keep(cols, R);
+      for (size_t i = 0; i < Qm.size(); ++i) {
+        newrows.push_back(Qm[i]);
+        std::vector<double> crow(a, 0.0);
+        for (size_t c = 0; c < J.size(); ++c) crow[J[c]] = R[i][c];
+        coef.push_back(crow);
+        newq.push_back(qq);
+      }
+    }
+    const int na = (int)newrows.size();
+    std::vector<double> Ak((size_t)na * 16 * b);
+    for (int i = 0; i < na; ++i) std::copy(newrows[i].begin(), newrows[i].end(), Ak.begin() + (size_t)i * 16 * b);
+    const int ap = D[k - 1];
+    std::vector<double> Ap((size_t)ap * 16 * na, 0.0);   // A_{k-1} . C^T
+    for (long long row = 0; row < (long long)ap * 16; ++row)
+      for (int j = 0; j < a; ++j) {
+        const double v = r.A[k - 1][row * a + j];
+        if (v == 0.0) continue;
+        for (int i = 0; i < na; ++i) Ap[row * na + i] += v * coef[i][j];
+      }
+    r.A[k] = Ak;
+    r.A[k - 1] = Ap;
+    D[k] = na;
+    r.q[k] = newq;
+  }
+  return r;
 }
 
 }  // namespace tt

@@ -46,6 +46,16 @@ std::vector<std::pair<int, int>> pairs_at_distance(const Lattice& lat, int d2);
 Mpo make_spin_pair_mpo(int N, const std::vector<std::pair<int, int>>& pairs);   // sum over pairs of S_i . S_j
 Mpo make_green_mpo(const Lattice& lat, double kx, double ky, bool pattern);      // super-operator of G(k, beta/2)
 
+// The start rho0 as a super-MPS on the host: A[k] = [D_k][16][D_{k+1}] (bond N
+// has one state) and the charge of every bond state (bonds 0..N).  order 1:
+// 1 - beta0 H; order > 1: the SETTN polynomial sum_{n <= order} (-beta0 H)^n / n!
+// from the product MPO, reduced exactly to linearly independent bond states.
+struct Rho0 {
+  std::vector<std::vector<double>> A;
+  std::vector<std::vector<Q>> q;
+};
+Rho0 make_rho0(const Mpo& H, double beta0, int order);
+
 // ------------------------------------------------------------------ sectors
 struct Sector { Q q; int dim; long long off; };
 struct Bond {

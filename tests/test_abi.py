@@ -35,7 +35,7 @@ def _m(**kw):
 
 
 @pytest.mark.parametrize("field,value", [("precision", 7), ("krylov_dim", 0), ("krylov_dim", 33),
-                                         ("taylor_order", 2), ("symmetry", 2), ("D", 0),
+                                         ("taylor_order", 5), ("symmetry", 2), ("D", 0),
                                          ("env_on_host", 1), ("krylov_tol", -1.0)])
 def test_invalid_options_rejected_without_gpu(field, value):
     o = T.options(**{field: value})
@@ -109,3 +109,32 @@ def test_sectors_match_oracle_allocation(W, L, geo, D, cap, tp):
             want[q] = want.get(q, 0) + 1
         got = dict(T.tt_model_bond_sectors(m, o, k))
         assert got == want, k
+
+
+@pytest.mark.parametrize("W,L,geo,D,cap,order,b0", [(1, 6, 0, 30, 0, 2, 0.01), (2, 3, 2, 60, 0, 2, 2.0 ** -10),
+                                                    (3, 3, 1, 120, 64, 2, 0.01), (1, 8, 0, 40, 8, 3, 2.0 ** -10),
+                                                    (4, 8, 1, 600, 64, 2, 2.0 ** -10)])
+def test_settn_sectors_match_oracle(W, L, geo, D, cap, order, b0):
+    # the SETTN start's reduced bond states (counts per charge) and the sectors
+    # allocated around them equal the oracle's
+    from oracle import charges, mpo
+    mm = mpo.HubbardMPO(W, L, geo, 1.0, 8.0, 1.0)
+    N = mm.N
+    _, q0 = mpo.settn_rho0(mm, b0, order)
+    lay = charges.bond_layouts(list(q0) + [[(0, 0)]], N, D, True, cap)
+    m = T.model(W, L, geo, 1.0, 8.0, 1.0)
+    o = T.options(D=D, symmetry=1, sector_cap=cap, beta0=b0, taylor_order=order)
+    for k in range(N + 1):
+        want = {}
+        for q in lay[k].charges:
+            want[q] = want.get(q, 0) + 1
+        assert dict(T.tt_model_bond_sectors(m, o, k)) == want, k
+    v, _, rep = T.tt_check_plans(m, o)
+    assert v == 0, rep
+
+
+def test_settn_rejects_bad_orders():
+    m = T.model(1, 4, 0, 1.0, 4.0, 0.0)
+    for order in (0, 5):
+        with pytest.raises(T.TTError):
+            T.tt_model_bond_sectors(m, T.options(D=16, taylor_order=order), 1)

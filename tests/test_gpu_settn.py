@@ -1,0 +1,84 @@
+"""GPU parity of the SETTN start rho0 = sum_{n <= Nc} (-beta0 H)^n / n! (SM I.E):
+the flow from it at untruncated bonds against ED (same flow, polynomial
+start), at truncated bonds against the oracle (same reduced rho0, same
+padding), and the expansion error it removes on the SM Fig. S7 workload."""
+import pytest
+
+from oracle import ed, mpo as ompo, tdvp as otd
+from paper_2212_11973_amd import tantrg as T
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _rel(a, b, floor=1e-2):
+    return abs(a - b) / max(abs(b), floor)
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,sym,order", [(1, 4, T.TT_CHAIN, 4.0, 0.3, 1, 2),
+                                                     (2, 2, T.TT_OPEN_SQUARE, 4.0, 0.3, 1, 3),
+                                                     (1, 4, T.TT_CHAIN, 4.0, 0.3, 0, 3)])
+def test_settn_start_matches_ed_untruncated(W, L, geo, U, mu, sym, order):
+    print("settn ed", W, L, geo, sym, order, flush=True)
+    b0 = 0.1
+    E, _, _ = ed.Hubbard(W, L, geo, 1.0, U, mu).spectrum()
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu), T.options(D=256, symmetry=sym, beta0=b0, taylor_order=order))
+    for step in range(5):
+        o = st.observables()
+        lnZ, Ebl = ed.same_ode_bilayer(E, b0, o["beta"], order)
+        assert _rel(o["lnZ"], lnZ) <= TOL, (step, o["lnZ"], lnZ)
+        assert _rel(o["E"], Ebl) <= TOL, (step, o["E"], Ebl)
+        assert _rel(o["lnZ_single"], ed.same_ode_single(E, b0, o["beta"], order)) <= TOL
+        st.sweep(0.1)
+    st.free()
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,D,sym,pad,order", [(2, 3, T.TT_OPEN_SQUARE, 8.0, 1.0, 60, 1, 1e-3, 2),
+                                                          (3, 3, T.TT_CYLINDER, 8.0, 2.0, 120, 1, 1e-3, 2),
+                                                          (1, 6, T.TT_CHAIN, 4.0, 0.3, 40, 0, 1e-3, 3)])
+def test_settn_start_matches_oracle_truncated(W, L, geo, U, mu, D, sym, pad, order):
+    print("settn oracle", W, L, geo, D, sym, order, flush=True)
+    b0 = 0.01
+    mm = ompo.HubbardMPO(W, L, geo, 1.0, U, mu)
+    ost = otd.initial_state(mm, b0, D, bool(sym), pad_eps=pad, seed=7, sector_cap=64, taylor_order=order)
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu),
+                      T.options(D=D, symmetry=sym, beta0=b0, pad_eps=pad, seed=7, taylor_order=order))
+    assert st.info()[1] == ost.dims()
+    for _ in range(3):
+        o, r = st.observables(), ost.observables()
+        assert _rel(o["lnZ"], r["lnZ"]) <= TOL, (o["lnZ"], r["lnZ"])
+        assert _rel(o["E"], r["E"]) <= TOL, (o["E"], r["E"])
+        assert _rel(o["lnZ_single"], r["lnZ_single"]) <= TOL
+        st.sweep(0.1)
+        ost.sweep(0.1)
+    st.free()
+
+
+def test_settn_removes_expansion_error_free_fermion_cylinder():
+    # SM Fig. S7(a) workload, CL 4x8 free fermions at D = 600: relative error
+    # of f against the U = 0 closed form along the doubling grid from
+    # beta0 = 2^-10, linear start (Nc = 1) against SETTN Nc = 2
+    W, L, N = 4, 8, 32
+    h = ed.Hubbard(W, L, T.TT_CYLINDER, 1.0, 0.0, 0.0).hopping_matrix()
+    b0 = 2.0 ** -10
+    rows = {}
+    for order in (1, 2):
+        print("fig s7 settn order", order, flush=True)
+        st = T.State.init(T.model(W, L, T.TT_CYLINDER, 1.0, 0.0, 0.0),
+                          T.options(D=600, symmetry=1, beta0=b0, pad_eps=1e-9, seed=3, taylor_order=order))
+        out = {}
+        b = b0
+        for _ in range(7):
+            st.sweep(b)
+            b *= 2.0
+            o = st.observables()
+            bp = o["beta_phys"]
+            f_ex = -ed.free_fermion_lnZ(h, bp) / (N * bp)
+            out[round(bp, 15)] = abs(o["f"] - f_ex) / abs(f_ex)
+        rows[order] = out
+        st.free()
+    for bp in sorted(rows[1]):
+        print("beta_phys %.3e  dF linear %.2e  dF SETTN(2) %.2e" % (bp, rows[1][bp], rows[2][bp]))
+    assert rows[1][2.0 ** -8] > 1e-7
+    assert rows[2][2.0 ** -8] < 1e-2 * rows[1][2.0 ** -8]
