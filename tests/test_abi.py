@@ -124,7 +124,8 @@ def test_settn_sectors_match_oracle(W, L, geo, D, cap, order, b0):
     lay = charges.bond_layouts(list(q0) + [[(0, 0)]], N, D, True, cap)
     m = T.model(W, L, geo, 1.0, 8.0, 1.0)
     o = T.options(D=D, symmetry=1, sector_cap=cap, beta0=b0, taylor_order=order)
-    for k in range(N + 1):
+    bonds = range(N + 1) if N <= 16 else sorted({0, 1, 2, 3, 4, N // 2, N - 3, N - 1, N})
+    for k in bonds:
         want = {}
         for q in lay[k].charges:
             want[q] = want.get(q, 0) + 1

@@ -23,10 +23,11 @@ def test_contracts_to_taylor_polynomial(W, L, geo, order):
     assert np.abs(mpo.mpo_to_dense(A) - _dense_poly(H, 0.2, order)).max() < 1e-13
 
 
-@pytest.mark.parametrize("order", [1, 2, 3, 4])
-def test_taylor_remainder_bound(order):
+@pytest.mark.parametrize("W,L,geo,order", [(2, 2, lattice.OPEN_SQUARE, 1), (2, 2, lattice.OPEN_SQUARE, 2),
+                                           (2, 2, lattice.OPEN_SQUARE, 3), (1, 4, lattice.CHAIN, 4)])
+def test_taylor_remainder_bound(W, L, geo, order):
     # ||rho0 - exp(-beta0 H)||_2 <= (beta0 ||H||)^(order+1) / (order+1)! x exp(beta0 ||H||)
-    W, L, geo, b0 = 2, 2, lattice.OPEN_SQUARE, 0.05
+    b0 = 0.05
     h = ed.Hubbard(W, L, geo, 1.0, 6.0, 1.0)
     A, _ = mpo.settn_rho0(mpo.HubbardMPO(W, L, geo, 1.0, 6.0, 1.0), b0, order)
     rho0 = mpo.mpo_to_dense(A)
@@ -67,6 +68,12 @@ def test_reduction_is_exact_minimal_and_charge_conserving(W, L, geo, order):
         for (x, s, y) in zip(*np.nonzero(np.abs(a16) > 1e-14)):
             ql, qr, qs = Qs[k][x], Qs[k + 1][y], charges.s_charge(s)
             assert (ql[0] + qs[0], ql[1] + qs[1]) == tuple(qr)
+
+
+def test_product_size_guard():
+    # Nc = 4 on a 2x2 square: the product bond exceeds 8192 states
+    with pytest.raises(ValueError):
+        mpo.settn_rho0(mpo.HubbardMPO(2, 2, lattice.OPEN_SQUARE, 1.0, 4.0, 0.0), 0.05, 4)
 
 
 def test_mgs_threshold_guard():
