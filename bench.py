@@ -65,6 +65,44 @@ def cpu_baseline(D, DH):
     return t, flops
 
 
+def green_map(args, T, WL):
+    """beta G(k, beta/2) (main text, Fermi-surface paragraph) on the 10x10 open
+    square at U = 8, mu = 2, T = 2: linear start at beta0 = 2^-20, doubling
+    grid to beta = 1/4 (beta_phys = 1/2), then G on kx, ky in {0, pi/5, ..., pi}."""
+    c = WL.MODELS["os10x10"]
+    D = args.D or c["D"]
+    b0 = 2.0 ** -20
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], 2.0)
+    t0 = time.perf_counter()
+    st = T.State.init(m, T.options(D=D, symmetry=1, beta0=b0, pad_eps=1e-3, seed=1, krylov_dim=c["krylov"]))
+    t_init = time.perf_counter() - t0
+    b, nsw = b0, 0
+    t0 = time.perf_counter()
+    while b < 0.25:
+        st.sweep(b)
+        b *= 2.0
+        nsw += 1
+        print("green map: beta %.3g" % b, file=sys.stderr, flush=True)
+    t_sweeps = time.perf_counter() - t0
+    o = st.observables()
+    ks = [math.pi * i / 5 for i in range(6)]
+    grid = []
+    t0 = time.perf_counter()
+    for kx in ks:
+        for ky in ks:
+            G = st.green_function(kx, ky)
+            grid.append([kx, ky, o["beta_phys"] * G])
+        print("green map: kx %.3f done" % kx, file=sys.stderr, flush=True)
+    t_g = time.perf_counter() - t0
+    loc = st.local_observables()
+    st.free()
+    print(json.dumps({"metric": "beta G(k, beta/2) map", "workload": "Hubbard 10x10 open square, U=8, mu=2, "
+                      "U(1)xU(1) D=%d" % D, "beta_phys": o["beta_phys"], "n": loc["n"], "docc": loc["docc"],
+                      "e": o["e"],
+                      "grid": grid, "sweeps": nsw, "seconds_init": t_init, "seconds_sweeps": t_sweeps,
+                      "seconds_per_k": t_g / len(grid)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,10 +127,12 @@ def main():
     ap.add_argument("--mu-scan", type=int, default=8,
                     help="instances of the batched mu-scan on the 6x12 cylinder (0: skip)")
     ap.add_argument("--mu-scan-D", type=int, default=0, help="override the mu-scan bond dimension")
+    ap.add_argument("--green-map", action="store_true",
+                    help="instead of the headline: beta G(k, beta/2) over a k grid on the 10x10 open square "
+                         "(U=8, mu=2, T=2, D=4000), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU (--gpus 1); multi-GPU runs are not part of this build",
-              file=sys.stderr)
+        print("bench.py runs on exactly one GPU (--gpus 1); the sweep has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -110,6 +150,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.green_map:
+        green_map(args, T, WL)
+        return
     c = WL.MODELS[args.workload]
     D = args.D or c["D"]
     m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
