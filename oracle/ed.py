@@ -402,3 +402,86 @@ def atomic_green(U, mu, beta):
     G = 2 [exp(beta mu / 2) + exp(-beta (U - 3 mu) / 2)] / Z_site."""
     z = 1.0 + 2.0 * np.exp(beta * mu) + np.exp(-beta * (U - 2.0 * mu))
     return 2.0 * (np.exp(0.5 * beta * mu) + np.exp(-0.5 * beta * (U - 3.0 * mu))) / z
+
+
+# ---------------------------------------------------------------- pairing field
+def pairing_bonds(W, L, geometry):
+    """Nearest-neighbour bonds (i < j) with the d-wave form factor s_ij: +1 for
+    a bond along the length (x), -1 across the width (y) (main text, d-wave
+    pairing paragraph)."""
+    order = lattice.snake_order(W, L)
+    out = []
+    for (i, j) in lattice.nn_bonds(W, L, geometry):
+        (xi, _), (xj, _) = order[i], order[j]
+        out.append((i, j, 1.0 if xi != xj else -1.0))
+    return out
+
+
+def dense_pairing(model):
+    """Delta_tot = sum_<ij> s_ij (Delta_ij + Delta_ij^+)/2 with
+    Delta_ij = (c_i,dn c_j,up - c_i,up c_j,dn)/sqrt 2, as a dense 4^N matrix."""
+    N = model.N
+    C = {(i, s): model.dense_annihilator(i, s) for i in range(N) for s in (0, 1)}
+    out = np.zeros((4 ** N, 4 ** N))
+    for (i, j, s) in pairing_bonds(model.W, model.L, model.geometry):
+        d = (C[(i, 1)] @ C[(j, 0)] - C[(i, 0)] @ C[(j, 1)]) / np.sqrt(2.0)
+        out += s * (d + d.T) / 2.0
+    return out
+
+
+def dense_hamiltonian_with_pairing(model, hp):
+    """H - hp Delta_tot as a dense matrix (the field breaks N_up, N_down)."""
+    return model.dense_hamiltonian() - hp * dense_pairing(model)
+
+
+def same_ode_bilayer_pairing(model, hp, beta0, beta):
+    """Bilayer values at beta_phys = 2 beta for rho(beta) = exp(-(beta-beta0) H)
+    (1 - beta0 H), H with the pairing field: (ln Z_bl, E_bl, Delta_p) with
+    Delta_p = <Delta_tot> / N_p, <O> = Tr(O rho^2) / Tr(rho^2)."""
+    H = dense_hamiltonian_with_pairing(model, hp)
+    E, V = np.linalg.eigh(H)
+    a = 1.0 - beta0 * E
+    x = 2.0 * np.log(np.abs(a)) - 2.0 * (beta - beta0) * E
+    lnZ = _logsumexp(x)
+    w = np.exp(x - lnZ)
+    Dt = dense_pairing(model)
+    d = np.einsum("fk,fg,gk->k", V, Dt, V)
+    nb = len(pairing_bonds(model.W, model.L, model.geometry))
+    return lnZ, float(np.sum(w * E)), float(np.sum(w * d)) / nb
+
+
+def thermal_pairing(model, hp, beta):
+    """Exact thermal (ln Z, Delta_p) of exp(-beta (H - hp Delta_tot)), dense."""
+    H = dense_hamiltonian_with_pairing(model, hp)
+    E, V = np.linalg.eigh(H)
+    x = -beta * E
+    lnZ = _logsumexp(x)
+    w = np.exp(x - lnZ)
+    d = np.einsum("fk,fg,gk->k", V, dense_pairing(model), V)
+    nb = len(pairing_bonds(model.W, model.L, model.geometry))
+    return lnZ, float(np.sum(w * d)) / nb
+
+
+def bdg_pairing(model, hp, beta):
+    """U = 0 closed form (Bogoliubov-de Gennes).  With the Nambu spinor
+    psi = (c_up, c+_dn), H = psi^+ H_B psi + Tr h, H_B = [[h, K], [K, -h]],
+    h the hopping matrix (with -mu) and K_ij = K_ji = -hp s_ij / (2 sqrt 2)
+    on the bonds (from c_i,dn c_j,up + c_j,dn c_i,up = psi^+_{N+i} psi_j +
+    psi^+_{N+j} psi_i).  With <psi^+_a psi_b> = [f(H_B)]_ba:
+    ln Z = -beta Tr h + sum_n ln(1 + exp(-beta E_n)) over the 2N eigenvalues,
+    <Delta_tot> = sum_<ij> s_ij / sqrt 2 (<psi^+_{N+i} psi_j> + <psi^+_{N+j} psi_i>).
+    Returns (ln Z, Delta_p)."""
+    assert model.U == 0.0
+    N = model.N
+    h = model.hopping_matrix()
+    K = np.zeros((N, N))
+    bonds = pairing_bonds(model.W, model.L, model.geometry)
+    for (i, j, s) in bonds:
+        K[i, j] = K[j, i] = -hp * s / (2.0 * np.sqrt(2.0))
+    HB = np.block([[h, K], [K, -h]])
+    E, U = np.linalg.eigh(HB)
+    f = 1.0 / (np.exp(beta * E) + 1.0)
+    G = (U * f) @ U.T                      # G[b, a] = <psi^+_a psi_b>
+    lnZ = -beta * np.trace(h) + float(np.sum(np.logaddexp(0.0, -beta * E)))
+    tot = sum(s / np.sqrt(2.0) * (G[j, N + i] + G[i, N + j]) for (i, j, s) in bonds)
+    return lnZ, float(tot) / len(bonds)

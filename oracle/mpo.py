@@ -51,8 +51,25 @@ CHANNELS = (
     (PAR @ C_UP, CDAG_UP),
     (PAR @ C_DN, CDAG_DN),
 )
+# pairing-field channels (main text, d-wave pairing paragraph): for i < j,
+# a_i b_j = (a P)_i (prod P) b_j; the four terms of
+# c_i,dn c_j,up - c_i,up c_j,dn - c+_i,dn c+_j,up + c+_i,up c+_j,dn
+PAIR_CHANNELS = (
+    (C_DN @ PAR, C_UP, 1.0),
+    (C_UP @ PAR, C_DN, -1.0),
+    (CDAG_DN @ PAR, CDAG_UP, -1.0),
+    (CDAG_UP @ PAR, CDAG_DN, 1.0),
+)
 # U(1)xU(1) charge carried by a channel: q(b) = q(a) + q(so) - q(si)
-CHANNEL_CHARGE = ((1, 0), (0, 1), (-1, 0), (0, -1))
+CHANNEL_CHARGE = ((1, 0), (0, 1), (-1, 0), (0, -1), (0, -1), (-1, 0), (0, 1), (1, 0))
+
+
+def channel_ops(ty):
+    """(left operator, right operator, sign) of channel type ty: 0..3 hopping
+    (sign 1, amplitude -t), 4..7 pairing (amplitude -hp s_ij / (2 sqrt 2))."""
+    if ty < 4:
+        return CHANNELS[ty][0], CHANNELS[ty][1], 1.0
+    return PAIR_CHANNELS[ty - 4]
 
 
 def local_charge(sigma):
@@ -63,16 +80,24 @@ def local_charge(sigma):
 class HubbardMPO:
     """W tensors of Eq. (3) with the bond-state convention above."""
 
-    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0):
+    def __init__(self, W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0, hp=0.0):
         self.N = N = W * L
-        self.t, self.U, self.mu, self.tp = float(t), float(U), float(mu), float(tp)
+        self.t, self.U, self.mu, self.tp, self.hp = float(t), float(U), float(mu), float(tp), float(hp)
         # hopping amplitude per coupled pair (i < j): t on bonds, tp on the
         # diagonal neighbours of SM Eq. S1 when tp != 0
         self.amp = {b: self.t for b in lattice.nn_bonds(W, L, geometry)}
         if self.tp != 0.0:
             self.amp.update({b: self.tp for b in lattice.nnn_bonds(W, L, geometry)})
+        # pairing field -hp Delta_tot on the bonds (d-wave form factor s_ij)
+        self.ntypes = 8 if self.hp != 0.0 else 4
+        self.pamp = {}
+        if self.hp != 0.0:
+            order = lattice.snake_order(W, L)
+            for (i, j) in lattice.nn_bonds(W, L, geometry):
+                s = 1.0 if order[i][0] != order[j][0] else -1.0
+                self.pamp[(i, j)] = -self.hp * s / (2.0 * np.sqrt(2.0))
         self.partners = [set() for _ in range(N)]
-        for (i, j) in self.amp:
+        for (i, j) in list(self.amp) + list(self.pamp):
             self.partners[i].add(j)
         # bond states: list of labels per bond k = 0..N
         self.ks = ks = N // 2
@@ -87,10 +112,10 @@ class HubbardMPO:
             lab = ["start"]
             if k <= ks:
                 pend = [i for i in range(k) if any(j >= k for j in self.partners[i])]
-                lab += [("src", i, ty) for i in pend for ty in range(4)]
+                lab += [("src", i, ty) for i in pend for ty in range(self.ntypes)]
             else:
                 pend = [j for j in range(k, N) if any(i < k for i in self.neighbours(j))]
-                lab += [("dst", j, ty) for j in pend for ty in range(4)]
+                lab += [("dst", j, ty) for j in pend for ty in range(self.ntypes)]
             lab.append("done")
             self.states.append(lab)
         self.W = [self._site(k) for k in range(N)]
@@ -106,6 +131,12 @@ class HubbardMPO:
     def bond_charges(self, k):
         return [self.charge(lab) for lab in self.states[k]]
 
+    def coef(self, i, j, ty):
+        """Amplitude of channel type ty between i < j (times the channel's sign)."""
+        if ty < 4:
+            return -self.amp.get((i, j), 0.0)
+        return self.pamp.get((i, j), 0.0) * PAIR_CHANNELS[ty - 4][2]
+
     def _site(self, k):
         left, right = self.states[k], self.states[k + 1]
         ri = {lab: n for n, lab in enumerate(right)}
@@ -117,12 +148,13 @@ class HubbardMPO:
                 Wk[a, :, :, ri["start"]] += ID4
                 if "done" in ri:
                     Wk[a, :, :, ri["done"]] += onsite
-                for ty in range(4):
+                for ty in range(self.ntypes):
+                    left = channel_ops(ty)[0]
                     if ("src", k, ty) in ri:
-                        Wk[a, :, :, ri[("src", k, ty)]] += CHANNELS[ty][0]
+                        Wk[a, :, :, ri[("src", k, ty)]] += left
                     for j in later:
                         if ("dst", j, ty) in ri:
-                            Wk[a, :, :, ri[("dst", j, ty)]] += -self.amp[(k, j)] * CHANNELS[ty][0]
+                            Wk[a, :, :, ri[("dst", j, ty)]] += self.coef(k, j, ty) * left
             elif lab == "done":
                 Wk[a, :, :, ri["done"]] += ID4
             elif lab[0] == "src":
@@ -131,13 +163,13 @@ class HubbardMPO:
                     Wk[a, :, :, ri[lab]] += PAR
                 for j in sorted(self.partners[i]):
                     if j > k and ("dst", j, ty) in ri:
-                        Wk[a, :, :, ri[("dst", j, ty)]] += -self.amp[(i, j)] * PAR
+                        Wk[a, :, :, ri[("dst", j, ty)]] += self.coef(i, j, ty) * PAR
                 if k in self.partners[i]:
-                    Wk[a, :, :, ri["done"]] += -self.amp[(i, k)] * CHANNELS[ty][1]
+                    Wk[a, :, :, ri["done"]] += self.coef(i, k, ty) * channel_ops(ty)[1]
             else:
                 _, j, ty = lab
                 if j == k:
-                    Wk[a, :, :, ri["done"]] += CHANNELS[ty][1]
+                    Wk[a, :, :, ri["done"]] += channel_ops(ty)[1]
                 else:
                     Wk[a, :, :, ri[lab]] += PAR
         return Wk
