@@ -61,11 +61,16 @@ typedef struct tt_state tt_state;
  * h.c.), over diagonal neighbours (squared lattice distance 2, a cylinder's
  * width taken the short way for W >= 3; a chain has none).  tp = 0 gives the
  * MPO of Eq. (3) unchanged; tp != 0 adds the diagonal partners to its
- * channels (larger D_H). */
+ * channels (larger D_H).  hp != 0 adds the d-wave pairing field of the main
+ * text's pairing paragraph, -hp sum_<ij> s_ij (Delta_ij + Delta_ij^+)/2 with
+ * Delta_ij = (c_i,dn c_j,up - c_i,up c_j,dn)/sqrt 2 and s_ij = +1 (-1) for a
+ * bond along the length (across the width); it breaks the U(1) charges, so it
+ * needs symmetry = 0 (TT_EINVAL otherwise). */
 typedef struct {
   int W, L;          /* width and length; chain: W = 1 */
   int geometry;      /* TT_CHAIN, TT_CYLINDER (wrap across W only for W >= 3), TT_OPEN_SQUARE */
   double t, tp, U, mu;
+  double hp;         /* pairing field (0: none) */
 } tt_model;
 
 typedef struct {
@@ -177,6 +182,14 @@ int thermo_spin_correlation(tt_state* s, int d2, double* host_F, int* host_npair
  * another k rewrites their weights only.  Synchronises.  TT_EINVAL for a
  * non-finite k. */
 int thermo_green_function(tt_state* s, double kx, double ky, double* host_G);
+
+/* d-wave pairing order per bond (main text, pairing paragraph):
+ * *host_delta = <Delta_tot> / N_p at beta_phys = 2 beta (bilayer), Delta_tot
+ * as in tt_model with N_p nearest-neighbour bonds (*host_nbonds, may be NULL);
+ * the susceptibility is chi_SC = Delta_p / hp.  Needs a state with
+ * symmetry = 0 (TT_EINVAL otherwise: with the U(1) charges the value is 0 by
+ * symmetry).  The first call builds the plans; FP64.  Synchronises. */
+int thermo_pairing_order(tt_state* s, double* host_delta, int* host_nbonds);
 
 /* Entropy and specific heat per site from n >= 3 bilayer observables taken
  * along a sweep (host arrays of length n, beta = beta_phys strictly

@@ -440,7 +440,8 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   // the plans keep every MPO entry that is nonzero for generic couplings, so
   // states that differ only in t, U, mu (an exact zero such as U - 2 mu at
   // half filling included) get identical plans and can share launches
-  s.Wpat = env_tensors(make_hubbard_mpo(s.lat, 1.0, s.model.tp != 0.0 ? 0.7 : 0.0, 1.0, 0.3));
+  s.Wpat = env_tensors(make_hubbard_mpo(s.lat, 1.0, s.model.tp != 0.0 ? 0.7 : 0.0, 1.0, 0.3,
+                                        s.model.hp != 0.0 ? 0.45 : 0.0));
   s.site.clear(); s.env.clear(); s.bmat.clear();
   for (int k = 0; k < N; ++k) s.site.push_back(make_site_layout(s.bonds[k], s.bonds[k + 1], s.G));
   for (int k = 0; k <= N; ++k) {
@@ -645,8 +646,10 @@ void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(o.env_on_host == 0, TT_EINVAL, "host-resident environments are not supported");
   TT_REQUIRE(o.sector_cap >= 0, TT_EINVAL, "sector_cap must be >= 0");
   TT_REQUIRE(std::isfinite(o.beta0) && std::isfinite(o.pad_eps), TT_EINVAL, "beta0 and pad_eps must be finite");
-  TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.tp) && std::isfinite(m.U) && std::isfinite(m.mu), TT_EINVAL,
-             "model parameters must be finite");
+  TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.tp) && std::isfinite(m.U) && std::isfinite(m.mu) &&
+                 std::isfinite(m.hp), TT_EINVAL, "model parameters must be finite");
+  TT_REQUIRE(m.hp == 0.0 || o.symmetry == 0, TT_EINVAL,
+             "the pairing field breaks the U(1) charges: it needs symmetry = 0");
 }
 
 std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o, bool with_plans = true) {
@@ -656,7 +659,7 @@ std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o
   s->opts = o;
   s->lat = make_lattice(m.W, m.L, m.geometry);
   s->N = s->lat.N;
-  s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu);
+  s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu, m.hp);
   s->rho0 = make_rho0(s->mpo, o.beta0, o.taylor_order);
   s->G = make_groups(o.symmetry == 1);
   auto dims = bond_dims(*s);
@@ -869,6 +872,7 @@ template <typename T> bool same_bytes(const std::vector<T>& x, const std::vector
   return x.size() == y.size() && (x.empty() || std::memcmp(x.data(), y.data(), sizeof(T) * x.size()) == 0);
 }
 constexpr int kObsGreen = 2000;                          // the Green's function G(k, beta/2)
+constexpr int kObsPairing = 3000;                        // the d-wave pairing sum Delta_tot
 
 // MPO charges per bond of an observable MPO (bond 0: start; bond N: done)
 std::vector<std::vector<Q>> obs_charges(const tt_state& s, const Mpo& m) {
@@ -1356,6 +1360,23 @@ int thermo_green_function(tt_state* s, double kx, double ky, double* host_G) {
   ABI_END
 }
 
+int thermo_pairing_order(tt_state* s, double* host_delta, int* host_nbonds) {
+  ABI_BEGIN
+  TT_REQUIRE(s && host_delta, TT_EINVAL, "null argument");
+  TT_REQUIRE(s->G.ng == 1, TT_EINVAL, "thermo_pairing_order: needs a state with symmetry = 0");
+  const auto bonds = pairing_bonds(s->lat);
+  TT_REQUIRE(!bonds.empty(), TT_EINVAL, "thermo_pairing_order: no bonds");
+  auto it = s->obs.find(kObsPairing);
+  // H - hp Delta_tot with t = U = mu = 0 and hp = -1 is Delta_tot itself
+  tt_state::ObsMpo& O =
+      it != s->obs.end() ? it->second : build_obs_mpo(*s, kObsPairing, make_hubbard_mpo(s->lat, 0.0, 0.0, 0.0, 0.0, -1.0));
+  const double d = obs_expectation(*s, O) / (double)bonds.size();
+  TT_REQUIRE(std::isfinite(d), TT_ENUMERIC, "non-finite pairing order");
+  *host_delta = d;
+  if (host_nbonds) *host_nbonds = (int)bonds.size();
+  ABI_END
+}
+
 void tt_state_free(tt_state* s) {
   if (!s) return;
   (void)hipStreamSynchronize(ST());
@@ -1498,7 +1519,7 @@ int tt_state_load(const char* path, tt_state** out) {
   s->opts = o;
   s->lat = make_lattice(m.W, m.L, m.geometry);
   s->N = s->lat.N;
-  s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu);
+  s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu, m.hp);
   s->G = make_groups(o.symmetry == 1);
   std::vector<std::map<Q, int>> dims(s->N + 1);
   for (int k = 0; k <= s->N; ++k) {

@@ -67,6 +67,7 @@ M4 transpose(const M4& a) {
 struct LocalOps {
   M4 id, par, cdu, cdd, cu, cd, onsite;
   M4 left[4], right[4];
+  M4 pleft[4], pright[4];   // pairing channels: (a P)_i ... b_j
 };
 LocalOps local_ops(double U, double mu) {
   LocalOps o;
@@ -86,11 +87,21 @@ LocalOps local_ops(double U, double mu) {
   o.left[1] = mul(o.cdd, o.par); o.right[1] = o.cd;
   o.left[2] = mul(o.par, o.cu);  o.right[2] = o.cdu;
   o.left[3] = mul(o.par, o.cd);  o.right[3] = o.cdd;
+  // pairing: c_i,dn c_j,up, c_i,up c_j,dn, c+_i,dn c+_j,up, c+_i,up c+_j,dn
+  o.pleft[0] = mul(o.cd, o.par);  o.pright[0] = o.cu;
+  o.pleft[1] = mul(o.cu, o.par);  o.pright[1] = o.cd;
+  o.pleft[2] = mul(o.cdd, o.par); o.pright[2] = o.cdu;
+  o.pleft[3] = mul(o.cdu, o.par); o.pright[3] = o.cdd;
   return o;
 }
+// signs of the pairing channels in
+// c_i,dn c_j,up - c_i,up c_j,dn - c+_i,dn c+_j,up + c+_i,up c+_j,dn
+const double kPairSign[4] = {1.0, -1.0, -1.0, 1.0};
 // channel charges: the hopping channels 0..3 (c+_up, c+_dn, c_up, c_dn at the
-// source), then the spin channels 4..6 (Sz, S+, S- at the source)
-const Q kChannelQ[7] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}, {0, 0}, {1, -1}, {-1, 1}};
+// source), the spin channels 4..6 (Sz, S+, S- at the source), the pairing
+// channels 7..10 (c_dn, c_up, c+_dn, c+_up at the source)
+const Q kChannelQ[11] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}, {0, 0}, {1, -1}, {-1, 1},
+                         {0, -1}, {-1, 0}, {0, 1}, {1, 0}};
 }  // namespace
 
 Q Mpo::charge(int k, int a) const {
@@ -99,22 +110,46 @@ Q Mpo::charge(int k, int a) const {
   return kChannelQ[s.type];
 }
 
-Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double mu) {
+std::vector<std::pair<std::pair<int, int>, double>> pairing_bonds(const Lattice& lat) {
+  std::vector<std::pair<std::pair<int, int>, double>> out;
+  for (auto& b : lat.bonds) {
+    const int xi = b.first / lat.W, xj = b.second / lat.W;   // column along the length
+    out.push_back({b, xi != xj ? 1.0 : -1.0});
+  }
+  return out;
+}
+
+Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double mu, double hp) {
   const int N = lat.N;
   Mpo m;
   m.N = N;
   // hopping amplitude of every coupled pair (i < j): t on nearest neighbours,
   // tp on next-nearest (diagonal) neighbours when tp != 0 (SM Eq. S1)
-  std::map<std::pair<int, int>, double> hop;
+  std::map<std::pair<int, int>, double> hop, pair;
   for (auto& b : lat.bonds) hop[b] = t;
   if (tp != 0.0)
     for (auto& b : pairs_at_distance(lat, 2)) hop[b] = tp;
-  auto amp = [&](int i, int j) { return hop.at({std::min(i, j), std::max(i, j)}); };
+  // pairing field -hp Delta_tot: amplitude -hp s_ij / (2 sqrt 2) per bond
+  if (hp != 0.0)
+    for (auto& b : pairing_bonds(lat)) pair[b.first] = -hp * b.second / (2.0 * std::sqrt(2.0));
+  std::vector<int> types = {0, 1, 2, 3};
+  if (hp != 0.0) types.insert(types.end(), {7, 8, 9, 10});
+  // amplitude of channel type ty between i < j (with the channel's sign)
+  auto coef = [&](int i, int j, int ty) {
+    const std::pair<int, int> key{std::min(i, j), std::max(i, j)};
+    if (ty < 4) {
+      auto it = hop.find(key);
+      return it == hop.end() ? 0.0 : -it->second;
+    }
+    auto it = pair.find(key);
+    return it == pair.end() ? 0.0 : it->second * kPairSign[ty - 7];
+  };
   std::vector<std::set<int>> later(N), earlier(N);   // coupled sites j > i, i < j
-  for (auto& kv : hop) {
-    later[kv.first.first].insert(kv.first.second);
-    earlier[kv.first.second].insert(kv.first.first);
-  }
+  for (auto* mp : {&hop, &pair})
+    for (auto& kv : *mp) {
+      later[kv.first.first].insert(kv.first.second);
+      earlier[kv.first.second].insert(kv.first.first);
+    }
   const int ks = N / 2;
   m.states.resize(N + 1);
   m.states[0] = {{0, -1, -1}};
@@ -126,19 +161,21 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double m
       for (int i = 0; i < k; ++i) {
         bool pending = !later[i].empty() && *later[i].rbegin() >= k;
         if (pending)
-          for (int ty = 0; ty < 4; ++ty) st.push_back({2, i, ty});
+          for (int ty : types) st.push_back({2, i, ty});
       }
     } else {
       for (int j = k; j < N; ++j) {
         bool pending = !earlier[j].empty() && *earlier[j].begin() < k;
         if (pending)
-          for (int ty = 0; ty < 4; ++ty) st.push_back({3, j, ty});
+          for (int ty : types) st.push_back({3, j, ty});
       }
     }
     st.push_back({1, -1, -1});
   }
   for (int k = 0; k <= N; ++k) m.DH.push_back((int)m.states[k].size());
   LocalOps o = local_ops(U, mu);
+  auto left = [&](int ty) -> const M4& { return ty < 4 ? o.left[ty] : o.pleft[ty - 7]; };
+  auto right = [&](int ty) -> const M4& { return ty < 4 ? o.right[ty] : o.pright[ty - 7]; };
   m.W.resize(N);
   for (int k = 0; k < N; ++k) {
     const auto& Ls = m.states[k];
@@ -161,12 +198,12 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double m
       if (s.kind == 0) {
         put(a, bstart, o.id, 1.0);
         if (bdone >= 0) put(a, bdone, o.onsite, 1.0);
-        for (int ty = 0; ty < 4; ++ty) {
+        for (int ty : types) {
           int b = find(2, k, ty);
-          if (b >= 0) put(a, b, o.left[ty], 1.0);
+          if (b >= 0) put(a, b, left(ty), 1.0);
           for (int j : later[k]) {
             int bd = find(3, j, ty);
-            if (bd >= 0) put(a, bd, o.left[ty], -amp(k, j));
+            if (bd >= 0) put(a, bd, left(ty), coef(k, j, ty));
           }
         }
       } else if (s.kind == 1) {
@@ -177,12 +214,12 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double m
         for (int j : later[s.site]) {
           if (j <= k) continue;
           int bd = find(3, j, s.type);
-          if (bd >= 0) put(a, bd, o.par, -amp(s.site, j));
+          if (bd >= 0) put(a, bd, o.par, coef(s.site, j, s.type));
         }
-        if (later[s.site].count(k)) put(a, bdone, o.right[s.type], -amp(s.site, k));
+        if (later[s.site].count(k)) put(a, bdone, right(s.type), coef(s.site, k, s.type));
       } else {
         if (s.site == k) {
-          put(a, bdone, o.right[s.type], 1.0);
+          put(a, bdone, right(s.type), 1.0);
         } else {
           int b = find(3, s.site, s.type);
           TT_REQUIRE(b >= 0, TT_EINVAL, "mpo: lost destination channel");

@@ -40,7 +40,8 @@ struct Mpo {
   std::vector<int> DH;                         // per bond
   Q charge(int k, int a) const;
 };
-Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double mu);
+Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double mu, double hp);
+std::vector<std::pair<std::pair<int, int>, double>> pairing_bonds(const Lattice& lat);   // bonds with s_ij
 Mpo make_local_sum_mpo(int N, const double op[4]);   // sum_i op_i, op diagonal
 std::vector<std::pair<int, int>> pairs_at_distance(const Lattice& lat, int d2);
 Mpo make_spin_pair_mpo(int N, const std::vector<std::pair<int, int>>& pairs);   // sum over pairs of S_i . S_j

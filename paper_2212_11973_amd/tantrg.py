@@ -23,13 +23,14 @@ SYMBOLS = [
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
-    "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function",
+    "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function", "thermo_pairing_order",
 ]
 
 
 class tt_model(C.Structure):
     _fields_ = [("W", C.c_int), ("L", C.c_int), ("geometry", C.c_int),
-                ("t", C.c_double), ("tp", C.c_double), ("U", C.c_double), ("mu", C.c_double)]
+                ("t", C.c_double), ("tp", C.c_double), ("U", C.c_double), ("mu", C.c_double),
+                ("hp", C.c_double)]
 
 
 class tt_options(C.Structure):
@@ -92,6 +93,7 @@ def lib():
         L.thermo_spin_correlation.argtypes = [vp, C.c_int, dp, ip]
         L.tt_sweep_graphs.argtypes = [C.c_int]
         L.thermo_green_function.argtypes = [vp, C.c_double, C.c_double, dp]
+        L.thermo_pairing_order.argtypes = [vp, dp, ip]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -124,8 +126,8 @@ def options_default():
     return o
 
 
-def model(W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0):
-    return tt_model(W, L, geometry, t, tp, U, mu)
+def model(W, L, geometry, t=1.0, U=8.0, mu=0.0, tp=0.0, hp=0.0):
+    return tt_model(W, L, geometry, t, tp, U, mu, hp)
 
 
 def options(**kw):
@@ -190,6 +192,13 @@ def thermo_green_function(state, kx, ky):
     G = C.c_double()
     _check(lib().thermo_green_function(state, float(kx), float(ky), C.byref(G)))
     return G.value
+
+
+def thermo_pairing_order(state):
+    """(Delta_p = <Delta_tot> / N_p, N_p) for a state with symmetry = 0."""
+    d, n = C.c_double(), C.c_int()
+    _check(lib().thermo_pairing_order(state, C.byref(d), C.byref(n)))
+    return d.value, n.value
 
 
 def tt_thermo_derived(beta_phys, e, f):
@@ -330,6 +339,9 @@ class State:
 
     def green_function(self, kx, ky):
         return thermo_green_function(self.h, kx, ky)
+
+    def pairing_order(self):
+        return thermo_pairing_order(self.h)
 
     def info(self):
         return tt_state_info(self.h)

@@ -44,6 +44,32 @@ def test_invalid_options_rejected_without_gpu(field, value):
     assert e.value.code == T.TT_EINVAL
 
 
+def test_pairing_field_needs_the_non_symmetric_mode():
+    m = T.model(1, 4, T.TT_CHAIN, 1.0, 4.0, 0.0, hp=0.1)
+    with pytest.raises(T.TTError) as e:
+        T.mpo_init_highT(m, T.options(symmetry=1))
+    assert e.value.code == T.TT_EINVAL
+    with pytest.raises(T.TTError) as e:
+        T.mpo_init_highT(T.model(1, 4, T.TT_CHAIN, 1.0, 4.0, 0.0, hp=float("inf")), T.options(symmetry=0))
+    assert e.value.code == T.TT_EINVAL
+    # non-symmetric bonds hold the larger pairing MPO: max(min(D, 16^k), D_H) states
+    from oracle import mpo
+    mm = mpo.HubbardMPO(2, 3, lattice_open_square(), 1.0, 8.0, 1.0, hp=0.2)
+    o = T.options(D=20, symmetry=0)
+    m = T.model(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, 1.0, hp=0.2)
+    for k in range(7):
+        n = len(mm.bond_charges(k)) if k < 6 else 1
+        want = max(min(20, 16 ** min(k, 6 - k)), n)
+        assert dict(T.tt_model_bond_sectors(m, o, k)) == {(0, 0): want}, k
+    v, _, rep = T.tt_check_plans(m, o)
+    assert v == 0, rep
+
+
+def lattice_open_square():
+    from oracle import lattice
+    return lattice.OPEN_SQUARE
+
+
 @pytest.mark.parametrize("kw", [dict(tp=float("nan")), dict(W=2, geometry=T.TT_CHAIN), dict(L=1), dict(geometry=5)])
 def test_invalid_model_rejected_without_gpu(kw):
     with pytest.raises(T.TTError) as e:

@@ -1,0 +1,71 @@
+"""GPU parity of the d-wave pairing field -hp Delta_tot and the pairing order
+Delta_p = <Delta_tot> / N_p (main text, pairing paragraph; bilayer values at
+beta_phys = 2 beta) with ED at untruncated bonds and with the oracle at
+truncated bonds, in the non-symmetric bond mode the field needs."""
+import pytest
+
+from oracle import ed, mpo as ompo, tdvp as otd
+from paper_2212_11973_amd import tantrg as T
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _rel(a, b, floor=1e-2):
+    return abs(a - b) / max(abs(b), floor)
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,hp", [(1, 4, T.TT_CHAIN, 4.0, 0.3, 0.3), (2, 2, T.TT_OPEN_SQUARE, 8.0, 1.5, 0.5),
+                                              (1, 4, T.TT_CHAIN, 0.0, -0.4, 0.05)])
+def test_pairing_matches_ed_untruncated(W, L, geo, U, mu, hp):
+    print("pairing ed", W, L, geo, U, hp, flush=True)
+    b0 = 0.01
+    h = ed.Hubbard(W, L, geo, 1.0, U, mu)
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu, hp=hp), T.options(D=256, symmetry=0, beta0=b0))
+    for step in range(7):
+        if step % 3 == 0:
+            o = st.observables()
+            lnZ, E, dp = ed.same_ode_bilayer_pairing(h, hp, b0, o["beta"])
+            d, nb = st.pairing_order()
+            assert nb == len(ed.pairing_bonds(W, L, geo))
+            assert _rel(o["lnZ"], lnZ) <= TOL, (step, o["lnZ"], lnZ)
+            assert _rel(o["E"], E) <= TOL, (step, o["E"], E)
+            assert abs(d - dp) <= TOL, (step, d, dp)
+        st.sweep(0.05)
+    st.free()
+
+
+def test_pairing_order_needs_the_non_symmetric_mode():
+    st = T.State.init(T.model(1, 4, T.TT_CHAIN, 1.0, 4.0, 0.0), T.options(D=16, symmetry=1, beta0=0.01))
+    with pytest.raises(T.TTError):
+        st.pairing_order()
+    st.free()
+    # without a field the order vanishes (charge conservation) in the non-symmetric mode too
+    st = T.State.init(T.model(1, 4, T.TT_CHAIN, 1.0, 4.0, 0.0), T.options(D=256, symmetry=0, beta0=0.01))
+    st.sweep(0.1)
+    assert abs(st.pairing_order()[0]) < 1e-13
+    st.free()
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,D,pad,hp", [(1, 6, T.TT_CHAIN, 4.0, 0.3, 12, 1e-3, 0.2),
+                                                   (2, 3, T.TT_OPEN_SQUARE, 8.0, 1.0, 20, 1e-3, 0.1)])
+def test_pairing_matches_oracle_truncated(W, L, geo, U, mu, D, pad, hp):
+    print("pairing oracle", W, L, geo, D, flush=True)
+    b0 = 0.01
+    mm = ompo.HubbardMPO(W, L, geo, 1.0, U, mu, hp=hp)
+    ost = otd.initial_state(mm, b0, D, False, pad_eps=pad, seed=11)
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu, hp=hp),
+                      T.options(D=D, symmetry=0, beta0=b0, pad_eps=pad, seed=11))
+    assert st.info()[1] == ost.dims()
+    for _ in range(2):
+        st.sweep(0.1)
+        ost.sweep(0.1)
+    o, r = st.observables(), ost.observables()
+    assert _rel(o["lnZ"], r["lnZ"]) <= TOL, (o["lnZ"], r["lnZ"])
+    assert _rel(o["E"], r["E"]) <= TOL, (o["E"], r["E"])
+    nb = len(ed.pairing_bonds(W, L, geo))
+    ref = ost.expectation(ompo.HubbardMPO(W, L, geo, 0.0, 0.0, 0.0, hp=-1.0).mpo_for_env()) / nb
+    d, _ = st.pairing_order()
+    assert abs(d - ref) <= TOL, (d, ref)
+    st.free()
