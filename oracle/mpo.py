@@ -382,10 +382,14 @@ def settn_rho0(model, beta0, order, tol_rel=SETTN_TOL):
     N = model.N
     W = model.W
     charges = [model.bond_charges(k) for k in range(N + 1)]
+    total = 0
     for k in range(N):
         dl, dr = len(charges[k]) ** order, len(charges[k + 1]) ** order
+        total += dl * 16 * dr
         if dl > 8192 or dr > 8192 or dl * 16 * dr > 2 ** 26:
             raise ValueError("SETTN start: the product MPO is too large for this order")
+    if total > 2 ** 28:
+        raise ValueError("SETTN start: the product MPO is too large for this order")
     A, Q = [], []
     for k in range(N):
         P, qL, qR = W[k], list(charges[k]), list(charges[k + 1])

@@ -693,6 +693,9 @@ Rho0 make_rho0(const Mpo& H, double beta0, int order) {
     }
     r.q[k] = qs;
   }
+  long long total = 0;
+  for (int k = 0; k < N; ++k) total += (long long)D[k] * 16 * D[k + 1];
+  TT_REQUIRE(total <= (1LL << 28), TT_EINVAL, "SETTN start: the product MPO is too large (lower taylor_order)");
   for (int k = 0; k < N; ++k) {
     TT_REQUIRE((long long)D[k] * 16 * D[k + 1] <= (1LL << 26), TT_EINVAL,
                "SETTN start: the product MPO tensor is too large (lower taylor_order)");
