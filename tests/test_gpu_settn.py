@@ -82,3 +82,29 @@ def test_settn_removes_expansion_error_free_fermion_cylinder():
         print("beta_phys %.3e  dF linear %.2e  dF SETTN(2) %.2e" % (bp, rows[1][bp], rows[2][bp]))
     assert rows[1][2.0 ** -8] > 1e-7
     assert rows[2][2.0 ** -8] < 1e-2 * rows[1][2.0 ** -8]
+
+
+def test_full_size_settn_start_agrees_with_tiny_linear_start():
+    # 4x16 cylinder at D = 2000 (the sweep workload, padding kept tiny so that
+    # both states are their starts): SETTN Nc = 2 from beta0 = 2^-10 and the
+    # linear start from 2^-20, both doubled to beta = 2^-8 (beta_phys = 1/128).
+    # Their expansion errors are far below 1e-8; the two runs differ by the
+    # projection errors of their different paths on the padded manifold
+    # (measured 2.5e-7 in f here), so the bar is loose: the full-size SETTN
+    # start runs and agrees with the independent route
+    print("settn 4x16", flush=True)
+    m = T.model(4, 16, T.TT_CYLINDER, 1.0, 8.0, 1.5)
+    out = []
+    for b0, order in ((2.0 ** -10, 2), (2.0 ** -20, 1)):
+        st = T.State.init(m, T.options(D=2000, symmetry=1, beta0=b0, pad_eps=1e-9, seed=1, taylor_order=order))
+        b = b0
+        while b < 2.0 ** -8:
+            st.sweep(b)
+            b *= 2.0
+        o = st.observables()
+        assert abs(o["beta"] - 2.0 ** -8) < 1e-15
+        out.append(o)
+        st.free()
+    print("f", out[0]["f"], out[1]["f"], "e", out[0]["e"], out[1]["e"])
+    assert _rel(out[0]["f"], out[1]["f"]) < 1e-5, (out[0]["f"], out[1]["f"])
+    assert _rel(out[0]["e"], out[1]["e"]) < 1e-4, (out[0]["e"], out[1]["e"])
