@@ -44,6 +44,19 @@ def heff1(L, W, R, A):
     return out.transpose(0, 2, 1, 3)
 
 
+def heff2(L, W1, W2, R, C):
+    """Two-site generator H^(2) C of the 2-TDVP flow (SM Sec. 2-TDVP in the
+    initial stage, Eq. S-2TDVP) on C_i = A_i^L A_{i+1}:
+    out[x,so1,sp1,so2,sp2,y] = sum L[x,a,al] C[al,si1,sp1,si2,sp2,be]
+    W1[a,so1,si1,b] W2[b,so2,si2,c] R[y,c,be], contracted as L.C, then W1,
+    then W2, then R."""
+    T1 = np.tensordot(L, C, axes=([2], [0]))              # x a si1 sp1 si2 sp2 be
+    T2 = np.tensordot(T1, W1, axes=([1, 2], [0, 2]))      # x sp1 si2 sp2 be so1 b
+    T3 = np.tensordot(T2, W2, axes=([6, 2], [0, 2]))      # x sp1 sp2 be so1 so2 c
+    out = np.tensordot(T3, R, axes=([3, 6], [2, 1]))      # x sp1 sp2 so1 so2 y
+    return out.transpose(0, 3, 1, 4, 2, 5)
+
+
 def heff0(L, R, S):
     """H^(0) S (SM Fig. optimalB(d)): out[x,y] = sum L[x,a,al] S[al,be] R[y,a,be]."""
     T = np.tensordot(L, S, axes=([2], [0]))               # x a be

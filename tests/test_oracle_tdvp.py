@@ -207,3 +207,31 @@ def test_canonical_form_after_sweep():
     for A in st.A[1:]:
         M = A.reshape(A.shape[0], -1)
         assert np.allclose(M @ M.T, np.eye(A.shape[0]), atol=1e-12)
+
+
+def test_two_site_generator_against_loops():
+    Dl, Dr, DH = 2, 2, 2
+    L, R = _rand((Dl, DH, Dl), 11), _rand((Dr, DH, Dr), 12)
+    W1, W2 = _rand((DH, 4, 4, DH), 13), _rand((DH, 4, 4, DH), 14)
+    C = _rand((Dl, 4, 4, 4, 4, Dr), 15)
+    out = np.zeros((Dl, 4, 4, 4, 4, Dr))
+    for x, so1, sp1, so2, sp2, y in itertools.product(range(Dl), range(4), range(4), range(4), range(4), range(Dr)):
+        v = 0.0
+        for a, al, si1, b, si2, c, be in itertools.product(range(DH), range(Dl), range(4), range(DH), range(4),
+                                                          range(DH), range(Dr)):
+            v += L[x, a, al] * C[al, si1, sp1, si2, sp2, be] * W1[a, so1, si1, b] * W2[b, so2, si2, c] * R[y, c, be]
+        out[x, so1, sp1, so2, sp2, y] = v
+    assert np.allclose(tdvp.heff2(L, W1, W2, R, C), out, atol=1e-12)
+
+
+def test_two_site_generator_is_h_on_a_two_site_system():
+    # N = 2 with trivial environments: H^(2) C is (H (x) 1)|rho>> for the dense
+    # two-site H of ED and any two-site super tensor C (Choi map, SM Sec. II.A)
+    h = ed.Hubbard(1, 2, 0, 1.0, 5.0, 0.7)
+    Ws = mpo.HubbardMPO(1, 2, 0, 1.0, 5.0, 0.7).mpo_for_env()
+    C = _rand((1, 4, 4, 4, 4, 1), 16)
+    one = np.ones((1, 1, 1))
+    got = tdvp.heff2(one, Ws[0], Ws[1], one, C)[0, :, :, :, :, 0]      # so1 sp1 so2 sp2
+    rho = C[0, :, :, :, :, 0].transpose(0, 2, 1, 3).reshape(16, 16)   # (s1 s2), (s1' s2')
+    want = (h.dense_hamiltonian() @ rho).reshape(4, 4, 4, 4).transpose(0, 2, 1, 3)
+    assert np.abs(got - want).max() < 1e-13
