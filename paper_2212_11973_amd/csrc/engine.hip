@@ -1165,6 +1165,64 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   c.Dl = Dl; c.Dr = Dr; c.DH = DH;
 }
 
+// The two-site generator H^(2) C of 2-TDVP on dense operands: the ket MPO
+// tensor W2 of the second site and R form one right environment
+// R2[(s2o, y2)][b][(s2i, y)] = sum_c W2[b, so, si, c] delta(ao, ai) R[y2, c, y]
+// (s = 4 sigma + sigma'), so that H^(2) C is the one-site apply with W1 and R2
+// on C read as A[x][s1][(s2, y)] (right bond 16 Dr).  R2 is one grouped GEMM
+// per (y2, ancilla): rows (b, so, si), columns y, depth c.
+struct Heff2Cache {
+  int Dl = -1, Dr = -1, DH = -1;
+  SiteTables tabs;
+  GemmPlan rg;
+  double* R2 = nullptr;
+  long long r2 = 0;
+};
+Heff2Cache g_heff2;
+
+void build_heff2_cache(int Dl, int Dr, int DH) {
+  Heff2Cache& c = g_heff2;
+  free_plan(c.rg);
+  dfree(c.tabs.dev);
+  c.tabs = SiteTables();
+  const long long Dr16 = 16LL * Dr;
+  std::vector<long long> rows[4];
+  for (int ap = 0; ap < 4; ++ap)
+    for (int b = 0; b < DH; ++b)
+      for (int so = 0; so < 4; ++so)
+        for (int si = 0; si < 4; ++si)
+          rows[ap].push_back(((long long)(4 * so + ap) * Dr * DH + b) * Dr16 + (long long)(4 * si + ap) * Dr);
+  long long tab[4];
+  for (int ap = 0; ap < 4; ++ap) tab[ap] = c.tabs.add(rows[ap]);
+  c.rg = GemmPlan();
+  c.rg.tag = TAG_WGEMM;
+  for (int y2 = 0; y2 < Dr; ++y2)
+    for (int ap = 0; ap < 4; ++ap) {
+      GemmProb g{};
+      g.M = 16 * DH; g.N = Dr; g.K = DH;
+      g.ia = 0; g.ib = 1; g.ic = 2;
+      g.sam = DH; g.sak = 1; g.tam = -1; g.tak = -1;
+      g.offB = (long long)y2 * DH * Dr; g.sbk = Dr; g.sbn = 1; g.tbk = -1; g.tbn = -1;
+      g.offC = (long long)y2 * DH * Dr16; g.tcm = tab[ap];
+      g.alpha = 1.0; g.beta = 0.0;
+      c.rg.probs.push_back(g);
+      c.rg.flops += 2.0 * g.M * (double)g.N * g.K;
+    }
+  const long long r2 = Dr16 * DH * Dr16;
+  tile_plan(c.rg, &c.tabs.host);
+  std::string rep;
+  long long sizes[kSlots] = {(long long)DH * 16 * DH, (long long)Dr * DH * Dr, r2, 0};
+  TT_REQUIRE(check_gemm(c.rg, c.tabs.host, sizes, "heff2 R2", rep) == 0, TT_EINVAL, "heff2 plan out of bounds: " + rep);
+  hipStream_t st = ST();
+  c.tabs.dev = upload(c.tabs.host, st);
+  upload_plan(c.rg, &c.tabs.host, st);
+  if (r2 > c.r2) { dfree(c.R2); c.R2 = (double*)dalloc(8 * r2); c.r2 = r2; }
+  // the GEMM writes the entries with equal ancilla indices only; the others
+  // are zero (delta(ao, ai)) and stay so while the layout is kept
+  launch_fill(c.R2, 0.0, r2, st);
+  c.Dl = Dl; c.Dr = Dr; c.DH = DH;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1573,6 +1631,43 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
     HIPX(hipEventRecord(c.ev[2], st));
     launch_gemm(c.plan.s3, c.tabs.dev, one(Slots{{c.T2, const_cast<double*>(R), out, nullptr}}), 1, precision,
                 one(c.pws), st);
+    HIPX(hipEventRecord(c.ev[3], st));
+    c.timed = true;
+  } catch (...) {
+    g_stream = saved;
+    throw;
+  }
+  g_stream = saved;
+  ABI_END
+}
+
+int tt_heff2_apply(int Dl, int Dr, int DH, const double* L, const double* W1, const double* W2, const double* C,
+                   const double* R, double* out, int precision, void* stream) {
+  ABI_BEGIN
+  TT_REQUIRE(Dl >= 1 && Dr >= 1 && DH >= 1, TT_EINVAL, "dimensions must be positive");
+  TT_REQUIRE(L && W1 && W2 && C && R && out, TT_EINVAL, "null device pointer");
+  TT_REQUIRE(precision >= TT_FP64 && precision <= TT_BF16X6, TT_EINVAL, "unknown precision");
+  TT_REQUIRE((double)Dl * DH * 256 * Dr < 4.0e9 && 256.0 * Dr * Dr * DH < 4.0e9, TT_EINVAL, "problem too large");
+  hipStream_t saved = g_stream;
+  if (stream) g_stream = (hipStream_t)stream;
+  try {
+    if (g_heff2.Dl != Dl || g_heff2.Dr != Dr || g_heff2.DH != DH) build_heff2_cache(Dl, Dr, DH);
+    if (g_heff.Dl != Dl || g_heff.Dr != 16 * Dr || g_heff.DH != DH) build_heff_cache(Dl, 16 * Dr, DH);
+    Heff2Cache& c2 = g_heff2;
+    HeffCache& c = g_heff;
+    if (c2.rg.pws_size > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * c2.rg.pws_size); c.pw = c2.rg.pws_size; }
+    hipStream_t st = ST();
+    // R2 = W2.R is formed in FP64 in every mode (one contraction per two-site step)
+    launch_gemm(c2.rg, c2.tabs.dev, one(Slots{{const_cast<double*>(W2), const_cast<double*>(R), c2.R2, nullptr}}), 1,
+                TT_FP64, one(c.pws), st);
+    HIPX(hipEventRecord(c.ev[0], st));
+    launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(C), c.T1, nullptr}}), 1,
+                precision, one(c.pws), st);
+    HIPX(hipEventRecord(c.ev[1], st));
+    launch_gemm(c.wg, c.tabs.dev, one(Slots{{const_cast<double*>(W1), c.T1, c.T2, nullptr}}), 1, precision, one(c.pws),
+                st);
+    HIPX(hipEventRecord(c.ev[2], st));
+    launch_gemm(c.plan.s3, c.tabs.dev, one(Slots{{c.T2, c2.R2, out, nullptr}}), 1, precision, one(c.pws), st);
     HIPX(hipEventRecord(c.ev[3], st));
     c.timed = true;
   } catch (...) {

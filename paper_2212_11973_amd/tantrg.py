@@ -24,6 +24,7 @@ SYMBOLS = [
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
     "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function", "thermo_pairing_order",
+    "tt_heff2_apply",
 ]
 
 
@@ -94,6 +95,7 @@ def lib():
         L.tt_sweep_graphs.argtypes = [C.c_int]
         L.thermo_green_function.argtypes = [vp, C.c_double, C.c_double, dp]
         L.thermo_pairing_order.argtypes = [vp, dp, ip]
+        L.tt_heff2_apply.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.tt_state_free.argtypes = [vp]
         L.tt_state_free.restype = None
         L.tt_state_info.argtypes = [vp, ip, ip]
@@ -260,6 +262,13 @@ def tt_heff_apply(Dl, Dr, DH, L_ptr, W_ptr, A_ptr, R_ptr, out_ptr, precision=TT_
     _check(lib().tt_heff_apply(Dl, Dr, DH, C.c_void_p(L_ptr), C.c_void_p(W_ptr), C.c_void_p(A_ptr),
                                C.c_void_p(R_ptr), C.c_void_p(out_ptr), precision,
                                C.c_void_p(stream) if stream else None))
+
+
+def tt_heff2_apply(Dl, Dr, DH, L_ptr, W1_ptr, W2_ptr, C_ptr, R_ptr, out_ptr, precision=TT_FP64, stream=None):
+    """Two-site generator on device pointers of FP64 row-major arrays."""
+    _check(lib().tt_heff2_apply(Dl, Dr, DH, C.c_void_p(L_ptr), C.c_void_p(W1_ptr), C.c_void_p(W2_ptr),
+                                C.c_void_p(C_ptr), C.c_void_p(R_ptr), C.c_void_p(out_ptr), precision,
+                                C.c_void_p(stream) if stream else None))
 
 
 def tt_heff_last_timing():

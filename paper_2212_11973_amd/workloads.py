@@ -42,6 +42,17 @@ def heff_inputs(D, DH=18, seed_base=20221223):
     return L, W, A, R
 
 
+def heff2_inputs(Dl, Dr, DH, seed):
+    """Two-site operands L[Dl,DH,Dl], W1, W2 [DH,4,4,DH], C[Dl,4,4,4,4,Dr], R[Dr,DH,Dr]."""
+    rng = np.random.default_rng(seed)
+    L = rng.standard_normal((Dl, DH, Dl))
+    W1 = rng.standard_normal((DH, 4, 4, DH))
+    W2 = rng.standard_normal((DH, 4, 4, DH))
+    C = rng.standard_normal((Dl, 4, 4, 4, 4, Dr))
+    R = rng.standard_normal((Dr, DH, Dr))
+    return L, W1, W2, C, R
+
+
 def heff_inputs_rect(Dl, Dr, DH, seed):
     """Rectangular variant L[Dl,DH,Dl], W, A[Dl,4,4,Dr], R[Dr,DH,Dr]."""
     rng = np.random.default_rng(seed)
