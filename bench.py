@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--heff-D", type=int, default=2000)
     ap.add_argument("--heff-reps", type=int, default=5)
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
+    ap.add_argument("--heff2-D", type=int, default=0,
+                    help="also time the dense two-site 2-TDVP generator at this bond dimension (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graphs", action="store_true", help="replay captured sweeps (hipGraph) in the timed loop")
     ap.add_argument("--no-observables", action="store_true",
@@ -353,6 +355,31 @@ def main():
                                stage_ms=[statistics.median(x[i] for x in ms) for i in range(3)])
         print("heff done", file=sys.stderr, flush=True)
         del tl, tw, ta, tr, out
+    D2 = args.heff2_D
+    if D2 > 0:   # two-site generator: R2 = W2.R, then the one-site apply with right bond 16 D2
+        L, W1, W2, C2, R = WL.heff2_inputs(D2, D2, DH, 20221223)
+        dev = torch.device("cuda:0")
+        tt_ = [torch.from_numpy(x).to(dev) for x in (L, W1, W2, C2, R)]
+        out = torch.empty_like(tt_[3])
+        sm = torch.cuda.current_stream().cuda_stream
+        ptrs = [x.data_ptr() for x in tt_]
+        T.tt_heff2_apply(D2, D2, DH, *ptrs, out.data_ptr(), T.TT_FP64, sm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms, ms1 = [], []
+        for _ in range(args.heff_reps):
+            e0.record()
+            T.tt_heff2_apply(D2, D2, DH, *ptrs, out.data_ptr(), T.TT_FP64, sm)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            ms1.append(T.tt_heff_last_timing()[3])
+        # flops of the contraction in the paper's order (L.C, W1, W2, .R)
+        fl2 = 2.0 * 256 * D2 ** 3 * DH + 2.0 * 2 * 16 * 4 * D2 * D2 * DH * DH * 16 + 2.0 * 256 * D2 ** 3 * DH
+        heff["two_site_fp64"] = dict(D=D2, ms=statistics.median(ms), ms_without_r2=statistics.median(ms1),
+                                     tflops_paper_order=fl2 / (statistics.median(ms) * 1e-3) / 1e12)
+        print("heff2 done", file=sys.stderr, flush=True)
+        del tt_, out
 
     cpu = None
     if not args.no_cpu_baseline:
