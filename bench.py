@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--heff-D", type=int, default=2000)
     ap.add_argument("--heff-reps", type=int, default=5)
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
-    ap.add_argument("--heff2-D", type=int, default=0,
+    ap.add_argument("--heff2-D", type=int, default=256,
                     help="also time the dense two-site 2-TDVP generator at this bond dimension (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graphs", action="store_true", help="replay captured sweeps (hipGraph) in the timed loop")
