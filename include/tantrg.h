@@ -237,12 +237,11 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* dev_L, const double* dev
  * W2[b][so2][si2][c] R[y][c][y'], the MPO tensors acting on the ket index
  * sigma of s = 4 sigma + sigma'.  Device pointers, row-major FP64:
  * L[Dl][DH][Dl], W1 and W2 [DH][4][4][DH], C and out [Dl][16][16][Dr],
- * R[Dr][DH][Dr]; out must not alias an input.  Computed as one grouped GEMM
- * for R2 = W2.R (FP64), then the one-site apply on C with a right bond of
- * 16 Dr in the given precision (TT_FP64 ...).  Enqueued on `stream` (NULL: the
- * library's stream), no synchronisation; tt_heff_last_timing reports the
- * one-site part.  TT_EINVAL for non-positive sizes, null pointers or a
- * problem above 4e9 elements. */
+ * R[Dr][DH][Dr]; out must not alias an input.  Four grouped GEMMs in the
+ * order L.C, W1, W2, .R (the ancilla indices ride along), in the given
+ * precision (TT_FP64 ...).  Enqueued on `stream` (NULL: the library's stream),
+ * no synchronisation.  TT_EINVAL for non-positive sizes, null pointers or an
+ * intermediate above 4e9 elements. */
 int tt_heff2_apply(int Dl, int Dr, int DH, const double* L, const double* W1, const double* W2,
                    const double* C, const double* R, double* out, int precision, void* stream);
 

@@ -1165,61 +1165,110 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   c.Dl = Dl; c.Dr = Dr; c.DH = DH;
 }
 
-// The two-site generator H^(2) C of 2-TDVP on dense operands: the ket MPO
-// tensor W2 of the second site and R form one right environment
-// R2[(s2o, y2)][b][(s2i, y)] = sum_c W2[b, so, si, c] delta(ao, ai) R[y2, c, y]
-// (s = 4 sigma + sigma'), so that H^(2) C is the one-site apply with W1 and R2
-// on C read as A[x][s1][(s2, y)] (right bond 16 Dr).  R2 is one grouped GEMM
-// per (y2, ancilla): rows (b, so, si), columns y, depth c.
+// The two-site generator H^(2) C of 2-TDVP on dense operands, in the order
+// L.C, then W1, then W2, then R, as four grouped GEMMs.  The ancilla index of
+// each site (sigma' in s = 4 sigma + sigma') rides along in the column index of
+// the W stages, so no stage multiplies by the identity on it.  Layouts:
+//   T1[(x', a)][(s1, s2, y)]                       = L . C
+//   T2[x'][so1][b][(a1, s2, y)]                    = W1 stage, one GEMM per x'
+//   T3[x'][so1][a1][so2][c][(a2, y)] (T1's buffer) = W2 stage, one GEMM per (x', so1, a1)
+//   out[x'][4 so1 + a1][4 so2 + a2][y2]            = T3 . R
 struct Heff2Cache {
   int Dl = -1, Dr = -1, DH = -1;
   SiteTables tabs;
-  GemmPlan rg;
-  double* R2 = nullptr;
-  long long r2 = 0;
+  GemmPlan st[4];
+  double *T1 = nullptr, *T2 = nullptr, *pws = nullptr;
+  long long t = 0, pw = 0;
 };
 Heff2Cache g_heff2;
 
 void build_heff2_cache(int Dl, int Dr, int DH) {
   Heff2Cache& c = g_heff2;
-  free_plan(c.rg);
+  for (auto& p : c.st) free_plan(p);
   dfree(c.tabs.dev);
   c.tabs = SiteTables();
-  const long long Dr16 = 16LL * Dr;
-  std::vector<long long> rows[4];
-  for (int ap = 0; ap < 4; ++ap)
-    for (int b = 0; b < DH; ++b)
-      for (int so = 0; so < 4; ++so)
-        for (int si = 0; si < 4; ++si)
-          rows[ap].push_back(((long long)(4 * so + ap) * Dr * DH + b) * Dr16 + (long long)(4 * si + ap) * Dr);
-  long long tab[4];
-  for (int ap = 0; ap < 4; ++ap) tab[ap] = c.tabs.add(rows[ap]);
-  c.rg = GemmPlan();
-  c.rg.tag = TAG_WGEMM;
-  for (int y2 = 0; y2 < Dr; ++y2)
-    for (int ap = 0; ap < 4; ++ap) {
-      GemmProb g{};
-      g.M = 16 * DH; g.N = Dr; g.K = DH;
-      g.ia = 0; g.ib = 1; g.ic = 2;
-      g.sam = DH; g.sak = 1; g.tam = -1; g.tak = -1;
-      g.offB = (long long)y2 * DH * Dr; g.sbk = Dr; g.sbn = 1; g.tbk = -1; g.tbn = -1;
-      g.offC = (long long)y2 * DH * Dr16; g.tcm = tab[ap];
-      g.alpha = 1.0; g.beta = 0.0;
-      c.rg.probs.push_back(g);
-      c.rg.flops += 2.0 * g.M * (double)g.N * g.K;
-    }
-  const long long r2 = Dr16 * DH * Dr16;
-  tile_plan(c.rg, &c.tabs.host);
+  const long long D64 = 64LL * Dr, D256 = 256LL * Dr, D4 = 4LL * Dr;
+  const long long tsize = (long long)Dl * DH * D256;
+  // W[(so, b)][(a, si)] = W[a][so][si][b]: row and depth tables
+  std::vector<long long> wr, wk;
+  for (int so = 0; so < 4; ++so)
+    for (int b = 0; b < DH; ++b) wr.push_back((long long)so * 4 * DH + b);
+  for (int a = 0; a < DH; ++a)
+    for (int si = 0; si < 4; ++si) wk.push_back((long long)a * 16 * DH + (long long)si * DH);
+  std::vector<long long> t1k, t2k, t3k, t3r, outr;
+  for (int a = 0; a < DH; ++a)
+    for (int si = 0; si < 4; ++si) t1k.push_back(a * D256 + si * D64);
+  for (int b = 0; b < DH; ++b)
+    for (int si = 0; si < 4; ++si) t2k.push_back(b * D64 + si * D4);
+  for (int cc = 0; cc < DH; ++cc)
+    for (int y = 0; y < Dr; ++y) t3k.push_back(cc * D4 + y);
+  for (int x = 0; x < Dl; ++x)
+    for (int so1 = 0; so1 < 4; ++so1)
+      for (int a1 = 0; a1 < 4; ++a1)
+        for (int so2 = 0; so2 < 4; ++so2)
+          for (int a2 = 0; a2 < 4; ++a2) {
+            t3r.push_back((((long long)x * 4 + so1) * 4 + a1) * 16 * DH * Dr + (long long)so2 * DH * D4 + (long long)a2 * Dr);
+            outr.push_back((((long long)x * 16 + 4 * so1 + a1) * 16 + 4 * so2 + a2) * Dr);
+          }
+  const long long twr = c.tabs.add(wr), twk = c.tabs.add(wk), tt1k = c.tabs.add(t1k), tt2k = c.tabs.add(t2k),
+                  tt3k = c.tabs.add(t3k), tt3r = c.tabs.add(t3r), tout = c.tabs.add(outr);
+  auto prob = [](int M, int N, int K) {
+    GemmProb g{};
+    g.M = M; g.N = N; g.K = K;
+    g.ia = 0; g.ib = 1; g.ic = 2;
+    g.tam = g.tak = g.tbk = g.tbn = g.tcm = -1;
+    g.alpha = 1.0; g.beta = 0.0;
+    return g;
+  };
+  for (auto& p : c.st) { p = GemmPlan(); p.tag = TAG_WGEMM; p.wave_ok = true; }
+  {  // L . C
+    GemmProb g = prob(Dl * DH, (int)D256, Dl);
+    g.sam = Dl; g.sak = 1; g.sbk = D256; g.sbn = 1; g.scm = D256;
+    c.st[0].probs.push_back(g);
+  }
+  for (int x = 0; x < Dl; ++x) {  // W1 stage
+    GemmProb g = prob(4 * DH, (int)D64, 4 * DH);
+    g.tam = twr; g.tak = twk;
+    g.offB = (long long)x * DH * D256; g.tbk = tt1k; g.sbn = 1;
+    g.offC = (long long)x * 4 * DH * D64; g.scm = D64;
+    c.st[1].probs.push_back(g);
+  }
+  for (int x = 0; x < Dl; ++x)  // W2 stage
+    for (int so1 = 0; so1 < 4; ++so1)
+      for (int a1 = 0; a1 < 4; ++a1) {
+        GemmProb g = prob(4 * DH, (int)D4, 4 * DH);
+        g.tam = twr; g.tak = twk;
+        g.offB = ((long long)x * 4 + so1) * DH * D64 + a1 * 16LL * Dr; g.tbk = tt2k; g.sbn = 1;
+        g.offC = (((long long)x * 4 + so1) * 4 + a1) * 4 * DH * D4; g.scm = D4;
+        c.st[2].probs.push_back(g);
+      }
+  {  // . R
+    GemmProb g = prob(256 * Dl, Dr, DH * Dr);
+    g.tam = tt3r; g.tak = tt3k; g.sbk = 1; g.sbn = (long long)DH * Dr; g.tcm = tout;
+    c.st[3].probs.push_back(g);
+  }
+  for (auto& p : c.st)
+    for (auto& g : p.probs) p.flops += 2.0 * g.M * (double)g.N * g.K;
+  const long long sizes[4][kSlots] = {{(long long)Dl * DH * Dl, (long long)Dl * D256, tsize, 0},
+                                      {(long long)DH * 16 * DH, tsize, tsize, 0},
+                                      {(long long)DH * 16 * DH, tsize, tsize, 0},
+                                      {tsize, (long long)Dr * DH * Dr, (long long)Dl * D256, 0}};
   std::string rep;
-  long long sizes[kSlots] = {(long long)DH * 16 * DH, (long long)Dr * DH * Dr, r2, 0};
-  TT_REQUIRE(check_gemm(c.rg, c.tabs.host, sizes, "heff2 R2", rep) == 0, TT_EINVAL, "heff2 plan out of bounds: " + rep);
+  long long bad = 0, pw = 1;
+  for (int i = 0; i < 4; ++i) {
+    tile_plan(c.st[i], &c.tabs.host);
+    bad += check_gemm(c.st[i], c.tabs.host, sizes[i], "heff2", rep);
+    pw = std::max(pw, c.st[i].pws_size);
+  }
+  TT_REQUIRE(bad == 0, TT_EINVAL, "heff2 plan out of bounds: " + rep);
   hipStream_t st = ST();
   c.tabs.dev = upload(c.tabs.host, st);
-  upload_plan(c.rg, &c.tabs.host, st);
-  if (r2 > c.r2) { dfree(c.R2); c.R2 = (double*)dalloc(8 * r2); c.r2 = r2; }
-  // the GEMM writes the entries with equal ancilla indices only; the others
-  // are zero (delta(ao, ai)) and stay so while the layout is kept
-  launch_fill(c.R2, 0.0, r2, st);
+  for (auto& p : c.st) upload_plan(p, &c.tabs.host, st);
+  if (tsize > c.t) {
+    dfree(c.T1); dfree(c.T2);
+    c.T1 = (double*)dalloc(8 * tsize); c.T2 = (double*)dalloc(8 * tsize); c.t = tsize;
+  }
+  if (pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * pw); c.pw = pw; }
   c.Dl = Dl; c.Dr = Dr; c.DH = DH;
 }
 
@@ -1647,29 +1696,22 @@ int tt_heff2_apply(int Dl, int Dr, int DH, const double* L, const double* W1, co
   TT_REQUIRE(Dl >= 1 && Dr >= 1 && DH >= 1, TT_EINVAL, "dimensions must be positive");
   TT_REQUIRE(L && W1 && W2 && C && R && out, TT_EINVAL, "null device pointer");
   TT_REQUIRE(precision >= TT_FP64 && precision <= TT_BF16X6, TT_EINVAL, "unknown precision");
-  TT_REQUIRE((double)Dl * DH * 256 * Dr < 4.0e9 && 256.0 * Dr * Dr * DH < 4.0e9, TT_EINVAL, "problem too large");
+  TT_REQUIRE((double)Dl * DH * 256 * Dr < 4.0e9, TT_EINVAL, "problem too large");
   hipStream_t saved = g_stream;
   if (stream) g_stream = (hipStream_t)stream;
   try {
     if (g_heff2.Dl != Dl || g_heff2.Dr != Dr || g_heff2.DH != DH) build_heff2_cache(Dl, Dr, DH);
-    if (g_heff.Dl != Dl || g_heff.Dr != 16 * Dr || g_heff.DH != DH) build_heff_cache(Dl, 16 * Dr, DH);
-    Heff2Cache& c2 = g_heff2;
-    HeffCache& c = g_heff;
-    if (c2.rg.pws_size > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * c2.rg.pws_size); c.pw = c2.rg.pws_size; }
+    Heff2Cache& c = g_heff2;
     hipStream_t st = ST();
-    // R2 = W2.R is formed in FP64 in every mode (one contraction per two-site step)
-    launch_gemm(c2.rg, c2.tabs.dev, one(Slots{{const_cast<double*>(W2), const_cast<double*>(R), c2.R2, nullptr}}), 1,
-                TT_FP64, one(c.pws), st);
-    HIPX(hipEventRecord(c.ev[0], st));
-    launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(C), c.T1, nullptr}}), 1,
-                precision, one(c.pws), st);
-    HIPX(hipEventRecord(c.ev[1], st));
-    launch_gemm(c.wg, c.tabs.dev, one(Slots{{const_cast<double*>(W1), c.T1, c.T2, nullptr}}), 1, precision, one(c.pws),
-                st);
-    HIPX(hipEventRecord(c.ev[2], st));
-    launch_gemm(c.plan.s3, c.tabs.dev, one(Slots{{c.T2, c2.R2, out, nullptr}}), 1, precision, one(c.pws), st);
-    HIPX(hipEventRecord(c.ev[3], st));
-    c.timed = true;
+    double* l = const_cast<double*>(L);
+    double* w1 = const_cast<double*>(W1);
+    double* w2 = const_cast<double*>(W2);
+    double* a = const_cast<double*>(C);
+    double* r = const_cast<double*>(R);
+    launch_gemm(c.st[0], c.tabs.dev, one(Slots{{l, a, c.T1, nullptr}}), 1, precision, one(c.pws), st);
+    launch_gemm(c.st[1], c.tabs.dev, one(Slots{{w1, c.T1, c.T2, nullptr}}), 1, precision, one(c.pws), st);
+    launch_gemm(c.st[2], c.tabs.dev, one(Slots{{w2, c.T2, c.T1, nullptr}}), 1, precision, one(c.pws), st);
+    launch_gemm(c.st[3], c.tabs.dev, one(Slots{{c.T1, r, out, nullptr}}), 1, precision, one(c.pws), st);
   } catch (...) {
     g_stream = saved;
     throw;
