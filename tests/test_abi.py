@@ -165,3 +165,13 @@ def test_settn_rejects_bad_orders():
     for order in (0, 5):
         with pytest.raises(T.TTError):
             T.tt_model_bond_sectors(m, T.options(D=16, taylor_order=order), 1)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    # no fallback: with the shared library absent every call raises
+    monkeypatch.setattr(T, "_lib", None)
+    monkeypatch.setattr(T, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libtantrg.so"))
+    with pytest.raises(RuntimeError):
+        T.lib()
+    with pytest.raises(RuntimeError):
+        T.mpo_init_highT(_m(), T.options())
