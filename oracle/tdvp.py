@@ -256,6 +256,54 @@ class State:
             self._site_exp(k - 1, -tau, K, tol)
         self.beta += dbeta
 
+    # ------------------------------------------------------------ 2-TDVP
+    def _pair_exp(self, k, t, K, tol):
+        """C = A_k A_{k+1} <- exp(t H^(2)) C (normalised into Lambda)."""
+        C = np.tensordot(self.A[k], self.A[k + 1], axes=([3], [0]))     # x so1 si1 so2 si2 y
+        L, R = self.Lenv[k], self.Renv[k + 2]
+        W1, W2 = self.W[k], self.W[k + 1]
+        out, info = lanczos_expm(lambda x: heff2(L, W1, W2, R, x), C, t, K, tol)
+        self.max_krylov_err = max(self.max_krylov_err, info["err"])
+        return self._normalise(out)
+
+    @staticmethod
+    def _split(C, D_max, cutoff, left_orth):
+        """SVD of C reshaped (D_k 16) x (16 D_{k+2}), truncated to the largest
+        singular values: at most D_max of them, each above cutoff x the
+        largest.  left_orth: (U, S V^+), else (U S, V^+)."""
+        Dl, Dr = C.shape[0], C.shape[5]
+        U, s, Vh = np.linalg.svd(C.reshape(Dl * 16, 16 * Dr), full_matrices=False)
+        r = int(np.sum(s > cutoff * s[0])) if cutoff > 0 else len(s)
+        r = max(1, min(r, D_max))
+        U, s, Vh = U[:, :r], s[:r], Vh[:r]
+        if left_orth:
+            return U.reshape(Dl, 4, 4, r), (s[:, None] * Vh).reshape(r, 4, 4, Dr)
+        return (U * s).reshape(Dl, 4, 4, r), Vh.reshape(r, 4, 4, Dr)
+
+    def sweep2(self, dbeta, D_max, cutoff=0.0, K=8, tol=1e-13):
+        """One symmetric 2-TDVP step beta -> beta + dbeta (SM Sec. "2-TDVP in
+        the initial stage", Eq. S-2TDVP): left to right over the pairs
+        (k, k+1), C_k <- exp(-tau H^(2)) C_k, an SVD split that grows or
+        truncates the bond (at most D_max states, each above cutoff x the
+        largest singular value), then the backward one-site step
+        A_{k+1} <- exp(+tau H^(1)) A_{k+1}; the two exponentials of the last
+        pair merged into one with 2 tau; right to left mirrored.  Bond
+        dimensions change: the state carries no charge layouts here."""
+        assert self.centre == 0 and self.layouts is None
+        N, tau = self.N, 0.5 * dbeta
+        for k in range(N - 2):                       # left to right
+            C = self._pair_exp(k, -tau, K, tol)
+            self.A[k], self.A[k + 1] = self._split(C, D_max, cutoff, True)
+            self.Lenv[k + 1] = env_left(self.Lenv[k], self.A[k], self.W[k])
+            self._site_exp(k + 1, +tau, K, tol)
+        for k in range(N - 2, -1, -1):               # right to left, merged turn first
+            C = self._pair_exp(k, -2.0 * tau if k == N - 2 else -tau, K, tol)
+            self.A[k], self.A[k + 1] = self._split(C, D_max, cutoff, False)
+            self.Renv[k + 1] = env_right(self.Renv[k + 2], self.A[k + 1], self.W[k + 1])
+            if k > 0:
+                self._site_exp(k, +tau, K, tol)
+        self.beta += dbeta
+
     # ------------------------------------------------------------ observables
     def energy(self):
         """<<rho|H (x) 1|rho>>/<<rho|rho>> from the normalised centre (site 0)."""
