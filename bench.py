@@ -67,8 +67,9 @@ def cpu_baseline(D, DH):
 
 def green_map(args, T, WL):
     """beta G(k, beta/2) (main text, Fermi-surface paragraph) on the 10x10 open
-    square at U = 8, mu = 2, T = 2: linear start at beta0 = 2^-20, doubling
-    grid to beta = 1/4 (beta_phys = 1/2), then G on kx, ky in {0, pi/5, ..., pi}."""
+    square at U = 8, mu = 2 and temperature T: linear start at beta0 = 2^-20,
+    doubling grid up to beta = 1/4 (or to 1/(2T) if that is lower), linear
+    steps of 0.05 in beta to 1/(2T), then G on kx, ky in {0, pi/5, ..., pi}."""
     c = WL.MODELS["os10x10"]
     D = args.D or c["D"]
     b0 = 2.0 ** -20
@@ -77,10 +78,17 @@ def green_map(args, T, WL):
     st = T.State.init(m, T.options(D=D, symmetry=1, beta0=b0, pad_eps=1e-3, seed=1, krylov_dim=c["krylov"]))
     t_init = time.perf_counter() - t0
     b, nsw = b0, 0
+    b_end = 0.5 / args.green_map_T
     t0 = time.perf_counter()
-    while b < 0.25:
+    while 2.0 * b <= min(0.25, b_end) * (1 + 1e-12):
         st.sweep(b)
         b *= 2.0
+        nsw += 1
+        print("green map: beta %.3g" % b, file=sys.stderr, flush=True)
+    while b < b_end - 1e-12:
+        db = min(0.05, b_end - b)
+        st.sweep(db)
+        b += db
         nsw += 1
         print("green map: beta %.3g" % b, file=sys.stderr, flush=True)
     t_sweeps = time.perf_counter() - t0
@@ -131,7 +139,8 @@ def main():
     ap.add_argument("--mu-scan-D", type=int, default=0, help="override the mu-scan bond dimension")
     ap.add_argument("--green-map", action="store_true",
                     help="instead of the headline: beta G(k, beta/2) over a k grid on the 10x10 open square "
-                         "(U=8, mu=2, T=2, D=4000), one JSON line")
+                         "(U=8, mu=2, D=4000), one JSON line")
+    ap.add_argument("--green-map-T", type=float, default=2.0, help="temperature of --green-map (T = 1/beta_phys)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (--gpus 1); the sweep has no multi-GPU path", file=sys.stderr)
