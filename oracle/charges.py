@@ -62,6 +62,17 @@ def s_charge(s):
 S_CHARGES = [s_charge(s) for s in range(16)]
 
 
+def project(q, mode):
+    """A (q_up, q_dn) charge in the block structure of ``mode``: "u1u1" keeps
+    both U(1) charges; "sz" keeps only q_up - q_dn (as (sz, 0)), the one left
+    when a pairing field breaks the particle numbers."""
+    return tuple(q) if mode == "u1u1" else (q[0] - q[1], 0)
+
+
+def s_charges(mode):
+    return [project(c, mode) for c in S_CHARGES]
+
+
 def splitmix64(x):
     z = x & MASK
     z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
@@ -82,10 +93,17 @@ def noise_uniform(seed, site, flat):
     return 2.0 * u - 1.0
 
 
-def _dmax(N, k, q):
+def _dmax(N, k, q, mode="u1u1"):
+    """Number of super basis states of charge q on the k sites left of the
+    bond (or the N - k right of it, whichever is smaller): per site the
+    super charge of (n_up, n_dn) is a difference of two local values, so k
+    sites give comb(2k, k + a) comb(2k, k + b); with the Sz charge alone,
+    comb(4k, 2k + a)."""
     a, b = q
     m = N - k
     def cnt(n):
+        if mode == "sz":
+            return comb(4 * n, 2 * n + a) if abs(a) <= 2 * n else 0
         if abs(a) > n or abs(b) > n:
             return 0
         return comb(2 * n, n + a) * comb(2 * n, n + b)
@@ -105,14 +123,19 @@ def _share(D, qs, w):
     return base
 
 
-def allocate_sectors(N, D, n0, sector_cap=0):
+def allocate_sectors(N, D, n0, sector_cap=0, mode="u1u1"):
     """Sector dimensions per bond.  n0[k] maps charge -> number of rho0
-    states.  Returns a list over bonds 0..N of dicts {q: dim} (nonzero)."""
+    states.  Returns a list over bonds 0..N of dicts {q: dim} (nonzero).
+    mode "sz": charges (sz, 0) of the Sz-only block structure."""
     dims = [{(0, 0): 1}]
+    sc = s_charges(mode)
     for k in range(1, N):
         h = min(k, N - k)
-        qs = [(a, b) for a in range(-h, h + 1) for b in range(-h, h + 1)]
-        dmax = {q: _dmax(N, k, q) for q in qs}
+        if mode == "sz":
+            qs = [(a, 0) for a in range(-2 * h, 2 * h + 1)]
+        else:
+            qs = [(a, b) for a in range(-h, h + 1) for b in range(-h, h + 1)]
+        dmax = {q: _dmax(N, k, q, mode) for q in qs}
         if sum(dmax.values()) <= D:
             d = dict(dmax)
         else:
@@ -120,8 +143,11 @@ def allocate_sectors(N, D, n0, sector_cap=0):
             w = {}
             for q in qs:
                 a, b = q
-                w[q] = (comb(2 * hw, hw + a) * comb(2 * hw, hw + b)
-                        if abs(a) <= hw and abs(b) <= hw else 0)
+                if mode == "sz":
+                    w[q] = comb(4 * hw, 2 * hw + a) if abs(a) <= 2 * hw else 0
+                else:
+                    w[q] = (comb(2 * hw, hw + a) * comb(2 * hw, hw + b)
+                            if abs(a) <= hw and abs(b) <= hw else 0)
             cap = {q: dmax[q] if sector_cap <= 0 else min(dmax[q], sector_cap) for q in qs}
             fixed = {}
             while True:
@@ -143,14 +169,14 @@ def allocate_sectors(N, D, n0, sector_cap=0):
         for k in range(1, N):
             for q in list(dims[k]):
                 rows = sum(dims[k - 1].get((q[0] - c[0], q[1] - c[1]), 0)
-                           for c in S_CHARGES)
+                           for c in sc)
                 if dims[k][q] > rows:
                     dims[k][q] = rows
                     changed = True
         for k in range(N - 1, 0, -1):
             for q in list(dims[k]):
                 cols = sum(dims[k + 1].get((q[0] + c[0], q[1] + c[1]), 0)
-                           for c in S_CHARGES)
+                           for c in sc)
                 if dims[k][q] > cols:
                     dims[k][q] = cols
                     changed = True
@@ -172,17 +198,19 @@ class BondLayout:
         return len(self.charges)
 
 
-def bond_layouts(rho0_charges, N, D, symmetric, sector_cap=0):
-    """Layouts of bonds 0..N.  rho0_charges[k] = charge per rho0 bond state."""
+def bond_layouts(rho0_charges, N, D, symmetric, sector_cap=0, mode="u1u1"):
+    """Layouts of bonds 0..N.  rho0_charges[k] = charge per rho0 bond state
+    (as (q_up, q_dn); projected onto the block structure of ``mode``)."""
     layouts = []
     if symmetric:
+        rho0_charges = [[project(q, mode) for q in qk] for qk in rho0_charges]
         n0 = []
         for k in range(N + 1):
             cnt = {}
             for q in rho0_charges[k]:
                 cnt[q] = cnt.get(q, 0) + 1
             n0.append(cnt)
-        dims = allocate_sectors(N, D, n0, sector_cap)
+        dims = allocate_sectors(N, D, n0, sector_cap, mode)
         for k in range(N + 1):
             secs = sorted(dims[k])
             off, p = {}, 0
@@ -211,7 +239,7 @@ def bond_layouts(rho0_charges, N, D, symmetric, sector_cap=0):
     return layouts
 
 
-def padded_rho0(A0, layouts, symmetric, pad_eps, seed):
+def padded_rho0(A0, layouts, symmetric, pad_eps, seed, mode="u1u1"):
     """Embed rho0 tensors into the padded bonds and add the seeded noise."""
     out = []
     for k, a in enumerate(A0):
@@ -227,7 +255,7 @@ def padded_rho0(A0, layouts, symmetric, pad_eps, seed):
             if symmetric:
                 ql = np.array(Ll.charges)
                 qr = np.array(Lr.charges)
-                sc = np.array(S_CHARGES)
+                sc = np.array(s_charges(mode))
                 ok = ((ql[x, 0] + sc[s, 0] == qr[y, 0]) &
                       (ql[x, 1] + sc[s, 1] == qr[y, 1]))
                 mask &= ok

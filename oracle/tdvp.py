@@ -172,6 +172,7 @@ class State:
         self.Renv = [None] * (self.N + 1)
         self.max_krylov_err = 0.0
         self.layouts = None          # charge layouts of the bonds (symmetric runs)
+        self.mode = "u1u1"           # their block structure (charges.project)
 
     def dims(self):
         return [self.A[0].shape[0]] + [a.shape[3] for a in self.A]
@@ -182,9 +183,9 @@ class State:
         M = self.A[k].reshape(Dl * 16, Dr)
         if self.layouts is None:
             return qr_pos(M)
-        from .charges import S_CHARGES
+        from .charges import s_charges
         ql, qr = self.layouts[k].charges, self.layouts[k + 1].charges
-        row_q = [(a[0] + c[0], a[1] + c[1]) for a in ql for c in S_CHARGES]
+        row_q = [(a[0] + c[0], a[1] + c[1]) for a in ql for c in s_charges(self.mode)]
         return qr_pos_blocked(M, row_q, qr)
 
     def _lq(self, k):
@@ -193,9 +194,9 @@ class State:
         M = self.A[k].reshape(Dl, 16 * Dr)
         if self.layouts is None:
             return lq_pos(M)
-        from .charges import S_CHARGES
+        from .charges import s_charges
         ql, qr = self.layouts[k].charges, self.layouts[k + 1].charges
-        col_q = [(b[0] - c[0], b[1] - c[1]) for c in S_CHARGES for b in qr]
+        col_q = [(b[0] - c[0], b[1] - c[1]) for c in s_charges(self.mode) for b in qr]
         return lq_pos_blocked(M, ql, col_q)
 
     def canonicalise(self):
@@ -361,7 +362,7 @@ class State:
 
 
 # ---------------------------------------------------------------- start state
-def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0, sector_cap=0, taylor_order=1):
+def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0, sector_cap=0, taylor_order=1, mode="u1u1"):
     """rho0 = 1 - beta0 H (main text, noninteracting-benchmark paragraph), or
     for taylor_order > 1 the SETTN start sum_{n <= order} (-beta0 H)^n / n!
     (SM I.E, ``oracle.mpo.settn_rho0``), padded to bond D as described in
@@ -377,10 +378,11 @@ def initial_state(mpo_model, beta0, D, symmetric, pad_eps=0.0, seed=0, sector_ca
         A0, rho0_q = _mpo.settn_rho0(mpo_model, beta0, taylor_order)
         rho0_q = list(rho0_q)
     rho0_q.append([(0, 0)])            # bond N of rho0 after the boundary vector
-    layouts = charges.bond_layouts(rho0_q, N, D, symmetric, sector_cap)
-    A = charges.padded_rho0(A0, layouts, symmetric, pad_eps, seed)
+    layouts = charges.bond_layouts(rho0_q, N, D, symmetric, sector_cap, mode)
+    A = charges.padded_rho0(A0, layouts, symmetric, pad_eps, seed, mode)
     st = State(A, mpo_model.mpo_for_env(), beta0)
     if symmetric:
         st.layouts = layouts
+        st.mode = mode
     st.canonicalise()
     return st

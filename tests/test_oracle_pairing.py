@@ -62,3 +62,34 @@ def test_oracle_flow_exact_at_maximal_bond(W, L, geo, U, mu, hp):
     assert abs(o["lnZ"] - lnZ) <= 1e-10 * abs(lnZ)
     assert abs(o["E"] - E) <= 1e-10 * max(abs(E), 1e-2)
     assert abs(got - dp) <= 1e-10
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,hp", [(1, 4, lattice.CHAIN, 4.0, 0.3, 0.3), (2, 2, lattice.OPEN_SQUARE, 8.0, 1.5, 0.5)])
+def test_sz_block_structure_flow_exact_at_maximal_bond(W, L, geo, U, mu, hp):
+    # the pairing field conserves q_up - q_dn: blocks by that charge alone
+    # (charges (sz, 0)) hold the flow exactly at untruncated bonds
+    m = mpo.HubbardMPO(W, L, geo, 1.0, U, mu, hp=hp)
+    st = tdvp.initial_state(m, 0.01, 16 ** 8, True, mode="sz")
+    assert all(q[1] == 0 for lay in st.layouts for q in lay.charges)
+    for _ in range(6):
+        st.sweep(0.05)
+    lnZ, E, dp = ed.same_ode_bilayer_pairing(ed.Hubbard(W, L, geo, 1.0, U, mu), hp, 0.01, st.beta)
+    o = st.observables()
+    nb = len(ed.pairing_bonds(W, L, geo))
+    got = st.expectation(mpo.HubbardMPO(W, L, geo, 0.0, 0.0, 0.0, hp=-1.0).mpo_for_env()) / nb
+    assert abs(o["lnZ"] - lnZ) <= 1e-10 * abs(lnZ)
+    assert abs(o["E"] - E) <= 1e-10 * max(abs(E), 1e-2)
+    assert abs(got - dp) <= 1e-10
+
+
+def test_sz_sector_counts():
+    # the Sz-only counts are the sums of the U(1)xU(1) counts over q_up - q_dn
+    from oracle import charges
+    for N, k in [(6, 2), (8, 3), (10, 5)]:
+        h = min(k, N - k)
+        for a in range(-2 * h, 2 * h + 1):
+            left = sum(charges.comb(2 * k, k + u) * charges.comb(2 * k, k + u - a)
+                       for u in range(-k, k + 1) if abs(u - a) <= k)
+            right = sum(charges.comb(2 * (N - k), N - k + u) * charges.comb(2 * (N - k), N - k + u - a)
+                        for u in range(-(N - k), N - k + 1) if abs(u - a) <= N - k)
+            assert charges._dmax(N, k, (a, 0), "sz") == min(left, right)
