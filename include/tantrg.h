@@ -64,8 +64,8 @@ typedef struct tt_state tt_state;
  * channels (larger D_H).  hp != 0 adds the d-wave pairing field of the main
  * text's pairing paragraph, -hp sum_<ij> s_ij (Delta_ij + Delta_ij^+)/2 with
  * Delta_ij = (c_i,dn c_j,up - c_i,up c_j,dn)/sqrt 2 and s_ij = +1 (-1) for a
- * bond along the length (across the width); it breaks the U(1) charges, so it
- * needs symmetry = 0 (TT_EINVAL otherwise). */
+ * bond along the length (across the width); it breaks the particle numbers,
+ * so it needs symmetry = 0 or 2 (TT_EINVAL otherwise). */
 typedef struct {
   int W, L;          /* width and length; chain: W = 1 */
   int geometry;      /* TT_CHAIN, TT_CYLINDER (wrap across W only for W >= 3), TT_OPEN_SQUARE */
@@ -75,7 +75,9 @@ typedef struct {
 
 typedef struct {
   int D;               /* target bond dimension (bonds never exceed the maximal one) */
-  int symmetry;        /* 0 dense, 1 U(1)charge x U(1)spin block-sparse */
+  int symmetry;        /* 0 dense, 1 U(1)charge x U(1)spin block-sparse, 2 block-sparse
+                          in q_up - q_dn alone (the charge a pairing field keeps;
+                          sectors reported as (sz, 0)) */
   double beta0;        /* rho0 = 1 - beta0 H (main text: high-temperature start) */
   int taylor_order;    /* 1: rho0 = 1 - beta0 H; 2..4: the SETTN start
                           sum_{n <= order} (-beta0 H)^n / n! (SM I.E), the
@@ -89,7 +91,7 @@ typedef struct {
   double pad_eps;      /* amplitude of the seeded padding noise (0: zero padding) */
   uint64_t seed;       /* SplitMix64 seed of the padding noise */
   int env_on_host;     /* must be 0 (not supported) */
-  int sector_cap;      /* largest U(1)xU(1) sector of a padded bond (0: no cap) */
+  int sector_cap;      /* largest sector of a padded block-sparse bond (0: no cap) */
 } tt_options;
 
 typedef struct {
@@ -187,8 +189,8 @@ int thermo_green_function(tt_state* s, double kx, double ky, double* host_G);
  * *host_delta = <Delta_tot> / N_p at beta_phys = 2 beta (bilayer), Delta_tot
  * as in tt_model with N_p nearest-neighbour bonds (*host_nbonds, may be NULL);
  * the susceptibility is chi_SC = Delta_p / hp.  Needs a state with
- * symmetry = 0 (TT_EINVAL otherwise: with the U(1) charges the value is 0 by
- * symmetry).  The first call builds the plans; FP64.  Synchronises. */
+ * symmetry = 0 or 2 (TT_EINVAL otherwise: with both U(1) charges the value is
+ * 0 by symmetry).  The first call builds the plans; FP64.  Synchronises. */
 int thermo_pairing_order(tt_state* s, double* host_delta, int* host_nbonds);
 
 /* Entropy and specific heat per site from n >= 3 bilayer observables taken

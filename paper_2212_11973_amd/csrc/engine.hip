@@ -424,7 +424,7 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   // environment MPO: bond 0 [start], bond N [done]; W_{N-1} contracted with the done selector
   s.qH.assign(N + 1, {});
   for (int k = 0; k < N; ++k)
-    for (int a = 0; a < s.mpo.DH[k]; ++a) s.qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : s.mpo.charge(k, a));
+    for (int a = 0; a < s.mpo.DH[k]; ++a) s.qH[k].push_back(project_charge(s.mpo.charge(k, a), s.opts.symmetry));
   s.qH[N] = {Q{0, 0}};
   // W_{N-1} contracted with the done selector
   auto env_tensors = [&](const Mpo& mpo) {
@@ -525,7 +525,6 @@ void alloc_state(tt_state& s) {
   // trace entries
   std::vector<TraceEntry> te;
   std::vector<int> start{0};
-  int diag_stride = (s.G.ng == 1) ? 5 : 1;
   for (int k = 0; k < N; ++k) {
     for (auto& e : s.plans[k].tr) {
       int l = (int)e[2], r = (int)e[3];
@@ -533,7 +532,8 @@ void alloc_state(tt_state& s) {
       t.src = e[0]; t.C = e[1];
       t.xoff = s.bonds[k].secs[l].off; t.dl = s.bonds[k].secs[l].dim;
       t.yoff = s.bonds[k + 1].secs[r].off; t.dr = s.bonds[k + 1].secs[r].dim;
-      t.site = k; t.diag_stride = diag_stride;
+      t.site = k;
+      for (int q = 0; q < 4; ++q) t.pos[q] = s.G.pos_of[5 * q];
       te.push_back(t);
     }
     start.push_back((int)te.size());
@@ -555,7 +555,7 @@ void fill_initial_tensors(tt_state& s, std::vector<std::vector<double>>& host) {
     n0[k].assign(s.bonds[k].secs.size(), 0);
     int nst = (int)r0.q[k].size();
     for (int a = 0; a < nst; ++a) {
-      Q q = (k == N || s.G.ng == 1) ? Q{0, 0} : r0.q[k][a];
+      Q q = k == N ? Q{0, 0} : project_charge(r0.q[k][a], s.opts.symmetry);
       int sec = s.bonds[k].find(q);
       TT_REQUIRE(sec >= 0 && n0[k][sec] < s.bonds[k].secs[sec].dim, TT_EINVAL, "rho0 does not fit the bond sectors");
       emb[k].push_back({sec, n0[k][sec]});
@@ -624,8 +624,8 @@ std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
   const int N = s.N;
   std::vector<std::map<Q, int>> n0(N + 1);
   for (int k = 0; k <= N; ++k)
-    for (const Q& q : s.rho0.q[k]) n0[k][q]++;
-  if (s.opts.symmetry) return allocate_sectors(N, s.opts.D, n0, s.opts.sector_cap);
+    for (const Q& q : s.rho0.q[k]) n0[k][project_charge(q, s.opts.symmetry)]++;
+  if (s.opts.symmetry) return allocate_sectors(N, s.opts.D, n0, s.opts.sector_cap, s.opts.symmetry);
   std::vector<std::map<Q, int>> d(N + 1);
   for (int k = 0; k <= N; ++k) {
     int n = (int)s.rho0.q[k].size();
@@ -638,7 +638,7 @@ std::vector<std::map<Q, int>> bond_dims(const tt_state& s) {
 
 void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(o.D >= 1, TT_EINVAL, "D must be positive");
-  TT_REQUIRE(o.symmetry == 0 || o.symmetry == 1, TT_EINVAL, "symmetry must be 0 or 1");
+  TT_REQUIRE(o.symmetry >= 0 && o.symmetry <= 2, TT_EINVAL, "symmetry must be 0, 1 or 2");
   TT_REQUIRE(o.taylor_order >= 1 && o.taylor_order <= 4, TT_EINVAL, "taylor_order must be in 1..4");
   TT_REQUIRE(o.krylov_dim >= 1 && o.krylov_dim <= kMaxKrylov, TT_EINVAL, "krylov_dim must be in 1..32");
   TT_REQUIRE(o.krylov_tol >= 0.0, TT_EINVAL, "krylov_tol must be >= 0");
@@ -648,8 +648,8 @@ void validate(const tt_model& m, const tt_options& o) {
   TT_REQUIRE(std::isfinite(o.beta0) && std::isfinite(o.pad_eps), TT_EINVAL, "beta0 and pad_eps must be finite");
   TT_REQUIRE(std::isfinite(m.t) && std::isfinite(m.tp) && std::isfinite(m.U) && std::isfinite(m.mu) &&
                  std::isfinite(m.hp), TT_EINVAL, "model parameters must be finite");
-  TT_REQUIRE(m.hp == 0.0 || o.symmetry == 0, TT_EINVAL,
-             "the pairing field breaks the U(1) charges: it needs symmetry = 0");
+  TT_REQUIRE(m.hp == 0.0 || o.symmetry != 1, TT_EINVAL,
+             "the pairing field breaks the U(1) charges: it needs symmetry = 0 or 2");
 }
 
 std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o, bool with_plans = true) {
@@ -661,7 +661,7 @@ std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o
   s->N = s->lat.N;
   s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu, m.hp);
   s->rho0 = make_rho0(s->mpo, o.beta0, o.taylor_order);
-  s->G = make_groups(o.symmetry == 1);
+  s->G = make_groups(o.symmetry);
   auto dims = bond_dims(*s);
   if (with_plans) {
     build_layouts(*s, dims);
@@ -846,12 +846,15 @@ long long check_all_plans(tt_state& s, std::string& rep) {
     bad += check_w(P.wr, P.y_size, P.z_size, "wr", rep);
     bad += check_qr(P.qr, T, ns, s.bmat[k + 1].size, "qr", rep);
     bad += check_qr(P.lq, T, ns, s.bmat[k].size, "lq", rep);
-    int ds = (s.G.ng == 1) ? 5 : 1;
+    int pmax = 0;
+    for (int q = 0; q < 4; ++q) pmax = std::max(pmax, s.G.pos_of[5 * q]);
     for (auto& e : P.tr) {
       int l = (int)e[2], r = (int)e[3];
       long long dl = s.bonds[k].secs[l].dim, dr = s.bonds[k + 1].secs[r].dim;
-      long long hi = e[0] + (dl - 1) * e[1] + 3LL * ds * dr + dr - 1;
+      long long hi = e[0] + (dl - 1) * e[1] + (long long)pmax * dr + dr - 1;
       if (hi >= ns) ++bad;
+      for (int q = 0; q < 4; ++q)
+        if (s.G.group_of[5 * q] != s.G.group_of[0]) ++bad;
     }
   }
   return bad;
@@ -878,7 +881,7 @@ constexpr int kObsPairing = 3000;                        // the d-wave pairing s
 std::vector<std::vector<Q>> obs_charges(const tt_state& s, const Mpo& m) {
   std::vector<std::vector<Q>> qH(s.N + 1);
   for (int k = 0; k < s.N; ++k)
-    for (int a = 0; a < m.DH[k]; ++a) qH[k].push_back(s.G.ng == 1 ? Q{0, 0} : m.charge(k, a));
+    for (int a = 0; a < m.DH[k]; ++a) qH[k].push_back(project_charge(m.charge(k, a), s.opts.symmetry));
   qH[s.N] = {Q{0, 0}};
   return qH;
 }
@@ -1118,7 +1121,7 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   Bond bl, br;
   bl.add({0, 0}, Dl);
   br.add({0, 0}, Dr);
-  Groups G = make_groups(false);
+  Groups G = make_groups(0);
   std::vector<Q> qh(DH, Q{0, 0});
   // the plan's W stage is replaced by a grouped GEMM reading W from device memory;
   // an all-zero W keeps the sparse W-stage plan empty
@@ -1470,7 +1473,7 @@ int thermo_green_function(tt_state* s, double kx, double ky, double* host_G) {
 int thermo_pairing_order(tt_state* s, double* host_delta, int* host_nbonds) {
   ABI_BEGIN
   TT_REQUIRE(s && host_delta, TT_EINVAL, "null argument");
-  TT_REQUIRE(s->G.ng == 1, TT_EINVAL, "thermo_pairing_order: needs a state with symmetry = 0");
+  TT_REQUIRE(s->opts.symmetry != 1, TT_EINVAL, "thermo_pairing_order: needs a state with symmetry = 0 or 2");
   const auto bonds = pairing_bonds(s->lat);
   TT_REQUIRE(!bonds.empty(), TT_EINVAL, "thermo_pairing_order: no bonds");
   auto it = s->obs.find(kObsPairing);
@@ -1627,7 +1630,7 @@ int tt_state_load(const char* path, tt_state** out) {
   s->lat = make_lattice(m.W, m.L, m.geometry);
   s->N = s->lat.N;
   s->mpo = make_hubbard_mpo(s->lat, m.t, m.tp, m.U, m.mu, m.hp);
-  s->G = make_groups(o.symmetry == 1);
+  s->G = make_groups(o.symmetry);
   std::vector<std::map<Q, int>> dims(s->N + 1);
   for (int k = 0; k <= s->N; ++k) {
     int ns = 0;

@@ -90,7 +90,8 @@ void launch_copy(BPtr<double> dst, BPtr<const double> src, long long n, int nb, 
 void launch_fill(double* dst, double val, long long n, hipStream_t st);
 void launch_dot_final(const double* part, int nparts, int nv, double* out, hipStream_t st);
 
-struct TraceEntry { long long src, C, xoff, dl, yoff, dr; int site, diag_stride; };
+// pos[q]: position of the diagonal super index s = 5q (sigma = sigma' = q) in its charge group
+struct TraceEntry { long long src, C, xoff, dl, yoff, dr; int site, pos[4]; };
 void launch_trace(const TraceEntry* d_entries, const int* d_site_start, int N, double* const* d_sites,
                   double* vbuf, long long vlen, double* out2, hipStream_t st);
 

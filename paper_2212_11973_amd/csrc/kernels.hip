@@ -1739,7 +1739,7 @@ __global__ __launch_bounds__(256) void k_trace(const TraceEntry* __restrict__ en
           if (vx == 0.0) continue;
           const double* row = A + E.src + x * E.C;
           double d = 0.0;
-          for (int q = 0; q < 4; ++q) d += row[(long long)q * E.diag_stride * E.dr + y];
+          for (int q = 0; q < 4; ++q) d += row[(long long)E.pos[q] * E.dr + y];
           s += vx * d;
         }
         w[E.yoff + y] += s;

@@ -548,8 +548,8 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
   finish_wplan(P.wr);
   finish_qrplan(P.qr);
   finish_qrplan(P.lq);
-  // ---------------- trace transfer: the group with delta = (0,0) holds the diagonal s = (sigma, sigma)
-  int g0 = (G.ng == 1) ? 0 : 4;
+  // ---------------- trace transfer: the group with zero charge holds the diagonal s = (sigma, sigma)
+  const int g0 = G.group_of[0];
   for (int l = 0; l < S.nl; ++l) {
     int r = S.rsec[l][g0];
     if (r < 0) continue;

@@ -232,11 +232,31 @@ Mpo make_hubbard_mpo(const Lattice& lat, double t, double tp, double U, double m
   return m;
 }
 
-Groups make_groups(bool symmetric) {
+Q project_charge(Q q, int mode) {
+  if (mode == 0) return {0, 0};
+  if (mode == 2) return {q.first - q.second, 0};
+  return q;
+}
+
+Groups make_groups(int mode) {
   Groups g;
   g.group_of.assign(16, 0);
   g.pos_of.assign(16, 0);
-  if (!symmetric) {
+  if (mode == 2) {   // Sz only: five groups by the super charge du - dd
+    g.ng = 5;
+    for (int sz = -2; sz <= 2; ++sz) g.delta.push_back({sz, 0});
+    g.s.resize(5);
+    for (int s = 0; s < 16; ++s) {
+      int sig = s / 4, sp = s % 4;
+      int du = (sig & 1) - (sp & 1), dd = (sig >> 1) - (sp >> 1);
+      int gi = du - dd + 2;
+      g.group_of[s] = gi;
+      g.pos_of[s] = (int)g.s[gi].size();
+      g.s[gi].push_back(s);
+    }
+    return g;
+  }
+  if (mode == 0) {
     g.ng = 1;
     g.delta = {{0, 0}};
     g.s.resize(1);
@@ -303,24 +323,35 @@ u128 count_side(int n, Q q) {
 }  // namespace
 
 std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0,
-                                               int sector_cap) {
+                                               int sector_cap, int mode) {
   std::vector<std::map<Q, int>> dims(N + 1);
   dims[0][{0, 0}] = 1;
   dims[N][{0, 0}] = 1;
+  const bool sz = mode == 2;
   std::vector<Q> sc;  // the 16 local super-index charges
   for (int s = 0; s < 16; ++s) {
     int sig = s / 4, sp = s % 4;
-    sc.push_back({(sig & 1) - (sp & 1), (sig >> 1) - (sp >> 1)});
+    sc.push_back(project_charge({(sig & 1) - (sp & 1), (sig >> 1) - (sp >> 1)}, mode));
   }
+  // super states of charge q on n sites: comb(2n, n + a) comb(2n, n + b), or
+  // comb(4n, 2n + a) with the Sz charge alone
+  auto count = [&](int n, Q q) -> u128 {
+    if (!sz) return count_side(n, q);
+    return std::abs(q.first) > 2 * n ? 0 : binom(4 * n, 2 * n + q.first);
+  };
   for (int k = 1; k < N; ++k) {
     int h = std::min(k, N - k);
     std::vector<Q> qs;
-    for (int a = -h; a <= h; ++a)
-      for (int b = -h; b <= h; ++b) qs.push_back({a, b});
+    if (sz) {
+      for (int a = -2 * h; a <= 2 * h; ++a) qs.push_back({a, 0});
+    } else {
+      for (int a = -h; a <= h; ++a)
+        for (int b = -h; b <= h; ++b) qs.push_back({a, b});
+    }
     std::map<Q, u128> dmax;
     u128 tot = 0;
     for (auto q : qs) {
-      u128 v = std::min(count_side(k, q), count_side(N - k, q));
+      u128 v = std::min(count(k, q), count(N - k, q));
       dmax[q] = v;
       tot = tot + v;
       if (tot > kSat) tot = kSat;
@@ -333,8 +364,11 @@ std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<s
       std::map<Q, u128> w, cap;
       for (auto q : qs) {
         u128 v = 0;
-        if (std::abs(q.first) <= hw && std::abs(q.second) <= hw)
+        if (sz) {
+          if (std::abs(q.first) <= 2 * hw) v = binom(4 * hw, 2 * hw + q.first);
+        } else if (std::abs(q.first) <= hw && std::abs(q.second) <= hw) {
           v = binom(2 * hw, hw + q.first) * binom(2 * hw, hw + q.second);
+        }
         w[q] = v;
         cap[q] = (sector_cap <= 0) ? dmax[q] : std::min(dmax[q], (u128)sector_cap);
       }

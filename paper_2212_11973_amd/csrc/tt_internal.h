@@ -74,13 +74,16 @@ struct Groups {
   std::vector<std::vector<int>> s;      // super indices s = 4*sigma + sigma' per group
   std::vector<int> group_of, pos_of;    // per s
 };
-Groups make_groups(bool symmetric);
+// block structure: 0 none (one sector), 1 U(1)charge x U(1)spin, 2 U(1) of
+// q_up - q_dn alone (charges (sz, 0))
+Groups make_groups(int mode);
+Q project_charge(Q q, int mode);
 
 uint64_t splitmix64(uint64_t x);
 double noise_uniform(uint64_t seed, int site, uint64_t flat);
 
 // sector dimensions of bonds 0..N for a target D (n0: rho0 states per charge)
 std::vector<std::map<Q, int>> allocate_sectors(int N, int D, const std::vector<std::map<Q, int>>& n0,
-                                               int sector_cap);
+                                               int sector_cap, int mode = 1);
 
 }  // namespace tt

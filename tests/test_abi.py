@@ -35,7 +35,7 @@ def _m(**kw):
 
 
 @pytest.mark.parametrize("field,value", [("precision", 7), ("krylov_dim", 0), ("krylov_dim", 33),
-                                         ("taylor_order", 5), ("symmetry", 2), ("D", 0),
+                                         ("taylor_order", 5), ("symmetry", 3), ("D", 0),
                                          ("env_on_host", 1), ("krylov_tol", -1.0)])
 def test_invalid_options_rejected_without_gpu(field, value):
     o = T.options(**{field: value})
@@ -175,3 +175,26 @@ def test_binding_fails_loudly_without_the_library(monkeypatch):
         T.lib()
     with pytest.raises(RuntimeError):
         T.mpo_init_highT(_m(), T.options())
+
+
+
+@pytest.mark.parametrize("W,L,geo,D,cap,hp", [(2, 3, 2, 40, 0, 0.1), (4, 4, 1, 64, 0, 0.2), (1, 6, 0, 30, 8, 0.0),
+                                              (4, 16, 1, 500, 64, 0.05), (3, 4, 2, 100, 5, 0.3)])
+def test_sz_sectors_match_oracle(W, L, geo, D, cap, hp):
+    # symmetry = 2: blocks by q_up - q_dn alone (sectors (sz, 0)), as the
+    # oracle allocates them for the pairing field
+    from oracle import charges, mpo
+    mm = mpo.HubbardMPO(W, L, geo, 1.0, 8.0, 1.0, hp=hp)
+    N = mm.N
+    q0 = [mm.bond_charges(k) for k in range(N)] + [[(0, 0)]]
+    lay = charges.bond_layouts(q0, N, D, True, cap, mode="sz")
+    m = T.model(W, L, geo, 1.0, 8.0, 1.0, hp=hp)
+    o = T.options(D=D, symmetry=2, sector_cap=cap)
+    bonds = range(N + 1) if N <= 16 else sorted({0, 1, 2, 3, 4, N // 2, N - 3, N - 1, N})
+    for k in bonds:
+        want = {}
+        for q in lay[k].charges:
+            want[q] = want.get(q, 0) + 1
+        assert dict(T.tt_model_bond_sectors(m, o, k)) == want, k
+    v, _, rep = T.tt_check_plans(m, o)
+    assert v == 0, rep

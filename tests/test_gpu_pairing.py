@@ -69,3 +69,56 @@ def test_pairing_matches_oracle_truncated(W, L, geo, U, mu, D, pad, hp):
     d, _ = st.pairing_order()
     assert abs(d - ref) <= TOL, (d, ref)
     st.free()
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,hp", [(1, 4, T.TT_CHAIN, 4.0, 0.3, 0.3), (2, 2, T.TT_OPEN_SQUARE, 8.0, 1.5, 0.5)])
+def test_pairing_sz_blocks_match_ed_untruncated(W, L, geo, U, mu, hp):
+    # symmetry = 2: blocks by q_up - q_dn alone, the charge the field keeps
+    print("pairing sz ed", W, L, geo, flush=True)
+    b0 = 0.01
+    h = ed.Hubbard(W, L, geo, 1.0, U, mu)
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu, hp=hp), T.options(D=256, symmetry=2, beta0=b0))
+    assert all(q[1] == 0 for q, _ in st.sectors(1))
+    for _ in range(6):
+        st.sweep(0.05)
+    o = st.observables()
+    lnZ, E, dp = ed.same_ode_bilayer_pairing(h, hp, b0, o["beta"])
+    assert _rel(o["lnZ"], lnZ) <= TOL and _rel(o["E"], E) <= TOL, (o["lnZ"], lnZ, o["E"], E)
+    assert abs(st.pairing_order()[0] - dp) <= TOL
+    st.free()
+
+
+@pytest.mark.parametrize("W,L,geo,U,mu,D,pad,hp", [(1, 6, T.TT_CHAIN, 4.0, 0.3, 16, 1e-3, 0.2),
+                                                   (2, 3, T.TT_OPEN_SQUARE, 8.0, 1.0, 24, 1e-3, 0.1)])
+def test_pairing_sz_blocks_match_oracle_truncated(W, L, geo, U, mu, D, pad, hp):
+    print("pairing sz oracle", W, L, geo, D, flush=True)
+    b0 = 0.01
+    mm = ompo.HubbardMPO(W, L, geo, 1.0, U, mu, hp=hp)
+    ost = otd.initial_state(mm, b0, D, True, pad_eps=pad, seed=11, sector_cap=64, mode="sz")
+    st = T.State.init(T.model(W, L, geo, 1.0, U, mu, hp=hp),
+                      T.options(D=D, symmetry=2, beta0=b0, pad_eps=pad, seed=11))
+    assert st.info()[1] == ost.dims()
+    for _ in range(2):
+        st.sweep(0.1)
+        ost.sweep(0.1)
+    o, r = st.observables(), ost.observables()
+    for key in ("lnZ", "E", "lnZ_single", "f"):
+        assert _rel(o[key], r[key]) <= TOL, (key, o[key], r[key])
+    nb = len(ed.pairing_bonds(W, L, geo))
+    ref = ost.expectation(ompo.HubbardMPO(W, L, geo, 0.0, 0.0, 0.0, hp=-1.0).mpo_for_env()) / nb
+    assert abs(st.pairing_order()[0] - ref) <= TOL
+    st.free()
+
+
+def test_full_size_cylinder_pairing_response():
+    # 4x16 cylinder at D = 2000 in the Sz block structure with a small field:
+    # the response chi_SC = Delta_p / hp is finite and positive
+    print("pairing 4x16", flush=True)
+    hp = 0.01
+    st = T.State.init(T.model(4, 16, T.TT_CYLINDER, 1.0, 8.0, 1.5, hp=hp),
+                      T.options(D=2000, symmetry=2, beta0=0.05 / 4096, pad_eps=1e-3, seed=1))
+    st.sweep(0.05)
+    d, nb = st.pairing_order()
+    assert nb == 124
+    assert 0.0 < d / hp < 10.0, d
+    st.free()
