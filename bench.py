@@ -111,6 +111,34 @@ def green_map(args, T, WL):
                       "seconds_per_k": t_g / len(grid)}))
 
 
+def pairing_scan(args, T):
+    """d-wave pairing response (main text, pairing paragraph; Fig. 5 workload):
+    chi_SC = <Delta_tot> / (N_p hp) on the 4x24 cylinder, U = 8, hp = 0.01,
+    T = 1 (beta_phys = 1), Sz blocks; linear start at 2^-20, doubling grid to
+    beta = 1/4, one linear step to 1/2."""
+    D = args.D or 2000
+    hp = 0.01
+    out = []
+    for mu in (4.0, 3.0, 2.0):
+        t0 = time.perf_counter()
+        st = T.State.init(T.model(4, 24, T.TT_CYLINDER, 1.0, 8.0, mu, hp=hp),
+                          T.options(D=D, symmetry=2, beta0=2.0 ** -20, pad_eps=1e-3, seed=1))
+        b = 2.0 ** -20
+        while 2.0 * b <= 0.25:
+            st.sweep(b)
+            b *= 2.0
+        st.sweep(0.25)
+        o = st.observables()
+        loc = st.local_observables()
+        d, nb = st.pairing_order()
+        out.append(dict(mu=mu, beta_phys=o["beta_phys"], n=loc["n"], delta_p=d, chi_sc=d / hp, e=o["e"],
+                        seconds=time.perf_counter() - t0))
+        print("pairing scan: mu %g done" % mu, file=sys.stderr, flush=True)
+        st.free()
+    print(json.dumps({"metric": "chi_SC = Delta_p / hp", "workload": "Hubbard 4x24 cylinder, U=8, hp=0.01, Sz blocks "
+                      "D=%d, T=1" % D, "points": out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +169,9 @@ def main():
                     help="instead of the headline: beta G(k, beta/2) over a k grid on the 10x10 open square "
                          "(U=8, mu=2, D=4000), one JSON line")
     ap.add_argument("--green-map-T", type=float, default=2.0, help="temperature of --green-map (T = 1/beta_phys)")
+    ap.add_argument("--pairing-scan", action="store_true",
+                    help="instead of the headline: chi_SC = Delta_p / hp on the 4x24 cylinder (U=8, hp=0.01, T=1, "
+                         "Sz blocks, D=--D or 2000) for a few mu, one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (--gpus 1); the sweep has no multi-GPU path", file=sys.stderr)
@@ -163,6 +194,9 @@ def main():
         del a, b
     if args.green_map:
         green_map(args, T, WL)
+        return
+    if args.pairing_scan:
+        pairing_scan(args, T)
         return
     c = WL.MODELS[args.workload]
     D = args.D or c["D"]
