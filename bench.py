@@ -69,13 +69,14 @@ def green_map(args, T, WL):
     """beta G(k, beta/2) (main text, Fermi-surface paragraph) on the 10x10 open
     square at U = 8, mu = 2 and temperature T: linear start at beta0 = 2^-20,
     doubling grid up to beta = 1/4 (or to 1/(2T) if that is lower), linear
-    steps of 0.05 in beta to 1/(2T), then G on kx, ky in {0, pi/5, ..., pi}."""
+    steps (0.05 in beta by default) to 1/(2T), then G on kx, ky in {0, pi/5, ..., pi}."""
     c = WL.MODELS["os10x10"]
     D = args.D or c["D"]
     b0 = 2.0 ** -20
     m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], 2.0)
     t0 = time.perf_counter()
-    st = T.State.init(m, T.options(D=D, symmetry=1, beta0=b0, pad_eps=1e-3, seed=1, krylov_dim=c["krylov"]))
+    st = T.State.init(m, T.options(D=D, symmetry=1, beta0=b0, pad_eps=args.green_map_pad, seed=1,
+                                   krylov_dim=c["krylov"], sector_cap=args.green_map_cap))
     t_init = time.perf_counter() - t0
     b, nsw = b0, 0
     b_end = 0.5 / args.green_map_T
@@ -86,7 +87,7 @@ def green_map(args, T, WL):
         nsw += 1
         print("green map: beta %.3g" % b, file=sys.stderr, flush=True)
     while b < b_end - 1e-12:
-        db = min(0.05, b_end - b)
+        db = min(args.green_map_dbeta, b_end - b)
         st.sweep(db)
         b += db
         nsw += 1
@@ -107,7 +108,7 @@ def green_map(args, T, WL):
     print(json.dumps({"metric": "beta G(k, beta/2) map", "workload": "Hubbard 10x10 open square, U=8, mu=2, "
                       "U(1)xU(1) D=%d" % D, "beta_phys": o["beta_phys"], "n": loc["n"], "docc": loc["docc"],
                       "e": o["e"],
-                      "grid": grid, "sweeps": nsw, "seconds_init": t_init, "seconds_sweeps": t_sweeps,
+                      "grid": grid, "sweeps": nsw, "dbeta": args.green_map_dbeta, "pad_eps": args.green_map_pad, "sector_cap": args.green_map_cap, "seconds_init": t_init, "seconds_sweeps": t_sweeps,
                       "seconds_per_k": t_g / len(grid)}))
 
 
@@ -169,6 +170,9 @@ def main():
                     help="instead of the headline: beta G(k, beta/2) over a k grid on the 10x10 open square "
                          "(U=8, mu=2, D=4000), one JSON line")
     ap.add_argument("--green-map-T", type=float, default=2.0, help="temperature of --green-map (T = 1/beta_phys)")
+    ap.add_argument("--green-map-dbeta", type=float, default=0.05, help="linear step of --green-map")
+    ap.add_argument("--green-map-pad", type=float, default=1e-3, help="padding noise amplitude of --green-map")
+    ap.add_argument("--green-map-cap", type=int, default=64, help="sector cap of --green-map (0: none)")
     ap.add_argument("--pairing-scan", action="store_true",
                     help="instead of the headline: chi_SC = Delta_p / hp on the 4x24 cylinder (U=8, hp=0.01, T=1, "
                          "Sz blocks, D=--D or 2000) for a few mu, one JSON line")
