@@ -81,7 +81,7 @@ def green_map(args, T, WL):
     b, nsw = b0, 0
     b_end = 0.5 / args.green_map_T
     t0 = time.perf_counter()
-    while 2.0 * b <= min(0.25, b_end) * (1 + 1e-12):
+    while 2.0 * b <= min(args.green_map_exp_end, b_end) * (1 + 1e-12):
         st.sweep(b)
         b *= 2.0
         nsw += 1
@@ -108,7 +108,7 @@ def green_map(args, T, WL):
     print(json.dumps({"metric": "beta G(k, beta/2) map", "workload": "Hubbard 10x10 open square, U=8, mu=2, "
                       "U(1)xU(1) D=%d" % D, "beta_phys": o["beta_phys"], "n": loc["n"], "docc": loc["docc"],
                       "e": o["e"],
-                      "grid": grid, "sweeps": nsw, "dbeta": args.green_map_dbeta, "pad_eps": args.green_map_pad, "sector_cap": args.green_map_cap, "seconds_init": t_init, "seconds_sweeps": t_sweeps,
+                      "grid": grid, "sweeps": nsw, "dbeta": args.green_map_dbeta, "pad_eps": args.green_map_pad, "sector_cap": args.green_map_cap, "exp_end": args.green_map_exp_end, "seconds_init": t_init, "seconds_sweeps": t_sweeps,
                       "seconds_per_k": t_g / len(grid)}))
 
 
@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--green-map-dbeta", type=float, default=0.05, help="linear step of --green-map")
     ap.add_argument("--green-map-pad", type=float, default=1e-3, help="padding noise amplitude of --green-map")
     ap.add_argument("--green-map-cap", type=int, default=64, help="sector cap of --green-map (0: none)")
+    ap.add_argument("--green-map-exp-end", type=float, default=0.25,
+                    help="beta where the doubling grid of --green-map hands over to the linear steps")
     ap.add_argument("--pairing-scan", action="store_true",
                     help="instead of the headline: chi_SC = Delta_p / hp on the 4x24 cylinder (U=8, hp=0.01, T=1, "
                          "Sz blocks, D=--D or 2000) for a few mu, one JSON line")
