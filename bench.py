@@ -140,6 +140,57 @@ def pairing_scan(args, T):
                       "D=%d, T=1" % D, "points": out}))
 
 
+def sweep_only(args):
+    """The headline sweep without torch in the process.  A profiler that
+    preloads the system HIP runtime would otherwise see torch map a second
+    HIP and HSA runtime; here the library is the only HIP user.  With
+    --calib-copy-mib, one device-to-device copy of that size runs first (the
+    runtime's own copy kernel), the reference for HBM byte counters."""
+    import ctypes
+    from paper_2212_11973_amd import tantrg as T
+    from paper_2212_11973_amd import workloads as WL
+    T.lib(init_torch=False)
+    if args.calib_copy_mib > 0:
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        nbytes = args.calib_copy_mib << 20
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        for x in (a, b):
+            if hip.hipMalloc(ctypes.byref(x), ctypes.c_size_t(nbytes)) != 0:
+                raise RuntimeError("hipMalloc failed")
+        if hip.hipMemset(a, 0, ctypes.c_size_t(nbytes)) != 0 or hip.hipDeviceSynchronize() != 0:
+            raise RuntimeError("hipMemset failed")
+        if hip.hipMemcpy(b, a, ctypes.c_size_t(nbytes), 3) != 0 or hip.hipDeviceSynchronize() != 0:
+            raise RuntimeError("hipMemcpy failed")   # 3 = hipMemcpyDeviceToDevice
+        hip.hipFree(a)
+        hip.hipFree(b)
+        print("calibration copy of %d MiB done" % args.calib_copy_mib, file=sys.stderr, flush=True)
+    c = WL.MODELS[args.workload]
+    D = args.D or c["D"]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
+                  precision=PREC[args.precision], sector_cap=args.sector_cap)
+    print("init %s D=%d %s (no torch)" % (args.workload, D, args.precision), file=sys.stderr, flush=True)
+    st = T.State.init(m, o)
+    for i in range(args.warmup):
+        st.sweep(c["dbeta"], stats=True)
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        stats.append(st.sweep(c["dbeta"], stats=True))   # returns after the stream is synchronised
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    s_step = (time.perf_counter() - t0) / args.steps
+    obs = st.observables()
+    st.free()
+    print(json.dumps({"metric": "s/step (sweep only, no torch)", "value": s_step, "unit": "s/step",
+                      "steps": args.steps, "warmup": args.warmup, "precision": args.precision,
+                      "sector_cap": args.sector_cap,
+                      "workload": "%s D=%d" % (args.workload, D),
+                      "flops_alg_per_step": statistics.mean(x.flops_alg for x in stats),
+                      "applies_per_step": statistics.mean(x.n_applies for x in stats),
+                      "f": obs["f"], "e": obs["e"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +198,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl4x16")
     ap.add_argument("--D", type=int, default=0, help="override the bond dimension")
+    ap.add_argument("--sector-cap", type=int, default=64,
+                    help="largest sector of a padded bond (0: no cap; the headline uses 64)")
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC),
                     help="precision of the timed sweep that gives 'value'")
     ap.add_argument("--mixed-precisions", default="bf16x6,fp32",
@@ -178,10 +231,16 @@ def main():
     ap.add_argument("--pairing-scan", action="store_true",
                     help="instead of the headline: chi_SC = Delta_p / hp on the 4x24 cylinder (U=8, hp=0.01, T=1, "
                          "Sz blocks, D=--D or 2000) for a few mu, one JSON line")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="time the sweep alone in a process without torch (the library's own hipMalloc and "
+                         "the null stream, one HIP runtime): the form for rocprofv3 counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (--gpus 1); the sweep has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.sweep_only:
+        sweep_only(args)
+        return
 
     import numpy as np
     import torch

@@ -673,8 +673,11 @@ std::unique_ptr<tt_state> make_host_state(const tt_model& m, const tt_options& o
   return s;
 }
 
+void require_sweep_plans(tt_state& s);
+
 std::unique_ptr<tt_state> make_state(const tt_model& m, const tt_options& o) {
   auto s = make_host_state(m, o);
+  require_sweep_plans(*s);
   check_device();
   alloc_state(*s);
   return s;
@@ -808,14 +811,10 @@ std::vector<SitePlan> make_obs_plans(const tt_state& s, const Mpo& m, const Mpo&
 long long check_obs_plans(const tt_state& s, const Mpo& m, std::vector<SitePlan>& plans, const SiteTables& tabs,
                           std::string& rep);
 
-long long check_all_plans(tt_state& s, std::string& rep) {
+// every descriptor of the sweep's launches (contractions, W stages, QR/LQ,
+// trace) against the buffers alloc_state sizes from the same plans
+long long check_sweep_plans(tt_state& s, std::string& rep) {
   long long bad = 0;
-  {   // the Green's-function observable (super-operator W stage), all momenta
-    const Mpo pat = make_green_mpo(s.lat, 0.0, 0.0, true);
-    SiteTables gt;
-    std::vector<SitePlan> gp = make_obs_plans(s, pat, pat, gt);
-    bad += check_obs_plans(s, pat, gp, gt, rep);
-  }
   const int N = s.N;
   long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, msite = 0, mb = 0;
   for (auto& P : s.plans) {
@@ -858,6 +857,25 @@ long long check_all_plans(tt_state& s, std::string& rep) {
     }
   }
   return bad;
+}
+
+long long check_all_plans(tt_state& s, std::string& rep) {
+  long long bad = 0;
+  {   // the Green's-function observable (super-operator W stage), all momenta
+    const Mpo pat = make_green_mpo(s.lat, 0.0, 0.0, true);
+    SiteTables gt;
+    std::vector<SitePlan> gp = make_obs_plans(s, pat, pat, gt);
+    bad += check_obs_plans(s, pat, gp, gt, rep);
+  }
+  return bad + check_sweep_plans(s, rep);
+}
+
+// refuse a state whose descriptors address anything outside their buffers,
+// before the first launch (a bad descriptor would be a GPU memory fault)
+void require_sweep_plans(tt_state& s) {
+  std::string rep;
+  const long long bad = check_sweep_plans(s, rep);
+  TT_REQUIRE(bad == 0, TT_EINVAL, "plans out of bounds (" + std::to_string(bad) + "): " + rep);
 }
 
 int fail(const Error& e) { g_err = e.what(); return e.code; }
@@ -1642,6 +1660,7 @@ int tt_state_load(const char* path, tt_state** out) {
     }
   }
   build_layouts(*s, dims);
+  require_sweep_plans(*s);
   alloc_state(*s);
   for (int k = 0; k < s->N; ++k) {
     long long n = 0;

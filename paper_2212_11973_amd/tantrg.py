@@ -62,10 +62,14 @@ _lib = None
 
 
 def _init_torch_runtime():
-    """Initialise torch's HIP runtime before the library's own.  The library
-    links the system ROCm runtime and torch ships another; both live in one
-    process and share the GPU address space (device pointers pass freely),
-    but torch finds no device if the system runtime initialised first."""
+    """Initialise torch's HIP runtime before the library's own.  torch ships
+    its own copy of the HIP runtime, whose soname equals the system one's;
+    loaded first, it is the only runtime in the process (the library's
+    dependency resolves to it by soname), so device pointers and streams pass
+    freely between torch and the library.  Loaded after the system runtime
+    (as under a profiler that preloads it), torch maps a second HIP and HSA
+    runtime into the process, because its libraries name the runtime without
+    the version suffix."""
     try:
         import torch
     except ImportError:
@@ -74,13 +78,17 @@ def _init_torch_runtime():
         torch.cuda.init()
 
 
-def lib():
-    """The loaded library (raises if it was not built)."""
+def lib(init_torch=True):
+    """The loaded library (raises if it was not built).  init_torch=False
+    keeps torch out of the process: the library then runs on the system HIP
+    runtime alone, with its own hipMalloc and the null stream (the form a
+    profiler that preloads the system runtime needs)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libtantrg.so is not built: run __graft_entry__.build()")
-        _init_torch_runtime()
+        if init_torch:
+            _init_torch_runtime()
         L = C.CDLL(LIB_PATH)
         vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
         L.tt_last_error.restype = C.c_char_p

@@ -108,12 +108,24 @@ def test_descriptor_bounds(W, L, geo, D, sym):
     assert work > 0
 
 
-@pytest.mark.parametrize("name", ["cl4x16", "cl6x12"])
-def test_descriptor_bounds_full_workloads(name):
+@pytest.mark.parametrize("name,cap,D", [("cl4x16", 64, 0), ("cl4x16", 0, 0), ("cl6x12", 64, 0),
+                                        ("os10x10", 0, 4000), ("os10x10", 64, 8000)])
+def test_descriptor_bounds_full_workloads(name, cap, D):
+    """The workloads' own shapes (sector cap 64 and uncapped, up to D = 8000):
+    every descriptor stays inside its buffer (the same check runs before the
+    first launch of every state)."""
     c = WL.MODELS[name]
     m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
-    v, work, rep = T.tt_check_plans(m, T.options(D=c["D"], symmetry=1))
+    v, work, rep = T.tt_check_plans(m, T.options(D=D or c["D"], symmetry=1, sector_cap=cap))
     assert v == 0, rep
+
+
+def test_mid_size_chain_plans_in_bounds():
+    """The 8-site chain at D = 1000 of the GPU parity tests: 64-column QR
+    blocks in four row chunks (cap 64) and the global-memory QR (no cap)."""
+    for cap in (64, 0):
+        v, _, rep = T.tt_check_plans(T.model(1, 8, 0, 1.0, 8.0, 1.5), T.options(D=1000, symmetry=1, sector_cap=cap))
+        assert v == 0, rep
 
 
 @pytest.mark.parametrize("W,L,geo,D,cap,tp", [(4, 4, 1, 64, 0, 0.0), (2, 3, 2, 40, 0, 0.0), (4, 16, 1, 300, 0, 0.0),
