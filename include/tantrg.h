@@ -233,6 +233,27 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* dev_L, const double* dev
                   const double* dev_A, const double* dev_R, double* dev_out, int precision,
                   void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the apply of
+ * tt_heff_apply, same arguments, layouts and result (the same kernels and
+ * launch plans, so the output is bit for bit that of tt_heff_apply), with
+ * every byte of device memory it needs beyond the caller's inputs and output
+ * (the intermediates T1 = L.A and T2, the K-slice partial tiles and the launch
+ * descriptors) taken from a static device array of 192 MiB that each GPU the
+ * library runs on holds until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine.  TT_EINVAL for sizes whose
+ * intermediates do not fit (16*Dl*DH*16*Dr bytes for T1 and T2 alone; e.g.
+ * Dl = Dr = 128 at DH = 18 fits), for non-positive sizes, null pointers, an
+ * unknown precision, or kernel profiling switched on.  Every call on one GPU
+ * shares that GPU's array and leaves its contents (descriptors of the last
+ * sizes are reused when the sizes repeat; nothing needs to start at zero):
+ * calls that overlap on one GPU (other streams, other threads) race and must
+ * be serialised by the caller.  Enqueued on `stream` (NULL: the library's
+ * stream), no synchronisation. */
+int tt_heff_apply_noalloc(int Dl, int Dr, int DH, const double* dev_L, const double* dev_W,
+                          const double* dev_A, const double* dev_R, double* dev_out, int precision,
+                          void* stream);
+
 /* The two-site generator of 2-TDVP (SM Sec. "2-TDVP in the initial stage",
  * Eq. S-2TDVP) on dense operands, for measurement and tests:
  * out[x][s1][s2][y] = sum L[x][a][x'] C[x'][s1'][s2'][y'] W1[a][so1][si1][b]

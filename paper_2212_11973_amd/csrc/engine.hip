@@ -16,6 +16,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -1120,6 +1121,60 @@ bool same_plans(const tt_state& a, const tt_state& b) {
 }
 
 // -------------------------------------------------------------- dense microbenchmark
+// Host side of the dense apply: the plans of its three launches (L.A, the W
+// stage as grouped GEMMs reading W from device memory, .R), tiled, with their
+// index tables and the sizes of the intermediates they address.
+struct HeffPlans {
+  SitePlan plan;
+  SiteTables tabs;
+  GemmPlan wg;
+  long long t1 = 0, t2 = 0, pw = 1;
+};
+
+HeffPlans heff_plans(int Dl, int Dr, int DH) {
+  HeffPlans h;
+  Bond bl, br;
+  bl.add({0, 0}, Dl);
+  br.add({0, 0}, Dr);
+  Groups G = make_groups(0);
+  std::vector<Q> qh(DH, Q{0, 0});
+  // the plan's W stage is replaced by a grouped GEMM reading W from device memory;
+  // an all-zero W keeps the sparse W-stage plan empty
+  std::vector<double> Wz((size_t)DH * 16 * DH, 0.0);
+  h.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, Wz, h.tabs);
+  // W stage as GEMMs: for each (x, sigma'): T2[(so,b)][y] = sum_(a,si) W[(so,b),(a,si)] T1[(a,si)][y]
+  std::vector<long long> am, ak, bk, cm;
+  for (int so = 0; so < 4; ++so)
+    for (int b = 0; b < DH; ++b) am.push_back((long long)so * 4 * DH + b);
+  for (int a = 0; a < DH; ++a)
+    for (int si = 0; si < 4; ++si) {
+      ak.push_back((long long)a * 16 * DH + (long long)si * DH);
+      bk.push_back((long long)a * Dl * 16 * Dr + (long long)si * 4 * Dr);
+    }
+  for (int so = 0; so < 4; ++so)
+    for (int b = 0; b < DH; ++b) cm.push_back((long long)4 * so * DH * Dr + (long long)b * Dr);
+  long long tam = h.tabs.add(am), tak = h.tabs.add(ak), tbk = h.tabs.add(bk), tcm = h.tabs.add(cm);
+  h.wg.tag = TAG_WGEMM;
+  for (int x = 0; x < Dl; ++x)
+    for (int sp = 0; sp < 4; ++sp) {
+      GemmProb g{};
+      g.M = 4 * DH; g.N = Dr; g.K = 4 * DH;
+      g.ia = 0; g.ib = 1; g.ic = 2;
+      g.tam = tam; g.tak = tak; g.tbk = tbk; g.tbn = -1; g.tcm = tcm;
+      g.sbn = 1;
+      g.offB = (long long)x * 16 * Dr + (long long)sp * Dr;
+      g.offC = ((long long)x * 16 + sp) * DH * Dr;
+      g.alpha = 1.0; g.beta = 0.0;
+      h.wg.probs.push_back(g);
+      h.wg.flops += 2.0 * g.M * (double)g.N * g.K;
+    }
+  for (GemmPlan* g : {&h.plan.s1, &h.plan.s3, &h.wg}) tile_plan(*g, &h.tabs.host);
+  h.t1 = h.plan.t1_size;
+  h.t2 = h.plan.t2_size;
+  h.pw = std::max(std::max(h.plan.s1.pws_size, h.plan.s3.pws_size), std::max(h.wg.pws_size, 1LL));
+  return h;
+}
+
 struct HeffCache {
   int Dl = -1, Dr = -1, DH = -1;
   SitePlan plan;
@@ -1136,54 +1191,78 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   HeffCache& c = g_heff;
   free_plan(c.plan.s1); free_plan(c.plan.s3); free_plan(c.wg);
   dfree(c.tabs.dev); c.tabs = SiteTables();
-  Bond bl, br;
-  bl.add({0, 0}, Dl);
-  br.add({0, 0}, Dr);
-  Groups G = make_groups(0);
-  std::vector<Q> qh(DH, Q{0, 0});
-  // the plan's W stage is replaced by a grouped GEMM reading W from device memory;
-  // an all-zero W keeps the sparse W-stage plan empty
-  std::vector<double> Wz((size_t)DH * 16 * DH, 0.0);
-  c.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, Wz, c.tabs);
-  // W stage as GEMMs: for each (x, sigma'): T2[(so,b)][y] = sum_(a,si) W[(so,b),(a,si)] T1[(a,si)][y]
-  std::vector<long long> am, ak, bk, cm;
-  for (int so = 0; so < 4; ++so)
-    for (int b = 0; b < DH; ++b) am.push_back((long long)so * 4 * DH + b);
-  for (int a = 0; a < DH; ++a)
-    for (int si = 0; si < 4; ++si) {
-      ak.push_back((long long)a * 16 * DH + (long long)si * DH);
-      bk.push_back((long long)a * Dl * 16 * Dr + (long long)si * 4 * Dr);
-    }
-  for (int so = 0; so < 4; ++so)
-    for (int b = 0; b < DH; ++b) cm.push_back((long long)4 * so * DH * Dr + (long long)b * Dr);
-  long long tam = c.tabs.add(am), tak = c.tabs.add(ak), tbk = c.tabs.add(bk), tcm = c.tabs.add(cm);
-  c.wg = GemmPlan();
-  c.wg.tag = TAG_WGEMM;
-  for (int x = 0; x < Dl; ++x)
-    for (int sp = 0; sp < 4; ++sp) {
-      GemmProb g{};
-      g.M = 4 * DH; g.N = Dr; g.K = 4 * DH;
-      g.ia = 0; g.ib = 1; g.ic = 2;
-      g.tam = tam; g.tak = tak; g.tbk = tbk; g.tbn = -1; g.tcm = tcm;
-      g.sbn = 1;
-      g.offB = (long long)x * 16 * Dr + (long long)sp * Dr;
-      g.offC = ((long long)x * 16 + sp) * DH * Dr;
-      g.alpha = 1.0; g.beta = 0.0;
-      c.wg.probs.push_back(g);
-      c.wg.flops += 2.0 * g.M * (double)g.N * g.K;
-    }
+  HeffPlans h = heff_plans(Dl, Dr, DH);
+  c.plan = std::move(h.plan);
+  c.tabs = std::move(h.tabs);
+  c.wg = std::move(h.wg);
   hipStream_t st = ST();
   c.tabs.dev = upload(c.tabs.host, st);
   upload_plan(c.plan.s1, &c.tabs.host, st);
   upload_plan(c.plan.s3, &c.tabs.host, st);
   upload_plan(c.wg, &c.tabs.host, st);
-  if (c.plan.t1_size > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * c.plan.t1_size); c.t1 = c.plan.t1_size; }
-  if (c.plan.t2_size > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * c.plan.t2_size); c.t2 = c.plan.t2_size; }
-  long long pw = std::max(std::max(c.plan.s1.pws_size, c.plan.s3.pws_size), std::max(c.wg.pws_size, 1LL));
-  if (pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * pw); c.pw = pw; }
+  if (h.t1 > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * h.t1); c.t1 = h.t1; }
+  if (h.t2 > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * h.t2); c.t2 = h.t2; }
+  if (h.pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * h.pw); c.pw = h.pw; }
   for (int i = 0; i < 4; ++i)
     if (!c.ev[i]) HIPX(hipEventCreate(&c.ev[i]));
   c.Dl = Dl; c.Dr = Dr; c.DH = DH;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------- allocation-free dense apply
+// The device memory of tt_heff_apply_noalloc: the intermediates T1 and T2, the
+// K-slice partial tiles and every descriptor table of its three launches.  One
+// copy per GPU, held until the process ends.  Host code must not pass the
+// array's name to a kernel or a copy (in host code it is a host-side stand-in):
+// it uses the address hipGetSymbolAddress returns on each device.
+constexpr long long kScratchBytes = 192LL << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / 8];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+struct NoAllocDev {
+  char* base = nullptr;            // this GPU's copy of the scratch array
+  int Dl = -1, Dr = -1, DH = -1;   // the sizes whose descriptors the scratch holds
+  HeffPlans host;                  // their host copy
+  GemmPlan s1, s3, wg;             // the same plans with device pointers into the scratch
+  long long* tabs = nullptr;
+  double *T1 = nullptr, *T2 = nullptr, *pws = nullptr;
+};
+NoAllocDev g_noalloc[kMaxDevices];
+
+// Lay the apply's buffers out in the scratch (256-byte aligned pieces); with
+// copy, also upload the descriptors.  Returns the bytes used.
+long long noalloc_layout(NoAllocDev& d, bool copy, hipStream_t st) {
+  long long used = 0;
+  auto carve = [&](long long bytes) -> char* {
+    used = (used + 255) & ~255LL;
+    char* p = d.base + used;
+    used += std::max(bytes, 8LL);
+    return p;
+  };
+  auto put = [&](auto*& dst, const auto& v) {
+    using T = typename std::decay<decltype(v)>::type::value_type;
+    dst = reinterpret_cast<T*>(carve((long long)(sizeof(T) * v.size())));
+    if (copy && !v.empty() && used <= kScratchBytes)
+      HIPX(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  };
+  HeffPlans& h = d.host;
+  d.T1 = reinterpret_cast<double*>(carve(8 * h.t1));
+  d.T2 = reinterpret_cast<double*>(carve(8 * h.t2));
+  d.pws = reinterpret_cast<double*>(carve(8 * h.pw));
+  put(d.tabs, h.tabs.host);
+  GemmPlan* dev[3] = {&d.s1, &d.wg, &d.s3};
+  const GemmPlan* src[3] = {&h.plan.s1, &h.wg, &h.plan.s3};
+  for (int i = 0; i < 3; ++i) {
+    *dev[i] = *src[i];
+    put(dev[i]->d_probs, src[i]->probs);
+    put(dev[i]->d_tiles, src[i]->tiles);
+    put(dev[i]->d_splits, src[i]->splits);
+    put(dev[i]->d_jobs, src[i]->jobs);
+  }
+  return used;
 }
 
 // The two-site generator H^(2) C of 2-TDVP on dense operands, in the order
@@ -1709,6 +1788,47 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
     throw;
   }
   g_stream = saved;
+  ABI_END
+}
+
+int tt_heff_apply_noalloc(int Dl, int Dr, int DH, const double* L, const double* W, const double* A,
+                          const double* R, double* out, int precision, void* stream) {
+  ABI_BEGIN
+  TT_REQUIRE(Dl >= 1 && Dr >= 1 && DH >= 1, TT_EINVAL, "dimensions must be positive");
+  TT_REQUIRE(L && W && A && R && out, TT_EINVAL, "null device pointer");
+  TT_REQUIRE(precision >= TT_FP64 && precision <= TT_BF16X6, TT_EINVAL, "unknown precision");
+  TT_REQUIRE(!prof_enabled(), TT_EINVAL, "tt_heff_apply_noalloc: kernel profiling (which creates events) is on");
+  // T1 and T2 alone take 16 Dl DH 16 Dr bytes: refuse what cannot fit before planning
+  TT_REQUIRE(16.0 * Dl * DH * 16.0 * Dr <= (double)kScratchBytes, TT_EINVAL,
+             "tt_heff_apply_noalloc: the intermediates need " + std::to_string(16.0 * Dl * DH * 16.0 * Dr) +
+                 " bytes, more than the " + std::to_string(kScratchBytes) + "-byte scratch");
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  TT_REQUIRE(dev >= 0 && dev < kMaxDevices, TT_EDEVICE, "device index out of range");
+  NoAllocDev& d = g_noalloc[dev];
+  hipStream_t st = stream ? (hipStream_t)stream : ST();
+  if (!d.base) {   // once per device, with that device current
+    void* p = nullptr;
+    HIPX(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    d.base = static_cast<char*>(p);
+  }
+  if (d.Dl != Dl || d.Dr != Dr || d.DH != DH) {
+    d.Dl = d.Dr = d.DH = -1;
+    d.host = heff_plans(Dl, Dr, DH);
+    const long long need = noalloc_layout(d, false, st);
+    TT_REQUIRE(need <= kScratchBytes, TT_EINVAL,
+               "tt_heff_apply_noalloc: the apply needs " + std::to_string(need) + " bytes of scratch, more than " +
+                   std::to_string(kScratchBytes));
+    noalloc_layout(d, true, st);
+    d.Dl = Dl; d.Dr = Dr; d.DH = DH;
+  }
+  double* l = const_cast<double*>(L);
+  double* w = const_cast<double*>(W);
+  double* a = const_cast<double*>(A);
+  double* r = const_cast<double*>(R);
+  launch_gemm(d.s1, d.tabs, one(Slots{{l, a, d.T1, nullptr}}), 1, precision, one(d.pws), st);
+  launch_gemm(d.wg, d.tabs, one(Slots{{w, d.T1, d.T2, nullptr}}), 1, precision, one(d.pws), st);
+  launch_gemm(d.s3, d.tabs, one(Slots{{d.T2, r, out, nullptr}}), 1, precision, one(d.pws), st);
   ABI_END
 }
 

@@ -24,7 +24,7 @@ SYMBOLS = [
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
     "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function", "thermo_pairing_order",
-    "tt_heff2_apply",
+    "tt_heff2_apply", "tt_heff_apply_noalloc",
 ]
 
 
@@ -113,6 +113,7 @@ def lib(init_torch=True):
         L.tt_state_save.argtypes = [vp, C.c_char_p]
         L.tt_state_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.tt_heff_apply.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.tt_heff_apply_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp]
         L.tt_set_stream.argtypes = [vp]
         L.tt_set_allocator.argtypes = [vp, vp, vp]
         L.tt_heff_last_timing.argtypes = [dp]
@@ -270,6 +271,13 @@ def tt_heff_apply(Dl, Dr, DH, L_ptr, W_ptr, A_ptr, R_ptr, out_ptr, precision=TT_
     _check(lib().tt_heff_apply(Dl, Dr, DH, C.c_void_p(L_ptr), C.c_void_p(W_ptr), C.c_void_p(A_ptr),
                                C.c_void_p(R_ptr), C.c_void_p(out_ptr), precision,
                                C.c_void_p(stream) if stream else None))
+
+
+def tt_heff_apply_noalloc(Dl, Dr, DH, L_ptr, W_ptr, A_ptr, R_ptr, out_ptr, precision=TT_FP64, stream=None):
+    """tt_heff_apply without device allocation (the library's static scratch)."""
+    _check(lib().tt_heff_apply_noalloc(Dl, Dr, DH, C.c_void_p(L_ptr), C.c_void_p(W_ptr), C.c_void_p(A_ptr),
+                                       C.c_void_p(R_ptr), C.c_void_p(out_ptr), precision,
+                                       C.c_void_p(stream) if stream else None))
 
 
 def tt_heff2_apply(Dl, Dr, DH, L_ptr, W1_ptr, W2_ptr, C_ptr, R_ptr, out_ptr, precision=TT_FP64, stream=None):
