@@ -35,34 +35,55 @@ def kernel_name(kind, prec):
             "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
 
 
-def dense_sweep_flops(dims, DH, K):
-    """Dense-equivalent flops of one sweep (what a dense contraction of the same
-    bond dimensions costs): site applies, bond applies, environments, QR."""
-    N = len(dims) - 1
-    def h1(Dl, Dr):
-        return 32.0 * DH * Dl * Dr * (Dl + Dr) + 128.0 * DH * DH * Dl * Dr
-    f = 0.0
-    for k in range(N):                       # 2N-1 site exponentials
-        f += (2 if k < N - 1 else 1) * K * h1(dims[k], dims[k + 1])
-    for k in range(1, N):                    # 2N-2 bond exponentials, 2N-2 environments, QR
-        D = dims[k]
-        f += 2 * K * 4.0 * D ** 3 * DH
-        f += h1(dims[k - 1], dims[k]) + h1(dims[k], dims[k + 1])
-        f += 2 * (4.0 * 16 * D * D * D)
-    return f
-
-
-def cpu_baseline(D, DH):
-    """The oracle's dense apply at D on the host (bounded sample)."""
-    import numpy as np
-    from oracle import tdvp as otd
-    from paper_2212_11973_amd import workloads as WL
-    L, W, A, R = WL.heff_inputs(D, DH)
+def cpu_baseline(c, D, sector_cap, budget_s=25.0):
+    """The block-sparse FP64 oracle on the same workload, timed on the host
+    over a bounded sample: from the same start (rho0 padded with seed 1), the
+    left-to-right site steps k = 0, 1, ... (site exponential, QR, left
+    environment, bond exponential, absorb) until budget_s has elapsed with at
+    least two steps between full bonds done.  A sweep's 2N - 1 site steps are
+    priced by the measured step whose pair of bond dimensions matches (the
+    right-to-left step at site k costs what the left-to-right one at k - 1
+    does: the same contractions mirrored)."""
+    from oracle import blocked, mpo as ompo
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    m = ompo.HubbardMPO(c["W"], c["L"], c["geometry"], t=c["t"], U=c["U"], mu=c["mu"])
     t0 = time.perf_counter()
-    otd.heff1(L, W, R, A)
-    t = time.perf_counter() - t0
-    flops = 32.0 * DH * D * D * (2 * D) + 128.0 * DH * DH * D * D
-    return t, flops
+    st = blocked.initial_state(m, c["beta0"], D, pad_eps=1e-3, seed=1, sector_cap=sector_cap)
+    t_start = time.perf_counter() - t0
+    dims = [b.dim for b in st.bonds]
+    N = st.N
+    tau = 0.5 * c["dbeta"]
+    cost = {}            # sorted (D_k, D_k+1) -> seconds of one step
+    t_sample, k = 0.0, 0
+    full = max(dims)
+    while k < N - 1:
+        t0 = time.perf_counter()
+        st.site_step_lr(k, tau, K=c["krylov"])
+        dt = time.perf_counter() - t0
+        t_sample += dt
+        key = tuple(sorted((dims[k], dims[k + 1])))
+        cost.setdefault(key, []).append(dt)
+        k += 1
+        print("cpu baseline: oracle site step %d %.2f s" % (k - 1, dt), file=sys.stderr, flush=True)
+        if t_sample >= budget_s and len(cost.get((full, full), [])) >= 2:
+            break
+    def price(k):
+        key = tuple(sorted((dims[k], dims[k + 1])))
+        if key not in cost:
+            return None
+        return sum(cost[key]) / len(cost[key])
+    prices = [price(k) for k in range(N - 1)]
+    if any(p is None for p in prices):
+        return None
+    est = 2.0 * sum(prices) + price(N - 2)   # both directions, plus the merged turn priced as an edge step
+    return dict(value=est, unit="s/step", cores=threads, kind="oracle",
+                sample="block-sparse FP64 oracle (oracle/blocked.py) on the same workload and start: %d left-to-right "
+                       "site steps timed (%.1f s; start built in %.1f s, not timed), the 2N-1 = %d site steps of a sweep "
+                       "priced by the measured step of the same bond dimensions" % (k, t_sample, t_start, 2 * N - 1))
 
 
 def green_map(args, T, WL):
@@ -144,13 +165,28 @@ def sweep_only(args):
     """The headline sweep without torch in the process.  A profiler that
     preloads the system HIP runtime would otherwise see torch map a second
     HIP and HSA runtime; here the library is the only HIP user.  With
-    --calib-copy-mib, one device-to-device copy of that size runs first (the
-    runtime's own copy kernel), the reference for HBM byte counters."""
+    --calib-copy-mib, one device-to-device copy of that size runs after the
+    warmup sweeps (the runtime's own copy kernel): the reference for HBM byte
+    counters."""
     import ctypes
     from paper_2212_11973_amd import tantrg as T
     from paper_2212_11973_amd import workloads as WL
     T.lib(init_torch=False)
+    c = WL.MODELS[args.workload]
+    D = args.D or c["D"]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
+                  precision=PREC[args.precision], sector_cap=args.sector_cap)
+    print("init %s D=%d %s (no torch)" % (args.workload, D, args.precision), file=sys.stderr, flush=True)
+    st = T.State.init(m, o)
+    forms = st.tune_apply(args.apply_form)
+    for i in range(args.warmup):
+        st.sweep(c["dbeta"], stats=True)
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
     if args.calib_copy_mib > 0:
+        # one device-to-device copy of known size (the runtime's own copy
+        # kernel): the reference for HBM byte counters, and the marker after
+        # which every dispatch belongs to the timed sweeps
         hip = ctypes.CDLL("libamdhip64.so.7")
         nbytes = args.calib_copy_mib << 20
         a, b = ctypes.c_void_p(), ctypes.c_void_p()
@@ -164,16 +200,6 @@ def sweep_only(args):
         hip.hipFree(a)
         hip.hipFree(b)
         print("calibration copy of %d MiB done" % args.calib_copy_mib, file=sys.stderr, flush=True)
-    c = WL.MODELS[args.workload]
-    D = args.D or c["D"]
-    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
-    o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
-                  precision=PREC[args.precision], sector_cap=args.sector_cap)
-    print("init %s D=%d %s (no torch)" % (args.workload, D, args.precision), file=sys.stderr, flush=True)
-    st = T.State.init(m, o)
-    for i in range(args.warmup):
-        st.sweep(c["dbeta"], stats=True)
-        print("warmup %d done" % i, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     stats = []
     for i in range(args.steps):
@@ -184,11 +210,101 @@ def sweep_only(args):
     st.free()
     print(json.dumps({"metric": "s/step (sweep only, no torch)", "value": s_step, "unit": "s/step",
                       "steps": args.steps, "warmup": args.warmup, "precision": args.precision,
-                      "sector_cap": args.sector_cap,
+                      "sector_cap": args.sector_cap, "apply_form": args.apply_form, "folded_sites": sum(forms),
                       "workload": "%s D=%d" % (args.workload, D),
                       "flops_alg_per_step": statistics.mean(x.flops_alg for x in stats),
                       "applies_per_step": statistics.mean(x.n_applies for x in stats),
                       "f": obs["f"], "e": obs["e"]}), flush=True)
+
+
+def summarize_counters(args):
+    """Per-kernel counter means over the timed sweeps of `bench.py
+    --sweep-only --calib-copy-mib M` runs under rocprofv3 --pmc (one rocpd
+    database per pass): every dispatch after the calibration copy, grouped by
+    kernel name.  FETCH_SIZE and WRITE_SIZE (KiB) are scaled by known bytes /
+    counter reading of the calibration copy (M MiB read and M MiB written),
+    and their sum per launch is the measured HBM traffic.  Writes
+    profiles/counters_<workload>_<precision>.txt."""
+    import sqlite3
+    from collections import defaultdict
+    known_kib = args.calib_copy_mib * 1024.0
+    per = defaultdict(lambda: defaultdict(list))   # kernel -> counter -> values
+    factors = {}
+    for db in args.summarize_counters:
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, kernel_name, counter_name, value, duration from counters_collection "
+                           "order by dispatch_id").fetchall()
+        counters = sorted({r[2] for r in rows})
+        # the calibration copy: the copy kernel with the largest reading of the first counter
+        copies = [r for r in rows if "copyBuffer" in r[1]]
+        calib = max(copies, key=lambda r: r[3])
+        for cn in counters:
+            cv = [r[3] for r in rows if r[0] == calib[0] and r[2] == cn]
+            if cn in ("FETCH_SIZE", "WRITE_SIZE") and cv and cv[0] > 0:
+                factors[cn] = known_kib / cv[0]
+        for (did, kname, cn, v, dur) in rows:
+            if did <= calib[0]:
+                continue
+            short = kname.split("(")[0].replace("void ", "")
+            per[short][cn].append(v)
+            per[short]["_duration_ns[" + cn + "]"].append(dur)
+    out = ["# rocprofv3 counter summary: the timed sweeps of bench.py --sweep-only (dispatches after the calibration "
+           "copy), means per dispatch",
+           "# commands: " + args.counter_commands,
+           "workload=%s" % args.workload, "precision=%s" % args.precision,
+           "sources_digest=%s" % kernel_sources_digest(),
+           "calibration_copy_MiB=%d" % args.calib_copy_mib]
+    for cn, f in sorted(factors.items()):
+        out.append("calibration_factor[%s]=%.6f" % (cn, f))
+    for k in sorted(per, key=lambda k: -len(per[k].get("FETCH_SIZE", per[k].get(next(iter(per[k])), [])))):
+        cs = per[k]
+        n = max(len(v) for c, v in cs.items() if not c.startswith("_"))
+        out.append("dispatches[%s]=%d" % (k, n))
+        for cn, v in sorted(cs.items()):
+            if cn.startswith("_"):
+                continue
+            out.append("mean[%s][%s]=%.6g" % (k, cn, sum(v) / len(v)))
+        if "FETCH_SIZE" in cs and "WRITE_SIZE" in cs and len(factors) == 2:
+            fb = sum(cs["FETCH_SIZE"]) / len(cs["FETCH_SIZE"]) * factors["FETCH_SIZE"] * 1024
+            wb = sum(cs["WRITE_SIZE"]) / len(cs["WRITE_SIZE"]) * factors["WRITE_SIZE"] * 1024
+            out.append("traffic_bytes_per_launch[%s]=%.6g" % (k, fb + wb))
+    path = os.path.join(ROOT, "profiles", "counters_%s_%s.txt" % (args.workload, args.precision))
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(path)
+
+
+def kernel_sources_digest():
+    """Digest of the sources that define the kernels and their launch plans:
+    counter readings stored under profiles/ apply only while it is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "plan.h", "layout.cpp", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_2212_11973_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, args):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 counter
+    summary under profiles/ (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled
+    by the factor a copy of known size gives), or None if there is none for
+    this kernel and workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "counters_%s_%s.txt" % (args.workload, args.precision))
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("sources_digest") != kernel_sources_digest():
+        return None, "%s was taken on other kernel sources" % os.path.basename(path)
+    key = "traffic_bytes_per_launch[%s]" % kernel
+    if key not in vals:
+        return None, "%s has no entry for %s" % (os.path.basename(path), kernel)
+    return float(vals[key]), os.path.basename(path)
 
 
 def main():
@@ -198,6 +314,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl4x16")
     ap.add_argument("--D", type=int, default=0, help="override the bond dimension")
+    ap.add_argument("--apply-form", type=int, default=2, choices=(0, 1, 2),
+                    help="site apply form: 0 the paper's contraction order, 1 the MPO folded into L, "
+                         "2 autotuned per site (default)")
     ap.add_argument("--sector-cap", type=int, default=64,
                     help="largest sector of a padded bond (0: no cap; the headline uses 64)")
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC),
@@ -215,7 +334,6 @@ def main():
     ap.add_argument("--graphs", action="store_true", help="replay captured sweeps (hipGraph) in the timed loop")
     ap.add_argument("--no-observables", action="store_true",
                     help="skip the entropy, specific heat and spin correlations after the timed sweeps")
-    ap.add_argument("--cpu-D", type=int, default=1500, help="bond dimension of the oracle sample")
     ap.add_argument("--mu-scan", type=int, default=8,
                     help="instances of the batched mu-scan on the 6x12 cylinder (0: skip)")
     ap.add_argument("--mu-scan-D", type=int, default=0, help="override the mu-scan bond dimension")
@@ -234,7 +352,14 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="time the sweep alone in a process without torch (the library's own hipMalloc and "
                          "the null stream, one HIP runtime): the form for rocprofv3 counter collection")
+    ap.add_argument("--summarize-counters", nargs="+", default=None, metavar="DB",
+                    help="write profiles/counters_<workload>_<precision>.txt from rocprofv3 --pmc databases of "
+                         "--sweep-only runs (no GPU needed)")
+    ap.add_argument("--counter-commands", default="", help="the profiler commands, recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (--gpus 1); the sweep has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
@@ -272,10 +397,13 @@ def main():
         number of sweeps again with HIP events around every grouped launch (the
         events cost host time per launch, so they stay out of the timed value)."""
         o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
-                      precision=PREC[prec])
+                      precision=PREC[prec], sector_cap=args.sector_cap)
         print("init %s D=%d %s" % (args.workload, D, prec), file=sys.stderr, flush=True)
         st = T.State.init(m, o)
-        info = st.info()
+        t_tune = time.perf_counter()
+        forms = st.tune_apply(args.apply_form)   # the per-site apply form (autotuned by default)
+        t_tune = time.perf_counter() - t_tune
+        info = st.info() + (dict(apply_form=args.apply_form, folded_sites=sum(forms), tune_s=t_tune),)
         T.tt_sweep_graphs(args.graphs)   # the first sweep of a step captures, later ones replay
         for i in range(warmup):
             st.sweep(c["dbeta"])
@@ -288,8 +416,15 @@ def main():
             print("step %d done" % i, file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof, prof_s = None, None
+        prof, prof_s, phases = None, None, None
         if profile:
+            # one pass with per-phase device timing (events around every phase occurrence)
+            T.tt_phase_timing(True)
+            ph = [st.sweep(c["dbeta"], stats=True) for _ in range(steps)]
+            T.tt_phase_timing(False)
+            phases = {k: statistics.mean(getattr(x, k) for x in ph)
+                      for k in ("t_heff", "t_bond", "t_lanczos", "t_qr", "t_env", "t_absorb")}
+            print("phase-timed steps done", file=sys.stderr, flush=True)
             T.tt_profile_enable(True)
             t2 = time.perf_counter()
             for i in range(steps):
@@ -300,7 +435,7 @@ def main():
             T.tt_profile_enable(False)
             prof = T.tt_profile_read()
         else:
-            for i in range(steps):   # same final beta as the profiled run, for the observable comparison
+            for i in range(2 * steps):   # same final beta as the profiled run, for the observable comparison
                 st.sweep(c["dbeta"])
         T.tt_sweep_graphs(False)
         obs = st.observables()
@@ -326,12 +461,14 @@ def main():
             thermo = dict(beta_phys=bp, e=[o_["e"] for o_ in series], f=[o_["f"] for o_ in series],
                           c_e=ce, s_e=se, spin_correlation=spin, green_k=green)
         st.free()
-        return (t1 - t0) / steps, stats, (prof, prof_s), obs, info, thermo
+        return (t1 - t0) / steps, stats, (prof, prof_s, phases), obs, info, thermo
 
-    s_per_step, stats, (prof, prof_s_per_step), obs, (n_sites, dims), thermo = timed_sweeps(
+    s_per_step, stats, (prof, prof_s_per_step, phases), obs, (n_sites, dims, forms_info), thermo = timed_sweeps(
         args.precision, args.steps, args.warmup, True)
     flops_step = statistics.mean(s.flops_alg for s in stats)
     applies_step = statistics.mean(s.n_applies for s in stats)
+    bytes_min_step = statistics.mean(s.bytes_min for s in stats)
+    launches_step = statistics.mean(s.n_launches for s in stats)
     mixed = {}
     for pname in [x for x in args.mixed_precisions.split(",") if x and x != args.precision]:
         sp, st2, _, ob2, _, _ = timed_sweeps(pname, args.steps, args.warmup, False)
@@ -339,8 +476,11 @@ def main():
                             rel_df_vs_main=abs(ob2["f"] - obs["f"]) / max(abs(obs["f"]), 1e-2),
                             rel_de_vs_main=abs(ob2["e"] - obs["e"]) / max(abs(obs["e"]), 1e-2))
 
-    # dominant single kernel of the timed region and its roofline: the binding
-    # roof is the lower of the compute peak and arithmetic intensity x HBM peak
+    # dominant single kernel of the timed region and its roofline.  A
+    # contraction kernel (grouped GEMM) is priced against the MFMA peak of the
+    # type it multiplies in (algorithmic flops, sum of 2mnk, over its event
+    # time); the W stage against HBM (its algorithmic bytes); the QR against
+    # the FP64 vector peak
     singles = [k for k in prof if k.startswith("k_gemm_") or k in ("k_wgemm", "wstage", "qr")]
     kind = max(singles, key=lambda k: prof[k]["ms"])
     pk = prof[kind]
@@ -350,25 +490,20 @@ def main():
         # the wave GEMM multiplies in FP64 in every mode
         pname = "fp64" if (args.precision == "fp64" or kind == "k_wgemm") else (
             "fp32" if args.precision == "fp32" else "bf16")
-        peak_f = PEAK[pname]
-    else:
-        peak_f = PEAK_FP64_VALU
-    ai = pk["flops"] / max(pk["bytes"], 1.0)
-    if pk["flops"] > 0 and peak_f <= ai * PEAK_HBM_GBS / 1e3:
-        roof = dict(bound="mfma" if is_mfma else "alu", unit="TFLOP/s", peak=peak_f,
-                    achieved=pk["flops"] / sec / 1e12)
+        roof = dict(bound="mfma", unit="TFLOP/s", peak=PEAK[pname], achieved=pk["flops"] / sec / 1e12)
+    elif kind == "qr":
+        roof = dict(bound="alu", unit="TFLOP/s", peak=PEAK_FP64_VALU, achieved=pk["flops"] / sec / 1e12)
     else:
         roof = dict(bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS, achieved=pk["bytes"] / sec / 1e9)
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
     roof["kernel"] = kernel_name(kind, PREC[args.precision])
     roof["avg_launch_ms"] = pk["ms"] / max(pk["launches"], 1)
     roof["launches"] = pk["launches"]
     roof["alg_flops_per_launch"] = pk["flops"] / max(pk["launches"], 1)
     roof["alg_bytes_per_launch"] = pk["bytes"] / max(pk["launches"], 1)
-    roof["intensity_flop_per_byte"] = ai
     roof["share_of_step"] = pk["ms"] / (prof_s_per_step * 1e3 * args.steps)
     roof["profiled_s_per_step"] = prof_s_per_step
+    roof["traffic"], roof["traffic_source"] = measured_traffic(roof["kernel"], args)
     kernels = {k: dict(ms_per_step=v["ms"] / args.steps, launches_per_step=v["launches"] / args.steps,
                        tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
                        gbs=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0)
@@ -384,6 +519,9 @@ def main():
                        precision=PREC[args.precision])
         print("init mu-scan: %d x 6x12 cylinder D=%d" % (len(mus), D4), file=sys.stderr, flush=True)
         sts = [T.State.init(T.model(c4["W"], c4["L"], c4["geometry"], c4["t"], c4["U"], mu), o4) for mu in mus]
+        forms4 = sts[0].tune_apply(args.apply_form)   # one instance's choice for the whole batch
+        for st in sts[1:]:
+            st.tune_apply(3, forms4)
         hs = [st.h for st in sts]
         T.tdvp_sweep_batch(hs, c4["dbeta"])
         torch.cuda.synchronize()
@@ -410,7 +548,8 @@ def main():
         chi = [(ns[i + 1] - ns[i - 1]) / (mus[i + 1] - mus[i - 1]) for i in range(1, len(mus) - 1)]
         mu_scan = dict(workload="Hubbard 6x12 cylinder, U=8, U(1)xU(1) D=%d, d_beta=%g, mu = %s"
                        % (D4, c4["dbeta"], ", ".join("%.4g" % m for m in mus)),
-                       instances=len(mus), batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
+                       instances=len(mus), folded_sites=sum(forms4),
+                       batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
                        single_instance_s_per_step=s_single, speedup_vs_one_at_a_time=s_single * len(mus) / s_batch,
                        tflops_alg=fl / args.steps / s_batch / 1e12,
                        beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens],
@@ -422,6 +561,9 @@ def main():
                             precision=PREC["fp32"])
             print("init mu-scan fp32", file=sys.stderr, flush=True)
             s32 = [T.State.init(T.model(c4["W"], c4["L"], c4["geometry"], c4["t"], c4["U"], mu), o32) for mu in mus]
+            f32 = s32[0].tune_apply(args.apply_form)
+            for st in s32[1:]:
+                st.tune_apply(3, f32)
             h32 = [st.h for st in s32]
             T.tdvp_sweep_batch(h32, c4["dbeta"])
             torch.cuda.synchronize()
@@ -490,14 +632,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t_apply, fl_apply = cpu_baseline(args.cpu_D, DH)
-        rate = fl_apply / t_apply
-        est = dense_sweep_flops(dims, DH, c["krylov"]) / rate
-        cpu = dict(value=est, unit="s/step", cores=nthreads, kind="oracle",
-                   sample="one dense oracle H_eff apply at D=%d (%.3g flop, %.2f s, %.3g flop/s) scaled by the "
-                          "dense-equivalent flops of one sweep of the same bond dimensions (%.3g flop)"
-                          % (args.cpu_D, fl_apply, t_apply, rate, dense_sweep_flops(dims, DH, c["krylov"])))
+        cpu = cpu_baseline(c, D, args.sector_cap)
 
     line = {
         "metric": "TDVP beta-sweep s/step & H_eff TFLOP/s (FP64 vs split-BF16) at D=2000",
@@ -512,13 +647,19 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16x6": "bf16x6+f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "Hubbard %dx%d %s, U=%g, mu=%g, U(1)xU(1) D=%d, d_beta=%g, Krylov %d"
+        "config": {"workload": "Hubbard %dx%d %s, U=%g, mu=%g, U(1)xU(1) D=%d (%s), d_beta=%g, Krylov %d"
                    % (c["W"], c["L"], "cylinder" if c["geometry"] == 1 else "open square", c["U"], c["mu"], D,
+                      "sector cap %d" % args.sector_cap if args.sector_cap else "no sector cap",
                       c["dbeta"], c["krylov"]),
+                   "sector_cap": args.sector_cap,
                    "n_sites": n_sites, "max_bond": max(dims), "parallelism": "single GPU"},
         "sweep": {"precision": args.precision, "flops_alg_per_step": flops_step,
                   "tflops_alg": flops_step / s_per_step / 1e12,
                   "applies_per_step": applies_step, "applies_per_s": applies_step / s_per_step,
+                  "launches_per_step": launches_step,
+                  "apply_min_bytes_per_step": bytes_min_step,
+                  "phase_ms_per_step": phases,
+                  "apply_forms": forms_info,
                   "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
                   "thermo": thermo, "other_precisions": mixed},
         "heff": {"D": Dh, "D_H": DH, **heff},

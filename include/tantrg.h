@@ -113,6 +113,15 @@ typedef struct {
   int n_applies;           /* site + bond effective-Hamiltonian applies */
   int n_exps;              /* local exponentials */
   double max_krylov_err;   /* max a-posteriori Lanczos estimate beta_K |[exp(tT)]_{K,1}| */
+  double bytes_min;        /* minimum HBM bytes of the applies: 8 (|L| + |R| + 2 |x|) per apply (each operand
+                              read once, the result written once; x the site tensor or bond matrix) */
+  /* device milliseconds per phase, from HIP events around every occurrence
+     (zeros unless tt_phase_timing is on): site applies (the MPO folded into the
+     left environment included), bond applies, the Lanczos vector work of the
+     local exponentials (their time minus their applies), QR/LQ, environment
+     updates, absorbs */
+  double t_heff, t_bond, t_lanczos, t_qr, t_env, t_absorb;
+  long long n_launches;    /* kernels enqueued (a replayed sweep graph counts the launches it holds) */
 } tt_sweep_stats;
 
 /* Default options: D=64, symmetry=1, beta0=1e-2, taylor_order=1, K=8,
@@ -143,6 +152,21 @@ int tdvp_sweep(tt_state* state, double dbeta, tt_sweep_stats* stats);
  * tdvp_sweep calls bit for bit.  A state may appear only once (TT_EINVAL).
  * stats (may be NULL) are summed. */
 int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* stats);
+
+/* How each site applies H^(1) (SM Fig. optimalB(c)); the result is the same
+ * up to rounding.  Form 0 is the contraction order of SM Fig. Lanczos: T1 =
+ * L.A, the sparse MPO stage into T2, then .R.  Form 1 folds the MPO into the
+ * left environment once per environment (LW^{b,so,si} = sum_a W[a,so,si,b]
+ * L^a) and applies T2 = LW.A, then .R: no T1 and no per-apply MPO stage, but
+ * grouped GEMMs one charge sector wide.  mode 0 or 1 sets that form at every
+ * site; mode 2 times both forms of every site's apply on the device (the
+ * fold's build spread over the 2K + 1 uses it serves per sweep) and keeps the
+ * faster; mode 3 sets the forms from host_forms (N entries, each 0 or 1;
+ * e.g. one instance's tuned choice for a whole batch).  The state starts in
+ * form 0.  For modes 0-2, host_forms (may be NULL) receives the N chosen
+ * forms.  States advance together in tdvp_sweep_batch only with equal forms.
+ * Synchronises. */
+int tt_tune_apply(tt_state* state, int mode, int* host_forms);
 
 /* Bilayer observables of SM Sec. II.A at beta_phys = 2*beta: lnZ = 2 Lambda,
  * E from one H^(1) apply at the canonical centre, and the single-layer
@@ -288,6 +312,13 @@ int tt_heff_last_timing(double* host_ms4);
  * anew.  Results equal those of uncaptured sweeps bit for bit.  Not used
  * while profiling is enabled, nor by tdvp_sweep_batch. */
 int tt_sweep_graphs(int on);
+
+/* Per-phase device timing of sweeps that return stats (default off): every
+ * phase occurrence of tdvp_sweep / tdvp_sweep_batch is bracketed by HIP events
+ * on the library stream and summed into the t_* fields of tt_sweep_stats
+ * (sweep graphs are not used meanwhile).  The events cost host time per phase,
+ * so timed runs leave it off. */
+int tt_phase_timing(int on);
 
 /* Opt-in kernel timing: when on, every launch of the grouped GEMM, the MPO
  * (W) stage and the QR kernels is bracketed by HIP events on its stream, and

@@ -42,5 +42,39 @@ def build(verbose=False):
     return OUT
 
 
+def build_host_sanitized(out_dir, verbose=False):
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    on its host code only (device code is built as usual): the planners, the
+    MPO and start builders and the host-side bounds checks run instrumented.
+    Load it in a process that preloads the ASan runtime (asan_runtime())."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+    os.makedirs(out_dir, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(out_dir, src + ".o")
+        if src.endswith(".cpp"):
+            cmd = [hipcc, "-O1", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj] + san
+        else:
+            cmd = [hipcc] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + san
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    out = os.path.join(out_dir, "libtantrg.so")
+    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", out] + objs + san
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def asan_runtime():
+    """Path of the compiler's shared ASan runtime (for LD_PRELOAD)."""
+    clang = os.path.join(os.path.dirname(os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")), "..", "lib", "llvm",
+                         "bin", "clang")
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

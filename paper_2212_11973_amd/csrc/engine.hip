@@ -15,8 +15,10 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
 
 #include "kernels.h"
 
@@ -27,6 +29,7 @@ namespace {
 thread_local std::string g_err;
 hipStream_t g_stream = nullptr;
 bool g_graphs = false;   // sweeps captured into hipGraphs and replayed (tt_sweep_graphs)
+bool g_phase = false;    // per-phase device timing of sweeps with stats (tt_phase_timing)
 tt_alloc_fn g_alloc = nullptr;
 tt_free_fn g_free = nullptr;
 void* g_alloc_ctx = nullptr;
@@ -37,12 +40,19 @@ void* g_alloc_ctx = nullptr;
     if (e_ != hipSuccess) throw Error(TT_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+// Allocations made through a registered allocator, with the free function
+// and context that must release them (the registration may change meanwhile).
+std::mutex g_alloc_mu;
+std::unordered_map<void*, std::pair<tt_free_fn, void*>> g_custom;
+
 void* dalloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   void* p = nullptr;
   if (g_alloc) {
     p = g_alloc(bytes, g_alloc_ctx);
     if (!p) throw Error(TT_ENOMEM, "device allocation failed (custom allocator)");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_custom[p] = {g_free, g_alloc_ctx};
   } else {
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) throw Error(TT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -51,7 +61,16 @@ void* dalloc(size_t bytes) {
 }
 void dfree(void* p) {
   if (!p) return;
-  if (g_free) g_free(p, g_alloc_ctx);
+  std::pair<tt_free_fn, void*> f{nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_custom.find(p);
+    if (it != g_custom.end()) {
+      f = it->second;
+      g_custom.erase(it);
+    }
+  }
+  if (f.first) f.first(p, f.second);
   else (void)hipFree(p);
 }
 template <class T>
@@ -137,6 +156,9 @@ struct tt_state {
   double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr, *U = nullptr;
   double *Sbuf = nullptr, *tmp = nullptr, *kry = nullptr, *wv = nullptr, *qrws = nullptr;
   double* pws = nullptr;                   // partial tiles of K-split GEMMs
+  double* LW = nullptr;                    // the MPO folded into the left environment of site lw_site
+  int lw_site = -1;                        // -1: LW holds no current fold
+  std::vector<char> fold;                  // per site: 1 = apply with the MPO folded into L, 0 = L.A, W, .R
   double *part = nullptr, *lz = nullptr;   // lz: alpha[K] beta[K] hn[K] coeff[K] scal[4] lambda errmax scratch[4]
   double** d_sites = nullptr;
   TraceEntry* d_trace = nullptr;
@@ -146,7 +168,7 @@ struct tt_state {
   double beta = 0.0;
   long long sweeps = 0;
   // statistics of the current call
-  double flops = 0.0, flops_heff = 0.0;
+  double flops = 0.0, flops_heff = 0.0, bytes_min = 0.0;
   int n_applies = 0, n_exps = 0;
 
   // observables given as MPOs (sums of on-site operators, sums of spin
@@ -164,8 +186,9 @@ struct tt_state {
   // with the same step; the host counters of one sweep are kept with it
   struct SweepGraph {
     hipGraphExec_t exec = nullptr;
-    double dbeta = 0.0, flops = 0.0, flops_heff = 0.0;
+    double dbeta = 0.0, flops = 0.0, flops_heff = 0.0, bytes_min = 0.0;
     int n_applies = 0, n_exps = 0;
+    long long n_launches = 0;
   } sg;
 
   double* lam_ptr() { return lz + 4 * kMaxKrylov + 4; }
@@ -175,15 +198,20 @@ struct tt_state {
 };
 
 tt_state::~tt_state() {
+  // work enqueued on this state's buffers (a construction that failed part way
+  // included) must finish before they go back to the allocator
+  (void)hipStreamSynchronize(g_stream);
   for (auto& p : plans) {
     free_plan(p.s1); free_plan(p.s3); free_plan(p.el); free_plan(p.r1); free_plan(p.r3);
     free_plan(p.absL); free_plan(p.absR); free_plan(p.b1); free_plan(p.b2);
     free_plan(p.w2); free_plan(p.wr); free_plan(p.qr); free_plan(p.lq);
+    free_plan(p.lw); free_plan(p.t2zero);
+    for (auto& g : p.s1w) free_plan(g);
   }
   for (auto p : A) dfree(p);
   for (auto p : Lenv) dfree(p);
   for (auto p : Renv) dfree(p);
-  for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws}) dfree(p);
+  for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws, LW}) dfree(p);
   dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
   if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
   for (auto& kv : obs) {
@@ -247,22 +275,128 @@ void add_flops(const Batch& b, double f, bool heff) {
   }
 }
 
+// -------------------------------------------------------------- phase clock
+// With tt_phase_timing on, a sweep that returns stats brackets every phase
+// occurrence with HIP events on the library stream: site applies (the MPO
+// fold included), bond applies, whole local exponentials, QR/LQ, environment
+// updates and absorbs.  The Lanczos vector work is an exponential's time
+// minus its applies.
+enum Phase { PH_HEFF = 0, PH_BOND, PH_EXP, PH_QR, PH_ENV, PH_ABSORB, PH_COUNT };
+bool g_phase_on = false;   // set for the duration of a sweep whose stats are wanted
+struct PhaseRec { hipEvent_t a, b; int ph; };
+std::vector<PhaseRec> g_phase_recs;
+std::vector<hipEvent_t> g_phase_pool;
+hipEvent_t phase_event() {
+  hipEvent_t e;
+  if (!g_phase_pool.empty()) {
+    e = g_phase_pool.back();
+    g_phase_pool.pop_back();
+    return e;
+  }
+  HIPX(hipEventCreate(&e));
+  return e;
+}
+struct PhaseScope {
+  int ph;
+  hipEvent_t a = nullptr;
+  explicit PhaseScope(int p) : ph(p) {
+    if (!g_phase_on) return;
+    a = phase_event();
+    HIPX(hipEventRecord(a, ST()));
+  }
+  ~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (!g_phase_pool.empty()) {
+      b = g_phase_pool.back();
+      g_phase_pool.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+      g_phase_pool.push_back(a);
+      return;
+    }
+    if (hipEventRecord(b, ST()) != hipSuccess) {
+      g_phase_pool.push_back(a);
+      g_phase_pool.push_back(b);
+      return;
+    }
+    g_phase_recs.push_back({a, b, ph});
+  }
+};
+// device ms per phase since the last read (synchronises the events)
+void phase_read(double out[PH_COUNT]) {
+  for (int i = 0; i < PH_COUNT; ++i) out[i] = 0.0;
+  if (!g_phase_recs.empty()) HIPX(hipEventSynchronize(g_phase_recs.back().b));
+  for (auto& r : g_phase_recs) {
+    float ms = 0.f;
+    HIPX(hipEventElapsedTime(&ms, r.a, r.b));
+    out[r.ph] += ms;
+    g_phase_pool.push_back(r.a);
+    g_phase_pool.push_back(r.b);
+  }
+  g_phase_recs.clear();
+}
+
 // -------------------------------------------------------------- contractions
-void apply_heff1(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
+// LW <- the MPO of site k folded into L_k (once per environment; every apply
+// and the left-environment update of site k read it)
+void build_lw(const Batch& b, int k) {
+  if (b.lead().lw_site == k) return;
+  launch_wstage(b.lead().plans[k].lw, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].lw; }),
+                cst(per_state(b, [&](tt_state& s) { return s.Lenv[k]; })),
+                per_state(b, [](tt_state& s) { return s.LW; }), b.n, ST());
+  for (int i = 0; i < b.n; ++i) b.s[i]->lw_site = k;
+  add_flops(b, b.lead().plans[k].lw.flops, false);
+}
+
+// T2 = LW . x in stage 3's layout: the pass-0 GEMMs, the cleared blocks, then
+// the passes that add the further terms of an output block
+void lw_times(const Batch& b, int k, BPtr<double> x) {
   SitePlan& P = b.lead().plans[k];
   const int prec = b.lead().opts.precision;
   const long long* tabs = b.lead().tabs.dev;
-  launch_gemm(P.s1, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.Lenv[k], x.p[i], s.T1, nullptr}}; }),
-              b.n, prec, pws_of(b), ST());
-  launch_wstage(P.w2, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].w2; }),
-                cst(per_state(b, [](tt_state& s) { return s.T1; })), per_state(b, [](tt_state& s) { return s.T2; }),
-                b.n, ST());
+  for (int j = 0; j < P.n_s1w; ++j) {
+    launch_gemm(P.s1w[j], tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.LW, x.p[i], s.T2, nullptr}}; }),
+                b.n, prec, pws_of(b), ST());
+    if (j == 0)
+      launch_wstage(P.t2zero, BPtr<const WTerm>{}, BPtr<const double>{}, per_state(b, [](tt_state& s) { return s.T2; }),
+                    b.n, ST());
+  }
+  double f = 0.0;
+  for (int j = 0; j < P.n_s1w; ++j) f += P.s1w[j].flops;
+  add_flops(b, f, false);
+}
+
+// H^(1) x at site k in the site's form: the paper's order (T1 = L.x, the W
+// stage into T2, then .R) or, with the MPO folded into L, T2 = LW.x then .R
+void apply_heff1(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
+  PhaseScope ps(PH_HEFF);
+  SitePlan& P = b.lead().plans[k];
+  const int prec = b.lead().opts.precision;
+  const long long* tabs = b.lead().tabs.dev;
+  double f1 = 0.0;
+  if (b.lead().fold[k]) {
+    build_lw(b, k);
+    lw_times(b, k, x);
+    for (int j = 0; j < P.n_s1w; ++j) f1 += P.s1w[j].flops;
+    add_flops(b, -f1, false);   // lw_times counted them as other work: they belong to the apply
+  } else {
+    launch_gemm(P.s1, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.Lenv[k], x.p[i], s.T1, nullptr}}; }),
+                b.n, prec, pws_of(b), ST());
+    launch_wstage(P.w2, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].w2; }),
+                  cst(per_state(b, [](tt_state& s) { return s.T1; })), per_state(b, [](tt_state& s) { return s.T2; }),
+                  b.n, ST());
+    f1 = P.s1.flops + P.w2.flops;
+  }
   launch_gemm(P.s3, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.T2, s.Renv[k + 1], out.p[i], nullptr}}; }),
               b.n, prec, pws_of(b), ST());
-  add_flops(b, P.s1.flops + P.w2.flops + P.s3.flops, true);
+  add_flops(b, f1 + P.s3.flops, true);
+  const tt_state& L = b.lead();
+  const double bmin = 8.0 * (L.env[k].size + L.env[k + 1].size + 2.0 * L.site[k].size);
+  for (int i = 0; i < b.n; ++i) b.s[i]->bytes_min += bmin;
 }
 
 void apply_heff0(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
+  PhaseScope ps(PH_BOND);
   SitePlan& P = b.lead().plans[k];
   const int prec = b.lead().opts.precision;
   const long long* tabs = b.lead().tabs.dev;
@@ -271,23 +405,35 @@ void apply_heff0(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
   launch_gemm(P.b2, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.U, s.Renv[k], out.p[i], nullptr}}; }),
               b.n, prec, pws_of(b), ST());
   add_flops(b, P.b1.flops + P.b2.flops, true);
+  const double bmin = 8.0 * (2.0 * b.lead().env[k].size + 2.0 * b.lead().bmat[k].size);
+  for (int i = 0; i < b.n; ++i) b.s[i]->bytes_min += bmin;
 }
 
-void env_left(const Batch& b, int k) {   // Lenv[k+1] from Lenv[k], A_k (left-canonical), W_k
+void env_left(const Batch& b, int k) {   // Lenv[k+1] from Lenv[k], A_k (left-canonical), W_k, in the site's form
+  PhaseScope ps(PH_ENV);
   SitePlan& P = b.lead().plans[k];
   const int prec = b.lead().opts.precision;
   const long long* tabs = b.lead().tabs.dev;
-  launch_gemm(P.s1, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}; }),
-              b.n, prec, pws_of(b), ST());
-  launch_wstage(P.w2, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].w2; }),
-                cst(per_state(b, [](tt_state& s) { return s.T1; })), per_state(b, [](tt_state& s) { return s.T2; }),
-                b.n, ST());
+  if (b.lead().fold[k]) {
+    build_lw(b, k);
+    lw_times(b, k, per_state(b, [&](tt_state& s) { return s.A[k]; }));
+  } else {
+    launch_gemm(P.s1, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.Lenv[k], s.A[k], s.T1, nullptr}}; }),
+                b.n, prec, pws_of(b), ST());
+    launch_wstage(P.w2, terms_of(b, [&](tt_state& s) -> WPlan& { return s.plans[k].w2; }),
+                  cst(per_state(b, [](tt_state& s) { return s.T1; })), per_state(b, [](tt_state& s) { return s.T2; }),
+                  b.n, ST());
+    add_flops(b, P.s1.flops + P.w2.flops, false);
+  }
   launch_gemm(P.el, tabs, slots_of(b, [&](tt_state& s, int) { return Slots{{s.A[k], s.T2, s.Lenv[k + 1], nullptr}}; }),
               b.n, prec, pws_of(b), ST());
-  add_flops(b, P.s1.flops + P.w2.flops + P.el.flops, false);
+  for (int i = 0; i < b.n; ++i)
+    if (b.s[i]->lw_site == k + 1) b.s[i]->lw_site = -1;
+  add_flops(b, P.el.flops, false);
 }
 
 void env_right(const Batch& b, int k) {  // Renv[k] from Renv[k+1], A_k (right-canonical), W_k
+  PhaseScope ps(PH_ENV);
   SitePlan& P = b.lead().plans[k];
   const int prec = b.lead().opts.precision;
   const long long* tabs = b.lead().tabs.dev;
@@ -305,6 +451,7 @@ void env_right(const Batch& b, int k) {  // Renv[k] from Renv[k+1], A_k (right-c
 // v <- exp(t H) v / ||exp(t H) v||, Lambda += ln ||exp(t H) v||, for every state of the batch
 void lanczos_exp(const Batch& b, double t, BPtr<double> v, long long n,
                  const std::function<void(BPtr<double>, BPtr<double>)>& H) {
+  PhaseScope ps(PH_EXP);
   const tt_state& L = b.lead();
   const int K = L.opts.krylov_dim;
   const double tol = L.opts.krylov_tol;
@@ -346,16 +493,19 @@ void bond_exp(const Batch& b, int k, double t) {
 }
 
 void qr_site(const Batch& b, int k) {
+  PhaseScope ps(PH_QR);
   launch_qr(b.lead().plans[k].qr, b.lead().tabs.dev, per_state(b, [&](tt_state& s) { return s.A[k]; }),
             per_state(b, [](tt_state& s) { return s.Sbuf; }), per_state(b, [](tt_state& s) { return s.qrws; }), b.n,
             ST());
 }
 void lq_site(const Batch& b, int k) {
+  PhaseScope ps(PH_QR);
   launch_qr(b.lead().plans[k].lq, b.lead().tabs.dev, per_state(b, [&](tt_state& s) { return s.A[k]; }),
             per_state(b, [](tt_state& s) { return s.Sbuf; }), per_state(b, [](tt_state& s) { return s.qrws; }), b.n,
             ST());
 }
 void absorb_left(const Batch& b, int k) {   // A_k <- S_k A_k (S on the left bond k)
+  PhaseScope ps(PH_ABSORB);
   SitePlan& P = b.lead().plans[k];
   launch_gemm(P.absL, b.lead().tabs.dev,
               slots_of(b, [&](tt_state& s, int) { return Slots{{s.Sbuf, s.A[k], s.tmp, nullptr}}; }), b.n, TT_FP64,
@@ -365,6 +515,7 @@ void absorb_left(const Batch& b, int k) {   // A_k <- S_k A_k (S on the left bon
   add_flops(b, P.absL.flops, false);
 }
 void absorb_right(const Batch& b, int k) {  // A_k <- A_k S_{k+1}
+  PhaseScope ps(PH_ABSORB);
   SitePlan& P = b.lead().plans[k];
   launch_gemm(P.absR, b.lead().tabs.dev,
               slots_of(b, [&](tt_state& s, int) { return Slots{{s.A[k], s.Sbuf, s.tmp, nullptr}}; }), b.n, TT_FP64,
@@ -386,6 +537,7 @@ void normalize_site(const Batch& b, int k) {
 void sweep_once(const Batch& b, double dbeta) {
   const int N = b.lead().N;
   const double tau = 0.5 * dbeta;
+  for (int i = 0; i < b.n; ++i) b.s[i]->lw_site = -1;   // the first apply folds L_0 again
   for (int k = 0; k < N - 1; ++k) {
     site_exp(b, k, -tau);
     qr_site(b, k);
@@ -457,6 +609,7 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   const bool wave = s.opts.precision == TT_FP64 || s.opts.precision == TT_FP32;
   for (auto& P : s.plans) {
     for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = wave;
+    for (GemmPlan& g : P.s1w) g.wave_ok = wave;
     P.absL.wave_ok = P.absR.wave_ok = true;
     if (s.opts.precision == TT_FP32) {
       // FP32 mode keeps the intermediates of H_eff and of the environment
@@ -465,6 +618,8 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
       P.s3.slot_f32[0] = true;                      // T2 read
       P.el.slot_f32[1] = P.r3.slot_f32[1] = true;   // T2, Z read
       P.w2.f32 = P.wr.f32 = true;
+      for (GemmPlan& g : P.s1w) g.slot_f32[2] = true;   // T2 written (and read back by the later passes)
+      P.t2zero.f32 = true;
     }
   }
 }
@@ -473,22 +628,26 @@ void alloc_state(tt_state& s) {
   const int N = s.N;
   hipStream_t st = ST();
   s.tabs.dev = upload(s.tabs.host, st);
-  long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, qw = 0;
+  long long t1 = 0, lw = 0, t2 = 0, y = 0, z = 0, u = 0, qw = 0;
   for (auto& P : s.plans) {
     const std::vector<long long>* T = &s.tabs.host;
     upload_plan(P.s1, T, st); upload_plan(P.s3, T, st); upload_plan(P.el, T, st);
     upload_plan(P.r1, T, st); upload_plan(P.r3, T, st); upload_plan(P.absL, T, st); upload_plan(P.absR, T, st);
     upload_plan(P.b1, T, st); upload_plan(P.b2, T, st);
-    upload_plan(P.w2, st); upload_plan(P.wr, st);
+    for (int j = 0; j < P.n_s1w; ++j) upload_plan(P.s1w[j], T, st);
+    upload_plan(P.w2, st); upload_plan(P.lw, st); upload_plan(P.t2zero, st); upload_plan(P.wr, st);
     upload_plan(P.qr, st); upload_plan(P.lq, st);
-    t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size);
+    t1 = std::max(t1, P.t1_size); lw = std::max(lw, P.lw_size); t2 = std::max(t2, P.t2_size);
     y = std::max(y, P.y_size); z = std::max(z, P.z_size); u = std::max(u, P.u_size);
     qw = std::max(qw, std::max(P.qr.ws_size + P.qr.lds_ws, P.lq.ws_size + P.lq.lds_ws));
   }
   long long pw = 1;
   for (auto& P : s.plans)
+  {
     for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2})
       pw = std::max(pw, g->pws_size);
+    for (int j = 0; j < P.n_s1w; ++j) pw = std::max(pw, P.s1w[j].pws_size);
+  }
   s.pws = (double*)dalloc(8 * pw);
   s.max_site = 0;
   for (auto& l : s.site) s.max_site = std::max(s.max_site, l.size);
@@ -508,8 +667,12 @@ void alloc_state(tt_state& s) {
   for (int k = 0; k <= N; ++k) {
     s.Lenv[k] = (double*)dalloc(8 * s.env[k].size);
     s.Renv[k] = (double*)dalloc(8 * s.env[k].size);
+    launch_fill(s.Lenv[k], 0.0, s.env[k].size, st);   // defined contents before the first sweep builds them
   }
   s.T1 = (double*)dalloc(8 * std::max(t1, 1LL));
+  s.LW = (double*)dalloc(8 * std::max(lw, 1LL));
+  s.lw_site = -1;
+  s.fold.assign(N, 0);
   s.T2 = (double*)dalloc(8 * std::max(t2, 1LL));
   s.Y = (double*)dalloc(8 * std::max(y, 1LL));
   s.Z = (double*)dalloc(8 * std::max(z, 1LL));
@@ -615,6 +778,7 @@ void canonicalise_and_envs(tt_state& s) {
     absorb_right(b, k - 1);
   }
   launch_fill(s.lam_ptr(), 0.0, 1, ST());
+  s.lw_site = -1;
   normalize_site(b, 0);
   set_unit_env(s.Lenv[0], ST());
   set_unit_env(s.Renv[N], ST());
@@ -817,9 +981,9 @@ long long check_obs_plans(const tt_state& s, const Mpo& m, std::vector<SitePlan>
 long long check_sweep_plans(tt_state& s, std::string& rep) {
   long long bad = 0;
   const int N = s.N;
-  long long t1 = 0, t2 = 0, y = 0, z = 0, u = 0, msite = 0, mb = 0;
+  long long t1 = 0, lw = 0, t2 = 0, y = 0, z = 0, u = 0, msite = 0, mb = 0;
   for (auto& P : s.plans) {
-    t1 = std::max(t1, P.t1_size); t2 = std::max(t2, P.t2_size); y = std::max(y, P.y_size);
+    t1 = std::max(t1, P.t1_size); lw = std::max(lw, P.lw_size); t2 = std::max(t2, P.t2_size); y = std::max(y, P.y_size);
     z = std::max(z, P.z_size); u = std::max(u, P.u_size);
   }
   for (auto& l : s.site) msite = std::max(msite, l.size);
@@ -828,12 +992,18 @@ long long check_sweep_plans(tt_state& s, std::string& rep) {
   for (int k = 0; k < N; ++k) {
     SitePlan& P = s.plans[k];
     for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.absL, &P.absR, &P.b1, &P.b2}) tile_plan(*g, &T);
+    for (int j = 0; j < P.n_s1w; ++j) tile_plan(P.s1w[j], &T);
     long long ns = s.site[k].size, el = s.env[k].size, er = s.env[k + 1].size;
-    long long s1[kSlots] = {el, ns, t1, 0}, s3[kSlots] = {t2, er, ns, 0}, se[kSlots] = {ns, t2, er, 0};
+    long long s1w[kSlots] = {lw, ns, t2, 0}, s1[kSlots] = {el, ns, t1, 0};
+    long long s3[kSlots] = {t2, er, ns, 0}, se[kSlots] = {ns, t2, er, 0};
     long long r1[kSlots] = {er, ns, y, 0}, r3[kSlots] = {ns, z, el, 0};
     long long aL[kSlots] = {s.bmat[k].size, ns, msite, 0}, aR[kSlots] = {ns, s.bmat[k + 1].size, msite, 0};
     long long b1[kSlots] = {el, s.bmat[k].size, u, 0}, b2[kSlots] = {u, el, s.bmat[k].size, 0};
     bad += check_gemm(P.s1, T, s1, "s1", rep);
+    bad += check_w(P.w2, P.t1_size, P.t2_size, "w2", rep);
+    for (int j = 0; j < P.n_s1w; ++j) bad += check_gemm(P.s1w[j], T, s1w, "s1w", rep);
+    bad += check_w(P.lw, el, P.lw_size, "lw", rep);
+    bad += check_w(P.t2zero, 0, t2, "t2zero", rep);
     bad += check_gemm(P.s3, T, s3, "s3", rep);
     bad += check_gemm(P.el, T, se, "el", rep);
     bad += check_gemm(P.r1, T, r1, "r1", rep);
@@ -842,7 +1012,6 @@ long long check_sweep_plans(tt_state& s, std::string& rep) {
     bad += check_gemm(P.absR, T, aR, "absR", rep);
     bad += check_gemm(P.b1, T, b1, "b1", rep);
     bad += check_gemm(P.b2, T, b2, "b2", rep);
-    bad += check_w(P.w2, P.t1_size, P.t2_size, "w2", rep);
     bad += check_w(P.wr, P.y_size, P.z_size, "wr", rep);
     bad += check_qr(P.qr, T, ns, s.bmat[k + 1].size, "qr", rep);
     bad += check_qr(P.lq, T, ns, s.bmat[k].size, "lq", rep);
@@ -922,7 +1091,8 @@ std::vector<SitePlan> make_obs_plans(const tt_state& s, const Mpo& m, const Mpo&
   const auto W = obs_tensors(m), Wp = obs_tensors(pat);
   std::vector<SitePlan> plans;
   for (int k = 0; k < s.N; ++k) {
-    SitePlan P = build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, qH[k], qH[k + 1], W[k], Wp[k], tabs, m.ld == 16);
+    SitePlan P = build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, qH[k], qH[k + 1], W[k], Wp[k], tabs, m.ld == 16,
+                                 false);
     for (GemmPlan* g : {&P.s1, &P.s3, &P.r1, &P.r3}) g->wave_ok = true;
     plans.push_back(std::move(P));
   }
@@ -1073,11 +1243,23 @@ void fill_stats(tt_state& s, tt_sweep_stats* st, double secs) {
   st->seconds += secs;
   st->flops_alg += s.flops;
   st->flops_heff += s.flops_heff;
+  st->bytes_min += s.bytes_min;
   st->n_applies += s.n_applies;
   st->n_exps += s.n_exps;
   st->max_krylov_err = std::max(st->max_krylov_err, err);
 }
-void reset_counters(tt_state& s) { s.flops = s.flops_heff = 0.0; s.n_applies = s.n_exps = 0; }
+// per-phase device time of the call (zeros unless phase timing was on)
+void fill_phases(tt_sweep_stats* st) {
+  double ph[PH_COUNT];
+  phase_read(ph);
+  st->t_heff = ph[PH_HEFF];
+  st->t_bond = ph[PH_BOND];
+  st->t_lanczos = std::max(0.0, ph[PH_EXP] - ph[PH_HEFF] - ph[PH_BOND]);
+  st->t_qr = ph[PH_QR];
+  st->t_env = ph[PH_ENV];
+  st->t_absorb = ph[PH_ABSORB];
+}
+void reset_counters(tt_state& s) { s.flops = s.flops_heff = s.bytes_min = 0.0; s.n_applies = s.n_exps = 0; }
 
 bool same_gemm(const GemmPlan& x, const GemmPlan& y) {
   return same_bytes(x.probs, y.probs) && same_bytes(x.tiles, y.tiles) && same_bytes(x.jobs, y.jobs) &&
@@ -1115,7 +1297,12 @@ bool same_plans(const tt_state& a, const tt_state& b) {
                     std::make_pair(&P.r1, &Q.r1), std::make_pair(&P.r3, &Q.r3), std::make_pair(&P.absL, &Q.absL),
                     std::make_pair(&P.absR, &Q.absR), std::make_pair(&P.b1, &Q.b1), std::make_pair(&P.b2, &Q.b2)})
       if (!same_gemm(*pr.first, *pr.second)) return false;
-    if (!same_w(P.w2, Q.w2) || !same_w(P.wr, Q.wr) || !same_qr(P.qr, Q.qr) || !same_qr(P.lq, Q.lq)) return false;
+    if (!same_w(P.lw, Q.lw) || !same_w(P.t2zero, Q.t2zero) || !same_w(P.wr, Q.wr) || !same_qr(P.qr, Q.qr) ||
+        !same_qr(P.lq, Q.lq) || P.n_s1w != Q.n_s1w)
+      return false;
+    for (int j = 0; j < P.n_s1w; ++j)
+      if (!same_gemm(P.s1w[j], Q.s1w[j])) return false;
+    if (!same_gemm(P.s1, Q.s1) || !same_w(P.w2, Q.w2) || a.fold[k] != b.fold[k]) return false;
   }
   return true;
 }
@@ -1141,7 +1328,7 @@ HeffPlans heff_plans(int Dl, int Dr, int DH) {
   // the plan's W stage is replaced by a grouped GEMM reading W from device memory;
   // an all-zero W keeps the sparse W-stage plan empty
   std::vector<double> Wz((size_t)DH * 16 * DH, 0.0);
-  h.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, Wz, h.tabs);
+  h.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, Wz, h.tabs, false, false);
   // W stage as GEMMs: for each (x, sigma'): T2[(so,b)][y] = sum_(a,si) W[(so,b),(a,si)] T1[(a,si)][y]
   std::vector<long long> am, ak, bk, cm;
   for (int so = 0; so < 4; ++so)
@@ -1447,11 +1634,13 @@ void sweep_graph(tt_state& s, double dbeta) {
       throw Error(TT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     G.dbeta = dbeta;
-    G.flops = s.flops; G.flops_heff = s.flops_heff; G.n_applies = s.n_applies; G.n_exps = s.n_exps;
+    G.flops = s.flops; G.flops_heff = s.flops_heff; G.bytes_min = s.bytes_min; G.n_applies = s.n_applies;
+    G.n_exps = s.n_exps;
   } else {
     s.beta += dbeta;
     s.sweeps++;
-    s.flops = G.flops; s.flops_heff = G.flops_heff; s.n_applies = G.n_applies; s.n_exps = G.n_exps;
+    s.flops = G.flops; s.flops_heff = G.flops_heff; s.bytes_min = G.bytes_min; s.n_applies = G.n_applies;
+    s.n_exps = G.n_exps;
   }
   HIPX(hipGraphLaunch(G.exec, g_stream));
 }
@@ -1461,16 +1650,27 @@ int tdvp_sweep(tt_state* s, double dbeta, tt_sweep_stats* stats) {
   TT_REQUIRE(s, TT_EINVAL, "null state");
   TT_REQUIRE(std::isfinite(dbeta), TT_EINVAL, "dbeta must be finite");
   reset_counters(*s);
+  g_phase_on = g_phase && stats;
+  struct PhaseOff { ~PhaseOff() { g_phase_on = false; } } phase_off;
+  const long long l0 = launch_count();
+  long long launches = 0;
   auto t0 = std::chrono::steady_clock::now();
-  if (g_graphs && !prof_enabled())
+  if (g_graphs && !prof_enabled() && !g_phase_on) {
+    const bool replay = s->sg.exec && s->sg.dbeta == dbeta;
     sweep_graph(*s, dbeta);
-  else
+    launches = replay ? s->sg.n_launches : launch_count() - l0;
+    if (!replay) s->sg.n_launches = launches;
+  } else {
     sweep_once(batch_of(*s), dbeta);
+    launches = launch_count() - l0;
+  }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     HIPX(hipStreamSynchronize(ST()));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(*s, stats, secs);
+    fill_phases(stats);
+    stats->n_launches = launches;
   }
   ABI_END
 }
@@ -1481,6 +1681,9 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
   for (int i = 0; i < n; ++i) TT_REQUIRE(states[i], TT_EINVAL, "null state in batch");
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < i; ++j) TT_REQUIRE(states[i] != states[j], TT_EINVAL, "a state appears twice in the batch");
+  g_phase_on = g_phase && stats;
+  struct PhaseOff { ~PhaseOff() { g_phase_on = false; } } phase_off;
+  const long long l0 = launch_count();
   auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < n; ++i) reset_counters(*states[i]);
   // consecutive states with identical plans run together, up to kMaxBatch per launch
@@ -1497,7 +1700,68 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
     HIPX(hipStreamSynchronize(ST()));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int i = 0; i < n; ++i) fill_stats(*states[i], stats, i == 0 ? secs : 0.0);
+    fill_phases(stats);
+    stats->n_launches = launch_count() - l0;
   }
+  ABI_END
+}
+
+int tt_tune_apply(tt_state* s, int mode, int* host_forms) {
+  ABI_BEGIN
+  TT_REQUIRE(s, TT_EINVAL, "null state");
+  TT_REQUIRE(mode >= 0 && mode <= 3, TT_EINVAL, "tt_tune_apply: mode must be 0, 1, 2 or 3");
+  const int N = s->N;
+  if (mode < 2) {
+    s->fold.assign(N, (char)mode);
+  } else if (mode == 3) {
+    TT_REQUIRE(host_forms, TT_EINVAL, "tt_tune_apply: mode 3 needs the forms");
+    for (int k = 0; k < N; ++k)
+      TT_REQUIRE(host_forms[k] == 0 || host_forms[k] == 1, TT_EINVAL, "tt_tune_apply: forms must be 0 or 1");
+    for (int k = 0; k < N; ++k) s->fold[k] = (char)host_forms[k];
+    s->lw_site = -1;
+  } else {
+    // time both forms of each site's apply on the device (the site tensor as
+    // input, the scratch vector as output; the state is not changed); the
+    // fold's one-off build is spread over the 2K + 1 uses it has per sweep
+    const int reps = 3;
+    const Batch b = batch_of(*s);
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIPX(hipEventCreate(&e));
+    struct Ev { hipEvent_t* e; ~Ev() { for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]); } } guard{ev};
+    const double uses = 2.0 * s->opts.krylov_dim + 1.0;
+    const double f0 = s->flops, fh0 = s->flops_heff, bm0 = s->bytes_min;
+    const int na0 = s->n_applies;
+    for (int k = 0; k < N; ++k) {
+      BPtr<double> x = one(s->A[k]), y = one(s->wv);
+      s->fold[k] = 0;
+      apply_heff1(b, k, x, y);   // warm
+      HIPX(hipEventRecord(ev[0], ST()));
+      for (int r = 0; r < reps; ++r) apply_heff1(b, k, x, y);
+      HIPX(hipEventRecord(ev[1], ST()));
+      s->fold[k] = 1;
+      s->lw_site = -1;
+      build_lw(b, k);
+      HIPX(hipEventRecord(ev[2], ST()));
+      apply_heff1(b, k, x, y);   // warm
+      HIPX(hipEventRecord(ev[3], ST()));
+      for (int r = 0; r < reps; ++r) apply_heff1(b, k, x, y);
+      HIPX(hipEventRecord(ev[4], ST()));
+      HIPX(hipEventSynchronize(ev[4]));
+      float t3 = 0.f, tb = 0.f, tf = 0.f;
+      HIPX(hipEventElapsedTime(&t3, ev[0], ev[1]));
+      HIPX(hipEventElapsedTime(&tb, ev[1], ev[2]));
+      HIPX(hipEventElapsedTime(&tf, ev[3], ev[4]));
+      s->fold[k] = (tf / reps + tb / uses < t3 / reps) ? 1 : 0;
+    }
+    s->lw_site = -1;
+    s->flops = f0; s->flops_heff = fh0; s->bytes_min = bm0; s->n_applies = na0;
+  }
+  if (s->sg.exec) {   // a captured sweep holds the old forms
+    HIPX(hipGraphExecDestroy(s->sg.exec));
+    s->sg.exec = nullptr;
+  }
+  if (host_forms && mode != 3)
+    for (int k = 0; k < N; ++k) host_forms[k] = s->fold[k];
   ABI_END
 }
 
@@ -1750,6 +2014,7 @@ int tt_state_load(const char* path, tt_state** out) {
   }
   HIPX(hipMemcpyAsync(s->lam_ptr(), &lam, 8, hipMemcpyHostToDevice, ST()));
   set_unit_env(s->Lenv[0], ST());
+  s->lw_site = -1;
   set_unit_env(s->Renv[s->N], ST());
   for (int k = s->N - 1; k >= 1; --k) env_right(batch_of(*s), k);
   s->beta = beta;
@@ -1890,6 +2155,12 @@ int tt_model_bond_sectors(const tt_model* model, const tt_options* opts, int k, 
 int tt_sweep_graphs(int on) {
   ABI_BEGIN
   g_graphs = on != 0;
+  ABI_END
+}
+
+int tt_phase_timing(int on) {
+  ABI_BEGIN
+  g_phase = on != 0;
   ABI_END
 }
 

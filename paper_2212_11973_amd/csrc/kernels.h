@@ -20,6 +20,9 @@ enum ProfKind {
   PROF_GEMM_REDUCE = PROF_GEMM_CFG0 + kGemmCfgs, PROF_GEMM_WAVE = PROF_GEMM_REDUCE + 1,
   PROF_KINDS = PROF_GEMM_WAVE + 1
 };
+// kernels enqueued by the library since it was loaded (every launch wrapper counts)
+long long launch_count();
+
 void prof_enable(bool on);
 bool prof_enabled();
 // begin an operation; prof_mark closes the dispatch launched since the previous

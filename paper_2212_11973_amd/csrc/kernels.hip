@@ -36,9 +36,13 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 #define HIP_CHECK_LAUNCH()                                                       \
   do {                                                                           \
+    ++g_launches;                                                                \
     hipError_t e_ = hipGetLastError();                                           \
     if (e_ != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e_));        \
   } while (0)
+
+long long g_launches = 0;   // kernels enqueued by this library since load
+long long launch_count() { return g_launches; }
 
 // ------------------------------------------------------------------ profiling
 namespace {

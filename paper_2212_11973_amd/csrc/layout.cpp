@@ -248,10 +248,162 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
   p.ntiles = (int)p.tiles.size();
 }
 
+// LW^{b,so,si}[x', x] = sum_a W[a,so,si,b] L^a[x', x] per bra sector p, and
+// T2^{b,(so,sp)} = sum_si LW^{b,so,si} A^{(si,sp)} written into stage 3's T2
+// layout (rows (p, g', x', s') of the right sector r' = p + Delta(so, sp),
+// columns (b, y) of R's row block r').  For the Hubbard MPOs an output block
+// (b, so) has 1.0-1.3 si terms on average, so T2 costs about the flops of L.A
+// while T1 and the per-apply W stage disappear: the fold runs once per
+// environment.  Problems are keyed by (pass j, l, si, sp): B is the block
+// A^{(si,sp)} of left sector l, A the stacked LW rows of every (p, b, so) whose
+// j-th term is (si, l); rows whose output block lies outside the truncated
+// bond are dropped (the projection onto the kept space, as in the W stage).
+static void build_lw_plans(SitePlan& P, const SiteLayout& S, const Bond& bl, const Bond& br, const Groups& G,
+                           const EnvLayout& EL, const EnvLayout& ER, const std::vector<Q>& qHl,
+                           const std::vector<Q>& qHr, const std::vector<double>& W, const std::vector<double>& Wp,
+                           const std::vector<long long>& t2base, const std::vector<std::array<int, 9>>& rowpos2,
+                           SiteTables& tabs) {
+  const int DHl = (int)qHl.size(), DHr = (int)qHr.size();
+  // charge of the ket operator |so><si| in the block structure's projection:
+  // Delta(4 so + sp) - Delta(4 si + sp) for any ancilla sp
+  auto dq = [&](int so, int si) { return subq(G.delta[G.group_of[4 * so]], G.delta[G.group_of[4 * si]]); };
+  auto wat = [&](const std::vector<double>& T, int a, int so, int si, int b) {
+    return T[(size_t)(((long long)a * 4 + so) * 4 + si) * DHr + b];
+  };
+  // groups of every bra sector p: (b, so, si) -> ket sector l and column base in LW
+  struct Grp { int b, so, si, l; long long col; };
+  std::vector<std::vector<Grp>> grp(S.nl);
+  std::vector<long long> lwbase(S.nl, 0), lwK(S.nl, 0);
+  std::vector<int> task_p;   // bra sector of every LW task
+  long long pos = 0;
+  for (int p = 0; p < S.nl; ++p) {
+    long long c = 0;
+    for (int b = 0; b < DHr; ++b)
+      for (int so = 0; so < 4; ++so)
+        for (int si = 0; si < 4; ++si) {
+          const Q ql = subq(addq(bl.secs[p].q, dq(so, si)), qHr[b]);
+          const int l = bl.find(ql);
+          if (l < 0) continue;
+          WTask t;
+          t.t0 = (int)P.lw.terms.size();
+          for (int a = 0; a < DHl; ++a) {
+            const double w = wat(W, a, so, si, b);
+            if (w == 0.0 && wat(Wp, a, so, si, b) == 0.0) continue;
+            TT_REQUIRE(EL.csec[p][a] == l, TT_EINVAL, "plan: MPO entry breaks charge conservation (LW)");
+            WTerm tm;
+            tm.src = EL.base[p] + EL.colb[p][a];
+            tm.ssi = EL.K[p];
+            tm.ssj = 1;
+            tm.w = w;
+            P.lw.terms.push_back(tm);
+            P.lw.widx.push_back((((long long)a * 4 + so) * 4 + si) * DHr + b);
+          }
+          t.nt = (int)P.lw.terms.size() - t.t0;
+          if (t.nt == 0) continue;
+          grp[p].push_back({b, so, si, l, c});
+          t.dst = pos + c;   // lwbase[p] == pos while p's columns are laid out
+          t.dsi = 0;         // p's row width, set once it is known
+          t.dsj = 1;
+          t.ni = S.dl[p];
+          t.nj = bl.secs[l].dim;
+          P.lw.tasks.push_back(t);
+          task_p.push_back(p);
+          c += bl.secs[l].dim;
+        }
+    lwbase[p] = pos;
+    lwK[p] = c;
+    pos += (long long)S.dl[p] * c;
+  }
+  for (size_t i = 0; i < P.lw.tasks.size(); ++i) P.lw.tasks[i].dsi = lwK[task_p[i]];
+  P.lw_size = pos;
+  for (auto& t : P.lw.tasks) P.lw.flops += 2.0 * t.nt * (double)t.ni * t.nj;
+
+  // term lists of every output block (p, b, so, sp): si ascending, where the
+  // group exists and A^{(si,sp)} has a block in left sector l
+  struct Row { int p, b, so, sp, pass; const Grp* g; };
+  std::vector<Row> rows;
+  std::vector<char> written;   // per (p, b, s_out)
+  auto widx3 = [&](int p, int b, int s) { return ((size_t)p * DHr + b) * 16 + s; };
+  written.assign((size_t)S.nl * DHr * 16, 0);
+  for (int p = 0; p < S.nl; ++p)
+    for (int b = 0; b < DHr; ++b)
+      for (int so = 0; so < 4; ++so)
+        for (int sp = 0; sp < 4; ++sp) {
+          const int s_out = 4 * so + sp, g_out = G.group_of[s_out];
+          const int rq = S.rsec[p][g_out];
+          if (rq < 0 || ER.csec[rq][b] < 0) continue;   // T2 has no such block
+          int j = 0;
+          for (const Grp& gr : grp[p]) {
+            if (gr.b != b || gr.so != so) continue;
+            const int s_in = 4 * gr.si + sp;
+            if (S.rsec[gr.l][G.group_of[s_in]] < 0) continue;
+            TT_REQUIRE(S.rsec[gr.l][G.group_of[s_in]] == ER.csec[rq][b], TT_EINVAL, "plan: inconsistent charges (LW)");
+            TT_REQUIRE(j < SitePlan::kMaxLwPasses, TT_EINVAL, "plan: too many MPO terms per output block");
+            rows.push_back({p, b, so, sp, j, &gr});
+            ++j;
+          }
+          if (j > 0) written[widx3(p, b, s_out)] = 1;
+        }
+  // problems keyed by (pass, l, si, sp), rows in (p, b, so) order
+  std::map<std::array<int, 4>, std::vector<const Row*>> probs;
+  for (const Row& r : rows) probs[{r.pass, r.g->l, r.g->si, r.sp}].push_back(&r);
+  P.n_s1w = 0;
+  for (auto& kv : probs) {
+    const int pass = kv.first[0], l = kv.first[1], si = kv.first[2], sp = kv.first[3];
+    const int s_in = 4 * si + sp, g_in = G.group_of[s_in];
+    const int r = S.rsec[l][g_in];
+    std::vector<long long> arow, crow;
+    for (const Row* rw : kv.second) {
+      const int p = rw->p, s_out = 4 * rw->so + sp, g_out = G.group_of[s_out];
+      const int rq = S.rsec[p][g_out];
+      const int ns = (int)G.s[g_out].size();
+      for (int x = 0; x < S.dl[p]; ++x) {
+        arow.push_back(lwbase[p] + (long long)x * lwK[p] + rw->g->col);
+        crow.push_back(t2base[rq] + ((long long)rowpos2[p][g_out] + (long long)x * ns + G.pos_of[s_out]) * ER.K[rq] +
+                       ER.colb[rq][rw->b]);
+      }
+    }
+    GemmProb g = gp((int)arow.size(), br.secs[r].dim, S.dl[l], 0, 1, 2);
+    g.tam = tabs.add(arow); g.sak = 1;
+    g.offB = S.base[l] + S.colb[l][g_in] + (long long)G.pos_of[s_in] * br.secs[r].dim;
+    g.sbk = S.C[l]; g.sbn = 1;
+    g.tcm = tabs.add(crow);
+    g.beta = pass == 0 ? 0.0 : 1.0;
+    add_prob(P.s1w[pass], g);
+    P.n_s1w = std::max(P.n_s1w, pass + 1);
+  }
+  for (int j = 0; j < SitePlan::kMaxLwPasses; ++j) P.s1w[j].tag = TAG_LA;
+  // T2 blocks that no term reaches are cleared (a task with no terms writes zeros)
+  for (int rq = 0; rq < (int)br.secs.size(); ++rq)
+    for (int p = 0; p < S.nl; ++p)
+      for (int g = 0; g < G.ng; ++g) {
+        if (S.rsec[p][g] != rq) continue;
+        const int ns = (int)G.s[g].size();
+        for (int si = 0; si < ns; ++si) {
+          const int s_out = G.s[g][si];
+          for (int b = 0; b < DHr; ++b) {
+            const int c = ER.csec[rq][b];
+            if (c < 0 || written[widx3(p, b, s_out)]) continue;
+            WTask t;
+            t.dst = t2base[rq] + (long long)(rowpos2[p][g] + si) * ER.K[rq] + ER.colb[rq][b];
+            t.dsi = (long long)ns * ER.K[rq];
+            t.dsj = 1;
+            t.ni = S.dl[p];
+            t.nj = br.secs[c].dim;
+            t.t0 = 0;
+            t.nt = 0;
+            P.t2zero.tasks.push_back(t);
+          }
+        }
+      }
+  finish_wplan(P.lw);
+  finish_wplan(P.t2zero);
+}
+
 SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<Q>& qHl, const std::vector<Q>& qHr,
                          const std::vector<double>& W, const std::vector<double>& Wp, SiteTables& tabs,
-                         bool super_op) {
+                         bool super_op, bool with_lw) {
   (void)k;
   SitePlan P;
   const int DHl = (int)qHl.size(), DHr = (int)qHr.size();
@@ -364,6 +516,9 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
         }
       }
   }
+
+  // ---------------- the MPO folded into the left environment (ket-only MPOs)
+  if (!super_op && with_lw) build_lw_plans(P, S, bl, br, G, EL, ER, qHl, qHr, W, Wp, t2base, rowpos2, tabs);
 
   // ---------------- stage 3: out rows (p,g',x,s') = T2_r' . R_r'^T ; env-left final
   for (int r = 0; r < nr; ++r) {

@@ -203,11 +203,24 @@ struct SitePlan {
   long long u_size = 0;
   // transfer-matrix trace: per left sector l with a (0,0) group, (row block, col base, d)
   std::vector<std::array<long long, 4>> tr;
+  // The MPO folded into the left environment (ket-only MPOs): lw builds
+  // LW^{b,so,si}[x', x] = sum_a W[a,so,si,b] L^a[x', x] (one block per bra
+  // sector and group (b, so, si) with an entry), then T2 = LW . A runs as the
+  // grouped GEMMs s1w[0..n_s1w): pass j adds the j-th si of every output block
+  // (b, so, sp) of T2 (beta 0 in pass 0), written straight into stage 3's T2
+  // layout; t2zero clears the T2 blocks no term reaches.
+  static constexpr int kMaxLwPasses = 4;
+  WPlan lw, t2zero;
+  GemmPlan s1w[kMaxLwPasses];
+  int n_s1w = 0;
+  long long lw_size = 0;
 };
 
 // slot conventions (kernel argument order)
 //   s1 : 0 = L env, 1 = site vector, 2 = T1
 //   w2 : in = T1, out = T2
+//   lw : in = L env, out = LW
+//   s1w: 0 = LW, 1 = site vector, 2 = T2 (t2zero: out = T2)
 //   s3 : 0 = T2, 1 = R env, 2 = output site vector
 //   el : 0 = site tensor (A^L), 1 = T2, 2 = new L env
 //   r1 : 0 = R env, 1 = site tensor, 2 = Y
@@ -233,7 +246,8 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          const std::vector<double>& W,    // DHl*16*DHr (super_op: DHl*256*DHr)
                          const std::vector<double>& Wp,   // pattern: entries kept when nonzero in W or Wp
                          SiteTables& tabs,
-                         bool super_op = false);          // W acts on the super index s = 4 sigma + sigma'
+                         bool super_op = false,           // W acts on the super index s = 4 sigma + sigma'
+                         bool with_lw = true);            // also plan the MPO folded into L (lw, s1w, t2zero)
 
 
 // tile the problems of a plan (shape per problem)

@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtantrg.so")
+# TANTRG_LIB names another build of the same library (e.g. one with host
+# sanitizers); by default the one built in this package's directory
+LIB_PATH = os.environ.get("TANTRG_LIB") or os.path.join(_HERE, "libtantrg.so")
 
 TT_OK, TT_EINVAL, TT_ENOMEM, TT_EDEVICE, TT_ENUMERIC, TT_EIO = 0, -1, -2, -3, -4, -5
 TT_CHAIN, TT_CYLINDER, TT_OPEN_SQUARE = 0, 1, 2
@@ -24,7 +26,7 @@ SYMBOLS = [
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
     "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function", "thermo_pairing_order",
-    "tt_heff2_apply", "tt_heff_apply_noalloc",
+    "tt_heff2_apply", "tt_heff_apply_noalloc", "tt_phase_timing", "tt_tune_apply",
 ]
 
 
@@ -49,7 +51,10 @@ class tt_observables(C.Structure):
 
 class tt_sweep_stats(C.Structure):
     _fields_ = [("seconds", C.c_double), ("flops_alg", C.c_double), ("flops_heff", C.c_double),
-                ("n_applies", C.c_int), ("n_exps", C.c_int), ("max_krylov_err", C.c_double)]
+                ("n_applies", C.c_int), ("n_exps", C.c_int), ("max_krylov_err", C.c_double),
+                ("bytes_min", C.c_double), ("t_heff", C.c_double), ("t_bond", C.c_double),
+                ("t_lanczos", C.c_double), ("t_qr", C.c_double), ("t_env", C.c_double),
+                ("t_absorb", C.c_double), ("n_launches", C.c_longlong)]
 
 
 class TTError(RuntimeError):
@@ -101,6 +106,8 @@ def lib(init_torch=True):
         L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         L.thermo_spin_correlation.argtypes = [vp, C.c_int, dp, ip]
         L.tt_sweep_graphs.argtypes = [C.c_int]
+        L.tt_phase_timing.argtypes = [C.c_int]
+        L.tt_tune_apply.argtypes = [vp, C.c_int, ip]
         L.thermo_green_function.argtypes = [vp, C.c_double, C.c_double, dp]
         L.thermo_pairing_order.argtypes = [vp, dp, ip]
         L.tt_heff2_apply.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, vp]
@@ -189,6 +196,20 @@ def thermo_local_observables(state):
 def tt_sweep_graphs(on):
     """Replay captured sweeps (hipGraph) for repeated steps of equal dbeta."""
     _check(lib().tt_sweep_graphs(1 if on else 0))
+
+
+def tt_tune_apply(state, mode, forms=None):
+    """Apply form per site (0: L.A, W, .R; 1: MPO folded into L; 2: time both
+    and keep the faster; 3: the given list of forms); returns the forms."""
+    n, _ = tt_state_info(state)
+    arr = (C.c_int * n)(*(forms or []))
+    _check(lib().tt_tune_apply(state, int(mode), arr))
+    return list(arr)
+
+
+def tt_phase_timing(on):
+    """Per-phase device timing (t_heff ... t_absorb) of sweeps that return stats."""
+    _check(lib().tt_phase_timing(1 if on else 0))
 
 
 def thermo_spin_correlation(state, d2):
@@ -340,6 +361,50 @@ def tt_set_stream(stream):
     _check(lib().tt_set_stream(C.c_void_p(stream) if stream else None))
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocator = None   # the registered callbacks (kept alive while registered)
+
+
+def tt_set_allocator(alloc, free):
+    """Register Python callables alloc(nbytes) -> device address (0 on
+    failure) and free(address) as the library's device allocator; None, None
+    restores hipMalloc/hipFree."""
+    global _allocator
+    if alloc is None and free is None:
+        _check(lib().tt_set_allocator(None, None, None))
+        _allocator = None
+        return
+    a = ALLOC_FN(lambda n, ctx: alloc(n) or None)
+    f = FREE_FN(lambda p, ctx: free(p))
+    _check(lib().tt_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None))
+    _allocator = (a, f)
+
+
+def use_torch_memory_and_stream(device=0):
+    """Route the library's device memory through torch's caching allocator and
+    its work onto torch's current stream of `device` (torch stays the owner
+    of both; the library only borrows them)."""
+    import torch
+    dev = torch.device("cuda", device)
+    stream = torch.cuda.current_stream(dev)
+
+    def alloc(n):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(n), dev, stream)
+        except RuntimeError:
+            return 0
+
+    tt_set_allocator(alloc, torch.cuda.caching_allocator_delete)
+    tt_set_stream(stream.cuda_stream)
+
+
+def use_library_memory_and_stream():
+    """Back to hipMalloc/hipFree and the null stream."""
+    tt_set_allocator(None, None)
+    tt_set_stream(None)
+
+
 class State:
     """Owning wrapper of a tt_state handle."""
 
@@ -355,6 +420,9 @@ class State:
 
     def observables(self):
         return thermo_observables(self.h)
+
+    def tune_apply(self, mode=2, forms=None):
+        return tt_tune_apply(self.h, mode, forms)
 
     def local_observables(self):
         return thermo_local_observables(self.h)

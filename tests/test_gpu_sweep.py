@@ -177,7 +177,12 @@ def test_import_export_roundtrip():
 TOL_MIXED = 1e-6
 
 
-@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X6, T.TT_BF16X3])
+BF16X3_MISSES_BAR = pytest.mark.xfail(
+    strict=True, reason="bf16x3 (two BF16 parts per operand, 16 mantissa bits) misses the 1e-6 mixed bar: "
+    "measured on the chain against ED after 100 sweeps, rel err f 1.45e-6, E/N 7.7e-6")
+
+
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X6, pytest.param(T.TT_BF16X3, marks=BF16X3_MISSES_BAR)])
 def test_mixed_precision_chain4_vs_ed(prec):
     c = WL.MODELS["chain4"]
     m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
@@ -191,14 +196,12 @@ def test_mixed_precision_chain4_vs_ed(prec):
     f_ref = -lnZ / (4 * 2 * o["beta"])
     errs = (_rel(o["f"], f_ref), _rel(o["e"], Ebl / 4))
     print("precision", prec, "rel err f, e", errs)
-    if prec != T.TT_BF16X3:
-        assert errs[0] <= TOL_MIXED and errs[1] <= TOL_MIXED, errs
-    else:
-        assert errs[0] <= 1e-4 and errs[1] <= 1e-4, errs
     st.free()
+    assert errs[0] <= TOL_MIXED and errs[1] <= TOL_MIXED, errs
 
 
-@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X6])
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X6, pytest.param(T.TT_BF16X3, marks=pytest.mark.xfail(
+    strict=False, reason="bf16x3 misses the 1e-6 mixed bar on the chain (see above); here measured, not required"))])
 def test_mixed_precision_truncated_vs_oracle(prec):
     W, L, geo, U, mu, D, pad = 3, 3, T.TT_CYLINDER, 8.0, 2.0, 24, 0.3
     b0 = 0.01
@@ -210,9 +213,10 @@ def test_mixed_precision_truncated_vs_oracle(prec):
         st.sweep(0.1)
         ost.sweep(0.1)
     o, r = st.observables(), ost.observables()
+    print("precision", prec, "rel err f, e vs the oracle", _rel(o["f"], r["f"]), _rel(o["e"], r["e"]))
+    st.free()
     assert _rel(o["f"], r["f"]) <= TOL_MIXED, (o["f"], r["f"])
     assert _rel(o["e"], r["e"]) <= TOL_MIXED, (o["e"], r["e"])
-    st.free()
 
 
 def _grouped_launches(fn):
