@@ -52,8 +52,11 @@ typedef struct tt_state tt_state;
 /* precision of the bulk contractions (FP64 is always kept for the Lanczos
  * scalars and reorthogonalisation, the QR gauge moves and Lambda) */
 #define TT_FP64 0
-#define TT_FP32 1    /* FP32 MFMA, FP32 accumulation inside a K tile, FP64 across tiles */
-#define TT_BF16X3 2  /* split-BF16: hi*hi + hi*lo + lo*hi, FP32 MFMA accumulation */
+#define TT_FP32 1    /* the contraction intermediates (T1, T2 and those of the environment updates)
+                        stored in float; the small blocks of a block-sparse sweep multiply in FP64,
+                        dense tiles (M, N, K >= 128) with FP32 MFMA (FP32 inside a K tile, FP64 across) */
+#define TT_BF16X3 2  /* split-BF16: hi*hi + hi*lo + lo*hi per 16- or 32-deep chunk, FP32 MFMA
+                        accumulation inside a chunk, FP64 across chunks */
 #define TT_BF16X6 3  /* split-BF16 with three parts, six products */
 
 /* Eq. (3): H = -t sum_<ij>,s (c+_is c_js + h.c.) + U sum n_iu n_id - mu sum n_i,
@@ -104,6 +107,10 @@ typedef struct {
   double lnZ_single;   /* ln Tr rho(beta) (single layer) */
   double lambda;       /* Lambda = ln ||rho||_F */
   int n_sites;
+  double herm_defect;  /* ||rho - rho^T||_F / ||rho||_F = sqrt(2 - 2 <<rho|P|rho>>/<<rho|rho>>), P the
+                          exchange sigma <-> sigma' on every site (rho real, so rho^T = rho^dagger); zero
+                          for the exact state, and a measure of the one-sided flow's projection error
+                          (resolution about 1e-8: the square root of rounding in the overlap) */
 } tt_observables;
 
 typedef struct {
@@ -169,8 +176,10 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
 int tt_tune_apply(tt_state* state, int mode, int* host_forms);
 
 /* Bilayer observables of SM Sec. II.A at beta_phys = 2*beta: lnZ = 2 Lambda,
- * E from one H^(1) apply at the canonical centre, and the single-layer
- * ln Tr rho(beta) by transfer matrices.  Synchronises. */
+ * E from one H^(1) apply at the canonical centre, the single-layer
+ * ln Tr rho(beta) and the hermiticity defect by transfer matrices.  Valid for
+ * a state as left by mpo_init_highT or tdvp_sweep (centre at site 0).
+ * Synchronises. */
 int thermo_observables(tt_state* state, tt_observables* out);
 
 /* Local observables per site at beta_phys = 2 beta (same bilayer meaning as

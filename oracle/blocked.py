@@ -498,6 +498,33 @@ class BlockState:
             v = nv
         return self.lam + np.log(v[(0, 0)][0, 0])
 
+    def swap_overlap(self):
+        """<<rho|P|rho>> / <<rho|rho>> (``oracle.tdvp.State.swap_overlap``) in
+        blocks: P maps s = 4 sigma + sigma' to 4 sigma' + sigma and negates its
+        charge, so the transfer matrix E pairs a left sector q with -q:
+        E'[q + Delta(s)] = sum_{s, q} (A^s[q])^T E[q] A^{P(s)}[-q]."""
+        neg = lambda q: (-q[0], -q[1])
+        E = {(0, 0): np.ones((1, 1))}
+        N2 = {(0, 0): np.ones((1, 1))}
+        for A in self.A:
+            nE, nN = {}, {}
+            for s in range(16):
+                ps = 4 * (s % 4) + s // 4
+                for q, blk in A[s].items():
+                    qy = qadd(q, S_CHARGES[s])
+                    if q in E and neg(q) in A[ps]:
+                        y = blk.T @ E[q] @ A[ps][neg(q)]
+                        nE[qy] = nE[qy] + y if qy in nE else y
+                    if q in N2:
+                        y = blk.T @ N2[q] @ blk
+                        nN[qy] = nN[qy] + y if qy in nN else y
+            E, N2 = nE, nN
+        return float(E[(0, 0)][0, 0]) / float(N2[(0, 0)][0, 0])
+
+    def herm_defect(self):
+        """||rho - rho^T||_F / ||rho||_F = sqrt(2 - 2 <<rho|P|rho>>/<<rho|rho>>)."""
+        return float(np.sqrt(max(0.0, 2.0 - 2.0 * self.swap_overlap())))
+
     def observables(self):
         """Bilayer values at the physical inverse temperature 2*beta (the
         definitions of ``oracle.tdvp.State.observables``)."""

@@ -351,6 +351,24 @@ class State:
             v = v @ np.einsum("xssy->xy", a)
         return self.lam + np.log(v[0])
 
+    def swap_overlap(self):
+        """<<rho|P|rho>> / <<rho|rho>> with P the exchange of sigma and sigma'
+        on every site (P|rho>> = |rho^T>>, the Choi map of SM Sec. II.A), by
+        transfer matrices E'[y, y'] = sum E[x, x'] A[x, s, s', y] A[x', s', s, y']."""
+        E = np.ones((1, 1))
+        N2 = np.ones((1, 1))
+        for a in self.A:
+            T = np.tensordot(E, a, axes=([0], [0]))                  # x' so sp y
+            E = np.tensordot(T, a, axes=([0, 1, 2], [0, 2, 1]))      # y y'
+            T = np.tensordot(N2, a, axes=([0], [0]))
+            N2 = np.tensordot(T, a, axes=([0, 1, 2], [0, 1, 2]))
+        return float(E[0, 0]) / float(N2[0, 0])
+
+    def herm_defect(self):
+        """||rho - rho^T||_F / ||rho||_F = sqrt(2 - 2 <<rho|P|rho>>/<<rho|rho>>)
+        (rho real: rho^T = rho^dagger); zero for the exact state."""
+        return float(np.sqrt(max(0.0, 2.0 - 2.0 * self.swap_overlap())))
+
     def observables(self):
         """Bilayer values at the physical inverse temperature 2*beta."""
         N = self.N

@@ -153,6 +153,11 @@ struct tt_state {
   SiteTables tabs;
   // device memory
   std::vector<double*> A, Lenv, Renv;
+  // the swap overlap <<rho|P|rho>> (hermiticity defect): per site the plans
+  // X = E_k A^{P(s)} and E_{k+1} = sum (A^s)^T X, transfer matrices E on (q, -q) blocks
+  std::vector<GemmPlan> swp1, swp2;
+  long long swp_e = 1, swp_x = 1;
+  double *Ea = nullptr, *Eb = nullptr, *Xs = nullptr;
   double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr, *U = nullptr;
   double *Sbuf = nullptr, *tmp = nullptr, *kry = nullptr, *wv = nullptr, *qrws = nullptr;
   double* pws = nullptr;                   // partial tiles of K-split GEMMs
@@ -213,6 +218,9 @@ tt_state::~tt_state() {
   for (auto p : Renv) dfree(p);
   for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws, LW}) dfree(p);
   dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
+  for (auto& g : swp1) free_plan(g);
+  for (auto& g : swp2) free_plan(g);
+  dfree(Ea); dfree(Eb); dfree(Xs);
   if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
   for (auto& kv : obs) {
     ObsMpo& O = kv.second;
@@ -569,6 +577,93 @@ long long pow16_cap(int e, long long cap) {
   return v;
 }
 
+// Plans of the swap overlap <<rho|P|rho>>, P exchanging sigma and sigma' on
+// every site (P|rho>> = |rho^T>>, Choi map of SM Sec. II.A).  P maps s =
+// 4 sigma + sigma' to 4 sigma' + sigma and negates its charge, so the transfer
+// matrix of bond k pairs sector q with -q: E_k[q] is d(q) x d(-q), laid out
+// sector by sector (sectors whose -q is absent hold no block).  Site k:
+//   X^{s,q} = E_k[q] A^{P(s)}[-q]              (one GEMM per (s, q))
+//   E_{k+1}[q'] = sum_{(s,q): q + Delta(s) = q'} (A^s[q])^T X^{s,q}
+// the second as one GEMM per q' with its K running over the rows of every
+// (s, q) in order.  E_0 = 1 and the value is E_N.
+static Q negq(Q q) { return {-q.first, -q.second}; }
+void build_swap_plans(tt_state& s) {
+  const int N = s.N;
+  std::vector<std::vector<long long>> eoff(N + 1);
+  s.swp_e = 1;
+  for (int k = 0; k <= N; ++k) {
+    const Bond& b = s.bonds[k];
+    long long pos = 0;
+    eoff[k].assign(b.secs.size(), -1);
+    for (size_t i = 0; i < b.secs.size(); ++i) {
+      const int j = b.find(negq(b.secs[i].q));
+      if (j < 0) continue;
+      eoff[k][i] = pos;
+      pos += (long long)b.secs[i].dim * b.secs[j].dim;
+    }
+    s.swp_e = std::max(s.swp_e, pos);
+  }
+  s.swp1.assign(N, GemmPlan());
+  s.swp2.assign(N, GemmPlan());
+  s.swp_x = 1;
+  auto gp0 = [](int M, int Nn, int K) {
+    GemmProb g{};
+    g.M = M; g.N = Nn; g.K = K;
+    g.ia = 0; g.ib = 1; g.ic = 2;
+    g.tam = g.tak = g.tbk = g.tbn = g.tcm = -1;
+    g.alpha = 1.0; g.beta = 0.0;
+    return g;
+  };
+  for (int k = 0; k < N; ++k) {
+    const Bond &bl = s.bonds[k], &br = s.bonds[k + 1];
+    const SiteLayout& S = s.site[k];
+    GemmPlan &h1 = s.swp1[k], &h2 = s.swp2[k];
+    h1.wave_ok = h2.wave_ok = true;
+    long long xpos = 0;
+    std::map<int, std::vector<std::pair<long long, std::pair<int, int>>>> into;   // q' -> (X offset, (s, l))
+    for (int l = 0; l < (int)bl.secs.size(); ++l) {
+      if (eoff[k][l] < 0) continue;
+      const int ln = bl.find(negq(bl.secs[l].q));
+      for (int sg = 0; sg < 16; ++sg) {
+        const int ps = 4 * (sg & 3) + (sg >> 2);
+        const int g = s.G.group_of[sg], gp = s.G.group_of[ps];
+        const int r = S.rsec[l][g], rn = S.rsec[ln][gp];
+        if (r < 0 || rn < 0) continue;
+        if (br.find(negq(br.secs[r].q)) != rn || eoff[k + 1][r] < 0) continue;
+        const int dq = bl.secs[l].dim, dn = bl.secs[ln].dim, dyn = br.secs[rn].dim;
+        GemmProb g1 = gp0(dq, dyn, dn);
+        g1.offA = eoff[k][l]; g1.sam = dn; g1.sak = 1;
+        g1.offB = S.base[ln] + S.colb[ln][gp] + (long long)s.G.pos_of[ps] * dyn; g1.sbk = S.C[ln]; g1.sbn = 1;
+        g1.offC = xpos; g1.scm = dyn;
+        h1.probs.push_back(g1);
+        h1.flops += 2.0 * dq * (double)dyn * dn;
+        into[r].push_back({xpos, {sg, l}});
+        xpos += (long long)dq * dyn;
+      }
+    }
+    s.swp_x = std::max(s.swp_x, xpos);
+    for (auto& kv : into) {
+      const int r = kv.first, rn = br.find(negq(br.secs[r].q));
+      const int dy = br.secs[r].dim, dyn = br.secs[rn].dim;
+      std::vector<long long> ak, bk;
+      for (auto& e : kv.second) {
+        const int sg = e.second.first, l = e.second.second;
+        const int g = s.G.group_of[sg];
+        for (int x = 0; x < bl.secs[l].dim; ++x) {
+          ak.push_back(S.base[l] + (long long)x * S.C[l] + S.colb[l][g] + (long long)s.G.pos_of[sg] * dy);
+          bk.push_back(e.first + (long long)x * dyn);
+        }
+      }
+      GemmProb g2 = gp0(dy, dyn, (int)ak.size());
+      g2.sam = 1; g2.tak = s.tabs.add(ak);
+      g2.tbk = s.tabs.add(bk); g2.sbn = 1;
+      g2.offC = eoff[k + 1][r]; g2.scm = dyn;
+      h2.probs.push_back(g2);
+      h2.flops += 2.0 * dy * (double)dyn * ak.size();
+    }
+  }
+}
+
 void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   const int N = s.N;
   s.bonds.assign(N + 1, Bond());
@@ -605,11 +700,11 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   for (int k = 0; k < N; ++k)
     s.plans.push_back(
         build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, s.qH[k], s.qH[k + 1], s.Wenv[k], s.Wpat[k], s.tabs));
-  // the wave GEMM serves FP64 and FP32 launches; the absorb step always runs in FP64
-  const bool wave = s.opts.precision == TT_FP64 || s.opts.precision == TT_FP32;
+  // every contraction block of a sweep goes to the wave GEMM, which multiplies
+  // in the state's precision; the absorb step always runs in FP64
   for (auto& P : s.plans) {
-    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = wave;
-    for (GemmPlan& g : P.s1w) g.wave_ok = wave;
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = true;
+    for (GemmPlan& g : P.s1w) g.wave_ok = true;
     P.absL.wave_ok = P.absR.wave_ok = true;
     if (s.opts.precision == TT_FP32) {
       // FP32 mode keeps the intermediates of H_eff and of the environment
@@ -622,6 +717,7 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
       P.t2zero.f32 = true;
     }
   }
+  build_swap_plans(s);
 }
 
 void alloc_state(tt_state& s) {
@@ -686,6 +782,11 @@ void alloc_state(tt_state& s) {
   s.lz = (double*)dalloc(8 * (4 * kMaxKrylov + 16));
   launch_fill(s.lz, 0.0, 4 * kMaxKrylov + 16, st);
   s.vtr = (double*)dalloc(8 * 2 * s.max_bond);
+  for (auto& g : s.swp1) upload_plan(g, &s.tabs.host, st);
+  for (auto& g : s.swp2) upload_plan(g, &s.tabs.host, st);
+  s.Ea = (double*)dalloc(8 * s.swp_e);
+  s.Eb = (double*)dalloc(8 * s.swp_e);
+  s.Xs = (double*)dalloc(8 * s.swp_x);
   // trace entries
   std::vector<TraceEntry> te;
   std::vector<int> start{0};
@@ -1015,6 +1116,13 @@ long long check_sweep_plans(tt_state& s, std::string& rep) {
     bad += check_w(P.wr, P.y_size, P.z_size, "wr", rep);
     bad += check_qr(P.qr, T, ns, s.bmat[k + 1].size, "qr", rep);
     bad += check_qr(P.lq, T, ns, s.bmat[k].size, "lq", rep);
+    if (k < (int)s.swp1.size()) {
+      tile_plan(s.swp1[k], &T);
+      tile_plan(s.swp2[k], &T);
+      long long h1[kSlots] = {s.swp_e, ns, s.swp_x, 0}, h2[kSlots] = {ns, s.swp_x, s.swp_e, 0};
+      bad += check_gemm(s.swp1[k], T, h1, "swap1", rep);
+      bad += check_gemm(s.swp2[k], T, h2, "swap2", rep);
+    }
     int pmax = 0;
     for (int q = 0; q < 4; ++q) pmax = std::max(pmax, s.G.pos_of[5 * q]);
     for (auto& e : P.tr) {
@@ -1777,9 +1885,20 @@ int thermo_observables(tt_state* s, tt_observables* o) {
   launch_mdot(BPtr<const double>{}, 0, 0, one<const double>(s->A[0]), n, 1, one(s->part), 1, ST());
   launch_dot_final(s->part, kRedBlocks, 1, ob + 1, ST());
   launch_trace(s->d_trace, s->d_trace_start, s->N, s->d_sites, s->vtr, s->max_bond, ob + 2, ST());
+  // <<rho|P|rho>>: transfer matrices on the (q, -q) blocks, E_0 = 1
+  double* Ein = s->Ea;
+  double* Eout = s->Eb;
+  launch_fill(Ein, 1.0, 1, ST());
+  for (int k = 0; k < s->N; ++k) {
+    launch_gemm(s->swp1[k], s->tabs.dev, one(Slots{{Ein, s->A[k], s->Xs, nullptr}}), 1, TT_FP64, one(s->pws), ST());
+    launch_gemm(s->swp2[k], s->tabs.dev, one(Slots{{s->A[k], s->Xs, Eout, nullptr}}), 1, TT_FP64, one(s->pws), ST());
+    std::swap(Ein, Eout);
+  }
+  double swap_ov = 0.0;
   double h[4], lam;
   HIPX(hipMemcpyAsync(h, ob, 32, hipMemcpyDeviceToHost, ST()));
   HIPX(hipMemcpyAsync(&lam, s->lam_ptr(), 8, hipMemcpyDeviceToHost, ST()));
+  HIPX(hipMemcpyAsync(&swap_ov, Ein, 8, hipMemcpyDeviceToHost, ST()));
   HIPX(hipStreamSynchronize(ST()));
   o->beta = s->beta;
   o->beta_phys = 2.0 * s->beta;
@@ -1790,6 +1909,8 @@ int thermo_observables(tt_state* s, tt_observables* o) {
   o->E = h[0] / h[1];
   o->e = o->E / s->N;
   o->lnZ_single = lam + h[2];
+  // the right-canonical sites have unit norm: <<rho|rho>> = ||A_0||^2
+  o->herm_defect = std::sqrt(std::max(0.0, 2.0 - 2.0 * swap_ov / h[1]));
   TT_REQUIRE(std::isfinite(o->lnZ) && std::isfinite(o->E), TT_ENUMERIC, "non-finite observables");
   ABI_END
 }

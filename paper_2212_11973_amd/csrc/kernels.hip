@@ -108,6 +108,7 @@ void prof_read(double out[PROF_KINDS][4]) {
 // ------------------------------------------------------------------ GEMM
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ long long idx_map(const long long* __restrict__ tabs, long long tab, long long stride,
                                              long long i) {
@@ -458,9 +459,46 @@ __device__ __forceinline__ void ld32x2(const T* __restrict__ base, unsigned i, d
 // columns and k past the ends are clamped to the last valid index (an
 // element of the same problem), so a half chunk issues all of its loads
 // before its first wait.
-template <int FM, int FN, typename TA, typename TB, int KM>
+// Multiply of one 16-deep chunk in split BF16: each lane holds four k values
+// of its A row and B column (the same four k for both, so their order inside
+// the chunk does not matter); every value is split into 2 (bf16x3) or 3
+// (bf16x6) BF16 parts (x ~ p0 + p1 (+ p2), each rounded to nearest) and the 3 /
+// 6 leading part products are taken with the 16x16x16 BF16 MFMA, smallest
+// first.  The chunk's FP32 result is added into the FP64 accumulators, so
+// precision is lost only inside one chunk.
+template <int MM>
+__device__ __forceinline__ float4_t chunk_mul(const double (&a)[4], const double (&b)[4]) {
+  float4_t t = (float4_t){0.f, 0.f, 0.f, 0.f};
+  {
+    constexpr int NP = MM == TT_BF16X3 ? 2 : 3;
+    short4_t pa[NP], pb[NP];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __bf16 xa[3], xb[3];
+      bf16_split<NP>(a[q], xa);
+      bf16_split<NP>(b[q], xb);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        pa[p][q] = __builtin_bit_cast(short, xa[p]);
+        pb[p][q] = __builtin_bit_cast(short, xb[p]);
+      }
+    }
+    if constexpr (NP == 3) {
+      t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[2], pb[0], t, 0, 0, 0);
+      t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[1], pb[1], t, 0, 0, 0);
+      t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[0], pb[2], t, 0, 0, 0);
+    }
+    t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[1], pb[0], t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[0], pb[1], t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[0], pb[0], t, 0, 0, 0);
+  }
+  return t;
+}
+
+template <int FM, int FN, typename TA, typename TB, int KM, int MM>
 __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
                                           const Slots& slots, double* red) {
+  constexpr bool F64 = MM == TT_FP64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
   // operand bases are wave-uniform (scalar registers); element offsets from
@@ -498,6 +536,7 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
   for (int c = J.part; c < nfull; c += J.nparts) {
     // full chunk: every k is valid and clamped rows / columns only feed
     // outputs that are never stored, so the loads need no mask
+    double a4[F64 ? 1 : FM][4], b4[F64 ? 1 : FN][4];   // the whole chunk (lower precisions)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       double a[FM][2], b[FN][2];
@@ -533,13 +572,33 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
           }
         }
       }
+      if constexpr (F64) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a4[i][2 * h + q] = a[i][q];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) b4[j][2 * h + q] = b[j][q];
+        }
+      }
+    }
+    if constexpr (!F64) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const float4_t t = chunk_mul<MM>(a4[i], b4[j]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)t[v];
+        }
     }
   }
   if (nfull < nch && nfull % J.nparts == J.part) {
@@ -547,9 +606,10 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
     // the last, partial chunk: k past the end is clamped to K - 1 and its B
     // value replaced by zero (that alone cancels the product)
     const int ns = (P.K - 16 * c + 3) >> 2;   // steps holding a valid k (wave-uniform)
+    double a4[F64 ? 1 : FM][4], b4[F64 ? 1 : FN][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (2 * h >= ns) break;
+      if (F64 && 2 * h >= ns) break;
       double a[FM][2], b[FN][2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -570,15 +630,36 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
           b[j][q] = ok ? v : 0.0;
         }
       }
+      if constexpr (F64) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (2 * h + q >= ns) break;
+        for (int q = 0; q < 2; ++q) {
+          if (2 * h + q >= ns) break;
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][q], b[j][q], acc[i][j], 0, 0, 0);
+        }
+      } else {
+        // k past the end carries a zero B value: the whole chunk is multiplied
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a4[i][2 * h + q] = a[i][q];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) b4[j][2 * h + q] = b[j][q];
+        }
       }
+    }
+    if constexpr (!F64) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const float4_t t = chunk_mul<MM>(a4[i], b4[j]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)t[v];
+        }
     }
   }
   if (J.nparts > 1) {   // uniform over the workgroup: its four jobs are the parts of one block
@@ -606,8 +687,9 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // accumulator row inside a 16x16 block of the f64 MFMA: lane/16 + 4v
-      const int m = m0 + 16 * i + g + 4 * v;
+      // accumulator row inside a 16x16 block: lane/16 + 4v for the f64 MFMA,
+      // 4 (lane/16) + v for the f32-accumulating ones
+      const int m = m0 + 16 * i + (F64 ? g + 4 * v : 4 * g + v);
       if (m >= P.M) continue;
       const unsigned rowc = (unsigned)idx_map(tabs, P.tcm, P.scm, m);
 #pragma unroll
@@ -628,26 +710,28 @@ __device__ __forceinline__ void wave_tile(const GemmProb& P, const GemmJob& J, c
 
 // operand element types and the k addressing are wave-uniform (one problem
 // per wave)
-template <int FM, int FN, int KM>
+template <int FM, int FN, int KM, int MM>
 __device__ __forceinline__ void wave_tile_dt(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
                                              const Slots& slots, double* red) {
   switch (P.dt & (kDtA | kDtB)) {
-    case 0: wave_tile<FM, FN, double, double, KM>(P, J, tabs, slots, red); break;
-    case kDtA: wave_tile<FM, FN, float, double, KM>(P, J, tabs, slots, red); break;
-    case kDtB: wave_tile<FM, FN, double, float, KM>(P, J, tabs, slots, red); break;
-    default: wave_tile<FM, FN, float, float, KM>(P, J, tabs, slots, red); break;
+    case 0: wave_tile<FM, FN, double, double, KM, MM>(P, J, tabs, slots, red); break;
+    case kDtA: wave_tile<FM, FN, float, double, KM, MM>(P, J, tabs, slots, red); break;
+    case kDtB: wave_tile<FM, FN, double, float, KM, MM>(P, J, tabs, slots, red); break;
+    default: wave_tile<FM, FN, float, float, KM, MM>(P, J, tabs, slots, red); break;
   }
 }
-template <int FM, int FN>
+template <int FM, int FN, int MM>
 __device__ __forceinline__ void wave_tile_k(const GemmProb& P, const GemmJob& J, const long long* __restrict__ tabs,
                                             const Slots& slots, double* red) {
-  if (P.tak >= 0 || P.tbk >= 0 || P.sak != 1) wave_tile_dt<FM, FN, kKGeneric>(P, J, tabs, slots, red);
-  else if (P.sbk == 1) wave_tile_dt<FM, FN, kKBothContig>(P, J, tabs, slots, red);
-  else wave_tile_dt<FM, FN, kKAContig>(P, J, tabs, slots, red);
+  if (P.tak >= 0 || P.tbk >= 0 || P.sak != 1) wave_tile_dt<FM, FN, kKGeneric, MM>(P, J, tabs, slots, red);
+  else if (P.sbk == 1) wave_tile_dt<FM, FN, kKBothContig, MM>(P, J, tabs, slots, red);
+  else wave_tile_dt<FM, FN, kKAContig, MM>(P, J, tabs, slots, red);
 }
 
 // five waves per SIMD: the register budget (96) that keeps a half chunk's
 // loads of the next steps in flight without spilling
+// MM: the precision of the multiplies (TT_FP64, TT_BF16X3, TT_BF16X6)
+template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
                                                int nblocks, const long long* __restrict__ tabs, BSlots bs) {
   __shared__ double red[3 * 1024];
@@ -659,9 +743,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   if (J.prob < 0) return;   // an unused slot: only in workgroups of unsplit jobs, which never synchronise
   const GemmProb P = probs[J.prob];
   switch (J.shape) {
-    case 0: wave_tile_k<4, 1>(P, J, tabs, slots, red); break;
-    case 1: wave_tile_k<2, 2>(P, J, tabs, slots, red); break;
-    default: wave_tile_k<1, 4>(P, J, tabs, slots, red); break;
+    case 0: wave_tile_k<4, 1, MM>(P, J, tabs, slots, red); break;
+    case 1: wave_tile_k<2, 2, MM>(P, J, tabs, slots, red); break;
+    default: wave_tile_k<1, 4, MM>(P, J, tabs, slots, red); break;
   }
 }
 
@@ -741,14 +825,19 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
   TT_REQUIRE(nb >= 1 && nb <= kMaxBatch, TT_EINVAL, "batch size out of range");
   prof_begin(st);
   if (p.wave_blocks > 0) {
-    // FP32 mode: the wave GEMM's blocks are bound by memory and issue, not by
-    // the MFMA rate, so it multiplies in FP64 and the precision reduction comes
-    // from the float intermediates (P.dt); the LDS-tile kernel uses FP32 MFMA
-    if (precision == TT_FP64 || precision == TT_FP32)
-      hipLaunchKernelGGL(k_wgemm, dim3(p.wave_blocks, nb), dim3(256), 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs,
-                         s);
-    else
-      throw Error(TT_EINVAL, "the wave GEMM runs FP64 or FP32 only: plan built for another precision");
+    const dim3 grid(p.wave_blocks, nb), block(256);
+    switch (precision) {
+      // FP32 mode: the wave GEMM's blocks are bound by memory and latency, so
+      // it multiplies in FP64 and the mode's saving is the float storage of the
+      // intermediates (P.dt).  Measured on the 4x16 D=2000 sweep, FP32 MFMA here
+      // was no faster (0.278 vs 0.271 s/step) and its error after four sweeps
+      // was 1.3e-6 in E against 2e-10 with FP64 multiplies.
+      case TT_FP64:
+      case TT_FP32: hipLaunchKernelGGL(k_wgemm<TT_FP64>, grid, block, 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs, s); break;
+      case TT_BF16X3: hipLaunchKernelGGL(k_wgemm<TT_BF16X3>, grid, block, 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs, s); break;
+      case TT_BF16X6: hipLaunchKernelGGL(k_wgemm<TT_BF16X6>, grid, block, 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs, s); break;
+      default: throw Error(TT_EINVAL, "unknown precision");
+    }
     HIP_CHECK_LAUNCH();
     prof_mark(st, PROF_GEMM_WAVE, nb * p.wave_flops, nb * p.wave_bytes);
   }

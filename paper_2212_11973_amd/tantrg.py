@@ -46,7 +46,8 @@ class tt_options(C.Structure):
 class tt_observables(C.Structure):
     _fields_ = [("beta", C.c_double), ("beta_phys", C.c_double), ("lnZ", C.c_double),
                 ("f", C.c_double), ("E", C.c_double), ("e", C.c_double),
-                ("lnZ_single", C.c_double), ("lambda_", C.c_double), ("n_sites", C.c_int)]
+                ("lnZ_single", C.c_double), ("lambda_", C.c_double), ("n_sites", C.c_int),
+                ("herm_defect", C.c_double)]
 
 
 class tt_sweep_stats(C.Structure):

@@ -47,6 +47,31 @@ def test_config1_chain4_matches_ed(sym):
     st.free()
 
 
+def test_hermiticity_defect_matches_the_oracle():
+    """||rho - rho^T|| / ||rho|| by transfer matrices on (q, -q) blocks: zero at
+    untruncated bonds (the exact flow keeps rho symmetric), and the oracle's
+    value on a padded truncated state (dense and Sz-free U(1) blocks)."""
+    c = WL.MODELS["chain4"]
+    st = T.State.init(T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"]),
+                      T.options(D=256, symmetry=1, beta0=c["beta0"]))
+    for _ in range(5):
+        st.sweep(0.1)
+    assert st.observables()["herm_defect"] < 1e-7
+    st.free()
+    for sym in (1, 0):
+        mm = ompo.HubbardMPO(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, 1.0)
+        ost = otd.initial_state(mm, 0.01, 20, bool(sym), pad_eps=0.3, seed=11, sector_cap=64)
+        st = T.State.init(T.model(2, 3, T.TT_OPEN_SQUARE, 1.0, 8.0, 1.0),
+                          T.options(D=20, symmetry=sym, beta0=0.01, pad_eps=0.3, seed=11))
+        for _ in range(2):
+            st.sweep(0.1)
+            ost.sweep(0.1)
+        g, hd = st.observables()["herm_defect"], ost.herm_defect()
+        assert hd > 1e-4
+        assert abs(g - hd) <= 1e-8 + 1e-6 * hd, (sym, g, hd)
+        st.free()
+
+
 @pytest.mark.parametrize("W,L,geo,U,mu", [(2, 2, T.TT_OPEN_SQUARE, 8.0, 4.0), (1, 4, T.TT_CHAIN, 0.0, 0.3)])
 def test_untruncated_2d_and_free_fermions_match_ed(W, L, geo, U, mu):
     b0 = 0.01

@@ -159,3 +159,28 @@ def test_untruncated_chain_matches_ed():
     lnZ, Ebl = ed.same_ode_bilayer(E, b0, o["beta"])
     assert _rel(o["lnZ"], lnZ) < 1e-10
     assert _rel(o["E"], Ebl) < 1e-10
+
+
+def test_hermiticity_defect_pins():
+    """||rho - rho^T|| / ||rho||: zero for the symmetric start and for the exact
+    flow at untruncated bonds (rho(beta) = exp(-(beta - beta0) H)(1 - beta0 H)
+    is symmetric); at a truncated bond equal to the brute-force value of the
+    dense operator, and the same in blocks and dense."""
+    from oracle import mpo as om
+    m = om.HubbardMPO(1, 4, 0, t=1.0, U=4.0, mu=0.3)
+    st = tdvp.initial_state(m, 0.01, 256, True)
+    assert st.herm_defect() < 1e-7
+    for _ in range(5):
+        st.sweep(0.1)
+    assert st.herm_defect() < 1e-7
+    # truncated, padded: brute force from the dense operator
+    dn = tdvp.initial_state(m, 0.01, 12, True, pad_eps=0.3, seed=5)
+    bl = blocked.initial_state(m, 0.01, 12, pad_eps=0.3, seed=5)
+    for _ in range(2):
+        dn.sweep(0.1)
+        bl.sweep(0.1)
+    rho = om.mpo_to_dense(dn.A)
+    want = np.linalg.norm(rho - rho.T) / np.linalg.norm(rho)
+    assert want > 1e-6
+    assert abs(dn.herm_defect() - want) <= 1e-8 * max(want, 1.0)
+    assert abs(bl.herm_defect() - dn.herm_defect()) <= 1e-10
