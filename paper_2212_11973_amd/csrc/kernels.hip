@@ -957,6 +957,16 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ------------------------------------------------------------------ QR
+// Householder QR of a block wider than the register kernels take, in global
+// memory, one workgroup per block, blocked in panels of kQrPanel columns
+// (compact WY form, I - V T V^T for the product of a panel's reflectors):
+// the panel's columns are factored one by one with the reflectors applied
+// inside the panel, its T factor is formed from the Gram matrix of V, and every
+// later column gets the whole panel's product in two passes (the kQrPanel dot
+// products, then the update), instead of one pass per reflector.  Q is formed
+// explicitly the same way, panels in reverse order.  Same reflectors as the
+// column-by-column algorithm; only the order of the sums differs.
+constexpr int kQrPanel = 8;
 __global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
                                                  const long long* __restrict__ tabs, BPtr<double> b_A, BPtr<double> b_S,
                                                  BPtr<double> b_ws) {
@@ -964,10 +974,11 @@ __global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ task
   double* S = b_S.p[blockIdx.y];
   double* ws = b_ws.p[blockIdx.y];
   __shared__ double red[8];
-  __shared__ double s_tau[1];
+  __shared__ double Tm[kQrPanel][kQrPanel];   // T of the current panel (upper triangular)
+  __shared__ double Gm[kQrPanel][kQrPanel];   // V^T V of the current panel (strict upper part)
   const QRTask T = tasks[wide[blockIdx.x]];
   const int m = T.m, n = T.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* Wm = ws + T.ws;                 // m x n column-major
+  double* Wm = ws + T.ws;                 // m x n column-major: R above the diagonal, reflectors below
   double* Qm = Wm + (long long)m * n;     // m x n column-major
   double* taus = Qm + (long long)m * n;   // n
   auto row = [&](int i) -> long long { return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs; };
@@ -976,61 +987,136 @@ __global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ task
     Wm[e] = A[T.rbase + row(i) + (long long)j * T.cs];
   }
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < m; i += blockDim.x) {
-      double x = Wm[i + (long long)j * m];
-      part += x * x;
+  // the panel's T from tau and G = V^T V: T_ii = tau_i,
+  // T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+  auto make_t = [&](int j0, int pb) {
+    for (int e = wave; e < pb * pb; e += 4) {   // one wave per pair (r < i)
+      const int r = e / pb, i = e % pb;
+      if (r >= i) continue;
+      const int ji = j0 + i;
+      const double* vr = Wm + (long long)(j0 + r) * m;
+      const double* vi = Wm + (long long)ji * m;
+      double d = 0.0;
+      for (int q = ji + 1 + lane; q < m; q += 64) d += vr[q] * vi[q];
+      d = wave_sum(d);
+      if (lane == 0) Gm[r][i] = d + vr[ji];   // v_i[ji] = 1
     }
-    double xn2 = block_sum(part, red);
-    double alpha = Wm[j + (long long)j * m];
-    double tau = 0.0;
-    if (xn2 > 0.0) {
-      double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tau = (beta - alpha) / beta;
-      double scal = 1.0 / (alpha - beta);
-      for (int i = j + 1 + tid; i < m; i += blockDim.x) Wm[i + (long long)j * m] *= scal;
-      __syncthreads();
-      if (tid == 0) Wm[j + (long long)j * m] = beta;
-    }
-    if (tid == 0) { taus[j] = tau; s_tau[0] = tau; }
     __syncthreads();
-    if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < n; c += 4) {
-        double* col = Wm + (long long)c * m;
-        const double* v = Wm + (long long)j * m;
-        double d = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-        d = wave_sum(d);
-        d = __shfl(d, 0, 64) + col[j];
-        double f = tau * d;
-        if (lane == 0) col[j] -= f;
-        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+    if (tid == 0) {
+      for (int i = 0; i < pb; ++i) {
+        const double ti = taus[j0 + i];
+        for (int r = 0; r < i; ++r) {
+          double t = 0.0;
+          for (int q = r; q < i; ++q) t += Tm[r][q] * Gm[q][i];
+          Tm[r][i] = -ti * t;
+        }
+        Tm[i][i] = ti;
+        for (int r = i + 1; r < kQrPanel; ++r) Tm[r][i] = 0.0;
       }
+      for (int i = pb; i < kQrPanel; ++i)
+        for (int r = 0; r < kQrPanel; ++r) Tm[r][i] = 0.0;
     }
     __syncthreads();
+  };
+  // column col <- (I - V T' V^T) col for the panel at j0 (T' = T^T with trans)
+  // by one wave: w = V^T col over the rows >= j0, u = T' w, col -= V u.  Rows
+  // j0 .. j0 + pb - 1 hold the unit diagonal of V (one lane each); below them
+  // every v_r is a stored column.
+  auto apply_panel = [&](int j0, int pb, double* col, bool trans) {
+    double w[kQrPanel];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) w[r] = 0.0;
+    const double* V = Wm + (long long)j0 * m;
+    for (int i = j0 + pb + lane; i < m; i += 64) {
+      const double x = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? V[i + (long long)r * m] : 0.0) * x;
+    }
+    if (lane < pb) {
+      const int i = j0 + lane;
+      const double x = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r)
+        w[r] += (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * x;
+    }
+    double u[kQrPanel];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) w[r] = __shfl(wave_sum(w[r]), 0, 64);
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kQrPanel; ++q) t += (trans ? Tm[q][r] : Tm[r][q]) * w[q];
+      u[r] = t;
+    }
+    for (int i = j0 + pb + lane; i < m; i += 64) {
+      double x = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) x -= (r < pb ? V[i + (long long)r * m] : 0.0) * u[r];
+      col[i] = x;
+    }
+    if (lane < pb) {
+      const int i = j0 + lane;
+      double x = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) x -= (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * u[r];
+      col[i] = x;
+    }
+  };
+  for (int j0 = 0; j0 < n; j0 += kQrPanel) {
+    const int pb = min(kQrPanel, n - j0);
+    for (int j = j0; j < j0 + pb; ++j) {   // the panel, one column at a time
+      double part = 0.0;
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+        double x = Wm[i + (long long)j * m];
+        part += x * x;
+      }
+      double xn2 = block_sum(part, red);
+      double alpha = Wm[j + (long long)j * m];
+      double tau = 0.0;
+      if (xn2 > 0.0) {
+        double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        double scal = 1.0 / (alpha - beta);
+        for (int i = j + 1 + tid; i < m; i += blockDim.x) Wm[i + (long long)j * m] *= scal;
+        __syncthreads();
+        if (tid == 0) Wm[j + (long long)j * m] = beta;
+      }
+      if (tid == 0) taus[j] = tau;
+      __syncthreads();
+      if (tau != 0.0) {
+        for (int c = j + 1 + wave; c < j0 + pb; c += 4) {
+          double* col = Wm + (long long)c * m;
+          const double* v = Wm + (long long)j * m;
+          double d = 0.0;
+          for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
+          d = wave_sum(d);
+          d = __shfl(d, 0, 64) + col[j];
+          double f = tau * d;
+          if (lane == 0) col[j] -= f;
+          for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+        }
+      }
+      __syncthreads();
+    }
+    if (j0 + pb < n) {   // the rest of the matrix: Q_panel^T = I - V T^T V^T
+      make_t(j0, pb);
+      for (int c = j0 + pb + wave; c < n; c += 4) apply_panel(j0, pb, Wm + (long long)c * m, true);
+      __syncthreads();
+    }
   }
-  // explicit Q = H_0 ... H_{n-1} [I; 0]
+  // explicit Q = H_0 ... H_{n-1} [I; 0]: Q <- (I - V T V^T) Q panel by panel
+  // from the last, on the columns >= j0 (earlier columns of Q are still unit
+  // vectors that the panel's reflectors leave unchanged)
   for (long long e = tid; e < (long long)m * n; e += blockDim.x) {
     int i = (int)(e % m), j = (int)(e / m);
     Qm[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
-    double tau = taus[j];
-    if (tau != 0.0) {
-      const double* v = Wm + (long long)j * m;
-      for (int c = j + wave; c < n; c += 4) {
-        double* col = Qm + (long long)c * m;
-        double d = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-        d = wave_sum(d);
-        d = __shfl(d, 0, 64) + col[j];
-        double f = tau * d;
-        if (lane == 0) col[j] -= f;
-        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
-      }
-    }
+  for (int j0 = ((n - 1) / kQrPanel) * kQrPanel; j0 >= 0; j0 -= kQrPanel) {
+    const int pb = min(kQrPanel, n - j0);
+    make_t(j0, pb);
+    for (int c = j0 + wave; c < n; c += 4) apply_panel(j0, pb, Qm + (long long)c * m, false);
     __syncthreads();
   }
   // non-negative diagonal: flip column j of Q and row j of R when R_jj < 0
