@@ -255,7 +255,9 @@ int tt_state_save(const tt_state* state, const char* path);
 int tt_state_load(const char* path, tt_state** out);
 
 /* One dense effective-Hamiltonian apply (SM Fig. optimalB(c), contraction
- * order of SM Fig. Lanczos):
+ * order of SM Fig. Lanczos).  In the split-BF16 precisions every operand is
+ * split once into BF16 planes and T1, T2 are written as planes by the tiles
+ * that produce them:
  *   out[x,so,sp,y] = sum L[x,a,al] A[al,si,sp,be] W[a,so,si,b] R[y,b,be]
  * with dev_L [Dl][DH][Dl], dev_W [DH][4][4][DH], dev_A and dev_out
  * [Dl][4][4][Dr], dev_R [Dr][DH][Dr], all FP64 row-major device arrays owned
@@ -269,7 +271,10 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* dev_L, const double* dev
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the apply of
  * tt_heff_apply, same arguments, layouts and result (the same kernels and
- * launch plans, so the output is bit for bit that of tt_heff_apply), with
+ * launch plans, so in FP64 and FP32 the output is bit for bit that of
+ * tt_heff_apply; in the split-BF16 modes it splits every element inside the
+ * tiles and keeps T1 and T2 in FP64, where tt_heff_apply works on operands
+ * and intermediates pre-split into BF16 planes), with
  * every byte of device memory it needs beyond the caller's inputs and output
  * (the intermediates T1 = L.A and T2, the K-slice partial tiles and the launch
  * descriptors) taken from a static device array of 192 MiB that each GPU the

@@ -1477,6 +1477,11 @@ struct HeffCache {
   GemmPlan wg;
   double *T1 = nullptr, *T2 = nullptr, *pws = nullptr;
   long long t1 = 0, t2 = 0, pw = 0;
+  // split-BF16 modes: the three launches unsplit in K, and the operands and
+  // intermediates as BF16 planes (up to three parts each)
+  GemmPlan s1p, wgp, s3p;
+  void* planes = nullptr;
+  long long plane_bytes = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
 };
@@ -1495,6 +1500,12 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   upload_plan(c.plan.s1, &c.tabs.host, st);
   upload_plan(c.plan.s3, &c.tabs.host, st);
   upload_plan(c.wg, &c.tabs.host, st);
+  free_plan(c.s1p); free_plan(c.wgp); free_plan(c.s3p);
+  c.s1p = c.plan.s1; c.wgp = c.wg; c.s3p = c.plan.s3;
+  for (GemmPlan* g : {&c.s1p, &c.wgp, &c.s3p}) {
+    g->no_split = true;
+    upload_plan(*g, &c.tabs.host, st);
+  }
   if (h.t1 > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * h.t1); c.t1 = h.t1; }
   if (h.t2 > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * h.t2); c.t2 = h.t2; }
   if (h.pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * h.pw); c.pw = h.pw; }
@@ -2158,16 +2169,53 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
     if (g_heff.Dl != Dl || g_heff.Dr != Dr || g_heff.DH != DH) build_heff_cache(Dl, Dr, DH);
     HeffCache& c = g_heff;
     hipStream_t st = ST();
-    HIPX(hipEventRecord(c.ev[0], st));
-    launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}}), 1,
-                precision, one(c.pws), st);
-    HIPX(hipEventRecord(c.ev[1], st));
-    launch_gemm(c.wg, c.tabs.dev, one(Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}), 1, precision, one(c.pws),
-                st);
-    HIPX(hipEventRecord(c.ev[2], st));
-    launch_gemm(c.plan.s3, c.tabs.dev, one(Slots{{c.T2, const_cast<double*>(R), out, nullptr}}), 1, precision,
-                one(c.pws), st);
-    HIPX(hipEventRecord(c.ev[3], st));
+    if (precision == TT_BF16X3 || precision == TT_BF16X6) {
+      // split-BF16: every operand split once into BF16 planes (the split of L
+      // and A counted with L.A, of W with the W stage, of R with .R), the
+      // intermediates written as planes by the tiles that produce them
+      const int np = precision == TT_BF16X3 ? 2 : 3;
+      const long long nL = (long long)Dl * DH * Dl, nA = (long long)Dl * 16 * Dr, nW = (long long)DH * 16 * DH,
+                      nR = (long long)Dr * DH * Dr;
+      const long long need = 2LL * np * (nL + nA + nW + nR + c.t1 + c.t2) + 6 * 256;
+      if (need > c.plane_bytes) {
+        dfree(c.planes);
+        c.planes = nullptr;
+        c.planes = dalloc(need);
+        c.plane_bytes = need;
+      }
+      char* base = static_cast<char*>(c.planes);
+      long long off = 0;
+      auto carve = [&](long long n) { char* q = base + off; off += ((2LL * np * n + 255) / 256) * 256; return (double*)q; };
+      double *Lp = carve(nL), *Ap = carve(nA), *Wp = carve(nW), *Rp = carve(nR), *T1p = carve(c.t1), *T2p = carve(c.t2);
+      HIPX(hipEventRecord(c.ev[0], st));
+      launch_split(L, nL, Lp, nL, precision, st);
+      launch_split(A, nA, Ap, nA, precision, st);
+      Planes p1;
+      p1.s[0] = nL; p1.s[1] = nA; p1.s[2] = c.t1; p1.c = 1;
+      launch_gemm_planes(c.s1p, c.tabs.dev, Slots{{Lp, Ap, T1p, nullptr}}, p1, precision, st);
+      HIPX(hipEventRecord(c.ev[1], st));
+      launch_split(W, nW, Wp, nW, precision, st);
+      Planes p2;
+      p2.s[0] = nW; p2.s[1] = c.t1; p2.s[2] = c.t2; p2.c = 1;
+      launch_gemm_planes(c.wgp, c.tabs.dev, Slots{{Wp, T1p, T2p, nullptr}}, p2, precision, st);
+      HIPX(hipEventRecord(c.ev[2], st));
+      launch_split(R, nR, Rp, nR, precision, st);
+      Planes p3;
+      p3.s[0] = c.t2; p3.s[1] = nR;
+      launch_gemm_planes(c.s3p, c.tabs.dev, Slots{{T2p, Rp, out, nullptr}}, p3, precision, st);
+      HIPX(hipEventRecord(c.ev[3], st));
+    } else {
+      HIPX(hipEventRecord(c.ev[0], st));
+      launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}}), 1,
+                  precision, one(c.pws), st);
+      HIPX(hipEventRecord(c.ev[1], st));
+      launch_gemm(c.wg, c.tabs.dev, one(Slots{{const_cast<double*>(W), c.T1, c.T2, nullptr}}), 1, precision, one(c.pws),
+                  st);
+      HIPX(hipEventRecord(c.ev[2], st));
+      launch_gemm(c.plan.s3, c.tabs.dev, one(Slots{{c.T2, const_cast<double*>(R), out, nullptr}}), 1, precision,
+                  one(c.pws), st);
+      HIPX(hipEventRecord(c.ev[3], st));
+    }
     c.timed = true;
   } catch (...) {
     g_stream = saved;

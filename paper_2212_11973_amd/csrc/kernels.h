@@ -59,6 +59,15 @@ inline BSlots one(Slots s) {
 // pws: partial-tile workspace of at least p.pws_size doubles (split problems)
 void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, int nb, int precision,
                  BPtr<double> pws, hipStream_t st);
+// Pre-split BF16 operands: part p of an element lives p * s[slot] elements
+// after its first part; c: the result is written as planes too.
+struct Planes { long long s[kSlots] = {0, 0, 0, 0}; int c = 0; };
+// the LDS-tile GEMM on pre-split operands (split-BF16 precisions; plan with
+// LDS tiles only and no K slices)
+void launch_gemm_planes(const GemmPlan& p, const long long* d_tabs, const Slots& s, const Planes& pl, int precision,
+                        hipStream_t st);
+// the BF16 parts of n doubles into planes pstride elements apart
+void launch_split(const double* x, long long n, void* out, long long pstride, int precision, hipStream_t st);
 // terms: each state's copy of the plan's terms (the weights may differ)
 void launch_wstage(const WPlan& p, BPtr<const WTerm> terms, BPtr<const double> in, BPtr<double> out, int nb,
                    hipStream_t st);

@@ -155,9 +155,14 @@ __device__ __forceinline__ void bf16_split(double x, __bf16* out) {
 // added into FP64 accumulators after every K tile.
 // Global loads of the next K tile are issued before the MFMAs of the current
 // one (register double buffering), so their latency overlaps the compute.
-template <int WGM, int WGN, int FM, int FN, bool SPLITK, int PREC>
+// With PL (split BF16 only) both operands are BF16 planes (part p of an
+// element at plane p, pl.s[slot] elements apart: the element offsets of the
+// plan apply to every plane), read without splitting; with pl.c the result is
+// written as planes too (each value split into the NP parts).
+template <int WGM, int WGN, int FM, int FN, bool SPLITK, int PREC, bool PL = false>
 __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, const long long* __restrict__ tabs,
-                                          const Slots& slots, char* smem, double* __restrict__ pws) {
+                                          const Slots& slots, char* smem, double* __restrict__ pws,
+                                          const Planes& pl = Planes{}) {
   constexpr int BK = PrecTraits<PREC>::BK, NP = PrecTraits<PREC>::PARTS;
   constexpr int WM = 16 * FM, WN = 16 * FN;
   constexpr int BM = WGM * WM, BN = WGN * WN;
@@ -182,6 +187,9 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
   const double* __restrict__ A = slots.p[P.ia] + P.offA;
   const double* __restrict__ B = slots.p[P.ib] + P.offB;
   double* C = slots.p[P.ic] + P.offC;
+  const __bf16* __restrict__ Ap = reinterpret_cast<const __bf16*>(slots.p[P.ia]) + P.offA;
+  const __bf16* __restrict__ Bp = reinterpret_cast<const __bf16*>(slots.p[P.ib]) + P.offB;
+  __bf16* Cp = reinterpret_cast<__bf16*>(slots.p[P.ic]) + P.offC;
   for (int i = tid; i < BM; i += 256) {
     int m = m0 + i;
     rA[i] = m < P.M ? idx_map(tabs, P.tam, P.sam, m) : 0;
@@ -213,7 +221,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
   auto b_jk = [&](int e, int& j, int& kk) {
     if (b_nfast) { j = e % BN; kk = e / BN; } else { j = e / BK; kk = e % BK; }
   };
-  double ra[EA], rb[EB];
+  double ra[PL ? 1 : EA], rb[PL ? 1 : EB];
+  __bf16 pa[PL ? EA : 1][NP], pb[PL ? EB : 1][NP];
   __syncthreads();   // row / column offsets ready
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -222,7 +231,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
       a_ik(e, i, kk);
       const int k = k0 + kk;
       const bool ok = (e < BM * BK) && (m0 + i < P.M) && (k < kstop);
-      ra[q] = ok ? A[rA[i] + idx_map(tabs, P.tak, P.sak, k)] : 0.0;
+      const long long o = ok ? rA[i] + idx_map(tabs, P.tak, P.sak, k) : 0;
+      if constexpr (PL) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) pa[q][p] = ok ? Ap[p * pl.s[P.ia] + o] : (__bf16)0.0f;
+      } else {
+        ra[q] = ok ? A[o] : 0.0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < EB; ++q) {
@@ -230,7 +245,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
       b_jk(e, j, kk);
       const int k = k0 + kk;
       const bool ok = (e < BN * BK) && (n0 + j < P.N) && (k < kstop);
-      rb[q] = ok ? B[idx_map(tabs, P.tbk, P.sbk, k) + cB[j]] : 0.0;
+      const long long o = ok ? idx_map(tabs, P.tbk, P.sbk, k) + cB[j] : 0;
+      if constexpr (PL) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) pb[q][p] = ok ? Bp[p * pl.s[P.ib] + o] : (__bf16)0.0f;
+      } else {
+        rb[q] = ok ? B[o] : 0.0;
+      }
     }
   };
   auto stash = [&]() {
@@ -239,7 +260,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
       int e = tid + q * 256, i, kk;
       if (e >= BM * BK) break;
       a_ik(e, i, kk);
-      if (F64) dA[kk][i] = ra[q];
+      if constexpr (PL) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bA[(p * BM + i) * (BK + kBfPad) + kk] = pa[q][p];
+      } else if (F64) dA[kk][i] = ra[q];
       else if (F32) fA[kk][i] = (float)ra[q];
       else {
         __bf16 parts[3];
@@ -253,7 +277,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
       int e = tid + q * 256, j, kk;
       if (e >= BN * BK) break;
       b_jk(e, j, kk);
-      if (F64) dB[kk][j] = rb[q];
+      if constexpr (PL) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bB[(p * BN + j) * (BK + kBfPad) + kk] = pb[q][p];
+      } else if (F64) dB[kk][j] = rb[q];
       else if (F32) fB[kk][j] = (float)rb[q];
       else {
         __bf16 parts[3];
@@ -350,6 +377,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, const GemmTile& T, 
   auto store = [&](int row, int col, double v) {
     const int m = m0 + row, n = n0 + col;
     if (m < P.M && n < P.N) {
+      if (PL && pl.c) {   // the result as BF16 planes (beta = 0 only)
+        __bf16 parts[3];
+        bf16_split<NP>(P.alpha * v, parts);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) Cp[p * pl.s[P.ic] + rC[row] + n] = parts[p];
+        return;
+      }
       double* cp = C + rC[row] + n;
       double val = P.alpha * v;
       if (P.beta != 0.0) val += P.beta * (*cp);
@@ -775,6 +809,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
   gemm_tile<C::WGM, C::WGN, C::FM, C::FN, C::SK, PREC>(P, t, tabs, slots, smem_gemm, pws);
 }
 
+
 template <int CFG, int PREC>
 int cfg_smem() {
   using C = CfgT<CFG, PREC>;
@@ -817,6 +852,79 @@ void launch_prec(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
   launch_cfg<2, PREC>(p, d_tabs, s, nb, pws, st);
   launch_cfg<3, PREC>(p, d_tabs, s, nb, pws, st);
   launch_cfg<4, PREC>(p, d_tabs, s, nb, pws, st);
+}
+
+// the same tiles on pre-split BF16 operands (no K slices: the plan has none)
+template <int CFG, int PREC>
+__global__ __launch_bounds__(256) void k_gemm_planes(const GemmProb* __restrict__ probs,
+                                                     const GemmTile* __restrict__ tiles, int tile0,
+                                                     const long long* __restrict__ tabs, Slots slots, Planes pl) {
+  extern __shared__ __attribute__((aligned(16))) char smem_gemm[];
+  using C = CfgT<CFG, PREC>;
+  const GemmTile t = tiles[tile0 + blockIdx.x];
+  const GemmProb P = probs[t.prob];
+  gemm_tile<C::WGM, C::WGN, C::FM, C::FN, C::SK, PREC, true>(P, t, tabs, slots, smem_gemm, nullptr, pl);
+}
+
+template <int CFG, int PREC>
+void launch_cfg_planes(const GemmPlan& p, const long long* d_tabs, const Slots& s, const Planes& pl, hipStream_t st) {
+  const int n = p.cfg_off[CFG + 1] - p.cfg_off[CFG];
+  if (n == 0) return;
+  static bool attr = false;
+  const int smem = cfg_smem<CFG, PREC>();
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_gemm_planes<CFG, PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            smem) != hipSuccess)
+      throw Error(TT_EDEVICE, "cannot set the LDS limit of the GEMM kernel");
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gemm_planes<CFG, PREC>), dim3(n), dim3(256), smem, st, p.d_probs, p.d_tiles, p.cfg_off[CFG],
+                     d_tabs, s, pl);
+  HIP_CHECK_LAUNCH();
+}
+
+template <int PREC>
+void launch_prec_planes(const GemmPlan& p, const long long* d_tabs, const Slots& s, const Planes& pl, hipStream_t st) {
+  launch_cfg_planes<0, PREC>(p, d_tabs, s, pl, st);
+  launch_cfg_planes<1, PREC>(p, d_tabs, s, pl, st);
+  launch_cfg_planes<2, PREC>(p, d_tabs, s, pl, st);
+  launch_cfg_planes<3, PREC>(p, d_tabs, s, pl, st);
+  launch_cfg_planes<4, PREC>(p, d_tabs, s, pl, st);
+}
+
+void launch_gemm_planes(const GemmPlan& p, const long long* d_tabs, const Slots& s, const Planes& pl, int precision,
+                        hipStream_t st) {
+  if (p.ntiles == 0) return;
+  TT_REQUIRE(p.wave_blocks == 0 && p.splits.empty(), TT_EINVAL, "planes: the plan must have LDS tiles only, unsplit");
+  prof_begin(st);
+  if (precision == TT_BF16X3) launch_prec_planes<TT_BF16X3>(p, d_tabs, s, pl, st);
+  else if (precision == TT_BF16X6) launch_prec_planes<TT_BF16X6>(p, d_tabs, s, pl, st);
+  else throw Error(TT_EINVAL, "planes: split-BF16 precisions only");
+  prof_end(st, p.tag, p.flops, p.bytes);
+}
+
+// out[p * pstride + i] = part p of x[i] (x ~ part 0 + part 1 (+ part 2), each
+// rounded to nearest BF16)
+template <int NP>
+__global__ void k_split(const double* __restrict__ x, long long n, __bf16* __restrict__ out, long long pstride) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    __bf16 parts[3];
+    bf16_split<NP>(x[i], parts);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) out[p * pstride + i] = parts[p];
+  }
+}
+
+void launch_split(const double* x, long long n, void* out, long long pstride, int precision, hipStream_t st) {
+  if (n <= 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  if (precision == TT_BF16X3)
+    hipLaunchKernelGGL(k_split<2>, dim3((unsigned)blocks), dim3(256), 0, st, x, n, (__bf16*)out, pstride);
+  else if (precision == TT_BF16X6)
+    hipLaunchKernelGGL(k_split<3>, dim3((unsigned)blocks), dim3(256), 0, st, x, n, (__bf16*)out, pstride);
+  else
+    throw Error(TT_EINVAL, "split: split-BF16 precisions only");
+  HIP_CHECK_LAUNCH();
 }
 
 void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, int nb, int precision,

@@ -214,7 +214,7 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
     int cfg = gemm_cfg_for(g.M, g.N);
     tiles0 += (long long)((g.M + kGemmBM[cfg] - 1) / kGemmBM[cfg]) * ((g.N + kGemmBN[cfg] - 1) / kGemmBN[cfg]);
   }
-  const bool may_split = tiles0 < kSplitBelowTiles;
+  const bool may_split = tiles0 < kSplitBelowTiles && !p.no_split;
   for (int i = 0; i < (int)p.probs.size(); ++i) {
     const GemmProb& g = p.probs[i];
     if (use_wave(g)) continue;

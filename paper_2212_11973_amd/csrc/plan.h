@@ -126,6 +126,7 @@ struct GemmPlan {
   GemmJob* d_jobs = nullptr;
   int wave_blocks = 0;
   double wave_flops = 0, wave_bytes = 0;
+  bool no_split = false;    // never split K (tiles whose result is written as BF16 planes)
 };
 struct WPlan {
   bool f32 = false;    // input and output stored as float

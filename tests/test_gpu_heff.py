@@ -71,6 +71,22 @@ def test_heff_apply_d2000_sampled():
     assert np.abs(g - want).max() <= 1e-12 * scale, (np.abs(g - want).max(), scale)
 
 
+@pytest.mark.parametrize("prec", [T.TT_FP32, T.TT_BF16X3, T.TT_BF16X6])
+def test_heff_apply_d2000_sampled_mixed(prec):
+    """The timed configuration of the mixed dense apply (pre-split BF16 planes
+    in the split-BF16 modes) on sampled outputs, to the mixed bounds below."""
+    D = 2000
+    L, W, A, R = WL.heff_inputs(D)
+    got = _apply_gpu(L, W, A, R, prec)
+    rng = np.random.default_rng(8)
+    idx = [(int(rng.integers(D)), int(rng.integers(4)), int(rng.integers(4)), int(rng.integers(D))) for _ in range(16)]
+    want = _sampled_reference(L, W, A, R, idx)
+    g = np.array([got[i] for i in idx])
+    err = np.linalg.norm(g - want) / np.linalg.norm(want)
+    print("precision", prec, "sampled relative error at D=2000", err)
+    assert err < MIXED_TOL[prec], err
+
+
 # relative Frobenius error bounds of the mixed paths (one apply, N(0,1) inputs):
 # FP32 MFMA rounds operands to 24 bits; split-BF16 x3 keeps ~16 bits per
 # operand, x6 ~24 bits; accumulation is FP32 inside a K tile, FP64 across.
