@@ -129,6 +129,8 @@ typedef struct {
      updates, absorbs */
   double t_heff, t_bond, t_lanczos, t_qr, t_env, t_absorb;
   long long n_launches;    /* kernels enqueued (a replayed sweep graph counts the launches it holds) */
+  double discarded;        /* tdvp_sweep2: the largest discarded weight of a split, sum of the dropped
+                              squared singular values over the sum of all of them; 0 otherwise */
 } tt_sweep_stats;
 
 /* Default options: D=64, symmetry=1, beta0=1e-2, taylor_order=1, K=8,
@@ -159,6 +161,29 @@ int tdvp_sweep(tt_state* state, double dbeta, tt_sweep_stats* stats);
  * tdvp_sweep calls bit for bit.  A state may appear only once (TT_EINVAL).
  * stats (may be NULL) are summed. */
 int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* stats);
+
+/* One symmetric 2-TDVP step beta -> beta + dbeta (SM Sec. "2-TDVP in the
+ * initial stage", Eq. S-2TDVP), which grows the bonds: left to right over the
+ * pairs (k, k+1), the two-site tensor Theta = A_k A_{k+1} <- exp(-tau
+ * H^(2)) Theta (Lanczos, normalised into Lambda), split by an SVD in every
+ * charge sector of the middle bond with a left-orthonormal A_k, the left
+ * environment, then the backward step A_{k+1} <- exp(+tau H^(1)) A_{k+1};
+ * the two exponentials of the last pair merged into one with 2 tau; right to
+ * left mirrored (A_k = U S, A_{k+1} = V^+, the right environment, then
+ * A_k <- exp(+tau H^(1)) A_k for k > 0).  Each split keeps the largest
+ * singular values over all sectors: at most D_max, each above cutoff times
+ * the largest (cutoff 0: no relative threshold), exact zeros never, at least
+ * one.  A sector may appear or vanish at every split; the bond sectors of the
+ * state change accordingly and every plan is rebuilt for them before the
+ * call returns (cached observable plans and a captured sweep are dropped).
+ * Typical use: start at the bare rho0 (opts.D = 1, pad_eps = 0), run a few
+ * tdvp_sweep2 steps until the bonds reach the wanted size, then tdvp_sweep.
+ * FP64 states only (TT_EINVAL otherwise).  TT_ENUMERIC if a later
+ * truncation left a bond sector with more states than the one-site gauge
+ * moves can hold (the bond's neighbours reach fewer states): then only
+ * tdvp_sweep2 and the observables run on the state until a further
+ * tdvp_sweep2 repairs it.  Synchronises; stats may be NULL. */
+int tdvp_sweep2(tt_state* state, double dbeta, int D_max, double cutoff, tt_sweep_stats* stats);
 
 /* How each site applies H^(1) (SM Fig. optimalB(c)); the result is the same
  * up to rounding.  Form 0 is the contraction order of SM Fig. Lanczos: T1 =

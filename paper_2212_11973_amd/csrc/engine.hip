@@ -161,6 +161,14 @@ struct tt_state {
   double *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Z = nullptr, *U = nullptr;
   double *Sbuf = nullptr, *tmp = nullptr, *kry = nullptr, *wv = nullptr, *qrws = nullptr;
   double* pws = nullptr;                   // partial tiles of K-split GEMMs
+  // capacities (doubles) of the scratch buffers above; the 2-TDVP steps grow them
+  long long cap_T1 = 0, cap_T2 = 0, cap_Y = 0, cap_Z = 0, cap_U = 0, cap_pws = 0, cap_tmp = 0, cap_Sbuf = 0,
+            cap_kry = 0, cap_wv = 0;
+  // 2-TDVP: the two-site tensor, the H^(2) intermediates, the SVD work array
+  // and singular values (allocated by the first two-site sweep)
+  double *th = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *svw = nullptr, *svs = nullptr;
+  long long cap_th = 0, cap_P1 = 0, cap_P2 = 0, cap_P3 = 0, cap_svw = 0, cap_svs = 0;
+  bool one_site_ok = true;                 // every QR/LQ block has at least as many rows as columns
   double* LW = nullptr;                    // the MPO folded into the left environment of site lw_site
   int lw_site = -1;                        // -1: LW holds no current fold
   std::vector<char> fold;                  // per site: 1 = apply with the MPO folded into L, 0 = L.A, W, .R
@@ -202,34 +210,51 @@ struct tt_state {
   ~tt_state();
 };
 
-tt_state::~tt_state() {
-  // work enqueued on this state's buffers (a construction that failed part way
-  // included) must finish before they go back to the allocator
-  (void)hipStreamSynchronize(g_stream);
-  for (auto& p : plans) {
+// release every plan descriptor, table and scratch buffer sized by the plans
+// (everything the bonds determine apart from the site tensors, environments,
+// Lambda and the 2-TDVP buffers); cached observable plans and a captured sweep too
+void free_scratch(tt_state& s) {
+  auto free_site = [](SitePlan& p) {
     free_plan(p.s1); free_plan(p.s3); free_plan(p.el); free_plan(p.r1); free_plan(p.r3);
     free_plan(p.absL); free_plan(p.absR); free_plan(p.b1); free_plan(p.b2);
     free_plan(p.w2); free_plan(p.wr); free_plan(p.qr); free_plan(p.lq);
     free_plan(p.lw); free_plan(p.t2zero);
     for (auto& g : p.s1w) free_plan(g);
+  };
+  for (auto& p : s.plans) free_site(p);
+  for (double** p : {&s.T1, &s.T2, &s.Y, &s.Z, &s.U, &s.Sbuf, &s.tmp, &s.kry, &s.wv, &s.qrws, &s.vtr, &s.pws, &s.LW,
+                     &s.Ea, &s.Eb, &s.Xs}) {
+    dfree(*p);
+    *p = nullptr;
   }
-  for (auto p : A) dfree(p);
-  for (auto p : Lenv) dfree(p);
-  for (auto p : Renv) dfree(p);
-  for (double* p : {T1, T2, Y, Z, U, Sbuf, tmp, kry, wv, qrws, part, lz, vtr, pws, LW}) dfree(p);
-  dfree(d_sites); dfree(d_trace); dfree(d_trace_start); dfree(tabs.dev);
-  for (auto& g : swp1) free_plan(g);
-  for (auto& g : swp2) free_plan(g);
-  dfree(Ea); dfree(Eb); dfree(Xs);
-  if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
-  for (auto& kv : obs) {
-    ObsMpo& O = kv.second;
+  s.cap_T1 = s.cap_T2 = s.cap_Y = s.cap_Z = s.cap_U = s.cap_pws = s.cap_tmp = s.cap_Sbuf = s.cap_kry = s.cap_wv = 0;
+  dfree(s.d_sites); dfree(s.d_trace); dfree(s.d_trace_start); dfree(s.tabs.dev);
+  s.d_sites = nullptr; s.d_trace = nullptr; s.d_trace_start = nullptr;
+  s.tabs = SiteTables();
+  for (auto& g : s.swp1) free_plan(g);
+  for (auto& g : s.swp2) free_plan(g);
+  if (s.sg.exec) (void)hipGraphExecDestroy(s.sg.exec);
+  s.sg = tt_state::SweepGraph();
+  for (auto& kv : s.obs) {
+    tt_state::ObsMpo& O = kv.second;
     for (auto& p : O.plans) {
       free_plan(p.s1); free_plan(p.s3); free_plan(p.r1); free_plan(p.r3); free_plan(p.w2); free_plan(p.wr);
     }
     for (double* p : {O.ea, O.eb, O.unit, O.pws, O.T1, O.T2, O.Y, O.Z}) dfree(p);
     dfree(O.tabs.dev);
   }
+  s.obs.clear();
+}
+
+tt_state::~tt_state() {
+  // work enqueued on this state's buffers (a construction that failed part way
+  // included) must finish before they go back to the allocator
+  (void)hipStreamSynchronize(g_stream);
+  free_scratch(*this);
+  for (auto p : A) dfree(p);
+  for (auto p : Lenv) dfree(p);
+  for (auto p : Renv) dfree(p);
+  for (double* p : {part, lz, th, P1, P2, P3, svw, svs}) dfree(p);
 }
 
 namespace {
@@ -664,6 +689,24 @@ void build_swap_plans(tt_state& s) {
   }
 }
 
+// every contraction block of a sweep goes to the wave GEMM, which multiplies
+// in the state's precision; the absorb step always runs in FP64
+void configure_plan(const tt_options& o, SitePlan& P) {
+  for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = true;
+  for (GemmPlan& g : P.s1w) g.wave_ok = true;
+  P.absL.wave_ok = P.absR.wave_ok = true;
+  if (o.precision == TT_FP32) {
+    // FP32 mode keeps the intermediates of H_eff and of the environment
+    // updates (T1, T2, Y, Z) in float: half the memory traffic of those stages
+    P.s1.slot_f32[2] = P.r1.slot_f32[2] = true;   // T1, Y written
+    P.s3.slot_f32[0] = true;                      // T2 read
+    P.el.slot_f32[1] = P.r3.slot_f32[1] = true;   // T2, Z read
+    P.w2.f32 = P.wr.f32 = true;
+    for (GemmPlan& g : P.s1w) g.slot_f32[2] = true;   // T2 written (and read back by the later passes)
+    P.t2zero.f32 = true;
+  }
+}
+
 void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   const int N = s.N;
   s.bonds.assign(N + 1, Bond());
@@ -700,27 +743,21 @@ void build_layouts(tt_state& s, const std::vector<std::map<Q, int>>& dims) {
   for (int k = 0; k < N; ++k)
     s.plans.push_back(
         build_site_plan(k, s.bonds[k], s.bonds[k + 1], s.G, s.qH[k], s.qH[k + 1], s.Wenv[k], s.Wpat[k], s.tabs));
-  // every contraction block of a sweep goes to the wave GEMM, which multiplies
-  // in the state's precision; the absorb step always runs in FP64
-  for (auto& P : s.plans) {
-    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3, &P.b1, &P.b2}) g->wave_ok = true;
-    for (GemmPlan& g : P.s1w) g.wave_ok = true;
-    P.absL.wave_ok = P.absR.wave_ok = true;
-    if (s.opts.precision == TT_FP32) {
-      // FP32 mode keeps the intermediates of H_eff and of the environment
-      // updates (T1, T2, Y, Z) in float: half the memory traffic of those stages
-      P.s1.slot_f32[2] = P.r1.slot_f32[2] = true;   // T1, Y written
-      P.s3.slot_f32[0] = true;                      // T2 read
-      P.el.slot_f32[1] = P.r3.slot_f32[1] = true;   // T2, Z read
-      P.w2.f32 = P.wr.f32 = true;
-      for (GemmPlan& g : P.s1w) g.slot_f32[2] = true;   // T2 written (and read back by the later passes)
-      P.t2zero.f32 = true;
-    }
-  }
+  for (auto& P : s.plans) configure_plan(s.opts, P);
   build_swap_plans(s);
 }
 
-void alloc_state(tt_state& s) {
+bool qr_fits(const QRPlan& p) {
+  for (const QRTask& t : p.tasks)
+    if (t.m < t.n) return false;
+  return true;
+}
+
+// plan descriptors, tables and the scratch buffers the plans size, for the
+// current bonds (the site tensors must exist: the trace kernel takes their
+// addresses).  A state marked !one_site_ok keeps no QR/LQ descriptors for
+// blocks with fewer rows than columns.
+void alloc_scratch(tt_state& s) {
   const int N = s.N;
   hipStream_t st = ST();
   s.tabs.dev = upload(s.tabs.host, st);
@@ -732,7 +769,8 @@ void alloc_state(tt_state& s) {
     upload_plan(P.b1, T, st); upload_plan(P.b2, T, st);
     for (int j = 0; j < P.n_s1w; ++j) upload_plan(P.s1w[j], T, st);
     upload_plan(P.w2, st); upload_plan(P.lw, st); upload_plan(P.t2zero, st); upload_plan(P.wr, st);
-    upload_plan(P.qr, st); upload_plan(P.lq, st);
+    if (s.one_site_ok || qr_fits(P.qr)) upload_plan(P.qr, st);
+    if (s.one_site_ok || qr_fits(P.lq)) upload_plan(P.lq, st);
     t1 = std::max(t1, P.t1_size); lw = std::max(lw, P.lw_size); t2 = std::max(t2, P.t2_size);
     y = std::max(y, P.y_size); z = std::max(z, P.z_size); u = std::max(u, P.u_size);
     qw = std::max(qw, std::max(P.qr.ws_size + P.qr.lds_ws, P.lq.ws_size + P.lq.lds_ws));
@@ -745,6 +783,7 @@ void alloc_state(tt_state& s) {
     for (int j = 0; j < P.n_s1w; ++j) pw = std::max(pw, P.s1w[j].pws_size);
   }
   s.pws = (double*)dalloc(8 * pw);
+  s.cap_pws = pw;
   s.max_site = 0;
   for (auto& l : s.site) s.max_site = std::max(s.max_site, l.size);
   s.max_bmat = 0;
@@ -756,31 +795,24 @@ void alloc_state(tt_state& s) {
     s.max_env = std::max(s.max_env, s.env[k].size);
   }
   long long nvec = std::max(s.max_site, s.max_bmat);
-  s.A.resize(N);
-  for (int k = 0; k < N; ++k) s.A[k] = (double*)dalloc(8 * s.site[k].size);
-  s.Lenv.assign(N + 1, nullptr);
-  s.Renv.assign(N + 1, nullptr);
-  for (int k = 0; k <= N; ++k) {
-    s.Lenv[k] = (double*)dalloc(8 * s.env[k].size);
-    s.Renv[k] = (double*)dalloc(8 * s.env[k].size);
-    launch_fill(s.Lenv[k], 0.0, s.env[k].size, st);   // defined contents before the first sweep builds them
-  }
-  s.T1 = (double*)dalloc(8 * std::max(t1, 1LL));
-  s.LW = (double*)dalloc(8 * std::max(lw, 1LL));
+  auto buf = [](double*& p, long long& cap, long long n) {
+    cap = std::max(n, 1LL);
+    p = (double*)dalloc(8 * cap);
+  };
+  buf(s.T1, s.cap_T1, t1);
+  long long cap_lw = 0;
+  buf(s.LW, cap_lw, lw);
   s.lw_site = -1;
   s.fold.assign(N, 0);
-  s.T2 = (double*)dalloc(8 * std::max(t2, 1LL));
-  s.Y = (double*)dalloc(8 * std::max(y, 1LL));
-  s.Z = (double*)dalloc(8 * std::max(z, 1LL));
-  s.U = (double*)dalloc(8 * std::max(u, 1LL));
-  s.Sbuf = (double*)dalloc(8 * s.max_bmat);
-  s.tmp = (double*)dalloc(8 * s.max_site);
-  s.kry = (double*)dalloc(8 * nvec * (long long)s.opts.krylov_dim);
-  s.wv = (double*)dalloc(8 * nvec);
+  buf(s.T2, s.cap_T2, t2);
+  buf(s.Y, s.cap_Y, y);
+  buf(s.Z, s.cap_Z, z);
+  buf(s.U, s.cap_U, u);
+  buf(s.Sbuf, s.cap_Sbuf, s.max_bmat);
+  buf(s.tmp, s.cap_tmp, s.max_site);
+  buf(s.kry, s.cap_kry, nvec * (long long)s.opts.krylov_dim);
+  buf(s.wv, s.cap_wv, nvec);
   s.qrws = (double*)dalloc(8 * std::max(qw, 1LL));
-  s.part = (double*)dalloc(8 * 2 * (long long)kRedBlocks * (kMaxKrylov + 2));
-  s.lz = (double*)dalloc(8 * (4 * kMaxKrylov + 16));
-  launch_fill(s.lz, 0.0, 4 * kMaxKrylov + 16, st);
   s.vtr = (double*)dalloc(8 * 2 * s.max_bond);
   for (auto& g : s.swp1) upload_plan(g, &s.tabs.host, st);
   for (auto& g : s.swp2) upload_plan(g, &s.tabs.host, st);
@@ -806,6 +838,24 @@ void alloc_state(tt_state& s) {
   s.d_trace = upload(te, st);
   s.d_trace_start = upload(start, st);
   s.d_sites = upload(s.A, st);
+}
+
+void alloc_state(tt_state& s) {
+  const int N = s.N;
+  hipStream_t st = ST();
+  s.A.resize(N);
+  for (int k = 0; k < N; ++k) s.A[k] = (double*)dalloc(8 * s.site[k].size);
+  s.Lenv.assign(N + 1, nullptr);
+  s.Renv.assign(N + 1, nullptr);
+  for (int k = 0; k <= N; ++k) {
+    s.Lenv[k] = (double*)dalloc(8 * s.env[k].size);
+    s.Renv[k] = (double*)dalloc(8 * s.env[k].size);
+    launch_fill(s.Lenv[k], 0.0, s.env[k].size, st);   // defined contents before the first sweep builds them
+  }
+  s.part = (double*)dalloc(8 * 2 * (long long)kRedBlocks * (kMaxKrylov + 2));
+  s.lz = (double*)dalloc(8 * (4 * kMaxKrylov + 16));
+  launch_fill(s.lz, 0.0, 4 * kMaxKrylov + 16, st);
+  alloc_scratch(s);
 }
 
 // rho0 tensors embedded in the padded block-sparse layout, plus the noise
@@ -1114,8 +1164,8 @@ long long check_sweep_plans(tt_state& s, std::string& rep) {
     bad += check_gemm(P.b1, T, b1, "b1", rep);
     bad += check_gemm(P.b2, T, b2, "b2", rep);
     bad += check_w(P.wr, P.y_size, P.z_size, "wr", rep);
-    bad += check_qr(P.qr, T, ns, s.bmat[k + 1].size, "qr", rep);
-    bad += check_qr(P.lq, T, ns, s.bmat[k].size, "lq", rep);
+    if (s.one_site_ok || qr_fits(P.qr)) bad += check_qr(P.qr, T, ns, s.bmat[k + 1].size, "qr", rep);
+    if (s.one_site_ok || qr_fits(P.lq)) bad += check_qr(P.lq, T, ns, s.bmat[k].size, "lq", rep);
     if (k < (int)s.swp1.size()) {
       tile_plan(s.swp1[k], &T);
       tile_plan(s.swp2[k], &T);
@@ -1154,6 +1204,331 @@ void require_sweep_plans(tt_state& s) {
   std::string rep;
   const long long bad = check_sweep_plans(s, rep);
   TT_REQUIRE(bad == 0, TT_EINVAL, "plans out of bounds (" + std::to_string(bad) + "): " + rep);
+}
+
+// ------------------------------------------------------------ 2-TDVP
+// SM Sec. "2-TDVP in the initial stage" (Eq. S-2TDVP): the two-site flow
+// grows (or truncates) every bond by an SVD of the evolved two-site tensor.
+// Bond sectors change at every split, so the descriptors of the two sites a
+// step touches are rebuilt there (the other sites' plans and tables are not
+// launched until the sweep ends) and every plan is rebuilt for the final
+// bonds afterwards.
+
+void grow(double*& p, long long& cap, long long n) {
+  n = std::max(n, 1LL);
+  if (p && n <= cap) return;
+  if (p) HIPX(hipStreamSynchronize(ST()));
+  dfree(p);
+  p = nullptr;
+  p = (double*)dalloc(8 * n);
+  cap = n;
+}
+
+void free_site_plan(SitePlan& p) {
+  free_plan(p.s1); free_plan(p.s3); free_plan(p.el); free_plan(p.r1); free_plan(p.r3);
+  free_plan(p.absL); free_plan(p.absR); free_plan(p.b1); free_plan(p.b2);
+  free_plan(p.w2); free_plan(p.wr); free_plan(p.qr); free_plan(p.lq);
+  free_plan(p.lw); free_plan(p.t2zero);
+  for (auto& g : p.s1w) free_plan(g);
+}
+
+// device copies of the two-site plan of one step
+struct PairDev {
+  PairPlan P;
+  SiteTables tabs;
+  SvdTask* d_svd = nullptr;
+  PairDev() = default;
+  PairDev(const PairDev&) = delete;
+  PairDev& operator=(const PairDev&) = delete;
+  ~PairDev() {
+    free_plan(P.join); free_plan(P.s1); free_plan(P.s4); free_plan(P.w1); free_plan(P.w2);
+    dfree(d_svd);
+    dfree(tabs.dev);
+  }
+};
+
+long long check_pair(const tt_state& s, int k, const PairPlan& P, const std::vector<long long>& T, std::string& rep) {
+  long long bad = 0;
+  const long long th = P.L.size, el = s.env[k].size, er = s.env[k + 2].size;
+  const long long j[kSlots] = {s.site[k].size, s.site[k + 1].size, th, 0};
+  const long long a1[kSlots] = {el, th, P.t1_size, 0}, a4[kSlots] = {P.t3_size, er, th, 0};
+  bad += check_gemm(P.join, T, j, "join", rep);
+  bad += check_gemm(P.s1, T, a1, "pair s1", rep);
+  bad += check_w(P.w1, P.t1_size, P.t2_size, "pair w1", rep);
+  bad += check_w(P.w2, P.t2_size, P.t3_size, "pair w2", rep);
+  bad += check_gemm(P.s4, T, a4, "pair s4", rep);
+  for (const SvdTask& t : P.svd) {
+    const Range r = map_range(T, t.rtab, 0, t.R);
+    const long long mn = std::min(t.R, t.w), mx = std::max(t.R, t.w);
+    if (t.R <= 0 || t.w <= 0 || r.lo < 0 || r.hi + t.w - 1 >= th || t.ws < 0 ||
+        t.ws + mx * mn + mn * mn > P.svd_ws || t.sig < 0 || t.sig + mn > P.svd_nsig) {
+      ++bad;
+      if (rep.size() < 2000) rep += "svd task out of range\n";
+    }
+  }
+  return bad;
+}
+
+std::unique_ptr<PairDev> make_pair(tt_state& s, int k) {
+  auto d = std::make_unique<PairDev>();
+  PairPlan& P = d->P;
+  P = build_pair_plan(s.bonds[k], s.bonds[k + 1], s.bonds[k + 2], s.G, s.qH[k], s.qH[k + 1], s.qH[k + 2],
+                      s.Wenv[k], s.Wenv[k + 1], s.site[k], s.site[k + 1], d->tabs);
+  const std::vector<long long>& T = d->tabs.host;
+  for (GemmPlan* g : {&P.join, &P.s1, &P.s4}) tile_plan(*g, &T);
+  std::string rep;
+  const long long bad = check_pair(s, k, P, T, rep);
+  TT_REQUIRE(bad == 0, TT_EINVAL, "two-site plans out of bounds (" + std::to_string(bad) + "): " + rep);
+  hipStream_t st = ST();
+  d->tabs.dev = upload(d->tabs.host, st);
+  for (GemmPlan* g : {&P.join, &P.s1, &P.s4}) upload_plan(*g, &T, st);
+  upload_plan(P.w1, st);
+  upload_plan(P.w2, st);
+  d->d_svd = upload(P.svd, st);
+  const long long n = P.L.size;
+  grow(s.th, s.cap_th, n);
+  grow(s.P1, s.cap_P1, P.t1_size);
+  grow(s.P2, s.cap_P2, P.t2_size);
+  grow(s.P3, s.cap_P3, P.t3_size);
+  grow(s.svw, s.cap_svw, P.svd_ws);
+  grow(s.svs, s.cap_svs, P.svd_nsig);
+  grow(s.kry, s.cap_kry, n * (long long)s.opts.krylov_dim);
+  grow(s.wv, s.cap_wv, n);
+  return d;
+}
+
+// H^(2) x (SM Eq. S-2TDVP): L.x, the MPO of site k, the MPO of site k+1, .R
+void apply_heff2(tt_state& s, int k, const PairDev& d, BPtr<double> x, BPtr<double> y) {
+  PhaseScope ps(PH_HEFF);
+  const PairPlan& P = d.P;
+  const long long* tb = d.tabs.dev;
+  launch_gemm(P.s1, tb, one(Slots{{s.Lenv[k], x.p[0], s.P1, nullptr}}), 1, TT_FP64, one(s.pws), ST());
+  launch_wstage(P.w1, one<const WTerm>(P.w1.d_terms), one<const double>(s.P1), one(s.P2), 1, ST());
+  launch_wstage(P.w2, one<const WTerm>(P.w2.d_terms), one<const double>(s.P2), one(s.P3), 1, ST());
+  launch_gemm(P.s4, tb, one(Slots{{s.P3, s.Renv[k + 2], y.p[0], nullptr}}), 1, TT_FP64, one(s.pws), ST());
+  add_flops(batch_of(s), P.s1.flops + P.w1.flops + P.w2.flops + P.s4.flops, true);
+  s.bytes_min += 8.0 * (s.env[k].size + s.env[k + 2].size + 2.0 * P.L.size);
+}
+
+// Theta = A_k A_{k+1}, then Theta <- exp(t H^(2)) Theta / ||.|| (log-norm into Lambda)
+void pair_exp(tt_state& s, int k, const PairDev& d, double t) {
+  const Batch b = batch_of(s);
+  launch_fill(s.th, 0.0, d.P.L.size, ST());
+  launch_gemm(d.P.join, d.tabs.dev, one(Slots{{s.A[k], s.A[k + 1], s.th, nullptr}}), 1, TT_FP64, one(s.pws), ST());
+  add_flops(b, d.P.join.flops, false);
+  lanczos_exp(b, t, one(s.th), d.P.L.size, [&](BPtr<double> x, BPtr<double> y) { apply_heff2(s, k, d, x, y); });
+}
+
+// SVD of every middle-charge block of Theta, the kept values chosen over all
+// blocks, the new middle bond, and the two site tensors written in its
+// layouts: A_k = U (left) or U S, A_{k+1} = S V^+ or V^+.  Returns the
+// discarded weight (dropped squared singular values over all of them).
+double split_pair(tt_state& s, int k, const PairDev& d, bool left, int Dmax, double cutoff) {
+  PhaseScope ps(PH_QR);
+  const PairPlan& P = d.P;
+  const int nt = (int)P.svd.size();
+  TT_REQUIRE(nt > 0, TT_ENUMERIC, "2-TDVP: the two-site tensor has no block");
+  launch_svd(d.d_svd, nt, d.tabs.dev, s.th, s.svw, s.svs, ST());
+  std::vector<double> sig((size_t)P.svd_nsig);
+  HIPX(hipMemcpyAsync(sig.data(), s.svs, 8 * (size_t)P.svd_nsig, hipMemcpyDeviceToHost, ST()));
+  HIPX(hipStreamSynchronize(ST()));
+  struct SV { double v; int task, j; };
+  std::vector<SV> all;
+  for (int t = 0; t < nt; ++t) {
+    const int mn = std::min(P.svd[t].R, P.svd[t].w);
+    for (int j = 0; j < mn; ++j) all.push_back({sig[(size_t)(P.svd[t].sig + j)], t, j});
+  }
+  // largest first; equal values keep the (block, index) order
+  std::stable_sort(all.begin(), all.end(), [](const SV& a, const SV& b) { return a.v > b.v; });
+  const double smax = all.empty() ? 0.0 : all[0].v;
+  TT_REQUIRE(smax > 0.0 && std::isfinite(smax), TT_ENUMERIC, "2-TDVP: the two-site tensor vanished or overflowed");
+  size_t keep = 0;
+  while (keep < all.size() && keep < (size_t)Dmax && all[keep].v > 0.0 && (cutoff <= 0.0 || all[keep].v > cutoff * smax))
+    ++keep;
+  keep = std::max<size_t>(keep, 1);
+  double tot = 0.0, kept = 0.0;
+  for (size_t i = 0; i < all.size(); ++i) {
+    tot += all[i].v * all[i].v;
+    if (i < keep) kept += all[i].v * all[i].v;
+  }
+  std::vector<std::vector<int>> sel(nt);
+  for (size_t i = 0; i < keep; ++i) sel[all[i].task].push_back(all[i].j);
+  std::map<Q, int> dims;
+  for (int t = 0; t < nt; ++t)
+    if (!sel[t].empty()) dims[P.mq[t]] = (int)sel[t].size();
+  Bond nb;
+  for (auto& kv : dims) nb.add(kv.first, kv.second);
+  const SiteLayout SA = make_site_layout(s.bonds[k], nb, s.G), SB = make_site_layout(nb, s.bonds[k + 2], s.G);
+  std::vector<SvdEmit> em;
+  std::vector<long long> et;
+  long long bad = 0;
+  for (int t = 0; t < nt; ++t) {
+    if (sel[t].empty()) continue;
+    const int mi = nb.find(P.mq[t]);
+    const int kap = (int)sel[t].size();
+    SvdEmit e{};
+    e.task = t;
+    e.kappa = kap;
+    e.left = left ? 1 : 0;
+    e.atab = (long long)et.size();
+    for (const auto& rg : P.rowgroups[t]) {
+      const int l = rg[0], g1 = rg[1], p1 = rg[2];
+      if (SA.rsec[l][g1] != mi) { ++bad; continue; }
+      for (int x = 0; x < SA.dl[l]; ++x) {
+        const long long o = SA.base[l] + (long long)x * SA.C[l] + SA.colb[l][g1] + (long long)p1 * kap;
+        if (o < 0 || o + kap > SA.size) ++bad;
+        et.push_back(o);
+      }
+    }
+    if ((long long)et.size() - e.atab != P.svd[t].R) ++bad;
+    e.bbase = SB.base[mi];
+    e.bstride = SB.C[mi];
+    if (SB.C[mi] != P.svd[t].w || e.bbase + (long long)(kap - 1) * e.bstride + P.svd[t].w > SB.size) ++bad;
+    e.sel = (long long)et.size();
+    for (int j : sel[t]) et.push_back(j);
+    em.push_back(e);
+  }
+  TT_REQUIRE(bad == 0, TT_EINVAL, "2-TDVP: split descriptors out of bounds (" + std::to_string(bad) + ")");
+  double* An = (double*)dalloc(8 * std::max(SA.size, 1LL));
+  double* Bn = nullptr;
+  try {
+    Bn = (double*)dalloc(8 * std::max(SB.size, 1LL));
+  } catch (...) {
+    dfree(An);
+    throw;
+  }
+  long long* dt = upload(et, ST());
+  SvdEmit* de = upload(em, ST());
+  launch_svd_emit(d.d_svd, de, (int)em.size(), dt, s.svw, s.svs, An, Bn, ST());
+  HIPX(hipStreamSynchronize(ST()));
+  dfree(dt);
+  dfree(de);
+  dfree(s.A[k]);
+  dfree(s.A[k + 1]);
+  s.A[k] = An;
+  s.A[k + 1] = Bn;
+  s.bonds[k + 1] = nb;
+  return tot > 0.0 ? std::max(0.0, tot - kept) / tot : 0.0;
+}
+
+// layouts, environments' buffers and the one-site descriptors of sites k and
+// k+1 for the current bonds; the tables of every other site are dropped
+void install_sites(tt_state& s, int k) {
+  HIPX(hipStreamSynchronize(ST()));
+  free_site_plan(s.plans[k]);
+  free_site_plan(s.plans[k + 1]);
+  dfree(s.tabs.dev);
+  s.tabs = SiteTables();
+  s.env[k + 1] = make_env_layout(s.bonds[k + 1], s.qH[k + 1]);
+  s.bmat[k + 1] = make_bondmat_layout(s.bonds[k + 1]);
+  for (int j = k; j <= k + 1; ++j) {
+    s.site[j] = make_site_layout(s.bonds[j], s.bonds[j + 1], s.G);
+    s.plans[j] = build_site_plan(j, s.bonds[j], s.bonds[j + 1], s.G, s.qH[j], s.qH[j + 1], s.Wenv[j], s.Wpat[j],
+                                 s.tabs, false, false);
+    configure_plan(s.opts, s.plans[j]);
+  }
+  const auto& T = s.tabs.host;
+  std::string rep;
+  long long bad = 0;
+  for (int j = k; j <= k + 1; ++j) {
+    SitePlan& P = s.plans[j];
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3}) tile_plan(*g, &T);
+    const long long ns = s.site[j].size, el = s.env[j].size, er = s.env[j + 1].size;
+    const long long s1[kSlots] = {el, ns, P.t1_size, 0}, s3[kSlots] = {P.t2_size, er, ns, 0};
+    const long long se[kSlots] = {ns, P.t2_size, er, 0}, r1[kSlots] = {er, ns, P.y_size, 0};
+    const long long r3[kSlots] = {ns, P.z_size, el, 0};
+    bad += check_gemm(P.s1, T, s1, "s1", rep);
+    bad += check_w(P.w2, P.t1_size, P.t2_size, "w2", rep);
+    bad += check_gemm(P.s3, T, s3, "s3", rep);
+    bad += check_gemm(P.el, T, se, "el", rep);
+    bad += check_gemm(P.r1, T, r1, "r1", rep);
+    bad += check_w(P.wr, P.y_size, P.z_size, "wr", rep);
+    bad += check_gemm(P.r3, T, r3, "r3", rep);
+  }
+  TT_REQUIRE(bad == 0, TT_EINVAL, "2-TDVP: site plans out of bounds (" + std::to_string(bad) + "): " + rep);
+  hipStream_t st = ST();
+  s.tabs.dev = upload(s.tabs.host, st);
+  long long pw = 1;
+  for (int j = k; j <= k + 1; ++j) {
+    SitePlan& P = s.plans[j];
+    for (GemmPlan* g : {&P.s1, &P.s3, &P.el, &P.r1, &P.r3}) {
+      upload_plan(*g, &T, st);
+      pw = std::max(pw, g->pws_size);
+    }
+    upload_plan(P.w2, st);
+    upload_plan(P.wr, st);
+    grow(s.T1, s.cap_T1, P.t1_size);
+    grow(s.T2, s.cap_T2, P.t2_size);
+    grow(s.Y, s.cap_Y, P.y_size);
+    grow(s.Z, s.cap_Z, P.z_size);
+    grow(s.kry, s.cap_kry, s.site[j].size * (long long)s.opts.krylov_dim);
+    grow(s.wv, s.cap_wv, s.site[j].size);
+  }
+  grow(s.pws, s.cap_pws, pw);
+  for (double** e : {&s.Lenv[k + 1], &s.Renv[k + 1]}) {
+    dfree(*e);
+    *e = nullptr;
+    *e = (double*)dalloc(8 * std::max(s.env[k + 1].size, 1LL));
+  }
+  s.fold[k] = s.fold[k + 1] = 0;
+  s.lw_site = -1;
+}
+
+// one symmetric 2-TDVP step; returns the largest discarded weight of its splits
+double tdvp2_once(tt_state& s, double dbeta, int Dmax, double cutoff) {
+  const int N = s.N;
+  const Batch b = batch_of(s);
+  const double tau = 0.5 * dbeta;
+  double disc = 0.0;
+  std::fill(s.fold.begin(), s.fold.end(), (char)0);
+  s.lw_site = -1;
+  for (int k = 0; k + 2 < N; ++k) {   // left to right
+    {
+      auto d = make_pair(s, k);
+      pair_exp(s, k, *d, -tau);
+      disc = std::max(disc, split_pair(s, k, *d, true, Dmax, cutoff));
+    }
+    install_sites(s, k);
+    env_left(b, k);
+    site_exp(b, k + 1, +tau);
+  }
+  for (int k = N - 2; k >= 0; --k) {  // right to left; the last pair's two exponentials merged
+    {
+      auto d = make_pair(s, k);
+      pair_exp(s, k, *d, k == N - 2 ? -2.0 * tau : -tau);
+      disc = std::max(disc, split_pair(s, k, *d, false, Dmax, cutoff));
+    }
+    install_sites(s, k);
+    env_right(b, k + 1);
+    if (k > 0) site_exp(b, k, +tau);
+  }
+  s.beta += dbeta;
+  s.sweeps++;
+  return disc;
+}
+
+// every plan, table and scratch buffer for the bonds the two-site sweep left
+// (right environments are current; left ones are rebuilt by the next sweep)
+void rebuild_plans(tt_state& s) {
+  HIPX(hipStreamSynchronize(ST()));
+  const int N = s.N;
+  std::vector<std::map<Q, int>> dims(N + 1);
+  for (int k = 0; k <= N; ++k)
+    for (const Sector& sc : s.bonds[k].secs) dims[k][sc.q] = sc.dim;
+  free_scratch(s);
+  build_layouts(s, dims);
+  s.one_site_ok = true;
+  for (const SitePlan& P : s.plans)
+    if (!qr_fits(P.qr) || !qr_fits(P.lq)) s.one_site_ok = false;
+  require_sweep_plans(s);
+  for (int k = 0; k < N; ++k)
+    if (k > 0) {
+      dfree(s.Lenv[k]);
+      s.Lenv[k] = nullptr;
+      s.Lenv[k] = (double*)dalloc(8 * std::max(s.env[k].size, 1LL));
+      launch_fill(s.Lenv[k], 0.0, s.env[k].size, ST());
+    }
+  alloc_scratch(s);
 }
 
 int fail(const Error& e) { g_err = e.what(); return e.code; }
@@ -1768,6 +2143,7 @@ int tdvp_sweep(tt_state* s, double dbeta, tt_sweep_stats* stats) {
   ABI_BEGIN
   TT_REQUIRE(s, TT_EINVAL, "null state");
   TT_REQUIRE(std::isfinite(dbeta), TT_EINVAL, "dbeta must be finite");
+  TT_REQUIRE(s->one_site_ok, TT_EINVAL, "a bond sector exceeds what its neighbours reach: run tdvp_sweep2 first");
   reset_counters(*s);
   g_phase_on = g_phase && stats;
   struct PhaseOff { ~PhaseOff() { g_phase_on = false; } } phase_off;
@@ -1799,6 +2175,8 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
   TT_REQUIRE(states && n >= 1, TT_EINVAL, "need at least one state");
   for (int i = 0; i < n; ++i) TT_REQUIRE(states[i], TT_EINVAL, "null state in batch");
   for (int i = 0; i < n; ++i)
+    TT_REQUIRE(states[i]->one_site_ok, TT_EINVAL, "a bond sector exceeds what its neighbours reach: run tdvp_sweep2 first");
+  for (int i = 0; i < n; ++i)
     for (int j = 0; j < i; ++j) TT_REQUIRE(states[i] != states[j], TT_EINVAL, "a state appears twice in the batch");
   g_phase_on = g_phase && stats;
   struct PhaseOff { ~PhaseOff() { g_phase_on = false; } } phase_off;
@@ -1822,6 +2200,36 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
     fill_phases(stats);
     stats->n_launches = launch_count() - l0;
   }
+  ABI_END
+}
+
+int tdvp_sweep2(tt_state* s, double dbeta, int D_max, double cutoff, tt_sweep_stats* stats) {
+  ABI_BEGIN
+  TT_REQUIRE(s, TT_EINVAL, "null state");
+  TT_REQUIRE(std::isfinite(dbeta), TT_EINVAL, "dbeta must be finite");
+  TT_REQUIRE(D_max >= 1, TT_EINVAL, "D_max must be positive");
+  TT_REQUIRE(std::isfinite(cutoff) && cutoff >= 0.0, TT_EINVAL, "cutoff must be finite and >= 0");
+  TT_REQUIRE(s->opts.precision == TT_FP64, TT_EINVAL, "tdvp_sweep2 runs on FP64 states only");
+  TT_REQUIRE(s->N >= 2, TT_EINVAL, "tdvp_sweep2 needs at least two sites");
+  reset_counters(*s);
+  g_phase_on = g_phase && stats;
+  struct PhaseOff { ~PhaseOff() { g_phase_on = false; } } phase_off;
+  const long long l0 = launch_count();
+  auto t0 = std::chrono::steady_clock::now();
+  const double disc = tdvp2_once(*s, dbeta, D_max, cutoff);
+  rebuild_plans(*s);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    HIPX(hipStreamSynchronize(ST()));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(*s, stats, secs);
+    fill_phases(stats);
+    stats->n_launches = launch_count() - l0;
+    stats->discarded = disc;
+  }
+  TT_REQUIRE(s->one_site_ok, TT_ENUMERIC,
+             "tdvp_sweep2: a truncated bond sector exceeds what its neighbours reach; tdvp_sweep refuses this "
+             "state until a further tdvp_sweep2");
   ABI_END
 }
 

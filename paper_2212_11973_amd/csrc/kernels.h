@@ -102,6 +102,14 @@ void launch_copy(BPtr<double> dst, BPtr<const double> src, long long n, int nb, 
 void launch_fill(double* dst, double val, long long n, hipStream_t st);
 void launch_dot_final(const double* part, int nparts, int nv, double* out, hipStream_t st);
 
+// SVD of every task (one-sided Jacobi, one workgroup per task; ws holds the
+// plan's svd_ws doubles, sig its svd_nsig singular values), then the kept
+// vectors of every emit entry into the two site tensors
+void launch_svd(const SvdTask* d_tasks, int ntasks, const long long* d_tabs, const double* src, double* ws,
+                double* sig, hipStream_t st);
+void launch_svd_emit(const SvdTask* d_tasks, const SvdEmit* d_em, int nem, const long long* d_tabs, const double* ws,
+                     const double* sig, double* Aout, double* Bout, hipStream_t st);
+
 // pos[q]: position of the diagonal super index s = 5q (sigma = sigma' = q) in its charge group
 struct TraceEntry { long long src, C, xoff, dl, yoff, dr; int site, pos[4]; };
 void launch_trace(const TraceEntry* d_entries, const int* d_site_start, int N, double* const* d_sites,

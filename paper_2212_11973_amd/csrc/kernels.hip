@@ -2063,4 +2063,136 @@ void launch_trace(const TraceEntry* d_entries, const int* d_site_start, int N, d
   HIP_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------- SVD of the 2-TDVP split
+// One-sided Jacobi (Hestenes): the columns of X are rotated in pairs until
+// every pair is orthogonal to a relative tolerance; then X = U Sigma and the
+// product V of the rotations gives X_in = X V^T.  The pairs follow the
+// round-robin order (one index fixed, the others rotating), so the n/2
+// rotations of a round touch disjoint columns and run on separate waves; sums
+// are taken in a fixed order, so the result is deterministic.  Small singular
+// values keep their relative accuracy.  One workgroup per task.
+constexpr int kSvdThreads = 1024;
+constexpr int kSvdMaxSweeps = 40;
+
+__device__ inline double wave_sum64(double v) {
+  // butterfly: every lane ends with the same bits (each addition is commutative)
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __restrict__ tasks,
+                                                           const long long* __restrict__ tabs,
+                                                           const double* __restrict__ src, double* __restrict__ ws,
+                                                           double* __restrict__ sig) {
+  const SvdTask t = tasks[blockIdx.x];
+  const bool tr = t.R < t.w;
+  const int mw = tr ? t.w : t.R, nw = tr ? t.R : t.w;
+  double* X = ws + t.ws;
+  double* V = X + (long long)mw * nw;
+  const long long* rt = tabs + t.rtab;
+  const long long tot = (long long)t.R * t.w;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    const long long i = e / t.w, j = e - i * t.w;
+    const double v = src[rt[i] + j];
+    if (!tr) X[i + j * mw] = v;
+    else X[j + i * mw] = v;
+  }
+  for (long long e = threadIdx.x; e < (long long)nw * nw; e += blockDim.x) V[e] = (e / nw == e % nw) ? 1.0 : 0.0;
+  __shared__ int rotated;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int np = nw + (nw & 1);                 // an idle index when nw is odd
+  const double tol = 2.220446049250313e-16 * (double)(mw > 16 ? mw : 16);
+  __syncthreads();
+  for (int sw = 0; sw < kSvdMaxSweeps && np > 1; ++sw) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < np - 1; ++rd) {
+      for (int k = wave; k < np / 2; k += nwaves) {
+        int a = k == 0 ? 0 : 1 + (k + rd) % (np - 1);
+        int b = 1 + ((k == 0 ? 0 : np - 1 - k) + rd) % (np - 1);
+        if (a > b) { const int q = a; a = b; b = q; }
+        if (b >= nw) continue;
+        double* xa = X + (long long)a * mw;
+        double* xb = X + (long long)b * mw;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < mw; i += 64) {
+          const double u = xa[i], v = xb[i];
+          al += u * u; be += v * v; ga += u * v;
+        }
+        al = wave_sum64(al); be = wave_sum64(be); ga = wave_sum64(ga);
+        if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
+        for (int i = lane; i < mw; i += 64) {
+          const double u = xa[i], v = xb[i];
+          xa[i] = c * u - s * v;
+          xb[i] = s * u + c * v;
+        }
+        double* va = V + (long long)a * nw;
+        double* vb = V + (long long)b * nw;
+        for (int i = lane; i < nw; i += 64) {
+          const double u = va[i], v = vb[i];
+          va[i] = c * u - s * v;
+          vb[i] = s * u + c * v;
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int j = wave; j < nw; j += nwaves) {
+    const double* xj = X + (long long)j * mw;
+    double s2 = 0.0;
+    for (int i = lane; i < mw; i += 64) s2 += xj[i] * xj[i];
+    s2 = wave_sum64(s2);
+    if (lane == 0) sig[t.sig + j] = sqrt(s2);
+  }
+}
+
+// M = sum_j s_j u_j v_j^T with unit u_j (R entries) and v_j (w entries), read
+// from the Jacobi result: u_j = X_j / s_j, v_j = V_j when R >= w (X = M V);
+// u_j = V_j, v_j = X_j / s_j when R < w (X = M^T V).  Written as u to the left
+// and s v to the right (left-orthonormal split), or s u and v.
+__global__ __launch_bounds__(256) void k_svd_emit(const SvdTask* __restrict__ tasks, const SvdEmit* __restrict__ em,
+                                                 const long long* __restrict__ tabs, const double* __restrict__ ws,
+                                                 const double* __restrict__ sig, double* __restrict__ Aout,
+                                                 double* __restrict__ Bout) {
+  const SvdEmit e = em[blockIdx.x];
+  const SvdTask t = tasks[e.task];
+  const bool tr = t.R < t.w;
+  const int mw = tr ? t.w : t.R, nw = tr ? t.R : t.w;
+  const double* X = ws + t.ws;
+  const double* V = X + (long long)mw * nw;
+  for (int mu = 0; mu < e.kappa; ++mu) {
+    const int j = (int)tabs[e.sel + mu];
+    const double s = sig[t.sig + j];
+    const double inv = 1.0 / s;   // only positive singular values are kept
+    for (int i = threadIdx.x; i < t.R; i += blockDim.x) {
+      const double u = tr ? V[i + (long long)j * nw] : X[i + (long long)j * mw] * inv;
+      Aout[tabs[e.atab + i] + mu] = e.left ? u : u * s;
+    }
+    for (int c = threadIdx.x; c < t.w; c += blockDim.x) {
+      const double v = tr ? X[c + (long long)j * mw] * inv : V[c + (long long)j * nw];
+      Bout[e.bbase + (long long)mu * e.bstride + c] = e.left ? v * s : v;
+    }
+  }
+}
+
+void launch_svd(const SvdTask* d_tasks, int ntasks, const long long* d_tabs, const double* src, double* ws,
+                double* sig, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_svd_jacobi, dim3(ntasks), dim3(kSvdThreads), 0, st, d_tasks, d_tabs, src, ws, sig);
+  HIP_CHECK_LAUNCH();
+}
+void launch_svd_emit(const SvdTask* d_tasks, const SvdEmit* d_em, int nem, const long long* d_tabs, const double* ws,
+                     const double* sig, double* Aout, double* Bout, hipStream_t st) {
+  if (nem <= 0) return;
+  hipLaunchKernelGGL(k_svd_emit, dim3(nem), dim3(256), 0, st, d_tasks, d_em, d_tabs, ws, sig, Aout, Bout);
+  HIP_CHECK_LAUNCH();
+}
+
 }  // namespace tt

@@ -713,4 +713,291 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
   return P;
 }
 
+// ---------------------------------------------------------------- 2-TDVP
+// The two-site step of SM Sec. "2-TDVP in the initial stage" (Eq. S-2TDVP) in
+// charge blocks: Theta = A_k A_{k+1}, then H^(2) Theta contracted as L.Theta,
+// the MPO of site k, the MPO of site k+1, then .R (the order of SM Fig.
+// Lanczos with one more W stage), and the SVD tasks of the split.
+PairPlan build_pair_plan(const Bond& bl, const Bond& bm, const Bond& br, const Groups& G,
+                         const std::vector<Q>& qHl, const std::vector<Q>& qHm, const std::vector<Q>& qHr,
+                         const std::vector<double>& W1, const std::vector<double>& W2,
+                         const SiteLayout& SA, const SiteLayout& SB, SiteTables& tabs) {
+  PairPlan P;
+  PairLayout& L = P.L;
+  const int DHl = (int)qHl.size(), DHm = (int)qHm.size(), DHr = (int)qHr.size();
+  const EnvLayout EL = make_env_layout(bl, qHl), ER = make_env_layout(br, qHr);
+  // columns of a middle charge: (g2, s2, y) for every g2 that reaches the right bond
+  auto width = [&](const Q& m) -> long long {
+    auto it = L.width.find(m);
+    if (it != L.width.end()) return it->second;
+    std::vector<MidBlock> v;
+    long long off = 0;
+    for (int g2 = 0; g2 < G.ng; ++g2) {
+      const int r = br.find(addq(m, G.delta[g2]));
+      if (r < 0) continue;
+      v.push_back({g2, r, off});
+      off += (long long)G.s[g2].size() * br.secs[r].dim;
+    }
+    L.mid[m] = v;
+    L.width[m] = off;
+    return off;
+  };
+  auto midblock = [&](const Q& m, int g2) -> const MidBlock* {
+    for (const MidBlock& b : L.mid.at(m))
+      if (b.g2 == g2) return &b;
+    return nullptr;
+  };
+  // ket-only MPO entry W[a, so, si, b] between super indices (the ancilla is unchanged)
+  auto wsup = [](const std::vector<double>& W, int DHo, int a, int sout, int sin, int b) -> double {
+    if ((sout & 3) != (sin & 3)) return 0.0;
+    return W[(size_t)((((long long)a * 4 + (sout >> 2)) * 4 + (sin >> 2)) * DHo + b)];
+  };
+
+  // ---------------- layout of Theta
+  L.nl = (int)bl.secs.size();
+  L.dl.resize(L.nl);
+  L.C.resize(L.nl);
+  L.base.resize(L.nl);
+  L.colg.resize(L.nl);
+  long long pos = 0;
+  for (int l = 0; l < L.nl; ++l) {
+    L.dl[l] = bl.secs[l].dim;
+    L.colg[l].fill(-1);
+    long long c = 0;
+    for (int g1 = 0; g1 < G.ng; ++g1) {
+      const long long w = width(addq(bl.secs[l].q, G.delta[g1]));
+      if (w == 0) continue;
+      L.colg[l][g1] = c;
+      c += (long long)G.s[g1].size() * w;
+    }
+    L.C[l] = c;
+    L.base[l] = pos;
+    pos += (long long)L.dl[l] * c;
+  }
+  L.size = pos;
+  // column of (s1, s2, y = 0) in the row block of l
+  auto tcol = [&](int l, int s1, int s2) -> long long {
+    const int g1 = G.group_of[s1];
+    const Q m = addq(bl.secs[l].q, G.delta[g1]);
+    const MidBlock* b = midblock(m, G.group_of[s2]);
+    TT_REQUIRE(L.colg[l][g1] >= 0 && b, TT_EINVAL, "pair plan: no such block");
+    return L.colg[l][g1] + (long long)G.pos_of[s1] * L.w(m) + b->off +
+           (long long)G.pos_of[s2] * br.secs[b->r].dim;
+  };
+  P.join.tag = TAG_ABSORB;
+  P.s1.tag = TAG_LA;
+  P.s4.tag = TAG_R;
+
+  // ---------------- join: Theta(l; s1, :) = A_k(l; s1, mu) . A_{k+1}(m; mu, :)
+  for (int l = 0; l < L.nl; ++l)
+    for (int g1 = 0; g1 < G.ng; ++g1) {
+      const int mi = SA.rsec[l][g1];
+      if (mi < 0) continue;
+      TT_REQUIRE(L.colg[l][g1] >= 0 && bm.secs[mi].q == addq(bl.secs[l].q, G.delta[g1]), TT_EINVAL,
+                 "pair plan: inconsistent middle bond");
+      const long long w = L.w(bm.secs[mi].q);
+      TT_REQUIRE(SB.C[mi] == w, TT_EINVAL, "pair plan: right site columns differ from the two-site layout");
+      const int dm = bm.secs[mi].dim;
+      for (int p1 = 0; p1 < (int)G.s[g1].size(); ++p1) {
+        GemmProb g = gp(L.dl[l], (int)w, dm, 0, 1, 2);
+        g.offA = SA.base[l] + SA.colb[l][g1] + (long long)p1 * dm; g.sam = SA.C[l]; g.sak = 1;
+        g.offB = SB.base[mi]; g.sbk = SB.C[mi]; g.sbn = 1;
+        g.offC = L.base[l] + L.colg[l][g1] + (long long)p1 * w; g.scm = L.C[l];
+        add_prob(P.join, g);
+      }
+    }
+
+  // ---------------- s1: T1_l[(a, x')][cols of Theta_l] = L^a . Theta_l
+  std::vector<long long> t1base(L.nl, 0);
+  std::vector<std::vector<int>> rowbase1(L.nl, std::vector<int>(DHl, -1));
+  pos = 0;
+  for (int l = 0; l < L.nl; ++l) {
+    std::vector<long long> rows;
+    for (int a = 0; a < DHl; ++a) {
+      const int p = bl.find(addq(bl.secs[l].q, qHl[a]));
+      if (p < 0 || EL.csec[p][a] != l) continue;
+      rowbase1[l][a] = (int)rows.size();
+      for (int x = 0; x < EL.dp[p]; ++x) rows.push_back(EL.base[p] + (long long)x * EL.K[p] + EL.colb[p][a]);
+    }
+    t1base[l] = pos;
+    if (rows.empty() || L.C[l] == 0) continue;
+    GemmProb g = gp((int)rows.size(), (int)L.C[l], L.dl[l], 0, 1, 2);
+    g.tam = tabs.add(rows); g.sak = 1;
+    g.offB = L.base[l]; g.sbk = L.C[l]; g.sbn = 1;
+    g.offC = pos; g.scm = L.C[l];
+    add_prob(P.s1, g);
+    pos += (long long)rows.size() * L.C[l];
+  }
+  P.t1_size = pos;
+
+  // ---------------- w1: T2_p[x'][(s1', b, cols of m)] = sum W_k[a, so1, si1, b] T1,
+  // m = p - qH(b) + Delta(s1') the (unchanged) middle ket charge
+  std::vector<long long> t2base(L.nl, 0), K2(L.nl, 0);
+  std::vector<long long> col2((size_t)L.nl * 16 * DHm, -1);
+  auto c2 = [&](int p, int s1, int b) -> long long& { return col2[((size_t)p * 16 + s1) * DHm + b]; };
+  auto mid_of = [&](int p, int s1, int b) { return addq(subq(bl.secs[p].q, qHm[b]), G.delta[G.group_of[s1]]); };
+  pos = 0;
+  for (int p = 0; p < L.nl; ++p) {
+    long long c = 0;
+    for (int g1 = 0; g1 < G.ng; ++g1)
+      for (int s1 : G.s[g1])
+        for (int b = 0; b < DHm; ++b) {
+          const long long w = width(mid_of(p, s1, b));
+          if (w == 0) continue;
+          c2(p, s1, b) = c;
+          c += w;
+        }
+    K2[p] = c;
+    t2base[p] = pos;
+    pos += (long long)L.dl[p] * c;
+  }
+  P.t2_size = pos;
+  for (int p = 0; p < L.nl; ++p)
+    for (int g1 = 0; g1 < G.ng; ++g1)
+      for (int so : G.s[g1])
+        for (int b = 0; b < DHm; ++b) {
+          if (c2(p, so, b) < 0) continue;
+          const Q m = mid_of(p, so, b);
+          WTask t;
+          t.dst = t2base[p] + c2(p, so, b);
+          t.dsi = K2[p];
+          t.dsj = 1;
+          t.ni = L.dl[p];
+          t.nj = (int)L.w(m);
+          t.t0 = (int)P.w1.terms.size();
+          for (int a = 0; a < DHl; ++a) {
+            const int l = EL.csec[p][a];
+            if (l < 0) continue;
+            for (int si = (so & 3); si < 16; si += 4) {
+              const double w = wsup(W1, DHm, a, so, si, b);
+              if (w == 0.0) continue;
+              const int gi = G.group_of[si];
+              TT_REQUIRE(addq(bl.secs[l].q, G.delta[gi]) == m && L.colg[l][gi] >= 0 && rowbase1[l][a] >= 0,
+                         TT_EINVAL, "pair plan: MPO entry breaks charge conservation (site k)");
+              WTerm tm;
+              tm.src = t1base[l] + (long long)rowbase1[l][a] * L.C[l] + L.colg[l][gi] + (long long)G.pos_of[si] * L.w(m);
+              tm.ssi = L.C[l];
+              tm.ssj = 1;
+              tm.w = w;
+              P.w1.terms.push_back(tm);
+            }
+          }
+          t.nt = (int)P.w1.terms.size() - t.t0;
+          P.w1.flops += 2.0 * t.nt * (double)t.ni * t.nj;
+          P.w1.tasks.push_back(t);
+        }
+
+  // ---------------- w2: T3 grouped by the right bra sector r', rows (p, s1', s2', x'),
+  // columns (c, y) as in R's row block r'
+  const int nr = (int)br.secs.size();
+  struct Row3 { int p, s1, s2; long long row; };
+  std::vector<std::vector<Row3>> rows3(nr);
+  std::vector<long long> t3base(nr, 0), nrows3(nr, 0);
+  for (int p = 0; p < L.nl; ++p)
+    for (int g1 = 0; g1 < G.ng; ++g1) {
+      if (L.colg[p][g1] < 0) continue;
+      const Q m = addq(bl.secs[p].q, G.delta[g1]);
+      for (int s1 : G.s[g1])
+        for (const MidBlock& mb : L.mid.at(m))
+          for (int s2 : G.s[mb.g2]) {
+            rows3[mb.r].push_back({p, s1, s2, nrows3[mb.r]});
+            nrows3[mb.r] += L.dl[p];
+          }
+    }
+  pos = 0;
+  for (int r = 0; r < nr; ++r) {
+    t3base[r] = pos;
+    pos += nrows3[r] * ER.K[r];
+  }
+  P.t3_size = pos;
+  for (int r = 0; r < nr; ++r)
+    for (const Row3& rw : rows3[r]) {
+      const int so2 = rw.s2;
+      for (int c = 0; c < DHr; ++c) {
+        const int ry = ER.csec[r][c];
+        if (ry < 0) continue;
+        WTask t;
+        t.dst = t3base[r] + rw.row * ER.K[r] + ER.colb[r][c];
+        t.dsi = ER.K[r];
+        t.dsj = 1;
+        t.ni = L.dl[rw.p];
+        t.nj = br.secs[ry].dim;
+        t.t0 = (int)P.w2.terms.size();
+        for (int b = 0; b < DHm; ++b) {
+          if (c2(rw.p, rw.s1, b) < 0) continue;
+          const Q m = mid_of(rw.p, rw.s1, b);
+          for (int si = (so2 & 3); si < 16; si += 4) {
+            const double w = wsup(W2, DHr, b, so2, si, c);
+            if (w == 0.0) continue;
+            const MidBlock* mb = midblock(m, G.group_of[si]);
+            if (!mb) continue;   // the ket block (m, s2) does not reach the right bond
+            TT_REQUIRE(mb->r == ry, TT_EINVAL, "pair plan: MPO entry breaks charge conservation (site k+1)");
+            WTerm tm;
+            tm.src = t2base[rw.p] + c2(rw.p, rw.s1, b) + mb->off + (long long)G.pos_of[si] * br.secs[ry].dim;
+            tm.ssi = K2[rw.p];
+            tm.ssj = 1;
+            tm.w = w;
+            P.w2.terms.push_back(tm);
+          }
+        }
+        t.nt = (int)P.w2.terms.size() - t.t0;
+        P.w2.flops += 2.0 * t.nt * (double)t.ni * t.nj;
+        P.w2.tasks.push_back(t);
+      }
+    }
+
+  // ---------------- s4: out rows (p, s1', s2', x') = T3_r' . R_r'^T
+  for (int r = 0; r < nr; ++r) {
+    if (nrows3[r] == 0) continue;
+    std::vector<long long> crow;
+    crow.reserve((size_t)nrows3[r]);
+    for (const Row3& rw : rows3[r]) {
+      const long long col = tcol(rw.p, rw.s1, rw.s2);
+      for (int x = 0; x < L.dl[rw.p]; ++x) crow.push_back(L.base[rw.p] + (long long)x * L.C[rw.p] + col);
+    }
+    GemmProb g = gp((int)nrows3[r], br.secs[r].dim, (int)ER.K[r], 0, 1, 2);
+    g.offA = t3base[r]; g.sam = ER.K[r]; g.sak = 1;
+    g.offB = ER.base[r]; g.sbk = 1; g.sbn = ER.K[r];
+    g.tcm = tabs.add(crow);
+    add_prob(P.s4, g);
+  }
+
+  // ---------------- split: one task per middle charge
+  for (const auto& kv : L.width) {
+    const Q& m = kv.first;
+    const long long w = kv.second;
+    if (w == 0) continue;
+    std::vector<std::array<int, 3>> rg;
+    std::vector<long long> rows;
+    for (int l = 0; l < L.nl; ++l)
+      for (int g1 = 0; g1 < G.ng; ++g1) {
+        if (L.colg[l][g1] < 0 || addq(bl.secs[l].q, G.delta[g1]) != m) continue;
+        for (int p1 = 0; p1 < (int)G.s[g1].size(); ++p1) {
+          rg.push_back({l, g1, p1});
+          for (int x = 0; x < L.dl[l]; ++x)
+            rows.push_back(L.base[l] + (long long)x * L.C[l] + L.colg[l][g1] + (long long)p1 * w);
+        }
+      }
+    if (rows.empty()) continue;
+    TT_REQUIRE(rows.size() < (1u << 30) && w < (1LL << 30), TT_EINVAL, "pair plan: split block too large");
+    SvdTask t;
+    t.R = (int)rows.size();
+    t.w = (int)w;
+    t.rtab = tabs.add(rows);
+    t.ws = P.svd_ws;
+    t.sig = P.svd_nsig;
+    const long long mn = std::min<long long>(t.R, t.w), mx = std::max<long long>(t.R, t.w);
+    P.svd_ws += mx * mn + mn * mn;
+    P.svd_nsig += mn;
+    P.svd.push_back(t);
+    P.mq.push_back(m);
+    P.rowgroups.push_back(rg);
+  }
+  finish_wplan(P.w1);
+  finish_wplan(P.w2);
+  P.join.no_split = P.s1.no_split = P.s4.no_split = true;
+  P.join.wave_ok = P.s1.wave_ok = P.s4.wave_ok = true;
+  return P;
+}
+
 }  // namespace tt

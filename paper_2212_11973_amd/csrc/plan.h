@@ -250,6 +250,56 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
                          bool super_op = false,           // W acts on the super index s = 4 sigma + sigma'
                          bool with_lw = true);            // also plan the MPO folded into L (lw, s1w, t2zero)
 
+// ---------------------------------------------------------------- 2-TDVP
+// Two-site tensor Theta = A_k A_{k+1} on the bonds (k, k+2) (SM Sec. "2-TDVP in
+// the initial stage", Eq. S-2TDVP): row block per left sector l (row-major),
+// columns (group g1, s1 in g1, then the columns of the middle charge
+// m = l + Delta(g1): group g2, s2 in g2, y in the right sector m + Delta(g2)).
+// Every middle charge that reaches the right bond is present, whether or not
+// the current middle bond holds it: the two-site update can grow new sectors.
+// Within a middle charge the columns are ordered as the row block of A_{k+1}.
+struct MidBlock { int g2, r; long long off; };
+struct PairLayout {
+  int nl = 0;
+  std::vector<int> dl;
+  std::vector<long long> C, base;
+  std::vector<std::array<long long, 9>> colg;   // per (l, g1): first column, or -1
+  std::map<Q, std::vector<MidBlock>> mid;       // middle charge -> its column blocks
+  std::map<Q, long long> width;                 // middle charge -> its column count
+  long long size = 0;
+  long long w(const Q& m) const { auto it = width.find(m); return it == width.end() ? 0 : it->second; }
+};
+// SVD of the split: the matrix M of one middle charge, rows (l, s1, x) of
+// Theta (M(i, j) = theta[tabs[rtab + i] + j], i < R, j < w).  The work array
+// holds X = M (R >= w) or M^T (R < w) column-major, then the accumulated
+// rotations V; the singular values go to sig.
+struct SvdTask { int R, w; long long rtab, ws, sig; };
+// Output of one task: kappa kept vectors (tabs[sel + mu] = column of X) into
+// the left site tensor (row i of M at tabs[atab + i], plus mu) and the right
+// one (bbase + mu * bstride + j); left: U to the left site (left-orthonormal
+// split), else U S to the left and V^+ to the right.
+struct SvdEmit { int task, kappa, left, pad; long long atab, bbase, bstride, sel; };
+struct PairPlan {
+  PairLayout L;
+  // join: 0 = A_k, 1 = A_{k+1}, 2 = Theta (blocks whose middle charge the
+  // current middle bond lacks stay as cleared beforehand)
+  GemmPlan join;
+  // H^(2): s1 (0 = L env, 1 = Theta, 2 = T1), w1 (T1 -> T2: the MPO of site
+  // k), w2 (T2 -> T3: the MPO of site k+1, rows grouped by the right bra
+  // sector), s4 (0 = T3, 1 = R env, 2 = output)
+  GemmPlan s1, s4;
+  WPlan w1, w2;
+  long long t1_size = 0, t2_size = 0, t3_size = 0;
+  // split: one SVD task per middle charge (rows in (l, g1, s1, x) order)
+  std::vector<Q> mq;
+  std::vector<std::vector<std::array<int, 3>>> rowgroups;   // per task: (l, g1, position of s1), dl rows each
+  std::vector<SvdTask> svd;
+  long long svd_ws = 0, svd_nsig = 0;
+};
+PairPlan build_pair_plan(const Bond& bl, const Bond& bm, const Bond& br, const Groups& G,
+                         const std::vector<Q>& qHl, const std::vector<Q>& qHm, const std::vector<Q>& qHr,
+                         const std::vector<double>& W1, const std::vector<double>& W2,   // ket-only DH x 4 x 4 x DH
+                         const SiteLayout& SA, const SiteLayout& SB, SiteTables& tabs);
 
 // tile the problems of a plan (shape per problem)
 int gemm_cfg_for(int M, int N);

@@ -26,7 +26,7 @@ SYMBOLS = [
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
     "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function", "thermo_pairing_order",
-    "tt_heff2_apply", "tt_heff_apply_noalloc", "tt_phase_timing", "tt_tune_apply",
+    "tt_heff2_apply", "tt_heff_apply_noalloc", "tt_phase_timing", "tt_tune_apply", "tdvp_sweep2",
 ]
 
 
@@ -55,7 +55,7 @@ class tt_sweep_stats(C.Structure):
                 ("n_applies", C.c_int), ("n_exps", C.c_int), ("max_krylov_err", C.c_double),
                 ("bytes_min", C.c_double), ("t_heff", C.c_double), ("t_bond", C.c_double),
                 ("t_lanczos", C.c_double), ("t_qr", C.c_double), ("t_env", C.c_double),
-                ("t_absorb", C.c_double), ("n_launches", C.c_longlong)]
+                ("t_absorb", C.c_double), ("n_launches", C.c_longlong), ("discarded", C.c_double)]
 
 
 class TTError(RuntimeError):
@@ -102,6 +102,7 @@ def lib(init_torch=True):
         L.mpo_init_highT.argtypes = [C.POINTER(tt_model), C.POINTER(tt_options), C.POINTER(vp)]
         L.tdvp_sweep.argtypes = [vp, C.c_double, C.POINTER(tt_sweep_stats)]
         L.tdvp_sweep_batch.argtypes = [C.POINTER(vp), C.c_int, C.c_double, C.POINTER(tt_sweep_stats)]
+        L.tdvp_sweep2.argtypes = [vp, C.c_double, C.c_int, C.c_double, C.POINTER(tt_sweep_stats)]
         L.thermo_observables.argtypes = [vp, C.POINTER(tt_observables)]
         L.thermo_local_observables.argtypes = [vp, dp]
         L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
@@ -169,6 +170,13 @@ def tdvp_sweep(state, dbeta, stats=False):
         return s
     _check(lib().tdvp_sweep(state, dbeta, None))
     return None
+
+
+def tdvp_sweep2(state, dbeta, D_max, cutoff=0.0, stats=False):
+    """One 2-TDVP step (bond growth by SVD splits); returns tt_sweep_stats if stats."""
+    s = tt_sweep_stats()
+    _check(lib().tdvp_sweep2(state, dbeta, int(D_max), float(cutoff), C.byref(s) if stats else None))
+    return s if stats else None
 
 
 def tdvp_sweep_batch(states, dbeta, stats=False):
@@ -418,6 +426,9 @@ class State:
 
     def sweep(self, dbeta, stats=False):
         return tdvp_sweep(self.h, dbeta, stats)
+
+    def sweep2(self, dbeta, D_max, cutoff=0.0, stats=False):
+        return tdvp_sweep2(self.h, dbeta, D_max, cutoff, stats)
 
     def observables(self):
         return thermo_observables(self.h)
