@@ -68,6 +68,26 @@ def build_host_sanitized(out_dir, verbose=False):
     return out
 
 
+def host_sanitized_cached(verbose=False):
+    """build_host_sanitized into _build_asan/<digest of the sources and
+    flags>, reusing an earlier build of the same sources (the device code
+    makes the build take a minute)."""
+    import hashlib
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    names = sorted(os.listdir(CSRC)) + [os.path.join("..", "..", "include", "tantrg.h")]
+    for n in names:
+        path = os.path.join(CSRC, n)
+        if os.path.isfile(path):
+            h.update(n.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    out_dir = os.path.join(HERE, "_build_asan", h.hexdigest()[:16])
+    lib = os.path.join(out_dir, "libtantrg.so")
+    if not os.path.exists(lib):
+        build_host_sanitized(out_dir, verbose)
+    return lib
+
+
 def asan_runtime():
     """Path of the compiler's shared ASan runtime (for LD_PRELOAD)."""
     clang = os.path.join(os.path.dirname(os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")), "..", "lib", "llvm",

@@ -43,9 +43,9 @@ DRIVER = textwrap.dedent("""
 """)
 
 
-def test_host_code_under_asan_and_ubsan(tmp_path):
+def test_host_code_under_asan_and_ubsan():
     from paper_2212_11973_amd import build as B
-    lib = B.build_host_sanitized(str(tmp_path / "asan"))
+    lib = B.host_sanitized_cached()
     env = dict(os.environ)
     env.update(TANTRG_LIB=lib, LD_PRELOAD=B.asan_runtime(), ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1", PYTHONPATH=ROOT)
