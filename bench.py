@@ -31,7 +31,11 @@ SHAPES = ("64x64", "128x32", "256x16", "32x128", "32x32")
 def kernel_name(kind, prec):
     if kind.startswith("k_gemm_") and kind != "k_gemm_reduce":
         return "tt::k_gemm<%d, %d>" % (SHAPES.index(kind[len("k_gemm_"):]), prec)
-    return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm", "wstage": "tt::k_wstage",
+    # the names rocprofv3 reports: the wave GEMM is instantiated per multiply
+    # type (FP64 multiplies in the FP64 and FP32 modes), the W stage per
+    # intermediate type (the 32-bit index form in the headline plans)
+    return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm<%d>" % (prec if prec >= 2 else 0),
+            "wstage": "tt::k_wstage<%s, int>" % ("double" if prec == 0 else "float"),
             "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
 
 
@@ -206,7 +210,9 @@ def sweep_only(args):
         stats.append(st.sweep(c["dbeta"], stats=True))   # returns after the stream is synchronised
         print("step %d done" % i, file=sys.stderr, flush=True)
     s_step = (time.perf_counter() - t0) / args.steps
-    obs = st.observables()
+    # under a counter run every dispatch after the calibration copy belongs to
+    # the timed sweeps: no observables then
+    obs = st.observables() if args.calib_copy_mib <= 0 else {"f": None, "e": None}
     st.free()
     print(json.dumps({"metric": "s/step (sweep only, no torch)", "value": s_step, "unit": "s/step",
                       "steps": args.steps, "warmup": args.warmup, "precision": args.precision,
@@ -268,6 +274,10 @@ def summarize_counters(args):
             fb = sum(cs["FETCH_SIZE"]) / len(cs["FETCH_SIZE"]) * factors["FETCH_SIZE"] * 1024
             wb = sum(cs["WRITE_SIZE"]) / len(cs["WRITE_SIZE"]) * factors["WRITE_SIZE"] * 1024
             out.append("traffic_bytes_per_launch[%s]=%.6g" % (k, fb + wb))
+        for t in ("F64", "F32", "BF16"):
+            v = cs.get("SQ_INSTS_VALU_MFMA_MOPS_" + t)
+            if v:   # each MOPS unit is 512 floating-point operations
+                out.append("mfma_%s_flop_per_launch[%s]=%.6g" % (t.lower(), k, sum(v) / len(v) * 512))
     path = os.path.join(ROOT, "profiles", "counters_%s_%s.txt" % (args.workload, args.precision))
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
