@@ -36,6 +36,7 @@ def kernel_name(kind, prec):
     # intermediate type (the 32-bit index form in the headline plans)
     return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm<%d>" % (prec if prec >= 2 else 0),
             "wstage": "tt::k_wstage<%s, int>" % ("double" if prec == 0 else "float"),
+            "k_fused": "tt::k_fused_apply",
             "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
 
 
@@ -216,7 +217,9 @@ def sweep_only(args):
     st.free()
     print(json.dumps({"metric": "s/step (sweep only, no torch)", "value": s_step, "unit": "s/step",
                       "steps": args.steps, "warmup": args.warmup, "precision": args.precision,
-                      "sector_cap": args.sector_cap, "apply_form": args.apply_form, "folded_sites": sum(forms),
+                      "sector_cap": args.sector_cap, "apply_form": args.apply_form,
+                      "site_forms_0_1_2": [sum(f & 3 == i for f in forms) for i in (0, 1, 2)],
+                      "fused_bonds": sum(f >> 2 for f in forms),
                       "workload": "%s D=%d" % (args.workload, D),
                       "flops_alg_per_step": statistics.mean(x.flops_alg for x in stats),
                       "applies_per_step": statistics.mean(x.n_applies for x in stats),
@@ -231,18 +234,17 @@ def summarize_counters(args):
     counter reading of the calibration copy (M MiB read and M MiB written),
     and their sum per launch is the measured HBM traffic.  Writes
     profiles/counters_<workload>_<precision>.txt."""
-    import sqlite3
     from collections import defaultdict
     known_kib = args.calib_copy_mib * 1024.0
     per = defaultdict(lambda: defaultdict(list))   # kernel -> counter -> values
     factors = {}
     for db in args.summarize_counters:
-        con = sqlite3.connect(db)
-        rows = con.execute("select dispatch_id, kernel_name, counter_name, value, duration from counters_collection "
-                           "order by dispatch_id").fetchall()
+        rows = read_counter_rows(db)
         counters = sorted({r[2] for r in rows})
         # the calibration copy: the copy kernel with the largest reading of the first counter
         copies = [r for r in rows if "copyBuffer" in r[1]]
+        if not copies:
+            raise SystemExit("%s: no calibration copy kernel among %s" % (db, sorted({r[1] for r in rows})[:20]))
         calib = max(copies, key=lambda r: r[3])
         for cn in counters:
             cv = [r[3] for r in rows if r[0] == calib[0] and r[2] == cn]
@@ -282,6 +284,33 @@ def summarize_counters(args):
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     print(path)
+
+
+def read_counter_rows(path):
+    """(dispatch id, kernel name, counter name, value, duration ns) of every
+    counter record of one rocprofv3 --pmc run, in dispatch order, from its
+    counter_collection.csv (-f csv) or its rocpd database (-f rocpd).  A
+    counter that the profiler reports per hardware instance is summed over
+    them."""
+    from collections import defaultdict
+    acc = defaultdict(float)
+    meta = {}
+    if path.endswith(".csv"):
+        import csv
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                did = int(r["Dispatch_Id"])
+                key = (did, r["Kernel_Name"], r["Counter_Name"])
+                acc[key] += float(r["Counter_Value"])
+                meta[key] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    else:
+        import sqlite3
+        con = sqlite3.connect(path)
+        for did, kn, cn, v, dur in con.execute("select dispatch_id, kernel_name, counter_name, value, duration "
+                                               "from counters_collection"):
+            acc[(did, kn, cn)] += v
+            meta[(did, kn, cn)] = dur
+    return sorted((k[0], k[1], k[2], v, meta[k]) for k, v in acc.items())
 
 
 def kernel_sources_digest():
@@ -324,9 +353,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl4x16")
     ap.add_argument("--D", type=int, default=0, help="override the bond dimension")
-    ap.add_argument("--apply-form", type=int, default=2, choices=(0, 1, 2),
+    ap.add_argument("--apply-form", type=int, default=2, choices=(0, 1, 2, 4),
                     help="site apply form: 0 the paper's contraction order, 1 the MPO folded into L, "
-                         "2 autotuned per site (default)")
+                         "2 autotuned per site (default), 4 the fused LW.A.R kernel everywhere")
     ap.add_argument("--sector-cap", type=int, default=64,
                     help="largest sector of a padded bond (0: no cap; the headline uses 64)")
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC),
@@ -413,7 +442,9 @@ def main():
         t_tune = time.perf_counter()
         forms = st.tune_apply(args.apply_form)   # the per-site apply form (autotuned by default)
         t_tune = time.perf_counter() - t_tune
-        info = st.info() + (dict(apply_form=args.apply_form, folded_sites=sum(forms), tune_s=t_tune),)
+        info = st.info() + (dict(apply_form=args.apply_form,
+                                 site_forms_0_1_2=[sum(f & 3 == i for f in forms) for i in (0, 1, 2)],
+                                 fused_bonds=sum(f >> 2 for f in forms), tune_s=t_tune),)
         T.tt_sweep_graphs(args.graphs)   # the first sweep of a step captures, later ones replay
         for i in range(warmup):
             st.sweep(c["dbeta"])
@@ -491,14 +522,14 @@ def main():
     # type it multiplies in (algorithmic flops, sum of 2mnk, over its event
     # time); the W stage against HBM (its algorithmic bytes); the QR against
     # the FP64 vector peak
-    singles = [k for k in prof if k.startswith("k_gemm_") or k in ("k_wgemm", "wstage", "qr")]
+    singles = [k for k in prof if k.startswith("k_gemm_") or k in ("k_wgemm", "k_fused", "wstage", "qr")]
     kind = max(singles, key=lambda k: prof[k]["ms"])
     pk = prof[kind]
     sec = pk["ms"] * 1e-3
-    is_mfma = (kind.startswith("k_gemm_") and kind != "k_gemm_reduce") or kind == "k_wgemm"
+    is_mfma = (kind.startswith("k_gemm_") and kind != "k_gemm_reduce") or kind in ("k_wgemm", "k_fused")
     if is_mfma:
-        # the wave GEMM multiplies in FP64 in every mode
-        pname = "fp64" if (args.precision == "fp64" or kind == "k_wgemm") else (
+        # the wave GEMM multiplies in FP64 in every mode; the fused apply runs in FP64 states only
+        pname = "fp64" if (args.precision == "fp64" or kind in ("k_wgemm", "k_fused")) else (
             "fp32" if args.precision == "fp32" else "bf16")
         roof = dict(bound="mfma", unit="TFLOP/s", peak=PEAK[pname], achieved=pk["flops"] / sec / 1e12)
     elif kind == "qr":
@@ -558,7 +589,8 @@ def main():
         chi = [(ns[i + 1] - ns[i - 1]) / (mus[i + 1] - mus[i - 1]) for i in range(1, len(mus) - 1)]
         mu_scan = dict(workload="Hubbard 6x12 cylinder, U=8, U(1)xU(1) D=%d, d_beta=%g, mu = %s"
                        % (D4, c4["dbeta"], ", ".join("%.4g" % m for m in mus)),
-                       instances=len(mus), folded_sites=sum(forms4),
+                       instances=len(mus), site_forms_0_1_2=[sum(f & 3 == i for f in forms4) for i in (0, 1, 2)],
+                       fused_bonds=sum(f >> 2 for f in forms4),
                        batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
                        single_instance_s_per_step=s_single, speedup_vs_one_at_a_time=s_single * len(mus) / s_batch,
                        tflops_alg=fl / args.steps / s_batch / 1e12,

@@ -185,19 +185,27 @@ int tdvp_sweep_batch(tt_state** states, int n, double dbeta, tt_sweep_stats* sta
  * tdvp_sweep2 repairs it.  Synchronises; stats may be NULL. */
 int tdvp_sweep2(tt_state* state, double dbeta, int D_max, double cutoff, tt_sweep_stats* stats);
 
-/* How each site applies H^(1) (SM Fig. optimalB(c)); the result is the same
- * up to rounding.  Form 0 is the contraction order of SM Fig. Lanczos: T1 =
- * L.A, the sparse MPO stage into T2, then .R.  Form 1 folds the MPO into the
- * left environment once per environment (LW^{b,so,si} = sum_a W[a,so,si,b]
- * L^a) and applies T2 = LW.A, then .R: no T1 and no per-apply MPO stage, but
- * grouped GEMMs one charge sector wide.  mode 0 or 1 sets that form at every
- * site; mode 2 times both forms of every site's apply on the device (the
- * fold's build spread over the 2K + 1 uses it serves per sweep) and keeps the
- * faster; mode 3 sets the forms from host_forms (N entries, each 0 or 1;
- * e.g. one instance's tuned choice for a whole batch).  The state starts in
- * form 0.  For modes 0-2, host_forms (may be NULL) receives the N chosen
- * forms.  States advance together in tdvp_sweep_batch only with equal forms.
- * Synchronises. */
+/* How each site applies H^(1) (SM Fig. optimalB(c)), and its left bond
+ * H^(0) (SM Fig. optimalB(d)); the result is the same up to rounding.  Site
+ * form 0 is the contraction order of SM Fig. Lanczos: T1 = L.A, the sparse MPO
+ * stage into T2, then .R.  Form 1 folds the MPO into the left environment
+ * once per environment (LW^{b,so,si} = sum_a W[a,so,si,b] L^a) and applies
+ * T2 = LW.A, then .R: no T1 and no per-apply MPO stage, but grouped GEMMs one
+ * charge sector wide.  Form 2 (FP64 states only) uses the same fold and runs
+ * LW.A.R as one kernel per apply: each output block sums (LW.A)_b R_b^T over
+ * the MPO index b with the T2 block held in registers, so neither T1 nor T2
+ * is written.  The bond apply is L.S into an intermediate then .R (bond form
+ * 0), or (bond form 1, FP64 states) the same kernel with one term L^a S per
+ * MPO index a.  host_forms[k] = f + 4 b holds site k's form f and its left
+ * bond's form b.  mode 0 or 1 sets site form 0 or 1 and bond form 0
+ * everywhere, mode 4 sets site form 2 and bond form 1 everywhere; mode 2
+ * times every form of every site's apply and of its bond apply on the device
+ * (the fold's build spread over the 2K + 1 uses it serves per sweep) and
+ * keeps the fastest; mode 3 sets the forms from host_forms (N entries; e.g.
+ * one instance's tuned choice for a whole batch).  The state starts in forms
+ * 0.  For modes 0-2 and 4, host_forms (may be NULL) receives the N chosen
+ * values.  States advance together in tdvp_sweep_batch only with equal forms.
+ * TT_EINVAL for the fused forms on a state that is not FP64.  Synchronises. */
 int tt_tune_apply(tt_state* state, int mode, int* host_forms);
 
 /* Bilayer observables of SM Sec. II.A at beta_phys = 2*beta: lnZ = 2 Lambda,
@@ -362,8 +370,8 @@ int tt_phase_timing(int on);
 /* Opt-in kernel timing: when on, every launch of the grouped GEMM, the MPO
  * (W) stage and the QR kernels is bracketed by HIP events on its stream, and
  * inside a grouped GEMM every kernel dispatch is timed on its own.
- * tt_profile_read synchronises those events and fills host_out68 with
- * {ms, flops, bytes, launches} for seventeen kinds accumulated since the
+ * tt_profile_read synchronises those events and fills host_out72 with
+ * {ms, flops, bytes, launches} for eighteen kinds accumulated since the
  * previous read, then resets:
  *   0-7   the grouped GEMM by contraction (all its dispatches together):
  *         L.A, .R, left environment, right environment (R.A), right
@@ -373,12 +381,14 @@ int tt_phase_timing(int on);
  *         32x32), one record per dispatch;
  *   15    the K-slice reduce kernel, one record per dispatch;
  *   16    the wave GEMM kernel (small and skinny problems), one record per
- *         dispatch.
+ *         dispatch;
+ *   17    the fused one-site apply (L with the MPO folded in, times the site
+ *         tensor, times R, in one kernel), one record per dispatch.
  * Flops and bytes are algorithmic (sum of 2mnk; every operand element read
  * once, every output written once); for the reduce, the partial tiles read
  * and the outputs written. */
 int tt_profile_enable(int on);
-int tt_profile_read(double* host_out68);
+int tt_profile_read(double* host_out72);
 
 /* Host-only: the sectors bond k would get for this model and options (same
  * calling convention as tt_state_bond_sectors).  No GPU needed. */

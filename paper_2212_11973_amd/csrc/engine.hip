@@ -126,6 +126,16 @@ void free_plan(GemmPlan& p) {
   p.d_probs = nullptr; p.d_tiles = nullptr; p.d_splits = nullptr; p.d_jobs = nullptr;
 }
 void free_plan(WPlan& p) { dfree(p.d_tasks); dfree(p.d_terms); p.d_tasks = nullptr; p.d_terms = nullptr; }
+void upload_plan(FzPlan& p, hipStream_t st) {
+  p.d_outs = upload(p.outs, st);
+  p.d_bs = upload(p.bs, st);
+  p.d_terms = upload(p.terms, st);
+  p.d_jobs = upload(p.jobs, st);
+}
+void free_plan(FzPlan& p) {
+  dfree(p.d_outs); dfree(p.d_bs); dfree(p.d_terms); dfree(p.d_jobs);
+  p.d_outs = nullptr; p.d_bs = nullptr; p.d_terms = nullptr; p.d_jobs = nullptr;
+}
 void free_plan(QRPlan& p) {
   dfree(p.d_tasks); dfree(p.d_chunks); dfree(p.d_stacks); dfree(p.d_wide);
   p.d_tasks = nullptr; p.d_chunks = nullptr; p.d_stacks = nullptr; p.d_wide = nullptr;
@@ -172,6 +182,7 @@ struct tt_state {
   double* LW = nullptr;                    // the MPO folded into the left environment of site lw_site
   int lw_site = -1;                        // -1: LW holds no current fold
   std::vector<char> fold;                  // per site: 1 = apply with the MPO folded into L, 0 = L.A, W, .R
+  std::vector<char> bfz;                   // per site: 1 = its left bond's H^(0) apply as one fused launch
   double *part = nullptr, *lz = nullptr;   // lz: alpha[K] beta[K] hn[K] coeff[K] scal[4] lambda errmax scratch[4]
   double** d_sites = nullptr;
   TraceEntry* d_trace = nullptr;
@@ -218,7 +229,7 @@ void free_scratch(tt_state& s) {
     free_plan(p.s1); free_plan(p.s3); free_plan(p.el); free_plan(p.r1); free_plan(p.r3);
     free_plan(p.absL); free_plan(p.absR); free_plan(p.b1); free_plan(p.b2);
     free_plan(p.w2); free_plan(p.wr); free_plan(p.qr); free_plan(p.lq);
-    free_plan(p.lw); free_plan(p.t2zero);
+    free_plan(p.lw); free_plan(p.t2zero); free_plan(p.fz); free_plan(p.fzb);
     for (auto& g : p.s1w) free_plan(g);
   };
   for (auto& p : s.plans) free_site(p);
@@ -407,6 +418,17 @@ void apply_heff1(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
   const int prec = b.lead().opts.precision;
   const long long* tabs = b.lead().tabs.dev;
   double f1 = 0.0;
+  if (b.lead().fold[k] == 2) {   // LW . x . R in one launch
+    TT_REQUIRE(!P.fz.outs.empty(), TT_EINVAL, "fused apply: the site has no fused plan");
+    build_lw(b, k);
+    launch_fused(P.fz, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.LW, x.p[i], s.Renv[k + 1], out.p[i]}}; }),
+                 b.n, ST());
+    add_flops(b, P.fz.flops, true);
+    const tt_state& L0 = b.lead();
+    const double bm = 8.0 * (L0.env[k].size + L0.env[k + 1].size + 2.0 * L0.site[k].size);
+    for (int i = 0; i < b.n; ++i) b.s[i]->bytes_min += bm;
+    return;
+  }
   if (b.lead().fold[k]) {
     build_lw(b, k);
     lw_times(b, k, x);
@@ -433,6 +455,15 @@ void apply_heff0(const Batch& b, int k, BPtr<double> x, BPtr<double> out) {
   SitePlan& P = b.lead().plans[k];
   const int prec = b.lead().opts.precision;
   const long long* tabs = b.lead().tabs.dev;
+  if (b.lead().bfz[k]) {   // sum_a (L^a S) (R^a)^T in one launch
+    TT_REQUIRE(!P.fzb.outs.empty(), TT_EINVAL, "fused bond apply: the bond has no fused plan");
+    launch_fused(P.fzb, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.Lenv[k], x.p[i], s.Renv[k], out.p[i]}}; }),
+                 b.n, ST());
+    add_flops(b, P.fzb.flops, true);
+    const double bm = 8.0 * (2.0 * b.lead().env[k].size + 2.0 * b.lead().bmat[k].size);
+    for (int i = 0; i < b.n; ++i) b.s[i]->bytes_min += bm;
+    return;
+  }
   launch_gemm(P.b1, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.Lenv[k], x.p[i], s.U, nullptr}}; }),
               b.n, prec, pws_of(b), ST());
   launch_gemm(P.b2, tabs, slots_of(b, [&](tt_state& s, int i) { return Slots{{s.U, s.Renv[k], out.p[i], nullptr}}; }),
@@ -769,6 +800,7 @@ void alloc_scratch(tt_state& s) {
     upload_plan(P.b1, T, st); upload_plan(P.b2, T, st);
     for (int j = 0; j < P.n_s1w; ++j) upload_plan(P.s1w[j], T, st);
     upload_plan(P.w2, st); upload_plan(P.lw, st); upload_plan(P.t2zero, st); upload_plan(P.wr, st);
+    upload_plan(P.fz, st); upload_plan(P.fzb, st);
     if (s.one_site_ok || qr_fits(P.qr)) upload_plan(P.qr, st);
     if (s.one_site_ok || qr_fits(P.lq)) upload_plan(P.lq, st);
     t1 = std::max(t1, P.t1_size); lw = std::max(lw, P.lw_size); t2 = std::max(t2, P.t2_size);
@@ -804,6 +836,7 @@ void alloc_scratch(tt_state& s) {
   buf(s.LW, cap_lw, lw);
   s.lw_site = -1;
   s.fold.assign(N, 0);
+  s.bfz.assign(N, 0);
   buf(s.T2, s.cap_T2, t2);
   buf(s.Y, s.cap_Y, y);
   buf(s.Z, s.cap_Z, z);
@@ -1069,6 +1102,67 @@ long long check_gemm(const GemmPlan& p, const std::vector<long long>& tabs, cons
   return bad;
 }
 
+// the fused apply's descriptors against LW (lw_size), the input and output
+// site vectors (in_size, out_size) and the R environment (r_size); the kernel
+// forms in-block offsets in 32 bits (below 2^29 elements) and clamps rows and
+// columns to each block, so these ranges bound every access
+long long check_fz(const FzPlan& p, long long lw_size, long long in_size, long long out_size, long long r_size,
+                   std::string& rep) {
+  long long bad = 0;
+  const long long lim = 1LL << 29;
+  auto fail = [&](const char* what, size_t i) {
+    ++bad;
+    if (rep.size() < 2000) rep += std::string("fz ") + what + " " + std::to_string(i) + "\n";
+  };
+  for (size_t i = 0; i < p.outs.size(); ++i) {
+    const FzOut& o = p.outs[i];
+    if (o.dp < 1 || o.dr < 1 || o.ldo < o.dr || o.ldr < 1) { fail("out shape", i); continue; }
+    const long long oh = (long long)(o.dp - 1) * o.ldo + o.dr - 1;
+    if (o.out < 0 || o.out + oh >= out_size || oh >= lim) fail("out range", i);
+    if (o.b0 < 0 || o.nb < 0 || o.nb > kFzMaxB || (long long)o.b0 + o.nb > (long long)p.bs.size()) {
+      fail("out b range", i);
+      continue;
+    }
+    for (int bi = 0; bi < o.nb; ++bi) {
+      const FzB& b = p.bs[o.b0 + bi];
+      const long long rh = (long long)(o.dr - 1) * o.ldr + b.rcol + b.dc - 1;
+      if (b.dc < 1 || b.rcol < 0 || o.rrow < 0 || o.rrow + rh >= r_size || rh >= lim) fail("R range", i);
+      if (b.nt < 1 || b.nt > kFzMaxB || b.t0 < 0 || (long long)b.t0 + b.nt > (long long)p.terms.size()) {
+        fail("b terms", i);
+        continue;
+      }
+      if (bi > 0 && b.t0 != p.bs[o.b0 + bi - 1].t0 + p.bs[o.b0 + bi - 1].nt) fail("b terms not consecutive", i);
+      for (int ti = 0; ti < b.nt; ++ti) {
+        const FzT& t = p.terms[b.t0 + ti];
+        if (t.dl < 1 || t.ldlw < t.dl || t.lda < b.dc) { fail("term shape", i); continue; }
+        const long long lh = (long long)(o.dp - 1) * t.ldlw + t.dl - 1;
+        const long long ah = (long long)(t.dl - 1) * t.lda + b.dc - 1;
+        if (t.lw < 0 || t.lw + lh >= lw_size || lh >= lim) fail("LW range", i);
+        if (t.a < 0 || t.a + ah >= in_size || ah >= lim) fail("input range", i);
+      }
+    }
+  }
+  if (p.jobs.size() % 4 != 0 || (long long)p.jobs.size() != 4LL * p.nblocks) fail("job count", 0);
+  for (size_t w = 0; w + 3 < p.jobs.size(); w += 4) {
+    const FzJob& j0 = p.jobs[w];
+    for (int q = 0; q < 4; ++q) {
+      const FzJob& j = p.jobs[w + q];
+      if (j.nparts != j0.nparts) fail("job parts", w);
+      if (j.o < 0) { if (j.nparts != 1) fail("empty split job", w); continue; }
+      if (j.o >= (int)p.outs.size()) { fail("job block", w); continue; }
+      const FzOut& o = p.outs[j.o];
+      if (j.row0 < 0 || j.row0 >= o.dp || j.row0 % 16 || j.col0 < 0 || j.col0 >= o.dr || j.col0 % kFzCols)
+        fail("job tile", w);
+      if (j.nparts == 4) {
+        if (j.part != q || j.o != j0.o || j.row0 != j0.row0 || j.col0 != j0.col0) fail("split job", w);
+      } else if (j.nparts != 1 || j.part != 0) {
+        fail("job part", w);
+      }
+    }
+  }
+  return bad;
+}
+
 long long check_w(const WPlan& p, long long in_size, long long out_size, const char* name, std::string& rep) {
   long long bad = 0;
   for (size_t i = 0; i < p.tasks.size(); ++i) {
@@ -1155,6 +1249,8 @@ long long check_sweep_plans(tt_state& s, std::string& rep) {
     for (int j = 0; j < P.n_s1w; ++j) bad += check_gemm(P.s1w[j], T, s1w, "s1w", rep);
     bad += check_w(P.lw, el, P.lw_size, "lw", rep);
     bad += check_w(P.t2zero, 0, t2, "t2zero", rep);
+    bad += check_fz(P.fz, lw, ns, ns, er, rep);
+    bad += check_fz(P.fzb, el, s.bmat[k].size, s.bmat[k].size, el, rep);
     bad += check_gemm(P.s3, T, s3, "s3", rep);
     bad += check_gemm(P.el, T, se, "el", rep);
     bad += check_gemm(P.r1, T, r1, "r1", rep);
@@ -1228,7 +1324,7 @@ void free_site_plan(SitePlan& p) {
   free_plan(p.s1); free_plan(p.s3); free_plan(p.el); free_plan(p.r1); free_plan(p.r3);
   free_plan(p.absL); free_plan(p.absR); free_plan(p.b1); free_plan(p.b2);
   free_plan(p.w2); free_plan(p.wr); free_plan(p.qr); free_plan(p.lq);
-  free_plan(p.lw); free_plan(p.t2zero);
+  free_plan(p.lw); free_plan(p.t2zero); free_plan(p.fz); free_plan(p.fzb);
   for (auto& g : p.s1w) free_plan(g);
 }
 
@@ -1471,6 +1567,7 @@ void install_sites(tt_state& s, int k) {
     *e = (double*)dalloc(8 * std::max(s.env[k + 1].size, 1LL));
   }
   s.fold[k] = s.fold[k + 1] = 0;
+  s.bfz[k] = s.bfz[k + 1] = 0;
   s.lw_site = -1;
 }
 
@@ -1481,6 +1578,7 @@ double tdvp2_once(tt_state& s, double dbeta, int Dmax, double cutoff) {
   const double tau = 0.5 * dbeta;
   double disc = 0.0;
   std::fill(s.fold.begin(), s.fold.end(), (char)0);
+  std::fill(s.bfz.begin(), s.bfz.end(), (char)0);
   s.lw_site = -1;
   for (int k = 0; k + 2 < N; ++k) {   // left to right
     {
@@ -1785,7 +1883,7 @@ bool same_plans(const tt_state& a, const tt_state& b) {
       return false;
     for (int j = 0; j < P.n_s1w; ++j)
       if (!same_gemm(P.s1w[j], Q.s1w[j])) return false;
-    if (!same_gemm(P.s1, Q.s1) || !same_w(P.w2, Q.w2) || a.fold[k] != b.fold[k]) return false;
+    if (!same_gemm(P.s1, Q.s1) || !same_w(P.w2, Q.w2) || a.fold[k] != b.fold[k] || a.bfz[k] != b.bfz[k]) return false;
   }
   return true;
 }
@@ -2236,25 +2334,37 @@ int tdvp_sweep2(tt_state* s, double dbeta, int D_max, double cutoff, tt_sweep_st
 int tt_tune_apply(tt_state* s, int mode, int* host_forms) {
   ABI_BEGIN
   TT_REQUIRE(s, TT_EINVAL, "null state");
-  TT_REQUIRE(mode >= 0 && mode <= 3, TT_EINVAL, "tt_tune_apply: mode must be 0, 1, 2 or 3");
+  TT_REQUIRE(mode >= 0 && mode <= 4, TT_EINVAL, "tt_tune_apply: mode must be 0, 1, 2, 3 or 4");
   const int N = s->N;
-  if (mode < 2) {
-    s->fold.assign(N, (char)mode);
+  const bool fz_ok = s->opts.precision == TT_FP64;   // the fused kernel multiplies and stores in FP64
+  TT_REQUIRE(mode != 4 || fz_ok, TT_EINVAL, "tt_tune_apply: the fused applies need an FP64 state");
+  if (mode < 2 || mode == 4) {
+    s->fold.assign(N, (char)(mode == 4 ? 2 : mode));
+    s->bfz.assign(N, (char)(mode == 4 ? 1 : 0));
+    s->lw_site = -1;
   } else if (mode == 3) {
     TT_REQUIRE(host_forms, TT_EINVAL, "tt_tune_apply: mode 3 needs the forms");
-    for (int k = 0; k < N; ++k)
-      TT_REQUIRE(host_forms[k] == 0 || host_forms[k] == 1, TT_EINVAL, "tt_tune_apply: forms must be 0 or 1");
-    for (int k = 0; k < N; ++k) s->fold[k] = (char)host_forms[k];
+    for (int k = 0; k < N; ++k) {
+      const int f = host_forms[k] & 3, bf = host_forms[k] >> 2;
+      TT_REQUIRE(host_forms[k] >= 0 && f <= 2 && bf <= 1 && (fz_ok || (f < 2 && bf == 0)), TT_EINVAL,
+                 "tt_tune_apply: forms must be f + 4 b with f in 0..2 and b in 0..1 (f = 2, b = 1: FP64 states)");
+    }
+    for (int k = 0; k < N; ++k) {
+      s->fold[k] = (char)(host_forms[k] & 3);
+      s->bfz[k] = (char)(host_forms[k] >> 2);
+    }
     s->lw_site = -1;
   } else {
-    // time both forms of each site's apply on the device (the site tensor as
+    // time every form of each site's apply on the device (the site tensor as
     // input, the scratch vector as output; the state is not changed); the
-    // fold's one-off build is spread over the 2K + 1 uses it has per sweep
+    // fold's one-off build (forms 1 and 2) is spread over the 2K + 1 uses it
+    // has per sweep.  Then both forms of the left bond's H^(0) apply (the
+    // bond scratch matrix as input).
     const int reps = 3;
     const Batch b = batch_of(*s);
-    hipEvent_t ev[5];
+    hipEvent_t ev[11];
     for (auto& e : ev) HIPX(hipEventCreate(&e));
-    struct Ev { hipEvent_t* e; ~Ev() { for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]); } } guard{ev};
+    struct Ev { hipEvent_t* e; ~Ev() { for (int i = 0; i < 11; ++i) (void)hipEventDestroy(e[i]); } } guard{ev};
     const double uses = 2.0 * s->opts.krylov_dim + 1.0;
     const double f0 = s->flops, fh0 = s->flops_heff, bm0 = s->bytes_min;
     const int na0 = s->n_applies;
@@ -2273,12 +2383,37 @@ int tt_tune_apply(tt_state* s, int mode, int* host_forms) {
       HIPX(hipEventRecord(ev[3], ST()));
       for (int r = 0; r < reps; ++r) apply_heff1(b, k, x, y);
       HIPX(hipEventRecord(ev[4], ST()));
-      HIPX(hipEventSynchronize(ev[4]));
-      float t3 = 0.f, tb = 0.f, tf = 0.f;
-      HIPX(hipEventElapsedTime(&t3, ev[0], ev[1]));
+      BPtr<double> sx = one(s->Sbuf);
+      if (fz_ok) {
+        s->fold[k] = 2;
+        apply_heff1(b, k, x, y);   // warm
+        HIPX(hipEventRecord(ev[5], ST()));
+        for (int r = 0; r < reps; ++r) apply_heff1(b, k, x, y);
+        HIPX(hipEventRecord(ev[6], ST()));
+        s->bfz[k] = 0;
+        apply_heff0(b, k, sx, y);   // warm
+        HIPX(hipEventRecord(ev[7], ST()));
+        for (int r = 0; r < reps; ++r) apply_heff0(b, k, sx, y);
+        HIPX(hipEventRecord(ev[8], ST()));
+        s->bfz[k] = 1;
+        apply_heff0(b, k, sx, y);   // warm
+        HIPX(hipEventRecord(ev[9], ST()));
+        for (int r = 0; r < reps; ++r) apply_heff0(b, k, sx, y);
+      }
+      HIPX(hipEventRecord(ev[10], ST()));
+      HIPX(hipEventSynchronize(ev[10]));
+      float t0 = 0.f, tb = 0.f, t1 = 0.f, t2 = 0.f, tg = 0.f, tz = 0.f;
+      HIPX(hipEventElapsedTime(&t0, ev[0], ev[1]));
       HIPX(hipEventElapsedTime(&tb, ev[1], ev[2]));
-      HIPX(hipEventElapsedTime(&tf, ev[3], ev[4]));
-      s->fold[k] = (tf / reps + tb / uses < t3 / reps) ? 1 : 0;
+      HIPX(hipEventElapsedTime(&t1, ev[3], ev[4]));
+      if (fz_ok) {
+        HIPX(hipEventElapsedTime(&t2, ev[5], ev[6]));
+        HIPX(hipEventElapsedTime(&tg, ev[7], ev[8]));
+        HIPX(hipEventElapsedTime(&tz, ev[9], ev[10]));
+      }
+      const double c0 = t0 / reps, c1 = t1 / reps + tb / uses, c2 = fz_ok ? t2 / reps + tb / uses : 1e30;
+      s->fold[k] = (c2 <= c1 && c2 <= c0) ? 2 : (c1 < c0 ? 1 : 0);
+      s->bfz[k] = (fz_ok && tz < tg) ? 1 : 0;
     }
     s->lw_site = -1;
     s->flops = f0; s->flops_heff = fh0; s->bytes_min = bm0; s->n_applies = na0;
@@ -2288,7 +2423,7 @@ int tt_tune_apply(tt_state* s, int mode, int* host_forms) {
     s->sg.exec = nullptr;
   }
   if (host_forms && mode != 3)
-    for (int k = 0; k < N; ++k) host_forms[k] = s->fold[k];
+    for (int k = 0; k < N; ++k) host_forms[k] = s->fold[k] + 4 * s->bfz[k];
   ABI_END
 }
 
@@ -2747,14 +2882,14 @@ int tt_profile_enable(int on) {
   ABI_END
 }
 
-int tt_profile_read(double* host_out68) {
+int tt_profile_read(double* host_out72) {
   ABI_BEGIN
-  static_assert(PROF_KINDS == 17, "tt_profile_read fills 17 kinds");
-  TT_REQUIRE(host_out68, TT_EINVAL, "null argument");
+  static_assert(PROF_KINDS == 18, "tt_profile_read fills 18 kinds");
+  TT_REQUIRE(host_out72, TT_EINVAL, "null argument");
   double out[PROF_KINDS][4];
   prof_read(out);
   for (int k = 0; k < PROF_KINDS; ++k)
-    for (int j = 0; j < 4; ++j) host_out68[k * 4 + j] = out[k][j];
+    for (int j = 0; j < 4; ++j) host_out72[k * 4 + j] = out[k][j];
   ABI_END
 }
 

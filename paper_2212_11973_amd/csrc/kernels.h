@@ -14,11 +14,12 @@ constexpr int kMaxKrylov = 32;
 // Optional timing of the grouped kernels: HIP events on the launch stream.
 // kinds 0..TAG_COUNT-1 are the grouped GEMM contractions by tag, then the W
 // stage and the QR, then the individual GEMM kernels (one kind per tile shape,
-// then the K-slice reduce, then the wave GEMM), each timed per dispatch.
+// then the K-slice reduce, then the wave GEMM), each timed per dispatch, and
+// the fused apply (one dispatch per apply).
 enum ProfKind {
   PROF_WSTAGE = TAG_COUNT, PROF_QR = TAG_COUNT + 1, PROF_GEMM_CFG0 = TAG_COUNT + 2,
   PROF_GEMM_REDUCE = PROF_GEMM_CFG0 + kGemmCfgs, PROF_GEMM_WAVE = PROF_GEMM_REDUCE + 1,
-  PROF_KINDS = PROF_GEMM_WAVE + 1
+  PROF_FUSED = PROF_GEMM_WAVE + 1, PROF_KINDS = PROF_FUSED + 1
 };
 // kernels enqueued by the library since it was loaded (every launch wrapper counts)
 long long launch_count();
@@ -68,6 +69,9 @@ void launch_gemm_planes(const GemmPlan& p, const long long* d_tabs, const Slots&
                         hipStream_t st);
 // the BF16 parts of n doubles into planes pstride elements apart
 void launch_split(const double* x, long long n, void* out, long long pstride, int precision, hipStream_t st);
+// the fused one-site apply LW . x . R of every state of the batch (slots:
+// 0 = LW, 1 = input site vector, 2 = R env, 3 = output site vector)
+void launch_fused(const FzPlan& p, const BSlots& s, int nb, hipStream_t st);
 // terms: each state's copy of the plan's terms (the weights may differ)
 void launch_wstage(const WPlan& p, BPtr<const WTerm> terms, BPtr<const double> in, BPtr<double> out, int nb,
                    hipStream_t st);

@@ -783,6 +783,212 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   }
 }
 
+// ------------------------------------------------------------------ fused apply
+// One wave's 16 x (16 FN) tile of a fused-apply output block (FzOut).  For
+// each of its b blocks and each 16-wide chunk of that block's y range, the
+// chunk of T2^T (rows y, columns x') is summed over the terms t as
+// x_t^T LW_t^T with the f64 MFMA 16x16x4, then out += T2 R^T takes that chunk
+// as its A operand.  Lane (r, g) = (lane % 16, lane / 16) ends the first
+// product holding T2[x' = row0 + r][y = y0 + g + 4 v] in register v, which is
+// exactly its A operand of the second product's step v (k = y = y0 + 4 v + g):
+// the two products chain in registers.  In the first product lane (r, g)
+// supplies the input row y = y0 + r and the LW row x' = row0 + r; a full
+// 16-deep chunk of x takes k = 16 c + 4 g + s on step s (one 32-byte run of
+// an LW row per lane), the partial last chunk k = 16 c + 4 s + g with LW
+// zeroed past dl.  Rows x', y and columns y' past the ends are clamped to the
+// last valid index (an element of the same block), so every load is
+// unconditional and in bounds; the clamped products reach only outputs that
+// are never stored, or meet the R value zeroed past dc.
+// The descriptors of the b blocks sit one per lane (lane i: block b0 + i)
+// and those of a window of 64 consecutive terms likewise; the loop reads them
+// with readlane (no memory access), so the only memory round trips of a b
+// block are its operand loads, and the R values of a chunk are loaded before
+// the product they enter.
+__device__ __forceinline__ long long rl64(int lo, int hi, int i) {
+  return (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readlane(hi, i) << 32) |
+                     (unsigned long long)(unsigned)__builtin_amdgcn_readlane(lo, i));
+}
+
+template <int FN>
+__device__ __forceinline__ void fz_tile(const FzOut& O, const FzJob& J, const FzB* __restrict__ bs,
+                                        const FzT* __restrict__ ts, const Slots& slots, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const double* __restrict__ LW = slots.p[0];
+  const double* __restrict__ X = slots.p[1];
+  const double* __restrict__ R = slots.p[2] + O.rrow;
+  const unsigned xr = (unsigned)min(J.row0 + r16, O.dp - 1);
+  unsigned rr[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) rr[j] = (unsigned)min(J.col0 + 16 * j + r16, O.dr - 1) * (unsigned)O.ldr;
+  double4_t acc[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) acc[j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  // b block descriptors, lane i: block b0 + i (nb <= 64, checked by the planner)
+  int b_rlo = 0, b_rhi = 0, b_dc = 1, b_t0 = 0, b_nt = 0;
+  if (lane < O.nb) {
+    const FzB B = bs[O.b0 + lane];
+    b_rlo = (int)(unsigned)(B.rcol & 0xffffffffLL);
+    b_rhi = (int)(B.rcol >> 32);
+    b_dc = B.dc;
+    b_t0 = B.t0;
+    b_nt = B.nt;
+  }
+  const int t_end = O.nb > 0 ? __builtin_amdgcn_readlane(b_t0, O.nb - 1) + __builtin_amdgcn_readlane(b_nt, O.nb - 1) : 0;
+  // a window of term descriptors, lane i: term tw + i
+  int tw = -(1 << 30);
+  int t_llo = 0, t_lhi = 0, t_alo = 0, t_ahi = 0, t_ldlw = 1, t_lda = 1, t_dl = 1;
+  for (int bi = J.part; bi < O.nb; bi += J.nparts) {
+    const long long rcol = rl64(b_rlo, b_rhi, bi);
+    const int dc = __builtin_amdgcn_readlane(b_dc, bi);
+    const int t0 = __builtin_amdgcn_readlane(b_t0, bi), nt = __builtin_amdgcn_readlane(b_nt, bi);
+    if (t0 < tw || t0 + nt > tw + 64) {   // uniform: move the window to start at this block's terms
+      tw = t0;
+      if (tw + lane < t_end) {
+        const FzT T = ts[tw + lane];
+        t_llo = (int)(unsigned)(T.lw & 0xffffffffLL);
+        t_lhi = (int)(T.lw >> 32);
+        t_alo = (int)(unsigned)(T.a & 0xffffffffLL);
+        t_ahi = (int)(T.a >> 32);
+        t_ldlw = T.ldlw;
+        t_lda = T.lda;
+        t_dl = T.dl;
+      }
+    }
+    const double* __restrict__ Rb = R + rcol;
+    for (int y0 = 0; y0 < dc; y0 += 16) {
+      // R values of this chunk: step s of the product with R takes y = y0 + 4 s + g
+      // (loaded ahead of the first product for up to two column tiles)
+      constexpr int FP = FN <= 2 ? FN : 1;
+      const int ns = min(4, (dc - y0 + 3) >> 2);
+      auto rval = [&](int j, int s) {
+        const int y = y0 + 4 * s + g;
+        const bool ok = y < dc;
+        double v = ld32(Rb, rr[j] + (unsigned)(ok ? y : dc - 1));
+        asm volatile("" : "+v"(v));   // keeps the load unconditional
+        return ok ? v : 0.0;
+      };
+      double rv[FP][4];
+      if constexpr (FN <= 2) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (s < ns) rv[j][s] = rval(j, s);
+      }
+      const unsigned yl = (unsigned)min(y0 + r16, dc - 1);
+      double4_t t2 = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int ti = 0; ti < nt; ++ti) {
+        const int li = t0 - tw + ti;
+        const long long tlw = rl64(t_llo, t_lhi, li), ta = rl64(t_alo, t_ahi, li);
+        const int ldlw = __builtin_amdgcn_readlane(t_ldlw, li), lda = __builtin_amdgcn_readlane(t_lda, li);
+        const int dl = __builtin_amdgcn_readlane(t_dl, li);
+        const double* __restrict__ Lr = LW + tlw + xr * (unsigned)ldlw;
+        const double* __restrict__ Xa = X + ta + yl;
+        const int nfull = dl >> 4;
+#pragma unroll 2
+        for (int c = 0; c < nfull; ++c) {
+          const unsigned k0 = 16u * c + 4u * g;
+          double lv[4], av[4];
+          ld32x2(Lr, k0, lv[0], lv[1]);
+          ld32x2(Lr, k0 + 2u, lv[2], lv[3]);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) av[s] = ld32(Xa, (k0 + s) * (unsigned)lda);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], lv[s], t2, 0, 0, 0);
+        }
+        if (16 * nfull < dl) {
+          const int c = nfull;
+          const int nk = (dl - 16 * c + 3) >> 2;   // steps holding a valid k (wave-uniform)
+          double lv[4], av[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            if (s < nk) {
+              const int k = 16 * c + 4 * s + g;
+              const bool ok = k < dl;
+              const unsigned kc = (unsigned)(ok ? k : dl - 1);
+              double v = ld32(Lr, kc);
+              asm volatile("" : "+v"(v));
+              lv[s] = ok ? v : 0.0;
+              av[s] = ld32(Xa, kc * (unsigned)lda);
+            }
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (s < nk) t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], lv[s], t2, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s < ns)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            double r;
+            if constexpr (FN <= 2) r = rv[j][s];
+            else r = rval(j, s);
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(t2[s], r, acc[j], 0, 0, 0);
+          }
+    }
+  }
+  if (J.nparts > 1) {   // uniform over the workgroup: its four jobs are the parts of one tile
+    if (wave > 0) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave - 1) * 1024 + (j * 4 + v) * 64 + lane] = acc[j][v];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = (j * 4 + v) * 64 + lane;
+        acc[j][v] = ((acc[j][v] + red[e]) + red[1024 + e]) + red[2048 + e];
+      }
+  }
+  double* __restrict__ out = slots.p[3] + O.out;
+  const int ncol = min(O.dr, J.col0 + kFzCols);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = J.row0 + g + 4 * v;
+    if (m >= O.dp) continue;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = J.col0 + 16 * j + r16;
+      if (n < ncol) out[(long long)m * O.ldo + n] = acc[j][v];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_apply(const FzOut* __restrict__ outs, const FzB* __restrict__ bs,
+                                                     const FzT* __restrict__ ts, const FzJob* __restrict__ jobs,
+                                                     int nblocks, BSlots bsl) {
+  __shared__ double red[3 * 1024];
+  const Slots& slots = bsl.s[blockIdx.y];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  const int jidx = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+  const FzJob J = jobs[jidx];
+  if (J.o < 0) return;   // an unused slot: only in workgroups of unsplit jobs, which never synchronise
+  const FzOut O = outs[J.o];
+  switch ((min(O.dr - J.col0, kFzCols) + 15) >> 4) {
+    case 1: fz_tile<1>(O, J, bs, ts, slots, red); break;
+    case 2: fz_tile<2>(O, J, bs, ts, slots, red); break;
+    case 3: fz_tile<3>(O, J, bs, ts, slots, red); break;
+    default: fz_tile<4>(O, J, bs, ts, slots, red); break;
+  }
+}
+
+void launch_fused(const FzPlan& p, const BSlots& s, int nb, hipStream_t st) {
+  if (p.nblocks == 0) return;
+  TT_REQUIRE(nb >= 1 && nb <= kMaxBatch, TT_EINVAL, "batch size out of range");
+  prof_begin(st);
+  hipLaunchKernelGGL(k_fused_apply, dim3(p.nblocks, nb), dim3(256), 0, st, p.d_outs, p.d_bs, p.d_terms, p.d_jobs,
+                     p.nblocks, s);
+  HIP_CHECK_LAUNCH();
+  prof_end(st, PROF_FUSED, nb * p.flops, nb * p.bytes);
+}
+
 // tile shapes: 0 64x64, 1 128x32, 2 256x16, 3 32x128, 4 32x32 (split K over the
 // waves; with BF16 the four waves take one 16x16 block each instead)
 template <int CFG, int PREC> struct CfgT;

@@ -248,6 +248,53 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
   p.ntiles = (int)p.tiles.size();
 }
 
+// MFMA instructions of one fused-apply job (16 rows, up to kFzCols columns)
+// over all b blocks of output block o: per b and 16-wide y chunk, the
+// 4-deep steps of every term, then the steps of the product with R
+static double fz_steps(const FzPlan& F, const FzOut& o) {
+  const int fn = (std::min(o.dr, kFzCols) + 15) / 16;
+  double steps = 0.0;
+  for (int bi = 0; bi < o.nb; ++bi) {
+    const FzB& b = F.bs[o.b0 + bi];
+    double k1 = 0.0;
+    for (int t = b.t0; t < b.t0 + b.nt; ++t) k1 += (F.terms[t].dl + 3) / 4;
+    steps += ((b.dc + 15) / 16) * k1 + (double)fn * ((b.dc + 3) / 4);
+  }
+  return steps;
+}
+
+// the jobs of a fused-apply plan: every (block, 16-row tile, kFzCols-column
+// tile); a tile with enough work for every wave to take several b blocks
+// becomes four K parts in one workgroup.  The heaviest first; split jobs stay
+// in groups of four.
+static void plan_fz_jobs(FzPlan& F) {
+  struct JobW { FzJob j; double steps; };
+  std::vector<JobW> split, single;
+  for (int oi = 0; oi < (int)F.outs.size(); ++oi) {
+    const FzOut& o = F.outs[oi];
+    const double steps = fz_steps(F, o);
+    const bool sp4 = o.nb >= 8 && steps >= 256.0;
+    for (int r0 = 0; r0 < o.dp; r0 += 16)
+      for (int c0 = 0; c0 < o.dr; c0 += kFzCols) {
+        if (sp4) {
+          for (int q = 0; q < 4; ++q) split.push_back({{oi, r0, c0, q, 4, 0}, steps});
+        } else {
+          single.push_back({{oi, r0, c0, 0, 1, 0}, steps});
+        }
+      }
+  }
+  std::stable_sort(single.begin(), single.end(), [](const JobW& a, const JobW& b) { return a.steps > b.steps; });
+  std::vector<int> order(split.size() / 4);
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return split[4 * a].steps > split[4 * b].steps; });
+  F.jobs.clear();
+  for (int g : order)
+    for (int q = 0; q < 4; ++q) F.jobs.push_back(split[4 * g + q].j);
+  for (auto& j : single) F.jobs.push_back(j.j);
+  while (F.jobs.size() % 4) F.jobs.push_back({-1, 0, 0, 0, 1, 0});
+  F.nblocks = (int)(F.jobs.size() / 4);
+}
+
 // LW^{b,so,si}[x', x] = sum_a W[a,so,si,b] L^a[x', x] per bra sector p, and
 // T2^{b,(so,sp)} = sum_si LW^{b,so,si} A^{(si,sp)} written into stage 3's T2
 // layout (rows (p, g', x', s') of the right sector r' = p + Delta(so, sp),
@@ -373,6 +420,67 @@ static void build_lw_plans(SitePlan& P, const SiteLayout& S, const Bond& bl, con
     P.n_s1w = std::max(P.n_s1w, pass + 1);
   }
   for (int j = 0; j < SitePlan::kMaxLwPasses; ++j) P.s1w[j].tag = TAG_LA;
+
+  // the fused apply: one output block per (p, so, sp) that has a right sector;
+  // per block the b of R's row block with at least one term, per b the terms
+  // (b, so, si) of LW with the input block (l, 4 si + sp) in the same order as
+  // the passes above.  A block with no b is written as zeros.
+  {
+    FzPlan& F = P.fz;
+    F = FzPlan();
+    for (int p = 0; p < S.nl; ++p)
+      for (int so = 0; so < 4; ++so)
+        for (int sp = 0; sp < 4; ++sp) {
+          const int s_out = 4 * so + sp, g_out = G.group_of[s_out];
+          const int rq = S.rsec[p][g_out];
+          if (rq < 0) continue;
+          FzOut o;
+          o.dr = br.secs[rq].dim;
+          o.out = S.base[p] + S.colb[p][g_out] + (long long)G.pos_of[s_out] * o.dr;
+          o.ldo = S.C[p];
+          o.dp = S.dl[p];
+          o.rrow = ER.base[rq];
+          o.ldr = ER.K[rq];
+          o.b0 = (int)F.bs.size();
+          o.nb = 0;
+          for (int b = 0; b < DHr; ++b) {
+            const int c = ER.csec[rq][b];
+            if (c < 0) continue;
+            FzB fb;
+            fb.rcol = ER.colb[rq][b];
+            fb.dc = br.secs[c].dim;
+            fb.t0 = (int)F.terms.size();
+            fb.nt = 0;
+            fb.pad = 0;
+            for (const Grp& gr : grp[p]) {
+              if (gr.b != b || gr.so != so) continue;
+              const int s_in = 4 * gr.si + sp, g_in = G.group_of[s_in];
+              if (S.rsec[gr.l][g_in] < 0) continue;
+              TT_REQUIRE(S.rsec[gr.l][g_in] == c, TT_EINVAL, "plan: inconsistent charges (fused apply)");
+              FzT t;
+              t.lw = lwbase[p] + gr.col;
+              t.ldlw = (int)lwK[p];
+              t.a = S.base[gr.l] + S.colb[gr.l][g_in] + (long long)G.pos_of[s_in] * fb.dc;
+              t.lda = S.C[gr.l];
+              t.dl = S.dl[gr.l];
+              t.pad = 0;
+              F.terms.push_back(t);
+              ++fb.nt;
+              F.flops += 2.0 * o.dp * (double)fb.dc * t.dl;
+              F.bytes += 8.0 * ((double)o.dp * t.dl + (double)t.dl * fb.dc);
+            }
+            if (fb.nt == 0) continue;
+            F.flops += 2.0 * o.dp * (double)fb.dc * o.dr;
+            F.bytes += 8.0 * (double)o.dr * fb.dc;
+            F.bs.push_back(fb);
+            ++o.nb;
+          }
+          F.bytes += 8.0 * (double)o.dp * o.dr;
+          F.outs.push_back(o);
+        }
+    plan_fz_jobs(F);
+  }
+
   // T2 blocks that no term reaches are cleared (a task with no terms writes zeros)
   for (int rq = 0; rq < (int)br.secs.size(); ++rq)
     for (int p = 0; p < S.nl; ++p)
@@ -698,6 +806,35 @@ SitePlan build_site_plan(int k, const Bond& bl, const Bond& br, const Groups& G,
       g.offC = bm.off[p]; g.scm = EL.dp[p];
       add_prob(P.b2, g);
     }
+    // the same apply as one fused launch: out_p = sum_a (L^a_p S_q) (R^a_p)^T
+    // with q = p - qH(a), one b block per a with the single term L^a_p . S_q
+    // (slots: 0 = L env, 1 = S, 2 = R env, 3 = output S)
+    FzPlan& F = P.fzb;
+    F = FzPlan();
+    for (int p = 0; p < EL.np; ++p) {
+      FzOut o;
+      o.out = bm.off[p]; o.ldo = EL.dp[p]; o.dp = o.dr = EL.dp[p];
+      o.rrow = EL.base[p]; o.ldr = EL.K[p];
+      o.b0 = (int)F.bs.size(); o.nb = 0;
+      for (int a = 0; a < DHl; ++a) {
+        const int q = EL.csec[p][a];
+        if (q < 0) continue;
+        const int dq = bl.secs[q].dim;
+        FzB fb;
+        fb.rcol = EL.colb[p][a]; fb.dc = dq; fb.t0 = (int)F.terms.size(); fb.nt = 1; fb.pad = 0;
+        FzT t;
+        t.lw = EL.base[p] + EL.colb[p][a]; t.ldlw = EL.K[p];
+        t.a = bm.off[q]; t.lda = dq; t.dl = dq; t.pad = 0;
+        F.terms.push_back(t);
+        F.bs.push_back(fb);
+        ++o.nb;
+        F.flops += 2.0 * o.dp * (double)dq * dq + 2.0 * o.dp * (double)dq * o.dr;
+        F.bytes += 8.0 * ((double)o.dp * dq + (double)dq * dq + (double)o.dr * dq);
+      }
+      F.bytes += 8.0 * (double)o.dp * o.dr;
+      F.outs.push_back(o);
+    }
+    plan_fz_jobs(F);
   }
   finish_wplan(P.w2);
   finish_wplan(P.wr);

@@ -96,6 +96,40 @@ constexpr int kQrStackRows = 256;   // 16 rows per lane, as the chunks (larger s
 struct QRChunk { int task, row0, rows, chunk, nchunks, pad; long long qw, rw; };
 struct QRStack { int task, nchunks; long long rw; };
 
+// Fused one-site apply with the MPO folded into L (SM Fig. Lanczos; W summed
+// into L once per environment).  Output block o = (p, so, sp) of H^(1) x has
+// the rows x' of bra sector p and the columns y' of the right sector r' it
+// reaches:
+//   out[x', y'] = sum_b sum_{y in c(b)} T2_b[x', y] R_r'[y', (b, y)],
+//   T2_b[x', y] = sum_t sum_{x < dl_t} LW_t[x', x] x_t[x, y],
+// with T2 formed in registers 16 x 16 at a time, so neither the L.A
+// intermediate nor T2 goes to memory.  Element offsets: out at
+// out + x' ldo + y' (the output site vector), R at rrow + y' ldr + rcol + y,
+// LW at lw + x' ldlw + x, the input site vector at a + x lda + y.
+struct FzOut { long long out, rrow; int ldo, ldr, dp, dr, b0, nb; };
+struct FzB { long long rcol; int dc, t0, nt, pad; };
+struct FzT { long long lw, a; int ldlw, lda, dl, pad; };
+// One wave's share: rows row0 .. row0 + 15 and columns col0 .. col0 + 63 of
+// block o, over the b blocks part, part + nparts, ...; with nparts = 4 the
+// four waves of a workgroup hold the four parts and add them in part order.
+// Split jobs come first, whole workgroups each; unused slots have o = -1.
+struct FzJob { int o, row0, col0, part, nparts, pad; };
+constexpr int kFzCols = 64;   // output columns per job
+constexpr int kFzMaxB = 64;   // b blocks per output block and terms per b block (one per lane)
+struct FzPlan {
+  std::vector<FzOut> outs;
+  std::vector<FzB> bs;
+  std::vector<FzT> terms;
+  std::vector<FzJob> jobs;
+  FzOut* d_outs = nullptr;
+  FzB* d_bs = nullptr;
+  FzT* d_terms = nullptr;
+  FzJob* d_jobs = nullptr;
+  int nblocks = 0;          // workgroups (four jobs each)
+  double flops = 0;         // algorithmic: 2 dp dc dl per term and 2 dp dc dr per b block
+  double bytes = 0;         // minimum: LW rows, input, R rows read once, output written once
+};
+
 // A plan: descriptors uploaded once, launched many times with varying slots.
 // profiler tags of the grouped GEMMs (which contraction a launch belongs to)
 enum GemmTag { TAG_LA = 0, TAG_R = 1, TAG_ENVL = 2, TAG_ENVR1 = 3, TAG_ENVR3 = 4, TAG_BOND = 5, TAG_ABSORB = 6,
@@ -199,8 +233,10 @@ struct SitePlan {
   QRPlan qr, lq;
   // absorb from the left (S_k . A, S on the left bond) and from the right (A . S_{k+1})
   GemmPlan absL, absR;
-  // bond effective Hamiltonian on the left bond k (H^(0) with L_k, R_k)
+  // bond effective Hamiltonian on the left bond k (H^(0) with L_k, R_k); fzb:
+  // the same as one fused launch (slots: 0 = L env, 1 = S, 2 = R env, 3 = output)
   GemmPlan b1, b2;
+  FzPlan fzb;
   long long u_size = 0;
   // transfer-matrix trace: per left sector l with a (0,0) group, (row block, col base, d)
   std::vector<std::array<long long, 4>> tr;
@@ -215,6 +251,9 @@ struct SitePlan {
   GemmPlan s1w[kMaxLwPasses];
   int n_s1w = 0;
   long long lw_size = 0;
+  // the whole apply LW . x . R in one launch (slots: 0 = LW, 1 = input site
+  // vector, 2 = R env, 3 = output site vector)
+  FzPlan fz;
 };
 
 // slot conventions (kernel argument order)

@@ -208,8 +208,11 @@ def tt_sweep_graphs(on):
 
 
 def tt_tune_apply(state, mode, forms=None):
-    """Apply form per site (0: L.A, W, .R; 1: MPO folded into L; 2: time both
-    and keep the faster; 3: the given list of forms); returns the forms."""
+    """Apply forms per site, f + 4 b: f the site apply (0: L.A, W, .R; 1: MPO
+    folded into L; 2: the fused LW.A.R kernel, FP64 states), b the left bond's
+    apply (0: L.S then .R; 1: fused, FP64 states).  mode 0 / 1: f = 0 / 1 and
+    b = 0 everywhere; 2: time every form and keep the fastest; 3: the given
+    list; 4: f = 2, b = 1 everywhere.  Returns the forms."""
     n, _ = tt_state_info(state)
     arr = (C.c_int * n)(*(forms or []))
     _check(lib().tt_tune_apply(state, int(mode), arr))
@@ -346,13 +349,13 @@ def tt_profile_enable(on):
 PROFILE_KINDS = ("gemm_LA", "gemm_R", "gemm_envL", "gemm_envR1", "gemm_envR3", "gemm_bond", "gemm_absorb",
                  "gemm_Wdense", "wstage", "qr",
                  "k_gemm_64x64", "k_gemm_128x32", "k_gemm_256x16", "k_gemm_32x128", "k_gemm_32x32",
-                 "k_gemm_reduce", "k_wgemm")
+                 "k_gemm_reduce", "k_wgemm", "k_fused")
 
 
 def tt_profile_read():
     """{kind: dict(ms, flops, bytes, launches)} since the last read; 'gemm' sums the
     grouped-GEMM kinds (gemm_*), the k_gemm_* kinds time single kernel dispatches."""
-    buf = (C.c_double * 68)()
+    buf = (C.c_double * 72)()
     _check(lib().tt_profile_read(buf))
     out = {}
     for i, k in enumerate(PROFILE_KINDS):
