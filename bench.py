@@ -358,6 +358,8 @@ def main():
                          "2 autotuned per site (default), 4 the fused LW.A.R kernel everywhere")
     ap.add_argument("--sector-cap", type=int, default=64,
                     help="largest sector of a padded bond (0: no cap; the headline uses 64)")
+    ap.add_argument("--uncapped-steps", type=int, default=1,
+                    help="also time this many sweeps with no sector cap (0: skip)")
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC),
                     help="precision of the timed sweep that gives 'value'")
     ap.add_argument("--mixed-precisions", default="bf16x6,fp32",
@@ -431,12 +433,12 @@ def main():
     D = args.D or c["D"]
     m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
 
-    def timed_sweeps(prec, steps, warmup, profile):
+    def timed_sweeps(prec, steps, warmup, profile, cap=None):
         """warmup sweeps, `steps` timed sweeps (value), then with profile the same
         number of sweeps again with HIP events around every grouped launch (the
         events cost host time per launch, so they stay out of the timed value)."""
         o = T.options(D=D, symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
-                      precision=PREC[prec], sector_cap=args.sector_cap)
+                      precision=PREC[prec], sector_cap=args.sector_cap if cap is None else cap)
         print("init %s D=%d %s" % (args.workload, D, prec), file=sys.stderr, flush=True)
         st = T.State.init(m, o)
         t_tune = time.perf_counter()
@@ -516,6 +518,14 @@ def main():
         mixed[pname] = dict(s_per_step=sp, f=ob2["f"], e=ob2["e"],
                             rel_df_vs_main=abs(ob2["f"] - obs["f"]) / max(abs(obs["f"]), 1e-2),
                             rel_de_vs_main=abs(ob2["e"] - obs["e"]) / max(abs(obs["e"]), 1e-2))
+    # the same sweep with the sectors uncapped (every sector at its share of D
+    # up to its maximal dimension): the method's bond space without the cap,
+    # at the cost the cap saves
+    uncapped = None
+    if args.uncapped_steps > 0 and args.sector_cap != 0:
+        su, stu, _, obu, (_, dims_u, _), _ = timed_sweeps(args.precision, args.uncapped_steps, 1, False, cap=0)
+        uncapped = dict(s_per_step=su, steps=args.uncapped_steps, warmup=1, max_bond=max(dims_u),
+                        flops_alg_per_step=statistics.mean(x.flops_alg for x in stu), f=obu["f"], e=obu["e"])
 
     # dominant single kernel of the timed region and its roofline.  A
     # contraction kernel (grouped GEMM) is priced against the MFMA peak of the
@@ -703,7 +713,7 @@ def main():
                   "phase_ms_per_step": phases,
                   "apply_forms": forms_info,
                   "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
-                  "thermo": thermo, "other_precisions": mixed},
+                  "thermo": thermo, "other_precisions": mixed, "uncapped": uncapped},
         "heff": {"D": Dh, "D_H": DH, **heff},
         "mu_scan": mu_scan,
         "roofline": roof,
