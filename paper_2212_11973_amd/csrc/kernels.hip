@@ -779,7 +779,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   switch (J.shape) {
     case 0: wave_tile_k<4, 1, MM>(P, J, tabs, slots, red); break;
     case 1: wave_tile_k<2, 2, MM>(P, J, tabs, slots, red); break;
-    default: wave_tile_k<1, 4, MM>(P, J, tabs, slots, red); break;
+    case 2: wave_tile_k<1, 4, MM>(P, J, tabs, slots, red); break;
+    default: wave_tile_k<1, 1, MM>(P, J, tabs, slots, red); break;
   }
 }
 

@@ -182,27 +182,42 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
   }
   auto use_wave = [&](const GemmProb& g) { return wave[&g - p.probs.data()] != 0; };
   // wave jobs: split blocks (four K parts in one workgroup) first, then
-  // unsplit blocks four to a workgroup
-  std::vector<GemmJob> single;
+  // unsplit blocks four to a workgroup.  fine: 16x16 blocks and K split from
+  // four chunks on, for launches too small to fill the GPU otherwise.
+  auto plan_jobs = [&](bool fine, std::vector<GemmJob>& jobs) {
+    std::vector<GemmJob> single;
+    jobs.clear();
+    for (int i = 0; i < (int)p.probs.size(); ++i) {
+      const GemmProb& g = p.probs[i];
+      if (!use_wave(g) || g.M == 0 || g.N == 0) continue;
+      const int sh = fine ? 3 : wave_shape_for(g.M, g.N);
+      const int tm = (g.M + kWaveBM[sh] - 1) / kWaveBM[sh], tn = (g.N + kWaveBN[sh] - 1) / kWaveBN[sh];
+      // every part then takes at least two (one when fine) 16-deep chunks
+      const bool split = (g.K + 15) / 16 >= (fine ? 4 : 8);
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) {
+          if (split) {
+            for (int q = 0; q < 4; ++q) jobs.push_back({i, a, b, sh, q, 4});
+          } else {
+            single.push_back({i, a, b, sh, 0, 1});
+          }
+        }
+    }
+    for (auto& j : single) jobs.push_back(j);
+  };
   for (int i = 0; i < (int)p.probs.size(); ++i) {
     const GemmProb& g = p.probs[i];
     if (!use_wave(g) || g.M == 0 || g.N == 0) continue;
-    const int sh = wave_shape_for(g.M, g.N);
-    const int tm = (g.M + kWaveBM[sh] - 1) / kWaveBM[sh], tn = (g.N + kWaveBN[sh] - 1) / kWaveBN[sh];
-    const bool split = (g.K + 15) / 16 >= 8;   // every part then takes at least two 16-deep chunks
     p.wave_flops += 2.0 * g.M * g.N * g.K;
     p.wave_bytes += (g.dt & kDtA ? 4.0 : 8.0) * g.M * g.K + (g.dt & kDtB ? 4.0 : 8.0) * g.K * g.N +
                     (g.dt & kDtC ? 4.0 : 8.0) * g.M * g.N;
-    for (int a = 0; a < tm; ++a)
-      for (int b = 0; b < tn; ++b) {
-        if (split) {
-          for (int q = 0; q < 4; ++q) p.jobs.push_back({i, a, b, sh, q, 4});
-        } else {
-          single.push_back({i, a, b, sh, 0, 1});
-        }
-      }
   }
-  for (auto& j : single) p.jobs.push_back(j);
+  plan_jobs(false, p.jobs);
+  if (!p.jobs.empty() && (long long)p.jobs.size() < kWaveMinJobs) {
+    std::vector<GemmJob> fine;
+    plan_jobs(true, fine);
+    if (fine.size() > p.jobs.size()) p.jobs.swap(fine);
+  }
   while (p.jobs.size() % 4) p.jobs.push_back({-1, 0, 0, 0, 0, 1});
   p.wave_blocks = (int)(p.jobs.size() / 4);
 

@@ -52,16 +52,22 @@ constexpr int kGemmBM[kGemmCfgs] = {64, 128, 256, 32, 32};
 constexpr int kGemmBN[kGemmCfgs] = {64, 32, 16, 128, 32};
 
 // Wave GEMM for small, short-K or skinny problems: one 64-wide wave computes a
-// 64x16, 32x32 or 16x64 output block (shape 0, 1, 2) straight from global
-// memory.  A job is one wave's share: a whole block (nparts = 1), or part
-// `part` of the nparts = 4 interleaved K parts of a block, whose partial sums
-// the four waves of one workgroup add in LDS.  Jobs are grouped four per
+// 64x16, 32x32, 16x64 or 16x16 output block (shape 0, 1, 2, 3) straight from
+// global memory.  A job is one wave's share: a whole block (nparts = 1), or
+// part `part` of the nparts = 4 interleaved K parts of a block, whose partial
+// sums the four waves of one workgroup add in LDS.  Jobs are grouped four per
 // workgroup; the four jobs of a split block fill one workgroup, and unused
-// slots of a workgroup have prob = -1.
+// slots of a workgroup have prob = -1.  A launch whose blocks give fewer
+// than kWaveMinJobs jobs is planned finer (16x16 blocks, K split from four
+// 16-deep chunks on) so that more waves share its latency.
 struct GemmJob { int prob, tm, tn, shape, part, nparts; };
-constexpr int kWaveShapes = 3;
-constexpr int kWaveBM[kWaveShapes] = {64, 32, 16};
-constexpr int kWaveBN[kWaveShapes] = {16, 32, 64};
+constexpr int kWaveShapes = 4;
+constexpr int kWaveBM[kWaveShapes] = {64, 32, 16, 16};
+constexpr int kWaveBN[kWaveShapes] = {16, 32, 64, 16};
+#ifndef TT_WAVE_MIN_JOBS
+#define TT_WAVE_MIN_JOBS 4096
+#endif
+constexpr int kWaveMinJobs = TT_WAVE_MIN_JOBS;
 // problems at least this large in M, N and K use the LDS-staged tile kernel.
 // Below K = 128 the wave kernel (one pass over each operand row, paired
 // loads) is faster: that covers every block of a block-sparse sweep, whose K

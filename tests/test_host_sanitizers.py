@@ -1,5 +1,5 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer
-(device code built unoptimised, no GPU needed): the MPO and start builders, the
+(HIP sources built for the host only, no GPU needed): the MPO and start builders, the
 sector allocation, every planner and the descriptor bounds checks run for the
 workloads' lattices and options, and the argument checks reject bad input,
 in a process that preloads the ASan runtime.  Any report aborts that process."""
