@@ -371,6 +371,10 @@ def main():
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
     ap.add_argument("--heff2-D", type=int, default=256,
                     help="also time the dense two-site 2-TDVP generator at this bond dimension (0: skip)")
+    ap.add_argument("--tdvp2-sweeps", type=int, default=2,
+                    help="also grow the workload from the bare rho0 with this many 2-TDVP sweeps (0: skip)")
+    ap.add_argument("--tdvp2-D", type=int, default=2000, help="D_max of the 2-TDVP growth")
+    ap.add_argument("--tdvp2-cutoff", type=float, default=1e-12, help="discarded-weight cutoff of the 2-TDVP splits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graphs", action="store_true", help="replay captured sweeps (hipGraph) in the timed loop")
     ap.add_argument("--no-observables", action="store_true",
@@ -682,6 +686,35 @@ def main():
         print("heff2 done", file=sys.stderr, flush=True)
         del tt_, out
 
+    # 2-TDVP growth (the exponential stage's bond growth): the headline lattice
+    # from the bare rho0, steps of d_beta doubling from beta0, D_max and the
+    # discarded-weight cutoff as given
+    tdvp2 = None
+    if args.tdvp2_sweeps > 0:
+        o2 = T.options(D=1, symmetry=1, beta0=c["beta0"], pad_eps=0.0, krylov_dim=c["krylov"])
+        st2 = T.State.init(m, o2)
+        recs = []
+        b = c["beta0"]
+        for i in range(args.tdvp2_sweeps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s2 = st2.sweep2(b, args.tdvp2_D, args.tdvp2_cutoff, stats=True)   # synchronises
+            dt = time.perf_counter() - t0
+            b *= 2.0
+            recs.append(dict(seconds=dt, max_bond=max(st2.info()[1]), discarded=s2.discarded,
+                             flops_alg=s2.flops_alg))
+            print("tdvp2 sweep %d: %.2f s, max bond %d" % (i, dt, recs[-1]["max_bond"]), file=sys.stderr, flush=True)
+        o = st2.observables()
+        t0 = time.perf_counter()
+        st2.sweep(c["dbeta"])   # the one-site sweep on the grown bonds
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+        tdvp2 = dict(workload="%s from the bare rho0 (beta0 = %g), d_beta doubling, D_max %d, cutoff %g"
+                     % (args.workload, c["beta0"], args.tdvp2_D, args.tdvp2_cutoff),
+                     sweeps=recs, beta_phys=o["beta_phys"], f=o["f"], e=o["e"],
+                     bond_dims=st2.info()[1], one_site_sweep_s_after=t_one)
+        st2.free()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(c, D, args.sector_cap)
@@ -716,6 +749,7 @@ def main():
                   "thermo": thermo, "other_precisions": mixed, "uncapped": uncapped},
         "heff": {"D": Dh, "D_H": DH, **heff},
         "mu_scan": mu_scan,
+        "tdvp2": tdvp2,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
