@@ -697,12 +697,16 @@ def main():
         b = c["beta0"]
         for i in range(args.tdvp2_sweeps):
             torch.cuda.synchronize()
+            T.tt_phase_timing(i == args.tdvp2_sweeps - 1)   # device time per phase in the last sweep
             t0 = time.perf_counter()
             s2 = st2.sweep2(b, args.tdvp2_D, args.tdvp2_cutoff, stats=True)   # synchronises
             dt = time.perf_counter() - t0
+            T.tt_phase_timing(False)
             b *= 2.0
             recs.append(dict(seconds=dt, max_bond=max(st2.info()[1]), discarded=s2.discarded,
-                             flops_alg=s2.flops_alg))
+                             flops_alg=s2.flops_alg, n_launches=s2.n_launches,
+                             device_ms={k: getattr(s2, k) for k in ("t_heff", "t_bond", "t_lanczos", "t_qr",
+                                                                    "t_env", "t_absorb")}))
             print("tdvp2 sweep %d: %.2f s, max bond %d" % (i, dt, recs[-1]["max_bond"]), file=sys.stderr, flush=True)
         o = st2.observables()
         t0 = time.perf_counter()
