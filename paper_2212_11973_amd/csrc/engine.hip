@@ -1356,7 +1356,7 @@ long long check_pair(const tt_state& s, int k, const PairPlan& P, const std::vec
   for (const SvdTask& t : P.svd) {
     const Range r = map_range(T, t.rtab, 0, t.R);
     const long long mn = std::min(t.R, t.w), mx = std::max(t.R, t.w);
-    if (t.R <= 0 || t.w <= 0 || r.lo < 0 || r.hi + t.w - 1 >= th || t.ws < 0 ||
+    if (t.R <= 0 || t.w <= 0 || mn > kSvdMaxMinDim || r.lo < 0 || r.hi + t.w - 1 >= th || t.ws < 0 ||
         t.ws + mx * mn + mn * mn > P.svd_ws || t.sig < 0 || t.sig + mn > P.svd_nsig) {
       ++bad;
       if (rep.size() < 2000) rep += "svd task out of range\n";

@@ -106,6 +106,8 @@ void launch_copy(BPtr<double> dst, BPtr<const double> src, long long n, int nb, 
 void launch_fill(double* dst, double val, long long n, hipStream_t st);
 void launch_dot_final(const double* part, int nparts, int nv, double* out, hipStream_t st);
 
+// the smaller dimension of an SVD task is at most this (its column norms live in LDS)
+constexpr int kSvdMaxMinDim = 16384;
 // SVD of every task (one-sided Jacobi, one workgroup per task; ws holds the
 // plan's svd_ws doubles, sig its svd_nsig singular values), then the kept
 // vectors of every emit entry into the two site tensors

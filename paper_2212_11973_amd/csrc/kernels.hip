@@ -2278,8 +2278,18 @@ void launch_trace(const TraceEntry* d_entries, const int* d_site_start, int N, d
 // rotations of a round touch disjoint columns and run on separate waves; sums
 // are taken in a fixed order, so the result is deterministic.  Small singular
 // values keep their relative accuracy.  One workgroup per task.
+//  * X, and V when it fits too, live in LDS for the sweeps (copied back to the
+//    work array at the end) when the task is small enough; else in global memory.
+//  * The squared column norms are kept in LDS, recomputed exactly at the
+//    start of every sweep and updated by each rotation (||u'||^2 = al - t ga,
+//    ||v'||^2 = be + t ga), so a pair costs one dot product, not three.
+//  * A pair of columns both at the rounding level of the block (squared
+//    norms below (m eps ||X||_F)^2) is left alone: their mutual products are
+//    rounding noise that no rotation makes orthogonal, and such columns
+//    carry singular values far below any kept one.
 constexpr int kSvdThreads = 1024;
 constexpr int kSvdMaxSweeps = 40;
+constexpr int kSvdLdsBytes = 160 * 1024;
 
 __device__ inline double wave_sum64(double v) {
   // butterfly: every lane ends with the same bits (each addition is commutative)
@@ -2290,12 +2300,23 @@ __device__ inline double wave_sum64(double v) {
 __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __restrict__ tasks,
                                                            const long long* __restrict__ tabs,
                                                            const double* __restrict__ src, double* __restrict__ ws,
-                                                           double* __restrict__ sig) {
+                                                           double* __restrict__ sig, int lds_doubles) {
+  extern __shared__ __attribute__((aligned(16))) double svd_lds[];
   const SvdTask t = tasks[blockIdx.x];
   const bool tr = t.R < t.w;
   const int mw = tr ? t.w : t.R, nw = tr ? t.R : t.w;
-  double* X = ws + t.ws;
-  double* V = X + (long long)mw * nw;
+  double* Xg = ws + t.ws;
+  double* Vg = Xg + (long long)mw * nw;
+  if (nw > lds_doubles) {   // the norms must fit (the host refuses such tasks): report NaN values
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) sig[t.sig + j] = __builtin_nan("");
+    return;
+  }
+  // LDS: the squared norms, then X if it fits, then V if it fits too
+  double* nrm = svd_lds;
+  const long long need_x = (long long)nw + (long long)mw * nw, need_xv = need_x + (long long)nw * nw;
+  const bool x_lds = need_x <= lds_doubles, v_lds = need_xv <= lds_doubles;
+  double* X = x_lds ? svd_lds + nw : Xg;
+  double* V = v_lds ? svd_lds + need_x : Vg;
   const long long* rt = tabs + t.rtab;
   const long long tot = (long long)t.R * t.w;
   for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -2306,27 +2327,44 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __res
   }
   for (long long e = threadIdx.x; e < (long long)nw * nw; e += blockDim.x) V[e] = (e / nw == e % nw) ? 1.0 : 0.0;
   __shared__ int rotated;
+  __shared__ double s_thr;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int np = nw + (nw & 1);                 // an idle index when nw is odd
-  const double tol = 2.220446049250313e-16 * (double)(mw > 16 ? mw : 16);
+  const double eps = 2.220446049250313e-16;
+  const double tol = eps * (double)(mw > 16 ? mw : 16);
   __syncthreads();
   for (int sw = 0; sw < kSvdMaxSweeps && np > 1; ++sw) {
-    if (threadIdx.x == 0) rotated = 0;
+    // exact squared column norms, and the rounding level of the block
+    for (int j = wave; j < nw; j += nwaves) {
+      const double* xj = X + (long long)j * mw;
+      double s2 = 0.0;
+      for (int i = lane; i < mw; i += 64) s2 += xj[i] * xj[i];
+      s2 = wave_sum64(s2);
+      if (lane == 0) nrm[j] = s2;
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      double f = 0.0;
+      for (int j = 0; j < nw; ++j) f += nrm[j];
+      const double lev = (double)mw * eps;
+      s_thr = lev * lev * f;
+      rotated = 0;
+    }
+    __syncthreads();
+    const double thr = s_thr;
     for (int rd = 0; rd < np - 1; ++rd) {
       for (int k = wave; k < np / 2; k += nwaves) {
         int a = k == 0 ? 0 : 1 + (k + rd) % (np - 1);
         int b = 1 + ((k == 0 ? 0 : np - 1 - k) + rd) % (np - 1);
         if (a > b) { const int q = a; a = b; b = q; }
         if (b >= nw) continue;
+        const double al = nrm[a], be = nrm[b];
+        if (al <= thr && be <= thr) continue;
         double* xa = X + (long long)a * mw;
         double* xb = X + (long long)b * mw;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < mw; i += 64) {
-          const double u = xa[i], v = xb[i];
-          al += u * u; be += v * v; ga += u * v;
-        }
-        al = wave_sum64(al); be = wave_sum64(be); ga = wave_sum64(ga);
+        double ga = 0.0;
+        for (int i = lane; i < mw; i += 64) ga += xa[i] * xb[i];
+        ga = wave_sum64(ga);
         if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
@@ -2343,7 +2381,11 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __res
           va[i] = c * u - s * v;
           vb[i] = s * u + c * v;
         }
-        if (lane == 0) rotated = 1;
+        if (lane == 0) {
+          nrm[a] = al - tn * ga;
+          nrm[b] = be + tn * ga;
+          rotated = 1;
+        }
       }
       __syncthreads();
     }
@@ -2358,6 +2400,11 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __res
     s2 = wave_sum64(s2);
     if (lane == 0) sig[t.sig + j] = sqrt(s2);
   }
+  // the emit kernel reads X and V from the work array
+  if (x_lds)
+    for (long long e = threadIdx.x; e < (long long)mw * nw; e += blockDim.x) Xg[e] = X[e];
+  if (v_lds)
+    for (long long e = threadIdx.x; e < (long long)nw * nw; e += blockDim.x) Vg[e] = V[e];
 }
 
 // M = sum_j s_j u_j v_j^T with unit u_j (R entries) and v_j (w entries), read
@@ -2392,7 +2439,21 @@ __global__ __launch_bounds__(256) void k_svd_emit(const SvdTask* __restrict__ ta
 void launch_svd(const SvdTask* d_tasks, int ntasks, const long long* d_tabs, const double* src, double* ws,
                 double* sig, hipStream_t st) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_svd_jacobi, dim3(ntasks), dim3(kSvdThreads), 0, st, d_tasks, d_tabs, src, ws, sig);
+  // dynamic LDS: the device's per-workgroup limit, at most kSvdLdsBytes, less
+  // the kernel's static LDS (two shared scalars)
+  static int lds_bytes = -1;
+  if (lds_bytes < 0) {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      throw Error(TT_EDEVICE, "cannot read the LDS limit");
+    lds_bytes = std::min(lim, kSvdLdsBytes) - 64;
+    if (hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) !=
+        hipSuccess)
+      throw Error(TT_EDEVICE, "cannot set the LDS limit of the SVD kernel");
+  }
+  hipLaunchKernelGGL(k_svd_jacobi, dim3(ntasks), dim3(kSvdThreads), lds_bytes, st, d_tasks, d_tabs, src, ws, sig,
+                     lds_bytes / 8);
   HIP_CHECK_LAUNCH();
 }
 void launch_svd_emit(const SvdTask* d_tasks, const SvdEmit* d_em, int nem, const long long* d_tabs, const double* ws,
