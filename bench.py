@@ -608,6 +608,7 @@ def main():
                        batched_s_per_step=s_batch, s_per_instance_step=s_batch / len(mus),
                        single_instance_s_per_step=s_single, speedup_vs_one_at_a_time=s_single * len(mus) / s_batch,
                        tflops_alg=fl / args.steps / s_batch / 1e12,
+                       frac_fp64_mfma=fl / args.steps / s_batch / 1e12 / PEAK["fp64"],
                        beta_phys=dens[0]["beta_phys"], e_per_site=[d["e"] for d in dens],
                        s_per_site=[d["beta_phys"] * (d["e"] - d["f"]) for d in dens], n_per_site=ns,
                        docc_per_site=[lo["docc"] for lo in locs], chi_dn_dmu=chi, spin_corr_nn=f_nn)
@@ -624,15 +625,20 @@ def main():
             T.tdvp_sweep_batch(h32, c4["dbeta"])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            fl32 = 0.0
             for i in range(args.steps):
-                T.tdvp_sweep_batch(h32, c4["dbeta"])
+                fl32 += T.tdvp_sweep_batch(h32, c4["dbeta"], stats=True).flops_alg
             torch.cuda.synchronize()
             s_b32 = (time.perf_counter() - t0) / args.steps
             e32 = [st.observables()["e"] for st in s32]
             for st in s32:
                 st.free()
             print("mu-scan fp32 batch done", file=sys.stderr, flush=True)
-            mu_scan.update(fp32_batched_s_per_instance_step=s_b32 / len(mus),
+            tf32 = fl32 / args.steps / s_b32 / 1e12
+            mu_scan.update(fp32_batched_tflops_alg=tf32,
+                           # the wave GEMM multiplies in FP64 in both forms: the FP64 MFMA roof
+                           fp32_batched_frac_fp64_mfma=tf32 / PEAK["fp64"],
+                           fp32_batched_s_per_instance_step=s_b32 / len(mus),
                            fp32_batched_speedup_vs_fp64_one_at_a_time=s_single * len(mus) / s_b32,
                            fp32_max_rel_de_vs_fp64=max(abs(a - b) / max(abs(b), 1e-2)
                                                        for a, b in zip(e32, [d_["e"] for d_ in dens])))

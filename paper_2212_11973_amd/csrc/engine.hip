@@ -98,6 +98,7 @@ void upload_plan(GemmPlan& p, const std::vector<long long>* tabs, hipStream_t st
   p.d_tiles = upload(p.tiles, st);
   p.d_splits = upload(p.splits, st);
   p.d_jobs = upload(p.jobs, st);
+  p.d_jobs_fine = upload(p.jobs_fine, st);
 }
 void upload_plan(WPlan& p, hipStream_t st) {
   p.ntasks = (int)p.tasks.size();
@@ -122,8 +123,8 @@ void upload_plan(QRPlan& p, hipStream_t st) {
   p.d_wide = upload(p.wide, st);
 }
 void free_plan(GemmPlan& p) {
-  dfree(p.d_probs); dfree(p.d_tiles); dfree(p.d_splits); dfree(p.d_jobs);
-  p.d_probs = nullptr; p.d_tiles = nullptr; p.d_splits = nullptr; p.d_jobs = nullptr;
+  dfree(p.d_probs); dfree(p.d_tiles); dfree(p.d_splits); dfree(p.d_jobs); dfree(p.d_jobs_fine);
+  p.d_probs = nullptr; p.d_tiles = nullptr; p.d_splits = nullptr; p.d_jobs = nullptr; p.d_jobs_fine = nullptr;
 }
 void free_plan(WPlan& p) { dfree(p.d_tasks); dfree(p.d_terms); p.d_tasks = nullptr; p.d_terms = nullptr; }
 void upload_plan(FzPlan& p, hipStream_t st) {
@@ -1082,23 +1083,27 @@ long long check_gemm(const GemmPlan& p, const std::vector<long long>& tabs, cons
     if (sp.prob < 0 || sp.prob >= (int)p.probs.size() || sp.pw < 0 ||
         sp.pw + (long long)sp.nk * kGemmBM[sp.cfg] * kGemmBN[sp.cfg] > p.pws_size) ++bad;
   // wave jobs: four per workgroup; a split block fills its workgroup with parts 0..3
-  if (p.jobs.size() % 4 != 0 || (long long)p.jobs.size() != 4LL * p.wave_blocks) ++bad;
-  for (size_t w = 0; w + 3 < p.jobs.size(); w += 4) {
-    const GemmJob& j0 = p.jobs[w];
-    for (int q = 0; q < 4; ++q) {
-      const GemmJob& j = p.jobs[w + q];
-      if (j.nparts != j0.nparts) ++bad;
-      if (j.prob < 0) { if (j.nparts != 1) ++bad; continue; }
-      if (j.prob >= (int)p.probs.size() || j.shape < 0 || j.shape >= kWaveShapes) { ++bad; continue; }
-      const GemmProb& g = p.probs[j.prob];
-      if (j.tm < 0 || j.tn < 0 || j.tm * kWaveBM[j.shape] >= g.M || j.tn * kWaveBN[j.shape] >= g.N) ++bad;
-      if (j.nparts == 4) {
-        if (j.part != q || j.prob != j0.prob || j.tm != j0.tm || j.tn != j0.tn || j.shape != j0.shape) ++bad;
-      } else if (j.nparts != 1 || j.part != 0) {
-        ++bad;
+  auto check_jobs = [&](const std::vector<GemmJob>& jobs, int wave_blocks) {
+    if (jobs.size() % 4 != 0 || (long long)jobs.size() != 4LL * wave_blocks) ++bad;
+    for (size_t w = 0; w + 3 < jobs.size(); w += 4) {
+      const GemmJob& j0 = jobs[w];
+      for (int q = 0; q < 4; ++q) {
+        const GemmJob& j = jobs[w + q];
+        if (j.nparts != j0.nparts) ++bad;
+        if (j.prob < 0) { if (j.nparts != 1) ++bad; continue; }
+        if (j.prob >= (int)p.probs.size() || j.shape < 0 || j.shape >= kWaveShapes) { ++bad; continue; }
+        const GemmProb& g = p.probs[j.prob];
+        if (j.tm < 0 || j.tn < 0 || j.tm * kWaveBM[j.shape] >= g.M || j.tn * kWaveBN[j.shape] >= g.N) ++bad;
+        if (j.nparts == 4) {
+          if (j.part != q || j.prob != j0.prob || j.tm != j0.tm || j.tn != j0.tn || j.shape != j0.shape) ++bad;
+        } else if (j.nparts != 1 || j.part != 0) {
+          ++bad;
+        }
       }
     }
-  }
+  };
+  check_jobs(p.jobs, p.wave_blocks);
+  check_jobs(p.jobs_fine, p.wave_blocks_fine);
   return bad;
 }
 
@@ -1844,7 +1849,8 @@ void reset_counters(tt_state& s) { s.flops = s.flops_heff = s.bytes_min = 0.0; s
 
 bool same_gemm(const GemmPlan& x, const GemmPlan& y) {
   return same_bytes(x.probs, y.probs) && same_bytes(x.tiles, y.tiles) && same_bytes(x.jobs, y.jobs) &&
-         same_bytes(x.splits, y.splits) && x.pws_size == y.pws_size && x.wave_blocks == y.wave_blocks;
+         same_bytes(x.jobs_fine, y.jobs_fine) && same_bytes(x.splits, y.splits) && x.pws_size == y.pws_size &&
+         x.wave_blocks == y.wave_blocks && x.wave_blocks_fine == y.wave_blocks_fine;
 }
 bool same_w(const WPlan& x, const WPlan& y) {   // the weights may differ
   if (!same_bytes(x.tasks, y.tasks) || x.terms.size() != y.terms.size()) return false;
@@ -2040,6 +2046,7 @@ long long noalloc_layout(NoAllocDev& d, bool copy, hipStream_t st) {
     put(dev[i]->d_tiles, src[i]->tiles);
     put(dev[i]->d_splits, src[i]->splits);
     put(dev[i]->d_jobs, src[i]->jobs);
+    put(dev[i]->d_jobs_fine, src[i]->jobs_fine);
   }
   return used;
 }

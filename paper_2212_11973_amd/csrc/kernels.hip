@@ -1140,7 +1140,11 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
   TT_REQUIRE(nb >= 1 && nb <= kMaxBatch, TT_EINVAL, "batch size out of range");
   prof_begin(st);
   if (p.wave_blocks > 0) {
-    const dim3 grid(p.wave_blocks, nb), block(256);
+    // the finer job list when the launch would otherwise hold few waves
+    const bool fine = p.wave_blocks_fine > 0 && 4LL * p.wave_blocks * nb < kWaveMinJobs;
+    const int nblk = fine ? p.wave_blocks_fine : p.wave_blocks;
+    const GemmJob* jobs = fine ? p.d_jobs_fine : p.d_jobs;
+    const dim3 grid(nblk, nb), block(256);
     switch (precision) {
       // FP32 mode: the wave GEMM's blocks are bound by memory and latency, so
       // it multiplies in FP64 and the mode's saving is the float storage of the
@@ -1148,9 +1152,9 @@ void launch_gemm(const GemmPlan& p, const long long* d_tabs, const BSlots& s, in
       // was no faster (0.278 vs 0.271 s/step) and its error after four sweeps
       // was 1.3e-6 in E against 2e-10 with FP64 multiplies.
       case TT_FP64:
-      case TT_FP32: hipLaunchKernelGGL(k_wgemm<TT_FP64>, grid, block, 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs, s); break;
-      case TT_BF16X3: hipLaunchKernelGGL(k_wgemm<TT_BF16X3>, grid, block, 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs, s); break;
-      case TT_BF16X6: hipLaunchKernelGGL(k_wgemm<TT_BF16X6>, grid, block, 0, st, p.d_probs, p.d_jobs, p.wave_blocks, d_tabs, s); break;
+      case TT_FP32: hipLaunchKernelGGL(k_wgemm<TT_FP64>, grid, block, 0, st, p.d_probs, jobs, nblk, d_tabs, s); break;
+      case TT_BF16X3: hipLaunchKernelGGL(k_wgemm<TT_BF16X3>, grid, block, 0, st, p.d_probs, jobs, nblk, d_tabs, s); break;
+      case TT_BF16X6: hipLaunchKernelGGL(k_wgemm<TT_BF16X6>, grid, block, 0, st, p.d_probs, jobs, nblk, d_tabs, s); break;
       default: throw Error(TT_EINVAL, "unknown precision");
     }
     HIP_CHECK_LAUNCH();

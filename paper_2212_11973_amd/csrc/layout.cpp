@@ -154,6 +154,8 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
   p.tiles.clear();
   p.splits.clear();
   p.jobs.clear();
+  p.jobs_fine.clear();
+  p.wave_blocks_fine = 0;
   p.pws_size = 0;
   p.smem_bytes = 0;
   p.red_bytes = 0;
@@ -213,13 +215,15 @@ void tile_plan(GemmPlan& p, const std::vector<long long>* tabs) {
                     (g.dt & kDtC ? 4.0 : 8.0) * g.M * g.N;
   }
   plan_jobs(false, p.jobs);
+  p.jobs_fine.clear();
   if (!p.jobs.empty() && (long long)p.jobs.size() < kWaveMinJobs) {
-    std::vector<GemmJob> fine;
-    plan_jobs(true, fine);
-    if (fine.size() > p.jobs.size()) p.jobs.swap(fine);
+    plan_jobs(true, p.jobs_fine);
+    if (p.jobs_fine.size() <= p.jobs.size()) p.jobs_fine.clear();
   }
-  while (p.jobs.size() % 4) p.jobs.push_back({-1, 0, 0, 0, 0, 1});
+  for (auto* j : {&p.jobs, &p.jobs_fine})
+    while (j->size() % 4) j->push_back({-1, 0, 0, 0, 0, 1});
   p.wave_blocks = (int)(p.jobs.size() / 4);
+  p.wave_blocks_fine = (int)(p.jobs_fine.size() / 4);
 
   // LDS-staged tiles for the rest; K splitting only pays when the launch has
   // too few tiles to fill the GPU

@@ -57,9 +57,10 @@ constexpr int kGemmBN[kGemmCfgs] = {64, 32, 16, 128, 32};
 // part `part` of the nparts = 4 interleaved K parts of a block, whose partial
 // sums the four waves of one workgroup add in LDS.  Jobs are grouped four per
 // workgroup; the four jobs of a split block fill one workgroup, and unused
-// slots of a workgroup have prob = -1.  A launch whose blocks give fewer
-// than kWaveMinJobs jobs is planned finer (16x16 blocks, K split from four
-// 16-deep chunks on) so that more waves share its latency.
+// slots of a workgroup have prob = -1.  A plan whose blocks give fewer than
+// kWaveMinJobs jobs also holds a finer job list (16x16 blocks, K split from
+// four 16-deep chunks on); a launch takes it when the plan's jobs times the
+// batch's states stay below kWaveMinJobs, so that more waves share the latency.
 struct GemmJob { int prob, tm, tn, shape, part, nparts; };
 constexpr int kWaveShapes = 4;
 constexpr int kWaveBM[kWaveShapes] = {64, 32, 16, 16};
@@ -165,6 +166,9 @@ struct GemmPlan {
   std::vector<GemmJob> jobs;
   GemmJob* d_jobs = nullptr;
   int wave_blocks = 0;
+  std::vector<GemmJob> jobs_fine;   // empty unless it has more jobs than `jobs`
+  GemmJob* d_jobs_fine = nullptr;
+  int wave_blocks_fine = 0;
   double wave_flops = 0, wave_bytes = 0;
   bool no_split = false;    // never split K (tiles whose result is written as BF16 planes)
 };
