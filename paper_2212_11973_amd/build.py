@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtantrg.so")
 
-SOURCES = ["model.cpp", "layout.cpp", "kernels.hip", "engine.hip"]
+SOURCES = ["model.cpp", "layout.cpp", "kernels.hip", "bgemm.hip", "engine.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

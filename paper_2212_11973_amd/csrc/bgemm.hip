@@ -1,0 +1,387 @@
+// Large-tile split-BF16 GEMM of the dense effective-Hamiltonian apply
+// (SM Fig. optimalB(c): L.A and .R of one site, operands dense).
+//
+// C(m, n) = sum_k A(m, k) B(n, k), both operands held as NP BF16 planes
+// (x ~ part 0 + part 1 (+ part 2), each rounded to nearest) with rows
+// contiguous in k and zero-padded to a multiple of 32.  The products of the
+// parts that the precision keeps (x3: 00, 01, 10; x6: also 02, 11, 20) are
+// taken with the gfx950 BF16 MFMA 16x16x32 into FP32 accumulators, which are
+// added into FP64 accumulators every kFold K tiles, so the FP32 sums stay
+// short at any K.
+//
+// One 128 x 128 output tile per workgroup of four waves (2 x 2, 64 x 64 each,
+// 4 x 4 MFMA blocks).  K tiles of 32 go global -> LDS directly (one 16-byte
+// global_load_lds per lane, no register staging) into a ring of S stages, S - 1
+// tiles ahead of the one being multiplied.  An LDS row is 64 bytes (four
+// 16-byte chunks); chunk c of row r sits at position c ^ ((r >> 2) & 3), so the
+// 16 rows an MFMA operand read touches fall in distinct banks.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace tt {
+
+extern long long g_launches;
+
+namespace {
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+constexpr int kBM = 128, kBN = 128, kBK = 32;
+constexpr int kRowBytes = kBK * 2;             // one LDS row of one plane
+constexpr int kFold = 8;                       // K tiles between FP64 folds
+constexpr int kGroupM = 8;                     // tile rows per raster group
+
+template <int NP> struct BgTraits;
+template <> struct BgTraits<2> { static constexpr int S = 4; };
+template <> struct BgTraits<3> { static constexpr int S = 3; };
+template <int NP> constexpr int bg_stage_bytes() { return NP * (kBM + kBN) * kRowBytes; }
+template <int NP> constexpr int bg_lds_bytes() { return BgTraits<NP>::S * bg_stage_bytes<NP>(); }
+
+// s_waitcnt immediate: vmcnt(n), other counters left alone (gfx9 encoding)
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+template <int NP>
+__device__ __forceinline__ void bg_split(double x, __bf16* out) {
+  const __bf16 h = (__bf16)(float)x;
+  out[0] = h;
+  const double r = x - (double)(float)h;
+  const __bf16 m = (__bf16)(float)r;
+  out[1] = m;
+  if (NP == 3) out[2] = (__bf16)(float)(r - (double)(float)m);
+}
+
+__device__ __forceinline__ int bg_xcd_block(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, slot = b >> 3;
+  return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+// One K tile (all planes of both operands) into LDS stage `st`.  Wave w loads
+// rows 32w .. 32w + 31 of the A and B tiles, 16 rows per instruction: lane l
+// takes row 16 j + l / 4 of its group and the logical chunk that lands at
+// position l % 4.
+template <int NP>
+__device__ __forceinline__ void bg_issue(const BgArgs& g, char* lds, int st, int kt, int m0, int n0, int wave,
+                                         int lane) {
+  char* base = lds + st * bg_stage_bytes<NP>();
+  const int lc = (lane & 3) ^ (lane >> 4);
+  const long long k = (long long)kt * kBK + 8 * lc;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int row = 32 * wave + 16 * j + (lane >> 2);
+    const int ma = min(m0 + row, g.M - 1), nb = min(n0 + row, g.N - 1);
+    const __bf16* ga = g.A + (long long)ma * g.lda + k;
+    const __bf16* gb = g.B + (long long)nb * g.ldb + k;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      char* la = base + (p * kBM + 32 * wave + 16 * j) * kRowBytes;
+      char* lb = base + (NP * kBM + p * kBN + 32 * wave + 16 * j) * kRowBytes;
+      __builtin_amdgcn_global_load_lds((const void*)(ga + p * g.sa), (lds_void*)la, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(gb + p * g.sb), (lds_void*)lb, 16, 0, 0);
+    }
+  }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bgemm(BgArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char bg_lds[];
+  constexpr int S = BgTraits<NP>::S;
+  constexpr int LPS = 4 * NP;   // global_load_lds per wave per stage
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+
+  // XCD-contiguous block ranges, then a grouped raster (kGroupM tile rows)
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int blk = bg_xcd_block(blockIdx.x, ntiles);
+  const int per_group = kGroupM * g.tiles_n;
+  const int grp = blk / per_group, first = grp * kGroupM;
+  const int gsz = min(g.tiles_m - first, kGroupM);
+  const int in = blk - grp * per_group;
+  const int tm = first + in % gsz, tn = in / gsz;
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  double4_t acc[4][4];
+  float4_t part[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      part[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int nk = g.K / kBK;
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < nk) bg_issue<NP>(g, bg_lds, s, s, m0, n0, wave, lane);
+
+  // read position of this lane's operand chunk q in rows r (+16 i)
+  const int rpos = r * kRowBytes + 16 * (q ^ ((r >> 2) & 3));
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of tile kt are done once at most the later issued
+    // stages are outstanding
+    if (kt + S - 2 < nk) __builtin_amdgcn_s_waitcnt(vmcnt_imm((S - 2) * LPS));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    // every wave's loads of tile kt landed and stage (kt - 1) % S is read:
+    // a bare barrier (a fenced one would also wait for the later stages'
+    // loads), with the compiler kept from moving memory accesses across it
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kt + S - 1 < nk) bg_issue<NP>(g, bg_lds, (kt + S - 1) % S, kt + S - 1, m0, n0, wave, lane);
+    const char* base = bg_lds + (kt % S) * bg_stage_bytes<NP>();
+    bf16x8_t a[NP][4], b[NP][4];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[p][i] = *reinterpret_cast<const bf16x8_t*>(base + (p * kBM + wm + 16 * i) * kRowBytes + rpos);
+        b[p][i] = *reinterpret_cast<const bf16x8_t*>(base + (NP * kBM + p * kBN + wn + 16 * i) * kRowBytes + rpos);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float4_t t = part[i][j];
+        if constexpr (NP == 3) {
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], t, 0, 0, 0);
+        }
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], t, 0, 0, 0);
+        part[i][j] = t;
+      }
+    if ((kt + 1) % kFold == 0 || kt + 1 == nk) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+          part[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+
+  // accumulator element v of a 16 x 16 block: row 4 (lane / 16) + v, column lane % 16
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm + 16 * i + 4 * q + v;
+      if (m >= g.M) continue;
+      const long long row = (long long)(m / g.cdiv) * g.ldc1 + (long long)(m % g.cdiv) * g.ldc0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn + 16 * j + r;
+        if (n >= g.N) continue;
+        const double val = acc[i][j][v];
+        if (g.cplanes) {
+          __bf16 parts[3];
+          bg_split<NP>(val, parts);
+          __bf16* c = reinterpret_cast<__bf16*>(g.C) + row + n;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) c[p * g.sc] = parts[p];
+        } else {
+          reinterpret_cast<double*>(g.C)[row + n] = val;
+        }
+      }
+    }
+}
+
+// out[p][r * ldo + k] = part p of x[r * ldx + k] for k < K, zero for K <= k < ldo
+template <int NP>
+__global__ __launch_bounds__(256) void k_split_rows(const double* __restrict__ x, long long rows, int K, long long ldx,
+                                                   __bf16* __restrict__ out, long long ldo, long long plane) {
+  const long long n = rows * ldo;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const long long rr = e / ldo, k = e - rr * ldo;
+    __bf16 parts[3] = {(__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+    if (k < K) bg_split<NP>(x[rr * ldx + k], parts);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) out[p * plane + e] = parts[p];
+  }
+}
+
+// transposed: out[p][c * ldo + k] = part p of x[k * C + c] for k < K, zero for
+// K <= k < ldo; 32 x 32 tiles through LDS
+template <int NP>
+__global__ __launch_bounds__(256) void k_split_t(const double* __restrict__ x, int K, int C, __bf16* __restrict__ out,
+                                                long long ldo, long long plane) {
+  __shared__ double t[32][33];
+  const int k0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = k0 + ty + 8 * i, c = c0 + tx;
+    t[ty + 8 * i][tx] = (k < K && c < C) ? x[(long long)k * C + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = c0 + ty + 8 * i, k = k0 + tx;
+    if (c < C && k < ldo) {
+      __bf16 parts[3];
+      bg_split<NP>(t[tx][ty + 8 * i], parts);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) out[p * plane + (long long)c * ldo + k] = parts[p];
+    }
+  }
+}
+
+// The W stage of the dense apply on BF16 planes, in FP32 on the vector units
+// (its 2 (4 DH)^2 flops per element move 4 NP bytes, so the planes' traffic
+// bounds it):  T2[(x', 4 so + sp)][b Dr + y] = sum_(a, si) W[a, so, si, b]
+// T1[a][x'][si][sp][y].  One thread per y; blockIdx.y = 4 x' + sp.  W comes as
+// floats wf[(4 a + si) (4 DH) + DH so + b], staged in LDS with rows padded to
+// kWsMaxO and read as broadcasts.
+constexpr int kWsMaxO = 80;   // 4 DH at most
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_wstage_planes(const __bf16* __restrict__ T1, long long sT1,
+                                                       const float* __restrict__ wf, int DH, int Dl, int Dr,
+                                                       __bf16* __restrict__ T2, long long sT2, long long kp3) {
+  __shared__ __attribute__((aligned(16))) float wl[kWsMaxO * kWsMaxO];
+  const int KO = 4 * DH;
+  for (int e = threadIdx.x; e < KO * KO; e += 256) wl[(e / KO) * kWsMaxO + e % KO] = wf[e];
+  __syncthreads();
+  const int x = blockIdx.y >> 2, sp = blockIdx.y & 3;
+  const int y = blockIdx.x * 256 + threadIdx.x;
+  if (y >= Dr) return;
+  float acc[kWsMaxO];
+#pragma unroll
+  for (int o = 0; o < kWsMaxO; ++o) acc[o] = 0.f;
+  const long long N1 = 16LL * Dr;
+  const __bf16* t1 = T1 + (long long)x * N1 + (long long)sp * Dr + y;
+  for (int a = 0; a < DH; ++a)
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      const __bf16* e = t1 + (long long)a * Dl * N1 + (long long)si * 4 * Dr;
+      float t = 0.f;   // the parts summed smallest first
+#pragma unroll
+      for (int p = NP - 1; p >= 0; --p) t += (float)e[p * sT1];
+      const float* wr = wl + (4 * a + si) * kWsMaxO;
+#pragma unroll
+      for (int o = 0; o < kWsMaxO; o += 4)
+        if (o < KO) {
+          const float4 w = *reinterpret_cast<const float4*>(wr + o);
+          acc[o] += w.x * t;
+          acc[o + 1] += w.y * t;
+          acc[o + 2] += w.z * t;
+          acc[o + 3] += w.w * t;
+        }
+    }
+  __bf16* t2 = T2 + (long long)(16 * x + sp) * kp3 + y;
+#pragma unroll
+  for (int o = 0; o < kWsMaxO; ++o)
+    if (o < KO) {
+      const int so = o / DH, b = o - so * DH;
+      __bf16 parts[3];
+      bg_split<NP>((double)acc[o], parts);
+      __bf16* c = t2 + (long long)(4 * so) * kp3 + (long long)b * Dr;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) c[p * sT2] = parts[p];
+    }
+}
+
+// wf[(4 a + si) (4 DH) + DH so + b] = W[a][so][si][b] as float
+__global__ void k_w_float(const double* __restrict__ W, int DH, float* __restrict__ wf) {
+  const int KO = 4 * DH;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < KO * KO; e += gridDim.x * blockDim.x) {
+    const int k = e / KO, o = e - k * KO;
+    const int a = k >> 2, si = k & 3, so = o / DH, b = o - so * DH;
+    wf[e] = (float)W[((a * 4 + so) * 4 + si) * DH + b];
+  }
+}
+
+template <int NP>
+void bgemm_np(const BgArgs& a, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_bgemm<NP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bg_lds_bytes<NP>()) != hipSuccess)
+      throw Error(TT_EDEVICE, "cannot set the LDS limit of the split-BF16 GEMM");
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_bgemm<NP>, dim3(a.tiles_m * a.tiles_n), dim3(256), bg_lds_bytes<NP>(), st, a);
+}
+
+}  // namespace
+
+int bgemm_kpad(long long K) { return (int)((K + kBK - 1) / kBK * kBK); }
+
+void launch_bgemm(BgArgs a, int precision, hipStream_t st) {
+  TT_REQUIRE(precision == TT_BF16X3 || precision == TT_BF16X6, TT_EINVAL, "bgemm: split-BF16 precisions only");
+  TT_REQUIRE(a.M >= 1 && a.N >= 1 && a.K >= kBK && a.K % kBK == 0, TT_EINVAL, "bgemm: K must be a positive multiple of 32");
+  TT_REQUIRE(a.lda >= a.K && a.ldb >= a.K && a.lda % 8 == 0 && a.ldb % 8 == 0 && a.sa % 8 == 0 && a.sb % 8 == 0,
+             TT_EINVAL, "bgemm: operand rows must hold K and start 16-byte aligned");
+  TT_REQUIRE(a.cdiv >= 1, TT_EINVAL, "bgemm: bad row map");
+  TT_REQUIRE(((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0, TT_EINVAL, "bgemm: operands not 16-byte aligned");
+  a.tiles_m = (a.M + kBM - 1) / kBM;
+  a.tiles_n = (a.N + kBN - 1) / kBN;
+  TT_REQUIRE((long long)a.tiles_m * a.tiles_n < (1LL << 31), TT_EINVAL, "bgemm: too many tiles");
+  if (precision == TT_BF16X3) bgemm_np<2>(a, st);
+  else bgemm_np<3>(a, st);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+int wstage_planes_max_dh() { return kWsMaxO / 4; }
+
+void launch_wstage_planes(const void* T1, long long sT1, const double* W, float* wf, int DH, int Dl, int Dr, void* T2,
+                          long long sT2, long long kp3, int precision, hipStream_t st) {
+  TT_REQUIRE(precision == TT_BF16X3 || precision == TT_BF16X6, TT_EINVAL, "W stage: split-BF16 precisions only");
+  TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && 4LL * Dl < 65536 && kp3 >= (long long)DH * Dr,
+             TT_EINVAL, "W stage: shape out of range");
+  hipLaunchKernelGGL(k_w_float, dim3(8), dim3(256), 0, st, W, DH, wf);
+  ++g_launches;
+  const dim3 grid((unsigned)((Dr + 255) / 256), (unsigned)(4 * Dl));
+  if (precision == TT_BF16X3)
+    hipLaunchKernelGGL(k_wstage_planes<2>, grid, dim3(256), 0, st, (const __bf16*)T1, sT1, wf, DH, Dl, Dr, (__bf16*)T2,
+                       sT2, kp3);
+  else
+    hipLaunchKernelGGL(k_wstage_planes<3>, grid, dim3(256), 0, st, (const __bf16*)T1, sT1, wf, DH, Dl, Dr, (__bf16*)T2,
+                       sT2, kp3);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+void launch_split_rows(const double* x, long long rows, int K, long long ldx, void* out, long long ldo,
+                       long long plane, int precision, hipStream_t st) {
+  TT_REQUIRE(precision == TT_BF16X3 || precision == TT_BF16X6, TT_EINVAL, "split: split-BF16 precisions only");
+  TT_REQUIRE(ldo >= K && ldx >= K, TT_EINVAL, "split: rows shorter than K");
+  const long long n = rows * ldo;
+  if (n <= 0) return;
+  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 16384);
+  if (precision == TT_BF16X3)
+    hipLaunchKernelGGL(k_split_rows<2>, dim3(blocks), dim3(256), 0, st, x, rows, K, ldx, (__bf16*)out, ldo, plane);
+  else
+    hipLaunchKernelGGL(k_split_rows<3>, dim3(blocks), dim3(256), 0, st, x, rows, K, ldx, (__bf16*)out, ldo, plane);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+void launch_split_t(const double* x, int K, int C, void* out, long long ldo, long long plane, int precision,
+                    hipStream_t st) {
+  TT_REQUIRE(precision == TT_BF16X3 || precision == TT_BF16X6, TT_EINVAL, "split: split-BF16 precisions only");
+  TT_REQUIRE(ldo >= K && K >= 1 && C >= 1, TT_EINVAL, "split: bad shape");
+  const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((ldo + 31) / 32));
+  if (precision == TT_BF16X3)
+    hipLaunchKernelGGL(k_split_t<2>, grid, dim3(256), 0, st, x, K, C, (__bf16*)out, ldo, plane);
+  else
+    hipLaunchKernelGGL(k_split_t<3>, grid, dim3(256), 0, st, x, K, C, (__bf16*)out, ldo, plane);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+}  // namespace tt

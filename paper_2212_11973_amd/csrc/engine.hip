@@ -1905,6 +1905,8 @@ struct HeffPlans {
   long long t1 = 0, t2 = 0, pw = 1;
 };
 
+GemmPlan heff_wstage_plan(int Dl, int Dr, int DH, long long t2row, SiteTables& tabs);
+
 HeffPlans heff_plans(int Dl, int Dr, int DH) {
   HeffPlans h;
   Bond bl, br;
@@ -1916,7 +1918,19 @@ HeffPlans heff_plans(int Dl, int Dr, int DH) {
   // an all-zero W keeps the sparse W-stage plan empty
   std::vector<double> Wz((size_t)DH * 16 * DH, 0.0);
   h.plan = build_site_plan(0, bl, br, G, qh, qh, Wz, Wz, h.tabs, false, false);
-  // W stage as GEMMs: for each (x, sigma'): T2[(so,b)][y] = sum_(a,si) W[(so,b),(a,si)] T1[(a,si)][y]
+  h.wg = heff_wstage_plan(Dl, Dr, DH, (long long)DH * Dr, h.tabs);
+  for (GemmPlan* g : {&h.plan.s1, &h.plan.s3, &h.wg}) tile_plan(*g, &h.tabs.host);
+  h.t1 = h.plan.t1_size;
+  h.t2 = h.plan.t2_size;
+  h.pw = std::max(std::max(h.plan.s1.pws_size, h.plan.s3.pws_size), std::max(h.wg.pws_size, 1LL));
+  return h;
+}
+
+// The W stage of the dense apply as grouped GEMMs, one per (x', sigma'):
+// T2[(x', so, sp)][(b, y)] = sum_(a, si) W[a, so, si, b] T1[a][x'][si][sp][y],
+// rows of T2 t2row elements apart (its index tables go into tabs)
+GemmPlan heff_wstage_plan(int Dl, int Dr, int DH, long long t2row, SiteTables& tabs) {
+  GemmPlan wg;
   std::vector<long long> am, ak, bk, cm;
   for (int so = 0; so < 4; ++so)
     for (int b = 0; b < DH; ++b) am.push_back((long long)so * 4 * DH + b);
@@ -1926,9 +1940,9 @@ HeffPlans heff_plans(int Dl, int Dr, int DH) {
       bk.push_back((long long)a * Dl * 16 * Dr + (long long)si * 4 * Dr);
     }
   for (int so = 0; so < 4; ++so)
-    for (int b = 0; b < DH; ++b) cm.push_back((long long)4 * so * DH * Dr + (long long)b * Dr);
-  long long tam = h.tabs.add(am), tak = h.tabs.add(ak), tbk = h.tabs.add(bk), tcm = h.tabs.add(cm);
-  h.wg.tag = TAG_WGEMM;
+    for (int b = 0; b < DH; ++b) cm.push_back((long long)4 * so * t2row + (long long)b * Dr);
+  long long tam = tabs.add(am), tak = tabs.add(ak), tbk = tabs.add(bk), tcm = tabs.add(cm);
+  wg.tag = TAG_WGEMM;
   for (int x = 0; x < Dl; ++x)
     for (int sp = 0; sp < 4; ++sp) {
       GemmProb g{};
@@ -1937,16 +1951,12 @@ HeffPlans heff_plans(int Dl, int Dr, int DH) {
       g.tam = tam; g.tak = tak; g.tbk = tbk; g.tbn = -1; g.tcm = tcm;
       g.sbn = 1;
       g.offB = (long long)x * 16 * Dr + (long long)sp * Dr;
-      g.offC = ((long long)x * 16 + sp) * DH * Dr;
+      g.offC = ((long long)x * 16 + sp) * t2row;
       g.alpha = 1.0; g.beta = 0.0;
-      h.wg.probs.push_back(g);
-      h.wg.flops += 2.0 * g.M * (double)g.N * g.K;
+      wg.probs.push_back(g);
+      wg.flops += 2.0 * g.M * (double)g.N * g.K;
     }
-  for (GemmPlan* g : {&h.plan.s1, &h.plan.s3, &h.wg}) tile_plan(*g, &h.tabs.host);
-  h.t1 = h.plan.t1_size;
-  h.t2 = h.plan.t2_size;
-  h.pw = std::max(std::max(h.plan.s1.pws_size, h.plan.s3.pws_size), std::max(h.wg.pws_size, 1LL));
-  return h;
+  return wg;
 }
 
 struct HeffCache {
@@ -1956,11 +1966,14 @@ struct HeffCache {
   GemmPlan wg;
   double *T1 = nullptr, *T2 = nullptr, *pws = nullptr;
   long long t1 = 0, t2 = 0, pw = 0;
-  // split-BF16 modes: the three launches unsplit in K, and the operands and
-  // intermediates as BF16 planes (up to three parts each)
-  GemmPlan s1p, wgp, s3p;
+  // split-BF16 modes: L.A and .R by the large-tile BF16 GEMM on operands
+  // split (and padded in K) into BF16 planes, the W stage (wgq: T2 rows padded
+  // to kp3) by the grouped GEMM on planes; every intermediate as planes
+  GemmPlan wgq;
+  int kp1 = 0, kp3 = 0;
   void* planes = nullptr;
   long long plane_bytes = 0;
+  long long planes_key = -1;   // the layout whose T2 padding is known to be zero
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
 };
@@ -1979,12 +1992,15 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   upload_plan(c.plan.s1, &c.tabs.host, st);
   upload_plan(c.plan.s3, &c.tabs.host, st);
   upload_plan(c.wg, &c.tabs.host, st);
-  free_plan(c.s1p); free_plan(c.wgp); free_plan(c.s3p);
-  c.s1p = c.plan.s1; c.wgp = c.wg; c.s3p = c.plan.s3;
-  for (GemmPlan* g : {&c.s1p, &c.wgp, &c.s3p}) {
-    g->no_split = true;
-    upload_plan(*g, &c.tabs.host, st);
-  }
+  free_plan(c.wgq);
+  c.kp1 = bgemm_kpad(Dl);
+  c.kp3 = bgemm_kpad((long long)DH * Dr);
+  c.wgq = heff_wstage_plan(Dl, Dr, DH, c.kp3, c.tabs);
+  c.wgq.no_split = true;
+  dfree(c.tabs.dev);
+  c.tabs.dev = upload(c.tabs.host, st);
+  upload_plan(c.wgq, &c.tabs.host, st);
+  c.planes_key = -1;
   if (h.t1 > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * h.t1); c.t1 = h.t1; }
   if (h.t2 > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * h.t2); c.t2 = h.t2; }
   if (h.pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * h.pw); c.pw = h.pw; }
@@ -2721,38 +2737,62 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
     hipStream_t st = ST();
     if (precision == TT_BF16X3 || precision == TT_BF16X6) {
       // split-BF16: every operand split once into BF16 planes (the split of L
-      // and A counted with L.A, of W with the W stage, of R with .R), the
-      // intermediates written as planes by the tiles that produce them
+      // and A counted with L.A, of W with the W stage, of R with .R), rows
+      // contiguous in the contracted index and zero-padded to the GEMM's K
+      // tile; the intermediates written as planes by the launches that
+      // produce them.  Layouts (element offsets inside one plane):
+      //   Lp[(x', a)][kp1]  = L[x'][a][x]          At[(s, y)][kp1] = A[x][s][y]
+      //   T1[a][x'][s][y]   (the layout of the FP64 path)
+      //   T2[(x', s)][kp3]  = T2[x'][s][b][y]      Rp[y'][kp3]     = R[y'][b][y]
       const int np = precision == TT_BF16X3 ? 2 : 3;
-      const long long nL = (long long)Dl * DH * Dl, nA = (long long)Dl * 16 * Dr, nW = (long long)DH * 16 * DH,
-                      nR = (long long)Dr * DH * Dr;
-      const long long need = 2LL * np * (nL + nA + nW + nR + c.t1 + c.t2) + 6 * 256;
+      const long long M1 = (long long)Dl * DH, N1 = 16LL * Dr, K3 = (long long)DH * Dr;
+      auto pl = [](long long n) { return (n + 127) / 128 * 128; };   // plane strides: 256-byte multiples
+      const long long sL = pl(M1 * c.kp1), sA = pl(N1 * c.kp1), sW = pl((long long)DH * 16 * DH),
+                      sR = pl((long long)Dr * c.kp3), sT1 = pl(c.t1), sT2 = pl(16LL * Dl * c.kp3);
+      const long long need = 2LL * np * (sL + sA + sW + sR + sT1 + sT2);
       if (need > c.plane_bytes) {
         dfree(c.planes);
         c.planes = nullptr;
         c.planes = dalloc(need);
         c.plane_bytes = need;
+        c.planes_key = -1;
       }
       char* base = static_cast<char*>(c.planes);
       long long off = 0;
-      auto carve = [&](long long n) { char* q = base + off; off += ((2LL * np * n + 255) / 256) * 256; return (double*)q; };
-      double *Lp = carve(nL), *Ap = carve(nA), *Wp = carve(nW), *Rp = carve(nR), *T1p = carve(c.t1), *T2p = carve(c.t2);
+      auto carve = [&](long long n) { __bf16* q = reinterpret_cast<__bf16*>(base + off); off += 2LL * np * n; return q; };
+      __bf16 *Lp = carve(sL), *Ap = carve(sA), *Wp = carve(sW), *Rp = carve(sR), *T1p = carve(sT1), *T2p = carve(sT2);
+      const long long key = (((long long)Dl * 65536 + Dr) * 4096 + DH) * 4 + np;
+      if (c.planes_key != key) {   // the K padding of T2's rows, which the W stage never writes
+        HIPX(hipMemsetAsync(T2p, 0, 2LL * np * sT2, st));
+        c.planes_key = key;
+      }
       HIPX(hipEventRecord(c.ev[0], st));
-      launch_split(L, nL, Lp, nL, precision, st);
-      launch_split(A, nA, Ap, nA, precision, st);
-      Planes p1;
-      p1.s[0] = nL; p1.s[1] = nA; p1.s[2] = c.t1; p1.c = 1;
-      launch_gemm_planes(c.s1p, c.tabs.dev, Slots{{Lp, Ap, T1p, nullptr}}, p1, precision, st);
+      launch_split_rows(L, M1, Dl, Dl, Lp, c.kp1, sL, precision, st);
+      launch_split_t(A, Dl, (int)N1, Ap, c.kp1, sA, precision, st);
+      BgArgs g1{};
+      g1.A = Lp; g1.lda = c.kp1; g1.sa = sL;
+      g1.B = Ap; g1.ldb = c.kp1; g1.sb = sA;
+      g1.M = (int)M1; g1.N = (int)N1; g1.K = c.kp1;
+      g1.C = T1p; g1.cdiv = DH; g1.ldc0 = (long long)Dl * N1; g1.ldc1 = N1; g1.sc = sT1; g1.cplanes = 1;
+      launch_bgemm(g1, precision, st);
       HIPX(hipEventRecord(c.ev[1], st));
-      launch_split(W, nW, Wp, nW, precision, st);
-      Planes p2;
-      p2.s[0] = nW; p2.s[1] = c.t1; p2.s[2] = c.t2; p2.c = 1;
-      launch_gemm_planes(c.wgp, c.tabs.dev, Slots{{Wp, T1p, T2p, nullptr}}, p2, precision, st);
+      if (DH <= wstage_planes_max_dh()) {   // FP32 vector kernel, bound by the planes' traffic
+        launch_wstage_planes(T1p, sT1, W, reinterpret_cast<float*>(Wp), DH, Dl, Dr, T2p, sT2, c.kp3, precision, st);
+      } else {                               // grouped GEMMs on W split into planes
+        launch_split(W, (long long)DH * 16 * DH, Wp, sW, precision, st);
+        Planes p2;
+        p2.s[0] = sW; p2.s[1] = sT1; p2.s[2] = sT2; p2.c = 1;
+        launch_gemm_planes(c.wgq, c.tabs.dev, Slots{{(double*)Wp, (double*)T1p, (double*)T2p, nullptr}}, p2,
+                           precision, st);
+      }
       HIPX(hipEventRecord(c.ev[2], st));
-      launch_split(R, nR, Rp, nR, precision, st);
-      Planes p3;
-      p3.s[0] = c.t2; p3.s[1] = nR;
-      launch_gemm_planes(c.s3p, c.tabs.dev, Slots{{T2p, Rp, out, nullptr}}, p3, precision, st);
+      launch_split_rows(R, Dr, (int)K3, K3, Rp, c.kp3, sR, precision, st);
+      BgArgs g3{};
+      g3.A = T2p; g3.lda = c.kp3; g3.sa = sT2;
+      g3.B = Rp; g3.ldb = c.kp3; g3.sb = sR;
+      g3.M = 16 * Dl; g3.N = Dr; g3.K = c.kp3;
+      g3.C = out; g3.cdiv = 16 * Dl; g3.ldc0 = Dr; g3.ldc1 = 0; g3.sc = 0; g3.cplanes = 0;
+      launch_bgemm(g3, precision, st);
       HIPX(hipEventRecord(c.ev[3], st));
     } else {
       HIPX(hipEventRecord(c.ev[0], st));

@@ -69,6 +69,33 @@ void launch_gemm_planes(const GemmPlan& p, const long long* d_tabs, const Slots&
                         hipStream_t st);
 // the BF16 parts of n doubles into planes pstride elements apart
 void launch_split(const double* x, long long n, void* out, long long pstride, int precision, hipStream_t st);
+
+// Large-tile split-BF16 GEMM of dense operands (the dense apply's L.A and .R):
+// C(m, n) = sum_k A(m, k) B(n, k) with A(m, k) = A[p sa + m lda + k] and
+// B(n, k) = B[p sb + n ldb + k] for the BF16 planes p, K a multiple of 32
+// (rows zero-padded), results at C + (m / cdiv) ldc1 + (m % cdiv) ldc0 + n,
+// as FP64 or (cplanes) as BF16 planes sc elements apart.
+struct BgArgs {
+  const __bf16* A; long long lda, sa;
+  const __bf16* B; long long ldb, sb;
+  int M, N, K;
+  void* C; long long ldc0, ldc1, sc; int cdiv, cplanes;
+  int tiles_m, tiles_n;   // set by the launcher
+};
+int bgemm_kpad(long long K);   // K rounded up to the GEMM's K tile
+void launch_bgemm(BgArgs a, int precision, hipStream_t st);
+// the dense apply's W stage on BF16 planes (layouts of tt_heff_apply's split-BF16
+// path: T1[a][x'][s][y], T2 rows (x', s) kp3 apart); wf: 16 DH^2 floats of scratch
+// for W; DH at most wstage_planes_max_dh()
+int wstage_planes_max_dh();
+void launch_wstage_planes(const void* T1, long long sT1, const double* W, float* wf, int DH, int Dl, int Dr, void* T2,
+                          long long sT2, long long kp3, int precision, hipStream_t st);
+// out[p plane + r ldo + k] = part p of x[r ldx + k] (k < K), zero up to ldo
+void launch_split_rows(const double* x, long long rows, int K, long long ldx, void* out, long long ldo,
+                       long long plane, int precision, hipStream_t st);
+// out[p plane + c ldo + k] = part p of x[k C + c] (k < K), zero up to ldo
+void launch_split_t(const double* x, int K, int C, void* out, long long ldo, long long plane, int precision,
+                    hipStream_t st);
 // the fused one-site apply LW . x . R of every state of the batch (slots:
 // 0 = LW, 1 = input site vector, 2 = R env, 3 = output site vector)
 void launch_fused(const FzPlan& p, const BSlots& s, int nb, hipStream_t st);
