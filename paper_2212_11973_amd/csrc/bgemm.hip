@@ -30,14 +30,27 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
 
+#ifndef TT_BG_FOLD
+#define TT_BG_FOLD 8
+#endif
+#ifndef TT_BG_GROUP_M
+#define TT_BG_GROUP_M 8
+#endif
+#ifndef TT_BG_STAGES2
+#define TT_BG_STAGES2 2
+#endif
+#ifndef TT_BG_WPE2
+#define TT_BG_WPE2 2
+#endif
 constexpr int kBM = 128, kBN = 128, kBK = 32;
 constexpr int kRowBytes = kBK * 2;             // one LDS row of one plane
-constexpr int kFold = 8;                       // K tiles between FP64 folds
-constexpr int kGroupM = 8;                     // tile rows per raster group
+constexpr int kFold = TT_BG_FOLD;              // K tiles between FP64 folds
+constexpr int kGroupM = TT_BG_GROUP_M;         // tile rows per raster group
 
 template <int NP> struct BgTraits;
-template <> struct BgTraits<2> { static constexpr int S = 4; };
-template <> struct BgTraits<3> { static constexpr int S = 3; };
+// S: LDS stages (two workgroups per CU fit with x3's 2 x 32 KB); WPE: waves per SIMD
+template <> struct BgTraits<2> { static constexpr int S = TT_BG_STAGES2, WPE = TT_BG_WPE2; };
+template <> struct BgTraits<3> { static constexpr int S = 3, WPE = 1; };
 template <int NP> constexpr int bg_stage_bytes() { return NP * (kBM + kBN) * kRowBytes; }
 template <int NP> constexpr int bg_lds_bytes() { return BgTraits<NP>::S * bg_stage_bytes<NP>(); }
 
@@ -85,13 +98,34 @@ __device__ __forceinline__ void bg_issue(const BgArgs& g, char* lds, int st, int
   }
 }
 
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+// Products of one 32-deep K step for one output block: x3 takes 00, 01, 10
+// (smallest first), x6 also 02, 11, 20.
+template <int NP, typename ACC, typename MF>
+__device__ __forceinline__ ACC bg_products(const bf16x8_t (&a)[NP], const bf16x8_t (&b)[NP], ACC t, MF mf) {
+  if constexpr (NP == 3) {
+    t = mf(a[2], b[0], t);
+    t = mf(a[1], b[1], t);
+    t = mf(a[0], b[2], t);
+  }
+  t = mf(a[1], b[0], t);
+  t = mf(a[0], b[1], t);
+  t = mf(a[0], b[0], t);
+  return t;
+}
+
+// The 64 x 64 output of a wave as 2 x 2 blocks of the 32x32x16 MFMA: per
+// 16-deep step lane l supplies row (l % 32) of an A block and column (l % 32)
+// of a B block at k = 8 (l / 32) .. + 7; accumulator element v of a block sits
+// at row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bgemm(BgArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BgTraits<NP>::WPE, BgTraits<NP>::WPE))) void k_bgemm(BgArgs g) {
   extern __shared__ __attribute__((aligned(16))) char bg_lds[];
   constexpr int S = BgTraits<NP>::S;
   constexpr int LPS = 4 * NP;   // global_load_lds per wave per stage
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
+  const int r = lane & 31, h = lane >> 5;
 
   // XCD-contiguous block ranges, then a grouped raster (kGroupM tile rows)
   const int ntiles = g.tiles_m * g.tiles_n;
@@ -104,14 +138,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int m0 = tm * kBM, n0 = tn * kBN;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
-  double4_t acc[4][4];
-  float4_t part[4][4];
+  double acc[2][2][16];
+  float16_t part[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
-      part[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0;
+      part[i][j] = (float16_t){};
     }
 
   const int nk = g.K / kBK;
@@ -119,8 +154,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   for (int s = 0; s < S - 1; ++s)
     if (s < nk) bg_issue<NP>(g, bg_lds, s, s, m0, n0, wave, lane);
 
-  // read position of this lane's operand chunk q in rows r (+16 i)
-  const int rpos = r * kRowBytes + 16 * (q ^ ((r >> 2) & 3));
+  // read positions of this lane's chunk (2 s + h) of row r in the two 16-deep steps
+  const int rpos0 = r * kRowBytes + 16 * ((0 + h) ^ ((r >> 2) & 3));
+  const int rpos1 = r * kRowBytes + 16 * ((2 + h) ^ ((r >> 2) & 3));
+  auto mf = [](bf16x8_t x, bf16x8_t y, float16_t t) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, t, 0, 0, 0); };
   for (int kt = 0; kt < nk; ++kt) {
     // this wave's loads of tile kt are done once at most the later issued
     // stages are outstanding
@@ -134,52 +171,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     asm volatile("" ::: "memory");
     if (kt + S - 1 < nk) bg_issue<NP>(g, bg_lds, (kt + S - 1) % S, kt + S - 1, m0, n0, wave, lane);
     const char* base = bg_lds + (kt % S) * bg_stage_bytes<NP>();
-    bf16x8_t a[NP][4], b[NP][4];
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
+    for (int st = 0; st < 2; ++st) {
+      const int rp = st ? rpos1 : rpos0;
+      bf16x8_t a[2][NP], b[2][NP];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[p][i] = *reinterpret_cast<const bf16x8_t*>(base + (p * kBM + wm + 16 * i) * kRowBytes + rpos);
-        b[p][i] = *reinterpret_cast<const bf16x8_t*>(base + (NP * kBM + p * kBN + wn + 16 * i) * kRowBytes + rpos);
-      }
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float4_t t = part[i][j];
-        if constexpr (NP == 3) {
-          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], t, 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+          a[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (p * kBM + wm + 32 * i) * kRowBytes + rp);
+          b[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (NP * kBM + p * kBN + wn + 32 * i) * kRowBytes + rp);
         }
-        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], t, 0, 0, 0);
-        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], t, 0, 0, 0);
-        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], t, 0, 0, 0);
-        part[i][j] = t;
-      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) part[i][j] = bg_products<NP>(a[i], b[j], part[i][j], mf);
+    }
     if ((kt + 1) % kFold == 0 || kt + 1 == nk) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
-          part[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+          for (int v = 0; v < 16; ++v) acc[i][j][v] += (double)part[i][j][v];
+          part[i][j] = (float16_t){};
         }
     }
   }
 
-  // accumulator element v of a 16 x 16 block: row 4 (lane / 16) + v, column lane % 16
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int m = m0 + wm + 16 * i + 4 * q + v;
+    for (int v = 0; v < 16; ++v) {
+      const int m = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
       if (m >= g.M) continue;
       const long long row = (long long)(m / g.cdiv) * g.ldc1 + (long long)(m % g.cdiv) * g.ldc0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = n0 + wn + 16 * j + r;
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + wn + 32 * j + r;
         if (n >= g.N) continue;
         const double val = acc[i][j][v];
         if (g.cplanes) {
