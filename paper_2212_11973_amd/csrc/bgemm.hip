@@ -282,6 +282,12 @@ __global__ __launch_bounds__(256) void k_wstage_planes(const __bf16* __restrict_
   __syncthreads();
   const int x = blockIdx.y >> 2, sp = blockIdx.y & 3;
   const int y = blockIdx.x * 256 + threadIdx.x;
+  const long long used = (long long)DH * Dr;
+  if (y < kp3 - used)   // the K padding of this (x', sp)'s four T2 rows
+#pragma unroll
+    for (int so = 0; so < 4; ++so)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) T2[p * sT2 + (long long)(16 * x + 4 * so + sp) * kp3 + used + y] = (__bf16)0.f;
   if (y >= Dr) return;
   float acc[kWsMaxO];
 #pragma unroll
@@ -329,6 +335,171 @@ __global__ void k_w_float(const double* __restrict__ W, int DH, float* __restric
   }
 }
 
+// ------------------------------------------------------------------ FP64
+// The same tiling for FP64 operands (the FP64 dense apply): K tiles of 16
+// doubles, an LDS row of 128 bytes (eight 16-byte chunks) with chunk c of row r
+// at position c ^ ((r >> 1) & 7), which keeps the 16 rows x 4 k of an f64 MFMA
+// operand read conflict-free; each wave 4 x 4 blocks of the f64 MFMA 16x16x4
+// (lane (r, g) supplies row r at k = g; accumulator element v at row g + 4 v,
+// column r).  Two stages of 32 KB: two workgroups per CU.
+constexpr int kDBK = 16, kDRowBytes = kDBK * 8, kDS = 2;
+constexpr int kDStage = (kBM + kBN) * kDRowBytes;
+
+__device__ __forceinline__ void dg_issue(const DgArgs& g, char* lds, int st, int kt, int m0, int n0, int wave,
+                                         int lane) {
+  char* base = lds + st * kDStage;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {   // 8 rows x 8 chunks per instruction: lane l -> row l / 8, position l % 8
+    const int row = 32 * wave + 8 * j + (lane >> 3);
+    const int lc = (lane & 7) ^ ((row >> 1) & 7);
+    const long long k = (long long)kt * kDBK + 2 * lc;
+    const int ma = min(m0 + row, g.M - 1), nb = min(n0 + row, g.N - 1);
+    char* la = base + (32 * wave + 8 * j) * kDRowBytes;
+    char* lb = base + (kBM + 32 * wave + 8 * j) * kDRowBytes;
+    __builtin_amdgcn_global_load_lds((const void*)(g.A + (long long)ma * g.lda + k), (lds_void*)la, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(g.B + (long long)nb * g.ldb + k), (lds_void*)lb, 16, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dgemm(DgArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char dg_lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int blk = bg_xcd_block(blockIdx.x, ntiles);
+  const int per_group = kGroupM * g.tiles_n;
+  const int grp = blk / per_group, first = grp * kGroupM;
+  const int gsz = min(g.tiles_m - first, kGroupM);
+  const int in = blk - grp * per_group;
+  const int tm = first + in % gsz, tn = in / gsz;
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  double4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  const int nk = g.K / kDBK;
+  if (nk > 0) dg_issue(g, dg_lds, 0, 0, m0, n0, wave, lane);
+  // this lane's operand element of step t (k = 4 t + q): chunk 2 t + q / 2, half q % 2
+  const int rsw = (r >> 1) & 7;
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));   // this wave's loads of tile kt
+    // every wave's loads of tile kt landed and the other stage is read (a bare
+    // barrier: a fenced one waits the same way; memory accesses kept on their side)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kt + 1 < nk) dg_issue(g, dg_lds, (kt + 1) & 1, kt + 1, m0, n0, wave, lane);
+    const char* base = dg_lds + (kt & 1) * kDStage;
+#pragma unroll
+    for (int t = 0; t < kDBK / 4; ++t) {
+      const int off = r * kDRowBytes + 16 * ((2 * t + (q >> 1)) ^ rsw) + 8 * (q & 1);
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = *reinterpret_cast<const double*>(base + (wm + 16 * i) * kDRowBytes + off);
+        b[i] = *reinterpret_cast<const double*>(base + (kBM + wn + 16 * i) * kDRowBytes + off);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm + 16 * i + q + 4 * v;
+      if (m >= g.M) continue;
+      const long long row = (long long)(m / g.cdiv) * g.ldc1 + (long long)(m % g.cdiv) * g.ldc0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn + 16 * j + r;
+        if (n < g.N) g.C[row + n] = acc[i][j][v];
+      }
+    }
+}
+
+// out[r * ldo + k] = x[r * ldx + k] for k < K, zero for K <= k < ldo
+__global__ __launch_bounds__(256) void k_pad_rows(const double* __restrict__ x, long long rows, int K, long long ldx,
+                                                 double* __restrict__ out, long long ldo) {
+  const long long n = rows * ldo;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const long long rr = e / ldo, k = e - rr * ldo;
+    out[e] = k < K ? x[rr * ldx + k] : 0.0;
+  }
+}
+
+// out[c * ldo + k] = x[k * C + c] for k < K, zero for K <= k < ldo (32 x 32 tiles through LDS)
+__global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int K, int C, double* __restrict__ out,
+                                              long long ldo) {
+  __shared__ double t[32][33];
+  const int k0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = k0 + ty + 8 * i, c = c0 + tx;
+    t[ty + 8 * i][tx] = (k < K && c < C) ? x[(long long)k * C + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = c0 + ty + 8 * i, k = k0 + tx;
+    if (c < C && k < ldo) out[(long long)c * ldo + k] = t[tx][ty + 8 * i];
+  }
+}
+
+// The dense apply's W stage in FP64 on the vector units (layouts of the FP64
+// path: T1[a][x'][s][y], T2 rows (x', s) kp3 apart, their K padding written as
+// zeros here); W staged in LDS as wl[4 a + si][DH so + b].
+__global__ __launch_bounds__(256) void k_wstage_f64(const double* __restrict__ T1, const double* __restrict__ W, int DH,
+                                                   int Dl, int Dr, double* __restrict__ T2, long long kp3) {
+  __shared__ __attribute__((aligned(16))) double wl[kWsMaxO * kWsMaxO];
+  const int KO = 4 * DH;
+  for (int e = threadIdx.x; e < KO * KO; e += 256) {
+    const int k = e / KO, o = e - k * KO;
+    const int a = k >> 2, si = k & 3, so = o / DH, b = o - so * DH;
+    wl[k * kWsMaxO + o] = W[((a * 4 + so) * 4 + si) * DH + b];
+  }
+  __syncthreads();
+  const int x = blockIdx.y >> 2, sp = blockIdx.y & 3;
+  const int y = blockIdx.x * 256 + threadIdx.x;
+  const long long used = (long long)DH * Dr;
+  if (y < kp3 - used)
+#pragma unroll
+    for (int so = 0; so < 4; ++so) T2[(long long)(16 * x + 4 * so + sp) * kp3 + used + y] = 0.0;
+  if (y >= Dr) return;
+  double acc[kWsMaxO];
+#pragma unroll
+  for (int o = 0; o < kWsMaxO; ++o) acc[o] = 0.0;
+  const long long N1 = 16LL * Dr;
+  const double* t1 = T1 + (long long)x * N1 + (long long)sp * Dr + y;
+  for (int a = 0; a < DH; ++a)
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      const double t = t1[(long long)a * Dl * N1 + (long long)si * 4 * Dr];
+      const double* wr = wl + (4 * a + si) * kWsMaxO;
+#pragma unroll
+      for (int o = 0; o < kWsMaxO; o += 2)
+        if (o < KO) {
+          const double2 w = *reinterpret_cast<const double2*>(wr + o);
+          acc[o] += w.x * t;
+          acc[o + 1] += w.y * t;
+        }
+    }
+  double* t2 = T2 + (long long)(16 * x + sp) * kp3 + y;
+#pragma unroll
+  for (int o = 0; o < kWsMaxO; ++o)
+    if (o < KO) {
+      const int so = o / DH, b = o - so * DH;
+      t2[(long long)(4 * so) * kp3 + (long long)b * Dr] = acc[o];
+    }
+}
+
 template <int NP>
 void bgemm_np(const BgArgs& a, hipStream_t st) {
   static bool attr = false;
@@ -367,7 +538,8 @@ int wstage_planes_max_dh() { return kWsMaxO / 4; }
 void launch_wstage_planes(const void* T1, long long sT1, const double* W, float* wf, int DH, int Dl, int Dr, void* T2,
                           long long sT2, long long kp3, int precision, hipStream_t st) {
   TT_REQUIRE(precision == TT_BF16X3 || precision == TT_BF16X6, TT_EINVAL, "W stage: split-BF16 precisions only");
-  TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && 4LL * Dl < 65536 && kp3 >= (long long)DH * Dr,
+  TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && 4LL * Dl < 65536 && kp3 >= (long long)DH * Dr &&
+                 kp3 - (long long)DH * Dr <= 256,
              TT_EINVAL, "W stage: shape out of range");
   hipLaunchKernelGGL(k_w_float, dim3(8), dim3(256), 0, st, W, DH, wf);
   ++g_launches;
@@ -378,6 +550,62 @@ void launch_wstage_planes(const void* T1, long long sT1, const double* W, float*
   else
     hipLaunchKernelGGL(k_wstage_planes<3>, grid, dim3(256), 0, st, (const __bf16*)T1, sT1, wf, DH, Dl, Dr, (__bf16*)T2,
                        sT2, kp3);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+int dgemm_kpad(long long K) { return (int)((K + kDBK - 1) / kDBK * kDBK); }
+
+void launch_dgemm(DgArgs a, hipStream_t st) {
+  TT_REQUIRE(a.M >= 1 && a.N >= 1 && a.K >= kDBK && a.K % kDBK == 0, TT_EINVAL,
+             "dgemm: K must be a positive multiple of 16");
+  TT_REQUIRE(a.lda >= a.K && a.ldb >= a.K && a.lda % 2 == 0 && a.ldb % 2 == 0 && a.cdiv >= 1, TT_EINVAL,
+             "dgemm: operand rows must hold K and start 16-byte aligned");
+  TT_REQUIRE(((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0, TT_EINVAL, "dgemm: operands not 16-byte aligned");
+  a.tiles_m = (a.M + kBM - 1) / kBM;
+  a.tiles_n = (a.N + kBN - 1) / kBN;
+  TT_REQUIRE((long long)a.tiles_m * a.tiles_n < (1LL << 31), TT_EINVAL, "dgemm: too many tiles");
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_dgemm, hipFuncAttributeMaxDynamicSharedMemorySize, kDS * kDStage) !=
+        hipSuccess)
+      throw Error(TT_EDEVICE, "cannot set the LDS limit of the FP64 GEMM");
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_dgemm, dim3(a.tiles_m * a.tiles_n), dim3(256), kDS * kDStage, st, a);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+void launch_pad_rows(const double* x, long long rows, int K, long long ldx, double* out, long long ldo, hipStream_t st) {
+  TT_REQUIRE(ldo >= K && ldx >= K, TT_EINVAL, "pad: rows shorter than K");
+  const long long n = rows * ldo;
+  if (n <= 0) return;
+  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_pad_rows, dim3(blocks), dim3(256), 0, st, x, rows, K, ldx, out, ldo);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+void launch_pad_t(const double* x, int K, int C, double* out, long long ldo, hipStream_t st) {
+  TT_REQUIRE(ldo >= K && K >= 1 && C >= 1, TT_EINVAL, "pad: bad shape");
+  const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((ldo + 31) / 32));
+  hipLaunchKernelGGL(k_pad_t, grid, dim3(256), 0, st, x, K, C, out, ldo);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+void launch_wstage_f64(const double* T1, const double* W, int DH, int Dl, int Dr, double* T2, long long kp3,
+                       hipStream_t st) {
+  TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && 4LL * Dl < 65536 && kp3 >= (long long)DH * Dr &&
+                 kp3 - (long long)DH * Dr <= 256,
+             TT_EINVAL, "W stage: shape out of range");
+  const dim3 grid((unsigned)((Dr + 255) / 256), (unsigned)(4 * Dl));
+  hipLaunchKernelGGL(k_wstage_f64, grid, dim3(256), 0, st, T1, W, DH, Dl, Dr, T2, kp3);
   ++g_launches;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));

@@ -1959,6 +1959,50 @@ GemmPlan heff_wstage_plan(int Dl, int Dr, int DH, long long t2row, SiteTables& t
   return wg;
 }
 
+// The FP64 dense apply on the large-tile kernels: L and A copied into rows of
+// the contracted index zero-padded to the GEMM's K tile (A transposed), L.A
+// into T1[a][x'][s][y], the W stage on the vector units into T2 rows (x', s)
+// padded the same way (their padding written as zeros by it), R padded, .R.
+struct DenseF64Sizes {
+  int kq1 = 0, kq3 = 0;
+  long long lq = 0, aq = 0, rq = 0, t1 = 0, t2q = 0;
+};
+DenseF64Sizes dense_f64_sizes(int Dl, int Dr, int DH) {
+  DenseF64Sizes z;
+  z.kq1 = dgemm_kpad(Dl);
+  z.kq3 = dgemm_kpad((long long)DH * Dr);
+  z.lq = (long long)Dl * DH * z.kq1;
+  z.aq = 16LL * Dr * z.kq1;
+  z.rq = (long long)Dr * z.kq3;
+  z.t1 = (long long)Dl * DH * 16 * Dr;
+  z.t2q = 16LL * Dl * z.kq3;
+  return z;
+}
+bool dense_f64_applies(int DH) { return DH <= wstage_planes_max_dh(); }
+struct DenseF64Bufs { double *Lq, *Aq, *Rq, *T1, *T2q; };
+void dense_apply_f64(int Dl, int Dr, int DH, const double* L, const double* W, const double* A, const double* R,
+                     double* out, const DenseF64Bufs& b, const DenseF64Sizes& z, const hipEvent_t* ev, hipStream_t st) {
+  const long long M1 = (long long)Dl * DH, N1 = 16LL * Dr;
+  if (ev) HIPX(hipEventRecord(ev[0], st));
+  launch_pad_rows(L, M1, Dl, Dl, b.Lq, z.kq1, st);
+  launch_pad_t(A, Dl, (int)N1, b.Aq, z.kq1, st);
+  DgArgs g1{};
+  g1.A = b.Lq; g1.lda = z.kq1; g1.B = b.Aq; g1.ldb = z.kq1;
+  g1.M = (int)M1; g1.N = (int)N1; g1.K = z.kq1;
+  g1.C = b.T1; g1.cdiv = DH; g1.ldc0 = (long long)Dl * N1; g1.ldc1 = N1;
+  launch_dgemm(g1, st);
+  if (ev) HIPX(hipEventRecord(ev[1], st));
+  launch_wstage_f64(b.T1, W, DH, Dl, Dr, b.T2q, z.kq3, st);
+  if (ev) HIPX(hipEventRecord(ev[2], st));
+  launch_pad_rows(R, Dr, (int)((long long)DH * Dr), (long long)DH * Dr, b.Rq, z.kq3, st);
+  DgArgs g3{};
+  g3.A = b.T2q; g3.lda = z.kq3; g3.B = b.Rq; g3.ldb = z.kq3;
+  g3.M = 16 * Dl; g3.N = Dr; g3.K = z.kq3;
+  g3.C = out; g3.cdiv = 16 * Dl; g3.ldc0 = Dr; g3.ldc1 = 0;
+  launch_dgemm(g3, st);
+  if (ev) HIPX(hipEventRecord(ev[3], st));
+}
+
 struct HeffCache {
   int Dl = -1, Dr = -1, DH = -1;
   SitePlan plan;
@@ -1973,7 +2017,9 @@ struct HeffCache {
   int kp1 = 0, kp3 = 0;
   void* planes = nullptr;
   long long plane_bytes = 0;
-  long long planes_key = -1;   // the layout whose T2 padding is known to be zero
+  // FP64: padded copies of L, A, R and the padded T2 (T1 is the buffer above)
+  double* f64 = nullptr;
+  long long f64_doubles = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
 };
@@ -2000,7 +2046,6 @@ void build_heff_cache(int Dl, int Dr, int DH) {
   dfree(c.tabs.dev);
   c.tabs.dev = upload(c.tabs.host, st);
   upload_plan(c.wgq, &c.tabs.host, st);
-  c.planes_key = -1;
   if (h.t1 > c.t1) { dfree(c.T1); c.T1 = (double*)dalloc(8 * h.t1); c.t1 = h.t1; }
   if (h.t2 > c.t2) { dfree(c.T2); c.T2 = (double*)dalloc(8 * h.t2); c.t2 = h.t2; }
   if (h.pw > c.pw) { dfree(c.pws); c.pws = (double*)dalloc(8 * h.pw); c.pw = h.pw; }
@@ -2030,6 +2075,8 @@ struct NoAllocDev {
   GemmPlan s1, s3, wg;             // the same plans with device pointers into the scratch
   long long* tabs = nullptr;
   double *T1 = nullptr, *T2 = nullptr, *pws = nullptr;
+  double *Lq = nullptr, *Aq = nullptr, *Rq = nullptr;   // the FP64 path's padded copies
+  int Dl_pending = 0, Dr_pending = 0, DH_pending = 0;   // the sizes being laid out
 };
 NoAllocDev g_noalloc[kMaxDevices];
 
@@ -2050,8 +2097,12 @@ long long noalloc_layout(NoAllocDev& d, bool copy, hipStream_t st) {
       HIPX(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
   };
   HeffPlans& h = d.host;
+  const DenseF64Sizes z = dense_f64_sizes(d.Dl_pending, d.Dr_pending, d.DH_pending);
   d.T1 = reinterpret_cast<double*>(carve(8 * h.t1));
-  d.T2 = reinterpret_cast<double*>(carve(8 * h.t2));
+  d.T2 = reinterpret_cast<double*>(carve(8 * std::max(h.t2, z.t2q)));   // T2, or the FP64 path's padded T2
+  d.Lq = reinterpret_cast<double*>(carve(8 * z.lq));
+  d.Aq = reinterpret_cast<double*>(carve(8 * z.aq));
+  d.Rq = reinterpret_cast<double*>(carve(8 * z.rq));
   d.pws = reinterpret_cast<double*>(carve(8 * h.pw));
   put(d.tabs, h.tabs.host);
   GemmPlan* dev[3] = {&d.s1, &d.wg, &d.s3};
@@ -2755,17 +2806,11 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
         c.planes = nullptr;
         c.planes = dalloc(need);
         c.plane_bytes = need;
-        c.planes_key = -1;
       }
       char* base = static_cast<char*>(c.planes);
       long long off = 0;
       auto carve = [&](long long n) { __bf16* q = reinterpret_cast<__bf16*>(base + off); off += 2LL * np * n; return q; };
       __bf16 *Lp = carve(sL), *Ap = carve(sA), *Wp = carve(sW), *Rp = carve(sR), *T1p = carve(sT1), *T2p = carve(sT2);
-      const long long key = (((long long)Dl * 65536 + Dr) * 4096 + DH) * 4 + np;
-      if (c.planes_key != key) {   // the K padding of T2's rows, which the W stage never writes
-        HIPX(hipMemsetAsync(T2p, 0, 2LL * np * sT2, st));
-        c.planes_key = key;
-      }
       HIPX(hipEventRecord(c.ev[0], st));
       launch_split_rows(L, M1, Dl, Dl, Lp, c.kp1, sL, precision, st);
       launch_split_t(A, Dl, (int)N1, Ap, c.kp1, sA, precision, st);
@@ -2778,7 +2823,8 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
       HIPX(hipEventRecord(c.ev[1], st));
       if (DH <= wstage_planes_max_dh()) {   // FP32 vector kernel, bound by the planes' traffic
         launch_wstage_planes(T1p, sT1, W, reinterpret_cast<float*>(Wp), DH, Dl, Dr, T2p, sT2, c.kp3, precision, st);
-      } else {                               // grouped GEMMs on W split into planes
+      } else {   // grouped GEMMs on W split into planes; T2's K padding cleared first
+        launch_fill(reinterpret_cast<double*>(T2p), 0.0, (2LL * np * sT2) / 8, st);
         launch_split(W, (long long)DH * 16 * DH, Wp, sW, precision, st);
         Planes p2;
         p2.s[0] = sW; p2.s[1] = sT1; p2.s[2] = sT2; p2.c = 1;
@@ -2794,6 +2840,19 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
       g3.C = out; g3.cdiv = 16 * Dl; g3.ldc0 = Dr; g3.ldc1 = 0; g3.sc = 0; g3.cplanes = 0;
       launch_bgemm(g3, precision, st);
       HIPX(hipEventRecord(c.ev[3], st));
+    } else if (precision == TT_FP64 && dense_f64_applies(DH)) {
+      const DenseF64Sizes z = dense_f64_sizes(Dl, Dr, DH);
+      const long long need = z.lq + z.aq + z.rq + z.t2q + 4 * 32;
+      if (need > c.f64_doubles) {
+        dfree(c.f64);
+        c.f64 = nullptr;
+        c.f64 = (double*)dalloc(8 * need);
+        c.f64_doubles = need;
+      }
+      auto al = [](long long n) { return (n + 31) / 32 * 32; };   // 256-byte aligned pieces
+      DenseF64Bufs b{c.f64, c.f64 + al(z.lq), c.f64 + al(z.lq) + al(z.aq), c.T1,
+                     c.f64 + al(z.lq) + al(z.aq) + al(z.rq)};
+      dense_apply_f64(Dl, Dr, DH, L, W, A, R, out, b, z, c.ev, st);
     } else {
       HIPX(hipEventRecord(c.ev[0], st));
       launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}}), 1,
@@ -2839,6 +2898,7 @@ int tt_heff_apply_noalloc(int Dl, int Dr, int DH, const double* L, const double*
   if (d.Dl != Dl || d.Dr != Dr || d.DH != DH) {
     d.Dl = d.Dr = d.DH = -1;
     d.host = heff_plans(Dl, Dr, DH);
+    d.Dl_pending = Dl; d.Dr_pending = Dr; d.DH_pending = DH;
     const long long need = noalloc_layout(d, false, st);
     TT_REQUIRE(need <= kScratchBytes, TT_EINVAL,
                "tt_heff_apply_noalloc: the apply needs " + std::to_string(need) + " bytes of scratch, more than " +
@@ -2850,6 +2910,11 @@ int tt_heff_apply_noalloc(int Dl, int Dr, int DH, const double* L, const double*
   double* w = const_cast<double*>(W);
   double* a = const_cast<double*>(A);
   double* r = const_cast<double*>(R);
+  if (precision == TT_FP64 && dense_f64_applies(DH)) {   // the kernels of tt_heff_apply's FP64 path
+    DenseF64Bufs b{d.Lq, d.Aq, d.Rq, d.T1, d.T2};
+    dense_apply_f64(Dl, Dr, DH, L, W, A, R, out, b, dense_f64_sizes(Dl, Dr, DH), nullptr, st);
+    return TT_OK;
+  }
   launch_gemm(d.s1, d.tabs, one(Slots{{l, a, d.T1, nullptr}}), 1, precision, one(d.pws), st);
   launch_gemm(d.wg, d.tabs, one(Slots{{w, d.T1, d.T2, nullptr}}), 1, precision, one(d.pws), st);
   launch_gemm(d.s3, d.tabs, one(Slots{{d.T2, r, out, nullptr}}), 1, precision, one(d.pws), st);

@@ -90,6 +90,25 @@ void launch_bgemm(BgArgs a, int precision, hipStream_t st);
 int wstage_planes_max_dh();
 void launch_wstage_planes(const void* T1, long long sT1, const double* W, float* wf, int DH, int Dl, int Dr, void* T2,
                           long long sT2, long long kp3, int precision, hipStream_t st);
+// The FP64 large-tile GEMM of the dense apply: C(m, n) = sum_k A[m lda + k]
+// B[n ldb + k], K a multiple of 16 (rows zero-padded), results at
+// C + (m / cdiv) ldc1 + (m % cdiv) ldc0 + n.
+struct DgArgs {
+  const double* A; long long lda;
+  const double* B; long long ldb;
+  int M, N, K;
+  double* C; long long ldc0, ldc1; int cdiv;
+  int tiles_m, tiles_n;   // set by the launcher
+};
+int dgemm_kpad(long long K);   // K rounded up to the FP64 GEMM's K tile
+void launch_dgemm(DgArgs a, hipStream_t st);
+// out[r ldo + k] = x[r ldx + k] (k < K), zero up to ldo
+void launch_pad_rows(const double* x, long long rows, int K, long long ldx, double* out, long long ldo, hipStream_t st);
+// out[c ldo + k] = x[k C + c] (k < K), zero up to ldo
+void launch_pad_t(const double* x, int K, int C, double* out, long long ldo, hipStream_t st);
+// the dense apply's W stage in FP64 (T1[a][x'][s][y] -> T2 rows (x', s) kp3 apart)
+void launch_wstage_f64(const double* T1, const double* W, int DH, int Dl, int Dr, double* T2, long long kp3,
+                       hipStream_t st);
 // out[p plane + r ldo + k] = part p of x[r ldx + k] (k < K), zero up to ldo
 void launch_split_rows(const double* x, long long rows, int K, long long ldx, void* out, long long ldo,
                        long long plane, int precision, hipStream_t st);
