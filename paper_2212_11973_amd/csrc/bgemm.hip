@@ -17,6 +17,8 @@
 // 16 rows an MFMA operand read touches fall in distinct banks.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace tt {
@@ -264,76 +266,7 @@ __global__ __launch_bounds__(256) void k_split_t(const double* __restrict__ x, i
   }
 }
 
-// The W stage of the dense apply on BF16 planes, in FP32 on the vector units
-// (its 2 (4 DH)^2 flops per element move 4 NP bytes, so the planes' traffic
-// bounds it):  T2[(x', 4 so + sp)][b Dr + y] = sum_(a, si) W[a, so, si, b]
-// T1[a][x'][si][sp][y].  One thread per y; blockIdx.y = 4 x' + sp.  W comes as
-// floats wf[(4 a + si) (4 DH) + DH so + b], staged in LDS with rows padded to
-// kWsMaxO and read as broadcasts.
 constexpr int kWsMaxO = 80;   // 4 DH at most
-
-template <int NP>
-__global__ __launch_bounds__(256) void k_wstage_planes(const __bf16* __restrict__ T1, long long sT1,
-                                                       const float* __restrict__ wf, int DH, int Dl, int Dr,
-                                                       __bf16* __restrict__ T2, long long sT2, long long kp3) {
-  __shared__ __attribute__((aligned(16))) float wl[kWsMaxO * kWsMaxO];
-  const int KO = 4 * DH;
-  for (int e = threadIdx.x; e < KO * KO; e += 256) wl[(e / KO) * kWsMaxO + e % KO] = wf[e];
-  __syncthreads();
-  const int x = blockIdx.y >> 2, sp = blockIdx.y & 3;
-  const int y = blockIdx.x * 256 + threadIdx.x;
-  const long long used = (long long)DH * Dr;
-  if (y < kp3 - used)   // the K padding of this (x', sp)'s four T2 rows
-#pragma unroll
-    for (int so = 0; so < 4; ++so)
-#pragma unroll
-      for (int p = 0; p < NP; ++p) T2[p * sT2 + (long long)(16 * x + 4 * so + sp) * kp3 + used + y] = (__bf16)0.f;
-  if (y >= Dr) return;
-  float acc[kWsMaxO];
-#pragma unroll
-  for (int o = 0; o < kWsMaxO; ++o) acc[o] = 0.f;
-  const long long N1 = 16LL * Dr;
-  const __bf16* t1 = T1 + (long long)x * N1 + (long long)sp * Dr + y;
-  for (int a = 0; a < DH; ++a)
-#pragma unroll
-    for (int si = 0; si < 4; ++si) {
-      const __bf16* e = t1 + (long long)a * Dl * N1 + (long long)si * 4 * Dr;
-      float t = 0.f;   // the parts summed smallest first
-#pragma unroll
-      for (int p = NP - 1; p >= 0; --p) t += (float)e[p * sT1];
-      const float* wr = wl + (4 * a + si) * kWsMaxO;
-#pragma unroll
-      for (int o = 0; o < kWsMaxO; o += 4)
-        if (o < KO) {
-          const float4 w = *reinterpret_cast<const float4*>(wr + o);
-          acc[o] += w.x * t;
-          acc[o + 1] += w.y * t;
-          acc[o + 2] += w.z * t;
-          acc[o + 3] += w.w * t;
-        }
-    }
-  __bf16* t2 = T2 + (long long)(16 * x + sp) * kp3 + y;
-#pragma unroll
-  for (int o = 0; o < kWsMaxO; ++o)
-    if (o < KO) {
-      const int so = o / DH, b = o - so * DH;
-      __bf16 parts[3];
-      bg_split<NP>((double)acc[o], parts);
-      __bf16* c = t2 + (long long)(4 * so) * kp3 + (long long)b * Dr;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) c[p * sT2] = parts[p];
-    }
-}
-
-// wf[(4 a + si) (4 DH) + DH so + b] = W[a][so][si][b] as float
-__global__ void k_w_float(const double* __restrict__ W, int DH, float* __restrict__ wf) {
-  const int KO = 4 * DH;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < KO * KO; e += gridDim.x * blockDim.x) {
-    const int k = e / KO, o = e - k * KO;
-    const int a = k >> 2, si = k & 3, so = o / DH, b = o - so * DH;
-    wf[e] = (float)W[((a * 4 + so) * 4 + si) * DH + b];
-  }
-}
 
 // ------------------------------------------------------------------ FP64
 // The same tiling for FP64 operands (the FP64 dense apply): K tiles of 16
@@ -453,51 +386,99 @@ __global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int
   }
 }
 
-// The dense apply's W stage in FP64 on the vector units (layouts of the FP64
-// path: T1[a][x'][s][y], T2 rows (x', s) kp3 apart, their K padding written as
-// zeros here); W staged in LDS as wl[4 a + si][DH so + b].
-__global__ __launch_bounds__(256) void k_wstage_f64(const double* __restrict__ T1, const double* __restrict__ W, int DH,
-                                                   int Dl, int Dr, double* __restrict__ T2, long long kp3) {
-  __shared__ __attribute__((aligned(16))) double wl[kWsMaxO * kWsMaxO];
+// The dense apply's W stage on the matrix cores: for each (x', sp) the product
+// T2[(o = DH so + b)][y] = sum_(k = 4 a + si) W^T[o][k] T1[k][y] with W^T as
+// the A operand (from LDS: rows o padded to kWsMaxO with zeros) and T1 as the
+// B operand straight from memory (lane (r, g) takes k = 4 t + g, i.e. a = t,
+// si = g, at y = y0 + r: 128-byte rows), so the result rows o come out as
+// 128-byte runs of y.  NP = 0: FP64 T1 and T2 (f64 MFMA 16x16x4); NP = 2, 3:
+// BF16 planes, multiplied in FP32 (f32 MFMA 16x16x4, W rounded to FP32, the
+// parts of a T1 element summed smallest first).  T2's K padding is written as
+// zeros.  One workgroup per (x', sp); its four waves take every fourth block
+// of 16 y.
+template <int NP>
+__global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1v, long long sT1,
+                                                     const double* __restrict__ W, int DH, int Dl, int Dr,
+                                                     void* __restrict__ T2v, long long sT2, long long kp3) {
+  using E = typename std::conditional<NP == 0, double, float>::type;
+  using E4 = typename std::conditional<NP == 0, double4_t, float4_t>::type;
+  constexpr int OB = kWsMaxO / 16;
+  __shared__ E wl[kWsMaxO * kWsMaxO];   // wl[k][o]
   const int KO = 4 * DH;
-  for (int e = threadIdx.x; e < KO * KO; e += 256) {
-    const int k = e / KO, o = e - k * KO;
-    const int a = k >> 2, si = k & 3, so = o / DH, b = o - so * DH;
-    wl[k * kWsMaxO + o] = W[((a * 4 + so) * 4 + si) * DH + b];
+  for (int e = threadIdx.x; e < kWsMaxO * kWsMaxO; e += 256) {
+    const int k = e / kWsMaxO, o = e - k * kWsMaxO;
+    E v = 0;
+    if (k < KO && o < KO) {
+      const int a = k >> 2, si = k & 3, so = o / DH, b = o - so * DH;
+      v = (E)W[((a * 4 + so) * 4 + si) * DH + b];
+    }
+    wl[e] = v;
   }
-  __syncthreads();
-  const int x = blockIdx.y >> 2, sp = blockIdx.y & 3;
-  const int y = blockIdx.x * 256 + threadIdx.x;
+  const int x = blockIdx.x >> 2, sp = blockIdx.x & 3;
   const long long used = (long long)DH * Dr;
-  if (y < kp3 - used)
+  for (int y = threadIdx.x; y < kp3 - used; y += 256)   // the K padding of this (x', sp)'s four T2 rows
 #pragma unroll
-    for (int so = 0; so < 4; ++so) T2[(long long)(16 * x + 4 * so + sp) * kp3 + used + y] = 0.0;
-  if (y >= Dr) return;
-  double acc[kWsMaxO];
+    for (int so = 0; so < 4; ++so) {
+      const long long e = (long long)(16 * x + 4 * so + sp) * kp3 + used + y;
+      if constexpr (NP == 0) reinterpret_cast<double*>(T2v)[e] = 0.0;
+      else
 #pragma unroll
-  for (int o = 0; o < kWsMaxO; ++o) acc[o] = 0.0;
+        for (int p = 0; p < NP; ++p) reinterpret_cast<__bf16*>(T2v)[p * sT2 + e] = (__bf16)0.f;
+    }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  const int nob = (KO + 15) / 16;
   const long long N1 = 16LL * Dr;
-  const double* t1 = T1 + (long long)x * N1 + (long long)sp * Dr + y;
-  for (int a = 0; a < DH; ++a)
+  // this lane's B element for a = t: T1[t][x'][g][sp][y]
+  const long long base = (long long)x * N1 + (long long)g * 4 * Dr + (long long)sp * Dr;
+  const long long astep = (long long)Dl * N1;
+  for (int yb = wave; 16 * yb < Dr; yb += 4) {
+    const int y = 16 * yb + r, yc = min(y, Dr - 1);
+    E4 acc[OB];
 #pragma unroll
-    for (int si = 0; si < 4; ++si) {
-      const double t = t1[(long long)a * Dl * N1 + (long long)si * 4 * Dr];
-      const double* wr = wl + (4 * a + si) * kWsMaxO;
+    for (int ob = 0; ob < OB; ++ob) acc[ob] = (E4){0, 0, 0, 0};
+#pragma unroll 3
+    for (int t = 0; t < DH; ++t) {
+      const long long e = base + t * astep + yc;
+      E bv;
+      if constexpr (NP == 0) {
+        bv = reinterpret_cast<const double*>(T1v)[e];
+      } else {
+        const __bf16* t1 = reinterpret_cast<const __bf16*>(T1v);
+        float f = 0.f;
 #pragma unroll
-      for (int o = 0; o < kWsMaxO; o += 2)
-        if (o < KO) {
-          const double2 w = *reinterpret_cast<const double2*>(wr + o);
-          acc[o] += w.x * t;
-          acc[o + 1] += w.y * t;
+        for (int p = NP - 1; p >= 0; --p) f += (float)t1[p * sT1 + e];
+        bv = f;
+      }
+      const E* wr = wl + (4 * t + g) * kWsMaxO + r;
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob)
+        if (ob < nob) {
+          if constexpr (NP == 0) acc[ob] = __builtin_amdgcn_mfma_f64_16x16x4f64(wr[16 * ob], bv, acc[ob], 0, 0, 0);
+          else acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[16 * ob], bv, acc[ob], 0, 0, 0);
         }
     }
-  double* t2 = T2 + (long long)(16 * x + sp) * kp3 + y;
+    if (y >= Dr) continue;
 #pragma unroll
-  for (int o = 0; o < kWsMaxO; ++o)
-    if (o < KO) {
-      const int so = o / DH, b = o - so * DH;
-      t2[(long long)(4 * so) * kp3 + (long long)b * Dr] = acc[o];
-    }
+    for (int ob = 0; ob < OB; ++ob)
+      if (ob < nob)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // accumulator row: g + 4 v (f64 MFMA), 4 g + v (f32 MFMA)
+          const int o = 16 * ob + (NP == 0 ? g + 4 * v : 4 * g + v);
+          if (o >= KO) continue;
+          const int so = o / DH, b = o - so * DH;
+          const long long e = (long long)(16 * x + 4 * so + sp) * kp3 + (long long)b * Dr + y;
+          if constexpr (NP == 0) {
+            reinterpret_cast<double*>(T2v)[e] = acc[ob][v];
+          } else {
+            __bf16 parts[3];
+            bg_split<NP>((double)acc[ob][v], parts);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) reinterpret_cast<__bf16*>(T2v)[p * sT2 + e] = parts[p];
+          }
+        }
+  }
 }
 
 template <int NP>
@@ -535,21 +516,17 @@ void launch_bgemm(BgArgs a, int precision, hipStream_t st) {
 
 int wstage_planes_max_dh() { return kWsMaxO / 4; }
 
-void launch_wstage_planes(const void* T1, long long sT1, const double* W, float* wf, int DH, int Dl, int Dr, void* T2,
-                          long long sT2, long long kp3, int precision, hipStream_t st) {
+void launch_wstage_planes(const void* T1, long long sT1, const double* W, int DH, int Dl, int Dr, void* T2, long long sT2,
+                          long long kp3, int precision, hipStream_t st) {
   TT_REQUIRE(precision == TT_BF16X3 || precision == TT_BF16X6, TT_EINVAL, "W stage: split-BF16 precisions only");
   TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && 4LL * Dl < 65536 && kp3 >= (long long)DH * Dr &&
                  kp3 - (long long)DH * Dr <= 256,
              TT_EINVAL, "W stage: shape out of range");
-  hipLaunchKernelGGL(k_w_float, dim3(8), dim3(256), 0, st, W, DH, wf);
-  ++g_launches;
-  const dim3 grid((unsigned)((Dr + 255) / 256), (unsigned)(4 * Dl));
+  const dim3 grid((unsigned)(4 * Dl));
   if (precision == TT_BF16X3)
-    hipLaunchKernelGGL(k_wstage_planes<2>, grid, dim3(256), 0, st, (const __bf16*)T1, sT1, wf, DH, Dl, Dr, (__bf16*)T2,
-                       sT2, kp3);
+    hipLaunchKernelGGL(k_wstage_mfma<2>, grid, dim3(256), 0, st, T1, sT1, W, DH, Dl, Dr, T2, sT2, kp3);
   else
-    hipLaunchKernelGGL(k_wstage_planes<3>, grid, dim3(256), 0, st, (const __bf16*)T1, sT1, wf, DH, Dl, Dr, (__bf16*)T2,
-                       sT2, kp3);
+    hipLaunchKernelGGL(k_wstage_mfma<3>, grid, dim3(256), 0, st, T1, sT1, W, DH, Dl, Dr, T2, sT2, kp3);
   ++g_launches;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
@@ -604,8 +581,8 @@ void launch_wstage_f64(const double* T1, const double* W, int DH, int Dl, int Dr
   TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && 4LL * Dl < 65536 && kp3 >= (long long)DH * Dr &&
                  kp3 - (long long)DH * Dr <= 256,
              TT_EINVAL, "W stage: shape out of range");
-  const dim3 grid((unsigned)((Dr + 255) / 256), (unsigned)(4 * Dl));
-  hipLaunchKernelGGL(k_wstage_f64, grid, dim3(256), 0, st, T1, W, DH, Dl, Dr, T2, kp3);
+  const dim3 grid((unsigned)(4 * Dl));
+  hipLaunchKernelGGL(k_wstage_mfma<0>, grid, dim3(256), 0, st, (const void*)T1, 0LL, W, DH, Dl, Dr, (void*)T2, 0LL, kp3);
   ++g_launches;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));

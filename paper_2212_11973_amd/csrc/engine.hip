@@ -2822,7 +2822,7 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
       launch_bgemm(g1, precision, st);
       HIPX(hipEventRecord(c.ev[1], st));
       if (DH <= wstage_planes_max_dh()) {   // FP32 vector kernel, bound by the planes' traffic
-        launch_wstage_planes(T1p, sT1, W, reinterpret_cast<float*>(Wp), DH, Dl, Dr, T2p, sT2, c.kp3, precision, st);
+        launch_wstage_planes(T1p, sT1, W, DH, Dl, Dr, T2p, sT2, c.kp3, precision, st);
       } else {   // grouped GEMMs on W split into planes; T2's K padding cleared first
         launch_fill(reinterpret_cast<double*>(T2p), 0.0, (2LL * np * sT2) / 8, st);
         launch_split(W, (long long)DH * 16 * DH, Wp, sW, precision, st);

@@ -85,11 +85,11 @@ struct BgArgs {
 int bgemm_kpad(long long K);   // K rounded up to the GEMM's K tile
 void launch_bgemm(BgArgs a, int precision, hipStream_t st);
 // the dense apply's W stage on BF16 planes (layouts of tt_heff_apply's split-BF16
-// path: T1[a][x'][s][y], T2 rows (x', s) kp3 apart); wf: 16 DH^2 floats of scratch
-// for W; DH at most wstage_planes_max_dh()
+// path: T1[a][x'][s][y], T2 rows (x', s) kp3 apart, their K padding written as
+// zeros); DH at most wstage_planes_max_dh()
 int wstage_planes_max_dh();
-void launch_wstage_planes(const void* T1, long long sT1, const double* W, float* wf, int DH, int Dl, int Dr, void* T2,
-                          long long sT2, long long kp3, int precision, hipStream_t st);
+void launch_wstage_planes(const void* T1, long long sT1, const double* W, int DH, int Dl, int Dr, void* T2, long long sT2,
+                          long long kp3, int precision, hipStream_t st);
 // The FP64 large-tile GEMM of the dense apply: C(m, n) = sum_k A[m lda + k]
 // B[n ldb + k], K a multiple of 16 (rows zero-padded), results at
 // C + (m / cdiv) ldc1 + (m % cdiv) ldc0 + n.
