@@ -346,6 +346,78 @@ def measured_traffic(kernel, args):
     return float(vals[key]), os.path.basename(path)
 
 
+def heff_bench(args, T, WL, torch):
+    """The dense effective-Hamiltonian apply at D = --heff-D in each precision of
+    --heff-precisions (and the two-site generator at --heff2-D), timed with the
+    library's events per stage."""
+    # dense effective-Hamiltonian apply at D (microbenchmark)
+    heff = {}
+    Dh, DH = args.heff_D, 18
+    if Dh > 0:
+        L, W, A, R = WL.heff_inputs(Dh, DH)
+        dev = torch.device("cuda:0")
+        tl, tw, ta, tr = (torch.from_numpy(x).to(dev) for x in (L, W, A, R))
+        out = torch.empty_like(ta)
+        fl = 32.0 * DH * Dh * Dh * (2 * Dh) + 128.0 * DH * DH * Dh * Dh
+        sm = torch.cuda.current_stream().cuda_stream
+        # MFMA work per FP64-equivalent flop and the roof it runs against: the
+        # split-BF16 modes take 3 or 6 BF16 part products per product
+        heff_roof = dict(fp64=(1, PEAK["fp64"]), fp32=(1, PEAK["fp32"]), bf16x3=(3, PEAK["bf16"]),
+                         bf16x6=(6, PEAK["bf16"]))
+        ref64 = None
+        for pname in args.heff_precisions.split(","):
+            p = PREC[pname]
+            T.tt_heff_apply(Dh, Dh, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(), p, sm)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(args.heff_reps):
+                T.tt_heff_apply(Dh, Dh, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(),
+                                p, sm)
+                ms.append(T.tt_heff_last_timing())
+            med = statistics.median(x[3] for x in ms)
+            tf = fl / (med * 1e-3) / 1e12
+            mult, peak = heff_roof[pname]
+            heff[pname] = dict(ms=med, tflops=tf, applies_per_s=1e3 / med, mfma_tflops=tf * mult,
+                               frac_mfma_peak=tf * mult / peak, mfma_peak=peak,
+                               stage_ms=[statistics.median(x[i] for x in ms) for i in range(3)])
+            if pname == "fp64":
+                ref64 = out.clone()
+            elif ref64 is not None:   # the FP64 apply's result (itself held to 1e-12 of the oracle by the tests)
+                heff[pname]["rel_err_vs_fp64"] = (torch.linalg.norm(out - ref64) / torch.linalg.norm(ref64)).item()
+        if "fp64" in heff:
+            for pname in heff:
+                if pname != "fp64":
+                    heff[pname]["speedup_vs_fp64"] = heff["fp64"]["ms"] / heff[pname]["ms"]
+        del ref64
+        print("heff done", file=sys.stderr, flush=True)
+        del tl, tw, ta, tr, out
+    D2 = args.heff2_D
+    if D2 > 0:   # two-site generator: four grouped GEMMs (L.C, W1, W2, .R)
+        L, W1, W2, C2, R = WL.heff2_inputs(D2, D2, DH, 20221223)
+        dev = torch.device("cuda:0")
+        tt_ = [torch.from_numpy(x).to(dev) for x in (L, W1, W2, C2, R)]
+        out = torch.empty_like(tt_[3])
+        sm = torch.cuda.current_stream().cuda_stream
+        ptrs = [x.data_ptr() for x in tt_]
+        T.tt_heff2_apply(D2, D2, DH, *ptrs, out.data_ptr(), T.TT_FP64, sm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(args.heff_reps):
+            e0.record()
+            T.tt_heff2_apply(D2, D2, DH, *ptrs, out.data_ptr(), T.TT_FP64, sm)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        # flops of the contraction in the paper's order (L.C, W1, W2, .R)
+        fl2 = 2.0 * 256 * D2 ** 3 * DH + 2.0 * 2 * 16 * 4 * D2 * D2 * DH * DH * 16 + 2.0 * 256 * D2 ** 3 * DH
+        heff["two_site_fp64"] = dict(D=D2, ms=statistics.median(ms),
+                                     tflops=fl2 / (statistics.median(ms) * 1e-3) / 1e12)
+        print("heff2 done", file=sys.stderr, flush=True)
+        del tt_, out
+    return heff
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +441,8 @@ def main():
     ap.add_argument("--heff-D", type=int, default=2000)
     ap.add_argument("--heff-reps", type=int, default=5)
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
+    ap.add_argument("--heff-only", action="store_true",
+                    help="only the dense apply microbenchmark (--heff-D, --heff-precisions), one JSON line")
     ap.add_argument("--heff2-D", type=int, default=256,
                     help="also time the dense two-site 2-TDVP generator at this bond dimension (0: skip)")
     ap.add_argument("--tdvp2-sweeps", type=int, default=2,
@@ -427,6 +501,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.heff_only:
+        heff = heff_bench(args, T, WL, torch)
+        print(json.dumps({"heff": heff, "D": args.heff_D, "D_H": 18, "data": "synthetic N(0,1) tensors, seeded"}))
+        return
     if args.green_map:
         green_map(args, T, WL)
         return
@@ -643,54 +721,7 @@ def main():
                            fp32_max_rel_de_vs_fp64=max(abs(a - b) / max(abs(b), 1e-2)
                                                        for a, b in zip(e32, [d_["e"] for d_ in dens])))
 
-    # dense effective-Hamiltonian apply at D (microbenchmark)
-    heff = {}
-    Dh, DH = args.heff_D, 18
-    if Dh > 0:
-        L, W, A, R = WL.heff_inputs(Dh, DH)
-        dev = torch.device("cuda:0")
-        tl, tw, ta, tr = (torch.from_numpy(x).to(dev) for x in (L, W, A, R))
-        out = torch.empty_like(ta)
-        fl = 32.0 * DH * Dh * Dh * (2 * Dh) + 128.0 * DH * DH * Dh * Dh
-        sm = torch.cuda.current_stream().cuda_stream
-        for pname in args.heff_precisions.split(","):
-            p = PREC[pname]
-            T.tt_heff_apply(Dh, Dh, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(), p, sm)
-            torch.cuda.synchronize()
-            ms = []
-            for _ in range(args.heff_reps):
-                T.tt_heff_apply(Dh, Dh, DH, tl.data_ptr(), tw.data_ptr(), ta.data_ptr(), tr.data_ptr(), out.data_ptr(),
-                                p, sm)
-                ms.append(T.tt_heff_last_timing())
-            med = statistics.median(x[3] for x in ms)
-            heff[pname] = dict(ms=med, tflops=fl / (med * 1e-3) / 1e12, applies_per_s=1e3 / med,
-                               stage_ms=[statistics.median(x[i] for x in ms) for i in range(3)])
-        print("heff done", file=sys.stderr, flush=True)
-        del tl, tw, ta, tr, out
-    D2 = args.heff2_D
-    if D2 > 0:   # two-site generator: four grouped GEMMs (L.C, W1, W2, .R)
-        L, W1, W2, C2, R = WL.heff2_inputs(D2, D2, DH, 20221223)
-        dev = torch.device("cuda:0")
-        tt_ = [torch.from_numpy(x).to(dev) for x in (L, W1, W2, C2, R)]
-        out = torch.empty_like(tt_[3])
-        sm = torch.cuda.current_stream().cuda_stream
-        ptrs = [x.data_ptr() for x in tt_]
-        T.tt_heff2_apply(D2, D2, DH, *ptrs, out.data_ptr(), T.TT_FP64, sm)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ms = []
-        for _ in range(args.heff_reps):
-            e0.record()
-            T.tt_heff2_apply(D2, D2, DH, *ptrs, out.data_ptr(), T.TT_FP64, sm)
-            e1.record()
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        # flops of the contraction in the paper's order (L.C, W1, W2, .R)
-        fl2 = 2.0 * 256 * D2 ** 3 * DH + 2.0 * 2 * 16 * 4 * D2 * D2 * DH * DH * 16 + 2.0 * 256 * D2 ** 3 * DH
-        heff["two_site_fp64"] = dict(D=D2, ms=statistics.median(ms),
-                                     tflops=fl2 / (statistics.median(ms) * 1e-3) / 1e12)
-        print("heff2 done", file=sys.stderr, flush=True)
-        del tt_, out
+    heff = heff_bench(args, T, WL, torch)
 
     # 2-TDVP growth (the exponential stage's bond growth): the headline lattice
     # from the bare rho0, steps of d_beta doubling from beta0, D_max and the
