@@ -357,18 +357,126 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-// out[r * ldo + k] = x[r * ldx + k] for k < K, zero for K <= k < ldo
+// FP32 operands (the FP32 dense apply): the same tiles with K tiles of 32
+// floats (128-byte LDS rows, the same chunk positions).  Each wave's 64 x 64 as
+// 2 x 2 blocks of the f32 MFMA 32x32x2 (lane l supplies row l % 32 at
+// k = l / 32 of each step; accumulator element v at row 8 (v / 4) + 4 (l / 32)
+// + v % 4, column l % 32); on step 4 c + s lane half h takes k = 8 c + 4 h + s,
+// so each lane reads one 16-byte chunk per operand block and 8 k, and both
+// operands pair the same k.  The FP32 partials are added into FP64
+// accumulators every kFold K tiles.
+constexpr int kSBK = 32;
+
+__device__ __forceinline__ void sg_issue(const SgArgs& g, char* lds, int st, int kt, int m0, int n0, int wave,
+                                         int lane) {
+  char* base = lds + st * kDStage;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = 32 * wave + 8 * j + (lane >> 3);
+    const int lc = (lane & 7) ^ ((row >> 1) & 7);
+    const long long k = (long long)kt * kSBK + 4 * lc;
+    const int ma = min(m0 + row, g.M - 1), nb = min(n0 + row, g.N - 1);
+    char* la = base + (32 * wave + 8 * j) * kDRowBytes;
+    char* lb = base + (kBM + 32 * wave + 8 * j) * kDRowBytes;
+    __builtin_amdgcn_global_load_lds((const void*)(g.A + (long long)ma * g.lda + k), (lds_void*)la, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(g.B + (long long)nb * g.ldb + k), (lds_void*)lb, 16, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sgemm(SgArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char sg_lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int blk = bg_xcd_block(blockIdx.x, ntiles);
+  const int per_group = kGroupM * g.tiles_n;
+  const int grp = blk / per_group, first = grp * kGroupM;
+  const int gsz = min(g.tiles_m - first, kGroupM);
+  const int in = blk - grp * per_group;
+  const int tm = first + in % gsz, tn = in / gsz;
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  double acc[2][2][16];
+  float16_t part[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0;
+      part[i][j] = (float16_t){};
+    }
+
+  const int nk = g.K / kSBK;
+  if (nk > 0) sg_issue(g, sg_lds, 0, 0, m0, n0, wave, lane);
+  const int rsw = (r >> 1) & 7;
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));   // this wave's loads of tile kt
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kt + 1 < nk) sg_issue(g, sg_lds, (kt + 1) & 1, kt + 1, m0, n0, wave, lane);
+    const char* base = sg_lds + (kt & 1) * kDStage;
+#pragma unroll 2
+    for (int c = 0; c < 4; ++c) {
+      const int off = r * kDRowBytes + 16 * ((2 * c + h) ^ rsw);
+      float4_t a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const float4_t*>(base + (wm + 32 * i) * kDRowBytes + off);
+        b[i] = *reinterpret_cast<const float4_t*>(base + (kBM + wn + 32 * i) * kDRowBytes + off);
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            part[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][st], b[j][st], part[i][j], 0, 0, 0);
+    }
+    if ((kt + 1) % kFold == 0 || kt + 1 == nk) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[i][j][v] += (double)part[i][j][v];
+          part[i][j] = (float16_t){};
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (m >= g.M) continue;
+      const long long row = (long long)(m / g.cdiv) * g.ldc1 + (long long)(m % g.cdiv) * g.ldc0;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + wn + 32 * j + r;
+        if (n >= g.N) continue;
+        if (g.cfloat) reinterpret_cast<float*>(g.C)[row + n] = (float)acc[i][j][v];
+        else reinterpret_cast<double*>(g.C)[row + n] = acc[i][j][v];
+      }
+    }
+}
+
+// out[r * ldo + k] = x[r * ldx + k] for k < K, zero for K <= k < ldo (TO: double, or float rounded to nearest)
+template <typename TO>
 __global__ __launch_bounds__(256) void k_pad_rows(const double* __restrict__ x, long long rows, int K, long long ldx,
-                                                 double* __restrict__ out, long long ldo) {
+                                                 TO* __restrict__ out, long long ldo) {
   const long long n = rows * ldo;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
     const long long rr = e / ldo, k = e - rr * ldo;
-    out[e] = k < K ? x[rr * ldx + k] : 0.0;
+    out[e] = k < K ? (TO)x[rr * ldx + k] : (TO)0;
   }
 }
 
 // out[c * ldo + k] = x[k * C + c] for k < K, zero for K <= k < ldo (32 x 32 tiles through LDS)
-__global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int K, int C, double* __restrict__ out,
+template <typename TO>
+__global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int K, int C, TO* __restrict__ out,
                                               long long ldo) {
   __shared__ double t[32][33];
   const int k0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -382,7 +490,7 @@ __global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int c = c0 + ty + 8 * i, k = k0 + tx;
-    if (c < C && k < ldo) out[(long long)c * ldo + k] = t[tx][ty + 8 * i];
+    if (c < C && k < ldo) out[(long long)c * ldo + k] = (TO)t[tx][ty + 8 * i];
   }
 }
 
@@ -391,9 +499,9 @@ __global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int
 // the A operand (from LDS: rows o padded to kWsMaxO with zeros) and T1 as the
 // B operand straight from memory (lane (r, g) takes k = 4 t + g, i.e. a = t,
 // si = g, at y = y0 + r: 128-byte rows), so the result rows o come out as
-// 128-byte runs of y.  NP = 0: FP64 T1 and T2 (f64 MFMA 16x16x4); NP = 2, 3:
-// BF16 planes, multiplied in FP32 (f32 MFMA 16x16x4, W rounded to FP32, the
-// parts of a T1 element summed smallest first).  T2's K padding is written as
+// 128-byte runs of y.  NP = 0: FP64 T1 and T2 (f64 MFMA 16x16x4); NP = 1: FP32
+// T1 and T2; NP = 2, 3: BF16 planes; NP >= 1 multiply in FP32 (f32 MFMA
+// 16x16x4, W rounded to FP32, the parts of a T1 element summed smallest first).  T2's K padding is written as
 // zeros.  One workgroup per (x', sp); its four waves take every fourth block
 // of 16 y.
 template <int NP>
@@ -421,6 +529,7 @@ __global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1
     for (int so = 0; so < 4; ++so) {
       const long long e = (long long)(16 * x + 4 * so + sp) * kp3 + used + y;
       if constexpr (NP == 0) reinterpret_cast<double*>(T2v)[e] = 0.0;
+      else if constexpr (NP == 1) reinterpret_cast<float*>(T2v)[e] = 0.f;
       else
 #pragma unroll
         for (int p = 0; p < NP; ++p) reinterpret_cast<__bf16*>(T2v)[p * sT2 + e] = (__bf16)0.f;
@@ -443,6 +552,8 @@ __global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1
       E bv;
       if constexpr (NP == 0) {
         bv = reinterpret_cast<const double*>(T1v)[e];
+      } else if constexpr (NP == 1) {
+        bv = reinterpret_cast<const float*>(T1v)[e];
       } else {
         const __bf16* t1 = reinterpret_cast<const __bf16*>(T1v);
         float f = 0.f;
@@ -471,6 +582,8 @@ __global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1
           const long long e = (long long)(16 * x + 4 * so + sp) * kp3 + (long long)b * Dr + y;
           if constexpr (NP == 0) {
             reinterpret_cast<double*>(T2v)[e] = acc[ob][v];
+          } else if constexpr (NP == 1) {
+            reinterpret_cast<float*>(T2v)[e] = acc[ob][v];
           } else {
             __bf16 parts[3];
             bg_split<NP>((double)acc[ob][v], parts);
@@ -556,24 +669,72 @@ void launch_dgemm(DgArgs a, hipStream_t st) {
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
 }
 
-void launch_pad_rows(const double* x, long long rows, int K, long long ldx, double* out, long long ldo, hipStream_t st) {
-  TT_REQUIRE(ldo >= K && ldx >= K, TT_EINVAL, "pad: rows shorter than K");
-  const long long n = rows * ldo;
-  if (n <= 0) return;
-  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 16384);
-  hipLaunchKernelGGL(k_pad_rows, dim3(blocks), dim3(256), 0, st, x, rows, K, ldx, out, ldo);
+int sgemm_kpad(long long K) { return (int)((K + kSBK - 1) / kSBK * kSBK); }
+
+void launch_sgemm(SgArgs a, hipStream_t st) {
+  TT_REQUIRE(a.M >= 1 && a.N >= 1 && a.K >= kSBK && a.K % kSBK == 0, TT_EINVAL,
+             "sgemm: K must be a positive multiple of 32");
+  TT_REQUIRE(a.lda >= a.K && a.ldb >= a.K && a.lda % 4 == 0 && a.ldb % 4 == 0 && a.cdiv >= 1, TT_EINVAL,
+             "sgemm: operand rows must hold K and start 16-byte aligned");
+  TT_REQUIRE(((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0, TT_EINVAL, "sgemm: operands not 16-byte aligned");
+  a.tiles_m = (a.M + kBM - 1) / kBM;
+  a.tiles_n = (a.N + kBN - 1) / kBN;
+  TT_REQUIRE((long long)a.tiles_m * a.tiles_n < (1LL << 31), TT_EINVAL, "sgemm: too many tiles");
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_sgemm, hipFuncAttributeMaxDynamicSharedMemorySize, kDS * kDStage) !=
+        hipSuccess)
+      throw Error(TT_EDEVICE, "cannot set the LDS limit of the FP32 GEMM");
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_sgemm, dim3(a.tiles_m * a.tiles_n), dim3(256), kDS * kDStage, st, a);
   ++g_launches;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
 }
 
-void launch_pad_t(const double* x, int K, int C, double* out, long long ldo, hipStream_t st) {
-  TT_REQUIRE(ldo >= K && K >= 1 && C >= 1, TT_EINVAL, "pad: bad shape");
-  const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((ldo + 31) / 32));
-  hipLaunchKernelGGL(k_pad_t, grid, dim3(256), 0, st, x, K, C, out, ldo);
+template <typename TO>
+void pad_rows_t(const double* x, long long rows, int K, long long ldx, TO* out, long long ldo, hipStream_t st) {
+  TT_REQUIRE(ldo >= K && ldx >= K, TT_EINVAL, "pad: rows shorter than K");
+  const long long n = rows * ldo;
+  if (n <= 0) return;
+  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_pad_rows<TO>, dim3(blocks), dim3(256), 0, st, x, rows, K, ldx, out, ldo);
   ++g_launches;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+template <typename TO>
+void pad_t_t(const double* x, int K, int C, TO* out, long long ldo, hipStream_t st) {
+  TT_REQUIRE(ldo >= K && K >= 1 && C >= 1, TT_EINVAL, "pad: bad shape");
+  const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((ldo + 31) / 32));
+  hipLaunchKernelGGL(k_pad_t<TO>, grid, dim3(256), 0, st, x, K, C, out, ldo);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+void launch_pad_rows(const double* x, long long rows, int K, long long ldx, float* out, long long ldo, hipStream_t st) {
+  pad_rows_t(x, rows, K, ldx, out, ldo, st);
+}
+void launch_pad_t(const double* x, int K, int C, float* out, long long ldo, hipStream_t st) {
+  pad_t_t(x, K, C, out, ldo, st);
+}
+void launch_wstage_f32(const float* T1, const double* W, int DH, int Dl, int Dr, float* T2, long long kp3,
+                       hipStream_t st) {
+  TT_REQUIRE(DH >= 1 && 4 * DH <= kWsMaxO && Dl >= 1 && Dr >= 1 && kp3 >= (long long)DH * Dr, TT_EINVAL,
+             "W stage: shape out of range");
+  hipLaunchKernelGGL(k_wstage_mfma<1>, dim3((unsigned)(4 * Dl)), dim3(256), 0, st, (const void*)T1, 0LL, W, DH, Dl, Dr,
+                     (void*)T2, 0LL, kp3);
+  ++g_launches;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
+}
+
+void launch_pad_rows(const double* x, long long rows, int K, long long ldx, double* out, long long ldo, hipStream_t st) {
+  pad_rows_t(x, rows, K, ldx, out, ldo, st);
+}
+void launch_pad_t(const double* x, int K, int C, double* out, long long ldo, hipStream_t st) {
+  pad_t_t(x, K, C, out, ldo, st);
 }
 
 void launch_wstage_f64(const double* T1, const double* W, int DH, int Dl, int Dr, double* T2, long long kp3,

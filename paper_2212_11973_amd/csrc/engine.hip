@@ -2003,6 +2003,35 @@ void dense_apply_f64(int Dl, int Dr, int DH, const double* L, const double* W, c
   if (ev) HIPX(hipEventRecord(ev[3], st));
 }
 
+// The FP32 dense apply on the same plan: float copies of L, A, R (K padded to
+// the FP32 GEMM's tile), float T1 and T2, FP32 multiplies with the GEMMs'
+// partials added in FP64, the result in FP64.  Its buffers fit in the FP64
+// path's (every float piece is at most as many bytes as its FP64 counterpart).
+struct DenseF32Bufs { float *Lf, *Af, *Rf, *T1f, *T2f; };
+void dense_apply_f32(int Dl, int Dr, int DH, const double* L, const double* W, const double* A, const double* R,
+                     double* out, const DenseF32Bufs& b, const hipEvent_t* ev, hipStream_t st) {
+  const long long M1 = (long long)Dl * DH, N1 = 16LL * Dr, K3 = (long long)DH * Dr;
+  const int kp1 = sgemm_kpad(Dl), kp3 = sgemm_kpad(K3);
+  if (ev) HIPX(hipEventRecord(ev[0], st));
+  launch_pad_rows(L, M1, Dl, Dl, b.Lf, kp1, st);
+  launch_pad_t(A, Dl, (int)N1, b.Af, kp1, st);
+  SgArgs g1{};
+  g1.A = b.Lf; g1.lda = kp1; g1.B = b.Af; g1.ldb = kp1;
+  g1.M = (int)M1; g1.N = (int)N1; g1.K = kp1;
+  g1.C = b.T1f; g1.cdiv = DH; g1.ldc0 = (long long)Dl * N1; g1.ldc1 = N1; g1.cfloat = 1;
+  launch_sgemm(g1, st);
+  if (ev) HIPX(hipEventRecord(ev[1], st));
+  launch_wstage_f32(b.T1f, W, DH, Dl, Dr, b.T2f, kp3, st);
+  if (ev) HIPX(hipEventRecord(ev[2], st));
+  launch_pad_rows(R, Dr, (int)K3, K3, b.Rf, kp3, st);
+  SgArgs g3{};
+  g3.A = b.T2f; g3.lda = kp3; g3.B = b.Rf; g3.ldb = kp3;
+  g3.M = 16 * Dl; g3.N = Dr; g3.K = kp3;
+  g3.C = out; g3.cdiv = 16 * Dl; g3.ldc0 = Dr; g3.ldc1 = 0; g3.cfloat = 0;
+  launch_sgemm(g3, st);
+  if (ev) HIPX(hipEventRecord(ev[3], st));
+}
+
 struct HeffCache {
   int Dl = -1, Dr = -1, DH = -1;
   SitePlan plan;
@@ -2840,7 +2869,7 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
       g3.C = out; g3.cdiv = 16 * Dl; g3.ldc0 = Dr; g3.ldc1 = 0; g3.sc = 0; g3.cplanes = 0;
       launch_bgemm(g3, precision, st);
       HIPX(hipEventRecord(c.ev[3], st));
-    } else if (precision == TT_FP64 && dense_f64_applies(DH)) {
+    } else if ((precision == TT_FP64 || precision == TT_FP32) && dense_f64_applies(DH)) {
       const DenseF64Sizes z = dense_f64_sizes(Dl, Dr, DH);
       const long long need = z.lq + z.aq + z.rq + z.t2q + 4 * 32;
       if (need > c.f64_doubles) {
@@ -2852,7 +2881,12 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* L, const double* W, cons
       auto al = [](long long n) { return (n + 31) / 32 * 32; };   // 256-byte aligned pieces
       DenseF64Bufs b{c.f64, c.f64 + al(z.lq), c.f64 + al(z.lq) + al(z.aq), c.T1,
                      c.f64 + al(z.lq) + al(z.aq) + al(z.rq)};
-      dense_apply_f64(Dl, Dr, DH, L, W, A, R, out, b, z, c.ev, st);
+      if (precision == TT_FP64) {
+        dense_apply_f64(Dl, Dr, DH, L, W, A, R, out, b, z, c.ev, st);
+      } else {
+        DenseF32Bufs f{(float*)b.Lq, (float*)b.Aq, (float*)b.Rq, (float*)b.T1, (float*)b.T2q};
+        dense_apply_f32(Dl, Dr, DH, L, W, A, R, out, f, c.ev, st);
+      }
     } else {
       HIPX(hipEventRecord(c.ev[0], st));
       launch_gemm(c.plan.s1, c.tabs.dev, one(Slots{{const_cast<double*>(L), const_cast<double*>(A), c.T1, nullptr}}), 1,
@@ -2913,6 +2947,11 @@ int tt_heff_apply_noalloc(int Dl, int Dr, int DH, const double* L, const double*
   if (precision == TT_FP64 && dense_f64_applies(DH)) {   // the kernels of tt_heff_apply's FP64 path
     DenseF64Bufs b{d.Lq, d.Aq, d.Rq, d.T1, d.T2};
     dense_apply_f64(Dl, Dr, DH, L, W, A, R, out, b, dense_f64_sizes(Dl, Dr, DH), nullptr, st);
+    return TT_OK;
+  }
+  if (precision == TT_FP32 && dense_f64_applies(DH)) {   // and of its FP32 path, in the same pieces
+    DenseF32Bufs f{(float*)d.Lq, (float*)d.Aq, (float*)d.Rq, (float*)d.T1, (float*)d.T2};
+    dense_apply_f32(Dl, Dr, DH, L, W, A, R, out, f, nullptr, st);
     return TT_OK;
   }
   launch_gemm(d.s1, d.tabs, one(Slots{{l, a, d.T1, nullptr}}), 1, precision, one(d.pws), st);

@@ -102,10 +102,26 @@ struct DgArgs {
 };
 int dgemm_kpad(long long K);   // K rounded up to the FP64 GEMM's K tile
 void launch_dgemm(DgArgs a, hipStream_t st);
-// out[r ldo + k] = x[r ldx + k] (k < K), zero up to ldo
+// The FP32 version (the FP32 dense apply): float operands, K a multiple of 32,
+// FP32 MFMA with the partials added in FP64; results as double or (cfloat) float.
+struct SgArgs {
+  const float* A; long long lda;
+  const float* B; long long ldb;
+  int M, N, K;
+  void* C; long long ldc0, ldc1; int cdiv, cfloat;
+  int tiles_m, tiles_n;   // set by the launcher
+};
+int sgemm_kpad(long long K);   // K rounded up to the FP32 GEMM's K tile
+void launch_sgemm(SgArgs a, hipStream_t st);
+// out[r ldo + k] = x[r ldx + k] (k < K), zero up to ldo (float: rounded to nearest)
 void launch_pad_rows(const double* x, long long rows, int K, long long ldx, double* out, long long ldo, hipStream_t st);
+void launch_pad_rows(const double* x, long long rows, int K, long long ldx, float* out, long long ldo, hipStream_t st);
 // out[c ldo + k] = x[k C + c] (k < K), zero up to ldo
 void launch_pad_t(const double* x, int K, int C, double* out, long long ldo, hipStream_t st);
+void launch_pad_t(const double* x, int K, int C, float* out, long long ldo, hipStream_t st);
+// the W stage with float T1 and T2 (FP32 multiplies)
+void launch_wstage_f32(const float* T1, const double* W, int DH, int Dl, int Dr, float* T2, long long kp3,
+                       hipStream_t st);
 // the dense apply's W stage in FP64 (T1[a][x'][s][y] -> T2 rows (x', s) kp3 apart)
 void launch_wstage_f64(const double* T1, const double* W, int DH, int Dl, int Dr, double* T2, long long kp3,
                        hipStream_t st);
