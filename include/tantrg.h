@@ -288,15 +288,21 @@ int tt_state_save(const tt_state* state, const char* path);
 int tt_state_load(const char* path, tt_state** out);
 
 /* One dense effective-Hamiltonian apply (SM Fig. optimalB(c), contraction
- * order of SM Fig. Lanczos).  In the split-BF16 precisions every operand is
- * split once into BF16 planes and T1, T2 are written as planes by the tiles
- * that produce them:
+ * order of SM Fig. Lanczos):
  *   out[x,so,sp,y] = sum L[x,a,al] A[al,si,sp,be] W[a,so,si,b] R[y,b,be]
  * with dev_L [Dl][DH][Dl], dev_W [DH][4][4][DH], dev_A and dev_out
  * [Dl][4][4][Dr], dev_R [Dr][DH][Dr], all FP64 row-major device arrays owned
  * by the caller; stream is a hipStream_t (NULL: the library stream).
- * Workspace of 8*(Dl*DH*16*Dr)*2 bytes is kept by the library between
- * calls.  Returns after enqueueing. */
+ * L.A and .R run as large-tile MFMA GEMMs on copies of the operands whose
+ * rows run along the contracted index, zero-padded to the GEMM's K tile (A
+ * transposed): FP64 copies (TT_FP64), copies rounded to FP32 (TT_FP32, FP32
+ * multiplies, partial sums added in FP64), or BF16 planes (the split-BF16
+ * precisions: each element split once into 2 or 3 BF16 parts, 3 or 6 part
+ * products).  The W stage runs on the matrix cores between them.  T1 and T2
+ * are kept in the precision's storage (FP64, FP32 or planes).  For DH > 20
+ * the FP64 and FP32 modes use the grouped-GEMM path of the sweep instead.
+ * Workspace of about 8*(Dl*DH*16*Dr)*2 bytes plus the padded copies is kept
+ * by the library between calls.  Returns after enqueueing. */
 int tt_heff_apply(int Dl, int Dr, int DH, const double* dev_L, const double* dev_W,
                   const double* dev_A, const double* dev_R, double* dev_out, int precision,
                   void* stream);
@@ -305,13 +311,14 @@ int tt_heff_apply(int Dl, int Dr, int DH, const double* dev_L, const double* dev
  * capture, tight serving loops, harnesses that forbid hipMalloc): the apply of
  * tt_heff_apply, same arguments, layouts and result (the same kernels and
  * launch plans, so in FP64 and FP32 the output is bit for bit that of
- * tt_heff_apply; in the split-BF16 modes it splits every element inside the
- * tiles and keeps T1 and T2 in FP64, where tt_heff_apply works on operands
- * and intermediates pre-split into BF16 planes), with
+ * tt_heff_apply; in the split-BF16 modes it runs the sweep's grouped GEMMs,
+ * which split every element inside the tiles and keep T1 and T2 in FP64,
+ * where tt_heff_apply works on operands and intermediates pre-split into BF16
+ * planes), with
  * every byte of device memory it needs beyond the caller's inputs and output
- * (the intermediates T1 = L.A and T2, the K-slice partial tiles and the launch
- * descriptors) taken from a static device array of 192 MiB that each GPU the
- * library runs on holds until the process ends.  It calls no hipMalloc,
+ * (the intermediates T1 = L.A and T2, the padded operand copies, the K-slice
+ * partial tiles and the launch descriptors) taken from a static device array
+ * of 192 MiB that each GPU the library runs on holds until the process ends.  It calls no hipMalloc,
  * hipFree or other allocating routine.  TT_EINVAL for sizes whose
  * intermediates do not fit (16*Dl*DH*16*Dr bytes for T1 and T2 alone; e.g.
  * Dl = Dr = 128 at DH = 18 fits), for non-positive sizes, null pointers, an
