@@ -788,7 +788,7 @@ def main():
                   "apply_forms": forms_info,
                   "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
                   "thermo": thermo, "other_precisions": mixed, "uncapped": uncapped},
-        "heff": {"D": Dh, "D_H": DH, **heff},
+        "heff": {"D": args.heff_D, "D_H": 18, **heff},
         "mu_scan": mu_scan,
         "tdvp2": tdvp2,
         "roofline": roof,

@@ -358,6 +358,17 @@ int tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free_fn, void* ctx);
  * Synchronises. */
 int tt_heff_last_timing(double* host_ms4);
 
+/* The 2-TDVP split's SVD (SM Sec. "2-TDVP in the initial stage"): a
+ * middle-charge block whose matrix X (and its column norms) fits max_doubles
+ * doubles of one workgroup's LDS is orthogonalised by one workgroup; larger
+ * blocks run the same one-sided Jacobi with each round spread over the GPU
+ * (one launch per round, one wave per column pair; one host synchronisation
+ * per sweep).  0 (the default): the device's LDS.  A smaller limit sends more
+ * blocks to the spread form; both forms take the same pairs in the same
+ * order with the same arithmetic.  Takes effect for the splits planned after
+ * the call.  TT_EINVAL for a negative size. */
+int tt_svd_lds_limit(long long max_doubles);
+
 /* Sweeps as replayed hipGraphs (default off).  When on, the first
  * tdvp_sweep of a state with a step dbeta captures the sweep's launches
  * into a graph (on a private stream; the call's results are those of the

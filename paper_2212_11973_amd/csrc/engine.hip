@@ -1334,16 +1334,29 @@ void free_site_plan(SitePlan& p) {
 }
 
 // device copies of the two-site plan of one step
+// Largest X (plus its column norms), in doubles, of an SVD block that one
+// workgroup takes in LDS; 0: the device's LDS (tt_svd_lds_limit).
+long long g_svd_lds_limit = 0;
+
 struct PairDev {
   PairPlan P;
   SiteTables tabs;
   SvdTask* d_svd = nullptr;
+  // the blocks one workgroup takes (small) and those whose rounds spread over the GPU (big)
+  int n_small = 0, n_big = 0, n_pairs = 0, max_np = 0;
+  std::vector<int> small, big, pairs;   // host copies of the lists below
+  int *d_small = nullptr, *d_big = nullptr, *d_pairs = nullptr;
+  double* d_ctl = nullptr;
   PairDev() = default;
   PairDev(const PairDev&) = delete;
   PairDev& operator=(const PairDev&) = delete;
   ~PairDev() {
     free_plan(P.join); free_plan(P.s1); free_plan(P.s4); free_plan(P.w1); free_plan(P.w2);
     dfree(d_svd);
+    dfree(d_small);
+    dfree(d_big);
+    dfree(d_pairs);
+    dfree(d_ctl);
     dfree(tabs.dev);
   }
 };
@@ -1386,6 +1399,34 @@ std::unique_ptr<PairDev> make_pair(tt_state& s, int k) {
   upload_plan(P.w1, st);
   upload_plan(P.w2, st);
   d->d_svd = upload(P.svd, st);
+  {   // blocks whose X fits one workgroup's LDS, and the rest with their column pairs
+    const long long dev_lim = svd_lds_doubles();
+    const long long lim = g_svd_lds_limit > 0 ? std::min(g_svd_lds_limit, dev_lim) : dev_lim;
+    std::vector<int>& small = d->small;
+    std::vector<int>& big = d->big;
+    std::vector<int>& pairs = d->pairs;
+    for (int t = 0; t < (int)P.svd.size(); ++t) {
+      const long long mw = std::max(P.svd[t].R, P.svd[t].w), nw = std::min(P.svd[t].R, P.svd[t].w);
+      if (nw + mw * nw <= lim) {
+        small.push_back(t);
+        continue;
+      }
+      const int np = (int)(nw + (nw & 1));
+      for (int k = 0; k < np / 2; ++k) {
+        pairs.push_back((int)big.size());
+        pairs.push_back(k);
+      }
+      d->max_np = std::max(d->max_np, np);
+      big.push_back(t);
+    }
+    d->n_small = (int)small.size();
+    d->n_big = (int)big.size();
+    d->n_pairs = (int)pairs.size() / 2;
+    d->d_small = upload(small, st);
+    d->d_big = upload(big, st);
+    d->d_pairs = upload(pairs, st);
+    if (!big.empty()) d->d_ctl = (double*)dalloc(8 * 3 * big.size());
+  }
   const long long n = P.L.size;
   grow(s.th, s.cap_th, n);
   grow(s.P1, s.cap_P1, P.t1_size);
@@ -1429,7 +1470,9 @@ double split_pair(tt_state& s, int k, const PairDev& d, bool left, int Dmax, dou
   const PairPlan& P = d.P;
   const int nt = (int)P.svd.size();
   TT_REQUIRE(nt > 0, TT_ENUMERIC, "2-TDVP: the two-site tensor has no block");
-  launch_svd(d.d_svd, nt, d.tabs.dev, s.th, s.svw, s.svs, ST());
+  launch_svd(d.d_svd, d.n_small, d.d_small, d.tabs.dev, s.th, s.svw, s.svs, ST());
+  launch_svd_big(d.d_svd, d.d_big, d.n_big, d.d_pairs, d.n_pairs, d.max_np, d.tabs.dev, s.th, s.svw, s.svs, d.d_ctl,
+                 ST());
   std::vector<double> sig((size_t)P.svd_nsig);
   HIPX(hipMemcpyAsync(sig.data(), s.svs, 8 * (size_t)P.svd_nsig, hipMemcpyDeviceToHost, ST()));
   HIPX(hipStreamSynchronize(ST()));
@@ -3012,6 +3055,13 @@ int tt_model_bond_sectors(const tt_model* model, const tt_options* opts, int k, 
   TT_REQUIRE(model && opts && nsec, TT_EINVAL, "null argument");
   auto s = make_host_state(*model, *opts, false);
   return tt_state_bond_sectors(s.get(), k, nsec, qu, qd, dim);
+  ABI_END
+}
+
+int tt_svd_lds_limit(long long max_doubles) {
+  ABI_BEGIN
+  TT_REQUIRE(max_doubles >= 0, TT_EINVAL, "tt_svd_lds_limit: negative size");
+  g_svd_lds_limit = max_doubles;
   ABI_END
 }
 

@@ -173,8 +173,18 @@ constexpr int kSvdMaxMinDim = 16384;
 // SVD of every task (one-sided Jacobi, one workgroup per task; ws holds the
 // plan's svd_ws doubles, sig its svd_nsig singular values), then the kept
 // vectors of every emit entry into the two site tensors
-void launch_svd(const SvdTask* d_tasks, int ntasks, const long long* d_tabs, const double* src, double* ws,
-                double* sig, hipStream_t st);
+void launch_svd(const SvdTask* d_tasks, int ntasks, const int* d_idx, const long long* d_tabs, const double* src,
+                double* ws, double* sig, hipStream_t st);
+// doubles of LDS a workgroup of the SVD kernel can hold (blocks whose X needs
+// more run as launch_svd_big)
+int svd_lds_doubles();
+// The same Jacobi for the large blocks d_big[0..nbig) of d_tasks, one launch
+// per round spread over the GPU (d_pairs: (index into d_big, pair k) for every
+// pair of every large block; max_np: the largest column count rounded up to
+// even); ctl: 3 doubles per large block.  Synchronises once per sweep.
+void launch_svd_big(const SvdTask* d_tasks, const int* d_big, int nbig, const int* d_pairs, int npairs, int max_np,
+                    const long long* d_tabs, const double* src, double* ws, double* sig, double* ctl,
+                    hipStream_t st);
 void launch_svd_emit(const SvdTask* d_tasks, const SvdEmit* d_em, int nem, const long long* d_tabs, const double* ws,
                      const double* sig, double* Aout, double* Bout, hipStream_t st);
 

@@ -2302,11 +2302,12 @@ __device__ inline double wave_sum64(double v) {
 }
 
 __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __restrict__ tasks,
+                                                           const int* __restrict__ idx,
                                                            const long long* __restrict__ tabs,
                                                            const double* __restrict__ src, double* __restrict__ ws,
                                                            double* __restrict__ sig, int lds_doubles) {
   extern __shared__ __attribute__((aligned(16))) double svd_lds[];
-  const SvdTask t = tasks[blockIdx.x];
+  const SvdTask t = tasks[idx ? idx[blockIdx.x] : blockIdx.x];
   const bool tr = t.R < t.w;
   const int mw = tr ? t.w : t.R, nw = tr ? t.R : t.w;
   double* Xg = ws + t.ws;
@@ -2411,6 +2412,137 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(const SvdTask* __res
     for (long long e = threadIdx.x; e < (long long)nw * nw; e += blockDim.x) Vg[e] = V[e];
 }
 
+// The same one-sided Jacobi for blocks too large for one workgroup's LDS, with
+// the work of a round spread over the GPU: one launch per round, one wave per
+// column pair (all large blocks of the split in the same launch), the squared
+// column norms kept in the task's singular-value slots between launches.  The
+// pair order, the sums and the rotations are those of k_svd_jacobi, so both
+// give the same bits; a block that has had a sweep without rotation takes no
+// further part (k_svd_jacobi stops there too).  ctl per large block:
+// [0] the rounding-level threshold of the sweep, [1] rotated in this sweep,
+// [2] done.
+__device__ __forceinline__ void svd_dims(const SvdTask& t, int& mw, int& nw) {
+  const bool tr = t.R < t.w;
+  mw = tr ? t.w : t.R;
+  nw = tr ? t.R : t.w;
+}
+
+// X (columns of length mw, transposed when R < w) and V = I into the work array
+__global__ __launch_bounds__(256) void k_svd_big_load(const SvdTask* __restrict__ tasks, const int* __restrict__ big,
+                                                     const long long* __restrict__ tabs,
+                                                     const double* __restrict__ src, double* __restrict__ ws,
+                                                     double* __restrict__ ctl) {
+  const SvdTask t = tasks[big[blockIdx.y]];
+  int mw, nw;
+  svd_dims(t, mw, nw);
+  const bool tr = t.R < t.w;
+  double* X = ws + t.ws;
+  double* V = X + (long long)mw * nw;
+  const long long* rt = tabs + t.rtab;
+  const long long tot = (long long)t.R * t.w, step = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += step) {
+    const long long i = e / t.w, j = e - i * t.w;
+    const double v = src[rt[i] + j];
+    if (!tr) X[i + j * mw] = v;
+    else X[j + i * mw] = v;
+  }
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)nw * nw; e += step)
+    V[e] = (e / nw == e % nw) ? 1.0 : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[3 * blockIdx.y + 2] = 0.0;
+}
+
+// exact squared column norms (one wave per column) into the singular-value
+// slots; fin: their square roots, the singular values
+__global__ __launch_bounds__(256) void k_svd_big_norms(const SvdTask* __restrict__ tasks, const int* __restrict__ big,
+                                                      const double* __restrict__ ws, double* __restrict__ sig,
+                                                      const double* __restrict__ ctl, int fin) {
+  const SvdTask t = tasks[big[blockIdx.y]];
+  if (!fin && ctl[3 * blockIdx.y + 2] != 0.0) return;
+  int mw, nw;
+  svd_dims(t, mw, nw);
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nw) return;
+  const double* xj = ws + t.ws + (long long)j * mw;
+  double s2 = 0.0;
+  for (int i = lane; i < mw; i += 64) s2 += xj[i] * xj[i];
+  s2 = wave_sum64(s2);
+  if (lane == 0) sig[t.sig + j] = fin ? sqrt(s2) : s2;
+}
+
+// the sweep's threshold from the norms (summed in column order, one thread) and a cleared rotation flag
+__global__ void k_svd_big_thr(const SvdTask* __restrict__ tasks, const int* __restrict__ big,
+                              const double* __restrict__ sig, double* __restrict__ ctl) {
+  const SvdTask t = tasks[big[blockIdx.x]];
+  if (threadIdx.x != 0 || ctl[3 * blockIdx.x + 2] != 0.0) return;
+  int mw, nw;
+  svd_dims(t, mw, nw);
+  double f = 0.0;
+  for (int j = 0; j < nw; ++j) f += sig[t.sig + j];
+  const double lev = (double)mw * 2.220446049250313e-16;
+  ctl[3 * blockIdx.x] = lev * lev * f;
+  ctl[3 * blockIdx.x + 1] = 0.0;
+}
+
+// one round: wave -> (large block, pair k); pairs[2 q] = index into big, pairs[2 q + 1] = k
+__global__ __launch_bounds__(256) void k_svd_big_round(const SvdTask* __restrict__ tasks, const int* __restrict__ big,
+                                                      const int* __restrict__ pairs, int npairs, int rd,
+                                                      double* __restrict__ ws, double* __restrict__ sig,
+                                                      double* __restrict__ ctl) {
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= npairs) return;
+  const int lane = threadIdx.x & 63;
+  const int bi = pairs[2 * q], k = pairs[2 * q + 1];
+  if (ctl[3 * bi + 2] != 0.0) return;
+  const SvdTask t = tasks[big[bi]];
+  int mw, nw;
+  svd_dims(t, mw, nw);
+  const int np = nw + (nw & 1);
+  if (rd >= np - 1) return;
+  int a = k == 0 ? 0 : 1 + (k + rd) % (np - 1);
+  int b = 1 + ((k == 0 ? 0 : np - 1 - k) + rd) % (np - 1);
+  if (a > b) { const int x = a; a = b; b = x; }
+  if (b >= nw) return;
+  double* nrm = sig + t.sig;
+  const double al = nrm[a], be = nrm[b], thr = ctl[3 * bi];
+  if (al <= thr && be <= thr) return;
+  const double tol = 2.220446049250313e-16 * (double)(mw > 16 ? mw : 16);
+  double* X = ws + t.ws;
+  double* xa = X + (long long)a * mw;
+  double* xb = X + (long long)b * mw;
+  double ga = 0.0;
+  for (int i = lane; i < mw; i += 64) ga += xa[i] * xb[i];
+  ga = wave_sum64(ga);
+  if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+  const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
+  for (int i = lane; i < mw; i += 64) {
+    const double u = xa[i], v = xb[i];
+    xa[i] = c * u - s * v;
+    xb[i] = s * u + c * v;
+  }
+  double* V = X + (long long)mw * nw;
+  double* va = V + (long long)a * nw;
+  double* vb = V + (long long)b * nw;
+  for (int i = lane; i < nw; i += 64) {
+    const double u = va[i], v = vb[i];
+    va[i] = c * u - s * v;
+    vb[i] = s * u + c * v;
+  }
+  if (lane == 0) {
+    nrm[a] = al - tn * ga;
+    nrm[b] = be + tn * ga;
+    ctl[3 * bi + 1] = 1.0;   // every writer stores the same value
+  }
+}
+
+// after a sweep: a block without a rotation is done
+__global__ void k_svd_big_mark(int nbig, double* __restrict__ ctl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nbig && ctl[3 * i + 2] == 0.0 && ctl[3 * i + 1] == 0.0) ctl[3 * i + 2] = 1.0;
+}
+
 // M = sum_j s_j u_j v_j^T with unit u_j (R entries) and v_j (w entries), read
 // from the Jacobi result: u_j = X_j / s_j, v_j = V_j when R >= w (X = M V);
 // u_j = V_j, v_j = X_j / s_j when R < w (X = M^T V).  Written as u to the left
@@ -2440,8 +2572,48 @@ __global__ __launch_bounds__(256) void k_svd_emit(const SvdTask* __restrict__ ta
   }
 }
 
-void launch_svd(const SvdTask* d_tasks, int ntasks, const long long* d_tabs, const double* src, double* ws,
-                double* sig, hipStream_t st) {
+int svd_lds_doubles() {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    throw Error(TT_EDEVICE, "cannot read the LDS limit");
+  return (std::min(lim, kSvdLdsBytes) - 64) / 8;
+}
+
+void launch_svd_big(const SvdTask* d_tasks, const int* d_big, int nbig, const int* d_pairs, int npairs, int max_np,
+                    const long long* d_tabs, const double* src, double* ws, double* sig, double* ctl,
+                    hipStream_t st) {
+  if (nbig <= 0) return;
+  hipLaunchKernelGGL(k_svd_big_load, dim3(256, nbig), dim3(256), 0, st, d_tasks, d_big, d_tabs, src, ws, ctl);
+  HIP_CHECK_LAUNCH();
+  // the largest column count among the blocks bounds the norm launch
+  const unsigned ncol_blocks = (unsigned)((max_np + 3) / 4);
+  std::vector<double> h(3 * (size_t)nbig);
+  for (int sw = 0; sw < kSvdMaxSweeps && max_np > 1; ++sw) {
+    hipLaunchKernelGGL(k_svd_big_norms, dim3(ncol_blocks, nbig), dim3(256), 0, st, d_tasks, d_big, ws, sig, ctl, 0);
+    HIP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_svd_big_thr, dim3(nbig), dim3(64), 0, st, d_tasks, d_big, sig, ctl);
+    HIP_CHECK_LAUNCH();
+    for (int rd = 0; rd < max_np - 1; ++rd) {
+      hipLaunchKernelGGL(k_svd_big_round, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st, d_tasks, d_big, d_pairs,
+                         npairs, rd, ws, sig, ctl);
+      HIP_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_svd_big_mark, dim3((unsigned)((nbig + 255) / 256)), dim3(256), 0, st, nbig, ctl);
+    HIP_CHECK_LAUNCH();
+    if (hipMemcpyAsync(h.data(), ctl, 8 * h.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      throw Error(TT_EDEVICE, "SVD: cannot read the sweep flags");
+    bool all_done = true;
+    for (int i = 0; i < nbig; ++i) all_done = all_done && h[3 * (size_t)i + 2] != 0.0;
+    if (all_done) break;
+  }
+  hipLaunchKernelGGL(k_svd_big_norms, dim3(ncol_blocks, nbig), dim3(256), 0, st, d_tasks, d_big, ws, sig, ctl, 1);
+  HIP_CHECK_LAUNCH();
+}
+
+void launch_svd(const SvdTask* d_tasks, int ntasks, const int* d_idx, const long long* d_tabs, const double* src,
+                double* ws, double* sig, hipStream_t st) {
   if (ntasks <= 0) return;
   // dynamic LDS: the device's per-workgroup limit, at most kSvdLdsBytes, less
   // the kernel's static LDS (two shared scalars)
@@ -2456,8 +2628,8 @@ void launch_svd(const SvdTask* d_tasks, int ntasks, const long long* d_tabs, con
         hipSuccess)
       throw Error(TT_EDEVICE, "cannot set the LDS limit of the SVD kernel");
   }
-  hipLaunchKernelGGL(k_svd_jacobi, dim3(ntasks), dim3(kSvdThreads), lds_bytes, st, d_tasks, d_tabs, src, ws, sig,
-                     lds_bytes / 8);
+  hipLaunchKernelGGL(k_svd_jacobi, dim3(ntasks), dim3(kSvdThreads), lds_bytes, st, d_tasks, d_idx, d_tabs, src, ws,
+                     sig, lds_bytes / 8);
   HIP_CHECK_LAUNCH();
 }
 void launch_svd_emit(const SvdTask* d_tasks, const SvdEmit* d_em, int nem, const long long* d_tabs, const double* ws,

@@ -25,7 +25,7 @@ SYMBOLS = [
     "tt_state_save", "tt_state_load", "tt_heff_apply", "tt_set_stream",
     "tt_set_allocator", "tt_heff_last_timing", "tt_check_plans", "tt_model_bond_sectors",
     "tt_profile_enable", "tt_profile_read", "thermo_local_observables", "tt_thermo_derived",
-    "thermo_spin_correlation", "tt_sweep_graphs", "thermo_green_function", "thermo_pairing_order",
+    "thermo_spin_correlation", "tt_sweep_graphs", "tt_svd_lds_limit", "thermo_green_function", "thermo_pairing_order",
     "tt_heff2_apply", "tt_heff_apply_noalloc", "tt_phase_timing", "tt_tune_apply", "tdvp_sweep2",
 ]
 
@@ -108,6 +108,7 @@ def lib(init_torch=True):
         L.tt_thermo_derived.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         L.thermo_spin_correlation.argtypes = [vp, C.c_int, dp, ip]
         L.tt_sweep_graphs.argtypes = [C.c_int]
+        L.tt_svd_lds_limit.argtypes = [C.c_longlong]
         L.tt_phase_timing.argtypes = [C.c_int]
         L.tt_tune_apply.argtypes = [vp, C.c_int, ip]
         L.thermo_green_function.argtypes = [vp, C.c_double, C.c_double, dp]
@@ -200,6 +201,13 @@ def thermo_local_observables(state):
     out = (C.c_double * 2)()
     _check(lib().thermo_local_observables(state, out))
     return dict(n=out[0], docc=out[1])
+
+
+def tt_svd_lds_limit(max_doubles):
+    """Largest SVD block (doubles of X and its column norms) one workgroup takes
+    in LDS for the 2-TDVP split; larger blocks spread each Jacobi round over the
+    GPU.  0: the device's LDS."""
+    _check(lib().tt_svd_lds_limit(int(max_doubles)))
 
 
 def tt_sweep_graphs(on):

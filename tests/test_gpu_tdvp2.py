@@ -113,3 +113,49 @@ def test_refuses_what_it_cannot_run():
     st.sweep2(0.05, 100)                        # the state is untouched by the refusals
     assert st.info()[1][2] > 6
     st.free()
+
+
+def _grow(limit, W=1, L=6, geo=T.TT_CHAIN, U=4.0, mu=0.3, cutoff=1e-6, dbeta=0.1, n=2):
+    T.tt_svd_lds_limit(limit)
+    try:
+        st, _ = _bare(W, L, geo, U, mu)
+        for _ in range(n):
+            st.sweep2(dbeta, 10 ** 6, cutoff)
+        dims = st.info()[1]
+        return st, dims
+    finally:
+        T.tt_svd_lds_limit(0)
+
+
+def test_spread_svd_rounds_equal_the_workgroup_form():
+    # every block through the rounds spread over the GPU (limit 1) against the
+    # default (every block of this chain fits one workgroup's LDS): the same
+    # pairs in the same order with the same arithmetic
+    print("spread SVD vs one workgroup, 1x6 chain", flush=True)
+    a, da = _grow(0)
+    b, db = _grow(1)
+    try:
+        assert da == db
+        oa, ob = a.observables(), b.observables()
+        for key in ("lnZ", "E", "lnZ_single"):
+            assert _rel(oa[key], ob[key]) <= 1e-13, (key, oa[key], ob[key])
+        for k in range(len(da) - 1):
+            assert np.allclose(a.export_site(k), b.export_site(k), rtol=0, atol=1e-12), k
+    finally:
+        a.free()
+        b.free()
+
+
+def test_spread_svd_growth_matches_the_dense_oracle():
+    print("spread SVD vs oracle, 2x3 square", flush=True)
+    W, L, geo, U, mu, cutoff, dbeta = 2, 3, T.TT_OPEN_SQUARE, 8.0, 1.5, 1e-5, 0.1
+    st, dims = _grow(1, W, L, geo, U, mu, cutoff, dbeta, 1)
+    _, ost = _bare(W, L, geo, U, mu)
+    ost.sweep2(dbeta, 10 ** 6, cutoff)
+    try:
+        assert dims == ost.dims()
+        o, oo = st.observables(), ost.observables()
+        for key in ("lnZ", "E", "lnZ_single"):
+            assert _rel(o[key], oo[key]) <= TOL, (key, o[key], oo[key])
+    finally:
+        st.free()
