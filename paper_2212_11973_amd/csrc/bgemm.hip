@@ -49,11 +49,15 @@ constexpr int kRowBytes = kBK * 2;             // one LDS row of one plane
 constexpr int kFold = TT_BG_FOLD;              // K tiles between FP64 folds
 constexpr int kGroupM = TT_BG_GROUP_M;         // tile rows per raster group
 
+#ifndef TT_BG_BM2
+#define TT_BG_BM2 128
+#endif
 template <int NP> struct BgTraits;
-// S: LDS stages (two workgroups per CU fit with x3's 2 x 32 KB); WPE: waves per SIMD
-template <> struct BgTraits<2> { static constexpr int S = TT_BG_STAGES2, WPE = TT_BG_WPE2; };
-template <> struct BgTraits<3> { static constexpr int S = 3, WPE = 1; };
-template <int NP> constexpr int bg_stage_bytes() { return NP * (kBM + kBN) * kRowBytes; }
+// BM: tile rows (BM / 32 waves, 64 x 64 each); S: LDS stages; WPE: waves per SIMD
+template <> struct BgTraits<2> { static constexpr int BM = TT_BG_BM2, S = TT_BG_STAGES2, WPE = TT_BG_WPE2; };
+template <> struct BgTraits<3> { static constexpr int BM = 128, S = 3, WPE = 1; };
+template <int NP> constexpr int bg_waves() { return BgTraits<NP>::BM / 32; }
+template <int NP> constexpr int bg_stage_bytes() { return NP * (BgTraits<NP>::BM + kBN) * kRowBytes; }
 template <int NP> constexpr int bg_lds_bytes() { return BgTraits<NP>::S * bg_stage_bytes<NP>(); }
 
 // s_waitcnt immediate: vmcnt(n), other counters left alone (gfx9 encoding)
@@ -81,20 +85,29 @@ __device__ __forceinline__ int bg_xcd_block(int b, int n) {
 template <int NP>
 __device__ __forceinline__ void bg_issue(const BgArgs& g, char* lds, int st, int kt, int m0, int n0, int wave,
                                          int lane) {
+  constexpr int BM = BgTraits<NP>::BM, BROWS = kBN / bg_waves<NP>();   // B rows per wave
   char* base = lds + st * bg_stage_bytes<NP>();
   const int lc = (lane & 3) ^ (lane >> 4);
   const long long k = (long long)kt * kBK + 8 * lc;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int row = 32 * wave + 16 * j + (lane >> 2);
-    const int ma = min(m0 + row, g.M - 1), nb = min(n0 + row, g.N - 1);
+    const int ma = min(m0 + row, g.M - 1);
     const __bf16* ga = g.A + (long long)ma * g.lda + k;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      char* la = base + (p * BM + 32 * wave + 16 * j) * kRowBytes;
+      __builtin_amdgcn_global_load_lds((const void*)(ga + p * g.sa), (lds_void*)la, 16, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < BROWS / 16; ++j) {
+    const int row = BROWS * wave + 16 * j + (lane >> 2);
+    const int nb = min(n0 + row, g.N - 1);
     const __bf16* gb = g.B + (long long)nb * g.ldb + k;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      char* la = base + (p * kBM + 32 * wave + 16 * j) * kRowBytes;
-      char* lb = base + (NP * kBM + p * kBN + 32 * wave + 16 * j) * kRowBytes;
-      __builtin_amdgcn_global_load_lds((const void*)(ga + p * g.sa), (lds_void*)la, 16, 0, 0);
+      char* lb = base + (NP * BM + p * kBN + BROWS * wave + 16 * j) * kRowBytes;
       __builtin_amdgcn_global_load_lds((const void*)(gb + p * g.sb), (lds_void*)lb, 16, 0, 0);
     }
   }
@@ -122,10 +135,10 @@ __device__ __forceinline__ ACC bg_products(const bf16x8_t (&a)[NP], const bf16x8
 // of a B block at k = 8 (l / 32) .. + 7; accumulator element v of a block sits
 // at row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BgTraits<NP>::WPE, BgTraits<NP>::WPE))) void k_bgemm(BgArgs g) {
+__global__ __launch_bounds__(64 * bg_waves<NP>()) __attribute__((amdgpu_waves_per_eu(BgTraits<NP>::WPE, BgTraits<NP>::WPE))) void k_bgemm(BgArgs g) {
   extern __shared__ __attribute__((aligned(16))) char bg_lds[];
-  constexpr int S = BgTraits<NP>::S;
-  constexpr int LPS = 4 * NP;   // global_load_lds per wave per stage
+  constexpr int S = BgTraits<NP>::S, BM = BgTraits<NP>::BM;
+  constexpr int LPS = NP * (2 + kBN / bg_waves<NP>() / 16);   // global_load_lds per wave per stage
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
 
@@ -137,7 +150,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BgTraits<NP
   const int gsz = min(g.tiles_m - first, kGroupM);
   const int in = blk - grp * per_group;
   const int tm = first + in % gsz, tn = in / gsz;
-  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int m0 = tm * BM, n0 = tn * kBN;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
   double acc[2][2][16];
@@ -181,8 +194,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BgTraits<NP
       for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          a[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (p * kBM + wm + 32 * i) * kRowBytes + rp);
-          b[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (NP * kBM + p * kBN + wn + 32 * i) * kRowBytes + rp);
+          a[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (p * BM + wm + 32 * i) * kRowBytes + rp);
+          b[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (NP * BM + p * kBN + wn + 32 * i) * kRowBytes + rp);
         }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -595,7 +608,7 @@ __global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1
 }
 
 template <int NP>
-void bgemm_np(const BgArgs& a, hipStream_t st) {
+void bgemm_np(BgArgs a, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     if (hipFuncSetAttribute((const void*)k_bgemm<NP>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -603,7 +616,10 @@ void bgemm_np(const BgArgs& a, hipStream_t st) {
       throw Error(TT_EDEVICE, "cannot set the LDS limit of the split-BF16 GEMM");
     attr = true;
   }
-  hipLaunchKernelGGL(k_bgemm<NP>, dim3(a.tiles_m * a.tiles_n), dim3(256), bg_lds_bytes<NP>(), st, a);
+  a.tiles_m = (a.M + BgTraits<NP>::BM - 1) / BgTraits<NP>::BM;
+  a.tiles_n = (a.N + kBN - 1) / kBN;
+  TT_REQUIRE((long long)a.tiles_m * a.tiles_n < (1LL << 31), TT_EINVAL, "bgemm: too many tiles");
+  hipLaunchKernelGGL(k_bgemm<NP>, dim3(a.tiles_m * a.tiles_n), dim3(64 * bg_waves<NP>()), bg_lds_bytes<NP>(), st, a);
 }
 
 }  // namespace
@@ -617,9 +633,6 @@ void launch_bgemm(BgArgs a, int precision, hipStream_t st) {
              TT_EINVAL, "bgemm: operand rows must hold K and start 16-byte aligned");
   TT_REQUIRE(a.cdiv >= 1, TT_EINVAL, "bgemm: bad row map");
   TT_REQUIRE(((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0, TT_EINVAL, "bgemm: operands not 16-byte aligned");
-  a.tiles_m = (a.M + kBM - 1) / kBM;
-  a.tiles_n = (a.N + kBN - 1) / kBN;
-  TT_REQUIRE((long long)a.tiles_m * a.tiles_n < (1LL << 31), TT_EINVAL, "bgemm: too many tiles");
   if (precision == TT_BF16X3) bgemm_np<2>(a, st);
   else bgemm_np<3>(a, st);
   ++g_launches;
