@@ -239,6 +239,114 @@ __global__ __launch_bounds__(64 * bg_waves<NP>()) __attribute__((amdgpu_waves_pe
     }
 }
 
+// bf16x3 with wider waves: each wave's 64 x 128 output as 2 x 4 blocks of the
+// 32x32x16 MFMA with FP32 accumulation over the whole K (the three part
+// products of a 16-deep step added smallest first), eight waves on a
+// 256 x 256 tile, two LDS stages of 64 KB.  Against the 64 x 64 waves with
+// FP64 folding it reads a quarter less LDS and half the global data per flop.
+#ifndef TT_BG_WIDE2
+#define TT_BG_WIDE2 1
+#endif
+constexpr int kWBM = 256, kWBN = 256, kWStage = 2 * (kWBM + kWBN) * kRowBytes;
+
+__device__ __forceinline__ void bgw_issue(const BgArgs& g, char* lds, int st, int kt, int m0, int n0, int wave,
+                                          int lane) {
+  char* base = lds + st * kWStage;
+  const int lc = (lane & 3) ^ (lane >> 4);
+  const long long k = (long long)kt * kBK + 8 * lc;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {   // 32 rows of A and of B per wave, 16 per instruction
+    const int row = 32 * wave + 16 * j + (lane >> 2);
+    const int ma = min(m0 + row, g.M - 1), nb = min(n0 + row, g.N - 1);
+    const __bf16* ga = g.A + (long long)ma * g.lda + k;
+    const __bf16* gb = g.B + (long long)nb * g.ldb + k;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      char* la = base + (p * kWBM + 32 * wave + 16 * j) * kRowBytes;
+      char* lb = base + (2 * kWBM + p * kWBN + 32 * wave + 16 * j) * kRowBytes;
+      __builtin_amdgcn_global_load_lds((const void*)(ga + p * g.sa), (lds_void*)la, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(gb + p * g.sb), (lds_void*)lb, 16, 0, 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_bgemm_wide(BgArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char bgw_lds[];
+  constexpr int LPS = 8;   // global_load_lds per wave per stage
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int blk = bg_xcd_block(blockIdx.x, ntiles);
+  const int per_group = kGroupM * g.tiles_n;
+  const int grp = blk / per_group, first = grp * kGroupM;
+  const int gsz = min(g.tiles_m - first, kGroupM);
+  const int in = blk - grp * per_group;
+  const int tm = first + in % gsz, tn = in / gsz;
+  const int m0 = tm * kWBM, n0 = tn * kWBN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
+
+  float16_t part[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[i][j] = (float16_t){};
+
+  const int nk = g.K / kBK;
+  if (nk > 0) bgw_issue(g, bgw_lds, 0, 0, m0, n0, wave, lane);
+  const int rpos0 = r * kRowBytes + 16 * ((0 + h) ^ ((r >> 2) & 3));
+  const int rpos1 = r * kRowBytes + 16 * ((2 + h) ^ ((r >> 2) & 3));
+  auto mf = [](bf16x8_t x, bf16x8_t y, float16_t t) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, t, 0, 0, 0); };
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));   // this wave's loads of tile kt
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kt + 1 < nk) bgw_issue(g, bgw_lds, (kt + 1) & 1, kt + 1, m0, n0, wave, lane);
+    const char* base = bgw_lds + (kt & 1) * kWStage;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int rp = st ? rpos1 : rpos0;
+      bf16x8_t a[2][2], b[4][2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          a[i][p] = *reinterpret_cast<const bf16x8_t*>(base + (p * kWBM + wm + 32 * i) * kRowBytes + rp);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          b[j][p] = *reinterpret_cast<const bf16x8_t*>(base + (2 * kWBM + p * kWBN + wn + 32 * j) * kRowBytes + rp);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[i][j] = bg_products<2>(a[i], b[j], part[i][j], mf);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (m >= g.M) continue;
+      const long long row = (long long)(m / g.cdiv) * g.ldc1 + (long long)(m % g.cdiv) * g.ldc0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn + 32 * j + r;
+        if (n >= g.N) continue;
+        const double val = part[i][j][v];
+        if (g.cplanes) {
+          __bf16 parts[3];
+          bg_split<2>(val, parts);
+          __bf16* c = reinterpret_cast<__bf16*>(g.C) + row + n;
+          c[0] = parts[0];
+          c[g.sc] = parts[1];
+        } else {
+          reinterpret_cast<double*>(g.C)[row + n] = val;
+        }
+      }
+    }
+}
+
 // out[p][r * ldo + k] = part p of x[r * ldx + k] for k < K, zero for K <= k < ldo
 template <int NP>
 __global__ __launch_bounds__(256) void k_split_rows(const double* __restrict__ x, long long rows, int K, long long ldx,
@@ -633,8 +741,26 @@ void launch_bgemm(BgArgs a, int precision, hipStream_t st) {
              TT_EINVAL, "bgemm: operand rows must hold K and start 16-byte aligned");
   TT_REQUIRE(a.cdiv >= 1, TT_EINVAL, "bgemm: bad row map");
   TT_REQUIRE(((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0, TT_EINVAL, "bgemm: operands not 16-byte aligned");
-  if (precision == TT_BF16X3) bgemm_np<2>(a, st);
-  else bgemm_np<3>(a, st);
+  // the 256 x 256 tiles only when they give every CU one: below that the
+  // 128 x 128 form's four times as many workgroups win
+  const long long wide_tiles = (long long)((a.M + kWBM - 1) / kWBM) * ((a.N + kWBN - 1) / kWBN);
+  if (precision == TT_BF16X3 && TT_BG_WIDE2 && wide_tiles >= 256) {
+    static bool attr = false;
+    if (!attr) {
+      if (hipFuncSetAttribute((const void*)k_bgemm_wide, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kWStage) !=
+          hipSuccess)
+        throw Error(TT_EDEVICE, "cannot set the LDS limit of the split-BF16 GEMM");
+      attr = true;
+    }
+    a.tiles_m = (a.M + kWBM - 1) / kWBM;
+    a.tiles_n = (a.N + kWBN - 1) / kWBN;
+    TT_REQUIRE((long long)a.tiles_m * a.tiles_n < (1LL << 31), TT_EINVAL, "bgemm: too many tiles");
+    hipLaunchKernelGGL(k_bgemm_wide, dim3(a.tiles_m * a.tiles_n), dim3(512), 2 * kWStage, st, a);
+  } else if (precision == TT_BF16X3) {
+    bgemm_np<2>(a, st);
+  } else {
+    bgemm_np<3>(a, st);
+  }
   ++g_launches;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(TT_EDEVICE, hipGetErrorString(e));
