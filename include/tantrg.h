@@ -298,7 +298,9 @@ int tt_state_load(const char* path, tt_state** out);
  * transposed): FP64 copies (TT_FP64), copies rounded to FP32 (TT_FP32, FP32
  * multiplies, partial sums added in FP64), or BF16 planes (the split-BF16
  * precisions: each element split once into 2 or 3 BF16 parts, 3 or 6 part
- * products).  The W stage runs on the matrix cores between them.  T1 and T2
+ * products; bf16x6 adds its partial sums in FP64, bf16x3 accumulates in FP32
+ * on launches large enough for its 256 x 256 tiles).  The W stage runs on the
+ * matrix cores between them.  T1 and T2
  * are kept in the precision's storage (FP64, FP32 or planes).  For DH > 20
  * the FP64 and FP32 modes use the grouped-GEMM path of the sweep instead.
  * Workspace of about 8*(Dl*DH*16*Dr)*2 bytes plus the padded copies is kept
