@@ -441,6 +441,8 @@ def main():
     ap.add_argument("--heff-D", type=int, default=2000)
     ap.add_argument("--heff-reps", type=int, default=5)
     ap.add_argument("--heff-precisions", default="fp64,fp32,bf16x6,bf16x3")
+    ap.add_argument("--d4000", default="os10x10",
+                    help="D=4000 workloads to time one FP64 and one FP32 sweep of ('' for none; os10x10, cl8x16)")
     ap.add_argument("--heff-only", action="store_true",
                     help="only the dense apply microbenchmark (--heff-D, --heff-precisions), one JSON line")
     ap.add_argument("--heff2-D", type=int, default=256,
@@ -608,6 +610,38 @@ def main():
         su, stu, _, obu, (_, dims_u, _), _ = timed_sweeps(args.precision, args.uncapped_steps, 1, False, cap=0)
         uncapped = dict(s_per_step=su, steps=args.uncapped_steps, warmup=1, max_bond=max(dims_u),
                         flops_alg_per_step=statistics.mean(x.flops_alg for x in stu), f=obu["f"], e=obu["e"])
+
+    # the D=4000 lattices (the 10x10 open square by default): one sweep in FP64
+    # and one in the FP32 mode, each after a warmup sweep and from a state of its
+    # own (12-13 GB of site tensors and environments, resident in HBM)
+    d4000 = {}
+    for wname in [x for x in args.d4000.split(",") if x]:
+        c5 = WL.MODELS[wname]
+        m5 = T.model(c5["W"], c5["L"], c5["geometry"], c5["t"], c5["U"], c5["mu"])
+        res = dict(workload="%s, U=%g, mu=%g, U(1)xU(1) D=%d (sector cap %d), d_beta=%g, Krylov %d"
+                   % (wname, c5["U"], c5["mu"], c5["D"], args.sector_cap, c5["dbeta"], c5["krylov"]))
+        for pname in ("fp64", "fp32"):
+            o5 = T.options(D=c5["D"], symmetry=1, beta0=c5["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c5["krylov"],
+                           precision=PREC[pname], sector_cap=args.sector_cap)
+            print("init %s D=%d %s" % (wname, c5["D"], pname), file=sys.stderr, flush=True)
+            st5 = T.State.init(m5, o5)
+            st5.tune_apply(args.apply_form)
+            st5.sweep(c5["dbeta"])
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            s5 = st5.sweep(c5["dbeta"], stats=True)
+            torch.cuda.synchronize()
+            dt5 = time.perf_counter() - t5
+            ob5 = st5.observables()
+            res[pname] = dict(s_per_step=dt5, tflops_alg=s5.flops_alg / dt5 / 1e12,
+                              frac_fp64_mfma=s5.flops_alg / dt5 / 1e12 / PEAK["fp64"], f=ob5["f"], e=ob5["e"],
+                              max_bond=max(st5.info()[1]))
+            st5.free()
+            print("%s %s sweep: %.2f s" % (wname, pname, dt5), file=sys.stderr, flush=True)
+        res["fp32"]["speedup_vs_fp64"] = res["fp64"]["s_per_step"] / res["fp32"]["s_per_step"]
+        res["fp32"]["rel_de_vs_fp64"] = abs(res["fp32"]["e"] - res["fp64"]["e"]) / max(abs(res["fp64"]["e"]), 1e-2)
+        res["fp32"]["rel_df_vs_fp64"] = abs(res["fp32"]["f"] - res["fp64"]["f"]) / max(abs(res["fp64"]["f"]), 1e-2)
+        d4000[wname] = res
 
     # dominant single kernel of the timed region and its roofline.  A
     # contraction kernel (grouped GEMM) is priced against the MFMA peak of the
@@ -787,7 +821,7 @@ def main():
                   "phase_ms_per_step": phases,
                   "apply_forms": forms_info,
                   "kernels": kernels, "beta_end": obs["beta"], "f": obs["f"], "e": obs["e"],
-                  "thermo": thermo, "other_precisions": mixed, "uncapped": uncapped},
+                  "thermo": thermo, "other_precisions": mixed, "uncapped": uncapped, "d4000": d4000},
         "heff": {"D": args.heff_D, "D_H": 18, **heff},
         "mu_scan": mu_scan,
         "tdvp2": tdvp2,
