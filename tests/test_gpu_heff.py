@@ -112,3 +112,16 @@ def test_heff_apply_mixed_d256(prec):
     got = _apply_gpu(L, W, A, R, prec)
     want = otd.heff1(L, W, R, A)
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < MIXED_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [T.TT_FP64, T.TT_FP32, T.TT_BF16X3, T.TT_BF16X6])
+def test_heff_apply_wide_mpo_takes_the_grouped_path(prec):
+    """D_H above what the W-stage kernel on the matrix cores holds (20): the
+    FP64 and FP32 modes run the grouped GEMMs, the split-BF16 modes the grouped
+    W stage on planes (whose K padding of T2 is cleared first)."""
+    print("heff D_H 22", prec, flush=True)
+    L, W, A, R = WL.heff_inputs_rect(24, 20, 22, 11)
+    got = _apply_gpu(L, W, A, R, prec)
+    want = otd.heff1(L, W, R, A)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err < (1e-13 if prec == T.TT_FP64 else MIXED_TOL[prec]), err
