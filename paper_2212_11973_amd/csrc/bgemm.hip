@@ -623,12 +623,16 @@ __global__ __launch_bounds__(256) void k_pad_t(const double* __restrict__ x, int
 // 128-byte runs of y.  NP = 0: FP64 T1 and T2 (f64 MFMA 16x16x4); NP = 1: FP32
 // T1 and T2; NP = 2, 3: BF16 planes; NP >= 1 multiply in FP32 (f32 MFMA
 // 16x16x4, W rounded to FP32, the parts of a T1 element summed smallest first).  T2's K padding is written as
-// zeros.  One workgroup per (x', sp); its four waves take every fourth block
-// of 16 y.
+// zeros.  One workgroup per (x', sp); a wave takes kWsYB adjacent blocks of
+// 16 y at a time (their loads in flight together, each W operand read once
+// for all of them), the four waves every fourth such group.  Measured at
+// D = 2000: FP64 5.7 ms with two blocks (7.3 with one, 8.7 with four, where
+// the accumulators leave one wave per SIMD), planes 4.3 ms with four (4.8 with one).
 template <int NP>
 __global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1v, long long sT1,
                                                      const double* __restrict__ W, int DH, int Dl, int Dr,
                                                      void* __restrict__ T2v, long long sT2, long long kp3) {
+  constexpr int kWsYB = NP == 0 ? 2 : 4;
   using E = typename std::conditional<NP == 0, double, float>::type;
   using E4 = typename std::conditional<NP == 0, double4_t, float4_t>::type;
   constexpr int OB = kWsMaxO / 16;
@@ -662,56 +666,68 @@ __global__ __launch_bounds__(256) void k_wstage_mfma(const void* __restrict__ T1
   // this lane's B element for a = t: T1[t][x'][g][sp][y]
   const long long base = (long long)x * N1 + (long long)g * 4 * Dr + (long long)sp * Dr;
   const long long astep = (long long)Dl * N1;
-  for (int yb = wave; 16 * yb < Dr; yb += 4) {
-    const int y = 16 * yb + r, yc = min(y, Dr - 1);
-    E4 acc[OB];
+  for (int yb0 = kWsYB * wave; 16 * yb0 < Dr; yb0 += 4 * kWsYB) {
+    E4 acc[kWsYB][OB];
 #pragma unroll
-    for (int ob = 0; ob < OB; ++ob) acc[ob] = (E4){0, 0, 0, 0};
-#pragma unroll 3
+    for (int s = 0; s < kWsYB; ++s)
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) acc[s][ob] = (E4){0, 0, 0, 0};
+#pragma unroll 2
     for (int t = 0; t < DH; ++t) {
-      const long long e = base + t * astep + yc;
-      E bv;
-      if constexpr (NP == 0) {
-        bv = reinterpret_cast<const double*>(T1v)[e];
-      } else if constexpr (NP == 1) {
-        bv = reinterpret_cast<const float*>(T1v)[e];
-      } else {
-        const __bf16* t1 = reinterpret_cast<const __bf16*>(T1v);
-        float f = 0.f;
+      E bv[kWsYB];
 #pragma unroll
-        for (int p = NP - 1; p >= 0; --p) f += (float)t1[p * sT1 + e];
-        bv = f;
+      for (int s = 0; s < kWsYB; ++s) {
+        const long long e = base + t * astep + min(16 * (yb0 + s) + r, Dr - 1);
+        if constexpr (NP == 0) {
+          bv[s] = reinterpret_cast<const double*>(T1v)[e];
+        } else if constexpr (NP == 1) {
+          bv[s] = reinterpret_cast<const float*>(T1v)[e];
+        } else {
+          const __bf16* t1 = reinterpret_cast<const __bf16*>(T1v);
+          float f = 0.f;
+#pragma unroll
+          for (int p = NP - 1; p >= 0; --p) f += (float)t1[p * sT1 + e];
+          bv[s] = f;
+        }
       }
       const E* wr = wl + (4 * t + g) * kWsMaxO + r;
 #pragma unroll
       for (int ob = 0; ob < OB; ++ob)
         if (ob < nob) {
-          if constexpr (NP == 0) acc[ob] = __builtin_amdgcn_mfma_f64_16x16x4f64(wr[16 * ob], bv, acc[ob], 0, 0, 0);
-          else acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[16 * ob], bv, acc[ob], 0, 0, 0);
-        }
-    }
-    if (y >= Dr) continue;
+          const E wv = wr[16 * ob];
 #pragma unroll
-    for (int ob = 0; ob < OB; ++ob)
-      if (ob < nob)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          // accumulator row: g + 4 v (f64 MFMA), 4 g + v (f32 MFMA)
-          const int o = 16 * ob + (NP == 0 ? g + 4 * v : 4 * g + v);
-          if (o >= KO) continue;
-          const int so = o / DH, b = o - so * DH;
-          const long long e = (long long)(16 * x + 4 * so + sp) * kp3 + (long long)b * Dr + y;
-          if constexpr (NP == 0) {
-            reinterpret_cast<double*>(T2v)[e] = acc[ob][v];
-          } else if constexpr (NP == 1) {
-            reinterpret_cast<float*>(T2v)[e] = acc[ob][v];
-          } else {
-            __bf16 parts[3];
-            bg_split<NP>((double)acc[ob][v], parts);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) reinterpret_cast<__bf16*>(T2v)[p * sT2 + e] = parts[p];
+          for (int s = 0; s < kWsYB; ++s) {
+            if constexpr (NP == 0) acc[s][ob] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, bv[s], acc[s][ob], 0, 0, 0);
+            else acc[s][ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, bv[s], acc[s][ob], 0, 0, 0);
           }
         }
+    }
+#pragma unroll
+    for (int s = 0; s < kWsYB; ++s) {
+      const int y = 16 * (yb0 + s) + r;
+      if (y >= Dr) continue;
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob)
+        if (ob < nob)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            // accumulator row: g + 4 v (f64 MFMA), 4 g + v (f32 MFMA)
+            const int o = 16 * ob + (NP == 0 ? g + 4 * v : 4 * g + v);
+            if (o >= KO) continue;
+            const int so = o / DH, b = o - so * DH;
+            const long long e = (long long)(16 * x + 4 * so + sp) * kp3 + (long long)b * Dr + y;
+            if constexpr (NP == 0) {
+              reinterpret_cast<double*>(T2v)[e] = acc[s][ob][v];
+            } else if constexpr (NP == 1) {
+              reinterpret_cast<float*>(T2v)[e] = acc[s][ob][v];
+            } else {
+              __bf16 parts[3];
+              bg_split<NP>((double)acc[s][ob][v], parts);
+#pragma unroll
+              for (int p = 0; p < NP; ++p) reinterpret_cast<__bf16*>(T2v)[p * sT2 + e] = parts[p];
+            }
+          }
+    }
   }
 }
 
