@@ -113,7 +113,7 @@ void upload_plan(QRPlan& p, hipStream_t st) {
   for (auto& t : p.tasks) {
     TT_REQUIRE(t.m >= t.n, TT_ENUMERIC, "QR of a charge block with more columns than rows");
     t.ws = pos;
-    pos += 2LL * t.m * t.n + t.n;
+    pos += qr_wide_ws(t.m, t.n);
   }
   p.ws_size = pos;
   qr_plan_chunks(p);
@@ -1199,7 +1199,7 @@ long long check_qr(const QRPlan& p, const std::vector<long long>& tabs, long lon
     long long lo = t.rbase + r.lo, hi = t.rbase + r.hi + (long long)(t.n - 1) * t.cs;
     if (lo < 0 || hi >= a_size) ++bad;
     if (t.sdst < 0 || t.sdst + (long long)t.n * t.n > s_size) ++bad;
-    ws += 2LL * t.m * t.n + t.n;
+    ws += qr_wide_ws(t.m, t.n);
   }
   (void)ws;
   QRPlan q = p;

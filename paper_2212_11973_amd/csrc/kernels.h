@@ -143,6 +143,8 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, BPtr<double> A, BPtr<do
                hipStream_t st);
 // split the tasks of a plan into LDS chunks and stacks (host)
 void qr_plan_chunks(QRPlan& p);
+// workspace doubles of a block that the global-memory (wide) QR factors
+long long qr_wide_ws(int m, int n);
 
 // Lanczos pieces (see engine for the sequence)
 void launch_mdot(BPtr<const double> Q, long long ld, int nv, BPtr<const double> y, long long n, int with_self,

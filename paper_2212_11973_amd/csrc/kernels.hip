@@ -1277,177 +1277,221 @@ __device__ double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ QR
 // Householder QR of a block wider than the register kernels take, in global
-// memory, one workgroup per block, blocked in panels of kQrPanel columns
-// (compact WY form, I - V T V^T for the product of a panel's reflectors):
-// the panel's columns are factored one by one with the reflectors applied
-// inside the panel, its T factor is formed from the Gram matrix of V, and every
-// later column gets the whole panel's product in two passes (the kQrPanel dot
+// memory, blocked in panels of kQrPanel columns (compact WY form, I - V T V^T
+// for the product of a panel's reflectors): the panel's columns are factored
+// one by one with the reflectors applied inside the panel (one workgroup per
+// block), its T factor is formed from the Gram matrix of V, and every later
+// column gets the whole panel's product in two passes (the kQrPanel dot
 // products, then the update), instead of one pass per reflector.  Q is formed
 // explicitly the same way, panels in reverse order.  Same reflectors as the
-// column-by-column algorithm; only the order of the sums differs.
+// column-by-column algorithm; only the order of the sums differs.  The
+// updates of the later columns and of Q spread over the GPU: one launch per
+// panel step, kQrApplyCols columns per workgroup, one wave per column, every
+// column's arithmetic independent of which workgroup takes it.
+// Workspace of a task (ws + T.ws, qr_wide_ws doubles): Wm (m x n column-major:
+// R above the diagonal, reflectors below), Qm (m x n), the n taus, then the
+// T factor of every panel (kQrPanel x kQrPanel, row-major, zero past the panel).
+// The launches take blockIdx.x = wide block, blockIdx.z = state of the batch.
 constexpr int kQrPanel = 8;
-__global__ __launch_bounds__(256) void k_qr_wide(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
-                                                 const long long* __restrict__ tabs, BPtr<double> b_A, BPtr<double> b_S,
-                                                 BPtr<double> b_ws) {
-  double* A = b_A.p[blockIdx.y];
-  double* S = b_S.p[blockIdx.y];
-  double* ws = b_ws.p[blockIdx.y];
-  __shared__ double red[8];
-  __shared__ double Tm[kQrPanel][kQrPanel];   // T of the current panel (upper triangular)
-  __shared__ double Gm[kQrPanel][kQrPanel];   // V^T V of the current panel (strict upper part)
+constexpr int kQrApplyCols = 8;
+constexpr int kQrSpread = 64;   // workgroups per block of the copy-in and copy-out launches
+long long qr_wide_ws(int m, int n) {
+  return 2LL * m * n + n + (long long)((n + kQrPanel - 1) / kQrPanel) * kQrPanel * kQrPanel;
+}
+__device__ __forceinline__ double* qrw_tfac(double* Wm, int m, int n, int j0) {
+  return Wm + 2LL * m * n + n + (long long)(j0 / kQrPanel) * kQrPanel * kQrPanel;
+}
+__device__ __forceinline__ long long qrw_row(const QRTask& T, const long long* tabs, int i) {
+  return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs;
+}
+
+// column col <- (I - V T' V^T) col for the panel at j0 (T' = T^T with trans)
+// by one wave: w = V^T col over the rows >= j0, u = T' w, col -= V u.  Rows
+// j0 .. j0 + pb - 1 hold the unit diagonal of V (one lane each); below them
+// every v_r is a stored column of Wm.
+__device__ void qrw_apply_col(const double* __restrict__ Wm, int m, int j0, int pb,
+                              const double (*Tm)[kQrPanel], double* col, bool trans) {
+  const int lane = threadIdx.x & 63;
+  double w[kQrPanel];
+#pragma unroll
+  for (int r = 0; r < kQrPanel; ++r) w[r] = 0.0;
+  const double* V = Wm + (long long)j0 * m;
+  for (int i = j0 + pb + lane; i < m; i += 64) {
+    const double x = col[i];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? V[i + (long long)r * m] : 0.0) * x;
+  }
+  if (lane < pb) {
+    const int i = j0 + lane;
+    const double x = col[i];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r)
+      w[r] += (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * x;
+  }
+  double u[kQrPanel];
+#pragma unroll
+  for (int r = 0; r < kQrPanel; ++r) w[r] = __shfl(wave_sum(w[r]), 0, 64);
+#pragma unroll
+  for (int r = 0; r < kQrPanel; ++r) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQrPanel; ++q) t += (trans ? Tm[q][r] : Tm[r][q]) * w[q];
+    u[r] = t;
+  }
+  for (int i = j0 + pb + lane; i < m; i += 64) {
+    double x = col[i];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) x -= (r < pb ? V[i + (long long)r * m] : 0.0) * u[r];
+    col[i] = x;
+  }
+  if (lane < pb) {
+    const int i = j0 + lane;
+    double x = col[i];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) x -= (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * u[r];
+    col[i] = x;
+  }
+}
+
+// Wm, Qm of every wide block of the launch: Wm the block, Qm = [I; 0]
+__global__ __launch_bounds__(256) void k_qrw_load(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
+                                                  const long long* __restrict__ tabs, BPtr<const double> b_A,
+                                                  BPtr<double> b_ws) {
+  const double* A = b_A.p[blockIdx.z];
   const QRTask T = tasks[wide[blockIdx.x]];
-  const int m = T.m, n = T.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* Wm = ws + T.ws;                 // m x n column-major: R above the diagonal, reflectors below
-  double* Qm = Wm + (long long)m * n;     // m x n column-major
-  double* taus = Qm + (long long)m * n;   // n
-  auto row = [&](int i) -> long long { return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs; };
-  for (long long e = tid; e < (long long)m * n; e += blockDim.x) {
-    int i = (int)(e % m), j = (int)(e / m);
-    Wm[e] = A[T.rbase + row(i) + (long long)j * T.cs];
-  }
-  __syncthreads();
-  // the panel's T from tau and G = V^T V: T_ii = tau_i,
-  // T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-  auto make_t = [&](int j0, int pb) {
-    for (int e = wave; e < pb * pb; e += 4) {   // one wave per pair (r < i)
-      const int r = e / pb, i = e % pb;
-      if (r >= i) continue;
-      const int ji = j0 + i;
-      const double* vr = Wm + (long long)(j0 + r) * m;
-      const double* vi = Wm + (long long)ji * m;
-      double d = 0.0;
-      for (int q = ji + 1 + lane; q < m; q += 64) d += vr[q] * vi[q];
-      d = wave_sum(d);
-      if (lane == 0) Gm[r][i] = d + vr[ji];   // v_i[ji] = 1
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int i = 0; i < pb; ++i) {
-        const double ti = taus[j0 + i];
-        for (int r = 0; r < i; ++r) {
-          double t = 0.0;
-          for (int q = r; q < i; ++q) t += Tm[r][q] * Gm[q][i];
-          Tm[r][i] = -ti * t;
-        }
-        Tm[i][i] = ti;
-        for (int r = i + 1; r < kQrPanel; ++r) Tm[r][i] = 0.0;
-      }
-      for (int i = pb; i < kQrPanel; ++i)
-        for (int r = 0; r < kQrPanel; ++r) Tm[r][i] = 0.0;
-    }
-    __syncthreads();
-  };
-  // column col <- (I - V T' V^T) col for the panel at j0 (T' = T^T with trans)
-  // by one wave: w = V^T col over the rows >= j0, u = T' w, col -= V u.  Rows
-  // j0 .. j0 + pb - 1 hold the unit diagonal of V (one lane each); below them
-  // every v_r is a stored column.
-  auto apply_panel = [&](int j0, int pb, double* col, bool trans) {
-    double w[kQrPanel];
-#pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) w[r] = 0.0;
-    const double* V = Wm + (long long)j0 * m;
-    for (int i = j0 + pb + lane; i < m; i += 64) {
-      const double x = col[i];
-#pragma unroll
-      for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? V[i + (long long)r * m] : 0.0) * x;
-    }
-    if (lane < pb) {
-      const int i = j0 + lane;
-      const double x = col[i];
-#pragma unroll
-      for (int r = 0; r < kQrPanel; ++r)
-        w[r] += (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * x;
-    }
-    double u[kQrPanel];
-#pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) w[r] = __shfl(wave_sum(w[r]), 0, 64);
-#pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) {
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < kQrPanel; ++q) t += (trans ? Tm[q][r] : Tm[r][q]) * w[q];
-      u[r] = t;
-    }
-    for (int i = j0 + pb + lane; i < m; i += 64) {
-      double x = col[i];
-#pragma unroll
-      for (int r = 0; r < kQrPanel; ++r) x -= (r < pb ? V[i + (long long)r * m] : 0.0) * u[r];
-      col[i] = x;
-    }
-    if (lane < pb) {
-      const int i = j0 + lane;
-      double x = col[i];
-#pragma unroll
-      for (int r = 0; r < kQrPanel; ++r) x -= (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * u[r];
-      col[i] = x;
-    }
-  };
-  for (int j0 = 0; j0 < n; j0 += kQrPanel) {
-    const int pb = min(kQrPanel, n - j0);
-    for (int j = j0; j < j0 + pb; ++j) {   // the panel, one column at a time
-      double part = 0.0;
-      for (int i = j + 1 + tid; i < m; i += blockDim.x) {
-        double x = Wm[i + (long long)j * m];
-        part += x * x;
-      }
-      double xn2 = block_sum(part, red);
-      double alpha = Wm[j + (long long)j * m];
-      double tau = 0.0;
-      if (xn2 > 0.0) {
-        double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        tau = (beta - alpha) / beta;
-        double scal = 1.0 / (alpha - beta);
-        for (int i = j + 1 + tid; i < m; i += blockDim.x) Wm[i + (long long)j * m] *= scal;
-        __syncthreads();
-        if (tid == 0) Wm[j + (long long)j * m] = beta;
-      }
-      if (tid == 0) taus[j] = tau;
-      __syncthreads();
-      if (tau != 0.0) {
-        for (int c = j + 1 + wave; c < j0 + pb; c += 4) {
-          double* col = Wm + (long long)c * m;
-          const double* v = Wm + (long long)j * m;
-          double d = 0.0;
-          for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-          d = wave_sum(d);
-          d = __shfl(d, 0, 64) + col[j];
-          double f = tau * d;
-          if (lane == 0) col[j] -= f;
-          for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
-        }
-      }
-      __syncthreads();
-    }
-    if (j0 + pb < n) {   // the rest of the matrix: Q_panel^T = I - V T^T V^T
-      make_t(j0, pb);
-      for (int c = j0 + pb + wave; c < n; c += 4) apply_panel(j0, pb, Wm + (long long)c * m, true);
-      __syncthreads();
-    }
-  }
-  // explicit Q = H_0 ... H_{n-1} [I; 0]: Q <- (I - V T V^T) Q panel by panel
-  // from the last, on the columns >= j0 (earlier columns of Q are still unit
-  // vectors that the panel's reflectors leave unchanged)
-  for (long long e = tid; e < (long long)m * n; e += blockDim.x) {
-    int i = (int)(e % m), j = (int)(e / m);
+  const int m = T.m, n = T.n;
+  double* Wm = b_ws.p[blockIdx.z] + T.ws;
+  double* Qm = Wm + (long long)m * n;
+  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < (long long)m * n;
+       e += (long long)gridDim.y * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    Wm[e] = A[T.rbase + qrw_row(T, tabs, i) + (long long)j * T.cs];
     Qm[e] = (i == j) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  for (int j0 = ((n - 1) / kQrPanel) * kQrPanel; j0 >= 0; j0 -= kQrPanel) {
-    const int pb = min(kQrPanel, n - j0);
-    make_t(j0, pb);
-    for (int c = j0 + wave; c < n; c += 4) apply_panel(j0, pb, Qm + (long long)c * m, false);
+}
+
+// the panel at j0 of every wide block with more than j0 columns, one
+// workgroup each: its columns factored one by one, then its T factor from tau
+// and G = V^T V (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i])
+// stored for the later updates
+__global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
+                                                   BPtr<double> b_ws, int j0) {
+  const QRTask T = tasks[wide[blockIdx.x]];
+  const int m = T.m, n = T.n;
+  if (j0 >= n) return;
+  const int pb = min(kQrPanel, n - j0), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Wm = b_ws.p[blockIdx.z] + T.ws;
+  double* taus = Wm + 2LL * m * n;
+  __shared__ double red[8];
+  __shared__ double Tm[kQrPanel][kQrPanel];
+  __shared__ double Gm[kQrPanel][kQrPanel];
+  for (int j = j0; j < j0 + pb; ++j) {
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+      double x = Wm[i + (long long)j * m];
+      part += x * x;
+    }
+    double xn2 = block_sum(part, red);
+    double alpha = Wm[j + (long long)j * m];
+    double tau = 0.0;
+    if (xn2 > 0.0) {
+      double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      double scal = 1.0 / (alpha - beta);
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) Wm[i + (long long)j * m] *= scal;
+      __syncthreads();
+      if (tid == 0) Wm[j + (long long)j * m] = beta;
+    }
+    if (tid == 0) taus[j] = tau;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int c = j + 1 + wave; c < j0 + pb; c += 4) {
+        double* col = Wm + (long long)c * m;
+        const double* v = Wm + (long long)j * m;
+        double d = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
+        d = wave_sum(d);
+        d = __shfl(d, 0, 64) + col[j];
+        double f = tau * d;
+        if (lane == 0) col[j] -= f;
+        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+      }
+    }
     __syncthreads();
   }
-  // non-negative diagonal: flip column j of Q and row j of R when R_jj < 0
-  for (long long e = tid; e < (long long)m * n; e += blockDim.x) {
-    int i = (int)(e % m), j = (int)(e / m);
-    double sg = Wm[j + (long long)j * m] < 0.0 ? -1.0 : 1.0;
-    A[T.rbase + row(i) + (long long)j * T.cs] = sg * Qm[e];
+  for (int e = wave; e < pb * pb; e += 4) {   // G: one wave per pair (r < i)
+    const int r = e / pb, i = e % pb;
+    if (r >= i) continue;
+    const int ji = j0 + i;
+    const double* vr = Wm + (long long)(j0 + r) * m;
+    const double* vi = Wm + (long long)ji * m;
+    double d = 0.0;
+    for (int q = ji + 1 + lane; q < m; q += 64) d += vr[q] * vi[q];
+    d = wave_sum(d);
+    if (lane == 0) Gm[r][i] = d + vr[ji];   // v_i[ji] = 1
   }
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    int i = e / n, j = e % n;
-    double sg = Wm[i + (long long)i * m] < 0.0 ? -1.0 : 1.0;
-    double val = (i <= j) ? sg * Wm[i + (long long)j * m] : 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < pb; ++i) {
+      const double ti = taus[j0 + i];
+      for (int r = 0; r < i; ++r) {
+        double t = 0.0;
+        for (int q = r; q < i; ++q) t += Tm[r][q] * Gm[q][i];
+        Tm[r][i] = -ti * t;
+      }
+      Tm[i][i] = ti;
+      for (int r = i + 1; r < kQrPanel; ++r) Tm[r][i] = 0.0;
+    }
+    for (int i = pb; i < kQrPanel; ++i)
+      for (int r = 0; r < kQrPanel; ++r) Tm[r][i] = 0.0;
+  }
+  __syncthreads();
+  if (tid < kQrPanel * kQrPanel) qrw_tfac(Wm, m, n, j0)[tid] = Tm[tid / kQrPanel][tid % kQrPanel];
+}
+
+// the panel at j0 applied to kQrApplyCols columns per workgroup (group
+// blockIdx.y): qmode 0, the columns of Wm after the panel, with Q_panel^T =
+// I - V T^T V^T; qmode 1, the columns >= j0 of Qm, with I - V T V^T (Q's
+// earlier columns are unit vectors that the panel's reflectors leave alone)
+__global__ __launch_bounds__(256) void k_qrw_apply(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
+                                                   BPtr<double> b_ws, int j0, int qmode) {
+  const QRTask T = tasks[wide[blockIdx.x]];
+  const int m = T.m, n = T.n;
+  if (j0 >= n) return;
+  const int pb = min(kQrPanel, n - j0), wave = threadIdx.x >> 6;
+  const int c0 = (qmode ? j0 : j0 + pb) + kQrApplyCols * (int)blockIdx.y;
+  if (c0 >= n) return;   // uniform over the workgroup
+  double* Wm = b_ws.p[blockIdx.z] + T.ws;
+  double* base = qmode ? Wm + (long long)m * n : Wm;
+  __shared__ double Tm[kQrPanel][kQrPanel];
+  const double* tf = qrw_tfac(Wm, m, n, j0);
+  if (threadIdx.x < kQrPanel * kQrPanel) Tm[threadIdx.x / kQrPanel][threadIdx.x % kQrPanel] = tf[threadIdx.x];
+  __syncthreads();
+  const int c1 = min(n, c0 + kQrApplyCols);
+  for (int c = c0 + wave; c < c1; c += 4) qrw_apply_col(Wm, m, j0, pb, Tm, base + (long long)c * m, !qmode);
+}
+
+// non-negative diagonal: column j of Q and row j of R flipped when R_jj < 0;
+// Q into the block's place in A, R into S
+__global__ __launch_bounds__(256) void k_qrw_out(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
+                                                 const long long* __restrict__ tabs, BPtr<double> b_A,
+                                                 BPtr<double> b_S, BPtr<const double> b_ws) {
+  double* A = b_A.p[blockIdx.z];
+  double* S = b_S.p[blockIdx.z];
+  const QRTask T = tasks[wide[blockIdx.x]];
+  const int m = T.m, n = T.n;
+  const double* Wm = b_ws.p[blockIdx.z] + T.ws;
+  const double* Qm = Wm + (long long)m * n;
+  const long long stride = (long long)gridDim.y * blockDim.x, e0 = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+  for (long long e = e0; e < (long long)m * n; e += stride) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double sg = Wm[j + (long long)j * m] < 0.0 ? -1.0 : 1.0;
+    A[T.rbase + qrw_row(T, tabs, i) + (long long)j * T.cs] = sg * Qm[e];
+  }
+  for (long long e = e0; e < (long long)n * n; e += stride) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const double sg = Wm[i + (long long)i * m] < 0.0 ? -1.0 : 1.0;
+    const double val = (i <= j) ? sg * Wm[i + (long long)j * m] : 0.0;
     S[T.sdst + (T.trans ? (long long)j * n + i : (long long)i * n + j)] = val;
   }
 }
@@ -1793,9 +1837,33 @@ void launch_qr(const QRPlan& p, const long long* d_tabs, BPtr<double> A, BPtr<do
                        d_tabs, A, lws);
     HIP_CHECK_LAUNCH();
   }
-  if (!p.wide.empty()) {
-    hipLaunchKernelGGL(k_qr_wide, dim3((unsigned)p.wide.size(), nb), dim3(256), 0, st, p.d_tasks, p.d_wide, d_tabs, A,
-                       S, ws);
+  int maxn = 0;
+  for (int w : p.wide) {
+    const QRTask& t = p.tasks.at(w);
+    TT_REQUIRE(t.m >= t.n && t.ws >= 0 && t.ws + qr_wide_ws(t.m, t.n) <= p.ws_size, TT_EINVAL,
+               "wide QR: a block outside its workspace");
+    maxn = std::max(maxn, t.n);
+  }
+  if (maxn > 0) {
+    const unsigned nw = (unsigned)p.wide.size();
+    auto groups = [](int cols) { return (unsigned)((cols + kQrApplyCols - 1) / kQrApplyCols); };
+    hipLaunchKernelGGL(k_qrw_load, dim3(nw, kQrSpread, nb), dim3(256), 0, st, p.d_tasks, p.d_wide, d_tabs, cst(A), ws);
+    HIP_CHECK_LAUNCH();
+    for (int j0 = 0; j0 < maxn; j0 += kQrPanel) {
+      hipLaunchKernelGGL(k_qrw_panel, dim3(nw, 1, nb), dim3(256), 0, st, p.d_tasks, p.d_wide, ws, j0);
+      HIP_CHECK_LAUNCH();
+      if (maxn - j0 - kQrPanel > 0) {
+        hipLaunchKernelGGL(k_qrw_apply, dim3(nw, groups(maxn - j0 - kQrPanel), nb), dim3(256), 0, st, p.d_tasks,
+                           p.d_wide, ws, j0, 0);
+        HIP_CHECK_LAUNCH();
+      }
+    }
+    for (int j0 = ((maxn - 1) / kQrPanel) * kQrPanel; j0 >= 0; j0 -= kQrPanel) {
+      hipLaunchKernelGGL(k_qrw_apply, dim3(nw, groups(maxn - j0), nb), dim3(256), 0, st, p.d_tasks, p.d_wide, ws, j0,
+                         1);
+      HIP_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_qrw_out, dim3(nw, kQrSpread, nb), dim3(256), 0, st, p.d_tasks, p.d_wide, d_tabs, A, S, cst(ws));
     HIP_CHECK_LAUNCH();
   }
   prof_end(st, PROF_QR, nb * p.flops, nb * p.bytes);
