@@ -1293,7 +1293,7 @@ __device__ double block_sum(double v, double* red) {
 // T factor of every panel (kQrPanel x kQrPanel, row-major, zero past the panel).
 // The launches take blockIdx.x = wide block, blockIdx.z = state of the batch.
 constexpr int kQrPanel = 8;
-constexpr int kQrApplyCols = 8;
+constexpr int kQrApplyCols = 4;   // one column per wave
 constexpr int kQrSpread = 64;   // workgroups per block of the copy-in and copy-out launches
 long long qr_wide_ws(int m, int n) {
   return 2LL * m * n + n + (long long)((n + kQrPanel - 1) / kQrPanel) * kQrPanel * kQrPanel;
@@ -1373,16 +1373,22 @@ __global__ __launch_bounds__(256) void k_qrw_load(const QRTask* __restrict__ tas
 // the panel at j0 of every wide block with more than j0 columns, one
 // workgroup each: its columns factored one by one, then its T factor from tau
 // and G = V^T V (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i])
-// stored for the later updates
+// stored for the later updates.  Every pass over the rows is shared by the
+// whole workgroup (rows strided by the 256 threads): a column step reduces the
+// norm, then the dot products of the reflector with all later columns of the
+// panel at once; G takes one pass for all its pairs.  Sums: per thread, then
+// per wave, then the four waves in order.
 __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
                                                    BPtr<double> b_ws, int j0) {
+  constexpr int kPairs = kQrPanel * (kQrPanel - 1) / 2;
   const QRTask T = tasks[wide[blockIdx.x]];
   const int m = T.m, n = T.n;
   if (j0 >= n) return;
   const int pb = min(kQrPanel, n - j0), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* Wm = b_ws.p[blockIdx.z] + T.ws;
   double* taus = Wm + 2LL * m * n;
-  __shared__ double red[8];
+  __shared__ double red[4 * kPairs];
+  __shared__ double fsh[kQrPanel];
   __shared__ double Tm[kQrPanel][kQrPanel];
   __shared__ double Gm[kQrPanel][kQrPanel];
   for (int j = j0; j < j0 + pb; ++j) {
@@ -1404,31 +1410,75 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
     }
     if (tid == 0) taus[j] = tau;
     __syncthreads();
-    if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < j0 + pb; c += 4) {
-        double* col = Wm + (long long)c * m;
-        const double* v = Wm + (long long)j * m;
-        double d = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) d += v[i] * col[i];
-        d = wave_sum(d);
-        d = __shfl(d, 0, 64) + col[j];
-        double f = tau * d;
-        if (lane == 0) col[j] -= f;
-        for (int i = j + 1 + lane; i < m; i += 64) col[i] -= f * v[i];
+    const int nc = j0 + pb - j - 1;   // later columns of the panel (uniform, as is tau)
+    if (tau != 0.0 && nc > 0) {
+      const double* v = Wm + (long long)j * m;
+      double* c1 = Wm + (long long)(j + 1) * m;
+      double acc[kQrPanel - 1];
+#pragma unroll
+      for (int q = 0; q < kQrPanel - 1; ++q) acc[q] = 0.0;
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+        const double vi = v[i];
+#pragma unroll
+        for (int q = 0; q < kQrPanel - 1; ++q)
+          if (q < nc) acc[q] += vi * c1[i + (long long)q * m];
+      }
+#pragma unroll
+      for (int q = 0; q < kQrPanel - 1; ++q) {
+        if (q >= nc) break;
+        const double sq = wave_sum(acc[q]);
+        if (lane == 0) red[wave * kPairs + q] = sq;
+      }
+      __syncthreads();
+      if (tid < nc) {   // row j of v is 1
+        double* col = c1 + (long long)tid * m;
+        double d = ((red[tid] + red[kPairs + tid]) + red[2 * kPairs + tid]) + red[3 * kPairs + tid];
+        d += col[j];
+        const double f = tau * d;
+        col[j] -= f;
+        fsh[tid] = f;
+      }
+      __syncthreads();
+      double fq[kQrPanel - 1];
+#pragma unroll
+      for (int q = 0; q < kQrPanel - 1; ++q) fq[q] = q < nc ? fsh[q] : 0.0;
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+        const double vi = v[i];
+#pragma unroll
+        for (int q = 0; q < kQrPanel - 1; ++q)
+          if (q < nc) c1[i + (long long)q * m] -= fq[q] * vi;
       }
     }
     __syncthreads();
   }
-  for (int e = wave; e < pb * pb; e += 4) {   // G: one wave per pair (r < i)
-    const int r = e / pb, i = e % pb;
-    if (r >= i) continue;
-    const int ji = j0 + i;
-    const double* vr = Wm + (long long)(j0 + r) * m;
-    const double* vi = Wm + (long long)ji * m;
-    double d = 0.0;
-    for (int q = ji + 1 + lane; q < m; q += 64) d += vr[q] * vi[q];
-    d = wave_sum(d);
-    if (lane == 0) Gm[r][i] = d + vr[ji];   // v_i[ji] = 1
+  // G[r][i] = sum over rows q > j0 + i of v_r[q] v_i[q], plus v_r[j0 + i] (v_i is 1 there);
+  // pair (r < i) at index i (i - 1) / 2 + r
+  double g[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) g[p] = 0.0;
+  for (int q = j0 + 1 + tid; q < m; q += blockDim.x) {
+    double vq[kQrPanel];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) vq[r] = r < pb ? Wm[q + (long long)(j0 + r) * m] : 0.0;
+#pragma unroll
+    for (int i = 1; i < kQrPanel; ++i)
+#pragma unroll
+      for (int r = 0; r < i; ++r)
+        if (q > j0 + i) g[i * (i - 1) / 2 + r] += vq[r] * vq[i];
+  }
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    const double sp = wave_sum(g[p]);
+    if (lane == 0) red[wave * kPairs + p] = sp;
+  }
+  __syncthreads();
+  if (tid < kPairs) {
+    int i = 1;
+    while ((i + 1) * i / 2 <= tid) ++i;
+    const int r = tid - i * (i - 1) / 2;
+    if (i < pb)
+      Gm[r][i] = (((red[tid] + red[kPairs + tid]) + red[2 * kPairs + tid]) + red[3 * kPairs + tid]) +
+                 Wm[(j0 + i) + (long long)(j0 + r) * m];
   }
   __syncthreads();
   if (tid == 0) {
