@@ -1294,6 +1294,7 @@ __device__ double block_sum(double v, double* red) {
 // The launches take blockIdx.x = wide block, blockIdx.z = state of the batch.
 constexpr int kQrPanel = 8;
 constexpr int kQrApplyCols = 4;   // one column per wave
+constexpr int kQrRowU = 4;         // rows per thread whose loads the panel's passes issue together
 constexpr int kQrSpread = 64;   // workgroups per block of the copy-in and copy-out launches
 long long qr_wide_ws(int m, int n) {
   return 2LL * m * n + n + (long long)((n + kQrPanel - 1) / kQrPanel) * kQrPanel * kQrPanel;
@@ -1316,10 +1317,23 @@ __device__ void qrw_apply_col(const double* __restrict__ Wm, int m, int j0, int 
 #pragma unroll
   for (int r = 0; r < kQrPanel; ++r) w[r] = 0.0;
   const double* V = Wm + (long long)j0 * m;
-  for (int i = j0 + pb + lane; i < m; i += 64) {
-    const double x = col[i];
+  // two rows per lane per step, their loads issued together (rows past the
+  // end clamped to the last one, their products not taken)
+  for (int i0 = j0 + pb + lane; i0 < m; i0 += 2 * 64) {
+    double x[2], vv[2][kQrPanel];
 #pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? V[i + (long long)r * m] : 0.0) * x;
+    for (int u = 0; u < 2; ++u) {
+      const int i = min(i0 + 64 * u, m - 1);
+      x[u] = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) vv[u][r] = V[i + (long long)min(r, pb - 1) * m];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (i0 + 64 * u < m) {
+#pragma unroll
+        for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? vv[u][r] : 0.0) * x[u];
+      }
   }
   if (lane < pb) {
     const int i = j0 + lane;
@@ -1338,11 +1352,23 @@ __device__ void qrw_apply_col(const double* __restrict__ Wm, int m, int j0, int 
     for (int q = 0; q < kQrPanel; ++q) t += (trans ? Tm[q][r] : Tm[r][q]) * w[q];
     u[r] = t;
   }
-  for (int i = j0 + pb + lane; i < m; i += 64) {
-    double x = col[i];
+  for (int i0 = j0 + pb + lane; i0 < m; i0 += 2 * 64) {
+    double x[2], vv[2][kQrPanel];
 #pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) x -= (r < pb ? V[i + (long long)r * m] : 0.0) * u[r];
-    col[i] = x;
+    for (int h = 0; h < 2; ++h) {
+      const int i = min(i0 + 64 * h, m - 1);
+      x[h] = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) vv[h][r] = V[i + (long long)min(r, pb - 1) * m];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (i0 + 64 * h < m) {
+        double y = x[h];
+#pragma unroll
+        for (int r = 0; r < kQrPanel; ++r) y -= (r < pb ? vv[h][r] : 0.0) * u[r];
+        col[i0 + 64 * h] = y;
+      }
   }
   if (lane < pb) {
     const int i = j0 + lane;
@@ -1392,10 +1418,15 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
   __shared__ double Tm[kQrPanel][kQrPanel];
   __shared__ double Gm[kQrPanel][kQrPanel];
   for (int j = j0; j < j0 + pb; ++j) {
+    double* cj = Wm + (long long)j * m;
     double part = 0.0;
-    for (int i = j + 1 + tid; i < m; i += blockDim.x) {
-      double x = Wm[i + (long long)j * m];
-      part += x * x;
+    for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
+      double x[kQrRowU];
+#pragma unroll
+      for (int u = 0; u < kQrRowU; ++u) x[u] = cj[min(i0 + 256 * u, m - 1)];
+#pragma unroll
+      for (int u = 0; u < kQrRowU; ++u)
+        if (i0 + 256 * u < m) part += x[u] * x[u];
     }
     double xn2 = block_sum(part, red);
     double alpha = Wm[j + (long long)j * m];
@@ -1404,7 +1435,14 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
       double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
       tau = (beta - alpha) / beta;
       double scal = 1.0 / (alpha - beta);
-      for (int i = j + 1 + tid; i < m; i += blockDim.x) Wm[i + (long long)j * m] *= scal;
+      for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
+        double x[kQrRowU];
+#pragma unroll
+        for (int u = 0; u < kQrRowU; ++u) x[u] = cj[min(i0 + 256 * u, m - 1)];
+#pragma unroll
+        for (int u = 0; u < kQrRowU; ++u)
+          if (i0 + 256 * u < m) cj[i0 + 256 * u] = x[u] * scal;
+      }
       __syncthreads();
       if (tid == 0) Wm[j + (long long)j * m] = beta;
     }
@@ -1417,11 +1455,22 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
       double acc[kQrPanel - 1];
 #pragma unroll
       for (int q = 0; q < kQrPanel - 1; ++q) acc[q] = 0.0;
-      for (int i = j + 1 + tid; i < m; i += blockDim.x) {
-        const double vi = v[i];
+      for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
+        double vi[kQrRowU], x[kQrRowU][kQrPanel - 1];
 #pragma unroll
-        for (int q = 0; q < kQrPanel - 1; ++q)
-          if (q < nc) acc[q] += vi * c1[i + (long long)q * m];
+        for (int u = 0; u < kQrRowU; ++u) {
+          const int i = min(i0 + 256 * u, m - 1);
+          vi[u] = v[i];
+#pragma unroll
+          for (int q = 0; q < kQrPanel - 1; ++q) x[u][q] = c1[i + (long long)min(q, nc - 1) * m];
+        }
+#pragma unroll
+        for (int u = 0; u < kQrRowU; ++u)
+          if (i0 + 256 * u < m) {
+#pragma unroll
+            for (int q = 0; q < kQrPanel - 1; ++q)
+              if (q < nc) acc[q] += vi[u] * x[u][q];
+          }
       }
 #pragma unroll
       for (int q = 0; q < kQrPanel - 1; ++q) {
@@ -1442,11 +1491,22 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
       double fq[kQrPanel - 1];
 #pragma unroll
       for (int q = 0; q < kQrPanel - 1; ++q) fq[q] = q < nc ? fsh[q] : 0.0;
-      for (int i = j + 1 + tid; i < m; i += blockDim.x) {
-        const double vi = v[i];
+      for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
+        double vi[kQrRowU], x[kQrRowU][kQrPanel - 1];
 #pragma unroll
-        for (int q = 0; q < kQrPanel - 1; ++q)
-          if (q < nc) c1[i + (long long)q * m] -= fq[q] * vi;
+        for (int u = 0; u < kQrRowU; ++u) {
+          const int i = min(i0 + 256 * u, m - 1);
+          vi[u] = v[i];
+#pragma unroll
+          for (int q = 0; q < kQrPanel - 1; ++q) x[u][q] = c1[i + (long long)min(q, nc - 1) * m];
+        }
+#pragma unroll
+        for (int u = 0; u < kQrRowU; ++u)
+          if (i0 + 256 * u < m) {
+#pragma unroll
+            for (int q = 0; q < kQrPanel - 1; ++q)
+              if (q < nc) c1[i0 + 256 * u + (long long)q * m] = x[u][q] - fq[q] * vi[u];
+          }
       }
     }
     __syncthreads();
@@ -1456,15 +1516,24 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
   double g[kPairs];
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) g[p] = 0.0;
-  for (int q = j0 + 1 + tid; q < m; q += blockDim.x) {
-    double vq[kQrPanel];
+  for (int q0 = j0 + 1 + tid; q0 < m; q0 += 2 * 256) {
+    double vq[2][kQrPanel];
 #pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) vq[r] = r < pb ? Wm[q + (long long)(j0 + r) * m] : 0.0;
+    for (int u = 0; u < 2; ++u) {
+      const int q = min(q0 + 256 * u, m - 1);
 #pragma unroll
-    for (int i = 1; i < kQrPanel; ++i)
+      for (int r = 0; r < kQrPanel; ++r) vq[u][r] = Wm[q + (long long)(j0 + min(r, pb - 1)) * m];
+    }
 #pragma unroll
-      for (int r = 0; r < i; ++r)
-        if (q > j0 + i) g[i * (i - 1) / 2 + r] += vq[r] * vq[i];
+    for (int u = 0; u < 2; ++u) {
+      const int q = q0 + 256 * u;
+      if (q >= m) break;
+#pragma unroll
+      for (int i = 1; i < kQrPanel; ++i)
+#pragma unroll
+        for (int r = 0; r < i; ++r)
+          if (i < pb && q > j0 + i) g[i * (i - 1) / 2 + r] += vq[u][r] * vq[u][i];
+    }
   }
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) {
