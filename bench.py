@@ -37,7 +37,7 @@ def kernel_name(kind, prec):
     return {"k_gemm_reduce": "tt::k_gemm_reduce", "k_wgemm": "tt::k_wgemm<%d>" % (prec if prec >= 2 else 0),
             "wstage": "tt::k_wstage<%s, int>" % ("double" if prec == 0 else "float"),
             "k_fused": "tt::k_fused_apply",
-            "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qr_wide"}[kind]
+            "qr": "tt::k_qr_chunk + k_qr_stack + k_qr_combine + k_qrw_*"}[kind]
 
 
 def cpu_baseline(c, D, sector_cap, budget_s=25.0):
