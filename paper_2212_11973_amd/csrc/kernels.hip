@@ -1400,10 +1400,10 @@ __global__ __launch_bounds__(256) void k_qrw_load(const QRTask* __restrict__ tas
 // workgroup each: its columns factored one by one, then its T factor from tau
 // and G = V^T V (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i])
 // stored for the later updates.  Every pass over the rows is shared by the
-// whole workgroup (rows strided by the 256 threads): a column step reduces the
-// norm, then the dot products of the reflector with all later columns of the
-// panel at once; G takes one pass for all its pairs.  Sums: per thread, then
-// per wave, then the four waves in order.
+// whole workgroup (rows strided by the 256 threads, kQrRowU rows per thread
+// with their loads issued together): one pass per column step (below), and
+// one for G with all its pairs.  Sums: per thread, then per wave, then the
+// four waves in order.
 __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
                                                    BPtr<double> b_ws, int j0) {
   constexpr int kPairs = kQrPanel * (kQrPanel - 1) / 2;
@@ -1417,96 +1417,108 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
   __shared__ double fsh[kQrPanel];
   __shared__ double Tm[kQrPanel][kQrPanel];
   __shared__ double Gm[kQrPanel][kQrPanel];
-  for (int j = j0; j < j0 + pb; ++j) {
-    double* cj = Wm + (long long)j * m;
-    double part = 0.0;
-    for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
-      double x[kQrRowU];
+  // One pass over the rows per column step.  The pass of step j writes the
+  // reflector v_j = scal x_j below the diagonal, applies it to the later
+  // columns of the panel, and sums, from the updated values, what step j + 1
+  // needs: ||x_{j+1}||^2 below row j + 1 and x_{j+1} . col_c for every later
+  // column c (so v . col_c = col_c[j+1] + scal D_c).  acc[0] is the norm
+  // partial, acc[1 + q] the dot with column (current + 1 + q).
+  double acc[kQrPanel];
 #pragma unroll
-      for (int u = 0; u < kQrRowU; ++u) x[u] = cj[min(i0 + 256 * u, m - 1)];
+  for (int q = 0; q < kQrPanel; ++q) acc[q] = 0.0;
+  {
+    const int nc = pb - 1;
+    const double* x0 = Wm + (long long)j0 * m;
+    const double* yb = nc > 0 ? x0 + m : x0;   // later columns (none: the column itself, unused)
+    for (int i0 = j0 + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
+      double x[kQrRowU], y[kQrRowU][kQrPanel - 1];
+#pragma unroll
+      for (int u = 0; u < kQrRowU; ++u) {
+        const int i = min(i0 + 256 * u, m - 1);
+        x[u] = x0[i];
+#pragma unroll
+        for (int q = 0; q < kQrPanel - 1; ++q) y[u][q] = yb[i + (long long)min(q, max(nc - 1, 0)) * m];
+      }
 #pragma unroll
       for (int u = 0; u < kQrRowU; ++u)
-        if (i0 + 256 * u < m) part += x[u] * x[u];
-    }
-    double xn2 = block_sum(part, red);
-    double alpha = Wm[j + (long long)j * m];
-    double tau = 0.0;
-    if (xn2 > 0.0) {
-      double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tau = (beta - alpha) / beta;
-      double scal = 1.0 / (alpha - beta);
-      for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
-        double x[kQrRowU];
+        if (i0 + 256 * u < m) {
+          acc[0] += x[u] * x[u];
 #pragma unroll
-        for (int u = 0; u < kQrRowU; ++u) x[u] = cj[min(i0 + 256 * u, m - 1)];
-#pragma unroll
-        for (int u = 0; u < kQrRowU; ++u)
-          if (i0 + 256 * u < m) cj[i0 + 256 * u] = x[u] * scal;
-      }
-      __syncthreads();
-      if (tid == 0) Wm[j + (long long)j * m] = beta;
+          for (int q = 0; q < kQrPanel - 1; ++q)
+            if (q < nc) acc[1 + q] += x[u] * y[u][q];
+        }
     }
-    if (tid == 0) taus[j] = tau;
+  }
+  for (int j = j0; j < j0 + pb; ++j) {
+    const int nc = j0 + pb - j - 1;   // later columns of the panel (uniform)
+    // the step's sums: per wave, then the four waves in order (thread 0)
+#pragma unroll
+    for (int q = 0; q < kQrPanel; ++q) {
+      if (q > nc) break;
+      const double sq = wave_sum(acc[q]);
+      if (lane == 0) red[wave * kQrPanel + q] = sq;
+    }
     __syncthreads();
-    const int nc = j0 + pb - j - 1;   // later columns of the panel (uniform, as is tau)
-    if (tau != 0.0 && nc > 0) {
-      const double* v = Wm + (long long)j * m;
-      double* c1 = Wm + (long long)(j + 1) * m;
-      double acc[kQrPanel - 1];
-#pragma unroll
-      for (int q = 0; q < kQrPanel - 1; ++q) acc[q] = 0.0;
-      for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
-        double vi[kQrRowU], x[kQrRowU][kQrPanel - 1];
-#pragma unroll
-        for (int u = 0; u < kQrRowU; ++u) {
-          const int i = min(i0 + 256 * u, m - 1);
-          vi[u] = v[i];
-#pragma unroll
-          for (int q = 0; q < kQrPanel - 1; ++q) x[u][q] = c1[i + (long long)min(q, nc - 1) * m];
-        }
-#pragma unroll
-        for (int u = 0; u < kQrRowU; ++u)
-          if (i0 + 256 * u < m) {
-#pragma unroll
-            for (int q = 0; q < kQrPanel - 1; ++q)
-              if (q < nc) acc[q] += vi[u] * x[u][q];
-          }
+    if (tid == 0) {
+      double sum[kQrPanel];
+      for (int q = 0; q <= nc; ++q)
+        sum[q] = ((red[q] + red[kQrPanel + q]) + red[2 * kQrPanel + q]) + red[3 * kQrPanel + q];
+      const double xn2 = sum[0];
+      const double alpha = Wm[j + (long long)j * m];
+      double tau = 0.0, scal = 1.0;
+      if (xn2 > 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+        Wm[j + (long long)j * m] = beta;
       }
-#pragma unroll
-      for (int q = 0; q < kQrPanel - 1; ++q) {
-        if (q >= nc) break;
-        const double sq = wave_sum(acc[q]);
-        if (lane == 0) red[wave * kPairs + q] = sq;
-      }
-      __syncthreads();
-      if (tid < nc) {   // row j of v is 1
-        double* col = c1 + (long long)tid * m;
-        double d = ((red[tid] + red[kPairs + tid]) + red[2 * kPairs + tid]) + red[3 * kPairs + tid];
-        d += col[j];
-        const double f = tau * d;
+      taus[j] = tau;
+      fsh[kQrPanel - 1] = scal;
+      for (int q = 0; q < nc; ++q) {   // row j of v is 1
+        double* col = Wm + (long long)(j + 1 + q) * m;
+        const double f = tau * (col[j] + scal * sum[1 + q]);
         col[j] -= f;
-        fsh[tid] = f;
+        fsh[q] = f;
       }
-      __syncthreads();
-      double fq[kQrPanel - 1];
+    }
+    __syncthreads();
+    const double scal = fsh[kQrPanel - 1];
+    double fq[kQrPanel - 1];
 #pragma unroll
-      for (int q = 0; q < kQrPanel - 1; ++q) fq[q] = q < nc ? fsh[q] : 0.0;
-      for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
-        double vi[kQrRowU], x[kQrRowU][kQrPanel - 1];
+    for (int q = 0; q < kQrPanel - 1; ++q) fq[q] = q < nc ? fsh[q] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kQrRowU; ++u) {
-          const int i = min(i0 + 256 * u, m - 1);
-          vi[u] = v[i];
+    for (int q = 0; q < kQrPanel; ++q) acc[q] = 0.0;
+    double* xj = Wm + (long long)j * m;
+    double* c1 = xj + m;
+    const double* yb = nc > 0 ? c1 : xj;   // later columns (none: the column itself, unused)
+    for (int i0 = j + 1 + tid; i0 < m; i0 += kQrRowU * 256) {
+      double x[kQrRowU], y[kQrRowU][kQrPanel - 1];
 #pragma unroll
-          for (int q = 0; q < kQrPanel - 1; ++q) x[u][q] = c1[i + (long long)min(q, nc - 1) * m];
-        }
+      for (int u = 0; u < kQrRowU; ++u) {
+        const int i = min(i0 + 256 * u, m - 1);
+        x[u] = xj[i];
 #pragma unroll
-        for (int u = 0; u < kQrRowU; ++u)
-          if (i0 + 256 * u < m) {
+        for (int q = 0; q < kQrPanel - 1; ++q) y[u][q] = yb[i + (long long)min(q, max(nc - 1, 0)) * m];
+      }
 #pragma unroll
-            for (int q = 0; q < kQrPanel - 1; ++q)
-              if (q < nc) c1[i0 + 256 * u + (long long)q * m] = x[u][q] - fq[q] * vi[u];
+      for (int u = 0; u < kQrRowU; ++u) {
+        const int i = i0 + 256 * u;
+        if (i < m) {
+          const double v = x[u] * scal;
+          xj[i] = v;
+#pragma unroll
+          for (int q = 0; q < kQrPanel - 1; ++q)
+            if (q < nc) {
+              y[u][q] -= fq[q] * v;
+              c1[i + (long long)q * m] = y[u][q];
+            }
+          if (i > j + 1 && nc > 0) {   // step j + 1: column j + 1 is y[u][0]
+            acc[0] += y[u][0] * y[u][0];
+#pragma unroll
+            for (int q = 1; q < kQrPanel - 1; ++q)
+              if (q < nc) acc[q] += y[u][0] * y[u][q];
           }
+        }
       }
     }
     __syncthreads();
