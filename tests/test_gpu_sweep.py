@@ -321,3 +321,27 @@ def test_full_size_workload_properties():
         assert np.abs(G - np.eye(len(rows))).max() < 1e-11, k
     a.free()
     b.free()
+
+
+def test_uncapped_full_size_wide_lq_blocks_are_orthonormal():
+    # the benchmark's workload without the sector cap: sectors of up to 195
+    # states, so 14 sites at each end hold LQ blocks of 69-195 rows that the
+    # global-memory (wide) QR factors; after a sweep every site k >= 1 is
+    # right-canonical, checked on all rows of sites with such blocks
+    c = WL.MODELS["cl4x16"]
+    m = T.model(c["W"], c["L"], c["geometry"], c["t"], c["U"], c["mu"])
+    o = T.options(D=c["D"], symmetry=1, beta0=c["beta0"], pad_eps=1e-3, seed=1, krylov_dim=c["krylov"],
+                  sector_cap=0)
+    st = T.State.init(m, o)
+    n, dims = st.info()
+    widest = {k: max(d for _, d in st.sectors(k)) for k in range(n + 1)}
+    assert widest[3] > 64 and widest[n - 3] > 64                      # the wide form is exercised
+    print("uncapped 4x16 D=2000, widest sectors", widest[3], widest[n - 3], flush=True)
+    st.sweep(c["dbeta"])
+    ob = st.observables()
+    assert all(np.isfinite([ob["lnZ"], ob["E"], ob["f"]]))
+    for k in (3, 5, n - 5, n - 3):
+        A = st.export_site(k).reshape(dims[k], -1)
+        G = A @ A.T
+        assert np.abs(G - np.eye(dims[k])).max() < 1e-11, k
+    st.free()
