@@ -1286,14 +1286,13 @@ __device__ double block_sum(double v, double* red) {
 // explicitly the same way, panels in reverse order.  Same reflectors as the
 // column-by-column algorithm; only the order of the sums differs.  The
 // updates of the later columns and of Q spread over the GPU: one launch per
-// panel step, kQrApplyCols columns per workgroup, one wave per column, every
-// column's arithmetic independent of which workgroup takes it.
+// panel step, one column per workgroup.
 // Workspace of a task (ws + T.ws, qr_wide_ws doubles): Wm (m x n column-major:
 // R above the diagonal, reflectors below), Qm (m x n), the n taus, then the
 // T factor of every panel (kQrPanel x kQrPanel, row-major, zero past the panel).
 // The launches take blockIdx.x = wide block, blockIdx.z = state of the batch.
 constexpr int kQrPanel = 8;
-constexpr int kQrApplyCols = 4;   // one column per wave
+constexpr int kQrApplyCols = 1;   // columns per workgroup of the panel updates
 constexpr int kQrRowU = 4;         // rows per thread whose loads the panel's passes issue together
 constexpr int kQrSpread = 64;   // workgroups per block of the copy-in and copy-out launches
 long long qr_wide_ws(int m, int n) {
@@ -1304,79 +1303,6 @@ __device__ __forceinline__ double* qrw_tfac(double* Wm, int m, int n, int j0) {
 }
 __device__ __forceinline__ long long qrw_row(const QRTask& T, const long long* tabs, int i) {
   return T.rtab >= 0 ? tabs[T.rtab + i] : (long long)i * T.rs;
-}
-
-// column col <- (I - V T' V^T) col for the panel at j0 (T' = T^T with trans)
-// by one wave: w = V^T col over the rows >= j0, u = T' w, col -= V u.  Rows
-// j0 .. j0 + pb - 1 hold the unit diagonal of V (one lane each); below them
-// every v_r is a stored column of Wm.
-__device__ void qrw_apply_col(const double* __restrict__ Wm, int m, int j0, int pb,
-                              const double (*Tm)[kQrPanel], double* col, bool trans) {
-  const int lane = threadIdx.x & 63;
-  double w[kQrPanel];
-#pragma unroll
-  for (int r = 0; r < kQrPanel; ++r) w[r] = 0.0;
-  const double* V = Wm + (long long)j0 * m;
-  // two rows per lane per step, their loads issued together (rows past the
-  // end clamped to the last one, their products not taken)
-  for (int i0 = j0 + pb + lane; i0 < m; i0 += 2 * 64) {
-    double x[2], vv[2][kQrPanel];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int i = min(i0 + 64 * u, m - 1);
-      x[u] = col[i];
-#pragma unroll
-      for (int r = 0; r < kQrPanel; ++r) vv[u][r] = V[i + (long long)min(r, pb - 1) * m];
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (i0 + 64 * u < m) {
-#pragma unroll
-        for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? vv[u][r] : 0.0) * x[u];
-      }
-  }
-  if (lane < pb) {
-    const int i = j0 + lane;
-    const double x = col[i];
-#pragma unroll
-    for (int r = 0; r < kQrPanel; ++r)
-      w[r] += (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * x;
-  }
-  double u[kQrPanel];
-#pragma unroll
-  for (int r = 0; r < kQrPanel; ++r) w[r] = __shfl(wave_sum(w[r]), 0, 64);
-#pragma unroll
-  for (int r = 0; r < kQrPanel; ++r) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < kQrPanel; ++q) t += (trans ? Tm[q][r] : Tm[r][q]) * w[q];
-    u[r] = t;
-  }
-  for (int i0 = j0 + pb + lane; i0 < m; i0 += 2 * 64) {
-    double x[2], vv[2][kQrPanel];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = min(i0 + 64 * h, m - 1);
-      x[h] = col[i];
-#pragma unroll
-      for (int r = 0; r < kQrPanel; ++r) vv[h][r] = V[i + (long long)min(r, pb - 1) * m];
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      if (i0 + 64 * h < m) {
-        double y = x[h];
-#pragma unroll
-        for (int r = 0; r < kQrPanel; ++r) y -= (r < pb ? vv[h][r] : 0.0) * u[r];
-        col[i0 + 64 * h] = y;
-      }
-  }
-  if (lane < pb) {
-    const int i = j0 + lane;
-    double x = col[i];
-#pragma unroll
-    for (int r = 0; r < kQrPanel; ++r) x -= (r < lane ? V[i + (long long)r * m] : (r == lane ? 1.0 : 0.0)) * u[r];
-    col[i] = x;
-  }
 }
 
 // Wm, Qm of every wide block of the launch: Wm the block, Qm = [I; 0]
@@ -1580,26 +1506,99 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
   if (tid < kQrPanel * kQrPanel) qrw_tfac(Wm, m, n, j0)[tid] = Tm[tid / kQrPanel][tid % kQrPanel];
 }
 
-// the panel at j0 applied to kQrApplyCols columns per workgroup (group
-// blockIdx.y): qmode 0, the columns of Wm after the panel, with Q_panel^T =
-// I - V T^T V^T; qmode 1, the columns >= j0 of Qm, with I - V T V^T (Q's
-// earlier columns are unit vectors that the panel's reflectors leave alone)
+// the panel at j0 applied to one column per workgroup (blockIdx.y): qmode 0,
+// the columns of Wm after the panel, with Q_panel^T = I - V T^T V^T; qmode 1,
+// the columns >= j0 of Qm, with I - V T V^T (Q's earlier columns are unit
+// vectors that the panel's reflectors leave alone).  w = V^T col over the rows
+// >= j0 (rows j0 .. j0 + pb - 1 hold the unit diagonal of V, one thread each;
+// below them every v_r is a stored column of Wm), u = T' w, col -= V u; the
+// rows strided over the 256 threads, two per thread with their loads issued
+// together (rows past the end clamped to the last one, not used); sums per
+// thread, per wave, then the four waves in order.
 __global__ __launch_bounds__(256) void k_qrw_apply(const QRTask* __restrict__ tasks, const int* __restrict__ wide,
                                                    BPtr<double> b_ws, int j0, int qmode) {
   const QRTask T = tasks[wide[blockIdx.x]];
   const int m = T.m, n = T.n;
   if (j0 >= n) return;
-  const int pb = min(kQrPanel, n - j0), wave = threadIdx.x >> 6;
-  const int c0 = (qmode ? j0 : j0 + pb) + kQrApplyCols * (int)blockIdx.y;
-  if (c0 >= n) return;   // uniform over the workgroup
+  const int pb = min(kQrPanel, n - j0), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = (qmode ? j0 : j0 + pb) + (int)blockIdx.y;
+  if (c >= n) return;   // uniform over the workgroup
   double* Wm = b_ws.p[blockIdx.z] + T.ws;
-  double* base = qmode ? Wm + (long long)m * n : Wm;
+  double* col = (qmode ? Wm + (long long)m * n : Wm) + (long long)c * m;
+  const double* V = Wm + (long long)j0 * m;
+  const bool trans = !qmode;
   __shared__ double Tm[kQrPanel][kQrPanel];
+  __shared__ double red[4][kQrPanel];
+  __shared__ double wsh[kQrPanel];
   const double* tf = qrw_tfac(Wm, m, n, j0);
-  if (threadIdx.x < kQrPanel * kQrPanel) Tm[threadIdx.x / kQrPanel][threadIdx.x % kQrPanel] = tf[threadIdx.x];
+  if (tid < kQrPanel * kQrPanel) Tm[tid / kQrPanel][tid % kQrPanel] = tf[tid];
+  double w[kQrPanel];
+#pragma unroll
+  for (int r = 0; r < kQrPanel; ++r) w[r] = 0.0;
+  for (int i0 = j0 + pb + tid; i0 < m; i0 += 2 * 256) {
+    double x[2], vv[2][kQrPanel];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = min(i0 + 256 * h, m - 1);
+      x[h] = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) vv[h][r] = V[i + (long long)min(r, pb - 1) * m];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (i0 + 256 * h < m) {
+#pragma unroll
+        for (int r = 0; r < kQrPanel; ++r) w[r] += (r < pb ? vv[h][r] : 0.0) * x[h];
+      }
+  }
+  if (tid < pb) {
+    const int i = j0 + tid;
+    const double x = col[i];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r)
+      w[r] += (r < tid ? V[i + (long long)r * m] : (r == tid ? 1.0 : 0.0)) * x;
+  }
+#pragma unroll
+  for (int r = 0; r < kQrPanel; ++r) {
+    const double sr = wave_sum(w[r]);
+    if (lane == 0) red[wave][r] = sr;
+  }
   __syncthreads();
-  const int c1 = min(n, c0 + kQrApplyCols);
-  for (int c = c0 + wave; c < c1; c += 4) qrw_apply_col(Wm, m, j0, pb, Tm, base + (long long)c * m, !qmode);
+  if (tid < kQrPanel) wsh[tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+  __syncthreads();
+  double u[kQrPanel];
+#pragma unroll
+  for (int r = 0; r < kQrPanel; ++r) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kQrPanel; ++q) t += (trans ? Tm[q][r] : Tm[r][q]) * wsh[q];
+    u[r] = t;
+  }
+  for (int i0 = j0 + pb + tid; i0 < m; i0 += 2 * 256) {
+    double x[2], vv[2][kQrPanel];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = min(i0 + 256 * h, m - 1);
+      x[h] = col[i];
+#pragma unroll
+      for (int r = 0; r < kQrPanel; ++r) vv[h][r] = V[i + (long long)min(r, pb - 1) * m];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (i0 + 256 * h < m) {
+        double y = x[h];
+#pragma unroll
+        for (int r = 0; r < kQrPanel; ++r) y -= (r < pb ? vv[h][r] : 0.0) * u[r];
+        col[i0 + 256 * h] = y;
+      }
+  }
+  if (tid < pb) {
+    const int i = j0 + tid;
+    double x = col[i];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r) x -= (r < tid ? V[i + (long long)r * m] : (r == tid ? 1.0 : 0.0)) * u[r];
+    col[i] = x;
+  }
 }
 
 // non-negative diagonal: column j of Q and row j of R flipped when R_jj < 0;
