@@ -1340,7 +1340,7 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
   double* Wm = b_ws.p[blockIdx.z] + T.ws;
   double* taus = Wm + 2LL * m * n;
   __shared__ double red[4 * kPairs];
-  __shared__ double fsh[kQrPanel];
+  __shared__ double fsh[kQrPanel], sums[kQrPanel], rowj[kQrPanel];
   __shared__ double Tm[kQrPanel][kQrPanel];
   __shared__ double Gm[kQrPanel][kQrPanel];
   // One pass over the rows per column step.  The pass of step j writes the
@@ -1377,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
   }
   for (int j = j0; j < j0 + pb; ++j) {
     const int nc = j0 + pb - j - 1;   // later columns of the panel (uniform)
-    // the step's sums: per wave, then the four waves in order (thread 0)
+    // the step's sums: per wave, then the four waves in order
 #pragma unroll
     for (int q = 0; q < kQrPanel; ++q) {
       if (q > nc) break;
@@ -1385,30 +1385,29 @@ __global__ __launch_bounds__(256) void k_qrw_panel(const QRTask* __restrict__ ta
       if (lane == 0) red[wave * kQrPanel + q] = sq;
     }
     __syncthreads();
-    if (tid == 0) {
-      double sum[kQrPanel];
-      for (int q = 0; q <= nc; ++q)
-        sum[q] = ((red[q] + red[kQrPanel + q]) + red[2 * kQrPanel + q]) + red[3 * kQrPanel + q];
-      const double xn2 = sum[0];
-      const double alpha = Wm[j + (long long)j * m];
-      double tau = 0.0, scal = 1.0;
-      if (xn2 > 0.0) {
-        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-        Wm[j + (long long)j * m] = beta;
-      }
-      taus[j] = tau;
-      fsh[kQrPanel - 1] = scal;
-      for (int q = 0; q < nc; ++q) {   // row j of v is 1
-        double* col = Wm + (long long)(j + 1 + q) * m;
-        const double f = tau * (col[j] + scal * sum[1 + q]);
-        col[j] -= f;
-        fsh[q] = f;
-      }
+    // the step's sums and the row-j entries they combine with, one thread each,
+    // then tau and scal in every thread (the same arithmetic on the same values)
+    if (tid <= nc) {
+      sums[tid] = ((red[tid] + red[kQrPanel + tid]) + red[2 * kQrPanel + tid]) + red[3 * kQrPanel + tid];
+      rowj[tid] = Wm[j + (long long)(j + tid) * m];   // tid 0: alpha; else row j of column j + tid
     }
     __syncthreads();
-    const double scal = fsh[kQrPanel - 1];
+    const double xn2 = sums[0], alpha = rowj[0];
+    double tau = 0.0, scal = 1.0, beta = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (tid == 0) {
+      if (xn2 > 0.0) Wm[j + (long long)j * m] = beta;
+      taus[j] = tau;
+    } else if (tid <= nc) {   // row j of v is 1
+      const double f = tau * (rowj[tid] + scal * sums[tid]);
+      Wm[j + (long long)(j + tid) * m] = rowj[tid] - f;
+      fsh[tid - 1] = f;
+    }
+    __syncthreads();
     double fq[kQrPanel - 1];
 #pragma unroll
     for (int q = 0; q < kQrPanel - 1; ++q) fq[q] = q < nc ? fsh[q] : 0.0;
