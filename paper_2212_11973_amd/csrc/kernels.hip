@@ -765,8 +765,13 @@ __device__ __forceinline__ void wave_tile_k(const GemmProb& P, const GemmJob& J,
 // five waves per SIMD: the register budget (96) that keeps a half chunk's
 // loads of the next steps in flight without spilling
 // MM: the precision of the multiplies (TT_FP64, TT_BF16X3, TT_BF16X6)
+// waves per SIMD the wave GEMM is compiled for (4x16 D=2000 sweep: 0.316 s/step at
+// 5 and at 6, 0.325 at 4)
+#ifndef TT_WGEMM_WPE
+#define TT_WGEMM_WPE 5
+#endif
 template <int MM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TT_WGEMM_WPE))) void k_wgemm(const GemmProb* __restrict__ probs, const GemmJob* __restrict__ jobs,
                                                int nblocks, const long long* __restrict__ tabs, BSlots bs) {
   __shared__ double red[3 * 1024];
   const Slots& slots = bs.s[blockIdx.y];
